@@ -1,0 +1,639 @@
+"""FP64 CPU oracle for the per-layer Kalman-filter step.  TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this module.  It is a plain, slow, step-by-step statement of what the GPU path
+computes, in float64 PyTorch CPU ops, batched over tracks only (every per-track
+formula is written exactly as stated below; nothing is fused or reordered).
+It shares no code with the HIP kernels.
+
+The paper (Sec. 2.2 "Track finding algorithm" and Sec. 3.1 "Geometry &
+detector description") names the computations -- propagation of a track
+candidate to the next layer, hit selection, Kalman-filter calculations -- but
+gives no formulas.  The formulas are the textbook ones for a helix in a uniform
+solenoidal field, the Highland multiple-scattering angle and the linear Kalman
+filter; each function states the reading it takes.
+
+Units: cm, GeV/c, tesla, radians.  State p = (x, y, z, ipt, phi, theta) with
+ipt = 1/pT >= 0 and a separate charge q = +-1.  Covariances are full 6x6 / 3x3
+tensors here; packing is done only at the interface.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+DT = torch.float64
+C_LIGHT = 0.00299792458   # GeV/c per (T cm)
+GRAZING_COS = 0.05        # |cos(incidence)| below this is flagged and clamped
+SEED_COV_DIAG = (1.0, 1.0, 1.0, 1.0, 0.01, 0.01)
+
+# per-track status bits (shared meaning with the C interface)
+NO_CROSSING = 1
+GRAZING = 2
+NONFINITE = 4
+FP64_FALLBACK = 8
+CHARGE_FLIP = 16
+COV_NOT_PSD = 32
+
+BARREL = 0
+DISK = 1
+
+
+def _t(a):
+    """Any input as a float64 tensor (differentiable when it already is one)."""
+    return a.to(DT) if torch.is_tensor(a) else torch.as_tensor(a, dtype=DT)
+
+
+def wrap_phi(phi):
+    """Wrap to (-pi, pi]."""
+    return phi - 2.0 * math.pi * torch.ceil((phi - math.pi) / (2.0 * math.pi))
+
+
+def omega(q, ipt, bz):
+    """Signed curvature (rad per cm of transverse path): omega = -q c_B B_z / pT.
+    Positive charge in a positive field turns clockwise."""
+    return -q * C_LIGHT * bz * ipt
+
+
+def _safe_omega(w):
+    tiny = 1e-12
+    return torch.where(w.abs() < tiny, torch.where(w < 0, -tiny, tiny) + 0.0 * w, w)
+
+
+# --------------------------------------------------------------------------
+# a1: helix propagation
+# --------------------------------------------------------------------------
+
+def helix_at(p, q, s, bz):
+    """State after transverse path s along the helix (plain closed form):
+    phi(s) = phi0 + w s,  x(s) = x0 + [sin(phi0 + w s) - sin phi0]/w,
+    y(s) = y0 - [cos(phi0 + w s) - cos phi0]/w,  z(s) = z0 + s cot(theta).
+    ipt and theta are unchanged."""
+    p, q, s = _t(p), _t(q), _t(s)
+    x0, y0, z0, ipt, phi0, th = p.unbind(-1)
+    w = _safe_omega(omega(q, ipt, bz))
+    ph = phi0 + w * s
+    x = x0 + (torch.sin(ph) - torch.sin(phi0)) / w
+    y = y0 - (torch.cos(ph) - torch.cos(phi0)) / w
+    # for |u| = |w s| < 1e-2 the differences above lose digits; expand
+    # sin(phi0+u) = s0 cos u + c0 sin u, cos(phi0+u) = c0 cos u - s0 sin u:
+    # x = x0 + s [s0 (cos u - 1)/u + c0 sin(u)/u], y = y0 + s [-c0 (cos u - 1)/u + s0 sin(u)/u]
+    u = w * s
+    small = u.abs() < 1e-2
+    us = torch.where(small, u, torch.zeros_like(u))
+    cm1_u = -us / 2.0 + us ** 3 / 24.0 - us ** 5 / 720.0
+    sin_u = 1.0 - us ** 2 / 6.0 + us ** 4 / 120.0 - us ** 6 / 5040.0
+    s0, c0 = torch.sin(phi0), torch.cos(phi0)
+    x = torch.where(small, x0 + s * (s0 * cm1_u + c0 * sin_u), x)
+    y = torch.where(small, y0 + s * (-c0 * cm1_u + s0 * sin_u), y)
+    z = z0 + s * torch.cos(th) / torch.sin(th)
+    return torch.stack([x, y, z, ipt, ph, th], dim=-1)
+
+
+S_BACK = 1.0     # cm: a different layer may lie at most this far behind the state
+S_SAME = 0.01    # cm: re-crossing the layer the state sits on must go at least this far
+
+
+def _path_window(same):
+    """Lower end of the admissible path window: the crossing is the first root
+    of the surface equation with s > lo.  For a different layer lo = -S_BACK
+    (a surface just behind an estimate that overshot it is reached by a short
+    backward step); for the layer the state already sits on (a looper turning
+    round) lo = +S_SAME, so the current point itself is skipped."""
+    return torch.where(same, torch.full_like(same, S_SAME, dtype=DT), torch.full_like(same, -S_BACK, dtype=DT))
+
+
+def crossing_barrel(p, q, R, bz, same=None, newton_steps=3):
+    """First root s > lo (see _path_window) of x(s)^2 + y(s)^2 = R^2.
+
+    With A = x0 cos phi0 + y0 sin phi0, B = x0 sin phi0 - y0 cos phi0 and the
+    turning angle u = w s, the squared radius along the helix is
+        r^2(u) = r0^2 + (2A/w) sin u + 2(1 - wB)(1 - cos u)/w^2,
+    so the crossing solves (Aw) sin u - (1 - wB) cos u = w^2 (R^2 - r0^2)/2 - (1 - wB),
+    i.e. rho sin(u - delta) = rhs.  Both solutions are mapped onto the turn
+    (lo, lo + 2 pi/|w|], the smaller is taken and polished by Newton steps on
+    h(s) = r^2(s) - R^2.  Returns (s, ok)."""
+    p, q = _t(p), _t(q)
+    x0, y0, _, ipt, phi0, _ = p.unbind(-1)
+    if same is None:
+        same = torch.zeros_like(x0, dtype=torch.bool)
+    lo = _path_window(same)
+    w = omega(q, ipt, bz)
+    ws = _safe_omega(w)
+    R = _t(R) * torch.ones_like(x0)
+    A = x0 * torch.cos(phi0) + y0 * torch.sin(phi0)
+    B = x0 * torch.sin(phi0) - y0 * torch.cos(phi0)
+    d2 = R * R - (x0 * x0 + y0 * y0)
+    a = A * ws
+    b = 1.0 - ws * B
+    c = 0.5 * ws * ws * d2
+    rho = torch.sqrt(a * a + b * b)
+    t = (c - b) / rho
+    ok = t.abs() <= 1.0
+    tc = torch.clamp(t, -1.0, 1.0)
+    delta = torch.atan2(b, a)
+    u1 = delta + torch.asin(tc)
+    u2 = delta + math.pi - torch.asin(tc)
+    period = 2.0 * math.pi / ws.abs()
+    s1 = lo + torch.remainder(u1 / ws - lo, period)
+    s2 = lo + torch.remainder(u2 / ws - lo, period)
+    s = torch.minimum(s1, s2)
+    # straight-line limit (|w| tiny): s^2 + 2As - (R^2 - r0^2) = 0
+    disc = A * A + d2
+    sq = torch.sqrt(torch.clamp(disc, min=0.0))
+    r1, r2 = -A - sq, -A + sq
+    s_line = torch.where(r1 > lo, r1, r2)
+    line = w.abs() < 1e-9
+    s = torch.where(line, s_line, s)
+    ok = torch.where(line, (disc >= 0) & (s_line > lo), ok)
+    s = torch.where(ok, s, torch.zeros_like(s))
+    for _ in range(newton_steps):
+        h = helix_at(p, q, s, bz)
+        hx, hy, hph = h[..., 0], h[..., 1], h[..., 4]
+        f = hx * hx + hy * hy - R * R
+        df = 2.0 * (hx * torch.cos(hph) + hy * torch.sin(hph))
+        df = torch.where(df.abs() < 1e-30, torch.ones_like(df), df)
+        s = s - torch.where(ok, f / df, torch.zeros_like(f))
+    return s, ok
+
+
+def crossing_disk(p, Z, same=None):
+    """z(s) = Z:  s = (Z - z0) / cot(theta); must be > lo (see _path_window).
+    Returns (s, ok)."""
+    p = _t(p)
+    _, _, z0, _, _, th = p.unbind(-1)
+    if same is None:
+        same = torch.zeros_like(z0, dtype=torch.bool)
+    lo = _path_window(same)
+    cot = torch.cos(th) / torch.sin(th)
+    ok_c = cot.abs() > 1e-15
+    cot_s = torch.where(ok_c, cot, torch.ones_like(cot))
+    s = (_t(Z) - z0) / cot_s
+    ok = ok_c & (s > lo)
+    return torch.where(ok, s, torch.zeros_like(s)), ok
+
+
+def crossing(p, q, kind, pos, bz, same=None):
+    """Path to the layer surface (kind/pos per track); ``same`` marks tracks
+    whose state already sits on that layer."""
+    sb, okb = crossing_barrel(p, q, pos, bz, same)
+    sd, okd = crossing_disk(p, pos, same)
+    isb = kind == BARREL
+    return torch.where(isb, sb, sd), torch.where(isb, okb, okd)
+
+
+# --------------------------------------------------------------------------
+# a2: transport Jacobian (surface to surface)
+# --------------------------------------------------------------------------
+
+def jacobian(p, q, s, kind, bz):
+    """F = dp'/dp of the map 'propagate p to the surface', including the
+    dependence of the path length on p:
+        F = G + g_s (ds/dp),  ds/dp = -(dh/dp)/(dh/ds),
+    G = partials of the helix at fixed s, g_s = d(state)/ds, and h the surface
+    equation (barrel: x^2 + y^2 - R^2, disk: z - Z)."""
+    p, q, s = _t(p), _t(q), _t(s)
+    x0, y0, z0, ipt, phi0, th = p.unbind(-1)
+    w = _safe_omega(omega(q, ipt, bz))
+    dw_dipt = -q * C_LIGHT * bz
+    ph = phi0 + w * s
+    sp, cp = torch.sin(ph), torch.cos(ph)
+    s0, c0 = torch.sin(phi0), torch.cos(phi0)
+    cot = torch.cos(th) / torch.sin(th)
+    one = torch.ones_like(x0)
+    dx_dphi = (cp - c0) / w
+    dy_dphi = (sp - s0) / w
+    # dx/dw = [u cos(phi0+u) - sin(phi0+u) + sin phi0]/w^2 with u = w s; the
+    # bracket is O(u^2), so for |u| < 1e-2 it is expanded about phi0:
+    # dx/dw = s^2 [c0 (-u/3 + u^3/30 - u^5/840) - s0 (1/2 - u^2/8 + u^4/144)]
+    # dy/dw = s^2 [s0 (-u/3 + u^3/30 - u^5/840) + c0 (1/2 - u^2/8 + u^4/144)]
+    u = w * s
+    small = u.abs() < 1e-2
+    us = torch.where(small, u, torch.zeros_like(u))
+    odd = -us / 3.0 + us ** 3 / 30.0 - us ** 5 / 840.0
+    even = 0.5 - us ** 2 / 8.0 + us ** 4 / 144.0
+    ser_x = s * s * (c0 * odd - s0 * even)
+    ser_y = s * s * (s0 * odd + c0 * even)
+    dx_dw = torch.where(small, ser_x, s * cp / w - (sp - s0) / (w * w))
+    dy_dw = torch.where(small, ser_y, s * sp / w + (cp - c0) / (w * w))
+    rows = [
+        [one, 0 * one, 0 * one, dx_dw * dw_dipt, dx_dphi, 0 * one],
+        [0 * one, one, 0 * one, dy_dw * dw_dipt, dy_dphi, 0 * one],
+        [0 * one, 0 * one, one, 0 * one, 0 * one, -s / torch.sin(th) ** 2],
+        [0 * one, 0 * one, 0 * one, one, 0 * one, 0 * one],
+        [0 * one, 0 * one, 0 * one, s * dw_dipt, one, 0 * one],
+        [0 * one, 0 * one, 0 * one, 0 * one, 0 * one, one],
+    ]
+    G = torch.stack([torch.stack(r, dim=-1) for r in rows], dim=-2)
+    g_s = torch.stack([cp, sp, cot, 0 * one, w, 0 * one], dim=-1)
+    h = helix_at(p, q, s, bz)
+    xs, ys = h[..., 0], h[..., 1]
+    dh_dp_b = 2.0 * xs[:, None] * G[:, 0, :] + 2.0 * ys[:, None] * G[:, 1, :]
+    dh_ds_b = 2.0 * (xs * cp + ys * sp)
+    dh_dp_d = G[:, 2, :]
+    dh_ds_d = cot
+    isb = (kind == BARREL)
+    dh_dp = torch.where(isb[:, None], dh_dp_b, dh_dp_d)
+    dh_ds = torch.where(isb, dh_ds_b, dh_ds_d)
+    dh_ds = torch.where(dh_ds.abs() < 1e-30, torch.full_like(dh_ds, 1e-30), dh_ds)
+    ds_dp = -dh_dp / dh_ds[:, None]
+    return G + g_s[:, :, None] * ds_dp[:, None, :]
+
+
+# --------------------------------------------------------------------------
+# a3: material (multiple scattering) and covariance propagation
+# --------------------------------------------------------------------------
+
+def cos_incidence(p, kind):
+    """Cosine of the angle between the momentum and the surface normal:
+    barrel sin(theta) cos(phi - phi_pos), disk |cos(theta)|."""
+    x, y, _, _, ph, th = p.unbind(-1)
+    cb = torch.sin(th) * torch.cos(ph - torch.atan2(y, x))
+    cd = torch.cos(th).abs()
+    return torch.where(kind == BARREL, cb, cd)
+
+
+def highland_theta0(p, kind, x_over_x0, mass):
+    """Highland / PDG plane angle for unit charge:
+    theta0 = 0.0136/(beta p) sqrt(x) (1 + 0.038 ln(x / beta^2)),
+    x = t / |cos(incidence)|.  Returns (theta0, grazing)."""
+    ipt, th = p[..., 3], p[..., 5]
+    ca = cos_incidence(p, kind).abs()
+    grazing = ca < GRAZING_COS
+    ca = torch.clamp(ca, min=GRAZING_COS)
+    pmag = 1.0 / (ipt * torch.sin(th))
+    beta = pmag / torch.sqrt(pmag * pmag + mass * mass)
+    x = x_over_x0 / ca
+    th0 = 0.0136 / (beta * pmag) * torch.sqrt(x) * (1.0 + 0.038 * torch.log(x / (beta * beta)))
+    return th0, grazing
+
+
+def process_noise(p, kind, x_over_x0, mass):
+    """Q in (ipt, phi, theta) for two independent deflections of rms theta0
+    that keep |p|: Q_thth = th0^2, Q_phph = th0^2/sin^2(theta),
+    Q_ipt,ipt = (ipt cot)^2 th0^2, Q_ipt,th = -ipt cot th0^2 (rank 2)."""
+    p = _t(p)
+    th0, grazing = highland_theta0(p, kind, x_over_x0, mass)
+    ipt, th = p[..., 3], p[..., 5]
+    v = th0 * th0
+    cot = torch.cos(th) / torch.sin(th)
+    n = p.shape[0]
+    zero = torch.zeros_like(v)
+    q33 = (ipt * cot) ** 2 * v
+    q35 = -ipt * cot * v
+    q44 = v / torch.sin(th) ** 2
+    q55 = v
+    rows = [[zero] * 6 for _ in range(6)]
+    rows[3][3] = q33
+    rows[3][5] = q35
+    rows[5][3] = q35
+    rows[4][4] = q44
+    rows[5][5] = q55
+    Q = torch.stack([torch.stack(r, dim=-1) for r in rows], dim=-2)
+    return Q, grazing
+
+
+def propagate(p, C, q, kind, pos, x_over_x0, geom, apply_material=True, same=None):
+    """kf_propagate: move (p, C) to the layer surface.  ``same`` (bool per
+    track, default False) marks a re-crossing of the layer the state is on.
+    Returns (p', C', s, status)."""
+    p, C, q = _t(p), _t(C), _t(q)
+    s, ok = crossing(p, q, kind, pos, geom.bz, same)
+    p2 = helix_at(p, q, s, geom.bz)
+    p2 = torch.cat([p2[..., :4], wrap_phi(p2[..., 4:5]), p2[..., 5:]], dim=-1)
+    F = jacobian(p, q, s, kind, geom.bz)
+    C2 = F @ C @ F.transpose(-1, -2)
+    status = torch.where(ok, 0, NO_CROSSING).to(torch.int64)
+    if apply_material:
+        Q, grazing = process_noise(p2, kind, x_over_x0, geom.mass)
+        C2 = C2 + Q
+        status = status | torch.where(grazing, GRAZING, 0)
+    return p2, C2, s, status
+
+
+# --------------------------------------------------------------------------
+# a4/a5: residual, S, chi2, gain, Joseph update
+# --------------------------------------------------------------------------
+
+def update(p, C, q, m, V):
+    """kf_update: Kalman update with a 3-D hit m and its 3x3 covariance V.
+    r = m - Hp, S = H C H^T + V, chi2 = r^T S^-1 r, K = C H^T S^-1,
+    p <- p + K r, C <- (I - KH) C (I - KH)^T + K V K^T, then symmetrized.
+    If ipt turns negative the charge is flipped (ipt, q and row/column 3 of C
+    change sign) so that the curvature is unchanged; phi is wrapped.
+    Returns (p', C', q', chi2, status)."""
+    p, C, q, m, V = _t(p), _t(C), _t(q), _t(m), _t(V)
+    n = p.shape[0]
+    r = m - p[..., :3]
+    S = C[..., :3, :3] + V
+    Sinv = torch.linalg.inv(S)
+    chi2 = torch.einsum("ni,nij,nj->n", r, Sinv, r)
+    K = C[..., :, :3] @ Sinv
+    p2 = p + (K @ r[..., None])[..., 0]
+    H = torch.zeros(3, 6, dtype=DT)
+    H[0, 0] = H[1, 1] = H[2, 2] = 1.0
+    I = torch.eye(6, dtype=DT)
+    IKH = I - K @ H
+    C2 = IKH @ C @ IKH.transpose(-1, -2) + K @ V @ K.transpose(-1, -2)
+    C2 = 0.5 * (C2 + C2.transpose(-1, -2))
+    flip = p2[..., 3] < 0
+    sgn = torch.where(flip, -1.0, 1.0).to(DT)
+    D = torch.ones(n, 6, dtype=DT)
+    D = torch.cat([D[:, :3], sgn[:, None], D[:, 4:]], dim=1)
+    p2 = p2 * D
+    C2 = C2 * D[:, :, None] * D[:, None, :]
+    q2 = q * sgn
+    p2 = torch.cat([p2[..., :4], wrap_phi(p2[..., 4:5]), p2[..., 5:]], dim=-1)
+    # the 6x6 covariance of a state on a surface has the surface normal as a
+    # null vector (rank 5), so a zero position variance is legitimate: flag
+    # only non-positive angle/curvature variances or clearly negative position ones
+    d = torch.diagonal(C2, dim1=-2, dim2=-1)
+    tr_pos = d[..., 0] + d[..., 1] + d[..., 2]
+    diag_bad = (d[..., 3:] <= 0).any(dim=-1) | (d[..., :3] < -1e-6 * tr_pos[..., None]).any(dim=-1)
+    status = torch.where(flip, CHARGE_FLIP, 0) | torch.where(diag_bad, COV_NOT_PSD, 0)
+    return p2, C2, q2, chi2, status.to(torch.int64)
+
+
+# --------------------------------------------------------------------------
+# seeding from three hits
+# --------------------------------------------------------------------------
+
+def seed_from_hits(h1, h2, h3, bz):
+    """Helix through three hits (transverse Menger curvature, then the polar
+    angle from the arc length between hits 1 and 3); position = hit 1.
+    kappa = 2 ((h2-h1) x (h3-h1))_z / (d12 d13 d23), q = -sign(kappa) (+1 at 0),
+    ipt = |kappa|/(c_B B_z), phi1 = atan2(h2-h1) - asin(kappa d12 / 2),
+    s13 = 2 asin(|kappa| d13/2)/|kappa|, cot(theta) = (z3 - z1)/s13.
+    Returns (p, C0, q)."""
+    h1, h2, h3 = _t(h1), _t(h2), _t(h3)
+    dx12, dy12 = h2[..., 0] - h1[..., 0], h2[..., 1] - h1[..., 1]
+    dx13, dy13 = h3[..., 0] - h1[..., 0], h3[..., 1] - h1[..., 1]
+    dx23, dy23 = h3[..., 0] - h2[..., 0], h3[..., 1] - h2[..., 1]
+    d12 = torch.sqrt(dx12 ** 2 + dy12 ** 2)
+    d13 = torch.sqrt(dx13 ** 2 + dy13 ** 2)
+    d23 = torch.sqrt(dx23 ** 2 + dy23 ** 2)
+    cross = dx12 * dy13 - dy12 * dx13
+    kappa = 2.0 * cross / (d12 * d13 * d23)
+    q = torch.where(kappa > 0, -1.0, 1.0).to(DT)
+    ipt = kappa.abs() / (C_LIGHT * bz)
+    phi1 = torch.atan2(dy12, dx12) - torch.asin(torch.clamp(kappa * d12 / 2.0, -1.0, 1.0))
+    ak = kappa.abs()
+    ak_s = torch.where(ak > 0, ak, torch.ones_like(ak))
+    s13 = torch.where(ak > 0, 2.0 * torch.asin(torch.clamp(ak_s * d13 / 2.0, -1.0, 1.0)) / ak_s, d13)
+    cot = (h3[..., 2] - h1[..., 2]) / s13
+    theta = 0.5 * math.pi - torch.atan(cot)
+    p = torch.stack([h1[..., 0], h1[..., 1], h1[..., 2], ipt, wrap_phi(phi1), theta], dim=-1)
+    C0 = torch.diag(_t(SEED_COV_DIAG)).expand(p.shape[0], 6, 6).clone()
+    return p, C0, q
+
+
+def first_three_valid(hit_offsets, hit_valid):
+    """Indices of the first three valid entries of every track (-1 if absent)."""
+    off = torch.as_tensor(hit_offsets, dtype=torch.int64)
+    valid = torch.as_tensor(hit_valid, dtype=torch.int64)
+    n = off.shape[0] - 1
+    lens = off[1:] - off[:-1]
+    track = torch.repeat_interleave(torch.arange(n), lens)
+    csum = torch.cumsum(valid, 0) - valid            # valid entries before e (global)
+    rank = csum - torch.cat([torch.zeros(1, dtype=torch.int64), torch.cumsum(valid, 0)])[off[:-1]][track]
+    out = torch.full((n, 3), -1, dtype=torch.int64)
+    sel = (valid == 1) & (rank < 3)
+    e = torch.nonzero(sel)[:, 0]
+    out[track[e], rank[e]] = e
+    return out
+
+
+SEED_MIN_SPACING = 3.0   # cm, transverse distance between chosen seed hits (mode 1)
+
+
+def spaced_three_valid(hit_offsets, hit_valid, hit_pos, spacing=SEED_MIN_SPACING):
+    """Greedy choice along each track: the first valid entry, then each next
+    valid entry whose transverse distance from the previously chosen hit is at
+    least ``spacing``; three entries, or -1 everywhere if fewer qualify."""
+    off = torch.as_tensor(hit_offsets, dtype=torch.int64)
+    valid = torch.as_tensor(hit_valid, dtype=torch.int64)
+    hp = _t(hit_pos)
+    n = off.shape[0] - 1
+    lens = off[1:] - off[:-1]
+    out = torch.full((n, 3), -1, dtype=torch.int64)
+    cnt = torch.zeros(n, dtype=torch.int64)
+    lastx = torch.zeros(n, dtype=DT)
+    lasty = torch.zeros(n, dtype=DT)
+    maxlen = int(lens.max()) if n else 0
+    ar = torch.arange(n)
+    for j in range(maxlen):
+        has = j < lens
+        e = torch.where(has, off[:-1] + j, torch.zeros_like(lens))
+        hx, hy = hp[0, e], hp[1, e]
+        far = torch.sqrt((hx - lastx) ** 2 + (hy - lasty) ** 2) >= spacing
+        take = has & (valid[e] == 1) & (cnt < 3) & ((cnt == 0) | far)
+        t = ar[take]
+        out[t, cnt[t]] = e[t]
+        lastx = torch.where(take, hx, lastx)
+        lasty = torch.where(take, hy, lasty)
+        cnt = cnt + take.to(torch.int64)
+    out[cnt < 3] = -1
+    return out
+
+
+SEED_FIRST_THREE = 0
+SEED_SPACED = 1
+
+
+def make_seeds(hit_offsets, hit_valid, hit_pos, bz, mode=SEED_FIRST_THREE):
+    """Seed every track from three of its valid hits: the first three
+    (mode 0) or three hits at least SEED_MIN_SPACING apart in the transverse
+    plane (mode 1, a longer lever arm for tracks whose first hits are close
+    together there, such as forward tracks crossing barrel and disk layers).
+    The seed sits on the first valid hit.  Returns (p, C0, q, ok)."""
+    if mode == SEED_FIRST_THREE:
+        idx = first_three_valid(hit_offsets, hit_valid)
+    else:
+        idx = spaced_three_valid(hit_offsets, hit_valid, hit_pos)
+    ok = (idx >= 0).all(dim=1)
+    hp = _t(hit_pos)
+    safe = torch.where(idx >= 0, idx, torch.zeros_like(idx))
+    h = [hp[:, safe[:, i]].T for i in range(3)]
+    p, C0, q = seed_from_hits(h[0], h[1], h[2], bz)
+    return p, C0, q, ok
+
+
+# --------------------------------------------------------------------------
+# alignment of barrel hits
+# --------------------------------------------------------------------------
+
+def aligned_hits(hit_pos, hit_layer, geom, align):
+    """Apply per-layer corrections to barrel hits: rotate about z by a_rphi/R
+    (R = the layer radius) and shift z by a_z.  Disk hits are unchanged.
+    hit_pos: [3, nh] tensor; align: [2, L] tensor or None.  Returns [nh, 3]."""
+    h = hit_pos.T
+    if align is None:
+        return h
+    lay = torch.as_tensor(hit_layer, dtype=torch.int64)
+    kind = torch.as_tensor(geom.kind, dtype=torch.int64)[lay]
+    R = _t(geom.pos)[lay]
+    isb = kind == BARREL
+    ang = torch.where(isb, align[0][lay] / R, torch.zeros_like(R))
+    dz = torch.where(isb, align[1][lay], torch.zeros_like(R))
+    c, s = torch.cos(ang), torch.sin(ang)
+    x = c * h[:, 0] - s * h[:, 1]
+    y = s * h[:, 0] + c * h[:, 1]
+    z = h[:, 2] + dz
+    return torch.stack([x, y, z], dim=-1)
+
+
+# --------------------------------------------------------------------------
+# a6: the per-track layer loop
+# --------------------------------------------------------------------------
+
+def unpack_sym(packed, n):
+    """[k, N] packed lower triangle (row-major, idx(i,j) = i(i+1)/2 + j) -> [N, n, n]."""
+    P = torch.as_tensor(packed, dtype=DT)
+    N = P.shape[1]
+    M = torch.zeros(N, n, n, dtype=DT)
+    k = 0
+    for i in range(n):
+        for j in range(i + 1):
+            M[:, i, j] = P[k]
+            M[:, j, i] = P[k]
+            k += 1
+    return M
+
+
+def pack_sym(M):
+    n = M.shape[-1]
+    out = []
+    for i in range(n):
+        for j in range(i + 1):
+            out.append(M[..., i, j])
+    return torch.stack(out, dim=0)
+
+
+def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
+               align=None):
+    """kf_fit_tracks: forward Kalman fit of every track.
+
+    Each track starts at its seed, which sits on its first valid entry k0
+    (entries before k0 are skipped).  At k0 the material of that layer is added
+    at the seed; at every later entry the state is propagated to the entry's
+    layer and the layer's material is added; valid entries are then used in an
+    update and their chi2 summed.  The crossing of entry k is searched with the
+    re-crossing window when entry k-1 was on the same layer (a looper turning
+    round), otherwise with the window that admits a short backward step.  A
+    failed crossing or a non-finite result freezes the track at its last good
+    state.
+
+    seed_p [n,6], seed_C [n,6,6], seed_q [n] tensors (may require grad);
+    hit_pos [3,nh] tensor (may require grad); hit_cov [6,nh] packed;
+    align [2,L] tensor or None.
+    Returns dict(p, C, q, chi2, ndf, status)."""
+    off = torch.as_tensor(hit_offsets, dtype=torch.int64)
+    lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
+    val_all = torch.as_tensor(hit_valid, dtype=torch.int64)
+    V_all = unpack_sym(hit_cov, 3)
+    hp = hit_pos if torch.is_tensor(hit_pos) else _t(hit_pos)
+    m_all = aligned_hits(hp, lay_all, geom, align)
+    kind_l = torch.as_tensor(geom.kind, dtype=torch.int64)
+    pos_l = _t(geom.pos)
+    x0_l = _t(geom.x_over_x0)
+    n = off.shape[0] - 1
+
+    # first valid entry of each track
+    k0 = torch.full((n,), -1, dtype=torch.int64)
+    lens = off[1:] - off[:-1]
+    maxlen = int(lens.max()) if n > 0 else 0
+    for j in range(maxlen - 1, -1, -1):
+        e = off[:-1] + j
+        has = (j < lens)
+        ev = torch.where(has, e, torch.zeros_like(e))
+        k0 = torch.where(has & (val_all[ev] == 1), e, k0)
+
+    p = seed_p
+    C = seed_C
+    q = seed_q.to(DT)
+    chi2 = torch.zeros(n, dtype=DT) + 0.0 * seed_p[:, 0]
+    nval = torch.zeros(n, dtype=torch.int64)
+    status = torch.zeros(n, dtype=torch.int64)
+    alive = k0 >= 0
+    end = off[1:]
+
+    prev_e = k0.clone()
+    for j in range(maxlen):
+        e = k0 + j
+        act = alive & (e < end)
+        idx = torch.nonzero(act)[:, 0]
+        if idx.numel() == 0:
+            break
+        ei = e[idx]
+        lay = lay_all[ei]
+        kind = kind_l[lay]
+        pp, CC, qq = p[idx], C[idx], q[idx]
+        st = torch.zeros(idx.numel(), dtype=torch.int64)
+        if j > 0:
+            same = lay == lay_all[prev_e[idx]]
+            pp2, CC2, _, st_p = propagate(pp, CC, qq, kind, pos_l[lay], x0_l[lay], geom, apply_material=True,
+                                          same=same)
+        else:
+            Q, grazing = process_noise(pp, kind, x0_l[lay], geom.mass)
+            pp2, CC2 = pp, CC + Q
+            st_p = torch.where(grazing, GRAZING, 0).to(torch.int64)
+        st = st | st_p
+        good = (st_p & NO_CROSSING) == 0
+        valid = (val_all[ei] == 1) & good
+        pu, Cu, qu, c2, st_u = update(pp2, CC2, qq, m_all[ei], V_all[ei])
+        vmask = valid
+        pn = torch.where(vmask[:, None], pu, pp2)
+        Cn = torch.where(vmask[:, None, None], Cu, CC2)
+        qn = torch.where(vmask, qu, qq)
+        c2n = torch.where(vmask, c2, torch.zeros_like(c2))
+        st = st | torch.where(vmask, st_u, 0)
+        finite = torch.isfinite(pn).all(dim=1) & torch.isfinite(Cn).flatten(1).all(dim=1) & torch.isfinite(c2n)
+        st = st | torch.where(finite, 0, NONFINITE)
+        keep = good & finite
+        # frozen tracks keep their previous state
+        pn = torch.where(keep[:, None], pn, pp)
+        Cn = torch.where(keep[:, None, None], Cn, CC)
+        qn = torch.where(keep, qn, qq)
+        c2n = torch.where(keep, c2n, torch.zeros_like(c2n))
+        p = p.index_put((idx,), pn)
+        C = C.index_put((idx,), Cn)
+        q = q.index_put((idx,), qn)
+        chi2 = chi2.index_put((idx,), chi2[idx] + c2n)
+        nval = nval.index_put((idx,), nval[idx] + (vmask & keep).to(torch.int64))
+        status = status.index_put((idx,), status[idx] | st)
+        alive = alive.index_put((idx,), keep)
+        prev_e = prev_e.index_put((idx,), ei)
+    return dict(p=p, C=C, q=q, chi2=chi2, ndf=2 * nval - 5, status=status)
+
+
+def fit_event(ev, align=None, seed_mode=SEED_FIRST_THREE):
+    """Convenience: seed (first three valid hits, or spaced hits), then fit."""
+    sp, sC, sq, ok = make_seeds(ev.hit_offsets, ev.hit_valid, ev.hit_pos, ev.geometry.bz, mode=seed_mode)
+    out = fit_tracks(sp, sC, sq, ev.hit_offsets, ev.hit_layer, ev.hit_valid, _t(ev.hit_pos), ev.hit_cov,
+                     ev.geometry, align=align)
+    out["seed_p"], out["seed_q"], out["seed_ok"] = sp, sq, ok
+    return out
+
+
+# --------------------------------------------------------------------------
+# a8: gradient of sum_t w_t chi2_t (reverse-mode autodiff of the oracle)
+# --------------------------------------------------------------------------
+
+def fit_gradients(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
+                  align=None, weights=None):
+    """d(sum_t w_t chi2_t)/d(seed state, hit positions, alignment), by autograd
+    through fit_tracks (a mechanism independent of any hand-written reverse).
+    Returns (loss, g_seed [n,6], g_hits [3,nh], g_align [2,L], fit_out)."""
+    sp = _t(seed_p).detach().clone().requires_grad_(True)
+    hp = _t(hit_pos).detach().clone().requires_grad_(True)
+    L = len(geom.kind)
+    al = (torch.zeros(2, L, dtype=DT) if align is None else _t(align)).detach().clone().requires_grad_(True)
+    out = fit_tracks(sp, _t(seed_C), _t(seed_q), hit_offsets, hit_layer, hit_valid, hp, hit_cov, geom, align=al)
+    w = torch.ones_like(out["chi2"]) if weights is None else _t(weights)
+    loss = (w * out["chi2"]).sum()
+    gs, gh, ga = torch.autograd.grad(loss, [sp, hp, al], allow_unused=True)
+    gs = torch.zeros_like(sp) if gs is None else gs
+    gh = torch.zeros_like(hp) if gh is None else gh
+    ga = torch.zeros_like(al) if ga is None else ga
+    return loss.detach(), gs, gh, ga, {k: (v.detach() if torch.is_tensor(v) else v) for k, v in out.items()}
