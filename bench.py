@@ -1,0 +1,172 @@
+"""Benchmark of the Kalman-filter hot path on one MI355X.
+
+A step is one pass of the hot path over one batch: seeding plus the fused
+per-track fit (propagation, Jacobian, covariance propagation with scattering,
+residual-covariance inverse, gain, Joseph update, chi2) of the 100,000-track,
+20-layer barrel workload in FP32, with inputs resident in HBM.  The JSON line
+also carries the plain-FP64 GPU rate on the same batch, the accuracy of the
+FP32 results against the FP64 CPU oracle, the roofline position of the fit
+kernel and the oracle's own rate on the host cores."""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+
+# algorithmic work per fitted entry (FLOP; transcendental = 1): see the
+# operation count of the per-entry step in the design notes
+FLOP_VALID_ENTRY = 1280
+FLOP_HOLE_ENTRY = 475
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(ev):
+    valid = int(ev.hit_valid.sum())
+    holes = int(ev.hit_valid.size - valid)
+    return valid * FLOP_VALID_ENTRY + holes * FLOP_HOLE_ENTRY
+
+
+def algorithmic_bytes(ev, elem):
+    n, nh = ev.n_tracks, ev.n_hits
+    per_hit = 9 * elem + 2 + 1            # pos + cov, layer id, valid flag
+    per_track = (27 * elem + 1) * 2 + 4 + elem + 4 + 4   # seed in, fit out, offsets, chi2, ndf, status
+    return nh * per_hit + n * per_track
+
+
+def time_loop(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps   # ms
+
+
+def cpu_baseline(ev, seconds=10.0):
+    import torch
+    from oracle import kf_oracle as O
+    t0 = time.time()
+    reps = 0
+    while True:
+        O.fit_event(ev)
+        reps += 1
+        if time.time() - t0 > seconds:
+            break
+    dt = time.time() - t0
+    return dict(value=reps * ev.n_tracks / dt, unit="tracks/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{reps} x full batch of {ev.n_tracks} tracks (seeding + fit, float64 torch CPU)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (tracks are independent: "
+              "a multi-GPU run would shard the batch by track with no communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2312_11728_amd import kf as K
+    from toygen import generate, workloads
+
+    dev = torch.device("cuda", 0)
+    wl = workloads()["barrel20"]
+    log("generating", wl.name, wl.n_tracks)
+    ev = generate(wl)
+    ctx = K.Context(0)
+    geom = K.Geometry.from_toy(wl.geometry)
+    res = {}
+    for dt in (torch.float32, torch.float64):
+        t = K.event_tensors(ev, dt, dev)
+        n = ev.n_tracks
+        seeds = (torch.empty(6, n, dtype=dt, device=dev), torch.empty(21, n, dtype=dt, device=dev),
+                 torch.empty(n, dtype=torch.int8, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+        out = K.fit_outputs(n, dt, dev)
+
+        def seed_step():
+            ctx.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"], wl.geometry.bz, 0, out=seeds)
+
+        def fit_step():
+            ctx.fit_tracks(seeds[0], seeds[1], seeds[2], t["hit_offsets"], t["hit_layer"], t["hit_valid"],
+                           t["hit_pos"], t["hit_cov"], geom, out=out)
+
+        def step():
+            seed_step()
+            fit_step()
+
+        log("timing", dt)
+        ms_step = time_loop(step, args.steps, args.warmup)
+        ms_fit = time_loop(fit_step, args.steps, args.warmup)
+        res[dt] = dict(ms_step=ms_step, ms_fit=ms_fit, out=out, seeds=seeds)
+        log(dt, "ms/step", ms_step, "fit kernel ms", ms_fit)
+
+    r32, r64 = res[torch.float32], res[torch.float64]
+    n = ev.n_tracks
+    flops = algorithmic_flops(ev)
+    achieved_tf = flops / (r32["ms_fit"] * 1e-3) / 1e12
+    line = {
+        "metric": "fitted tracks/s (FP32 batched Kalman fit)",
+        "value": n / (r32["ms_step"] * 1e-3),
+        "unit": "tracks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded toy helices, 3.8 T, 0.02 X0 per layer)",
+        "config": {"workload": "barrel20: 100000 tracks x 20 barrel layers, seeded from the first 3 hits",
+                   "tracks": n, "entries": int(ev.n_hits)},
+        "fp64_gpu": {"value": n / (r64["ms_step"] * 1e-3), "unit": "tracks/s", "ms_per_step": r64["ms_step"]},
+        "fp32_over_fp64": r64["ms_step"] / r32["ms_step"],
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "fit_kernel<float>", "kernel_ms": r32["ms_fit"],
+                     "algorithmic_flop_per_launch": flops,
+                     "algorithmic_bytes_per_launch": algorithmic_bytes(ev, 4)},
+    }
+    if not args.no_accuracy:
+        from parity import chi2_error, gpu_fit, ill_conditioned, oracle_fit, param_error
+        o = oracle_fit(ev, torch.float32, 0)
+        g = dict(p=r32["out"]["state"].double().cpu().numpy().T, chi2=r32["out"]["chi2"].double().cpu().numpy())
+        bad = ill_conditioned(ev, torch.float32, o, 0)
+        ep = param_error(g["p"], o["p"]).max(axis=1)
+        ec = chi2_error(g["chi2"], o["chi2"])
+        line["accuracy_vs_oracle"] = {"max_param_err": float(ep[~bad].max()), "max_chi2_err": float(ec[~bad].max()),
+                                      "tracks_compared": int((~bad).sum()), "ill_conditioned": int(bad.sum()),
+                                      "tolerance": {"param": 1e-4, "chi2": 1e-3}}
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(ev)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

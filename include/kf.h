@@ -1,0 +1,251 @@
+/*
+ * kf.h -- C interface of the MI355X Kalman-filter track-fit library (libkf.so).
+ *
+ * The library runs the per-layer step of Kalman-filter track reconstruction
+ * over many tracks at once: propagation of each track to its next detector
+ * layer, the covariance propagation C' = F C F^T + Q with multiple scattering,
+ * the residual-covariance inverse, the gain and state/covariance update, and
+ * chi2 scoring of candidate hits.  The paper (Sec. 2.2 "Track finding
+ * algorithm") names these as the processing steps of track finding and
+ * (Sec. 3.1 "Geometry & detector description") as the vectorised key
+ * computations: track-candidate propagation, hit selection and Kalman-filter
+ * calculations.  A seed is a list of hits plus an initial parameter estimate
+ * (Sec. 2.2); a layer is an r-z bounding box in global cylindrical coordinates
+ * with its material (Sec. 3.1); configuration carries no global state
+ * (Sec. 3, opening paragraphs, and Sec. 3.2).
+ *
+ * Conventions (all entry points)
+ *   Units: cm, GeV/c, tesla, radians.
+ *   Track state p = (x, y, z, ipt, phi, theta), ipt = 1/pT >= 0, phi in
+ *   (-pi, pi], theta in (0, pi); the charge q = +-1 is a separate int8.
+ *   Symmetric matrices are packed lower-triangular, row-major:
+ *   idx(i, j) = i*(i+1)/2 + j for j <= i (6x6 -> 21 entries, 3x3 -> 6).
+ *   Array pointers named *_state, *_cov, hit_*, chi2, ... are DEVICE pointers
+ *   owned by the caller.  Structure-of-arrays: element (i, t) of a [k][ld]
+ *   array is at base[i*ld + t]; ld >= n.  Float arrays hold float (KF_F32) or
+ *   double (KF_F64) as selected by the precision argument.
+ *   `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *   and return; none synchronises the stream.  No call allocates device
+ *   memory except kf_create.
+ *   Errors: every call returns a kf_status.  KF_ERR_ARG is returned before any
+ *   device work for a null pointer, n < 0, ld < n, a bad geometry or another
+ *   invalid scalar argument; KF_ERR_DEVICE wraps a HIP error.  kf_last_error()
+ *   gives a message for the last non-OK return on the calling thread.
+ *   Per-track numerical trouble never fails a call: it sets bits in the
+ *   per-track status word and leaves finite outputs.
+ *   Concurrency: one kf_ctx may be used by one host thread / one stream at a
+ *   time (it owns a small device work counter); separate contexts are
+ *   independent.
+ */
+#ifndef KF_H
+#define KF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KF_OK = 0,
+  KF_ERR_ARG = -1,
+  KF_ERR_DEVICE = -2,
+  KF_ERR_NOMEM = -3,
+  KF_ERR_UNSUPPORTED = -4
+} kf_status;
+
+typedef enum { KF_F32 = 0, KF_F64 = 1 } kf_precision;
+
+/* Per-track status bits (OR-ed). */
+enum {
+  KF_TRK_NO_CROSSING = 1u,   /* the helix does not reach the target surface; track frozen */
+  KF_TRK_GRAZING = 2u,       /* |cos(incidence)| < 0.05 at a crossing; material clamped there */
+  KF_TRK_NONFINITE = 4u,     /* a step produced a non-finite value; track frozen before it */
+  KF_TRK_FP64_FALLBACK = 8u, /* a 3x3 inverse was recomputed in FP64 (FP32 path only) */
+  KF_TRK_CHARGE_FLIP = 16u,  /* an update turned 1/pT negative; charge flipped */
+  KF_TRK_COV_NOT_PSD = 32u,  /* a variance became negative after an update */
+  KF_TRK_BAD_INPUT = 64u     /* layer id out of range or fewer than 3 valid hits for seeding */
+};
+
+/* Detector description.  HOST struct and HOST arrays, read during the call
+ * (copied into the kernel arguments), so it may be freed when the call returns.
+ * A layer is a barrel cylinder r = pos with z in [lo, hi] or an endcap disk
+ * z = pos with r in [lo, hi] (an r-z box).  x_over_x0 is its thickness in
+ * radiation lengths at normal incidence.  1 <= n_layers <= KF_MAX_LAYERS. */
+#define KF_MAX_LAYERS 64
+typedef struct {
+  int32_t n_layers;
+  const int8_t *kind;       /* 0 = barrel cylinder, 1 = endcap disk */
+  const double *pos;        /* R (barrel) or Z (disk) */
+  const double *lo, *hi;    /* barrel: zmin, zmax; disk: rmin, rmax */
+  const double *x_over_x0;  /* material per crossing at normal incidence */
+  double bz_tesla;          /* uniform solenoidal field, != 0 */
+  double particle_mass_gev; /* mass hypothesis for the scattering angle, > 0 */
+} kf_geometry;
+
+typedef struct kf_ctx kf_ctx;
+
+/* Create a context on HIP device `hip_device` (allocates a few bytes of device
+ * work counters).  Returns KF_ERR_DEVICE if the device cannot be used. */
+int kf_create(kf_ctx **out, int hip_device);
+/* Destroy a context (NULL is a no-op).  Waits for nothing: the caller must not
+ * destroy a context with work still queued. */
+int kf_destroy(kf_ctx *ctx);
+/* Message for the last non-OK return on the calling thread ("" if none). */
+const char *kf_last_error(void);
+
+/* Seed every track from three of its valid hits (helix through three points:
+ * transverse Menger curvature, then the polar angle from the arc length;
+ * position = the first chosen hit).  mode 0: the first three valid hits.
+ * mode 1: the first valid hit, then each next valid hit at least 3 cm away
+ * (transverse) from the previously chosen one -- a longer lever arm for tracks
+ * whose first hits are close in the transverse plane.  The seed covariance is
+ * diag(1, 1, 1, 1, 0.01, 0.01) (a diffuse prior).
+ * Inputs: hit_offsets[n+1] (CSR into the hit arrays), hit_valid[n_hits],
+ * hit_pos[3][n_hits].  Outputs: seed_state[6][ld], seed_cov[21][ld],
+ * seed_charge[n], trk_status[n] (overwritten; KF_TRK_BAD_INPUT if fewer than
+ * three hits qualify, the seed is then zero with the prior covariance). */
+int kf_make_seeds(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                  const int32_t *hit_offsets, const uint8_t *hit_valid, int64_t n_hits,
+                  const void *hit_pos, double bz_tesla, int32_t mode,
+                  void *seed_state, void *seed_cov, int8_t *seed_charge,
+                  uint32_t *trk_status, void *stream);
+
+/* Propagate n tracks to their target layers (rows a1-a3 of the hot path):
+ * exact helix in the uniform field to the first admissible crossing of the
+ * target surface, the surface-to-surface Jacobian F (including the dependence
+ * of the path length on the state), C' = F C F^T, and, if apply_material, the
+ * multiple-scattering noise Q of the target layer evaluated at the propagated
+ * state (Highland angle, rank 2 in (ipt, phi, theta)).
+ * Crossing rule: the first root with path s > -1 cm, or s > 0.01 cm when
+ * from_layer[t] == target_layer[t] (a looper re-crossing the layer it sits on).
+ * from_layer may be NULL (never the same layer).
+ * state_in/out [6][ld], cov_in/out [21][ld] (in and out may alias),
+ * charge[n], target_layer[n], path_len[n] (transverse path, may be NULL),
+ * trk_status[n] (bits OR-ed in).  A track with no crossing is copied
+ * unchanged and gets KF_TRK_NO_CROSSING. */
+int kf_propagate(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                 const void *state_in, const void *cov_in, const int8_t *charge,
+                 const int16_t *target_layer, const int16_t *from_layer,
+                 const kf_geometry *geom, int32_t apply_material,
+                 void *state_out, void *cov_out, void *path_len,
+                 uint32_t *trk_status, void *stream);
+
+/* Kalman update with one 3-D hit per track (rows a4-a5): r = m - (x, y, z),
+ * S = C_pos + V, S^-1 (FP32: cofactors, recomputed in FP64 when the condition
+ * estimate ||S||inf ||S^-1||inf exceeds 1e6, det <= 0 or non-finite),
+ * chi2 = r^T S^-1 r, K = C H^T S^-1, p += K r, symmetrised Joseph form
+ * C = (I-KH) C (I-KH)^T + K V K^T; if ipt turns negative the charge flips
+ * (ipt, q and row/column 3 of C change sign); phi wrapped to (-pi, pi].
+ * state[6][ld], cov[21][ld], charge[n] updated in place; hit_pos[3][ld],
+ * hit_cov[6][ld]; chi2[n] out; trk_status[n] bits OR-ed in. */
+int kf_update(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+              void *state, void *cov, int8_t *charge,
+              const void *hit_pos, const void *hit_cov,
+              void *chi2, uint32_t *trk_status, void *stream);
+
+/* Forward Kalman fit of n tracks with uneven hit lists (row a6).
+ * Track t owns entries [hit_offsets[t], hit_offsets[t+1]) of the hit arrays,
+ * in crossing order: hit_layer[e] (layer id), hit_valid[e] (0 = hole: the
+ * layer's material is applied but no update), hit_pos[3][n_hits],
+ * hit_cov[6][n_hits].  The seed (seed_state[6][ld], seed_cov[21][ld],
+ * seed_charge[n]) sits on the track's first valid entry; the material of that
+ * layer is added there, then every later entry is propagated to (with the
+ * crossing rule of kf_propagate, from = the previous entry's layer), gets its
+ * layer's material and, if valid, an update.  align (device, [2][n_layers] or
+ * NULL) corrects barrel hits: rotation about z by align[0][l]/R_l and a z
+ * shift align[1][l]; disk hits are not corrected.
+ * Outputs: state_out[6][ld], cov_out[21][ld], charge_out[n], chi2[n] (sum),
+ * ndf[n] (= 2 * used hits - 5), trk_status[n] (overwritten).
+ * checkpoints: NULL, or a [28][ld * n_seg] buffer receiving (state, cov,
+ * charge) before entry 1 + j*seg of each track's fit (j = 0..n_seg-1,
+ * n_seg = ceil((max_len - 1) / seg)); used by kf_fit_adjoint.  max_len bounds
+ * every track's entry count (<= 64). */
+int kf_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                  const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
+                  const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
+                  int64_t n_hits, const void *hit_pos, const void *hit_cov,
+                  const kf_geometry *geom, const void *align,
+                  void *state_out, void *cov_out, int8_t *charge_out,
+                  void *chi2, int32_t *ndf,
+                  void *checkpoints, int32_t seg, int32_t max_len,
+                  uint32_t *trk_status, void *stream);
+
+/* Combinatorial chi2 scoring of candidate hits (row a7): see the definition
+ * of kf_search_params and kf_score_hits below. */
+typedef struct {
+  int32_t beam;          /* candidates kept per seed (<= 8) */
+  float chi2_max;        /* hits with chi2 above this are rejected */
+  float n_sigma;         /* window half-width in predicted standard deviations */
+  float hit_bonus;       /* score added per accepted hit (score = parent + bonus - chi2) */
+  float miss_penalty;    /* score subtracted for a layer with no accepted hit */
+  int32_t max_miss;      /* candidates with more misses are dropped */
+  float sigma_rphi, sigma_z;  /* hit resolutions added to the window */
+  const float *win_min_rphi, *win_max_rphi, *win_min_z, *win_max_z; /* [n_layers], HOST */
+} kf_search_params;
+
+/* For every seed, run the per-layer candidate search over the layer plan
+ * (barrel layers only): each live candidate is propagated to the layer and
+ * gets its material; its window is w = clamp(n_sigma * sqrt(var + sigma^2),
+ * win_min, win_max) in r-phi (dphi = w/R) and z; every pool hit inside the
+ * window gets its chi2; hits with chi2 <= chi2_max become children scored
+ * parent + hit_bonus - chi2; a candidate with no accepted hit gets one miss
+ * child scored parent - miss_penalty (dropped beyond max_miss misses).  Per
+ * seed the children are ranked by (score desc, hit id asc with a miss after
+ * every hit, parent rank asc) and the best `beam` are kept and updated with
+ * their hits.
+ * Seeds: seed_state[6][ld], seed_cov[21][ld], seed_charge[n] (states on the
+ * layer before the plan).  layer_plan[plan_len] (HOST).
+ * Pools: pool_layer_offsets[n_layers+1] (HOST), pool_pos[3][n_pool],
+ * pool_cov[6][n_pool], pool_hit_id[n_pool] (device; ids are what the output
+ * reports and what breaks ties).
+ * Outputs: cand_hits[n][beam][plan_len] (hit id, -1 = miss, -2 = no such
+ * candidate), cand_score[n][beam], cand_state[6][ld*beam] (may be NULL),
+ * trk_status[n] (overwritten). */
+int kf_score_hits(kf_ctx *ctx, int64_t n, int64_t ld,
+                  const float *seed_state, const float *seed_cov, const int8_t *seed_charge,
+                  const int16_t *layer_plan, int32_t plan_len,
+                  const kf_geometry *geom, const kf_search_params *params,
+                  const int32_t *pool_layer_offsets, int64_t n_pool,
+                  const float *pool_pos, const float *pool_cov, const int32_t *pool_hit_id,
+                  int32_t *cand_hits, float *cand_score, float *cand_state,
+                  uint32_t *trk_status, void *stream);
+
+/* Gradient of L = sum_t w_t chi2_t of kf_fit_tracks (FP32 only, row a8) with
+ * respect to the seed states, the hit positions and the per-layer alignment
+ * offsets, by a hand-written reverse pass.  The forward states are recomputed
+ * segment by segment from the checkpoints written by kf_fit_tracks (same seg,
+ * max_len and inputs) instead of being stored for every layer.
+ * dL_dchi2[n] = w (NULL = all ones).  Outputs: grad_seed[6][ld],
+ * grad_hit_pos[3][n_hits], grad_align[2][n_layers] (overwritten; a
+ * deterministic sum over tracks; may be NULL when align is NULL).
+ * Inputs as for kf_fit_tracks; trk_status[n] from that call (tracks with
+ * NO_CROSSING/NONFINITE/BAD_INPUT contribute only up to their frozen state). */
+int kf_fit_adjoint(kf_ctx *ctx, int64_t n, int64_t ld,
+                   const float *seed_state, const float *seed_cov, const int8_t *seed_charge,
+                   const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
+                   int64_t n_hits, const float *hit_pos, const float *hit_cov,
+                   const kf_geometry *geom, const float *align,
+                   const float *checkpoints, int32_t seg, int32_t max_len,
+                   const float *dL_dchi2,
+                   float *grad_seed, float *grad_hit_pos, float *grad_align,
+                   const uint32_t *trk_status, void *stream);
+
+/* ---- execution tuning (no effect on results) --------------------------------
+ * Launch shape of kf_fit_tracks for one precision: threads per block (64, 128,
+ * 192 or 256), persistent (1: a fixed grid of n_cu * blocks_per_cu blocks that
+ * pull tiles of `block` tracks from a device counter; 0: one thread per track)
+ * and blocks_per_cu (1..32).  Every launch shape computes bit-identical
+ * results; the choice is made by the autotuner of the Python package and only
+ * changes speed.  Stored in the context. */
+int kf_set_fit_launch(kf_ctx *ctx, kf_precision prec, int32_t block, int32_t persistent, int32_t blocks_per_cu);
+int kf_get_fit_launch(const kf_ctx *ctx, kf_precision prec, int32_t *block, int32_t *persistent,
+                      int32_t *blocks_per_cu);
+/* Number of compute units of the context's device. */
+int kf_device_cu_count(const kf_ctx *ctx, int32_t *n_cu);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KF_H */

@@ -308,7 +308,7 @@ def propagate(p, C, q, kind, pos, x_over_x0, geom, apply_material=True, same=Non
     if apply_material:
         Q, grazing = process_noise(p2, kind, x_over_x0, geom.mass)
         C2 = C2 + Q
-        status = status | torch.where(grazing, GRAZING, 0)
+        status = status | torch.where(grazing & ok, GRAZING, 0)
     return p2, C2, s, status
 
 

@@ -1,0 +1,12 @@
+"""MI355X-native Kalman-filter track-fit hot path (HIP kernels behind a C
+interface, include/kf.h).  ``kf`` is the ctypes binding; importing it loads
+libkf.so and fails if the library is not built."""
+
+__all__ = ["kf"]
+
+
+def __getattr__(name):
+    if name == "kf":
+        from . import kf
+        return kf
+    raise AttributeError(name)

@@ -1,0 +1,105 @@
+// Kernel argument structures and launch helpers shared by the host API.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kf_math.hpp"
+
+namespace kf {
+
+constexpr int kMaxLayers = 64;
+
+// Detector description passed by value in the kernel arguments.
+struct GeomArgs {
+  int32_t n_layers;
+  int8_t kind[kMaxLayers];
+  double pos[kMaxLayers];
+  double x0[kMaxLayers];
+  double bz;
+  double mass;
+};
+
+template <typename T>
+struct SeedArgs {
+  int64_t n, ld, n_hits;
+  const int32_t* hit_offsets;
+  const uint8_t* hit_valid;
+  const T* hit_pos;
+  double bz;
+  int32_t mode;
+  T* seed_state;
+  T* seed_cov;
+  int8_t* seed_charge;
+  uint32_t* trk_status;
+};
+
+template <typename T>
+struct PropArgs {
+  int64_t n, ld;
+  const T* state_in;
+  const T* cov_in;
+  const int8_t* charge;
+  const int16_t* target;
+  const int16_t* from;
+  int32_t material;
+  T* state_out;
+  T* cov_out;
+  T* path;
+  uint32_t* trk_status;
+};
+
+template <typename T>
+struct UpdArgs {
+  int64_t n, ld;
+  T* state;
+  T* cov;
+  int8_t* charge;
+  const T* hit_pos;
+  const T* hit_cov;
+  T* chi2;
+  uint32_t* trk_status;
+};
+
+template <typename T>
+struct FitArgs {
+  int64_t n, ld, n_hits;
+  const T* seed_state;
+  const T* seed_cov;
+  const int8_t* seed_charge;
+  const int32_t* hit_offsets;
+  const int16_t* hit_layer;
+  const uint8_t* hit_valid;
+  const T* hit_pos;
+  const T* hit_cov;
+  const T* align;  // [2][n_layers] or null
+  T* state_out;
+  T* cov_out;
+  int8_t* charge_out;
+  T* chi2;
+  int32_t* ndf;
+  T* ckpt;  // [28][ld * n_seg] or null
+  int32_t seg;
+  int32_t n_seg;
+  uint32_t* trk_status;
+  int32_t* tile_counter;  // persistent mode
+  int64_t n_tiles;
+};
+
+// Launch functions (defined in kf_kernels.hip).
+template <typename T>
+hipError_t launch_seeds(const SeedArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_propagate(const PropArgs<T>& a, const GeomArgs& g, hipStream_t s);
+template <typename T>
+hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s);
+
+struct FitLaunch {
+  int block;        // threads per block (multiple of 64)
+  int persistent;   // 0: one thread per track; 1: persistent blocks pulling tiles
+  int blocks_per_cu;
+};
+template <typename T>
+hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s);
+
+}  // namespace kf

@@ -1,0 +1,556 @@
+// Per-lane Kalman-filter step for one track: helix propagation to a layer
+// surface, transport Jacobian, covariance propagation with multiple
+// scattering, and the Kalman update.  Templated on the arithmetic type (float
+// or double); every function works on registers of one lane.
+//
+// The paper (Sec. 3.1) lists these as the vectorised key computations
+// (track-candidate propagation, hit selection, Kalman-filter calculations);
+// the formulas are the standard ones for a helix in a uniform solenoidal field,
+// the Highland scattering angle and the linear Kalman filter, written here in
+// forms that keep FP32 accurate (chord forms, a half-angle quadratic for the
+// crossing, series for small turning angles).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kf {
+
+constexpr double kCLight = 0.00299792458;  // GeV/c per (T cm)
+constexpr double kGrazingCos = 0.05;
+constexpr double kSBack = 1.0;    // cm: a different layer may be this far behind
+constexpr double kSSame = 0.01;   // cm: minimum path to re-cross the current layer
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+constexpr double kKappaMax = 1e6;  // condition estimate that triggers the FP64 inverse
+
+enum : uint32_t {
+  TRK_NO_CROSSING = 1u,
+  TRK_GRAZING = 2u,
+  TRK_NONFINITE = 4u,
+  TRK_FP64_FALLBACK = 8u,
+  TRK_CHARGE_FLIP = 16u,
+  TRK_COV_NOT_PSD = 32u,
+  TRK_BAD_INPUT = 64u,
+};
+
+// packed lower-triangular index of a symmetric matrix
+__host__ __device__ constexpr int sym(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+// ---- type-generic math -----------------------------------------------------
+__device__ __forceinline__ float k_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double k_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float k_abs(float x) { return fabsf(x); }
+__device__ __forceinline__ double k_abs(double x) { return fabs(x); }
+__device__ __forceinline__ void k_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void k_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ float k_atan2(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double k_atan2(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ float k_atan(float x) { return atanf(x); }
+__device__ __forceinline__ double k_atan(double x) { return atan(x); }
+__device__ __forceinline__ float k_log(float x) { return logf(x); }
+__device__ __forceinline__ double k_log(double x) { return log(x); }
+__device__ __forceinline__ float k_floor(float x) { return floorf(x); }
+__device__ __forceinline__ double k_floor(double x) { return floor(x); }
+__device__ __forceinline__ float k_ceil(float x) { return ceilf(x); }
+__device__ __forceinline__ double k_ceil(double x) { return ceil(x); }
+__device__ __forceinline__ bool k_finite(float x) { return isfinite(x); }
+__device__ __forceinline__ bool k_finite(double x) { return isfinite(x); }
+__device__ __forceinline__ float k_copysign(float a, float b) { return copysignf(a, b); }
+__device__ __forceinline__ double k_copysign(double a, double b) { return copysign(a, b); }
+
+template <typename T>
+__device__ __forceinline__ T wrap_phi(T phi) {
+  // to (-pi, pi]
+  return phi - T(kTwoPi) * k_ceil((phi - T(kPi)) / T(kTwoPi));
+}
+
+// sin(h)/h
+template <typename T>
+__device__ __forceinline__ T sinc(T h) {
+  T h2 = h * h;
+  if (k_abs(h) < T(0.05)) return T(1) - h2 * (T(1.0 / 6.0) - h2 * (T(1.0 / 120.0) - h2 * T(1.0 / 5040.0)));
+  T s, c;
+  k_sincos(h, &s, &c);
+  return s / h;
+}
+
+// (u - sin u)/u^2
+template <typename T>
+__device__ __forceinline__ T u_minus_sin_over_u2(T u) {
+  if (k_abs(u) < T(0.5)) {
+    T u2 = u * u;
+    // u/6 - u^3/120 + u^5/5040 - u^7/362880 + u^9/39916800 - u^11/6227020800 + u^13/1307674368000
+    T r = T(1.0 / 1307674368000.0);
+    r = T(1.0 / 6227020800.0) - u2 * r;
+    r = T(1.0 / 39916800.0) - u2 * r;
+    r = T(1.0 / 362880.0) - u2 * r;
+    r = T(1.0 / 5040.0) - u2 * r;
+    r = T(1.0 / 120.0) - u2 * r;
+    r = T(1.0 / 6.0) - u2 * r;
+    return u * r;
+  }
+  T s, c;
+  k_sincos(u, &s, &c);
+  return (u - s) / (u * u);
+}
+
+// atan(t)/t
+template <typename T>
+__device__ __forceinline__ T atanc(T t) {
+  if (k_abs(t) < T(0.05)) {
+    T t2 = t * t;
+    return T(1) - t2 * (T(1.0 / 3.0) - t2 * (T(0.2) - t2 * T(1.0 / 7.0)));
+  }
+  return k_atan(t) / t;
+}
+
+// ---- a1: crossing ------------------------------------------------------------
+
+// Map a root s onto the admissible window (lo, lo + 2 pi/|w|].
+template <typename T>
+__device__ __forceinline__ T to_window(T s, T lo, T w) {
+  T aw = k_abs(w);
+  if (aw == T(0)) return s;  // straight line: caller rejects s <= lo
+  T P = T(kTwoPi) / aw;
+  T d = s - lo;
+  T m = d - P * k_floor(d / P);
+  if (m <= T(0)) m += P;
+  return lo + m;
+}
+
+// Path s (transverse) along the helix through a half-angle quadratic root:
+// tan(u/2) = w*sig, s = u/w, evaluated without loss as w -> 0.
+template <typename T>
+__device__ __forceinline__ T path_from_sigma(T num, T den, T w) {
+  // sig = num/den; u = 2 atan2(w num, den) taken on the branch through 0
+  T t = w * num;
+  if (k_abs(t) < T(0.1) * k_abs(den)) {
+    T sig = num / den;
+    return T(2) * sig * atanc(w * sig);
+  }
+  return T(2) * k_atan2(t, den) / w;
+}
+
+// Position/direction at transverse path s (chord form).
+template <typename T>
+__device__ __forceinline__ void helix_point(const T p[6], T w, T s, T& x, T& y, T& z, T& phi, T& sphm, T& cphm,
+                                            T& dx, T& dy) {
+  T u = w * s;
+  T h = T(0.5) * u;
+  T sh = sinc(h);
+  T smid, cmid;
+  k_sincos(p[4] + h, &smid, &cmid);
+  dx = s * cmid * sh;
+  dy = s * smid * sh;
+  x = p[0] + dx;
+  y = p[1] + dy;
+  T st, ct;
+  k_sincos(p[5], &st, &ct);
+  z = p[2] + s * ct / st;
+  phi = p[4] + u;
+  k_sincos(phi, &sphm, &cphm);
+}
+
+// First admissible crossing of the layer surface.  Barrel: roots of
+// r(s)^2 = R^2 written as alpha sig^2 + 2 A sig - D/2 = 0 with tan(u/2) = w sig,
+// A = x cos phi + y sin phi, B = x sin phi - y cos phi, D = R^2 - r^2,
+// alpha = 2 (1 - w B) - w^2 D / 2; then one Newton step on r^2 - R^2.
+// Disk: s = (Z - z)/cot(theta).
+template <typename T>
+__device__ bool crossing(const T p[6], T w, int kind, T pos, bool same, T& s_out) {
+  T lo = same ? T(kSSame) : T(-kSBack);
+  if (kind == 1) {
+    T st, ct;
+    k_sincos(p[5], &st, &ct);
+    T cot = ct / st;
+    if (!(k_abs(cot) > T(1e-12))) return false;
+    T s = (pos - p[2]) / cot;
+    s_out = s;
+    return s > lo;
+  }
+  T sphi, cphi;
+  k_sincos(p[4], &sphi, &cphi);
+  T x = p[0], y = p[1];
+  T A = x * cphi + y * sphi;
+  T B = x * sphi - y * cphi;
+  T r0 = k_sqrt(x * x + y * y);
+  T D = (pos - r0) * (pos + r0);
+  T alpha = T(2) * (T(1) - w * B) - T(0.5) * w * w * D;
+  T disc = A * A + T(0.5) * alpha * D;
+  if (!(disc >= T(0))) return false;
+  T sq = k_sqrt(disc);
+  T qq = -(A + k_copysign(sq, A));
+  T best = T(0);
+  bool found = false;
+  // root 1: sig = qq / alpha
+  if (qq != T(0) || alpha != T(0)) {
+    T s1 = path_from_sigma(qq, alpha, w);
+    bool ok1 = k_finite(s1);
+    if (ok1) {
+      s1 = to_window(s1, lo, w);
+      if (s1 > lo) {
+        best = s1;
+        found = true;
+      }
+    }
+  }
+  // root 2: sig = -D / (2 qq)
+  if (qq != T(0)) {
+    T s2 = path_from_sigma(T(-0.5) * D, qq, w);
+    if (k_finite(s2)) {
+      s2 = to_window(s2, lo, w);
+      if (s2 > lo && (!found || s2 < best)) {
+        best = s2;
+        found = true;
+      }
+    }
+  }
+  if (!found) return false;
+  // Newton polish on h(s) = r(s)^2 - R^2
+  T xs, ys, zs, phs, sph, cph, dx, dy;
+  helix_point(p, w, best, xs, ys, zs, phs, sph, cph, dx, dy);
+  T f = (xs * xs + ys * ys - pos * pos);
+  T df = T(2) * (xs * cph + ys * sph);
+  if (k_abs(df) > T(1e-20)) best -= f / df;
+  s_out = best;
+  return true;
+}
+
+// ---- a1-a3: propagate state and covariance ----------------------------------
+
+struct LayerDesc {
+  int kind;
+  double pos;
+  double x0;
+};
+
+// Propagate (p, c) to the surface (kind, pos) and add its scattering noise.
+// Returns false (p, c untouched) if there is no admissible crossing.
+template <typename T>
+__device__ bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool same, bool material, T bz,
+                          T mass, uint32_t& st, T* path = nullptr) {
+  const T dw_dipt = -T(q) * T(kCLight) * bz;
+  const T w = dw_dipt * p[3];
+  T s;
+  if (!crossing(p, w, kind, pos, same, s)) {
+    st |= TRK_NO_CROSSING;
+    return false;
+  }
+  if (path) *path = s;
+  T x, y, z, phm, sphm, cphm, dx, dy;
+  helix_point(p, w, s, x, y, z, phm, sphm, cphm, dx, dy);
+  T sth, cth;
+  k_sincos(p[5], &sth, &cth);
+  const T cot = cth / sth;
+  const T u = w * s;
+  // helix partials at fixed s (G), with the chord-form derivatives
+  const T f1 = u_minus_sin_over_u2(u);
+  const T sh = sinc(T(0.5) * u);
+  const T f2 = T(0.5) * sh * sh;
+  const T s2 = s * s;
+  const T dxdw = s2 * (cphm * f1 - sphm * f2);
+  const T dydw = s2 * (sphm * f1 + cphm * f2);
+  const T G03 = dxdw * dw_dipt, G04 = -dy;
+  const T G13 = dydw * dw_dipt, G14 = dx;
+  const T G25 = -s / (sth * sth);
+  const T G43 = s * dw_dipt;
+  // ds/dp = -(dh/dp)/(dh/ds)
+  T d[6];
+  if (kind == 0) {
+    const T inv = T(-1) / (x * cphm + y * sphm);
+    d[0] = x * inv;
+    d[1] = y * inv;
+    d[2] = T(0);
+    d[3] = (x * G03 + y * G13) * inv;
+    d[4] = (x * G04 + y * G14) * inv;
+    d[5] = T(0);
+  } else {
+    const T inv = T(-1) / cot;
+    d[0] = T(0);
+    d[1] = T(0);
+    d[2] = inv;
+    d[3] = T(0);
+    d[4] = T(0);
+    d[5] = G25 * inv;
+  }
+  // g = d(state)/ds
+  const T g0 = cphm, g1 = sphm, g2 = cot, g4 = w;
+  // wv = C d, a = d^T C d, v = G wv
+  T wv[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc += c[sym(i, j)] * d[j];
+    wv[i] = acc;
+  }
+  T a = T(0);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) a += d[i] * wv[i];
+  T v[6];
+  v[0] = wv[0] + G03 * wv[3] + G04 * wv[4];
+  v[1] = wv[1] + G13 * wv[3] + G14 * wv[4];
+  v[2] = wv[2] + G25 * wv[5];
+  v[3] = wv[3];
+  v[4] = G43 * wv[3] + wv[4];
+  v[5] = wv[5];
+  // M = G C (rows), then N = M G^T (lower triangle)
+  T M[6][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    M[0][j] = c[sym(0, j)] + G03 * c[sym(3, j)] + G04 * c[sym(4, j)];
+    M[1][j] = c[sym(1, j)] + G13 * c[sym(3, j)] + G14 * c[sym(4, j)];
+    M[2][j] = c[sym(2, j)] + G25 * c[sym(5, j)];
+    M[3][j] = c[sym(3, j)];
+    M[4][j] = G43 * c[sym(3, j)] + c[sym(4, j)];
+    M[5][j] = c[sym(5, j)];
+  }
+  T N[21];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    N[sym(i, 0)] = M[i][0] + G03 * M[i][3] + G04 * M[i][4];
+    if (i >= 1) N[sym(i, 1)] = M[i][1] + G13 * M[i][3] + G14 * M[i][4];
+    if (i >= 2) N[sym(i, 2)] = M[i][2] + G25 * M[i][5];
+    if (i >= 3) N[sym(i, 3)] = M[i][3];
+    if (i >= 4) N[sym(i, 4)] = G43 * M[i][3] + M[i][4];
+    if (i >= 5) N[sym(i, 5)] = M[i][5];
+  }
+  // C' = N + g v^T + v g^T + a g g^T ; g = (g0, g1, g2, 0, g4, 0)
+  const T gg[6] = {g0, g1, g2, T(0), g4, T(0)};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      c[sym(i, j)] = N[sym(i, j)] + gg[i] * v[j] + v[i] * gg[j] + a * gg[i] * gg[j];
+    }
+  }
+  p[0] = x;
+  p[1] = y;
+  p[2] = (kind == 1) ? pos : z;
+  p[4] = wrap_phi(phm);
+  if (material) {
+    // Highland angle at the propagated state; x/X0 scaled by 1/|cos(incidence)|
+    T ca;
+    if (kind == 0) {
+      const T r = k_sqrt(x * x + y * y);
+      ca = k_abs(sth * (cphm * x + sphm * y) / r);
+    } else {
+      ca = k_abs(cth);
+    }
+    if (ca < T(kGrazingCos)) {
+      st |= TRK_GRAZING;
+      ca = T(kGrazingCos);
+    }
+    const T ipt = p[3];
+    const T mis = mass * ipt * sth;           // m / p
+    const T xl = x_over_x0 / ca;
+    const T one_m = T(1) + mis * mis;         // 1 / beta^2
+    const T inv_bp = ipt * sth * k_sqrt(one_m);  // 1 / (beta p)
+    const T th0 = T(0.0136) * inv_bp * k_sqrt(xl) * (T(1) + T(0.038) * k_log(xl * one_m));
+    const T var = th0 * th0;
+    const T ic = ipt * cot;
+    c[sym(3, 3)] += ic * ic * var;
+    c[sym(5, 3)] += -ic * var;
+    c[sym(4, 4)] += var / (sth * sth);
+    c[sym(5, 5)] += var;
+  }
+  return true;
+}
+
+// Material of a layer added at the current state (the seed's own layer).
+template <typename T>
+__device__ void add_material_here(const T p[6], T c[21], int kind, T x_over_x0, T mass, uint32_t& st) {
+  T sth, cth;
+  k_sincos(p[5], &sth, &cth);
+  T ca;
+  if (kind == 0) {
+    T sph, cph;
+    k_sincos(p[4], &sph, &cph);
+    const T r = k_sqrt(p[0] * p[0] + p[1] * p[1]);
+    ca = k_abs(sth * (cph * p[0] + sph * p[1]) / r);
+  } else {
+    ca = k_abs(cth);
+  }
+  if (ca < T(kGrazingCos)) {
+    st |= TRK_GRAZING;
+    ca = T(kGrazingCos);
+  }
+  const T cot = cth / sth;
+  const T ipt = p[3];
+  const T mis = mass * ipt * sth;
+  const T xl = x_over_x0 / ca;
+  const T one_m = T(1) + mis * mis;
+  const T inv_bp = ipt * sth * k_sqrt(one_m);
+  const T th0 = T(0.0136) * inv_bp * k_sqrt(xl) * (T(1) + T(0.038) * k_log(xl * one_m));
+  const T var = th0 * th0;
+  const T ic = ipt * cot;
+  c[sym(3, 3)] += ic * ic * var;
+  c[sym(5, 3)] += -ic * var;
+  c[sym(4, 4)] += var / (sth * sth);
+  c[sym(5, 5)] += var;
+}
+
+// ---- a4/a5: residual covariance inverse, chi2, gain, Joseph update ----------
+
+// Inverse of a symmetric 3x3 (packed) by cofactors; returns the determinant.
+template <typename T>
+__device__ __forceinline__ T inv3(const T S[6], T I[6]) {
+  const T a = S[0], b = S[1], cc = S[2], d = S[3], e = S[4], f = S[5];
+  const T i00 = cc * f - e * e;
+  const T i10 = d * e - b * f;
+  const T i11 = a * f - d * d;
+  const T i20 = b * e - cc * d;
+  const T i21 = b * d - a * e;
+  const T i22 = a * cc - b * b;
+  const T det = a * i00 + b * i10 + d * i20;
+  const T r = T(1) / det;
+  I[0] = i00 * r;
+  I[1] = i10 * r;
+  I[2] = i11 * r;
+  I[3] = i20 * r;
+  I[4] = i21 * r;
+  I[5] = i22 * r;
+  return det;
+}
+
+template <typename T>
+__device__ __forceinline__ T norm_inf3(const T S[6]) {
+  const T r0 = k_abs(S[0]) + k_abs(S[1]) + k_abs(S[3]);
+  const T r1 = k_abs(S[1]) + k_abs(S[2]) + k_abs(S[4]);
+  const T r2 = k_abs(S[3]) + k_abs(S[4]) + k_abs(S[5]);
+  return fmax(r0, fmax(r1, r2));
+}
+
+template <typename T>
+__device__ __forceinline__ void inverse_checked(const T S[6], T Si[6], uint32_t& st);
+
+template <>
+__device__ __forceinline__ void inverse_checked<double>(const double S[6], double Si[6], uint32_t& st) {
+  inv3(S, Si);
+}
+
+template <>
+__device__ __forceinline__ void inverse_checked<float>(const float S[6], float Si[6], uint32_t& st) {
+  const float det = inv3(S, Si);
+  const float kappa = norm_inf3(S) * norm_inf3(Si);
+  if (!(det > 0.f) || !(kappa <= float(kKappaMax))) {
+    double Sd[6], Id[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Sd[i] = double(S[i]);
+    inv3(Sd, Id);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Si[i] = float(Id[i]);
+    st |= TRK_FP64_FALLBACK;
+  }
+}
+
+// Kalman update with hit m (3) and covariance V (packed 3x3).
+template <typename T>
+__device__ void update(T p[6], T c[21], int& q, const T m[3], const T V[6], T& chi2, uint32_t& st) {
+  T S[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) S[sym(i, j)] = c[sym(i, j)] + V[sym(i, j)];
+  T Si[6];
+  inverse_checked<T>(S, Si, st);
+  const T r[3] = {m[0] - p[0], m[1] - p[1], m[2] - p[2]};
+  T Sr[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Sr[i] = Si[sym(i, 0)] * r[0] + Si[sym(i, 1)] * r[1] + Si[sym(i, 2)] * r[2];
+  chi2 = r[0] * Sr[0] + r[1] * Sr[1] + r[2] * Sr[2];
+  // K = C[:, 0:3] S^-1
+  T K[6][3];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      K[i][j] = c[sym(i, 0)] * Si[sym(0, j)] + c[sym(i, 1)] * Si[sym(1, j)] + c[sym(i, 2)] * Si[sym(2, j)];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) p[i] += K[i][0] * r[0] + K[i][1] * r[1] + K[i][2] * r[2];
+  // Joseph: C' = A C A^T + K V K^T with A = I - K H
+  T AC[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      AC[i][j] = c[sym(i, j)] - K[i][0] * c[sym(0, j)] - K[i][1] * c[sym(1, j)] - K[i][2] * c[sym(2, j)];
+  T KV[6][3];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      KV[i][j] = K[i][0] * V[sym(0, j)] + K[i][1] * V[sym(1, j)] + K[i][2] * V[sym(2, j)];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      const T aca = AC[i][j] - AC[i][0] * K[j][0] - AC[i][1] * K[j][1] - AC[i][2] * K[j][2];
+      const T kvk = KV[i][0] * K[j][0] + KV[i][1] * K[j][1] + KV[i][2] * K[j][2];
+      c[sym(i, j)] = aca + kvk;
+    }
+  if (p[3] < T(0)) {
+    p[3] = -p[3];
+    q = -q;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j != 3) c[sym(3, j)] = -c[sym(3, j)];
+    st |= TRK_CHARGE_FLIP;
+  }
+  p[4] = wrap_phi(p[4]);
+  const T tr = c[0] + c[2] + c[5];
+  if (!(c[sym(3, 3)] > T(0)) || !(c[sym(4, 4)] > T(0)) || !(c[sym(5, 5)] > T(0)) || c[0] < T(-1e-6) * tr ||
+      c[2] < T(-1e-6) * tr || c[5] < T(-1e-6) * tr)
+    st |= TRK_COV_NOT_PSD;
+}
+
+template <typename T>
+__device__ __forceinline__ bool all_finite(const T p[6], const T c[21], T chi2) {
+  bool ok = k_finite(chi2);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) ok = ok && k_finite(p[i]);
+#pragma unroll
+  for (int i = 0; i < 21; ++i) ok = ok && k_finite(c[i]);
+  return ok;
+}
+
+// ---- seeding from three hits -------------------------------------------------
+
+template <typename T>
+__device__ void seed_from_hits(const T h1[3], const T h2[3], const T h3[3], T bz, T p[6], int& q) {
+  const T dx12 = h2[0] - h1[0], dy12 = h2[1] - h1[1];
+  const T dx13 = h3[0] - h1[0], dy13 = h3[1] - h1[1];
+  const T dx23 = h3[0] - h2[0], dy23 = h3[1] - h2[1];
+  const T d12 = k_sqrt(dx12 * dx12 + dy12 * dy12);
+  const T d13 = k_sqrt(dx13 * dx13 + dy13 * dy13);
+  const T d23 = k_sqrt(dx23 * dx23 + dy23 * dy23);
+  const T cr = dx12 * dy13 - dy12 * dx13;
+  const T kappa = T(2) * cr / (d12 * d13 * d23);
+  q = kappa > T(0) ? -1 : 1;
+  const T ak = k_abs(kappa);
+  p[0] = h1[0];
+  p[1] = h1[1];
+  p[2] = h1[2];
+  p[3] = ak / (T(kCLight) * bz);
+  // half turning angle to hit 2: asin(kappa d12/2) = atan2(k, sqrt(1-k^2))
+  T a12 = kappa * d12 * T(0.5);
+  a12 = fmax(T(-1), fmin(T(1), a12));
+  const T half = k_atan2(a12, k_sqrt((T(1) - a12) * (T(1) + a12)));
+  p[4] = wrap_phi(k_atan2(dy12, dx12) - half);
+  // transverse arc 1 -> 3: 2 asin(|kappa| d13/2)/|kappa| = d13 * asin(x)/x
+  T a13 = ak * d13 * T(0.5);
+  a13 = fmin(T(1), a13);
+  T asin_over;
+  if (a13 < T(0.05)) {
+    const T x2 = a13 * a13;
+    asin_over = T(1) + x2 * (T(1.0 / 6.0) + x2 * (T(3.0 / 40.0) + x2 * T(5.0 / 112.0)));
+  } else {
+    asin_over = k_atan2(a13, k_sqrt((T(1) - a13) * (T(1) + a13))) / a13;
+  }
+  const T s13 = d13 * asin_over;
+  const T cot = (h3[2] - h1[2]) / s13;
+  p[5] = T(kPi * 0.5) - k_atan(cot);
+}
+
+}  // namespace kf

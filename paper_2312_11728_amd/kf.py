@@ -1,0 +1,285 @@
+"""Python binding of libkf (ctypes).  Argument marshalling only: every step of
+the computation runs in the HIP kernels behind the C interface in
+include/kf.h; PyTorch supplies device memory and the current stream.
+
+The library is loaded from this directory; if it is missing the import fails
+(there is no fallback path)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkf.so")
+
+KF_OK, KF_ERR_ARG, KF_ERR_DEVICE, KF_ERR_NOMEM, KF_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+KF_F32, KF_F64 = 0, 1
+TRK_NO_CROSSING, TRK_GRAZING, TRK_NONFINITE, TRK_FP64_FALLBACK = 1, 2, 4, 8
+TRK_CHARGE_FLIP, TRK_COV_NOT_PSD, TRK_BAD_INPUT = 16, 32, 64
+MAX_LAYERS = 64
+
+EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_propagate", "kf_update",
+           "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
+           "kf_device_cu_count"]
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+
+
+class KfGeometry(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("kind", _vp), ("pos", _vp), ("lo", _vp), ("hi", _vp),
+                ("x_over_x0", _vp), ("bz_tesla", _dbl), ("particle_mass_gev", _dbl)]
+
+
+class KfSearchParams(ctypes.Structure):
+    _fields_ = [("beam", ctypes.c_int32), ("chi2_max", ctypes.c_float), ("n_sigma", ctypes.c_float),
+                ("hit_bonus", ctypes.c_float), ("miss_penalty", ctypes.c_float), ("max_miss", ctypes.c_int32),
+                ("sigma_rphi", ctypes.c_float), ("sigma_z", ctypes.c_float),
+                ("win_min_rphi", _vp), ("win_max_rphi", _vp), ("win_min_z", _vp), ("win_max_z", _vp)]
+
+
+class KfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libkf error {code}: {msg}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_2312_11728_amd/build.py (or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    lib.kf_last_error.restype = ctypes.c_char_p
+    lib.kf_last_error.argtypes = []
+    lib.kf_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+    lib.kf_destroy.argtypes = [_vp]
+    lib.kf_make_seeds.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _i64, _vp, _dbl, _i32, _vp, _vp, _vp,
+                                  _vp, _vp]
+    lib.kf_propagate.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(KfGeometry),
+                                 _i32, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_update.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_fit_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
+                                  ctypes.POINTER(KfGeometry), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp]
+    lib.kf_score_hits.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(KfGeometry),
+                                  ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_fit_adjoint.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
+                                   ctypes.POINTER(KfGeometry), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_set_fit_launch.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i32]
+    lib.kf_get_fit_launch.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                      ctypes.POINTER(_i32)]
+    lib.kf_device_cu_count.argtypes = [_vp, ctypes.POINTER(_i32)]
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _check(rc):
+    if rc != KF_OK:
+        raise KfError(rc, lib().kf_last_error().decode())
+
+
+class Geometry:
+    """Host-side detector description (kept alive for the C struct)."""
+
+    def __init__(self, kind, pos, lo, hi, x_over_x0, bz=3.8, mass=0.13957):
+        self.kind = np.ascontiguousarray(kind, dtype=np.int8)
+        self.pos = np.ascontiguousarray(pos, dtype=np.float64)
+        self.lo = np.ascontiguousarray(lo, dtype=np.float64)
+        self.hi = np.ascontiguousarray(hi, dtype=np.float64)
+        self.x_over_x0 = np.ascontiguousarray(x_over_x0, dtype=np.float64)
+        self.bz = float(bz)
+        self.mass = float(mass)
+        self.struct = KfGeometry(self.kind.shape[0], self.kind.ctypes.data, self.pos.ctypes.data,
+                                 self.lo.ctypes.data, self.hi.ctypes.data, self.x_over_x0.ctypes.data,
+                                 self.bz, self.mass)
+
+    @property
+    def n_layers(self):
+        return int(self.kind.shape[0])
+
+    @classmethod
+    def from_toy(cls, g):
+        return cls(g.kind, g.pos, g.lo, g.hi, g.x_over_x0, g.bz, g.mass)
+
+
+def _ptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _prec(dtype):
+    if dtype == torch.float32:
+        return KF_F32
+    if dtype == torch.float64:
+        return KF_F64
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def _need(t, name, dtype=None, dev=None, rows=None):
+    if not torch.is_tensor(t):
+        raise TypeError(f"{name} must be a torch tensor")
+    if dev is not None and t.device != dev:
+        raise ValueError(f"{name} is on {t.device}, expected {dev}")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if rows is not None and (t.dim() != 2 or t.shape[0] != rows):
+        raise ValueError(f"{name} must have shape [{rows}, N], got {tuple(t.shape)}")
+    return t
+
+
+def _stream(dev):
+    return _vp(torch.cuda.current_stream(dev).cuda_stream)
+
+
+class Context:
+    """One libkf context on one device (re-entrant: no global state)."""
+
+    def __init__(self, device=0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = _vp()
+        _check(lib().kf_create(ctypes.byref(h), self.device.index or 0))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().kf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- tuning -----------------------------------------------------------
+    def set_fit_launch(self, dtype, block, persistent, blocks_per_cu):
+        _check(lib().kf_set_fit_launch(self.handle, _prec(dtype), block, persistent, blocks_per_cu))
+
+    def get_fit_launch(self, dtype):
+        b, p, k = _i32(), _i32(), _i32()
+        _check(lib().kf_get_fit_launch(self.handle, _prec(dtype), ctypes.byref(b), ctypes.byref(p), ctypes.byref(k)))
+        return b.value, p.value, k.value
+
+    def cu_count(self):
+        n = _i32()
+        _check(lib().kf_device_cu_count(self.handle, ctypes.byref(n)))
+        return n.value
+
+    # ---- entry points -----------------------------------------------------
+    def make_seeds(self, hit_offsets, hit_valid, hit_pos, bz, mode=0, out=None):
+        dev = self.device
+        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need(hit_valid, "hit_valid", torch.uint8, dev)
+        _need(hit_pos, "hit_pos", None, dev, rows=3)
+        dt = hit_pos.dtype
+        n = hit_offsets.shape[0] - 1
+        if out is None:
+            out = (torch.empty(6, n, dtype=dt, device=dev), torch.empty(21, n, dtype=dt, device=dev),
+                   torch.empty(n, dtype=torch.int8, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+        st, cov, q, status = out
+        _check(lib().kf_make_seeds(self.handle, _prec(dt), n, st.stride(0), _ptr(hit_offsets), _ptr(hit_valid),
+                                   hit_pos.shape[1], _ptr(hit_pos), float(bz), int(mode), _ptr(st), _ptr(cov),
+                                   _ptr(q), _ptr(status), _stream(dev)))
+        return st, cov, q, status
+
+    def propagate(self, state, cov, charge, target_layer, geom: Geometry, from_layer=None, apply_material=True,
+                  status=None):
+        dev = self.device
+        dt = state.dtype
+        n = state.shape[1]
+        _need(state, "state", dt, dev, rows=6)
+        _need(cov, "cov", dt, dev, rows=21)
+        _need(charge, "charge", torch.int8, dev)
+        _need(target_layer, "target_layer", torch.int16, dev)
+        if from_layer is not None:
+            _need(from_layer, "from_layer", torch.int16, dev)
+        so = torch.empty_like(state)
+        co = torch.empty_like(cov)
+        path = torch.empty(n, dtype=dt, device=dev)
+        if status is None:
+            status = torch.zeros(n, dtype=torch.int32, device=dev)
+        _check(lib().kf_propagate(self.handle, _prec(dt), n, state.stride(0), _ptr(state), _ptr(cov), _ptr(charge),
+                                  _ptr(target_layer), _ptr(from_layer), ctypes.byref(geom.struct),
+                                  int(bool(apply_material)), _ptr(so), _ptr(co), _ptr(path), _ptr(status),
+                                  _stream(dev)))
+        return so, co, path, status
+
+    def update(self, state, cov, charge, hit_pos, hit_cov, status=None):
+        """In-place update of state/cov/charge; returns (chi2, status)."""
+        dev = self.device
+        dt = state.dtype
+        n = state.shape[1]
+        _need(state, "state", dt, dev, rows=6)
+        _need(cov, "cov", dt, dev, rows=21)
+        _need(charge, "charge", torch.int8, dev)
+        _need(hit_pos, "hit_pos", dt, dev, rows=3)
+        _need(hit_cov, "hit_cov", dt, dev, rows=6)
+        chi2 = torch.empty(n, dtype=dt, device=dev)
+        if status is None:
+            status = torch.zeros(n, dtype=torch.int32, device=dev)
+        _check(lib().kf_update(self.handle, _prec(dt), n, state.stride(0), _ptr(state), _ptr(cov), _ptr(charge),
+                               _ptr(hit_pos), _ptr(hit_cov), _ptr(chi2), _ptr(status), _stream(dev)))
+        return chi2, status
+
+    def fit_tracks(self, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov,
+                   geom: Geometry, align=None, checkpoints=None, seg=1, max_len=26, out=None):
+        dev = self.device
+        dt = seed_state.dtype
+        n = seed_state.shape[1]
+        _need(seed_state, "seed_state", dt, dev, rows=6)
+        _need(seed_cov, "seed_cov", dt, dev, rows=21)
+        _need(seed_charge, "seed_charge", torch.int8, dev)
+        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need(hit_layer, "hit_layer", torch.int16, dev)
+        _need(hit_valid, "hit_valid", torch.uint8, dev)
+        _need(hit_pos, "hit_pos", dt, dev, rows=3)
+        _need(hit_cov, "hit_cov", dt, dev, rows=6)
+        if align is not None:
+            _need(align, "align", dt, dev, rows=2)
+        if checkpoints is not None:
+            _need(checkpoints, "checkpoints", dt, dev, rows=28)
+        if out is None:
+            out = fit_outputs(n, dt, dev)
+        _check(lib().kf_fit_tracks(self.handle, _prec(dt), n, seed_state.stride(0), _ptr(seed_state), _ptr(seed_cov),
+                                   _ptr(seed_charge), _ptr(hit_offsets), _ptr(hit_layer), _ptr(hit_valid),
+                                   hit_pos.shape[1], _ptr(hit_pos), _ptr(hit_cov), ctypes.byref(geom.struct),
+                                   _ptr(align), _ptr(out["state"]), _ptr(out["cov"]), _ptr(out["charge"]),
+                                   _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(checkpoints), int(seg), int(max_len),
+                                   _ptr(out["status"]), _stream(dev)))
+        return out
+
+
+def fit_outputs(n, dtype, device):
+    return dict(state=torch.empty(6, n, dtype=dtype, device=device), cov=torch.empty(21, n, dtype=dtype, device=device),
+                charge=torch.empty(n, dtype=torch.int8, device=device), chi2=torch.empty(n, dtype=dtype, device=device),
+                ndf=torch.empty(n, dtype=torch.int32, device=device), status=torch.empty(n, dtype=torch.int32, device=device))
+
+
+def n_checkpoint_segments(max_len, seg):
+    return max(1, (max_len - 1 + seg - 1) // seg)
+
+
+def event_tensors(ev, dtype=torch.float32, device="cuda"):
+    """Device copies of a batch in the CSR / SoA layout of the interface
+    (hit_pos [3][n_hits], hit_cov [6][n_hits], hit_offsets [n+1], ...)."""
+    dev = torch.device(device)
+    return dict(
+        hit_offsets=torch.as_tensor(np.ascontiguousarray(ev.hit_offsets, np.int32), device=dev),
+        hit_layer=torch.as_tensor(np.ascontiguousarray(ev.hit_layer, np.int16), device=dev),
+        hit_valid=torch.as_tensor(np.ascontiguousarray(ev.hit_valid, np.uint8), device=dev),
+        hit_pos=torch.as_tensor(np.ascontiguousarray(ev.hit_pos), device=dev).to(dtype).contiguous(),
+        hit_cov=torch.as_tensor(np.ascontiguousarray(ev.hit_cov), device=dev).to(dtype).contiguous(),
+    )

@@ -1,0 +1,97 @@
+"""The C interface without a GPU: the library loads, exports every entry
+point declared in include/kf.h, and rejects bad arguments before touching the
+device (these calls return KF_ERR_ARG from host-side validation)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kf.h")
+
+kf = pytest.importorskip("paper_2312_11728_amd.kf")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(kf_[a-z_0-9]+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_hot_path_entry_points():
+    names = _declared()
+    for n in ("kf_propagate", "kf_update", "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = kf.lib()
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(_declared()) <= set(kf.EXPORTS)
+
+
+def _geom(n=3):
+    return kf.Geometry([0] * n, [4.0 + i for i in range(n)], [-150.0] * n, [150.0] * n, [0.02] * n)
+
+
+P = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+def _fit_call(**over):
+    args = dict(ctx=P, prec=kf.KF_F32, n=10, ld=10, seed_state=P, seed_cov=P, seed_charge=P, hit_offsets=P,
+                hit_layer=P, hit_valid=P, n_hits=100, hit_pos=P, hit_cov=P, geom=ctypes.byref(_geom().struct),
+                align=None, state_out=P, cov_out=P, charge_out=P, chi2=P, ndf=P, checkpoints=None, seg=1,
+                max_len=26, trk_status=P, stream=None)
+    g = over.pop("geometry", None)
+    if g is not None:
+        args["geom"] = ctypes.byref(g.struct)
+    args.update(over)
+    return kf.lib().kf_fit_tracks(*args.values())
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(n=-1), "n = -1"),
+    (dict(ld=5), "ld = 5 < n = 10"),
+    (dict(prec=7), "precision 7"),
+    (dict(seed_state=None), "seed_state is NULL"),
+    (dict(hit_pos=None), "hit_pos is NULL"),
+    (dict(trk_status=None), "trk_status is NULL"),
+    (dict(n_hits=-3), "n_hits < 0"),
+    (dict(checkpoints=P, seg=0), "seg = 0"),
+    (dict(checkpoints=P, max_len=0), "max_len = 0"),
+    (dict(ctx=None), "ctx is NULL"),
+])
+def test_fit_tracks_argument_validation(over, msg):
+    rc = _fit_call(**over)
+    assert rc == kf.KF_ERR_ARG
+    assert msg in kf.lib().kf_last_error().decode()
+
+
+def test_geometry_validation():
+    bad = kf.Geometry([0, 2], [4.0, 5.0], [-1, -1], [1, 1], [0.02, 0.02])
+    assert _fit_call(geometry=bad) == kf.KF_ERR_ARG
+    assert "kind[1]" in kf.lib().kf_last_error().decode()
+    bad = kf.Geometry([0], [-4.0], [-1], [1], [0.02])
+    assert _fit_call(geometry=bad) == kf.KF_ERR_ARG
+    bad = kf.Geometry([0], [4.0], [-1], [1], [0.02], bz=0.0)
+    assert _fit_call(geometry=bad) == kf.KF_ERR_ARG
+    assert "bz_tesla" in kf.lib().kf_last_error().decode()
+    big = kf.Geometry([0] * 65, np.arange(65) + 4.0, [-1] * 65, [1] * 65, [0.02] * 65)
+    assert _fit_call(geometry=big) == kf.KF_ERR_ARG
+    assert "n_layers" in kf.lib().kf_last_error().decode()
+
+
+def test_other_entry_points_validate():
+    lib = kf.lib()
+    g = _geom()
+    assert lib.kf_propagate(P, 0, 5, 4, P, P, P, P, None, ctypes.byref(g.struct), 1, P, P, None, P, None) == kf.KF_ERR_ARG
+    assert lib.kf_propagate(P, 0, 5, 5, P, P, P, None, None, ctypes.byref(g.struct), 1, P, P, None, P, None) == kf.KF_ERR_ARG
+    assert "target_layer" in lib.kf_last_error().decode()
+    assert lib.kf_update(P, 0, 5, 5, P, P, P, P, None, P, P, None) == kf.KF_ERR_ARG
+    assert "hit_cov" in lib.kf_last_error().decode()
+    assert lib.kf_make_seeds(P, 0, 5, 5, P, P, 10, P, 3.8, 2, P, P, P, P, None) == kf.KF_ERR_ARG
+    assert "seed mode" in lib.kf_last_error().decode()
+    assert lib.kf_set_fit_launch(P, 0, 100, 0, 4) == kf.KF_ERR_ARG
+    assert lib.kf_set_fit_launch(P, 0, 128, 2, 4) == kf.KF_ERR_ARG

@@ -1,0 +1,318 @@
+"""GPU parity of seeding, single-step propagate/update and the fused fit
+(through the C interface) against the FP64 oracle on the same seeded inputs."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import kf_oracle as O
+from toygen import generate, subset, truncate, workloads
+
+from parity import (chi2_error, compare_fit, gpu_fit, ill_conditioned, oracle_fit, param_error, rounded,
+                    sym_unpack)
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = (1e-4, 1e-3)
+TOL64 = (1e-9, 1e-9)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_11728_amd import kf as _kf
+    return _kf
+
+
+@pytest.fixture(scope="module")
+def ctx(kf):
+    c = kf.Context(0)
+    yield c
+    c.close()
+
+
+# ---- seeding -------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,mode,dtype", [("barrel10", 0, torch.float64), ("barrel20", 0, torch.float32),
+                                             ("mixed26", 1, torch.float32), ("mixed26", 1, torch.float64)])
+def test_seeds_parity(ctx, kf, name, mode, dtype):
+    say("seeds", name, mode, dtype)
+    ev = generate(workloads()[name], 3000)
+    t = kf.event_tensors(ev, dtype, ctx.device)
+    st, cov, q, status = ctx.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"], ev.geometry.bz, mode)
+    hp = rounded(ev.hit_pos, dtype)
+    sp, sC, sq, ok = O.make_seeds(ev.hit_offsets, ev.hit_valid, hp, ev.geometry.bz, mode=mode)
+    g = st.double().cpu().numpy().T
+    err = param_error(g, sp.numpy()).max(axis=1)
+    tol = 1e-4 if dtype == torch.float32 else 1e-10
+    # ill-conditioned three-point circles (nearly collinear hits) are excluded by the
+    # oracle's own sensitivity to an FP32-ulp change of the hits
+    sp2, _, _, _ = O.make_seeds(ev.hit_offsets, ev.hit_valid, hp * (1 + 2.0 ** -23), ev.geometry.bz, mode=mode)
+    cond = param_error(sp2.numpy(), sp.numpy()).max(axis=1) < 0.5 * tol
+    assert cond.mean() > 0.99
+    assert err[cond].max() < tol, err[cond].max()
+    assert np.array_equal(q.cpu().numpy()[cond].astype(float), sq.numpy()[cond])
+    assert (status.cpu().numpy()[ok.numpy()] == 0).all()
+    C = cov.double().cpu().numpy().T
+    assert np.allclose(sym_unpack(C), sC.numpy())
+
+
+# ---- single steps ----------------------------------------------------------------
+
+def _step_inputs(name, n_tracks, seed):
+    """Generator truth at entry k (random k per track), a random SPD covariance
+    and the layer of entry k+1 as target."""
+    wl = workloads()[name]
+    ev = generate(wl, n_tracks)
+    rng = np.random.default_rng(seed)
+    L = ev.lengths()
+    k = rng.integers(0, L - 1)
+    e = ev.hit_offsets[:-1] + k
+    p = ev.truth_after[e].copy()
+    A = rng.normal(size=(n_tracks, 6, 6)) * np.array([0.01, 0.01, 0.01, 0.01, 0.001, 0.001])[None, :, None]
+    C = A @ A.transpose(0, 2, 1) + np.diag([1e-4, 1e-4, 1e-4, 1e-4, 1e-6, 1e-6])[None]
+    return ev, p, C, ev.charge.astype(np.float64), ev.hit_layer[e + 1], ev.hit_layer[e], e + 1
+
+
+def _pack(C):
+    out = []
+    for i in range(6):
+        for j in range(i + 1):
+            out.append(C[:, i, j])
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("name,dtype", [("barrel20", torch.float32), ("mixed26", torch.float32),
+                                        ("mixed26", torch.float64)])
+def test_propagate_parity(ctx, kf, name, dtype):
+    say("propagate", name, dtype)
+    ev, p, C, q, target, frm, _ = _step_inputs(name, 5000, 5)
+    p = rounded(p, dtype)
+    C = rounded(C, dtype)
+    dev = ctx.device
+    geom = kf.Geometry.from_toy(ev.geometry)
+    st = torch.tensor(p.T.copy(), dtype=dtype, device=dev)
+    cv = torch.tensor(_pack(C), dtype=dtype, device=dev)
+    ch = torch.tensor(q, dtype=torch.int8, device=dev)
+    tg = torch.tensor(target, dtype=torch.int16, device=dev)
+    fr = torch.tensor(frm, dtype=torch.int16, device=dev)
+    so, co, path, status = ctx.propagate(st, cv, ch, tg, geom, from_layer=fr)
+    torch.cuda.synchronize()
+    g = ev.geometry
+    kind = torch.tensor(g.kind[target].astype(np.int64))
+    op, oC, os_, ostat = O.propagate(torch.tensor(p), torch.tensor(C), torch.tensor(q), kind,
+                                     torch.tensor(g.pos[target]), torch.tensor(g.x_over_x0[target]), g,
+                                     same=torch.tensor(target == frm))
+    gp = so.double().cpu().numpy().T
+    ok = ostat.numpy() & O.NO_CROSSING == 0
+    tol = 1e-4 if dtype == torch.float32 else 1e-10
+    err = param_error(gp, op.numpy()).max(axis=1)
+    assert err[ok].max() < tol, err[ok].max()
+    assert np.array_equal(status.cpu().numpy(), ostat.numpy())
+    ce = np.abs(sym_unpack(co.double().cpu().numpy().T) - oC.numpy())
+    scale = np.sqrt(np.abs(np.einsum("nii->ni", oC.numpy())))
+    rel = ce / (scale[:, :, None] * scale[:, None, :] + 1e-30)
+    big = (scale[:, :, None] * scale[:, None, :]) > 1e-12
+    assert rel[ok][big[ok]].max() < (2e-3 if dtype == torch.float32 else 1e-8), rel[ok][big[ok]].max()
+    pe = np.abs(path.double().cpu().numpy() - os_.numpy()) / np.maximum(np.abs(os_.numpy()), 1.0)
+    assert pe[ok].max() < (1e-4 if dtype == torch.float32 else 1e-10)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_update_parity(ctx, kf, dtype):
+    say("update", dtype)
+    ev, p, C, q, target, frm, e = _step_inputs("barrel20", 5000, 7)
+    # predicted state: truth plus a small offset, hit of that crossing
+    rng = np.random.default_rng(8)
+    p = p.copy()
+    p[:, :2] += rng.normal(0, 0.01, (p.shape[0], 2))
+    e = e - 1
+    m = ev.hit_pos[:, e]
+    V = ev.hit_cov[:, e]
+    p, C, m, V = (rounded(x, dtype) for x in (p, C, m, V))
+    dev = ctx.device
+    st = torch.tensor(p.T.copy(), dtype=dtype, device=dev)
+    cv = torch.tensor(_pack(C), dtype=dtype, device=dev)
+    ch = torch.tensor(q, dtype=torch.int8, device=dev)
+    hp = torch.tensor(m, dtype=dtype, device=dev)
+    hc = torch.tensor(V, dtype=dtype, device=dev)
+    chi2, status = ctx.update(st, cv, ch, hp, hc)
+    torch.cuda.synchronize()
+    op, oC, oq, oc2, ostat = O.update(torch.tensor(p), torch.tensor(C), torch.tensor(q), torch.tensor(m.T),
+                                      O.unpack_sym(V, 3))
+    tol = 1e-4 if dtype == torch.float32 else 1e-10
+    assert param_error(st.double().cpu().numpy().T, op.numpy()).max() < tol
+    assert chi2_error(chi2.double().cpu().numpy(), oc2.numpy()).max() < (1e-3 if dtype == torch.float32 else 1e-9)
+    assert np.array_equal(ch.cpu().numpy().astype(float), oq.numpy())
+    assert np.array_equal(status.cpu().numpy() & ~O.FP64_FALLBACK, ostat.numpy())
+
+
+def test_update_fp64_fallback(ctx, kf):
+    """A nearly singular residual covariance (tiny normal variance) must take
+    the FP64 inverse in the FP32 path and still match the oracle."""
+    say("fp64 fallback")
+    n = 256
+    rng = np.random.default_rng(3)
+    ph = rng.uniform(-math.pi, math.pi, n)
+    R = 30.0
+    p = np.stack([R * np.cos(ph), R * np.sin(ph), rng.uniform(-10, 10, n), np.full(n, 0.5), ph, np.full(n, 1.2)], 1)
+    # covariance with the surface normal as a null vector in position
+    t = np.stack([-np.sin(ph), np.cos(ph), np.zeros(n)], 1)
+    z = np.tile([0.0, 0.0, 1.0], (n, 1))
+    nh = np.stack([np.cos(ph), np.sin(ph), np.zeros(n)], 1)
+    C = np.zeros((n, 6, 6))
+    Cp = 1e-2 * t[:, :, None] * t[:, None, :] + 4e-2 * z[:, :, None] * z[:, None, :]
+    C[:, :3, :3] = Cp
+    C[:, 3:, 3:] = np.diag([1e-3, 1e-4, 1e-4])
+    sn = 1e-5
+    V = (0.003 ** 2) * t[:, :, None] * t[:, None, :] + 0.01 ** 2 * z[:, :, None] * z[:, None, :] + \
+        sn ** 2 * nh[:, :, None] * nh[:, None, :]
+    m = p[:, :3] + 0.004 * t + 0.02 * z
+    p, C, m, V = (rounded(x, torch.float32) for x in (p, C, m, V))
+    Vp = np.stack([V[:, 0, 0], V[:, 1, 0], V[:, 1, 1], V[:, 2, 0], V[:, 2, 1], V[:, 2, 2]])
+    dev = ctx.device
+    st = torch.tensor(p.T.copy(), dtype=torch.float32, device=dev)
+    cv = torch.tensor(_pack(C), dtype=torch.float32, device=dev)
+    ch = torch.ones(n, dtype=torch.int8, device=dev)
+    chi2, status = ctx.update(st, cv, ch, torch.tensor(m.T.copy(), dtype=torch.float32, device=dev),
+                              torch.tensor(Vp, dtype=torch.float32, device=dev))
+    torch.cuda.synchronize()
+    stt = status.cpu().numpy()
+    assert (stt & O.FP64_FALLBACK).all()
+    op, oC, oq, oc2, ostat = O.update(torch.tensor(p), torch.tensor(C), torch.ones(n, dtype=torch.float64),
+                                      torch.tensor(m), torch.tensor(V))
+    assert param_error(st.double().cpu().numpy().T, op.numpy()).max() < 1e-4
+    assert chi2_error(chi2.double().cpu().numpy(), oc2.numpy()).max() < 1e-3
+
+
+# ---- the fused fit -------------------------------------------------------------------
+
+def _fit_case(ctx, kf, ev, dtype, seed_mode, tol, max_bad_frac=0.0):
+    g = gpu_fit(ctx, kf, ev, dtype, seed_mode)
+    o = oracle_fit(ev, dtype, seed_mode)
+    bad = ill_conditioned(ev, dtype, o, seed_mode, *tol)
+    mask = ~bad
+    assert bad.mean() <= max(max_bad_frac, 0.005), bad.mean()
+    s = compare_fit(g, o, tol[0], tol[1], mask)
+    s["ill_conditioned"] = int((~mask).sum())
+    say(s)
+    return g, o, s
+
+
+def test_fit_barrel10_fp64_all_tracks(ctx, kf):
+    say("fit barrel10 fp64")
+    ev = generate(workloads()["barrel10"])
+    _fit_case(ctx, kf, ev, torch.float64, 0, TOL64)
+
+
+def test_fit_barrel10_fp32(ctx, kf):
+    say("fit barrel10 fp32")
+    ev = generate(workloads()["barrel10"])
+    _fit_case(ctx, kf, ev, torch.float32, 0, TOL32, max_bad_frac=0.01)
+
+
+def test_fit_barrel20_full_size_fp32_and_fp64(ctx, kf):
+    say("fit barrel20 100k fp32 + fp64")
+    ev = generate(workloads()["barrel20"])
+    _fit_case(ctx, kf, ev, torch.float32, 0, TOL32, max_bad_frac=0.01)
+    _fit_case(ctx, kf, ev, torch.float64, 0, TOL64)
+
+
+def test_fit_mixed26_sample(ctx, kf):
+    say("fit mixed26 20k fp32 + fp64")
+    ev = generate(workloads()["mixed26"], 20_000)
+    _fit_case(ctx, kf, ev, torch.float32, 1, TOL32, max_bad_frac=0.02)
+    _fit_case(ctx, kf, ev, torch.float64, 1, TOL64)
+
+
+def test_fit_every_length_3_to_26(ctx, kf):
+    say("fit lengths 3..26")
+    ev = generate(workloads()["mixed26"], 4000)
+    long = np.nonzero(ev.lengths() >= 26)[0]
+    assert long.size >= 24
+    lengths = np.arange(3, 27)
+    pick = np.repeat(long[:24], 1)
+    ev2 = truncate(subset(ev, pick), lengths)
+    keep = np.add.reduceat(ev2.hit_valid.astype(int), ev2.hit_offsets[:-1]) >= 3
+    ev2 = subset(ev2, np.nonzero(keep)[0])
+    _fit_case(ctx, kf, ev2, torch.float64, 1, TOL64)
+    _fit_case(ctx, kf, ev2, torch.float32, 1, TOL32, max_bad_frac=0.1)
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1000 + 13])
+def test_fit_ragged_sizes(ctx, kf, n):
+    say("fit ragged", n)
+    ev = generate(workloads()["mixed26"], max(n, 1))
+    if n == 0:
+        ev = subset(ev, [])
+    _fit_case(ctx, kf, ev, torch.float64, 1, TOL64)
+
+
+def test_fit_edge_cases(ctx, kf):
+    """Holes in front of the first valid hit, a track with no valid hit, an
+    unreachable layer and a non-finite hit, all in one batch."""
+    say("fit edge cases")
+    wl = workloads()["barrel10"]
+    ev = generate(wl, 200)
+    valid = ev.hit_valid.copy()
+    off = ev.hit_offsets
+    valid[off[0]] = 0              # track 0: leading hole
+    valid[off[1]:off[1] + 2] = 0   # track 1: two leading holes
+    valid[off[2]:off[3]] = 0       # track 2: no valid hit at all
+    pos = ev.hit_pos.copy()
+    pos[:, off[4] + 5] = np.nan    # track 4: non-finite hit at entry 5
+    ev.hit_valid = valid
+    ev.hit_pos = pos
+    from toygen import barrel_geometry
+    g2 = barrel_geometry(list(wl.geometry.pos[:-1]) + [5000.0])   # last layer unreachable
+    ev.geometry = g2
+    dt = torch.float64
+    gres = gpu_fit(ctx, kf, ev, dt, 0)
+    assert gres["status"][2] & kf.TRK_BAD_INPUT
+    assert np.isfinite(gres["p"]).all() and np.isfinite(gres["chi2"]).all()
+    assert gres["status"][4] & O.NONFINITE
+    # compare every track the oracle can seed (track 2 cannot be seeded)
+    o = oracle_fit(ev, dt, 0)
+    mask = np.ones(ev.n_tracks, bool)
+    mask[2] = False
+    compare_fit(gres, o, TOL64[0], TOL64[1], mask)
+    full = ev.lengths() == 10
+    assert ((gres["status"][full] & O.NO_CROSSING) != 0).all()
+
+
+def test_fit_deterministic_and_launch_shape_independent(ctx, kf):
+    say("fit determinism")
+    ev = generate(workloads()["mixed26"], 20_000)
+    a = gpu_fit(ctx, kf, ev, torch.float32, 1)
+    b = gpu_fit(ctx, kf, ev, torch.float32, 1)
+    old = ctx.get_fit_launch(torch.float32)
+    try:
+        ctx.set_fit_launch(torch.float32, 64, 1, 8)
+        c = gpu_fit(ctx, kf, ev, torch.float32, 1)
+        ctx.set_fit_launch(torch.float32, 128, 0, 1)
+        d = gpu_fit(ctx, kf, ev, torch.float32, 1)
+    finally:
+        ctx.set_fit_launch(torch.float32, *old)
+    for x in (b, c, d):
+        assert np.array_equal(a["p"], x["p"]) and np.array_equal(a["C"], x["C"])
+        assert np.array_equal(a["chi2"], x["chi2"]) and np.array_equal(a["status"], x["status"])
+
+
+def test_fit_alignment_parity(ctx, kf):
+    say("fit with alignment")
+    wl = workloads()["align20"]
+    ev = generate(wl, 3000)
+    al = ev.align_true
+    for dt, tol in ((torch.float64, TOL64), (torch.float32, TOL32)):
+        g = gpu_fit(ctx, kf, ev, dt, 0, align=al)
+        o = oracle_fit(ev, dt, 0, align=al)
+        mask = ~ill_conditioned(ev, dt, o, 0, *tol, align=al)
+        say(compare_fit(g, o, tol[0], tol[1], mask))
