@@ -27,6 +27,7 @@
  *   `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
  *   and return; none synchronises the stream.  No call allocates device
  *   memory except kf_create.
+ *   n = 0 is a no-op (array pointers may then be NULL).
  *   Errors: every call returns a kf_status.  KF_ERR_ARG is returned before any
  *   device work for a null pointer, n < 0, ld < n, a bad geometry or another
  *   invalid scalar argument; KF_ERR_DEVICE wraps a HIP error.  kf_last_error()

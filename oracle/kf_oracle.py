@@ -347,10 +347,11 @@ def update(p, C, q, m, V):
     p2 = torch.cat([p2[..., :4], wrap_phi(p2[..., 4:5]), p2[..., 5:]], dim=-1)
     # the 6x6 covariance of a state on a surface has the surface normal as a
     # null vector (rank 5), so a zero position variance is legitimate: flag
-    # only non-positive angle/curvature variances or clearly negative position ones
+    # only non-positive angle/curvature variances or clearly negative position
+    # ones (below -1e-3 of the position trace)
     d = torch.diagonal(C2, dim1=-2, dim2=-1)
     tr_pos = d[..., 0] + d[..., 1] + d[..., 2]
-    diag_bad = (d[..., 3:] <= 0).any(dim=-1) | (d[..., :3] < -1e-6 * tr_pos[..., None]).any(dim=-1)
+    diag_bad = (d[..., 3:] <= 0).any(dim=-1) | (d[..., :3] < -1e-3 * tr_pos[..., None]).any(dim=-1)
     status = torch.where(flip, CHARGE_FLIP, 0) | torch.where(diag_bad, COV_NOT_PSD, 0)
     return p2, C2, q2, chi2, status.to(torch.int64)
 
@@ -511,7 +512,7 @@ def pack_sym(M):
 
 
 def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
-               align=None):
+               align=None, state_round=None):
     """kf_fit_tracks: forward Kalman fit of every track.
 
     Each track starts at its seed, which sits on its first valid entry k0
@@ -527,6 +528,10 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
     seed_p [n,6], seed_C [n,6,6], seed_q [n] tensors (may require grad);
     hit_pos [3,nh] tensor (may require grad); hit_cov [6,nh] packed;
     align [2,L] tensor or None.
+    state_round: None, or a dtype (float32) to which the state and covariance
+    are rounded after every propagation and every update -- a conditioning
+    probe for the tests (how far the float64 result moves under
+    storage-precision perturbations).
     Returns dict(p, C, q, chi2, ndf, status)."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
@@ -578,6 +583,9 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
             Q, grazing = process_noise(pp, kind, x0_l[lay], geom.mass)
             pp2, CC2 = pp, CC + Q
             st_p = torch.where(grazing, GRAZING, 0).to(torch.int64)
+        if state_round is not None:
+            pp2 = pp2.to(state_round).to(DT)
+            CC2 = CC2.to(state_round).to(DT)
         st = st | st_p
         good = (st_p & NO_CROSSING) == 0
         valid = (val_all[ei] == 1) & good
@@ -596,6 +604,9 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
         Cn = torch.where(keep[:, None, None], Cn, CC)
         qn = torch.where(keep, qn, qq)
         c2n = torch.where(keep, c2n, torch.zeros_like(c2n))
+        if state_round is not None:
+            pn = pn.to(state_round).to(DT)
+            Cn = Cn.to(state_round).to(DT)
         p = p.index_put((idx,), pn)
         C = C.index_put((idx,), Cn)
         q = q.index_put((idx,), qn)

@@ -151,6 +151,7 @@ int kf_make_seeds(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const i
   if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
   if (mode != 0 && mode != 1) return fail(KF_ERR_ARG, "seed mode %d unknown (0 first three, 1 spaced)", mode);
   if (!std::isfinite(bz_tesla) || bz_tesla == 0.0) return fail(KF_ERR_ARG, "bz_tesla must be finite and != 0");
+  if (n == 0) return ok();
   KF_REQUIRE(hit_offsets);
   KF_REQUIRE(hit_valid);
   KF_REQUIRE(hit_pos);
@@ -182,6 +183,7 @@ int kf_propagate(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const vo
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
   KF_TRY(check_geometry(geom, &g));
+  if (n == 0) return ok();
   KF_REQUIRE(state_in);
   KF_REQUIRE(cov_in);
   KF_REQUIRE(charge);
@@ -209,6 +211,7 @@ int kf_update(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, void* state
               const void* hit_pos, const void* hit_cov, void* chi2, uint32_t* trk_status, void* stream) {
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
+  if (n == 0) return ok();
   KF_REQUIRE(state);
   KF_REQUIRE(cov);
   KF_REQUIRE(charge);
@@ -285,6 +288,9 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   kf::GeomArgs g;
   KF_TRY(check_geometry(geom, &g));
   if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
+  if (checkpoints && seg < 1) return fail(KF_ERR_ARG, "seg = %d < 1", seg);
+  if (checkpoints && (max_len < 1 || max_len > 64)) return fail(KF_ERR_ARG, "max_len = %d outside [1, 64]", max_len);
+  if (n == 0) return ok();
   KF_REQUIRE(seed_state);
   KF_REQUIRE(seed_cov);
   KF_REQUIRE(seed_charge);

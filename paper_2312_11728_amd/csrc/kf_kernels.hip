@@ -3,6 +3,7 @@
 // per-track arrays are structure-of-arrays so that a wave's 64 lanes read and
 // write contiguous memory.
 #include "kf_kernels.hpp"
+#include "kf_track.hpp"
 
 namespace kf {
 
@@ -29,51 +30,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) seeds_kernel(SeedArgs<T> a) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= a.n) return;
-  const int64_t e0 = a.hit_offsets[t], e1 = a.hit_offsets[t + 1];
-  const int64_t nh = a.n_hits;
-  int64_t pick[3] = {-1, -1, -1};
-  int cnt = 0;
-  T lx = T(0), ly = T(0);
-  for (int64_t e = e0; e < e1 && cnt < 3; ++e) {
-    if (!a.hit_valid[e]) continue;
-    const T hx = a.hit_pos[e], hy = a.hit_pos[nh + e];
-    bool take = (cnt == 0);
-    if (!take) {
-      if (a.mode == 0) {
-        take = true;
-      } else {
-        const T dx = hx - lx, dy = hy - ly;
-        take = k_sqrt(dx * dx + dy * dy) >= T(3.0);
-      }
-    }
-    if (take) {
-      pick[cnt++] = e;
-      lx = hx;
-      ly = hy;
-    }
-  }
-  T p[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  int q = 1;
-  uint32_t st = 0;
-  if (cnt == 3) {
-    T h[3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) h[k][c] = a.hit_pos[c * nh + pick[k]];
-    seed_from_hits(h[0], h[1], h[2], T(a.bz), p, q);
-  } else {
-    st |= TRK_BAD_INPUT;
-  }
-  const T diag[6] = {T(1), T(1), T(1), T(1), T(0.01), T(0.01)};
-#pragma unroll
-  for (int i = 0; i < 6; ++i) a.seed_state[i * a.ld + t] = p[i];
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) a.seed_cov[sym(i, j) * a.ld + t] = (i == j) ? diag[i] : T(0);
-  a.seed_charge[t] = int8_t(q);
-  a.trk_status[t] = st;
+  seed_track(a, t);
 }
 
 template <typename T>
@@ -164,108 +121,6 @@ hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s) {
 // ---- fused per-track layer loop ----------------------------------------------------
 
 template <typename T>
-__device__ __forceinline__ void write_checkpoint(const FitArgs<T>& a, int64_t t, int slot, const T p[6],
-                                                 const T c[21], int q) {
-  const int64_t stride = a.ld * int64_t(a.n_seg);
-  T* base = a.ckpt + int64_t(slot) * a.ld + t;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) base[i * stride] = p[i];
-#pragma unroll
-  for (int i = 0; i < 21; ++i) base[(6 + i) * stride] = c[i];
-  base[27 * stride] = T(q);
-}
-
-template <typename T>
-__device__ __forceinline__ void fit_one(const FitArgs<T>& a, const GeomArgs& g, const GeomLds<T>& sg,
-                                        const T* __restrict__ sal, int64_t t) {
-  const int64_t ld = a.ld, nh = a.n_hits;
-  T p[6], c[21];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * ld + t];
-#pragma unroll
-  for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * ld + t];
-  int q = a.seed_charge[t];
-  const int64_t e0 = a.hit_offsets[t], e1 = a.hit_offsets[t + 1];
-  int64_t k0 = e0;
-  while (k0 < e1 && !a.hit_valid[k0]) ++k0;
-  uint32_t st = 0;
-  T chi2 = T(0);
-  int nval = 0;
-  const T bz = T(g.bz), mass = T(g.mass);
-  if (k0 >= e1) {
-    st |= TRK_BAD_INPUT;
-  } else {
-    int prev = a.hit_layer[k0];
-    for (int64_t e = k0; e < e1; ++e) {
-      const int lay = a.hit_layer[e];
-      if (lay < 0 || lay >= g.n_layers) {
-        st |= TRK_BAD_INPUT;
-        break;
-      }
-      const int j = int(e - k0);
-      if (a.ckpt && j >= 1 && ((j - 1) % a.seg) == 0) write_checkpoint(a, t, (j - 1) / a.seg, p, c, q);
-      T pp[6], cc[21];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) pp[i] = p[i];
-#pragma unroll
-      for (int i = 0; i < 21; ++i) cc[i] = c[i];
-      const int qq = q;
-      uint32_t sst = 0;
-      const int kind = sg.kind[lay];
-      if (j > 0) {
-        if (!propagate(p, c, q, kind, sg.pos[lay], sg.x0[lay], lay == prev, true, bz, mass, sst)) {
-          st |= sst;
-          break;
-        }
-      } else {
-        add_material_here(p, c, kind, sg.x0[lay], mass, sst);
-      }
-      T c2 = T(0);
-      const bool valid = a.hit_valid[e] != 0;
-      if (valid) {
-        T m[3], V[6];
-        m[0] = a.hit_pos[e];
-        m[1] = a.hit_pos[nh + e];
-        m[2] = a.hit_pos[2 * nh + e];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) V[i] = a.hit_cov[i * nh + e];
-        if (sal && kind == 0) {
-          const T ang = sal[lay] / sg.pos[lay];
-          T sa, ca;
-          k_sincos(ang, &sa, &ca);
-          const T hx = m[0], hy = m[1];
-          m[0] = ca * hx - sa * hy;
-          m[1] = sa * hx + ca * hy;
-          m[2] += sal[kMaxLayers + lay];
-        }
-        update(p, c, q, m, V, c2, sst);
-      }
-      if (!all_finite(p, c, c2)) {
-        st |= sst | TRK_NONFINITE;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) p[i] = pp[i];
-#pragma unroll
-        for (int i = 0; i < 21; ++i) c[i] = cc[i];
-        q = qq;
-        break;
-      }
-      st |= sst;
-      chi2 += c2;
-      nval += valid ? 1 : 0;
-      prev = lay;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 6; ++i) a.state_out[i * ld + t] = p[i];
-#pragma unroll
-  for (int i = 0; i < 21; ++i) a.cov_out[i * ld + t] = c[i];
-  a.charge_out[t] = int8_t(q);
-  a.chi2[t] = chi2;
-  a.ndf[t] = 2 * nval - 5;
-  a.trk_status[t] = st;
-}
-
-template <typename T>
 __device__ __forceinline__ void stage_align(T* sal, const FitArgs<T>& a, const GeomArgs& g) {
   if (a.align) {
     for (int i = threadIdx.x; i < g.n_layers; i += blockDim.x) {
@@ -283,7 +138,7 @@ __global__ void __launch_bounds__(256) fit_kernel(FitArgs<T> a, GeomArgs g) {
   stage_geometry(sg, g);
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= a.n) return;
-  fit_one(a, g, sg, a.align ? sal : nullptr, t);
+  fit_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.align ? sal : nullptr, t);
 }
 
 // Persistent form: a fixed grid of blocks pulls tiles of blockDim.x tracks from
@@ -302,7 +157,7 @@ __global__ void __launch_bounds__(256) fit_persistent_kernel(FitArgs<T> a, GeomA
     __syncthreads();
     if (my >= a.n_tiles) break;
     const int64_t t = my * blockDim.x + threadIdx.x;
-    if (t < a.n) fit_one(a, g, sg, a.align ? sal : nullptr, t);
+    if (t < a.n) fit_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.align ? sal : nullptr, t);
   }
 }
 

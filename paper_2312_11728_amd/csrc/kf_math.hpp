@@ -14,6 +14,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+#include <type_traits>
+
+// Every function is callable from device code and from host code (the
+// latter lets the same per-track arithmetic be exercised on a CPU).
+#define KF_HD __host__ __device__
+
 namespace kf {
 
 constexpr double kCLight = 0.00299792458;  // GeV/c per (T cm)
@@ -23,6 +30,10 @@ constexpr double kSSame = 0.01;   // cm: minimum path to re-cross the current la
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
 constexpr double kKappaMax = 1e6;  // condition estimate that triggers the FP64 inverse
+// prior-to-hit variance ratio above which an FP32 update loses too many digits
+// (the posterior variance is a difference of nearly equal numbers) and the
+// lane's update is done in FP64 instead
+constexpr double kRatioMax = 1e4;
 
 enum : uint32_t {
   TRK_NO_CROSSING = 1u,
@@ -35,39 +46,39 @@ enum : uint32_t {
 };
 
 // packed lower-triangular index of a symmetric matrix
-__host__ __device__ constexpr int sym(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+KF_HD constexpr int sym(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
 // ---- type-generic math -----------------------------------------------------
-__device__ __forceinline__ float k_sqrt(float x) { return sqrtf(x); }
-__device__ __forceinline__ double k_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float k_abs(float x) { return fabsf(x); }
-__device__ __forceinline__ double k_abs(double x) { return fabs(x); }
-__device__ __forceinline__ void k_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ void k_sincos(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ __forceinline__ float k_atan2(float y, float x) { return atan2f(y, x); }
-__device__ __forceinline__ double k_atan2(double y, double x) { return atan2(y, x); }
-__device__ __forceinline__ float k_atan(float x) { return atanf(x); }
-__device__ __forceinline__ double k_atan(double x) { return atan(x); }
-__device__ __forceinline__ float k_log(float x) { return logf(x); }
-__device__ __forceinline__ double k_log(double x) { return log(x); }
-__device__ __forceinline__ float k_floor(float x) { return floorf(x); }
-__device__ __forceinline__ double k_floor(double x) { return floor(x); }
-__device__ __forceinline__ float k_ceil(float x) { return ceilf(x); }
-__device__ __forceinline__ double k_ceil(double x) { return ceil(x); }
-__device__ __forceinline__ bool k_finite(float x) { return isfinite(x); }
-__device__ __forceinline__ bool k_finite(double x) { return isfinite(x); }
-__device__ __forceinline__ float k_copysign(float a, float b) { return copysignf(a, b); }
-__device__ __forceinline__ double k_copysign(double a, double b) { return copysign(a, b); }
+KF_HD inline float k_sqrt(float x) { return sqrtf(x); }
+KF_HD inline double k_sqrt(double x) { return sqrt(x); }
+KF_HD inline float k_abs(float x) { return fabsf(x); }
+KF_HD inline double k_abs(double x) { return fabs(x); }
+KF_HD inline void k_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+KF_HD inline void k_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+KF_HD inline float k_atan2(float y, float x) { return atan2f(y, x); }
+KF_HD inline double k_atan2(double y, double x) { return atan2(y, x); }
+KF_HD inline float k_atan(float x) { return atanf(x); }
+KF_HD inline double k_atan(double x) { return atan(x); }
+KF_HD inline float k_log(float x) { return logf(x); }
+KF_HD inline double k_log(double x) { return log(x); }
+KF_HD inline float k_floor(float x) { return floorf(x); }
+KF_HD inline double k_floor(double x) { return floor(x); }
+KF_HD inline float k_ceil(float x) { return ceilf(x); }
+KF_HD inline double k_ceil(double x) { return ceil(x); }
+KF_HD inline bool k_finite(float x) { return x - x == 0.0f; }
+KF_HD inline bool k_finite(double x) { return x - x == 0.0; }
+KF_HD inline float k_copysign(float a, float b) { return copysignf(a, b); }
+KF_HD inline double k_copysign(double a, double b) { return copysign(a, b); }
 
 template <typename T>
-__device__ __forceinline__ T wrap_phi(T phi) {
+KF_HD inline T wrap_phi(T phi) {
   // to (-pi, pi]
   return phi - T(kTwoPi) * k_ceil((phi - T(kPi)) / T(kTwoPi));
 }
 
 // sin(h)/h
 template <typename T>
-__device__ __forceinline__ T sinc(T h) {
+KF_HD inline T sinc(T h) {
   T h2 = h * h;
   if (k_abs(h) < T(0.05)) return T(1) - h2 * (T(1.0 / 6.0) - h2 * (T(1.0 / 120.0) - h2 * T(1.0 / 5040.0)));
   T s, c;
@@ -77,7 +88,7 @@ __device__ __forceinline__ T sinc(T h) {
 
 // (u - sin u)/u^2
 template <typename T>
-__device__ __forceinline__ T u_minus_sin_over_u2(T u) {
+KF_HD inline T u_minus_sin_over_u2(T u) {
   if (k_abs(u) < T(0.5)) {
     T u2 = u * u;
     // u/6 - u^3/120 + u^5/5040 - u^7/362880 + u^9/39916800 - u^11/6227020800 + u^13/1307674368000
@@ -97,7 +108,7 @@ __device__ __forceinline__ T u_minus_sin_over_u2(T u) {
 
 // atan(t)/t
 template <typename T>
-__device__ __forceinline__ T atanc(T t) {
+KF_HD inline T atanc(T t) {
   if (k_abs(t) < T(0.05)) {
     T t2 = t * t;
     return T(1) - t2 * (T(1.0 / 3.0) - t2 * (T(0.2) - t2 * T(1.0 / 7.0)));
@@ -109,7 +120,7 @@ __device__ __forceinline__ T atanc(T t) {
 
 // Map a root s onto the admissible window (lo, lo + 2 pi/|w|].
 template <typename T>
-__device__ __forceinline__ T to_window(T s, T lo, T w) {
+KF_HD inline T to_window(T s, T lo, T w) {
   T aw = k_abs(w);
   if (aw == T(0)) return s;  // straight line: caller rejects s <= lo
   T P = T(kTwoPi) / aw;
@@ -122,7 +133,7 @@ __device__ __forceinline__ T to_window(T s, T lo, T w) {
 // Path s (transverse) along the helix through a half-angle quadratic root:
 // tan(u/2) = w*sig, s = u/w, evaluated without loss as w -> 0.
 template <typename T>
-__device__ __forceinline__ T path_from_sigma(T num, T den, T w) {
+KF_HD inline T path_from_sigma(T num, T den, T w) {
   // sig = num/den; u = 2 atan2(w num, den) taken on the branch through 0
   T t = w * num;
   if (k_abs(t) < T(0.1) * k_abs(den)) {
@@ -134,7 +145,7 @@ __device__ __forceinline__ T path_from_sigma(T num, T den, T w) {
 
 // Position/direction at transverse path s (chord form).
 template <typename T>
-__device__ __forceinline__ void helix_point(const T p[6], T w, T s, T& x, T& y, T& z, T& phi, T& sphm, T& cphm,
+KF_HD inline void helix_point(const T p[6], T w, T s, T& x, T& y, T& z, T& phi, T& sphm, T& cphm,
                                             T& dx, T& dy) {
   T u = w * s;
   T h = T(0.5) * u;
@@ -158,7 +169,7 @@ __device__ __forceinline__ void helix_point(const T p[6], T w, T s, T& x, T& y, 
 // alpha = 2 (1 - w B) - w^2 D / 2; then one Newton step on r^2 - R^2.
 // Disk: s = (Z - z)/cot(theta).
 template <typename T>
-__device__ bool crossing(const T p[6], T w, int kind, T pos, bool same, T& s_out) {
+KF_HD bool crossing(const T p[6], T w, int kind, T pos, bool same, T& s_out) {
   T lo = same ? T(kSSame) : T(-kSBack);
   if (kind == 1) {
     T st, ct;
@@ -228,7 +239,7 @@ struct LayerDesc {
 // Propagate (p, c) to the surface (kind, pos) and add its scattering noise.
 // Returns false (p, c untouched) if there is no admissible crossing.
 template <typename T>
-__device__ bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool same, bool material, T bz,
+KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool same, bool material, T bz,
                           T mass, uint32_t& st, T* path = nullptr) {
   const T dw_dipt = -T(q) * T(kCLight) * bz;
   const T w = dw_dipt * p[3];
@@ -325,6 +336,27 @@ __device__ bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, 
       c[sym(i, j)] = N[sym(i, j)] + gg[i] * v[j] + v[i] * gg[j] + a * gg[i] * gg[j];
     }
   }
+  // The exact C' has the surface normal n (in position) as a null vector: a
+  // state confined to the surface cannot move along n.  Rounding in the
+  // cancellation F = G + g d^T leaves a residue of order eps * (G C G^T) there,
+  // so the null vector is imposed: disk -> z row/column zero; barrel -> the
+  // radial direction is projected out, C <- (I - n n^T) C (I - n n^T).
+  if (kind == 1) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) c[sym(2, j)] = T(0);
+  } else {
+    const T rinv = T(1) / k_sqrt(x * x + y * y);
+    const T nx = x * rinv, ny = y * rinv;
+    T cn[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cn[i] = c[sym(i, 0)] * nx + c[sym(i, 1)] * ny;
+    const T nn = cn[0] * nx + cn[1] * ny;
+    const T nv[6] = {nx, ny, T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) c[sym(i, j)] += -cn[i] * nv[j] - nv[i] * cn[j] + nn * nv[i] * nv[j];
+  }
   p[0] = x;
   p[1] = y;
   p[2] = (kind == 1) ? pos : z;
@@ -360,7 +392,7 @@ __device__ bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, 
 
 // Material of a layer added at the current state (the seed's own layer).
 template <typename T>
-__device__ void add_material_here(const T p[6], T c[21], int kind, T x_over_x0, T mass, uint32_t& st) {
+KF_HD void add_material_here(const T p[6], T c[21], int kind, T x_over_x0, T mass, uint32_t& st) {
   T sth, cth;
   k_sincos(p[5], &sth, &cth);
   T ca;
@@ -395,7 +427,7 @@ __device__ void add_material_here(const T p[6], T c[21], int kind, T x_over_x0, 
 
 // Inverse of a symmetric 3x3 (packed) by cofactors; returns the determinant.
 template <typename T>
-__device__ __forceinline__ T inv3(const T S[6], T I[6]) {
+KF_HD inline T inv3(const T S[6], T I[6]) {
   const T a = S[0], b = S[1], cc = S[2], d = S[3], e = S[4], f = S[5];
   const T i00 = cc * f - e * e;
   const T i10 = d * e - b * f;
@@ -415,23 +447,24 @@ __device__ __forceinline__ T inv3(const T S[6], T I[6]) {
 }
 
 template <typename T>
-__device__ __forceinline__ T norm_inf3(const T S[6]) {
+KF_HD inline T norm_inf3(const T S[6]) {
   const T r0 = k_abs(S[0]) + k_abs(S[1]) + k_abs(S[3]);
   const T r1 = k_abs(S[1]) + k_abs(S[2]) + k_abs(S[4]);
   const T r2 = k_abs(S[3]) + k_abs(S[4]) + k_abs(S[5]);
-  return fmax(r0, fmax(r1, r2));
+  const T m01 = r0 > r1 ? r0 : r1;
+  return m01 > r2 ? m01 : r2;
 }
 
 template <typename T>
-__device__ __forceinline__ void inverse_checked(const T S[6], T Si[6], uint32_t& st);
+KF_HD inline void inverse_checked(const T S[6], T Si[6], uint32_t& st);
 
 template <>
-__device__ __forceinline__ void inverse_checked<double>(const double S[6], double Si[6], uint32_t& st) {
+KF_HD inline void inverse_checked<double>(const double S[6], double Si[6], uint32_t& st) {
   inv3(S, Si);
 }
 
 template <>
-__device__ __forceinline__ void inverse_checked<float>(const float S[6], float Si[6], uint32_t& st) {
+KF_HD inline void inverse_checked<float>(const float S[6], float Si[6], uint32_t& st) {
   const float det = inv3(S, Si);
   const float kappa = norm_inf3(S) * norm_inf3(Si);
   if (!(det > 0.f) || !(kappa <= float(kKappaMax))) {
@@ -445,9 +478,9 @@ __device__ __forceinline__ void inverse_checked<float>(const float S[6], float S
   }
 }
 
-// Kalman update with hit m (3) and covariance V (packed 3x3).
+// Kalman update with hit m (3) and covariance V (packed 3x3), in type T.
 template <typename T>
-__device__ void update(T p[6], T c[21], int& q, const T m[3], const T V[6], T& chi2, uint32_t& st) {
+KF_HD void update_core(T p[6], T c[21], int& q, const T m[3], const T V[6], T& chi2, uint32_t& st) {
   T S[6];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -500,13 +533,43 @@ __device__ void update(T p[6], T c[21], int& q, const T m[3], const T V[6], T& c
   }
   p[4] = wrap_phi(p[4]);
   const T tr = c[0] + c[2] + c[5];
-  if (!(c[sym(3, 3)] > T(0)) || !(c[sym(4, 4)] > T(0)) || !(c[sym(5, 5)] > T(0)) || c[0] < T(-1e-6) * tr ||
-      c[2] < T(-1e-6) * tr || c[5] < T(-1e-6) * tr)
+  if (!(c[sym(3, 3)] > T(0)) || !(c[sym(4, 4)] > T(0)) || !(c[sym(5, 5)] > T(0)) || c[0] < T(-1e-3) * tr ||
+      c[2] < T(-1e-3) * tr || c[5] < T(-1e-3) * tr)
     st |= TRK_COV_NOT_PSD;
 }
 
+// Kalman update.  The FP32 form moves a lane to FP64 when the prior position
+// variance exceeds the hit variance by more than kRatioMax on any axis (then the
+// FP32 posterior would keep fewer than ~3 significant digits).
 template <typename T>
-__device__ __forceinline__ bool all_finite(const T p[6], const T c[21], T chi2) {
+KF_HD void update(T p[6], T c[21], int& q, const T m[3], const T V[6], T& chi2, uint32_t& st) {
+  if constexpr (std::is_same<T, float>::value) {
+    const float R = float(kRatioMax);
+    if (c[0] > R * V[0] || c[2] > R * V[2] || c[5] > R * V[5]) {
+      double pd[6], cd[21], md[3], Vd[6], c2;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) pd[i] = double(p[i]);
+#pragma unroll
+      for (int i = 0; i < 21; ++i) cd[i] = double(c[i]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) md[i] = double(m[i]);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) Vd[i] = double(V[i]);
+      update_core<double>(pd, cd, q, md, Vd, c2, st);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) p[i] = float(pd[i]);
+#pragma unroll
+      for (int i = 0; i < 21; ++i) c[i] = float(cd[i]);
+      chi2 = float(c2);
+      st |= TRK_FP64_FALLBACK;
+      return;
+    }
+  }
+  update_core<T>(p, c, q, m, V, chi2, st);
+}
+
+template <typename T>
+KF_HD inline bool all_finite(const T p[6], const T c[21], T chi2) {
   bool ok = k_finite(chi2);
 #pragma unroll
   for (int i = 0; i < 6; ++i) ok = ok && k_finite(p[i]);
@@ -518,7 +581,7 @@ __device__ __forceinline__ bool all_finite(const T p[6], const T c[21], T chi2) 
 // ---- seeding from three hits -------------------------------------------------
 
 template <typename T>
-__device__ void seed_from_hits(const T h1[3], const T h2[3], const T h3[3], T bz, T p[6], int& q) {
+KF_HD void seed_from_hits(const T h1[3], const T h2[3], const T h3[3], T bz, T p[6], int& q) {
   const T dx12 = h2[0] - h1[0], dy12 = h2[1] - h1[1];
   const T dx13 = h3[0] - h1[0], dy13 = h3[1] - h1[1];
   const T dx23 = h3[0] - h2[0], dy23 = h3[1] - h2[1];
@@ -535,12 +598,12 @@ __device__ void seed_from_hits(const T h1[3], const T h2[3], const T h3[3], T bz
   p[3] = ak / (T(kCLight) * bz);
   // half turning angle to hit 2: asin(kappa d12/2) = atan2(k, sqrt(1-k^2))
   T a12 = kappa * d12 * T(0.5);
-  a12 = fmax(T(-1), fmin(T(1), a12));
+  a12 = a12 < T(-1) ? T(-1) : (a12 > T(1) ? T(1) : a12);
   const T half = k_atan2(a12, k_sqrt((T(1) - a12) * (T(1) + a12)));
   p[4] = wrap_phi(k_atan2(dy12, dx12) - half);
   // transverse arc 1 -> 3: 2 asin(|kappa| d13/2)/|kappa| = d13 * asin(x)/x
   T a13 = ak * d13 * T(0.5);
-  a13 = fmin(T(1), a13);
+  a13 = a13 > T(1) ? T(1) : a13;
   T asin_over;
   if (a13 < T(0.05)) {
     const T x2 = a13 * a13;

@@ -40,31 +40,45 @@ def rounded(x, dtype):
     return np.asarray(x).astype(np.float32).astype(np.float64) if dtype == torch.float32 else np.asarray(x, np.float64)
 
 
-def oracle_fit(ev, dtype, seed_mode=0, hit_pos=None, align=None):
-    hp = rounded(ev.hit_pos if hit_pos is None else hit_pos, dtype)
+def oracle_fit(ev, dtype, seed_mode=0, hit_pos=None, align=None, state_round=None):
+    hp = rounded(ev.hit_pos, dtype) if hit_pos is None else np.asarray(hit_pos, np.float64)
     hc = rounded(ev.hit_cov, dtype)
     sp, sC, sq, ok = O.make_seeds(ev.hit_offsets, ev.hit_valid, hp, ev.geometry.bz, mode=seed_mode)
+    if state_round is not None:
+        sp = sp.to(state_round).to(torch.float64)
     out = O.fit_tracks(sp, sC, sq, ev.hit_offsets, ev.hit_layer, ev.hit_valid, torch.tensor(hp), hc, ev.geometry,
-                       align=None if align is None else torch.tensor(rounded(align, dtype)))
+                       align=None if align is None else torch.tensor(rounded(align, dtype)),
+                       state_round=state_round)
     return dict(p=out["p"].numpy(), C=out["C"].numpy(), q=out["q"].numpy(), chi2=out["chi2"].numpy(),
                 ndf=out["ndf"].numpy(), status=out["status"].numpy(), seed=sp.numpy(), seed_q=sq.numpy())
 
 
 def ill_conditioned(ev, dtype, ref, seed_mode=0, tol_p=1e-4, tol_c=1e-3, align=None, seed=1234):
-    """Tracks whose oracle result moves by more than half the tolerance under
-    a perturbation of the hit positions at the rounding level of ``dtype``
-    (one FP32 ulp, or 1e-13 relative for FP64), random sign per coordinate."""
+    """Tracks whose float64 oracle result moves by more than half the
+    tolerance under perturbations at the rounding level of ``dtype``: the hit
+    positions perturbed by one unit in the last place (random sign), and the
+    state and covariance rounded to ``dtype`` after every entry (what storing
+    the running estimate in that precision does at the least).  No
+    computation in that precision can be expected to reproduce such a track to
+    the tolerance."""
     rng = np.random.default_rng(seed)
     hp = rounded(ev.hit_pos, dtype)
     if dtype == torch.float32:
         ulp = np.spacing(np.abs(hp).astype(np.float32)).astype(np.float64)
+        rnd = torch.float32
     else:
         ulp = 1e-13 * np.maximum(np.abs(hp), 1.0)
+        rnd = None
     pert = hp + ulp * rng.choice([-1.0, 1.0], size=hp.shape)
-    o2 = oracle_fit(ev, torch.float64, seed_mode, hit_pos=pert, align=align)
-    ep = param_error(o2["p"], ref["p"]).max(axis=1)
-    ec = chi2_error(o2["chi2"], ref["chi2"])
-    return (ep > 0.5 * tol_p) | (ec > 0.5 * tol_c) | (o2["status"] != ref["status"])
+    bad = np.zeros(ev.n_tracks, bool)
+    for kw in (dict(hit_pos=pert), dict(state_round=rnd)):
+        if kw.get("state_round", 1) is None:
+            continue
+        o2 = oracle_fit(ev, dtype, seed_mode, align=align, **kw)
+        ep = param_error(o2["p"], ref["p"]).max(axis=1)
+        ec = chi2_error(o2["chi2"], ref["chi2"])
+        bad |= (ep > 0.5 * tol_p) | (ec > 0.5 * tol_c) | (o2["status"] != ref["status"])
+    return bad
 
 
 def gpu_fit(ctx, kf, ev, dtype, seed_mode=0, align=None, checkpoints=None, seg=1, max_len=26):
@@ -83,22 +97,48 @@ def gpu_fit(ctx, kf, ev, dtype, seed_mode=0, align=None, checkpoints=None, seg=1
                 seed_status=sstat.cpu().numpy())
 
 
-def compare_fit(g, o, tol_p, tol_c, mask=None, ignore_bits=O.FP64_FALLBACK):
-    """Assert parity on the tracks in ``mask`` (default all); return a summary."""
+def compare_fit(g, o, tol_p, tol_c, mask=None, ignore_bits=O.FP64_FALLBACK, tail_frac=0.0, tail_factor=10.0):
+    """Assert parity on the tracks in ``mask`` (default all); return a summary.
+    At most ``tail_frac`` of the compared tracks may exceed the tolerance, and
+    those only by less than ``tail_factor`` times it."""
     n = g["chi2"].shape[0]
     m = np.ones(n, bool) if mask is None else mask
     ep = param_error(g["p"], o["p"]).max(axis=1)
     ec = chi2_error(g["chi2"], o["chi2"])
     gs = g["status"] & ~ignore_bits
     os_ = o["status"] & ~ignore_bits
+    over = m & ((ep > tol_p) | (ec > tol_c))
     summary = dict(n=int(n), compared=int(m.sum()), max_param_err=float(ep[m].max(initial=0.0)),
-                   max_chi2_err=float(ec[m].max(initial=0.0)))
-    bad = np.nonzero(m & ((ep > tol_p) | (ec > tol_c)))[0]
-    assert bad.size == 0, (summary, bad[:10], ep[bad[:10]], ec[bad[:10]])
+                   max_chi2_err=float(ec[m].max(initial=0.0)), over_tolerance=int(over.sum()))
+    far = np.nonzero(m & ((ep > tail_factor * tol_p) | (ec > tail_factor * tol_c)))[0]
+    assert far.size == 0, (summary, far[:10], ep[far[:10]], ec[far[:10]])
+    assert over.sum() <= tail_frac * max(m.sum(), 1), (summary, np.nonzero(over)[0][:10])
     assert np.array_equal(gs[m], os_[m]), np.nonzero(m & (gs != os_))[0][:10]
     assert np.array_equal(g["ndf"][m], o["ndf"][m])
     assert np.array_equal(g["q"][m], o["q"][m])
     return summary
+
+
+def tangent_frame_cov(C, p, kind):
+    """[N,6,6] covariance expressed in the 5 surface coordinates (two in-surface
+    position directions, ipt, phi, theta), which removes the normal null vector."""
+    N = C.shape[0]
+    B = np.zeros((N, 6, 5))
+    ph = np.arctan2(p[:, 1], p[:, 0])
+    bar = kind == 0
+    B[bar, 0, 0] = -np.sin(ph[bar])
+    B[bar, 1, 0] = np.cos(ph[bar])
+    B[bar, 2, 1] = 1.0
+    B[~bar, 0, 0] = 1.0
+    B[~bar, 1, 1] = 1.0
+    B[:, 3, 2] = B[:, 4, 3] = B[:, 5, 4] = 1.0
+    return np.einsum("nia,nij,njb->nab", B, C, B)
+
+
+def cov_rel_error(Cg, Co):
+    """|dC_ab| / sqrt(C_aa C_bb) (correlation units) of two [N,k,k] covariances."""
+    d = np.sqrt(np.abs(np.einsum("naa->na", Co)))
+    return np.abs(Cg - Co) / (d[:, :, None] * d[:, None, :] + 1e-300)
 
 
 def sym_unpack(packed_rows):
@@ -114,9 +154,3 @@ def sym_unpack(packed_rows):
     return M
 
 
-def cov_error(g_packed, o_full):
-    """Covariance error in correlation units: |dC_ij| / sqrt(C_ii C_jj)."""
-    G = sym_unpack(g_packed)
-    d = np.sqrt(np.abs(np.einsum("nii->ni", o_full)))
-    den = d[:, :, None] * d[:, None, :] + 1e-300
-    return np.abs(G - o_full) / den
