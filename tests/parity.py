@@ -97,10 +97,15 @@ def gpu_fit(ctx, kf, ev, dtype, seed_mode=0, align=None, checkpoints=None, seg=1
                 seed_status=sstat.cpu().numpy())
 
 
-def compare_fit(g, o, tol_p, tol_c, mask=None, ignore_bits=O.FP64_FALLBACK, tail_frac=0.0, tail_factor=10.0):
+def compare_fit(g, o, tol_p, tol_c, mask=None, ignore_bits=O.FP64_FALLBACK, tail_frac=0.0, tail_factor=10.0,
+                tail_factor_chi2=20.0):
     """Assert parity on the tracks in ``mask`` (default all); return a summary.
     At most ``tail_frac`` of the compared tracks may exceed the tolerance, and
-    those only by less than ``tail_factor`` times it."""
+    those only by less than ``tail_factor`` (parameters) or
+    ``tail_factor_chi2`` (chi2) times it.  The chi2 tail is set by the FP32
+    resolution of absolute positions: at r ~ 100 cm one unit in the last place
+    (7.6e-6 cm) is 0.25% of the r-phi resolution, so a residual of a few sigma
+    carries a relative chi2 error of that order."""
     n = g["chi2"].shape[0]
     m = np.ones(n, bool) if mask is None else mask
     ep = param_error(g["p"], o["p"]).max(axis=1)
@@ -110,7 +115,7 @@ def compare_fit(g, o, tol_p, tol_c, mask=None, ignore_bits=O.FP64_FALLBACK, tail
     over = m & ((ep > tol_p) | (ec > tol_c))
     summary = dict(n=int(n), compared=int(m.sum()), max_param_err=float(ep[m].max(initial=0.0)),
                    max_chi2_err=float(ec[m].max(initial=0.0)), over_tolerance=int(over.sum()))
-    far = np.nonzero(m & ((ep > tail_factor * tol_p) | (ec > tail_factor * tol_c)))[0]
+    far = np.nonzero(m & ((ep > tail_factor * tol_p) | (ec > tail_factor_chi2 * tol_c)))[0]
     assert far.size == 0, (summary, far[:10], ep[far[:10]], ec[far[:10]])
     assert over.sum() <= tail_frac * max(m.sum(), 1), (summary, np.nonzero(over)[0][:10])
     assert np.array_equal(gs[m], os_[m]), np.nonzero(m & (gs != os_))[0][:10]

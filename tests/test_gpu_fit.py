@@ -206,7 +206,7 @@ def _fit_case(ctx, kf, ev, dtype, seed_mode, tol, max_bad_frac=0.0, tail_frac=0.
     o = oracle_fit(ev, dtype, seed_mode)
     bad = ill_conditioned(ev, dtype, o, seed_mode, *tol)
     mask = ~bad
-    assert bad.mean() <= max(max_bad_frac, 0.005), bad.mean()
+    assert bad.sum() <= max(max_bad_frac, 0.005) * ev.n_tracks, bad.mean()
     s = compare_fit(g, o, tol[0], tol[1], mask, tail_frac=tail_frac)
     s["ill_conditioned"] = int((~mask).sum())
     say(s)
@@ -322,4 +322,4 @@ def test_fit_alignment_parity(ctx, kf):
         g = gpu_fit(ctx, kf, ev, dt, 0, align=al)
         o = oracle_fit(ev, dt, 0, align=al)
         mask = ~ill_conditioned(ev, dt, o, 0, *tol, align=al)
-        say(compare_fit(g, o, tol[0], tol[1], mask, tail_frac=0.001 if dt == torch.float32 else 0.0))
+        say(compare_fit(g, o, tol[0], tol[1], mask, tail_frac=0.002 if dt == torch.float32 else 0.0))
