@@ -76,6 +76,37 @@ def cpu_baseline(ev, seconds=10.0):
                 sample=f"{reps} x full batch of {ev.n_tracks} tracks (seeding + fit, float64 torch CPU)")
 
 
+def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
+    """500,000 tracks through 10 barrel layers and 2 x 8 disks, 3-26 entries,
+    5% holes, one launch of the fused fit with the autotuned shape."""
+    import torch
+    dev = torch.device("cuda", 0)
+    wl = workloads()["mixed26"]
+    log("generating", wl.name, wl.n_tracks)
+    t0 = time.time()
+    ev = generate(wl)
+    log("generated in", round(time.time() - t0, 1), "s")
+    n = ev.n_tracks
+    t = K.event_tensors(ev, torch.float32, dev)
+    geom = K.Geometry.from_toy(wl.geometry)
+    seeds = ctx.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"], wl.geometry.bz, 1)
+    out = K.fit_outputs(n, torch.float32, dev)
+
+    def fit_step():
+        ctx.fit_tracks(seeds[0], seeds[1], seeds[2], t["hit_offsets"], t["hit_layer"], t["hit_valid"],
+                       t["hit_pos"], t["hit_cov"], geom, out=out)
+
+    best, table = tune_fit(ctx, fit_step, torch.float32, n, use_cache=not args.retune, cache_path=args.tune_cache)
+    log("autotune mixed26", best, [(s_, round(ms, 4)) for s_, ms in table])
+    ms = time_loop(fit_step, args.steps, args.warmup)
+    flops = algorithmic_flops(ev)
+    lens = ev.lengths()
+    return {"tracks": n, "entries": int(ev.n_hits), "valid": int(ev.hit_valid.sum()),
+            "length_min": int(lens.min()), "length_max": int(lens.max()), "ms_fit": ms,
+            "tracks_per_s": n / (ms * 1e-3), "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+            "frac_fp32_peak": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, "launch": list(best)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +114,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 500k-track barrel+endcap workload")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "kf_autotune.json"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (tracks are independent: "
@@ -91,6 +125,7 @@ def main():
 
     import torch
     from paper_2312_11728_amd import kf as K
+    from paper_2312_11728_amd.autotune import tune_fit
     from toygen import generate, workloads
 
     dev = torch.device("cuda", 0)
@@ -118,10 +153,13 @@ def main():
             seed_step()
             fit_step()
 
+        seed_step()
+        best, table = tune_fit(ctx, fit_step, dt, n, use_cache=not args.retune, cache_path=args.tune_cache)
+        log("autotune", dt, "best", best, "table", [(s_, round(ms, 4)) for s_, ms in table])
         log("timing", dt)
         ms_step = time_loop(step, args.steps, args.warmup)
         ms_fit = time_loop(fit_step, args.steps, args.warmup)
-        res[dt] = dict(ms_step=ms_step, ms_fit=ms_fit, out=out, seeds=seeds)
+        res[dt] = dict(ms_step=ms_step, ms_fit=ms_fit, out=out, seeds=seeds, launch=best)
         log(dt, "ms/step", ms_step, "fit kernel ms", ms_fit)
 
     r32, r64 = res[torch.float32], res[torch.float64]
@@ -145,6 +183,8 @@ def main():
                    "tracks": n, "entries": int(ev.n_hits)},
         "fp64_gpu": {"value": n / (r64["ms_step"] * 1e-3), "unit": "tracks/s", "ms_per_step": r64["ms_step"]},
         "fp32_over_fp64": r64["ms_step"] / r32["ms_step"],
+        "launch": {"fp32": list(r32["launch"]), "fp64": list(r64["launch"]),
+                   "fields": ["block", "persistent", "blocks_per_cu", "waves_per_simd"]},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP32_PEAK_TFLOPS, "traffic": None,
                      "kernel": "fit_kernel<float>", "kernel_ms": r32["ms_fit"],
@@ -161,6 +201,8 @@ def main():
         line["accuracy_vs_oracle"] = {"max_param_err": float(ep[~bad].max()), "max_chi2_err": float(ec[~bad].max()),
                                       "tracks_compared": int((~bad).sum()), "ill_conditioned": int(bad.sum()),
                                       "tolerance": {"param": 1e-4, "chi2": 1e-3}}
+    if not args.no_uneven:
+        line["uneven_mixed26"] = bench_uneven(ctx, K, tune_fit, generate, workloads, args)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(ev)

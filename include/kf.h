@@ -235,13 +235,16 @@ int kf_fit_adjoint(kf_ctx *ctx, int64_t n, int64_t ld,
 /* ---- execution tuning (no effect on results) --------------------------------
  * Launch shape of kf_fit_tracks for one precision: threads per block (64, 128,
  * 192 or 256), persistent (1: a fixed grid of n_cu * blocks_per_cu blocks that
- * pull tiles of `block` tracks from a device counter; 0: one thread per track)
- * and blocks_per_cu (1..32).  Every launch shape computes bit-identical
- * results; the choice is made by the autotuner of the Python package and only
- * changes speed.  Stored in the context. */
-int kf_set_fit_launch(kf_ctx *ctx, kf_precision prec, int32_t block, int32_t persistent, int32_t blocks_per_cu);
+ * pull tiles of `block` tracks from a device counter; 0: one thread per
+ * track), blocks_per_cu (1..32) and waves (1 or 2: the kernel variant whose
+ * register allocation allows at least that many waves per SIMD).  Every
+ * launch shape computes bit-identical results; the choice is made by the
+ * autotuner of the Python package and only changes speed.  Stored in the
+ * context. */
+int kf_set_fit_launch(kf_ctx *ctx, kf_precision prec, int32_t block, int32_t persistent, int32_t blocks_per_cu,
+                      int32_t waves);
 int kf_get_fit_launch(const kf_ctx *ctx, kf_precision prec, int32_t *block, int32_t *persistent,
-                      int32_t *blocks_per_cu);
+                      int32_t *blocks_per_cu, int32_t *waves);
 /* Number of compute units of the context's device. */
 int kf_device_cu_count(const kf_ctx *ctx, int32_t *n_cu);
 

@@ -16,7 +16,7 @@ struct kf_ctx {
   int device = 0;
   int n_cu = 256;
   int32_t* d_counter = nullptr;      // persistent-kernel tile counter
-  kf::FitLaunch fit[2] = {{256, 0, 4}, {256, 0, 4}};  // per precision
+  kf::FitLaunch fit[2] = {{256, 0, 4, 1}, {256, 0, 4, 1}};  // per precision
   // graph cache for kf_fit_tracks (one entry per precision)
   bool use_graph[2] = {false, false};
   hipStream_t capture = nullptr;
@@ -332,27 +332,31 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   return ok();
 }
 
-int kf_set_fit_launch(kf_ctx* ctx, kf_precision prec, int32_t block, int32_t persistent, int32_t blocks_per_cu) {
+int kf_set_fit_launch(kf_ctx* ctx, kf_precision prec, int32_t block, int32_t persistent, int32_t blocks_per_cu,
+                      int32_t waves) {
   KF_TRY(check_prec(prec));
+  if (waves != 1 && waves != 2) return fail(KF_ERR_ARG, "waves = %d (1 or 2)", waves);
   if (block < 64 || block > 256 || block % 64 != 0) return fail(KF_ERR_ARG, "block = %d (64, 128, 192 or 256)", block);
   if (persistent != 0 && persistent != 1) return fail(KF_ERR_ARG, "persistent must be 0 or 1");
   if (blocks_per_cu < 1 || blocks_per_cu > 32) return fail(KF_ERR_ARG, "blocks_per_cu = %d outside [1, 32]", blocks_per_cu);
   KF_REQUIRE(ctx);
-  ctx->fit[prec == KF_F32 ? 0 : 1] = kf::FitLaunch{block, persistent, blocks_per_cu};
+  ctx->fit[prec == KF_F32 ? 0 : 1] = kf::FitLaunch{block, persistent, blocks_per_cu, waves};
   return ok();
 }
 
 int kf_get_fit_launch(const kf_ctx* ctx, kf_precision prec, int32_t* block, int32_t* persistent,
-                      int32_t* blocks_per_cu) {
+                      int32_t* blocks_per_cu, int32_t* waves) {
   KF_TRY(check_prec(prec));
   KF_REQUIRE(ctx);
   KF_REQUIRE(block);
   KF_REQUIRE(persistent);
   KF_REQUIRE(blocks_per_cu);
+  KF_REQUIRE(waves);
   const kf::FitLaunch& l = ctx->fit[prec == KF_F32 ? 0 : 1];
   *block = l.block;
   *persistent = l.persistent;
   *blocks_per_cu = l.blocks_per_cu;
+  *waves = l.waves;
   return ok();
 }
 

@@ -130,23 +130,30 @@ __device__ __forceinline__ void stage_align(T* sal, const FitArgs<T>& a, const G
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) fit_kernel(FitArgs<T> a, GeomArgs g) {
+constexpr int kFitBlock = 256;   // upper bound of the fit kernels' block size
+
+// One thread per track.  WAVES: the minimum number of waves per SIMD the
+// register allocation must allow (1 or 2); the autotuner picks the faster.
+template <typename T, int WAVES>
+__global__ void __launch_bounds__(kFitBlock, WAVES) fit_kernel(FitArgs<T> a, GeomArgs g) {
   __shared__ GeomLds<T> sg;
   __shared__ T sal[2 * kMaxLayers];
+  __shared__ T bk[28 * kFitBlock];
   stage_align(sal, a, g);
   stage_geometry(sg, g);
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= a.n) return;
-  fit_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.align ? sal : nullptr, t);
+  fit_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.align ? sal : nullptr, t,
+            bk + threadIdx.x, int(blockDim.x));
 }
 
 // Persistent form: a fixed grid of blocks pulls tiles of blockDim.x tracks from
 // a device counter until none are left; every block reaches the exit.
-template <typename T>
-__global__ void __launch_bounds__(256) fit_persistent_kernel(FitArgs<T> a, GeomArgs g) {
+template <typename T, int WAVES>
+__global__ void __launch_bounds__(kFitBlock, WAVES) fit_persistent_kernel(FitArgs<T> a, GeomArgs g) {
   __shared__ GeomLds<T> sg;
   __shared__ T sal[2 * kMaxLayers];
+  __shared__ T bk[28 * kFitBlock];
   __shared__ int64_t tile;
   stage_align(sal, a, g);
   stage_geometry(sg, g);
@@ -157,19 +164,20 @@ __global__ void __launch_bounds__(256) fit_persistent_kernel(FitArgs<T> a, GeomA
     __syncthreads();
     if (my >= a.n_tiles) break;
     const int64_t t = my * blockDim.x + threadIdx.x;
-    if (t < a.n) fit_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.align ? sal : nullptr, t);
+    if (t < a.n)
+      fit_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.align ? sal : nullptr, t,
+                bk + threadIdx.x, int(blockDim.x));
   }
 }
 
 __global__ void reset_counter_kernel(int32_t* c) { *c = 0; }
 
-template <typename T>
-hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s) {
-  if (a.n == 0) return hipSuccess;
+template <typename T, int WAVES>
+hipError_t launch_fit_w(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s) {
   const int block = l.block;
   if (!l.persistent) {
     const int64_t grid = (a.n + block - 1) / block;
-    hipLaunchKernelGGL(fit_kernel<T>, dim3(unsigned(grid)), dim3(block), 0, s, a, g);
+    hipLaunchKernelGGL((fit_kernel<T, WAVES>), dim3(unsigned(grid)), dim3(block), 0, s, a, g);
     return hipGetLastError();
   }
   FitArgs<T> b = a;
@@ -177,8 +185,15 @@ hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l
   int64_t grid = int64_t(n_cu) * l.blocks_per_cu;
   if (grid > b.n_tiles) grid = b.n_tiles;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.tile_counter);
-  hipLaunchKernelGGL(fit_persistent_kernel<T>, dim3(unsigned(grid)), dim3(block), 0, s, b, g);
+  hipLaunchKernelGGL((fit_persistent_kernel<T, WAVES>), dim3(unsigned(grid)), dim3(block), 0, s, b, g);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  if (l.waves == 2) return launch_fit_w<T, 2>(a, g, l, n_cu, s);
+  return launch_fit_w<T, 1>(a, g, l, n_cu, s);
 }
 
 // explicit instantiations

@@ -98,6 +98,7 @@ struct FitLaunch {
   int block;        // threads per block (multiple of 64)
   int persistent;   // 0: one thread per track; 1: persistent blocks pulling tiles
   int blocks_per_cu;
+  int waves;        // register budget: at least this many waves per SIMD (1 or 2)
 };
 template <typename T>
 hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s);

@@ -70,10 +70,21 @@ KF_HD inline bool k_finite(double x) { return x - x == 0.0; }
 KF_HD inline float k_copysign(float a, float b) { return copysignf(a, b); }
 KF_HD inline double k_copysign(double a, double b) { return copysign(a, b); }
 
+// Reciprocal: the hardware approximation (1 ulp) for FP32 on the device,
+// the correctly rounded quotient otherwise.
+KF_HD inline float k_rcp(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+KF_HD inline double k_rcp(double x) { return 1.0 / x; }
+
 template <typename T>
 KF_HD inline T wrap_phi(T phi) {
   // to (-pi, pi]
-  return phi - T(kTwoPi) * k_ceil((phi - T(kPi)) / T(kTwoPi));
+  return phi - T(kTwoPi) * k_ceil((phi - T(kPi)) * T(1.0 / kTwoPi));
 }
 
 // sin(h)/h
@@ -83,7 +94,7 @@ KF_HD inline T sinc(T h) {
   if (k_abs(h) < T(0.05)) return T(1) - h2 * (T(1.0 / 6.0) - h2 * (T(1.0 / 120.0) - h2 * T(1.0 / 5040.0)));
   T s, c;
   k_sincos(h, &s, &c);
-  return s / h;
+  return s * k_rcp(h);
 }
 
 // (u - sin u)/u^2
@@ -103,7 +114,7 @@ KF_HD inline T u_minus_sin_over_u2(T u) {
   }
   T s, c;
   k_sincos(u, &s, &c);
-  return (u - s) / (u * u);
+  return (u - s) * k_rcp(u * u);
 }
 
 // atan(t)/t
@@ -113,7 +124,7 @@ KF_HD inline T atanc(T t) {
     T t2 = t * t;
     return T(1) - t2 * (T(1.0 / 3.0) - t2 * (T(0.2) - t2 * T(1.0 / 7.0)));
   }
-  return k_atan(t) / t;
+  return k_atan(t) * k_rcp(t);
 }
 
 // ---- a1: crossing ------------------------------------------------------------
@@ -123,9 +134,9 @@ template <typename T>
 KF_HD inline T to_window(T s, T lo, T w) {
   T aw = k_abs(w);
   if (aw == T(0)) return s;  // straight line: caller rejects s <= lo
-  T P = T(kTwoPi) / aw;
+  T P = T(kTwoPi) * k_rcp(aw);
   T d = s - lo;
-  T m = d - P * k_floor(d / P);
+  T m = d - P * k_floor(d * aw * T(1.0 / kTwoPi));
   if (m <= T(0)) m += P;
   return lo + m;
 }
@@ -137,51 +148,89 @@ KF_HD inline T path_from_sigma(T num, T den, T w) {
   // sig = num/den; u = 2 atan2(w num, den) taken on the branch through 0
   T t = w * num;
   if (k_abs(t) < T(0.1) * k_abs(den)) {
-    T sig = num / den;
+    T sig = num * k_rcp(den);
     return T(2) * sig * atanc(w * sig);
   }
-  return T(2) * k_atan2(t, den) / w;
+  return T(2) * k_atan2(t, den) * k_rcp(w);
 }
 
-// Position/direction at transverse path s (chord form).
+// Point of the helix at transverse path s, from the trigonometry of the start
+// direction (sphi, cphi = sin, cos phi0) and of the half turning angle only:
+// with u = w s and h = u/2, the chord is s sinc(h) along phi0 + h, and every
+// other angle follows from the addition identities (1 - cos u = 2 sin^2 h
+// exactly, so nothing cancels).
 template <typename T>
-KF_HD inline void helix_point(const T p[6], T w, T s, T& x, T& y, T& z, T& phi, T& sphm, T& cphm,
-                                            T& dx, T& dy) {
-  T u = w * s;
-  T h = T(0.5) * u;
-  T sh = sinc(h);
-  T smid, cmid;
-  k_sincos(p[4] + h, &smid, &cmid);
-  dx = s * cmid * sh;
-  dy = s * smid * sh;
-  x = p[0] + dx;
-  y = p[1] + dy;
-  T st, ct;
-  k_sincos(p[5], &st, &ct);
-  z = p[2] + s * ct / st;
-  phi = p[4] + u;
-  k_sincos(phi, &sphm, &cphm);
+struct HelixPt {
+  T x, y, z, phi;   // position and direction at s
+  T sphm, cphm;     // sin, cos of phi
+  T dx, dy;         // chord components
+  T u, sh, shc;     // turning angle, sin(u/2), sinc(u/2)
+};
+
+template <typename T>
+KF_HD inline void helix_eval(const T p[6], T sphi, T cphi, T cot, T w, T s, HelixPt<T>& o) {
+  const T u = w * s;
+  const T h = T(0.5) * u;
+  T sh, ch;
+  k_sincos(h, &sh, &ch);
+  T shc;
+  if (k_abs(h) < T(0.05)) {
+    const T h2 = h * h;
+    shc = T(1) - h2 * (T(1.0 / 6.0) - h2 * (T(1.0 / 120.0) - h2 * T(1.0 / 5040.0)));
+  } else {
+    shc = sh * k_rcp(h);
+  }
+  const T smid = sphi * ch + cphi * sh;
+  const T cmid = cphi * ch - sphi * sh;
+  const T sin_u = T(2) * sh * ch;
+  const T cos_u = T(1) - T(2) * sh * sh;
+  o.dx = s * cmid * shc;
+  o.dy = s * smid * shc;
+  o.x = p[0] + o.dx;
+  o.y = p[1] + o.dy;
+  o.z = p[2] + s * cot;
+  o.phi = p[4] + u;
+  o.sphm = sphi * cos_u + cphi * sin_u;
+  o.cphm = cphi * cos_u - sphi * sin_u;
+  o.u = u;
+  o.sh = sh;
+  o.shc = shc;
+}
+
+// Move a helix point by a small extra path ds (first order; used for the
+// Newton correction of the crossing, |w ds| ~ 1e-6).
+template <typename T>
+KF_HD inline void helix_nudge(HelixPt<T>& o, T w, T cot, T ds) {
+  o.x += ds * o.cphm;
+  o.y += ds * o.sphm;
+  o.dx += ds * o.cphm;
+  o.dy += ds * o.sphm;
+  o.z += ds * cot;
+  const T dphi = w * ds;
+  o.phi += dphi;
+  const T sp = o.sphm, cp = o.cphm;
+  o.sphm = sp + dphi * cp;
+  o.cphm = cp - dphi * sp;
 }
 
 // First admissible crossing of the layer surface.  Barrel: roots of
 // r(s)^2 = R^2 written as alpha sig^2 + 2 A sig - D/2 = 0 with tan(u/2) = w sig,
 // A = x cos phi + y sin phi, B = x sin phi - y cos phi, D = R^2 - r^2,
 // alpha = 2 (1 - w B) - w^2 D / 2; then one Newton step on r^2 - R^2.
-// Disk: s = (Z - z)/cot(theta).
+// Disk: s = (Z - z)/cot(theta).  On success fills the helix point at s.
 template <typename T>
-KF_HD bool crossing(const T p[6], T w, int kind, T pos, bool same, T& s_out) {
+KF_HD bool crossing(const T p[6], T sphi, T cphi, T cot, T w, int kind, T pos, bool same, T& s_out,
+                    HelixPt<T>& hp) {
   T lo = same ? T(kSSame) : T(-kSBack);
   if (kind == 1) {
-    T st, ct;
-    k_sincos(p[5], &st, &ct);
-    T cot = ct / st;
     if (!(k_abs(cot) > T(1e-12))) return false;
-    T s = (pos - p[2]) / cot;
+    T s = (pos - p[2]) * k_rcp(cot);
+    if (!(s > lo)) return false;
     s_out = s;
-    return s > lo;
+    helix_eval(p, sphi, cphi, cot, w, s, hp);
+    hp.z = pos;
+    return true;
   }
-  T sphi, cphi;
-  k_sincos(p[4], &sphi, &cphi);
   T x = p[0], y = p[1];
   T A = x * cphi + y * sphi;
   T B = x * sphi - y * cphi;
@@ -197,8 +246,7 @@ KF_HD bool crossing(const T p[6], T w, int kind, T pos, bool same, T& s_out) {
   // root 1: sig = qq / alpha
   if (qq != T(0) || alpha != T(0)) {
     T s1 = path_from_sigma(qq, alpha, w);
-    bool ok1 = k_finite(s1);
-    if (ok1) {
+    if (k_finite(s1)) {
       s1 = to_window(s1, lo, w);
       if (s1 > lo) {
         best = s1;
@@ -219,57 +267,81 @@ KF_HD bool crossing(const T p[6], T w, int kind, T pos, bool same, T& s_out) {
   }
   if (!found) return false;
   // Newton polish on h(s) = r(s)^2 - R^2
-  T xs, ys, zs, phs, sph, cph, dx, dy;
-  helix_point(p, w, best, xs, ys, zs, phs, sph, cph, dx, dy);
-  T f = (xs * xs + ys * ys - pos * pos);
-  T df = T(2) * (xs * cph + ys * sph);
-  if (k_abs(df) > T(1e-20)) best -= f / df;
+  helix_eval(p, sphi, cphi, cot, w, best, hp);
+  const T f = (hp.x * hp.x + hp.y * hp.y - pos * pos);
+  const T df = T(2) * (hp.x * hp.cphm + hp.y * hp.sphm);
+  if (k_abs(df) > T(1e-20)) {
+    const T ds = -f * k_rcp(df);
+    best += ds;
+    helix_nudge(hp, w, cot, ds);
+  }
   s_out = best;
   return true;
 }
 
 // ---- a1-a3: propagate state and covariance ----------------------------------
 
-struct LayerDesc {
-  int kind;
-  double pos;
-  double x0;
-};
+// Highland angle squared for unit charge at the state (ipt, theta) crossing
+// x_over_x0 at |cos(incidence)| = ca (clamped at kGrazingCos, flagged).
+template <typename T>
+KF_HD inline T highland_var(T ipt, T sth, T ca, T x_over_x0, T mass, uint32_t& st) {
+  if (ca < T(kGrazingCos)) {
+    st |= TRK_GRAZING;
+    ca = T(kGrazingCos);
+  }
+  const T mis = mass * ipt * sth;              // m / p
+  const T xl = x_over_x0 * k_rcp(ca);
+  const T one_m = T(1) + mis * mis;            // 1 / beta^2
+  const T inv_bp = ipt * sth * k_sqrt(one_m);  // 1 / (beta p)
+  const T th0 = T(0.0136) * inv_bp * k_sqrt(xl) * (T(1) + T(0.038) * k_log(xl * one_m));
+  return th0 * th0;
+}
+
+// Add the scattering noise Q (rank 2 in ipt, phi, theta).
+template <typename T>
+KF_HD inline void add_q(T c[21], T ipt, T sth, T cot, T var) {
+  const T ic = ipt * cot;
+  c[sym(3, 3)] += ic * ic * var;
+  c[sym(5, 3)] += -ic * var;
+  c[sym(4, 4)] += var * k_rcp(sth * sth);
+  c[sym(5, 5)] += var;
+}
 
 // Propagate (p, c) to the surface (kind, pos) and add its scattering noise.
 // Returns false (p, c untouched) if there is no admissible crossing.
 template <typename T>
 KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool same, bool material, T bz,
-                          T mass, uint32_t& st, T* path = nullptr) {
+                     T mass, uint32_t& st, T* path = nullptr) {
   const T dw_dipt = -T(q) * T(kCLight) * bz;
   const T w = dw_dipt * p[3];
+  T sphi, cphi, sth, cth;
+  k_sincos(p[4], &sphi, &cphi);
+  k_sincos(p[5], &sth, &cth);
+  const T isth = k_rcp(sth);
+  const T cot = cth * isth;
   T s;
-  if (!crossing(p, w, kind, pos, same, s)) {
+  HelixPt<T> hp;
+  if (!crossing(p, sphi, cphi, cot, w, kind, pos, same, s, hp)) {
     st |= TRK_NO_CROSSING;
     return false;
   }
   if (path) *path = s;
-  T x, y, z, phm, sphm, cphm, dx, dy;
-  helix_point(p, w, s, x, y, z, phm, sphm, cphm, dx, dy);
-  T sth, cth;
-  k_sincos(p[5], &sth, &cth);
-  const T cot = cth / sth;
-  const T u = w * s;
+  const T x = hp.x, y = hp.y, sphm = hp.sphm, cphm = hp.cphm;
+  const T u = hp.u;
   // helix partials at fixed s (G), with the chord-form derivatives
   const T f1 = u_minus_sin_over_u2(u);
-  const T sh = sinc(T(0.5) * u);
-  const T f2 = T(0.5) * sh * sh;
+  const T f2 = T(0.5) * hp.shc * hp.shc;   // (1 - cos u)/u^2
   const T s2 = s * s;
   const T dxdw = s2 * (cphm * f1 - sphm * f2);
   const T dydw = s2 * (sphm * f1 + cphm * f2);
-  const T G03 = dxdw * dw_dipt, G04 = -dy;
-  const T G13 = dydw * dw_dipt, G14 = dx;
-  const T G25 = -s / (sth * sth);
+  const T G03 = dxdw * dw_dipt, G04 = -hp.dy;
+  const T G13 = dydw * dw_dipt, G14 = hp.dx;
+  const T G25 = -s * isth * isth;
   const T G43 = s * dw_dipt;
   // ds/dp = -(dh/dp)/(dh/ds)
   T d[6];
   if (kind == 0) {
-    const T inv = T(-1) / (x * cphm + y * sphm);
+    const T inv = -k_rcp(x * cphm + y * sphm);
     d[0] = x * inv;
     d[1] = y * inv;
     d[2] = T(0);
@@ -277,7 +349,7 @@ KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool 
     d[4] = (x * G04 + y * G14) * inv;
     d[5] = T(0);
   } else {
-    const T inv = T(-1) / cot;
+    const T inv = -k_rcp(cot);
     d[0] = T(0);
     d[1] = T(0);
     d[2] = inv;
@@ -341,11 +413,11 @@ KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool 
   // cancellation F = G + g d^T leaves a residue of order eps * (G C G^T) there,
   // so the null vector is imposed: disk -> z row/column zero; barrel -> the
   // radial direction is projected out, C <- (I - n n^T) C (I - n n^T).
+  const T rinv = k_rcp(pos);
   if (kind == 1) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) c[sym(2, j)] = T(0);
   } else {
-    const T rinv = T(1) / k_sqrt(x * x + y * y);
     const T nx = x * rinv, ny = y * rinv;
     T cn[6];
 #pragma unroll
@@ -359,33 +431,13 @@ KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool 
   }
   p[0] = x;
   p[1] = y;
-  p[2] = (kind == 1) ? pos : z;
-  p[4] = wrap_phi(phm);
+  p[2] = hp.z;
+  p[4] = wrap_phi(hp.phi);
   if (material) {
     // Highland angle at the propagated state; x/X0 scaled by 1/|cos(incidence)|
-    T ca;
-    if (kind == 0) {
-      const T r = k_sqrt(x * x + y * y);
-      ca = k_abs(sth * (cphm * x + sphm * y) / r);
-    } else {
-      ca = k_abs(cth);
-    }
-    if (ca < T(kGrazingCos)) {
-      st |= TRK_GRAZING;
-      ca = T(kGrazingCos);
-    }
-    const T ipt = p[3];
-    const T mis = mass * ipt * sth;           // m / p
-    const T xl = x_over_x0 / ca;
-    const T one_m = T(1) + mis * mis;         // 1 / beta^2
-    const T inv_bp = ipt * sth * k_sqrt(one_m);  // 1 / (beta p)
-    const T th0 = T(0.0136) * inv_bp * k_sqrt(xl) * (T(1) + T(0.038) * k_log(xl * one_m));
-    const T var = th0 * th0;
-    const T ic = ipt * cot;
-    c[sym(3, 3)] += ic * ic * var;
-    c[sym(5, 3)] += -ic * var;
-    c[sym(4, 4)] += var / (sth * sth);
-    c[sym(5, 5)] += var;
+    const T ca = (kind == 0) ? k_abs(sth * (cphm * x + sphm * y) * rinv) : k_abs(cth);
+    const T var = highland_var(p[3], sth, ca, x_over_x0, mass, st);
+    add_q(c, p[3], sth, cot, var);
   }
   return true;
 }
@@ -400,27 +452,12 @@ KF_HD void add_material_here(const T p[6], T c[21], int kind, T x_over_x0, T mas
     T sph, cph;
     k_sincos(p[4], &sph, &cph);
     const T r = k_sqrt(p[0] * p[0] + p[1] * p[1]);
-    ca = k_abs(sth * (cph * p[0] + sph * p[1]) / r);
+    ca = k_abs(sth * (cph * p[0] + sph * p[1]) * k_rcp(r));
   } else {
     ca = k_abs(cth);
   }
-  if (ca < T(kGrazingCos)) {
-    st |= TRK_GRAZING;
-    ca = T(kGrazingCos);
-  }
-  const T cot = cth / sth;
-  const T ipt = p[3];
-  const T mis = mass * ipt * sth;
-  const T xl = x_over_x0 / ca;
-  const T one_m = T(1) + mis * mis;
-  const T inv_bp = ipt * sth * k_sqrt(one_m);
-  const T th0 = T(0.0136) * inv_bp * k_sqrt(xl) * (T(1) + T(0.038) * k_log(xl * one_m));
-  const T var = th0 * th0;
-  const T ic = ipt * cot;
-  c[sym(3, 3)] += ic * ic * var;
-  c[sym(5, 3)] += -ic * var;
-  c[sym(4, 4)] += var / (sth * sth);
-  c[sym(5, 5)] += var;
+  const T var = highland_var(p[3], sth, ca, x_over_x0, mass, st);
+  add_q(c, p[3], sth, cth * k_rcp(sth), var);
 }
 
 // ---- a4/a5: residual covariance inverse, chi2, gain, Joseph update ----------
@@ -436,7 +473,7 @@ KF_HD inline T inv3(const T S[6], T I[6]) {
   const T i21 = b * d - a * e;
   const T i22 = a * cc - b * b;
   const T det = a * i00 + b * i10 + d * i20;
-  const T r = T(1) / det;
+  const T r = k_rcp(det);
   I[0] = i00 * r;
   I[1] = i10 * r;
   I[2] = i11 * r;
@@ -502,24 +539,29 @@ KF_HD void update_core(T p[6], T c[21], int& q, const T m[3], const T V[6], T& c
       K[i][j] = c[sym(i, 0)] * Si[sym(0, j)] + c[sym(i, 1)] * Si[sym(1, j)] + c[sym(i, 2)] * Si[sym(2, j)];
 #pragma unroll
   for (int i = 0; i < 6; ++i) p[i] += K[i][0] * r[0] + K[i][1] * r[1] + K[i][2] * r[2];
-  // Joseph: C' = A C A^T + K V K^T with A = I - K H
-  T AC[6][6];
+  // Joseph form C' = A C A^T + K V K^T with A = I - K H, column by column:
+  // (A C)_ij = c_ij - sum_k K_ik c_kj, C'_ij = (A C)_ij - sum_k (A C)_ik K_jk + (K V)_i . K_j.
+  // Only (A C)[:, 0:3], K and K V stay live; columns are done from the last
+  // to the first so that every c entry is read before it is overwritten.
+  T AC3[6][3], KV[6][3];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
-      AC[i][j] = c[sym(i, j)] - K[i][0] * c[sym(0, j)] - K[i][1] * c[sym(1, j)] - K[i][2] * c[sym(2, j)];
-  T KV[6][3];
+    for (int k = 0; k < 3; ++k) {
+      AC3[i][k] = c[sym(i, k)] - K[i][0] * c[sym(0, k)] - K[i][1] * c[sym(1, k)] - K[i][2] * c[sym(2, k)];
+      KV[i][k] = K[i][0] * V[sym(0, k)] + K[i][1] * V[sym(1, k)] + K[i][2] * V[sym(2, k)];
+    }
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
+  for (int j = 5; j >= 0; --j)
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      KV[i][j] = K[i][0] * V[sym(0, j)] + K[i][1] * V[sym(1, j)] + K[i][2] * V[sym(2, j)];
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      const T aca = AC[i][j] - AC[i][0] * K[j][0] - AC[i][1] * K[j][1] - AC[i][2] * K[j][2];
+    for (int i = 5; i >= j; --i) {
+      T acij;
+      if (j < 3) {
+        acij = AC3[i][j];
+      } else {
+        acij = c[sym(i, j)] - K[i][0] * c[sym(0, j)] - K[i][1] * c[sym(1, j)] - K[i][2] * c[sym(2, j)];
+      }
+      const T aca = acij - AC3[i][0] * K[j][0] - AC3[i][1] * K[j][1] - AC3[i][2] * K[j][2];
       const T kvk = KV[i][0] * K[j][0] + KV[i][1] * K[j][1] + KV[i][2] * K[j][2];
       c[sym(i, j)] = aca + kvk;
     }

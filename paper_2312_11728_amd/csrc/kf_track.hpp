@@ -81,8 +81,12 @@ KF_HD inline void write_checkpoint(const FitArgs<T>& a, int64_t t, int slot, con
 }
 
 // Forward fit of track t.  sal: alignment staged as [rphi x kMaxLayers][z x kMaxLayers] or null.
+// bk: room for 28 values at bk[k * bk_stride] (k = 0..27) holding the state
+// before the current entry, read back only if that entry turns non-finite
+// (kept out of registers: in LDS on the device).
 template <typename T>
-KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t t) {
+KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t t,
+                            T* bk, int bk_stride) {
   const int64_t ld = a.ld, nh = a.n_hits;
   T p[6], c[21];
 #pragma unroll
@@ -100,19 +104,44 @@ KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
     st |= TRK_BAD_INPUT;
   } else {
     int prev = a.hit_layer[k0];
+    // entry data are loaded one entry ahead so that the loads of entry e+1
+    // overlap the arithmetic of entry e
+    int lay_n = prev;
+    bool valid_n = true;
+    T m_n[3], V_n[6];
+    m_n[0] = a.hit_pos[k0];
+    m_n[1] = a.hit_pos[nh + k0];
+    m_n[2] = a.hit_pos[2 * nh + k0];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) V_n[i] = a.hit_cov[i * nh + k0];
     for (int64_t e = k0; e < e1; ++e) {
-      const int lay = a.hit_layer[e];
+      const int lay = lay_n;
+      const bool valid = valid_n;
+      T m[3], V[6];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) m[i] = m_n[i];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) V[i] = V_n[i];
+      if (e + 1 < e1) {
+        const int64_t f = e + 1;
+        lay_n = a.hit_layer[f];
+        valid_n = a.hit_valid[f] != 0;
+        m_n[0] = a.hit_pos[f];
+        m_n[1] = a.hit_pos[nh + f];
+        m_n[2] = a.hit_pos[2 * nh + f];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) V_n[i] = a.hit_cov[i * nh + f];
+      }
       if (lay < 0 || lay >= g.n_layers) {
         st |= TRK_BAD_INPUT;
         break;
       }
       const int j = int(e - k0);
       if (a.ckpt && j >= 1 && ((j - 1) % a.seg) == 0) write_checkpoint(a, t, (j - 1) / a.seg, p, c, q);
-      T pp[6], cc[21];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) pp[i] = p[i];
+      for (int i = 0; i < 6; ++i) bk[i * bk_stride] = p[i];
 #pragma unroll
-      for (int i = 0; i < 21; ++i) cc[i] = c[i];
+      for (int i = 0; i < 21; ++i) bk[(6 + i) * bk_stride] = c[i];
       const int qq = q;
       uint32_t sst = 0;
       const int kind = g.kind[lay];
@@ -125,16 +154,9 @@ KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
         add_material_here(p, c, kind, g.x0[lay], g.mass, sst);
       }
       T c2 = T(0);
-      const bool valid = a.hit_valid[e] != 0;
       if (valid) {
-        T m[3], V[6];
-        m[0] = a.hit_pos[e];
-        m[1] = a.hit_pos[nh + e];
-        m[2] = a.hit_pos[2 * nh + e];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) V[i] = a.hit_cov[i * nh + e];
         if (sal && kind == 0) {
-          const T ang = sal[lay] / g.pos[lay];
+          const T ang = sal[lay] * k_rcp(g.pos[lay]);
           T sa, ca;
           k_sincos(ang, &sa, &ca);
           const T hx = m[0], hy = m[1];
@@ -147,9 +169,9 @@ KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
       if (!all_finite(p, c, c2)) {
         st |= sst | TRK_NONFINITE;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) p[i] = pp[i];
+        for (int i = 0; i < 6; ++i) p[i] = bk[i * bk_stride];
 #pragma unroll
-        for (int i = 0; i < 21; ++i) c[i] = cc[i];
+        for (int i = 0; i < 21; ++i) c[i] = bk[(6 + i) * bk_stride];
         q = qq;
         break;
       }

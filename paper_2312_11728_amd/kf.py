@@ -68,9 +68,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_adjoint.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                    ctypes.POINTER(KfGeometry), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
-    lib.kf_set_fit_launch.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i32]
+    lib.kf_set_fit_launch.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i32, _i32]
     lib.kf_get_fit_launch.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
-                                      ctypes.POINTER(_i32)]
+                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
     lib.kf_device_cu_count.argtypes = [_vp, ctypes.POINTER(_i32)]
     return lib
 
@@ -165,13 +165,14 @@ class Context:
             pass
 
     # ---- tuning -----------------------------------------------------------
-    def set_fit_launch(self, dtype, block, persistent, blocks_per_cu):
-        _check(lib().kf_set_fit_launch(self.handle, _prec(dtype), block, persistent, blocks_per_cu))
+    def set_fit_launch(self, dtype, block, persistent, blocks_per_cu, waves=1):
+        _check(lib().kf_set_fit_launch(self.handle, _prec(dtype), block, persistent, blocks_per_cu, waves))
 
     def get_fit_launch(self, dtype):
-        b, p, k = _i32(), _i32(), _i32()
-        _check(lib().kf_get_fit_launch(self.handle, _prec(dtype), ctypes.byref(b), ctypes.byref(p), ctypes.byref(k)))
-        return b.value, p.value, k.value
+        b, p, k, w = _i32(), _i32(), _i32(), _i32()
+        _check(lib().kf_get_fit_launch(self.handle, _prec(dtype), ctypes.byref(b), ctypes.byref(p), ctypes.byref(k),
+                                       ctypes.byref(w)))
+        return b.value, p.value, k.value, w.value
 
     def cu_count(self):
         n = _i32()
