@@ -107,6 +107,39 @@ def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
             "frac_fp32_peak": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, "launch": list(best)}
 
 
+def profile_only(args, K, tune_fit, generate, workloads):
+    """Launch one fit configuration --steps times and nothing else (the
+    launch shape comes from the autotune cache when present)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    name = "mixed26" if args.profile_only == "mixed32" else "barrel20"
+    dt = torch.float64 if args.profile_only == "fit64" else torch.float32
+    wl = workloads()[name]
+    ev = generate(wl)
+    ctx = K.Context(0)
+    t = K.event_tensors(ev, dt, dev)
+    geom = K.Geometry.from_toy(wl.geometry)
+    seeds = ctx.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"], wl.geometry.bz,
+                           1 if name == "mixed26" else 0)
+    out = K.fit_outputs(ev.n_tracks, dt, dev)
+    from paper_2312_11728_amd.autotune import load_cache, _key
+    cached = load_cache(args.tune_cache).get(_key(dt, ev.n_tracks, torch.cuda.get_device_name(dev)))
+    if cached:
+        ctx.set_fit_launch(dt, *cached["shape"])
+    # a plain device copy of known size (128 MiB read, 128 MiB written) in the
+    # same process: it calibrates the HBM byte counters of a counter run
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        ctx.fit_tracks(seeds[0], seeds[1], seeds[2], t["hit_offsets"], t["hit_layer"], t["hit_valid"],
+                       t["hit_pos"], t["hit_cov"], geom, out=out)
+    torch.cuda.synchronize()
+    log("profile-only", args.profile_only, "launch", ctx.get_fit_launch(dt), "steps", args.steps,
+        "calibration copy bytes", src.numel() * 4)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +150,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the 500k-track barrel+endcap workload")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "kf_autotune.json"))
+    ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32"],
+                    help="only launch the named fit --steps times (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (tracks are independent: "
@@ -129,6 +164,9 @@ def main():
     from toygen import generate, workloads
 
     dev = torch.device("cuda", 0)
+    if args.profile_only:
+        profile_only(args, K, tune_fit, generate, workloads)
+        return
     wl = workloads()["barrel20"]
     log("generating", wl.name, wl.n_tracks)
     ev = generate(wl)

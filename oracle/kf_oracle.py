@@ -512,7 +512,7 @@ def pack_sym(M):
 
 
 def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
-               align=None, state_round=None):
+               align=None, state_round=None, state_jitter=None):
     """kf_fit_tracks: forward Kalman fit of every track.
 
     Each track starts at its seed, which sits on its first valid entry k0
@@ -532,6 +532,9 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
     are rounded after every propagation and every update -- a conditioning
     probe for the tests (how far the float64 result moves under
     storage-precision perturbations).
+    state_jitter: None, or a relative size r; after every propagation and
+    update the state and covariance are scaled by (1 + r) or (1 - r)
+    (alternating by track and entry) -- the same probe at float64 rounding.
     Returns dict(p, C, q, chi2, ndf, status)."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
@@ -586,6 +589,10 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
         if state_round is not None:
             pp2 = pp2.to(state_round).to(DT)
             CC2 = CC2.to(state_round).to(DT)
+        if state_jitter is not None:
+            sgn = (1.0 - 2.0 * ((idx + j) % 2).to(DT)) * state_jitter
+            pp2 = pp2 * (1.0 + sgn[:, None])
+            CC2 = CC2 * (1.0 + sgn[:, None, None])
         st = st | st_p
         good = (st_p & NO_CROSSING) == 0
         valid = (val_all[ei] == 1) & good
@@ -607,6 +614,10 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
         if state_round is not None:
             pn = pn.to(state_round).to(DT)
             Cn = Cn.to(state_round).to(DT)
+        if state_jitter is not None:
+            sgn = (2.0 * ((idx + j) % 2).to(DT) - 1.0) * state_jitter
+            pn = pn * (1.0 + sgn[:, None])
+            Cn = Cn * (1.0 + sgn[:, None, None])
         p = p.index_put((idx,), pn)
         C = C.index_put((idx,), Cn)
         q = q.index_put((idx,), qn)

@@ -40,7 +40,7 @@ def rounded(x, dtype):
     return np.asarray(x).astype(np.float32).astype(np.float64) if dtype == torch.float32 else np.asarray(x, np.float64)
 
 
-def oracle_fit(ev, dtype, seed_mode=0, hit_pos=None, align=None, state_round=None):
+def oracle_fit(ev, dtype, seed_mode=0, hit_pos=None, align=None, state_round=None, state_jitter=None):
     hp = rounded(ev.hit_pos, dtype) if hit_pos is None else np.asarray(hit_pos, np.float64)
     hc = rounded(ev.hit_cov, dtype)
     sp, sC, sq, ok = O.make_seeds(ev.hit_offsets, ev.hit_valid, hp, ev.geometry.bz, mode=seed_mode)
@@ -48,7 +48,7 @@ def oracle_fit(ev, dtype, seed_mode=0, hit_pos=None, align=None, state_round=Non
         sp = sp.to(state_round).to(torch.float64)
     out = O.fit_tracks(sp, sC, sq, ev.hit_offsets, ev.hit_layer, ev.hit_valid, torch.tensor(hp), hc, ev.geometry,
                        align=None if align is None else torch.tensor(rounded(align, dtype)),
-                       state_round=state_round)
+                       state_round=state_round, state_jitter=state_jitter)
     return dict(p=out["p"].numpy(), C=out["C"].numpy(), q=out["q"].numpy(), chi2=out["chi2"].numpy(),
                 ndf=out["ndf"].numpy(), status=out["status"].numpy(), seed=sp.numpy(), seed_q=sq.numpy())
 
@@ -57,23 +57,22 @@ def ill_conditioned(ev, dtype, ref, seed_mode=0, tol_p=1e-4, tol_c=1e-3, align=N
     """Tracks whose float64 oracle result moves by more than half the
     tolerance under perturbations at the rounding level of ``dtype``: the hit
     positions perturbed by one unit in the last place (random sign), and the
-    state and covariance rounded to ``dtype`` after every entry (what storing
-    the running estimate in that precision does at the least).  No
-    computation in that precision can be expected to reproduce such a track to
-    the tolerance."""
+    state and covariance rounded to ``dtype`` after every propagation and
+    update (what storing the running estimate in that precision does at the
+    least; for float64, a relative jitter of 4e-16 instead).  No computation
+    in that precision can be expected to reproduce such a track to the
+    tolerance."""
     rng = np.random.default_rng(seed)
     hp = rounded(ev.hit_pos, dtype)
     if dtype == torch.float32:
         ulp = np.spacing(np.abs(hp).astype(np.float32)).astype(np.float64)
-        rnd = torch.float32
+        probe = dict(state_round=torch.float32)
     else:
         ulp = 1e-13 * np.maximum(np.abs(hp), 1.0)
-        rnd = None
+        probe = dict(state_jitter=4e-16)
     pert = hp + ulp * rng.choice([-1.0, 1.0], size=hp.shape)
     bad = np.zeros(ev.n_tracks, bool)
-    for kw in (dict(hit_pos=pert), dict(state_round=rnd)):
-        if kw.get("state_round", 1) is None:
-            continue
+    for kw in (dict(hit_pos=pert), probe):
         o2 = oracle_fit(ev, dtype, seed_mode, align=align, **kw)
         ep = param_error(o2["p"], ref["p"]).max(axis=1)
         ec = chi2_error(o2["chi2"], ref["chi2"])
