@@ -87,6 +87,7 @@ def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
     ev = generate(wl)
     log("generated in", round(time.time() - t0, 1), "s")
     n = ev.n_tracks
+    ctx.reserve(n, 26)
     t = K.event_tensors(ev, torch.float32, dev)
     geom = K.Geometry.from_toy(wl.geometry)
     seeds = ctx.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"], wl.geometry.bz, 1)
@@ -117,6 +118,7 @@ def profile_only(args, K, tune_fit, generate, workloads):
     wl = workloads()[name]
     ev = generate(wl)
     ctx = K.Context(0)
+    ctx.reserve(ev.n_tracks, 26)
     t = K.event_tensors(ev, dt, dev)
     geom = K.Geometry.from_toy(wl.geometry)
     seeds = ctx.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"], wl.geometry.bz,
@@ -171,6 +173,7 @@ def main():
     log("generating", wl.name, wl.n_tracks)
     ev = generate(wl)
     ctx = K.Context(0)
+    ctx.reserve(ev.n_tracks, 26)
     geom = K.Geometry.from_toy(wl.geometry)
     res = {}
     for dt in (torch.float32, torch.float64):

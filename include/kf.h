@@ -26,7 +26,7 @@
  *   double (KF_F64) as selected by the precision argument.
  *   `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
  *   and return; none synchronises the stream.  No call allocates device
- *   memory except kf_create.
+ *   memory except kf_create and kf_reserve.
  *   n = 0 is a no-op (array pointers may then be NULL).
  *   Errors: every call returns a kf_status.  KF_ERR_ARG is returned before any
  *   device work for a null pointer, n < 0, ld < n, a bad geometry or another
@@ -160,8 +160,14 @@ int kf_update(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
  * ndf[n] (= 2 * used hits - 5), trk_status[n] (overwritten).
  * checkpoints: NULL, or a [28][ld * n_seg] buffer receiving (state, cov,
  * charge) before entry 1 + j*seg of each track's fit (j = 0..n_seg-1,
- * n_seg = ceil((max_len - 1) / seg)); used by kf_fit_adjoint.  max_len bounds
- * every track's entry count (<= 64). */
+ * n_seg = ceil((max_len - 1) / seg)); used by kf_fit_adjoint.
+ * max_len (1..64) bounds the entries used per track: entries beyond it are
+ * ignored and the track gets KF_TRK_BAD_INPUT.
+ * Layout: when the context holds a workspace from kf_reserve large enough
+ * for n tracks and max_len, the call first sorts the tracks by entry count
+ * and copies the hits into a tile-transposed layout (entry k of 64 tracks
+ * contiguous) so that every hit load of a wave is one coalesced read;
+ * otherwise the fit reads the CSR arrays directly.  Results are identical. */
 int kf_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                   const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
                   const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
@@ -231,6 +237,12 @@ int kf_fit_adjoint(kf_ctx *ctx, int64_t n, int64_t ld,
                    const float *dL_dchi2,
                    float *grad_seed, float *grad_hit_pos, float *grad_align,
                    const uint32_t *trk_status, void *stream);
+
+/* Reserve the workspace of kf_fit_tracks' packed hit layout for up to
+ * max_tracks tracks of up to max_len (1..64) entries (about
+ * 80 * max_tracks * max_len bytes; replaces an earlier reservation;
+ * max_tracks = 0 releases it).  KF_ERR_NOMEM if the allocation fails. */
+int kf_reserve(kf_ctx *ctx, int64_t max_tracks, int32_t max_len);
 
 /* ---- execution tuning (no effect on results) --------------------------------
  * Launch shape of kf_fit_tracks for one precision: threads per block (64, 128,

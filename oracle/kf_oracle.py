@@ -511,6 +511,15 @@ def pack_sym(M):
     return torch.stack(out, dim=0)
 
 
+def _jitter(p, C, key, r):
+    """Scale every element by 1 + r or 1 - r with a sign pattern that
+    alternates with the element index and with ``key`` (C stays symmetric)."""
+    i6 = torch.arange(6)
+    sp = 1.0 - 2.0 * ((key[:, None] + i6[None, :]) % 2).to(DT)
+    sc = 1.0 - 2.0 * ((key[:, None, None] + i6[None, :, None] + i6[None, None, :]) % 2).to(DT)
+    return p * (1.0 + r * sp), C * (1.0 + r * sc)
+
+
 def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
                align=None, state_round=None, state_jitter=None):
     """kf_fit_tracks: forward Kalman fit of every track.
@@ -533,8 +542,9 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
     probe for the tests (how far the float64 result moves under
     storage-precision perturbations).
     state_jitter: None, or a relative size r; after every propagation and
-    update the state and covariance are scaled by (1 + r) or (1 - r)
-    (alternating by track and entry) -- the same probe at float64 rounding.
+    update every element of the state and covariance is scaled by (1 + r) or
+    (1 - r) (alternating by element, track and entry) -- the same probe at
+    float64 rounding.
     Returns dict(p, C, q, chi2, ndf, status)."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
@@ -590,9 +600,7 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
             pp2 = pp2.to(state_round).to(DT)
             CC2 = CC2.to(state_round).to(DT)
         if state_jitter is not None:
-            sgn = (1.0 - 2.0 * ((idx + j) % 2).to(DT)) * state_jitter
-            pp2 = pp2 * (1.0 + sgn[:, None])
-            CC2 = CC2 * (1.0 + sgn[:, None, None])
+            pp2, CC2 = _jitter(pp2, CC2, idx + j, state_jitter)
         st = st | st_p
         good = (st_p & NO_CROSSING) == 0
         valid = (val_all[ei] == 1) & good
@@ -615,9 +623,7 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
             pn = pn.to(state_round).to(DT)
             Cn = Cn.to(state_round).to(DT)
         if state_jitter is not None:
-            sgn = (2.0 * ((idx + j) % 2).to(DT) - 1.0) * state_jitter
-            pn = pn * (1.0 + sgn[:, None])
-            Cn = Cn * (1.0 + sgn[:, None, None])
+            pn, Cn = _jitter(pn, Cn, idx + j + 1, state_jitter)
         p = p.index_put((idx,), pn)
         C = C.index_put((idx,), Cn)
         q = q.index_put((idx,), qn)

@@ -22,6 +22,9 @@ struct kf_ctx {
   hipStream_t capture = nullptr;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   std::string key[2];
+  // workspace of the packed hit layout (kf_reserve)
+  void* work_mem = nullptr;
+  kf::PackWork work{};
 };
 
 namespace {
@@ -138,6 +141,7 @@ int kf_destroy(kf_ctx* c) {
     if (c->exec[i]) hipGraphExecDestroy(c->exec[i]);
   if (c->capture) hipStreamDestroy(c->capture);
   if (c->d_counter) hipFree(c->d_counter);
+  if (c->work_mem) hipFree(c->work_mem);
   hipSetDevice(prev);
   delete c;
   return ok();
@@ -270,6 +274,9 @@ kf::FitArgs<T> make_fit_args(int64_t n, int64_t ld, const void* seed_state, cons
   a.trk_status = trk_status;
   a.tile_counter = counter;
   a.n_tiles = 0;
+  a.max_len = kf::kMaxLen;
+  a.packed = 0;
+  a.pk = kf::PackedHits<T>{};
   return a;
 }
 
@@ -289,7 +296,7 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   KF_TRY(check_geometry(geom, &g));
   if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
   if (checkpoints && seg < 1) return fail(KF_ERR_ARG, "seg = %d < 1", seg);
-  if (checkpoints && (max_len < 1 || max_len > 64)) return fail(KF_ERR_ARG, "max_len = %d outside [1, 64]", max_len);
+  if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);
   if (n == 0) return ok();
   KF_REQUIRE(seed_state);
   KF_REQUIRE(seed_cov);
@@ -307,8 +314,6 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   KF_REQUIRE(trk_status);
   int32_t n_seg = 0;
   if (checkpoints) {
-    if (seg < 1) return fail(KF_ERR_ARG, "seg = %d < 1", seg);
-    if (max_len < 1 || max_len > 64) return fail(KF_ERR_ARG, "max_len = %d outside [1, 64]", max_len);
     n_seg = (max_len - 1 + seg - 1) / seg;
     if (n_seg < 1) n_seg = 1;
   }
@@ -316,19 +321,73 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   hipStream_t s = (hipStream_t)stream;
   const int pi = prec == KF_F32 ? 0 : 1;
   const kf::FitLaunch l = ctx->fit[pi];
+  const bool packed = ctx->work.cap > 0 && n <= ctx->work.max_tracks && max_len <= ctx->work.max_len;
   hipError_t e;
   if (prec == KF_F32) {
     auto a = make_fit_args<float>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, n_hits,
                                   hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf, checkpoints, seg,
                                   n_seg, trk_status, ctx->d_counter);
+    a.max_len = max_len;
+    if (packed && (e = kf::launch_pack(a, ctx->work, &a.pk, s)) != hipSuccess) return hip_fail(e, "kf_fit_tracks");
+    a.packed = packed ? 1 : 0;
     e = kf::launch_fit(a, g, l, ctx->n_cu, s);
   } else {
     auto a = make_fit_args<double>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
                                    n_hits, hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf,
                                    checkpoints, seg, n_seg, trk_status, ctx->d_counter);
+    a.max_len = max_len;
+    if (packed && (e = kf::launch_pack(a, ctx->work, &a.pk, s)) != hipSuccess) return hip_fail(e, "kf_fit_tracks");
+    a.packed = packed ? 1 : 0;
     e = kf::launch_fit(a, g, l, ctx->n_cu, s);
   }
   if (e != hipSuccess) return hip_fail(e, "kf_fit_tracks");
+  return ok();
+}
+
+int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {
+  if (max_tracks < 0) return fail(KF_ERR_ARG, "max_tracks = %lld < 0", (long long)max_tracks);
+  if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);
+  KF_REQUIRE(ctx);
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(ctx->device);
+  if (ctx->work_mem) {
+    hipFree(ctx->work_mem);
+    ctx->work_mem = nullptr;
+  }
+  ctx->work = kf::PackWork{};
+  if (max_tracks == 0) {
+    hipSetDevice(prev);
+    return ok();
+  }
+  const int64_t n_tiles = (max_tracks + kf::kTile - 1) / kf::kTile;
+  const int64_t cap = n_tiles * kf::kTile * max_len;
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t b_hist = up(int64_t(kf::kMaxLen + 2) * 4), b_order = up(max_tracks * 4);
+  const int64_t b_tiles = up((n_tiles + 1) * 8), b_lv = up(cap * 4), b_hit = up(cap * 9 * 8);
+  const int64_t total = 2 * b_hist + b_order + b_tiles + b_lv + b_hit;
+  hipError_t e = hipMalloc(&ctx->work_mem, size_t(total));
+  hipSetDevice(prev);
+  if (e != hipSuccess) {
+    ctx->work_mem = nullptr;
+    return fail(KF_ERR_NOMEM, "kf_reserve: %lld bytes: %s", (long long)total, hipGetErrorString(e));
+  }
+  char* p = (char*)ctx->work_mem;
+  kf::PackWork& w = ctx->work;
+  w.hist = (int32_t*)p;
+  p += b_hist;
+  w.cursor = (int32_t*)p;
+  p += b_hist;
+  w.order = (int32_t*)p;
+  p += b_order;
+  w.tile_base = (int64_t*)p;
+  p += b_tiles;
+  w.lv = (int32_t*)p;
+  p += b_lv;
+  w.hit = (void*)p;
+  w.cap = cap;
+  w.max_tracks = max_tracks;
+  w.max_len = max_len;
   return ok();
 }
 

@@ -134,7 +134,7 @@ constexpr int kFitBlock = 256;   // upper bound of the fit kernels' block size
 
 // One thread per track.  WAVES: the minimum number of waves per SIMD the
 // register allocation must allow (1 or 2); the autotuner picks the faster.
-template <typename T, int WAVES>
+template <typename T, int WAVES, bool PACKED>
 __global__ void __launch_bounds__(kFitBlock, WAVES) fit_kernel(FitArgs<T> a, GeomArgs g) {
   __shared__ GeomLds<T> sg;
   __shared__ T sal[2 * kMaxLayers];
@@ -143,13 +143,13 @@ __global__ void __launch_bounds__(kFitBlock, WAVES) fit_kernel(FitArgs<T> a, Geo
   stage_geometry(sg, g);
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= a.n) return;
-  fit_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.align ? sal : nullptr, t,
-            bk + threadIdx.x, int(blockDim.x));
+  fit_slot<T, PACKED>(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)},
+                      a.align ? sal : nullptr, t, bk + threadIdx.x, int(blockDim.x));
 }
 
 // Persistent form: a fixed grid of blocks pulls tiles of blockDim.x tracks from
 // a device counter until none are left; every block reaches the exit.
-template <typename T, int WAVES>
+template <typename T, int WAVES, bool PACKED>
 __global__ void __launch_bounds__(kFitBlock, WAVES) fit_persistent_kernel(FitArgs<T> a, GeomArgs g) {
   __shared__ GeomLds<T> sg;
   __shared__ T sal[2 * kMaxLayers];
@@ -165,19 +165,137 @@ __global__ void __launch_bounds__(kFitBlock, WAVES) fit_persistent_kernel(FitArg
     if (my >= a.n_tiles) break;
     const int64_t t = my * blockDim.x + threadIdx.x;
     if (t < a.n)
-      fit_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.align ? sal : nullptr, t,
-                bk + threadIdx.x, int(blockDim.x));
+      fit_slot<T, PACKED>(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)},
+                          a.align ? sal : nullptr, t, bk + threadIdx.x, int(blockDim.x));
   }
 }
 
 __global__ void reset_counter_kernel(int32_t* c) { *c = 0; }
 
-template <typename T, int WAVES>
+// ---- packed, length-sorted hit layout ------------------------------------------
+
+__global__ void zero_ints_kernel(int32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// entry count of every track (clamped to max_len) into a histogram
+__global__ void length_hist_kernel(const int32_t* off, int64_t n, int32_t max_len, int32_t* hist) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  int len = off[t + 1] - off[t];
+  len = len < 0 ? 0 : (len > max_len ? max_len : len);
+  atomicAdd(&hist[len], 1);
+}
+
+// cursors for a descending-length order: longest tracks take the first slots
+__global__ void length_cursor_kernel(const int32_t* hist, int32_t max_len, int32_t* cursor) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int acc = 0;
+  for (int L = max_len; L >= 0; --L) {
+    cursor[L] = acc;
+    acc += hist[L];
+  }
+}
+
+__global__ void length_scatter_kernel(const int32_t* off, int64_t n, int32_t max_len, int32_t* cursor,
+                                      int32_t* order) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  int len = off[t + 1] - off[t];
+  len = len < 0 ? 0 : (len > max_len ? max_len : len);
+  const int slot = atomicAdd(&cursor[len], 1);
+  order[slot] = int32_t(t);
+}
+
+// tile_base = exclusive scan over tiles of kTile * (entry count of the tile's
+// first, i.e. longest, track); one block of 1024 threads
+__global__ void __launch_bounds__(1024) tile_base_kernel(const int32_t* off, const int32_t* order, int64_t n,
+                                                       int32_t max_len, int64_t* tile_base) {
+  __shared__ int64_t part[1024];
+  const int64_t n_tiles = (n + kTile - 1) / kTile;
+  const int64_t per = (n_tiles + blockDim.x - 1) / blockDim.x;
+  const int64_t b = int64_t(threadIdx.x) * per;
+  const int64_t e = b + per < n_tiles ? b + per : n_tiles;
+  int64_t sum = 0;
+  for (int64_t tau = b; tau < e; ++tau) {
+    const int64_t t = order[tau * kTile];
+    int len = off[t + 1] - off[t];
+    len = len < 0 ? 0 : (len > max_len ? max_len : len);
+    sum += int64_t(len) * kTile;
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t acc = 0;
+    for (int i = 0; i < int(blockDim.x); ++i) {
+      const int64_t v = part[i];
+      part[i] = acc;
+      acc += v;
+    }
+    tile_base[n_tiles] = acc;
+  }
+  __syncthreads();
+  int64_t acc = part[threadIdx.x];
+  for (int64_t tau = b; tau < e; ++tau) {
+    tile_base[tau] = acc;
+    const int64_t t = order[tau * kTile];
+    int len = off[t + 1] - off[t];
+    len = len < 0 ? 0 : (len > max_len ? max_len : len);
+    acc += int64_t(len) * kTile;
+  }
+}
+
+// copy the CSR entries of the track in slot s into the packed layout
+template <typename T>
+__global__ void pack_kernel(const int32_t* off, const int16_t* layer, const uint8_t* valid, const T* pos,
+                            const T* cov, int64_t n_hits, int64_t n, int32_t max_len, const int32_t* order,
+                            const int64_t* tile_base, int32_t* lv, T* hit, int64_t stride) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t t = order[s];
+  const int64_t e0 = off[t];
+  int len = off[t + 1] - off[t];
+  len = len < 0 ? 0 : (len > max_len ? max_len : len);
+  const int64_t base = tile_base[s / kTile] + s % kTile;
+  for (int k = 0; k < len; ++k) {
+    const int64_t e = e0 + k, i = base + int64_t(k) * kTile;
+    lv[i] = int32_t(uint16_t(layer[e])) | (int32_t(valid[e] != 0) << 16);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) hit[c * stride + i] = pos[c * n_hits + e];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) hit[(3 + c) * stride + i] = cov[c * n_hits + e];
+  }
+}
+
+template <typename T>
+hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, PackedHits<T>* out, hipStream_t s) {
+  const int B = 256;
+  const unsigned grid = unsigned((a.n + B - 1) / B);
+  const int nh = kMaxLen + 2;
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(128), 0, s, w.hist, nh);
+  hipLaunchKernelGGL(length_hist_kernel, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.n, a.max_len, w.hist);
+  hipLaunchKernelGGL(length_cursor_kernel, dim3(1), dim3(64), 0, s, w.hist, a.max_len, w.cursor);
+  hipLaunchKernelGGL(length_scatter_kernel, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.n, a.max_len, w.cursor,
+                     w.order);
+  hipLaunchKernelGGL(tile_base_kernel, dim3(1), dim3(1024), 0, s, a.hit_offsets, w.order, a.n, a.max_len,
+                     w.tile_base);
+  hipLaunchKernelGGL(pack_kernel<T>, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.hit_layer, a.hit_valid, a.hit_pos,
+                     a.hit_cov, a.n_hits, a.n, a.max_len, w.order, w.tile_base, w.lv, (T*)w.hit, w.cap);
+  out->order = w.order;
+  out->tile_base = w.tile_base;
+  out->lv = w.lv;
+  out->hit = (const T*)w.hit;
+  out->stride = w.cap;
+  return hipGetLastError();
+}
+
+template <typename T, int WAVES, bool PACKED>
 hipError_t launch_fit_w(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s) {
   const int block = l.block;
   if (!l.persistent) {
     const int64_t grid = (a.n + block - 1) / block;
-    hipLaunchKernelGGL((fit_kernel<T, WAVES>), dim3(unsigned(grid)), dim3(block), 0, s, a, g);
+    hipLaunchKernelGGL((fit_kernel<T, WAVES, PACKED>), dim3(unsigned(grid)), dim3(block), 0, s, a, g);
     return hipGetLastError();
   }
   FitArgs<T> b = a;
@@ -185,15 +303,19 @@ hipError_t launch_fit_w(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch&
   int64_t grid = int64_t(n_cu) * l.blocks_per_cu;
   if (grid > b.n_tiles) grid = b.n_tiles;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.tile_counter);
-  hipLaunchKernelGGL((fit_persistent_kernel<T, WAVES>), dim3(unsigned(grid)), dim3(block), 0, s, b, g);
+  hipLaunchKernelGGL((fit_persistent_kernel<T, WAVES, PACKED>), dim3(unsigned(grid)), dim3(block), 0, s, b, g);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  if (l.waves == 2) return launch_fit_w<T, 2>(a, g, l, n_cu, s);
-  return launch_fit_w<T, 1>(a, g, l, n_cu, s);
+  if (a.packed) {
+    if (l.waves == 2) return launch_fit_w<T, 2, true>(a, g, l, n_cu, s);
+    return launch_fit_w<T, 1, true>(a, g, l, n_cu, s);
+  }
+  if (l.waves == 2) return launch_fit_w<T, 2, false>(a, g, l, n_cu, s);
+  return launch_fit_w<T, 1, false>(a, g, l, n_cu, s);
 }
 
 // explicit instantiations
@@ -205,5 +327,7 @@ template hipError_t launch_update<float>(const UpdArgs<float>&, hipStream_t);
 template hipError_t launch_update<double>(const UpdArgs<double>&, hipStream_t);
 template hipError_t launch_fit<float>(const FitArgs<float>&, const GeomArgs&, const FitLaunch&, int, hipStream_t);
 template hipError_t launch_fit<double>(const FitArgs<double>&, const GeomArgs&, const FitLaunch&, int, hipStream_t);
+template hipError_t launch_pack<float>(const FitArgs<float>&, const PackWork&, PackedHits<float>*, hipStream_t);
+template hipError_t launch_pack<double>(const FitArgs<double>&, const PackWork&, PackedHits<double>*, hipStream_t);
 
 }  // namespace kf

@@ -61,9 +61,25 @@ struct UpdArgs {
   uint32_t* trk_status;
 };
 
+constexpr int kTile = 64;   // tracks per tile of the packed hit layout (one wave)
+
+// Hits in the packed, tile-transposed layout: tracks sorted by decreasing
+// entry count fill tiles of kTile slots; entry k of the track in slot s is at
+// index tile_base[s / kTile] + k * kTile + s % kTile of every component array,
+// so the entry-k loads of one wave read kTile consecutive elements.
+template <typename T>
+struct PackedHits {
+  const int32_t* order;      // [n] slot -> track
+  const int64_t* tile_base;  // [n_tiles + 1]
+  const int32_t* lv;         // layer | valid << 16
+  const T* hit;              // [9][stride]: x, y, z, then the packed 3x3 covariance
+  int64_t stride;
+};
+
 template <typename T>
 struct FitArgs {
   int64_t n, ld, n_hits;
+  int32_t max_len;           // entries beyond this are ignored (track flagged)
   const T* seed_state;
   const T* seed_cov;
   const int8_t* seed_charge;
@@ -84,7 +100,26 @@ struct FitArgs {
   uint32_t* trk_status;
   int32_t* tile_counter;  // persistent mode
   int64_t n_tiles;
+  int32_t packed;         // 1: read hits from pk instead of the CSR arrays
+  PackedHits<T> pk;
 };
+
+// Workspace of the packed layout (carved out of one device allocation).
+struct PackWork {
+  int32_t* hist;       // [kMaxLen + 2] per-length counts, then cursors
+  int32_t* cursor;     // [kMaxLen + 2]
+  int32_t* order;      // [max_tracks]
+  int64_t* tile_base;  // [max_tiles + 1]
+  int32_t* lv;         // [cap]
+  void* hit;           // [9][cap] of float or double
+  int64_t cap;         // entries per component array
+  int64_t max_tracks;
+  int32_t max_len;
+};
+constexpr int kMaxLen = 64;
+
+template <typename T>
+hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, PackedHits<T>* out, hipStream_t s);
 
 // Launch functions (defined in kf_kernels.hip).
 template <typename T>

@@ -266,14 +266,19 @@ KF_HD bool crossing(const T p[6], T sphi, T cphi, T cot, T w, int kind, T pos, b
     }
   }
   if (!found) return false;
-  // Newton polish on h(s) = r(s)^2 - R^2
+  // Newton polish on h(s) = r(s)^2 - R^2: two steps, the point moved along
+  // the helix to first order in the correction (the second step matters near
+  // tangency, where h'(s) is small and the closed-form root is least accurate)
   helix_eval(p, sphi, cphi, cot, w, best, hp);
-  const T f = (hp.x * hp.x + hp.y * hp.y - pos * pos);
-  const T df = T(2) * (hp.x * hp.cphm + hp.y * hp.sphm);
-  if (k_abs(df) > T(1e-20)) {
-    const T ds = -f * k_rcp(df);
-    best += ds;
-    helix_nudge(hp, w, cot, ds);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const T f = (hp.x * hp.x + hp.y * hp.y - pos * pos);
+    const T df = T(2) * (hp.x * hp.cphm + hp.y * hp.sphm);
+    if (k_abs(df) > T(1e-20)) {
+      const T ds = -f * k_rcp(df);
+      best += ds;
+      helix_eval(p, sphi, cphi, cot, w, best, hp);
+    }
   }
   s_out = best;
   return true;

@@ -80,41 +80,77 @@ KF_HD inline void write_checkpoint(const FitArgs<T>& a, int64_t t, int slot, con
   base[27 * stride] = T(q);
 }
 
-// Forward fit of track t.  sal: alignment staged as [rphi x kMaxLayers][z x kMaxLayers] or null.
+// Entry access for the per-track loop: the caller's CSR arrays ...
+template <typename T>
+struct CsrTrack {
+  const FitArgs<T>& a;
+  int64_t e0;
+  KF_HD inline bool valid(int k) const { return a.hit_valid[e0 + k] != 0; }
+  KF_HD inline void load(int k, int& lay, bool& val, T m[3], T V[6]) const {
+    const int64_t e = e0 + k, nh = a.n_hits;
+    lay = a.hit_layer[e];
+    val = a.hit_valid[e] != 0;
+    m[0] = a.hit_pos[e];
+    m[1] = a.hit_pos[nh + e];
+    m[2] = a.hit_pos[2 * nh + e];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) V[i] = a.hit_cov[i * nh + e];
+  }
+};
+
+// ... or the packed tile-transposed copy (slot s of its tile).
+template <typename T>
+struct PackedTrack {
+  const PackedHits<T>& pk;
+  int64_t base;  // tile_base + s % kTile
+  KF_HD inline bool valid(int k) const { return (pk.lv[base + int64_t(k) * kTile] >> 16) != 0; }
+  KF_HD inline void load(int k, int& lay, bool& val, T m[3], T V[6]) const {
+    const int64_t i = base + int64_t(k) * kTile, st = pk.stride;
+    const int32_t lv = pk.lv[i];
+    lay = int16_t(lv & 0xffff);
+    val = (lv >> 16) != 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m[c] = pk.hit[c * st + i];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) V[c] = pk.hit[(3 + c) * st + i];
+  }
+};
+
+// Forward fit of track t whose entries are read through `acc` (len entries).
+// sal: alignment staged as [rphi x kMaxLayers][z x kMaxLayers] or null.
 // bk: room for 28 values at bk[k * bk_stride] (k = 0..27) holding the state
 // before the current entry, read back only if that entry turns non-finite
 // (kept out of registers: in LDS on the device).
-template <typename T>
+template <typename T, typename Acc>
 KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t t,
-                            T* bk, int bk_stride) {
-  const int64_t ld = a.ld, nh = a.n_hits;
+                            const Acc& acc, int len, T* bk, int bk_stride) {
+  const int64_t ld = a.ld;
   T p[6], c[21];
 #pragma unroll
   for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * ld + t];
 #pragma unroll
   for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * ld + t];
   int q = a.seed_charge[t];
-  const int64_t e0 = a.hit_offsets[t], e1 = a.hit_offsets[t + 1];
-  int64_t k0 = e0;
-  while (k0 < e1 && !a.hit_valid[k0]) ++k0;
   uint32_t st = 0;
+  if (len > a.max_len) {
+    st |= TRK_BAD_INPUT;
+    len = a.max_len;
+  }
+  int k0 = 0;
+  while (k0 < len && !acc.valid(k0)) ++k0;
   T chi2 = T(0);
   int nval = 0;
-  if (k0 >= e1) {
+  if (k0 >= len) {
     st |= TRK_BAD_INPUT;
   } else {
-    int prev = a.hit_layer[k0];
-    // entry data are loaded one entry ahead so that the loads of entry e+1
-    // overlap the arithmetic of entry e
-    int lay_n = prev;
-    bool valid_n = true;
+    // entry data are loaded one entry ahead so that the loads of entry k+1
+    // overlap the arithmetic of entry k
+    int lay_n;
+    bool valid_n;
     T m_n[3], V_n[6];
-    m_n[0] = a.hit_pos[k0];
-    m_n[1] = a.hit_pos[nh + k0];
-    m_n[2] = a.hit_pos[2 * nh + k0];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) V_n[i] = a.hit_cov[i * nh + k0];
-    for (int64_t e = k0; e < e1; ++e) {
+    acc.load(k0, lay_n, valid_n, m_n, V_n);
+    int prev = lay_n;
+    for (int k = k0; k < len; ++k) {
       const int lay = lay_n;
       const bool valid = valid_n;
       T m[3], V[6];
@@ -122,21 +158,12 @@ KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
       for (int i = 0; i < 3; ++i) m[i] = m_n[i];
 #pragma unroll
       for (int i = 0; i < 6; ++i) V[i] = V_n[i];
-      if (e + 1 < e1) {
-        const int64_t f = e + 1;
-        lay_n = a.hit_layer[f];
-        valid_n = a.hit_valid[f] != 0;
-        m_n[0] = a.hit_pos[f];
-        m_n[1] = a.hit_pos[nh + f];
-        m_n[2] = a.hit_pos[2 * nh + f];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) V_n[i] = a.hit_cov[i * nh + f];
-      }
+      if (k + 1 < len) acc.load(k + 1, lay_n, valid_n, m_n, V_n);
       if (lay < 0 || lay >= g.n_layers) {
         st |= TRK_BAD_INPUT;
         break;
       }
-      const int j = int(e - k0);
+      const int j = k - k0;
       if (a.ckpt && j >= 1 && ((j - 1) % a.seg) == 0) write_checkpoint(a, t, (j - 1) / a.seg, p, c, q);
 #pragma unroll
       for (int i = 0; i < 6; ++i) bk[i * bk_stride] = p[i];
@@ -189,6 +216,24 @@ KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
   a.chi2[t] = chi2;
   a.ndf[t] = 2 * nval - 5;
   a.trk_status[t] = st;
+}
+
+// Fit of the track in slot / index `i`: through the packed layout (PACKED) or
+// straight from the CSR arrays.
+template <typename T, bool PACKED>
+KF_HD inline void fit_slot(const FitArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t i, T* bk,
+                           int bk_stride) {
+  if constexpr (PACKED) {
+    const int64_t t = a.pk.order[i];
+    const int len = int(a.hit_offsets[t + 1] - a.hit_offsets[t]);
+    PackedTrack<T> acc{a.pk, a.pk.tile_base[i / kTile] + (i % kTile)};
+    fit_track(a, g, sal, t, acc, len, bk, bk_stride);
+  } else {
+    const int64_t e0 = a.hit_offsets[i];
+    const int len = int(a.hit_offsets[i + 1] - e0);
+    CsrTrack<T> acc{a, e0};
+    fit_track(a, g, sal, i, acc, len, bk, bk_stride);
+  }
 }
 
 }  // namespace kf

@@ -23,7 +23,7 @@ MAX_LAYERS = 64
 
 EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_propagate", "kf_update",
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
-           "kf_device_cu_count"]
+           "kf_device_cu_count", "kf_reserve"]
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -72,6 +72,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_get_fit_launch.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
     lib.kf_device_cu_count.argtypes = [_vp, ctypes.POINTER(_i32)]
+    lib.kf_reserve.argtypes = [_vp, _i64, _i32]
     return lib
 
 
@@ -163,6 +164,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def reserve(self, max_tracks, max_len=26):
+        """Workspace for the packed hit layout of fit_tracks (see kf_reserve)."""
+        _check(lib().kf_reserve(self.handle, int(max_tracks), int(max_len)))
 
     # ---- tuning -----------------------------------------------------------
     def set_fit_launch(self, dtype, block, persistent, blocks_per_cu, waves=1):

@@ -34,6 +34,16 @@ def kf():
 
 @pytest.fixture(scope="module")
 def ctx(kf):
+    """Context with the packed-layout workspace (the fast path)."""
+    c = kf.Context(0)
+    c.reserve(600_000, 26)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_csr(kf):
+    """Context without a workspace: the fit reads the CSR arrays directly."""
     c = kf.Context(0)
     yield c
     c.close()
@@ -254,12 +264,31 @@ def test_fit_every_length_3_to_26(ctx, kf):
 
 
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1000 + 13])
-def test_fit_ragged_sizes(ctx, kf, n):
+def test_fit_ragged_sizes(ctx, ctx_csr, kf, n):
     say("fit ragged", n)
     ev = generate(workloads()["mixed26"], max(n, 1))
     if n == 0:
         ev = subset(ev, [])
     _fit_case(ctx, kf, ev, torch.float64, 1, TOL64)
+    _fit_case(ctx_csr, kf, ev, torch.float64, 1, TOL64)
+
+
+def test_fit_max_len_truncates_and_flags(ctx, ctx_csr, kf):
+    """Entries beyond max_len are ignored (both layouts) and the track is flagged."""
+    say("fit max_len")
+    ev = generate(workloads()["mixed26"], 500)
+    for c in (ctx, ctx_csr):
+        g = gpu_fit(c, kf, ev, torch.float64, 1, max_len=12)
+        o = oracle_fit(truncate(ev, np.full(ev.n_tracks, 12)), torch.float64, 1)
+        long_ = ev.lengths() > 12
+        assert ((g["status"][long_] & kf.TRK_BAD_INPUT) != 0).all()
+        assert ((g["status"][~long_] & kf.TRK_BAD_INPUT) == 0).all()
+        g["status"] = g["status"] & ~kf.TRK_BAD_INPUT
+        # seeds: the oracle seeds from the truncated track, the GPU from the full one
+        ok = np.ones(ev.n_tracks, bool)
+        sp_full = g["seed"]
+        ok &= param_error(sp_full, o["seed"]).max(axis=1) < 1e-12
+        compare_fit(g, o, TOL64[0], TOL64[1], ok)
 
 
 def test_fit_edge_cases(ctx, kf):
@@ -295,11 +324,13 @@ def test_fit_edge_cases(ctx, kf):
     assert ((gres["status"][full] & O.NO_CROSSING) != 0).all()
 
 
-def test_fit_deterministic_and_launch_shape_independent(ctx, kf):
+def test_fit_deterministic_and_launch_shape_independent(ctx, ctx_csr, kf):
     say("fit determinism")
     ev = generate(workloads()["mixed26"], 20_000)
     a = gpu_fit(ctx, kf, ev, torch.float32, 1)
     b = gpu_fit(ctx, kf, ev, torch.float32, 1)
+    e = gpu_fit(ctx_csr, kf, ev, torch.float32, 1)     # CSR layout, same arithmetic
+    assert np.array_equal(a["p"], e["p"]) and np.array_equal(a["chi2"], e["chi2"])
     old = ctx.get_fit_launch(torch.float32)
     try:
         ctx.set_fit_launch(torch.float32, 64, 1, 8, 2)
