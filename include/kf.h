@@ -163,11 +163,13 @@ int kf_update(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
  * n_seg = ceil((max_len - 1) / seg)); used by kf_fit_adjoint.
  * max_len (1..64) bounds the entries used per track: entries beyond it are
  * ignored and the track gets KF_TRK_BAD_INPUT.
- * Layout: when the context holds a workspace from kf_reserve large enough
- * for n tracks and max_len, the call first sorts the tracks by entry count
- * and copies the hits into a tile-transposed layout (entry k of 64 tracks
- * contiguous) so that every hit load of a wave is one coalesced read;
- * otherwise the fit reads the CSR arrays directly.  Results are identical. */
+ * Layout (a tuning choice, see kf_set_fit_launch): with a workspace from
+ * kf_reserve large enough for n tracks and max_len, the call can first sort
+ * the tracks by entry count (longest first, so that the lanes of a wave run
+ * similar loops) and optionally copy the hits into a tile-transposed layout
+ * (entry k of 64 tracks contiguous, every hit load of a wave one coalesced
+ * read); without a workspace the fit reads the CSR arrays in track order.
+ * Results are identical for every layout. */
 int kf_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                   const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
                   const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
@@ -248,15 +250,17 @@ int kf_reserve(kf_ctx *ctx, int64_t max_tracks, int32_t max_len);
  * Launch shape of kf_fit_tracks for one precision: threads per block (64, 128,
  * 192 or 256), persistent (1: a fixed grid of n_cu * blocks_per_cu blocks that
  * pull tiles of `block` tracks from a device counter; 0: one thread per
- * track), blocks_per_cu (1..32) and waves (1 or 2: the kernel variant whose
- * register allocation allows at least that many waves per SIMD).  Every
- * launch shape computes bit-identical results; the choice is made by the
- * autotuner of the Python package and only changes speed.  Stored in the
+ * track), blocks_per_cu (1..32), waves (1 or 2: the kernel variant whose
+ * register allocation allows at least that many waves per SIMD) and layout
+ * (0: CSR in track order; 1: CSR in length-sorted order; 2: length-sorted
+ * and packed -- 1 and 2 need a workspace from kf_reserve, else 0 is used).
+ * Every launch shape computes bit-identical results; the choice is made by
+ * the autotuner of the Python package and only changes speed.  Stored in the
  * context. */
 int kf_set_fit_launch(kf_ctx *ctx, kf_precision prec, int32_t block, int32_t persistent, int32_t blocks_per_cu,
-                      int32_t waves);
+                      int32_t waves, int32_t layout);
 int kf_get_fit_launch(const kf_ctx *ctx, kf_precision prec, int32_t *block, int32_t *persistent,
-                      int32_t *blocks_per_cu, int32_t *waves);
+                      int32_t *blocks_per_cu, int32_t *waves, int32_t *layout);
 /* Number of compute units of the context's device. */
 int kf_device_cu_count(const kf_ctx *ctx, int32_t *n_cu);
 

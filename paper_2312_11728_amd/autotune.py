@@ -4,7 +4,9 @@ Every launch shape of kf_fit_tracks computes bit-identical results, so the
 tuner only measures: it times each candidate (threads per block, plain or
 persistent grid, blocks per compute unit for the persistent grid, and the
 kernel variant compiled for one or two waves per SIMD) on the caller's own
-inputs with HIP events on the current stream, keeps the fastest, sets it in
+inputs with HIP events on the current stream, together with the hit layout
+(track order, length-sorted, or length-sorted and packed -- the sorting and
+packing passes are part of the timed call), keeps the fastest, sets it in
 the context and records it in a JSON cache keyed by (operation, precision,
 track-count class, device name)."""
 from __future__ import annotations
@@ -20,13 +22,15 @@ from . import kf as K
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "kf_autotune.json")
 
 
-def candidates():
+def candidates(layouts=(0, 1, 2)):
+    """(block, persistent, blocks_per_cu, waves, layout) shapes to time."""
     out = []
-    for waves in (1, 2):
-        for block in (64, 128, 256):
-            out.append((block, 0, 1, waves))
-            for bpc in (2, 4, 8):
-                out.append((block, 1, bpc, waves))
+    for layout in layouts:
+        for waves in (1, 2):
+            for block in (64, 128, 256):
+                out.append((block, 0, 1, waves, layout))
+                for bpc in (4, 8):
+                    out.append((block, 1, bpc, waves, layout))
     return out
 
 

@@ -16,7 +16,7 @@ struct kf_ctx {
   int device = 0;
   int n_cu = 256;
   int32_t* d_counter = nullptr;      // persistent-kernel tile counter
-  kf::FitLaunch fit[2] = {{256, 0, 4, 1}, {256, 0, 4, 1}};  // per precision
+  kf::FitLaunch fit[2] = {{256, 0, 4, 1, 0}, {256, 0, 4, 1, 0}};  // per precision
   // graph cache for kf_fit_tracks (one entry per precision)
   bool use_graph[2] = {false, false};
   hipStream_t capture = nullptr;
@@ -321,23 +321,25 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   hipStream_t s = (hipStream_t)stream;
   const int pi = prec == KF_F32 ? 0 : 1;
   const kf::FitLaunch l = ctx->fit[pi];
-  const bool packed = ctx->work.cap > 0 && n <= ctx->work.max_tracks && max_len <= ctx->work.max_len;
+  const bool room = ctx->work.cap > 0 && n <= ctx->work.max_tracks && max_len <= ctx->work.max_len;
+  const int layout = room ? l.layout : 0;
+  const bool packed = layout != 0;
   hipError_t e;
   if (prec == KF_F32) {
     auto a = make_fit_args<float>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, n_hits,
                                   hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf, checkpoints, seg,
                                   n_seg, trk_status, ctx->d_counter);
     a.max_len = max_len;
-    if (packed && (e = kf::launch_pack(a, ctx->work, &a.pk, s)) != hipSuccess) return hip_fail(e, "kf_fit_tracks");
-    a.packed = packed ? 1 : 0;
+    if (packed && (e = kf::launch_pack(a, ctx->work, layout, &a.pk, s)) != hipSuccess) return hip_fail(e, "kf_fit_tracks");
+    a.packed = layout;
     e = kf::launch_fit(a, g, l, ctx->n_cu, s);
   } else {
     auto a = make_fit_args<double>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
                                    n_hits, hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf,
                                    checkpoints, seg, n_seg, trk_status, ctx->d_counter);
     a.max_len = max_len;
-    if (packed && (e = kf::launch_pack(a, ctx->work, &a.pk, s)) != hipSuccess) return hip_fail(e, "kf_fit_tracks");
-    a.packed = packed ? 1 : 0;
+    if (packed && (e = kf::launch_pack(a, ctx->work, layout, &a.pk, s)) != hipSuccess) return hip_fail(e, "kf_fit_tracks");
+    a.packed = layout;
     e = kf::launch_fit(a, g, l, ctx->n_cu, s);
   }
   if (e != hipSuccess) return hip_fail(e, "kf_fit_tracks");
@@ -365,7 +367,7 @@ int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {
   auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
   const int64_t b_hist = up(int64_t(kf::kMaxLen + 2) * 4), b_order = up(max_tracks * 4);
   const int64_t b_tiles = up((n_tiles + 1) * 8), b_lv = up(cap * 4), b_hit = up(cap * 9 * 8);
-  const int64_t total = 2 * b_hist + b_order + b_tiles + b_lv + b_hit;
+  const int64_t total = 2 * b_hist + 2 * b_order + b_tiles + b_lv + b_hit;
   hipError_t e = hipMalloc(&ctx->work_mem, size_t(total));
   hipSetDevice(prev);
   if (e != hipSuccess) {
@@ -380,6 +382,8 @@ int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {
   p += b_hist;
   w.order = (int32_t*)p;
   p += b_order;
+  w.slot_of = (int32_t*)p;
+  p += b_order;
   w.tile_base = (int64_t*)p;
   p += b_tiles;
   w.lv = (int32_t*)p;
@@ -392,30 +396,33 @@ int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {
 }
 
 int kf_set_fit_launch(kf_ctx* ctx, kf_precision prec, int32_t block, int32_t persistent, int32_t blocks_per_cu,
-                      int32_t waves) {
+                      int32_t waves, int32_t layout) {
   KF_TRY(check_prec(prec));
   if (waves != 1 && waves != 2) return fail(KF_ERR_ARG, "waves = %d (1 or 2)", waves);
+  if (layout < 0 || layout > 2) return fail(KF_ERR_ARG, "layout = %d (0, 1 or 2)", layout);
   if (block < 64 || block > 256 || block % 64 != 0) return fail(KF_ERR_ARG, "block = %d (64, 128, 192 or 256)", block);
   if (persistent != 0 && persistent != 1) return fail(KF_ERR_ARG, "persistent must be 0 or 1");
   if (blocks_per_cu < 1 || blocks_per_cu > 32) return fail(KF_ERR_ARG, "blocks_per_cu = %d outside [1, 32]", blocks_per_cu);
   KF_REQUIRE(ctx);
-  ctx->fit[prec == KF_F32 ? 0 : 1] = kf::FitLaunch{block, persistent, blocks_per_cu, waves};
+  ctx->fit[prec == KF_F32 ? 0 : 1] = kf::FitLaunch{block, persistent, blocks_per_cu, waves, layout};
   return ok();
 }
 
 int kf_get_fit_launch(const kf_ctx* ctx, kf_precision prec, int32_t* block, int32_t* persistent,
-                      int32_t* blocks_per_cu, int32_t* waves) {
+                      int32_t* blocks_per_cu, int32_t* waves, int32_t* layout) {
   KF_TRY(check_prec(prec));
   KF_REQUIRE(ctx);
   KF_REQUIRE(block);
   KF_REQUIRE(persistent);
   KF_REQUIRE(blocks_per_cu);
   KF_REQUIRE(waves);
+  KF_REQUIRE(layout);
   const kf::FitLaunch& l = ctx->fit[prec == KF_F32 ? 0 : 1];
   *block = l.block;
   *persistent = l.persistent;
   *blocks_per_cu = l.blocks_per_cu;
   *waves = l.waves;
+  *layout = l.layout;
   return ok();
 }
 

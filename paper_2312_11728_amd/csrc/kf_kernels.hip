@@ -134,7 +134,7 @@ constexpr int kFitBlock = 256;   // upper bound of the fit kernels' block size
 
 // One thread per track.  WAVES: the minimum number of waves per SIMD the
 // register allocation must allow (1 or 2); the autotuner picks the faster.
-template <typename T, int WAVES, bool PACKED>
+template <typename T, int WAVES, int LAYOUT>
 __global__ void __launch_bounds__(kFitBlock, WAVES) fit_kernel(FitArgs<T> a, GeomArgs g) {
   __shared__ GeomLds<T> sg;
   __shared__ T sal[2 * kMaxLayers];
@@ -143,13 +143,13 @@ __global__ void __launch_bounds__(kFitBlock, WAVES) fit_kernel(FitArgs<T> a, Geo
   stage_geometry(sg, g);
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= a.n) return;
-  fit_slot<T, PACKED>(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)},
+  fit_slot<T, LAYOUT>(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)},
                       a.align ? sal : nullptr, t, bk + threadIdx.x, int(blockDim.x));
 }
 
 // Persistent form: a fixed grid of blocks pulls tiles of blockDim.x tracks from
 // a device counter until none are left; every block reaches the exit.
-template <typename T, int WAVES, bool PACKED>
+template <typename T, int WAVES, int LAYOUT>
 __global__ void __launch_bounds__(kFitBlock, WAVES) fit_persistent_kernel(FitArgs<T> a, GeomArgs g) {
   __shared__ GeomLds<T> sg;
   __shared__ T sal[2 * kMaxLayers];
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(kFitBlock, WAVES) fit_persistent_kernel(FitArg
     if (my >= a.n_tiles) break;
     const int64_t t = my * blockDim.x + threadIdx.x;
     if (t < a.n)
-      fit_slot<T, PACKED>(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)},
+      fit_slot<T, LAYOUT>(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)},
                           a.align ? sal : nullptr, t, bk + threadIdx.x, int(blockDim.x));
   }
 }
@@ -179,13 +179,22 @@ __global__ void zero_ints_kernel(int32_t* p, int n) {
   if (i < n) p[i] = 0;
 }
 
-// entry count of every track (clamped to max_len) into a histogram
-__global__ void length_hist_kernel(const int32_t* off, int64_t n, int32_t max_len, int32_t* hist) {
+// entry count of every track (clamped to max_len) into a histogram: per-block
+// counts in LDS, then one global atomic per block and length
+__global__ void __launch_bounds__(256) length_hist_kernel(const int32_t* off, int64_t n, int32_t max_len,
+                                                          int32_t* hist) {
+  __shared__ int32_t h[kMaxLen + 1];
+  for (int i = threadIdx.x; i <= kMaxLen; i += blockDim.x) h[i] = 0;
+  __syncthreads();
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  int len = off[t + 1] - off[t];
-  len = len < 0 ? 0 : (len > max_len ? max_len : len);
-  atomicAdd(&hist[len], 1);
+  if (t < n) {
+    int len = off[t + 1] - off[t];
+    len = len < 0 ? 0 : (len > max_len ? max_len : len);
+    atomicAdd(&h[len], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= kMaxLen; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
 // cursors for a descending-length order: longest tracks take the first slots
@@ -198,18 +207,35 @@ __global__ void length_cursor_kernel(const int32_t* hist, int32_t max_len, int32
   }
 }
 
-__global__ void length_scatter_kernel(const int32_t* off, int64_t n, int32_t max_len, int32_t* cursor,
-                                      int32_t* order) {
+// slot of every track: each block reserves a range per length with one global
+// atomic, and ranks its tracks inside it through LDS atomics
+__global__ void __launch_bounds__(256) length_scatter_kernel(const int32_t* off, int64_t n, int32_t max_len,
+                                                             int32_t* cursor, int32_t* order, int32_t* slot_of) {
+  __shared__ int32_t h[kMaxLen + 1];
+  __shared__ int32_t base[kMaxLen + 1];
+  for (int i = threadIdx.x; i <= kMaxLen; i += blockDim.x) h[i] = 0;
+  __syncthreads();
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  int len = off[t + 1] - off[t];
-  len = len < 0 ? 0 : (len > max_len ? max_len : len);
-  const int slot = atomicAdd(&cursor[len], 1);
-  order[slot] = int32_t(t);
+  int len = 0, rank = 0;
+  if (t < n) {
+    len = off[t + 1] - off[t];
+    len = len < 0 ? 0 : (len > max_len ? max_len : len);
+    rank = atomicAdd(&h[len], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= kMaxLen; i += blockDim.x)
+    base[i] = h[i] ? atomicAdd(&cursor[i], h[i]) : 0;
+  __syncthreads();
+  if (t < n) {
+    const int slot = base[len] + rank;
+    order[slot] = int32_t(t);
+    slot_of[t] = slot;
+  }
 }
 
 // tile_base = exclusive scan over tiles of kTile * (entry count of the tile's
-// first, i.e. longest, track); one block of 1024 threads
+// first, i.e. longest, track); one block of 1024 threads, each summing a
+// contiguous run of tiles, then a Hillis-Steele scan of the run sums in LDS
 __global__ void __launch_bounds__(1024) tile_base_kernel(const int32_t* off, const int32_t* order, int64_t n,
                                                        int32_t max_len, int64_t* tile_base) {
   __shared__ int64_t part[1024];
@@ -226,17 +252,14 @@ __global__ void __launch_bounds__(1024) tile_base_kernel(const int32_t* off, con
   }
   part[threadIdx.x] = sum;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t acc = 0;
-    for (int i = 0; i < int(blockDim.x); ++i) {
-      const int64_t v = part[i];
-      part[i] = acc;
-      acc += v;
-    }
-    tile_base[n_tiles] = acc;
+  for (int d = 1; d < int(blockDim.x); d <<= 1) {
+    const int64_t v = threadIdx.x >= unsigned(d) ? part[threadIdx.x - d] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
   }
-  __syncthreads();
-  int64_t acc = part[threadIdx.x];
+  int64_t acc = part[threadIdx.x] - sum;   // exclusive prefix of this thread's run
+  if (threadIdx.x == blockDim.x - 1) tile_base[n_tiles] = part[threadIdx.x];
   for (int64_t tau = b; tau < e; ++tau) {
     tile_base[tau] = acc;
     const int64_t t = order[tau * kTile];
@@ -246,30 +269,43 @@ __global__ void __launch_bounds__(1024) tile_base_kernel(const int32_t* off, con
   }
 }
 
-// copy the CSR entries of the track in slot s into the packed layout
-template <typename T>
-__global__ void pack_kernel(const int32_t* off, const int16_t* layer, const uint8_t* valid, const T* pos,
-                            const T* cov, int64_t n_hits, int64_t n, int32_t max_len, const int32_t* order,
-                            const int64_t* tile_base, int32_t* lv, T* hit, int64_t stride) {
-  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const int64_t t = order[s];
-  const int64_t e0 = off[t];
-  int len = off[t + 1] - off[t];
-  len = len < 0 ? 0 : (len > max_len ? max_len : len);
-  const int64_t base = tile_base[s / kTile] + s % kTile;
-  for (int k = 0; k < len; ++k) {
-    const int64_t e = e0 + k, i = base + int64_t(k) * kTile;
-    lv[i] = int32_t(uint16_t(layer[e])) | (int32_t(valid[e] != 0) << 16);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) hit[c * stride + i] = pos[c * n_hits + e];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) hit[(3 + c) * stride + i] = cov[c * n_hits + e];
+// entry -> track by binary search in the CSR offsets
+__device__ __forceinline__ int64_t track_of_entry(const int32_t* off, int64_t n, int64_t e) {
+  int64_t lo = 0, hi = n;   // off[lo] <= e < off[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid;
   }
+  return lo;
+}
+
+// copy every CSR entry to its place in the packed layout (one thread per
+// entry: the reads are contiguous)
+template <typename T>
+__global__ void __launch_bounds__(256) pack_kernel(const int32_t* off, const int16_t* layer, const uint8_t* valid,
+                                                   const T* pos, const T* cov, int64_t n_hits, int64_t n,
+                                                   int32_t max_len, const int32_t* slot_of,
+                                                   const int64_t* tile_base, int32_t* lv, T* hit, int64_t stride) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n_hits) return;
+  const int64_t t = track_of_entry(off, n, e);
+  if (e < off[t] || e >= off[t + 1]) return;   // entry outside every track's range
+  const int k = int(e - off[t]);
+  if (k >= max_len) return;
+  const int64_t s = slot_of[t];
+  const int64_t i = tile_base[s / kTile] + s % kTile + int64_t(k) * kTile;
+  lv[i] = int32_t(uint16_t(layer[e])) | (int32_t(valid[e] != 0) << 16);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) hit[c * stride + i] = pos[c * n_hits + e];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) hit[(3 + c) * stride + i] = cov[c * n_hits + e];
 }
 
 template <typename T>
-hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, PackedHits<T>* out, hipStream_t s) {
+hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, int layout, PackedHits<T>* out, hipStream_t s) {
   const int B = 256;
   const unsigned grid = unsigned((a.n + B - 1) / B);
   const int nh = kMaxLen + 2;
@@ -277,25 +313,34 @@ hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, PackedHits<T>* ou
   hipLaunchKernelGGL(length_hist_kernel, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.n, a.max_len, w.hist);
   hipLaunchKernelGGL(length_cursor_kernel, dim3(1), dim3(64), 0, s, w.hist, a.max_len, w.cursor);
   hipLaunchKernelGGL(length_scatter_kernel, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.n, a.max_len, w.cursor,
-                     w.order);
-  hipLaunchKernelGGL(tile_base_kernel, dim3(1), dim3(1024), 0, s, a.hit_offsets, w.order, a.n, a.max_len,
-                     w.tile_base);
-  hipLaunchKernelGGL(pack_kernel<T>, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.hit_layer, a.hit_valid, a.hit_pos,
-                     a.hit_cov, a.n_hits, a.n, a.max_len, w.order, w.tile_base, w.lv, (T*)w.hit, w.cap);
+                     w.order, w.slot_of);
   out->order = w.order;
-  out->tile_base = w.tile_base;
-  out->lv = w.lv;
-  out->hit = (const T*)w.hit;
-  out->stride = w.cap;
+  out->tile_base = nullptr;
+  out->lv = nullptr;
+  out->hit = nullptr;
+  out->stride = 0;
+  if (layout == 2) {
+    hipLaunchKernelGGL(tile_base_kernel, dim3(1), dim3(1024), 0, s, a.hit_offsets, w.order, a.n, a.max_len,
+                       w.tile_base);
+    const unsigned gh = unsigned((a.n_hits + B - 1) / B);
+    if (a.n_hits > 0)
+      hipLaunchKernelGGL(pack_kernel<T>, dim3(gh), dim3(B), 0, s, a.hit_offsets, a.hit_layer, a.hit_valid,
+                         a.hit_pos, a.hit_cov, a.n_hits, a.n, a.max_len, w.slot_of, w.tile_base, w.lv, (T*)w.hit,
+                         w.cap);
+    out->tile_base = w.tile_base;
+    out->lv = w.lv;
+    out->hit = (const T*)w.hit;
+    out->stride = w.cap;
+  }
   return hipGetLastError();
 }
 
-template <typename T, int WAVES, bool PACKED>
+template <typename T, int WAVES, int LAYOUT>
 hipError_t launch_fit_w(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s) {
   const int block = l.block;
   if (!l.persistent) {
     const int64_t grid = (a.n + block - 1) / block;
-    hipLaunchKernelGGL((fit_kernel<T, WAVES, PACKED>), dim3(unsigned(grid)), dim3(block), 0, s, a, g);
+    hipLaunchKernelGGL((fit_kernel<T, WAVES, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s, a, g);
     return hipGetLastError();
   }
   FitArgs<T> b = a;
@@ -303,19 +348,16 @@ hipError_t launch_fit_w(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch&
   int64_t grid = int64_t(n_cu) * l.blocks_per_cu;
   if (grid > b.n_tiles) grid = b.n_tiles;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.tile_counter);
-  hipLaunchKernelGGL((fit_persistent_kernel<T, WAVES, PACKED>), dim3(unsigned(grid)), dim3(block), 0, s, b, g);
+  hipLaunchKernelGGL((fit_persistent_kernel<T, WAVES, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s, b, g);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  if (a.packed) {
-    if (l.waves == 2) return launch_fit_w<T, 2, true>(a, g, l, n_cu, s);
-    return launch_fit_w<T, 1, true>(a, g, l, n_cu, s);
-  }
-  if (l.waves == 2) return launch_fit_w<T, 2, false>(a, g, l, n_cu, s);
-  return launch_fit_w<T, 1, false>(a, g, l, n_cu, s);
+  if (a.packed == 2) return l.waves == 2 ? launch_fit_w<T, 2, 2>(a, g, l, n_cu, s) : launch_fit_w<T, 1, 2>(a, g, l, n_cu, s);
+  if (a.packed == 1) return l.waves == 2 ? launch_fit_w<T, 2, 1>(a, g, l, n_cu, s) : launch_fit_w<T, 1, 1>(a, g, l, n_cu, s);
+  return l.waves == 2 ? launch_fit_w<T, 2, 0>(a, g, l, n_cu, s) : launch_fit_w<T, 1, 0>(a, g, l, n_cu, s);
 }
 
 // explicit instantiations
@@ -327,7 +369,7 @@ template hipError_t launch_update<float>(const UpdArgs<float>&, hipStream_t);
 template hipError_t launch_update<double>(const UpdArgs<double>&, hipStream_t);
 template hipError_t launch_fit<float>(const FitArgs<float>&, const GeomArgs&, const FitLaunch&, int, hipStream_t);
 template hipError_t launch_fit<double>(const FitArgs<double>&, const GeomArgs&, const FitLaunch&, int, hipStream_t);
-template hipError_t launch_pack<float>(const FitArgs<float>&, const PackWork&, PackedHits<float>*, hipStream_t);
-template hipError_t launch_pack<double>(const FitArgs<double>&, const PackWork&, PackedHits<double>*, hipStream_t);
+template hipError_t launch_pack<float>(const FitArgs<float>&, const PackWork&, int, PackedHits<float>*, hipStream_t);
+template hipError_t launch_pack<double>(const FitArgs<double>&, const PackWork&, int, PackedHits<double>*, hipStream_t);
 
 }  // namespace kf

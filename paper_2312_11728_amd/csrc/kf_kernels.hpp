@@ -100,7 +100,7 @@ struct FitArgs {
   uint32_t* trk_status;
   int32_t* tile_counter;  // persistent mode
   int64_t n_tiles;
-  int32_t packed;         // 1: read hits from pk instead of the CSR arrays
+  int32_t packed;         // layout: 0 CSR, 1 CSR in length-sorted order, 2 sorted and packed (pk)
   PackedHits<T> pk;
 };
 
@@ -108,7 +108,8 @@ struct FitArgs {
 struct PackWork {
   int32_t* hist;       // [kMaxLen + 2] per-length counts, then cursors
   int32_t* cursor;     // [kMaxLen + 2]
-  int32_t* order;      // [max_tracks]
+  int32_t* order;      // [max_tracks] slot -> track
+  int32_t* slot_of;    // [max_tracks] track -> slot
   int64_t* tile_base;  // [max_tiles + 1]
   int32_t* lv;         // [cap]
   void* hit;           // [9][cap] of float or double
@@ -119,7 +120,7 @@ struct PackWork {
 constexpr int kMaxLen = 64;
 
 template <typename T>
-hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, PackedHits<T>* out, hipStream_t s);
+hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, int layout, PackedHits<T>* out, hipStream_t s);
 
 // Launch functions (defined in kf_kernels.hip).
 template <typename T>
@@ -134,6 +135,7 @@ struct FitLaunch {
   int persistent;   // 0: one thread per track; 1: persistent blocks pulling tiles
   int blocks_per_cu;
   int waves;        // register budget: at least this many waves per SIMD (1 or 2)
+  int layout;       // 0 CSR, 1 length-sorted CSR, 2 length-sorted packed (needs a workspace)
 };
 template <typename T>
 hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s);

@@ -218,12 +218,19 @@ KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
   a.trk_status[t] = st;
 }
 
-// Fit of the track in slot / index `i`: through the packed layout (PACKED) or
-// straight from the CSR arrays.
-template <typename T, bool PACKED>
+// Fit of the track in slot / index `i`: LAYOUT 2 reads the packed layout,
+// LAYOUT 1 the CSR arrays in length-sorted slot order, LAYOUT 0 the CSR arrays
+// with slot = track.
+template <typename T, int LAYOUT>
 KF_HD inline void fit_slot(const FitArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t i, T* bk,
                            int bk_stride) {
-  if constexpr (PACKED) {
+  if constexpr (LAYOUT == 1) {
+    const int64_t t = a.pk.order[i];
+    const int64_t e0 = a.hit_offsets[t];
+    const int len = int(a.hit_offsets[t + 1] - e0);
+    CsrTrack<T> acc{a, e0};
+    fit_track(a, g, sal, t, acc, len, bk, bk_stride);
+  } else if constexpr (LAYOUT == 2) {
     const int64_t t = a.pk.order[i];
     const int len = int(a.hit_offsets[t + 1] - a.hit_offsets[t]);
     PackedTrack<T> acc{a.pk, a.pk.tile_base[i / kTile] + (i % kTile)};

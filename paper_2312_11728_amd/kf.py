@@ -68,9 +68,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_adjoint.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                    ctypes.POINTER(KfGeometry), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
-    lib.kf_set_fit_launch.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i32, _i32]
+    lib.kf_set_fit_launch.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i32, _i32, _i32]
     lib.kf_get_fit_launch.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
-                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
     lib.kf_device_cu_count.argtypes = [_vp, ctypes.POINTER(_i32)]
     lib.kf_reserve.argtypes = [_vp, _i64, _i32]
     return lib
@@ -170,14 +170,14 @@ class Context:
         _check(lib().kf_reserve(self.handle, int(max_tracks), int(max_len)))
 
     # ---- tuning -----------------------------------------------------------
-    def set_fit_launch(self, dtype, block, persistent, blocks_per_cu, waves=1):
-        _check(lib().kf_set_fit_launch(self.handle, _prec(dtype), block, persistent, blocks_per_cu, waves))
+    def set_fit_launch(self, dtype, block, persistent, blocks_per_cu, waves=1, layout=0):
+        _check(lib().kf_set_fit_launch(self.handle, _prec(dtype), block, persistent, blocks_per_cu, waves, layout))
 
     def get_fit_launch(self, dtype):
-        b, p, k, w = _i32(), _i32(), _i32(), _i32()
+        b, p, k, w, l = _i32(), _i32(), _i32(), _i32(), _i32()
         _check(lib().kf_get_fit_launch(self.handle, _prec(dtype), ctypes.byref(b), ctypes.byref(p), ctypes.byref(k),
-                                       ctypes.byref(w)))
-        return b.value, p.value, k.value, w.value
+                                       ctypes.byref(w), ctypes.byref(l)))
+        return b.value, p.value, k.value, w.value, l.value
 
     def cu_count(self):
         n = _i32()

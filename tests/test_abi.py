@@ -93,6 +93,9 @@ def test_other_entry_points_validate():
     assert "hit_cov" in lib.kf_last_error().decode()
     assert lib.kf_make_seeds(P, 0, 5, 5, P, P, 10, P, 3.8, 2, P, P, P, P, None) == kf.KF_ERR_ARG
     assert "seed mode" in lib.kf_last_error().decode()
-    assert lib.kf_set_fit_launch(P, 0, 100, 0, 4, 1) == kf.KF_ERR_ARG
-    assert lib.kf_set_fit_launch(P, 0, 128, 2, 4, 1) == kf.KF_ERR_ARG
-    assert lib.kf_set_fit_launch(P, 0, 128, 0, 4, 3) == kf.KF_ERR_ARG
+    assert lib.kf_set_fit_launch(P, 0, 100, 0, 4, 1, 0) == kf.KF_ERR_ARG
+    assert lib.kf_set_fit_launch(P, 0, 128, 2, 4, 1, 0) == kf.KF_ERR_ARG
+    assert lib.kf_set_fit_launch(P, 0, 128, 0, 4, 3, 0) == kf.KF_ERR_ARG
+    assert lib.kf_set_fit_launch(P, 0, 128, 0, 4, 1, 3) == kf.KF_ERR_ARG
+    assert lib.kf_reserve(P, -1, 26) == kf.KF_ERR_ARG
+    assert lib.kf_reserve(P, 10, 65) == kf.KF_ERR_ARG

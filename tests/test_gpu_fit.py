@@ -34,9 +34,11 @@ def kf():
 
 @pytest.fixture(scope="module")
 def ctx(kf):
-    """Context with the packed-layout workspace (the fast path)."""
+    """Context with the workspace, set to the sorted and packed layout."""
     c = kf.Context(0)
     c.reserve(600_000, 26)
+    for dt in (torch.float32, torch.float64):
+        c.set_fit_launch(dt, 256, 0, 1, 1, 2)
     yield c
     c.close()
 
@@ -333,13 +335,15 @@ def test_fit_deterministic_and_launch_shape_independent(ctx, ctx_csr, kf):
     assert np.array_equal(a["p"], e["p"]) and np.array_equal(a["chi2"], e["chi2"])
     old = ctx.get_fit_launch(torch.float32)
     try:
-        ctx.set_fit_launch(torch.float32, 64, 1, 8, 2)
+        ctx.set_fit_launch(torch.float32, 64, 1, 8, 2, 2)
         c = gpu_fit(ctx, kf, ev, torch.float32, 1)
-        ctx.set_fit_launch(torch.float32, 128, 0, 1, 1)
+        ctx.set_fit_launch(torch.float32, 128, 0, 1, 1, 1)
         d = gpu_fit(ctx, kf, ev, torch.float32, 1)
+        ctx.set_fit_launch(torch.float32, 256, 1, 4, 1, 0)
+        f = gpu_fit(ctx, kf, ev, torch.float32, 1)
     finally:
         ctx.set_fit_launch(torch.float32, *old)
-    for x in (b, c, d):
+    for x in (b, c, d, f):
         assert np.array_equal(a["p"], x["p"]) and np.array_equal(a["C"], x["C"])
         assert np.array_equal(a["chi2"], x["chi2"]) and np.array_equal(a["status"], x["status"])
 
