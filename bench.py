@@ -25,6 +25,10 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 # operation count of the per-entry step in the design notes
 FLOP_VALID_ENTRY = 1280
 FLOP_HOLE_ENTRY = 475
+# reverse of one entry (update, material and transport adjoints), excluding
+# the recomputation of forward states from checkpoints
+FLOP_VJP_VALID_ENTRY = 2660
+FLOP_VJP_HOLE_ENTRY = 1550
 FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
@@ -108,6 +112,57 @@ def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
             "frac_fp32_peak": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, "launch": list(best)}
 
 
+def bench_adjoint(ctx, K, generate, workloads, args, seg=5):
+    """d(sum chi2)/d(seed states, hit positions, alignment offsets) for
+    100,000 FP32 tracks x 20 barrel layers: the forward fit writing
+    checkpoints every `seg` entries, then the reverse pass (which recomputes
+    the states inside each segment) and the alignment reduction.  The
+    gradient is taken at zero alignment offsets (the nominal geometry)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    wl = workloads()["align20"]
+    log("generating", wl.name, wl.n_tracks)
+    ev = generate(wl)
+    n = ev.n_tracks
+    dt = torch.float32
+    max_len = int(ev.lengths().max())
+    t = K.event_tensors(ev, dt, dev)
+    geom = K.Geometry.from_toy(wl.geometry)
+    st, cov, q, _ = ctx.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"], wl.geometry.bz, 0)
+    al = torch.zeros(2, wl.geometry.n_layers, dtype=dt, device=dev)
+    ck = torch.empty(28, n * K.n_checkpoint_segments(max_len, seg), dtype=dt, device=dev)
+    out = K.fit_outputs(n, dt, dev)
+    grads = []
+
+    def fwd():
+        ctx.fit_tracks(st, cov, q, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"],
+                       geom, align=al, checkpoints=ck, seg=seg, max_len=max_len, out=out)
+
+    def adj():
+        grads[:] = ctx.fit_adjoint(st, cov, q, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"],
+                                   t["hit_cov"], geom, ck, seg, max_len, out["status"], align=al)
+
+    def step():
+        fwd()
+        adj()
+
+    ms_step = time_loop(step, args.steps, args.warmup)
+    ms_adj = time_loop(adj, args.steps, args.warmup)
+    ms_fwd = time_loop(fwd, args.steps, args.warmup)
+    valid = int(ev.hit_valid.sum())
+    holes = int(ev.n_hits - valid)
+    f_fwd = algorithmic_flops(ev)
+    f_rev = valid * FLOP_VJP_VALID_ENTRY + holes * FLOP_VJP_HOLE_ENTRY
+    tf_step = (f_fwd + f_rev) / (ms_step * 1e-3) / 1e12
+    tf_adj = f_rev / (ms_adj * 1e-3) / 1e12
+    ga = grads[2]
+    return {"tracks": n, "layers": wl.geometry.n_layers, "seg": seg, "ms_step": ms_step,
+            "tracks_per_s": n / (ms_step * 1e-3), "ms_forward_with_checkpoints": ms_fwd, "ms_adjoint": ms_adj,
+            "achieved_tflops_step": tf_step, "frac_fp32_peak_step": tf_step / FP32_PEAK_TFLOPS,
+            "achieved_tflops_adjoint": tf_adj, "frac_fp32_peak_adjoint": tf_adj / FP32_PEAK_TFLOPS,
+            "checkpoint_bytes": ck.numel() * 4, "grad_align_finite": bool(torch.isfinite(ga).all().item())}
+
+
 def profile_only(args, K, tune_fit, generate, workloads):
     """Launch one fit configuration --steps times and nothing else (the
     launch shape comes from the autotune cache when present)."""
@@ -150,6 +205,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 500k-track barrel+endcap workload")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint workload")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "kf_autotune.json"))
     ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32"],
@@ -208,7 +264,7 @@ def main():
     flops = algorithmic_flops(ev)
     achieved_tf = flops / (r32["ms_fit"] * 1e-3) / 1e12
     line = {
-        "metric": "fitted tracks/s (FP32 batched Kalman fit)",
+        "metric": "fitted tracks/s FP32 batched vs plain FP64 GPU at stated error; fwd+adjoint tracks/s",
         "value": n / (r32["ms_step"] * 1e-3),
         "unit": "tracks/s",
         "n_gpus": 1,
@@ -244,6 +300,8 @@ def main():
                                       "tolerance": {"param": 1e-4, "chi2": 1e-3}}
     if not args.no_uneven:
         line["uneven_mixed26"] = bench_uneven(ctx, K, tune_fit, generate, workloads, args)
+    if not args.no_adjoint:
+        line["fwd_adjoint_align20"] = bench_adjoint(ctx, K, generate, workloads, args)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(ev)

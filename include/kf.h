@@ -220,24 +220,37 @@ int kf_score_hits(kf_ctx *ctx, int64_t n, int64_t ld,
                   int32_t *cand_hits, float *cand_score, float *cand_state,
                   uint32_t *trk_status, void *stream);
 
-/* Gradient of L = sum_t w_t chi2_t of kf_fit_tracks (FP32 only, row a8) with
- * respect to the seed states, the hit positions and the per-layer alignment
- * offsets, by a hand-written reverse pass.  The forward states are recomputed
- * segment by segment from the checkpoints written by kf_fit_tracks (same seg,
- * max_len and inputs) instead of being stored for every layer.
- * dL_dchi2[n] = w (NULL = all ones).  Outputs: grad_seed[6][ld],
- * grad_hit_pos[3][n_hits], grad_align[2][n_layers] (overwritten; a
- * deterministic sum over tracks; may be NULL when align is NULL).
- * Inputs as for kf_fit_tracks; trk_status[n] from that call (tracks with
- * NO_CROSSING/NONFINITE/BAD_INPUT contribute only up to their frozen state). */
-int kf_fit_adjoint(kf_ctx *ctx, int64_t n, int64_t ld,
-                   const float *seed_state, const float *seed_cov, const int8_t *seed_charge,
+/* Gradient of L = sum_t w_t chi2_t of kf_fit_tracks (row a8) with respect to
+ * the seed states, the hit positions and the per-layer alignment offsets, by
+ * a hand-written reverse pass (the alignment application the paper's
+ * differentiable fit builds on).  Every entry is reversed in three parts:
+ * the update (whose Joseph form has the short form's derivative at the
+ * optimal gain), the material noise Q(p), and the transport p' = g(p),
+ * C' = F C F^T, where the path length s(p) enters by the implicit-function
+ * rule ds/dp = d, so the crossing solve is not differentiated.  The forward
+ * states are recomputed segment by segment from the checkpoints written by
+ * kf_fit_tracks (same prec, seg, max_len and inputs) instead of being stored
+ * for every entry.  The seed covariance and the hit covariances are
+ * constants of L.
+ * dL_dchi2[n] = w (NULL = all ones).  Outputs (overwritten):
+ * grad_seed[6][ld]; grad_hit_pos[3][n_hits] (0 for holes, entries beyond
+ * max_len and entries after the track stopped); grad_align[2][n_layers] or
+ * NULL: a deterministic sum over barrel hits of (h_x g_y - h_y g_x)/R_l
+ * (r-phi) and g_z (z), with g the hit gradient (disk layers get 0; with
+ * align NULL it is the gradient at zero offsets).
+ * trk_status[n]: the status kf_fit_tracks returned; tracks it stopped
+ * (NO_CROSSING, NONFINITE, bad layer id) contribute only up to the entry
+ * where they stopped.  Uses a context-owned buffer of
+ * 2 * 64 * ceil(n_hits / 4096) values for the alignment reduction (allocated
+ * on first need, KF_ERR_NOMEM if that fails). */
+int kf_fit_adjoint(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                   const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
                    const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
-                   int64_t n_hits, const float *hit_pos, const float *hit_cov,
-                   const kf_geometry *geom, const float *align,
-                   const float *checkpoints, int32_t seg, int32_t max_len,
-                   const float *dL_dchi2,
-                   float *grad_seed, float *grad_hit_pos, float *grad_align,
+                   int64_t n_hits, const void *hit_pos, const void *hit_cov,
+                   const kf_geometry *geom, const void *align,
+                   const void *checkpoints, int32_t seg, int32_t max_len,
+                   const void *dL_dchi2,
+                   void *grad_seed, void *grad_hit_pos, void *grad_align,
                    const uint32_t *trk_status, void *stream);
 
 /* Reserve the workspace of kf_fit_tracks' packed hit layout for up to

@@ -649,15 +649,18 @@ def fit_event(ev, align=None, seed_mode=SEED_FIRST_THREE):
 # --------------------------------------------------------------------------
 
 def fit_gradients(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
-                  align=None, weights=None):
+                  align=None, weights=None, state_round=None):
     """d(sum_t w_t chi2_t)/d(seed state, hit positions, alignment), by autograd
     through fit_tracks (a mechanism independent of any hand-written reverse).
+    state_round is passed to fit_tracks (a conditioning probe: the rounding
+    is the identity for the gradient).
     Returns (loss, g_seed [n,6], g_hits [3,nh], g_align [2,L], fit_out)."""
     sp = _t(seed_p).detach().clone().requires_grad_(True)
     hp = _t(hit_pos).detach().clone().requires_grad_(True)
     L = len(geom.kind)
     al = (torch.zeros(2, L, dtype=DT) if align is None else _t(align)).detach().clone().requires_grad_(True)
-    out = fit_tracks(sp, _t(seed_C), _t(seed_q), hit_offsets, hit_layer, hit_valid, hp, hit_cov, geom, align=al)
+    out = fit_tracks(sp, _t(seed_C), _t(seed_q), hit_offsets, hit_layer, hit_valid, hp, hit_cov, geom, align=al,
+                     state_round=state_round)
     w = torch.ones_like(out["chi2"]) if weights is None else _t(weights)
     loss = (w * out["chi2"]).sum()
     gs, gh, ga = torch.autograd.grad(loss, [sp, hp, al], allow_unused=True)

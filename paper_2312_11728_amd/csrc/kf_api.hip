@@ -25,6 +25,9 @@ struct kf_ctx {
   // workspace of the packed hit layout (kf_reserve)
   void* work_mem = nullptr;
   kf::PackWork work{};
+  // block partials of the alignment-gradient reduction (grown on demand)
+  void* red_mem = nullptr;
+  size_t red_bytes = 0;
 };
 
 namespace {
@@ -142,6 +145,7 @@ int kf_destroy(kf_ctx* c) {
   if (c->capture) hipStreamDestroy(c->capture);
   if (c->d_counter) hipFree(c->d_counter);
   if (c->work_mem) hipFree(c->work_mem);
+  if (c->red_mem) hipFree(c->red_mem);
   hipSetDevice(prev);
   delete c;
   return ok();
@@ -439,11 +443,94 @@ int kf_score_hits(kf_ctx*, int64_t, int64_t, const float*, const float*, const i
   return fail(KF_ERR_UNSUPPORTED, "kf_score_hits: not built yet");
 }
 
-int kf_fit_adjoint(kf_ctx*, int64_t, int64_t, const float*, const float*, const int8_t*, const int32_t*,
-                   const int16_t*, const uint8_t*, int64_t, const float*, const float*, const kf_geometry*,
-                   const float*, const float*, int32_t, int32_t, const float*, float*, float*, float*,
-                   const uint32_t*, void*) {
-  return fail(KF_ERR_UNSUPPORTED, "kf_fit_adjoint: not built yet");
+int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state,
+                   const void* seed_cov, const int8_t* seed_charge, const int32_t* hit_offsets,
+                   const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
+                   const void* hit_cov, const kf_geometry* geom, const void* align, const void* checkpoints,
+                   int32_t seg, int32_t max_len, const void* dL_dchi2, void* grad_seed, void* grad_hit_pos,
+                   void* grad_align, const uint32_t* trk_status, void* stream) {
+  KF_TRY(check_prec(prec));
+  KF_TRY(check_sizes(n, ld));
+  kf::GeomArgs g;
+  KF_TRY(check_geometry(geom, &g));
+  if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
+  if (seg < 1) return fail(KF_ERR_ARG, "seg = %d < 1", seg);
+  if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);
+  KF_REQUIRE(ctx);
+  if (n > 0) {
+    KF_REQUIRE(seed_state);
+    KF_REQUIRE(seed_cov);
+    KF_REQUIRE(seed_charge);
+    KF_REQUIRE(hit_offsets);
+    KF_REQUIRE(hit_layer);
+    KF_REQUIRE(hit_valid);
+    KF_REQUIRE(hit_pos);
+    KF_REQUIRE(hit_cov);
+    KF_REQUIRE(checkpoints);
+    KF_REQUIRE(grad_seed);
+    KF_REQUIRE(grad_hit_pos);
+    KF_REQUIRE(trk_status);
+  } else if (!grad_align) {
+    return ok();
+  }
+  if (grad_align && n_hits > 0) {
+    KF_REQUIRE(hit_layer);
+    KF_REQUIRE(hit_valid);
+    KF_REQUIRE(hit_pos);
+    KF_REQUIRE(grad_hit_pos);
+  }
+  int32_t n_seg = (max_len - 1 + seg - 1) / seg;
+  if (n_seg < 1) n_seg = 1;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t esz = prec == KF_F32 ? 4 : 8;
+  if (grad_align) {
+    const size_t need = size_t(kf::adjoint_partial_blocks(n_hits)) * 2 * kf::kMaxLayers * esz;
+    if (need > ctx->red_bytes) {
+      int prev = 0;
+      hipGetDevice(&prev);
+      hipSetDevice(ctx->device);
+      if (ctx->red_mem) hipFree(ctx->red_mem);
+      ctx->red_mem = nullptr;
+      ctx->red_bytes = 0;
+      hipError_t e = hipMalloc(&ctx->red_mem, need);
+      hipSetDevice(prev);
+      if (e != hipSuccess) {
+        ctx->red_mem = nullptr;
+        return fail(KF_ERR_NOMEM, "kf_fit_adjoint: %zu bytes: %s", need, hipGetErrorString(e));
+      }
+      ctx->red_bytes = need;
+    }
+  }
+  hipError_t e;
+  if (prec == KF_F32) {
+    kf::AdjArgs<float> a;
+    a.f = make_fit_args<float>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, n_hits,
+                               hit_pos, hit_cov, align, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               const_cast<void*>(checkpoints), seg, n_seg, nullptr, nullptr);
+    a.f.max_len = max_len;
+    a.w = (const float*)dL_dchi2;
+    a.fwd_status = trk_status;
+    a.grad_seed = (float*)grad_seed;
+    a.grad_hit = (float*)grad_hit_pos;
+    a.grad_align = (float*)grad_align;
+    a.partial = (float*)ctx->red_mem;
+    e = kf::launch_adjoint(a, g, s);
+  } else {
+    kf::AdjArgs<double> a;
+    a.f = make_fit_args<double>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, n_hits,
+                                hit_pos, hit_cov, align, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                const_cast<void*>(checkpoints), seg, n_seg, nullptr, nullptr);
+    a.f.max_len = max_len;
+    a.w = (const double*)dL_dchi2;
+    a.fwd_status = trk_status;
+    a.grad_seed = (double*)grad_seed;
+    a.grad_hit = (double*)grad_hit_pos;
+    a.grad_align = (double*)grad_align;
+    a.partial = (double*)ctx->red_mem;
+    e = kf::launch_adjoint(a, g, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "kf_fit_adjoint");
+  return ok();
 }
 
 }  // extern "C"

@@ -3,27 +3,10 @@
 // per-track arrays are structure-of-arrays so that a wave's 64 lanes read and
 // write contiguous memory.
 #include "kf_kernels.hpp"
+#include "kf_stage.hpp"
 #include "kf_track.hpp"
 
 namespace kf {
-
-// ---- geometry staged in LDS --------------------------------------------------
-template <typename T>
-struct GeomLds {
-  T pos[kMaxLayers];
-  T x0[kMaxLayers];
-  int kind[kMaxLayers];
-};
-
-template <typename T>
-__device__ __forceinline__ void stage_geometry(GeomLds<T>& sg, const GeomArgs& g) {
-  for (int i = threadIdx.x; i < g.n_layers; i += blockDim.x) {
-    sg.pos[i] = T(g.pos[i]);
-    sg.x0[i] = T(g.x0[i]);
-    sg.kind[i] = g.kind[i];
-  }
-  __syncthreads();
-}
 
 // ---- seeding -----------------------------------------------------------------
 template <typename T>
@@ -119,16 +102,6 @@ hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s) {
 }
 
 // ---- fused per-track layer loop ----------------------------------------------------
-
-template <typename T>
-__device__ __forceinline__ void stage_align(T* sal, const FitArgs<T>& a, const GeomArgs& g) {
-  if (a.align) {
-    for (int i = threadIdx.x; i < g.n_layers; i += blockDim.x) {
-      sal[i] = a.align[i];
-      sal[kMaxLayers + i] = a.align[g.n_layers + i];
-    }
-  }
-}
 
 constexpr int kFitBlock = 256;   // upper bound of the fit kernels' block size
 

@@ -140,4 +140,20 @@ struct FitLaunch {
 template <typename T>
 hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s);
 
+// Reverse pass of the fit (gradient of sum_t w_t chi2_t).
+template <typename T>
+struct AdjArgs {
+  FitArgs<T> f;                // the forward fit's inputs and checkpoints (outputs unused)
+  const T* w;                  // [n] chi2 weights or null (= 1)
+  const uint32_t* fwd_status;  // [n] status of the forward fit
+  T* grad_seed;                // [6][ld]
+  T* grad_hit;                 // [3][n_hits]
+  T* grad_align;               // [2][n_layers] or null
+  T* partial;                  // [adjoint_partial_blocks(n_hits)][2][kMaxLayers] when grad_align is set
+};
+constexpr int kAlignChunk = 4096;  // hits per block of the alignment reduction
+inline int64_t adjoint_partial_blocks(int64_t n_hits) { return (n_hits + kAlignChunk - 1) / kAlignChunk; }
+template <typename T>
+hipError_t launch_adjoint(const AdjArgs<T>& a, const GeomArgs& g, hipStream_t s);
+
 }  // namespace kf

@@ -164,7 +164,8 @@ struct HelixPt {
   T x, y, z, phi;   // position and direction at s
   T sphm, cphm;     // sin, cos of phi
   T dx, dy;         // chord components
-  T u, sh, shc;     // turning angle, sin(u/2), sinc(u/2)
+  T u, sh, ch, shc; // turning angle, sin(u/2), cos(u/2), sinc(u/2)
+  T smid, cmid;     // sin, cos of phi0 + u/2
 };
 
 template <typename T>
@@ -194,7 +195,10 @@ KF_HD inline void helix_eval(const T p[6], T sphi, T cphi, T cot, T w, T s, Heli
   o.cphm = cphi * cos_u - sphi * sin_u;
   o.u = u;
   o.sh = sh;
+  o.ch = ch;
   o.shc = shc;
+  o.smid = smid;
+  o.cmid = cmid;
 }
 
 // Move a helix point by a small extra path ds (first order; used for the
@@ -312,11 +316,21 @@ KF_HD inline void add_q(T c[21], T ipt, T sth, T cot, T var) {
   c[sym(5, 5)] += var;
 }
 
+// Intermediates of one propagation, recorded for the reverse pass.
+template <typename T>
+struct PropTape {
+  T s, w, dw_dipt, sphi, cphi, sth, cth, isth, cot, f1, f2, dxdw, dydw;
+  T G03, G04, G13, G14, G25, G43, inv;
+  T d[6];
+  HelixPt<T> hp;
+};
+
 // Propagate (p, c) to the surface (kind, pos) and add its scattering noise.
-// Returns false (p, c untouched) if there is no admissible crossing.
+// Returns false (p, c untouched) if there is no admissible crossing.  If
+// `tape` is given, the intermediates needed by the reverse pass are stored.
 template <typename T>
 KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool same, bool material, T bz,
-                     T mass, uint32_t& st, T* path = nullptr) {
+                     T mass, uint32_t& st, T* path = nullptr, PropTape<T>* tape = nullptr) {
   const T dw_dipt = -T(q) * T(kCLight) * bz;
   const T w = dw_dipt * p[3];
   T sphi, cphi, sth, cth;
@@ -361,6 +375,31 @@ KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool 
     d[3] = T(0);
     d[4] = T(0);
     d[5] = G25 * inv;
+  }
+  if (tape) {
+    tape->s = s;
+    tape->w = w;
+    tape->dw_dipt = dw_dipt;
+    tape->sphi = sphi;
+    tape->cphi = cphi;
+    tape->sth = sth;
+    tape->cth = cth;
+    tape->isth = isth;
+    tape->cot = cot;
+    tape->f1 = f1;
+    tape->f2 = f2;
+    tape->dxdw = dxdw;
+    tape->dydw = dydw;
+    tape->G03 = G03;
+    tape->G04 = G04;
+    tape->G13 = G13;
+    tape->G14 = G14;
+    tape->G25 = G25;
+    tape->G43 = G43;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) tape->d[i] = d[i];
+    tape->inv = (kind == 0) ? -k_rcp(x * cphm + y * sphm) : -k_rcp(cot);
+    tape->hp = hp;
   }
   // g = d(state)/ds
   const T g0 = cphm, g1 = sphm, g2 = cot, g4 = w;

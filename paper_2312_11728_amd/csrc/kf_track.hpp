@@ -116,6 +116,37 @@ struct PackedTrack {
   }
 };
 
+// One entry of the forward fit: transport to layer `lay` (entry j > 0; the
+// first entry only adds its own layer's material), then, for a valid hit, the
+// alignment correction of the hit (barrel layers: rotation by a_rphi / R about
+// the beam axis and a shift a_z along it) and the update.  m is overwritten
+// with the aligned hit.  Returns false when the crossing fails; c2 is the
+// entry's chi2 contribution (0 for a hole).
+template <typename T>
+KF_HD inline bool step_forward(T p[6], T c[21], int& q, int j, int lay, int prev, bool valid, T m[3], const T V[6],
+                               const TrackGeom<T>& g, const T* __restrict__ sal, T& c2, uint32_t& sst) {
+  const int kind = g.kind[lay];
+  if (j > 0) {
+    if (!propagate(p, c, q, kind, g.pos[lay], g.x0[lay], lay == prev, true, g.bz, g.mass, sst)) return false;
+  } else {
+    add_material_here(p, c, kind, g.x0[lay], g.mass, sst);
+  }
+  c2 = T(0);
+  if (valid) {
+    if (sal && kind == 0) {
+      const T ang = sal[lay] * k_rcp(g.pos[lay]);
+      T sa, ca;
+      k_sincos(ang, &sa, &ca);
+      const T hx = m[0], hy = m[1];
+      m[0] = ca * hx - sa * hy;
+      m[1] = sa * hx + ca * hy;
+      m[2] += sal[kMaxLayers + lay];
+    }
+    update(p, c, q, m, V, c2, sst);
+  }
+  return true;
+}
+
 // Forward fit of track t whose entries are read through `acc` (len entries).
 // sal: alignment staged as [rphi x kMaxLayers][z x kMaxLayers] or null.
 // bk: room for 28 values at bk[k * bk_stride] (k = 0..27) holding the state
@@ -171,27 +202,10 @@ KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
       for (int i = 0; i < 21; ++i) bk[(6 + i) * bk_stride] = c[i];
       const int qq = q;
       uint32_t sst = 0;
-      const int kind = g.kind[lay];
-      if (j > 0) {
-        if (!propagate(p, c, q, kind, g.pos[lay], g.x0[lay], lay == prev, true, g.bz, g.mass, sst)) {
-          st |= sst;
-          break;
-        }
-      } else {
-        add_material_here(p, c, kind, g.x0[lay], g.mass, sst);
-      }
-      T c2 = T(0);
-      if (valid) {
-        if (sal && kind == 0) {
-          const T ang = sal[lay] * k_rcp(g.pos[lay]);
-          T sa, ca;
-          k_sincos(ang, &sa, &ca);
-          const T hx = m[0], hy = m[1];
-          m[0] = ca * hx - sa * hy;
-          m[1] = sa * hx + ca * hy;
-          m[2] += sal[kMaxLayers + lay];
-        }
-        update(p, c, q, m, V, c2, sst);
+      T c2;
+      if (!step_forward(p, c, q, j, lay, prev, valid, m, V, g, sal, c2, sst)) {
+        st |= sst;
+        break;
       }
       if (!all_finite(p, c, c2)) {
         st |= sst | TRK_NONFINITE;

@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(HERE, "libkf.so")
 
 KF_OK, KF_ERR_ARG, KF_ERR_DEVICE, KF_ERR_NOMEM, KF_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 KF_F32, KF_F64 = 0, 1
+# per-track status bits (kf_status of include/kf.h)
+(KF_TRK_NO_CROSSING, KF_TRK_GRAZING, KF_TRK_NONFINITE, KF_TRK_FP64_FALLBACK, KF_TRK_CHARGE_FLIP, KF_TRK_COV_NOT_PSD,
+ KF_TRK_BAD_INPUT) = 1, 2, 4, 8, 16, 32, 64
 TRK_NO_CROSSING, TRK_GRAZING, TRK_NONFINITE, TRK_FP64_FALLBACK = 1, 2, 4, 8
 TRK_CHARGE_FLIP, TRK_COV_NOT_PSD, TRK_BAD_INPUT = 16, 32, 64
 MAX_LAYERS = 64
@@ -66,7 +69,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   ctypes.POINTER(KfGeometry), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp]
     lib.kf_score_hits.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(KfGeometry),
                                   ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
-    lib.kf_fit_adjoint.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
+    lib.kf_fit_adjoint.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                    ctypes.POINTER(KfGeometry), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_set_fit_launch.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i32, _i32, _i32]
     lib.kf_get_fit_launch.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
@@ -266,6 +269,87 @@ class Context:
                                    _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(checkpoints), int(seg), int(max_len),
                                    _ptr(out["status"]), _stream(dev)))
         return out
+
+
+    def fit_adjoint(self, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov,
+                    geom: Geometry, checkpoints, seg, max_len, fwd_status, align=None, dL_dchi2=None,
+                    want_align=True):
+        """Reverse pass of fit_tracks (kf_fit_adjoint): returns (grad_seed [6, n],
+        grad_hit_pos [3, n_hits], grad_align [2, n_layers] or None).  The inputs,
+        seg and max_len must be those of the fit_tracks call that wrote
+        `checkpoints` and `fwd_status`."""
+        dev = self.device
+        dt = seed_state.dtype
+        n = seed_state.shape[1]
+        _need(seed_state, "seed_state", dt, dev, rows=6)
+        _need(seed_cov, "seed_cov", dt, dev, rows=21)
+        _need(seed_charge, "seed_charge", torch.int8, dev)
+        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need(hit_layer, "hit_layer", torch.int16, dev)
+        _need(hit_valid, "hit_valid", torch.uint8, dev)
+        _need(hit_pos, "hit_pos", dt, dev, rows=3)
+        _need(hit_cov, "hit_cov", dt, dev, rows=6)
+        _need(checkpoints, "checkpoints", dt, dev, rows=28)
+        _need(fwd_status, "fwd_status", torch.int32, dev)
+        if align is not None:
+            _need(align, "align", dt, dev, rows=2)
+        if dL_dchi2 is not None:
+            _need(dL_dchi2, "dL_dchi2", dt, dev)
+        gs = torch.empty(6, n, dtype=dt, device=dev)
+        gh = torch.empty(3, hit_pos.shape[1], dtype=dt, device=dev)
+        ga = torch.empty(2, geom.n_layers, dtype=dt, device=dev) if want_align else None
+        _check(lib().kf_fit_adjoint(self.handle, _prec(dt), n, seed_state.stride(0), _ptr(seed_state),
+                                    _ptr(seed_cov), _ptr(seed_charge), _ptr(hit_offsets), _ptr(hit_layer),
+                                    _ptr(hit_valid), hit_pos.shape[1], _ptr(hit_pos), _ptr(hit_cov),
+                                    ctypes.byref(geom.struct), _ptr(align), _ptr(checkpoints), int(seg),
+                                    int(max_len), _ptr(dL_dchi2), _ptr(gs), _ptr(gh), _ptr(ga), _ptr(fwd_status),
+                                    _stream(dev)))
+        return gs, gh, ga
+
+
+class KfFit(torch.autograd.Function):
+    """chi2 of the forward fit as a differentiable function of the seed states
+    [6, n], the hit positions [3, n_hits] and the alignment offsets
+    [2, n_layers]: forward = kf_fit_tracks with checkpoints every `seg` entries,
+    backward = kf_fit_adjoint (the states are recomputed from the checkpoints).
+    The other inputs are constants.  Returns (chi2 [n], state, cov, charge, ndf,
+    status) as fit_tracks does; only chi2 carries a gradient."""
+
+    @staticmethod
+    def forward(fctx, seed_state, hit_pos, align, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_cov,
+                geom, kctx, seg, max_len):
+        n = seed_state.shape[1]
+        ck = torch.empty(28, n * n_checkpoint_segments(max_len, seg), dtype=seed_state.dtype,
+                         device=seed_state.device)
+        out = kctx.fit_tracks(seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_pos,
+                              hit_cov, geom, align=align, checkpoints=ck, seg=seg, max_len=max_len)
+        fctx.save_for_backward(seed_state, hit_pos, align if align is not None else torch.empty(0), seed_cov,
+                               seed_charge, hit_offsets, hit_layer, hit_valid, hit_cov, ck, out["status"])
+        fctx.has_align = align is not None
+        fctx.geom, fctx.kctx, fctx.seg, fctx.max_len = geom, kctx, seg, max_len
+        rest = (out["state"], out["cov"], out["charge"], out["ndf"], out["status"])
+        fctx.mark_non_differentiable(*rest)
+        return (out["chi2"],) + rest
+
+    @staticmethod
+    def backward(fctx, g_chi2, *unused):
+        (seed_state, hit_pos, align, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_cov, ck,
+         status) = fctx.saved_tensors
+        al = align if fctx.has_align else None
+        want_align = fctx.needs_input_grad[2]
+        gs, gh, ga = fctx.kctx.fit_adjoint(seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
+                                           hit_pos, hit_cov, fctx.geom, ck, fctx.seg, fctx.max_len, status,
+                                           align=al, dL_dchi2=g_chi2.contiguous(), want_align=want_align)
+        return (gs, gh, ga if want_align else None) + (None,) * 10
+
+
+def fit_chi2(kctx, seed_state, hit_pos, align, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_cov,
+             geom, seg=5, max_len=26):
+    """Differentiable fit (see KfFit); returns (chi2, fit outputs dict)."""
+    chi2, state, cov, charge, ndf, status = KfFit.apply(seed_state, hit_pos, align, seed_cov, seed_charge,
+                                                        hit_offsets, hit_layer, hit_valid, hit_cov, geom, kctx, seg,
+                                                        max_len)
+    return chi2, dict(state=state, cov=cov, charge=charge, chi2=chi2.detach(), ndf=ndf, status=status)
 
 
 def fit_outputs(n, dtype, device):

@@ -5,7 +5,7 @@ stated tolerances.
 Tolerances (parameters and chi2, FP32 path):
   |dp_i| <= 1e-4 * max(|p_i|, s_i), s = (1 cm, 1 cm, 1 cm, 0.1 c/GeV, 1 rad, 1 rad)
   |dchi2| <= 1e-3 * max(chi2, 1)
-The FP64 GPU path is held to 1e-9 on the same scales.
+The FP64 GPU path is held to 1e-8 on the same scales.
 
 Conditioning: a track whose FP64 result moves by more than half the tolerance
 when its hit positions are perturbed at the FP32 rounding level (one unit in

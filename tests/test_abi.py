@@ -99,3 +99,32 @@ def test_other_entry_points_validate():
     assert lib.kf_set_fit_launch(P, 0, 128, 0, 4, 1, 3) == kf.KF_ERR_ARG
     assert lib.kf_reserve(P, -1, 26) == kf.KF_ERR_ARG
     assert lib.kf_reserve(P, 10, 65) == kf.KF_ERR_ARG
+
+
+def _adj_call(**over):
+    args = dict(ctx=P, prec=kf.KF_F32, n=10, ld=10, seed_state=P, seed_cov=P, seed_charge=P, hit_offsets=P,
+                hit_layer=P, hit_valid=P, n_hits=100, hit_pos=P, hit_cov=P, geom=ctypes.byref(_geom().struct),
+                align=None, checkpoints=P, seg=4, max_len=26, dL_dchi2=None, grad_seed=P, grad_hit_pos=P,
+                grad_align=None, trk_status=P, stream=None)
+    args.update(over)
+    return kf.lib().kf_fit_adjoint(*args.values())
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(n=-1), "n = -1"),
+    (dict(prec=3), "precision 3"),
+    (dict(seg=0), "seg = 0"),
+    (dict(max_len=65), "max_len = 65"),
+    (dict(checkpoints=None), "checkpoints is NULL"),
+    (dict(grad_seed=None), "grad_seed is NULL"),
+    (dict(grad_hit_pos=None), "grad_hit_pos is NULL"),
+    (dict(trk_status=None), "trk_status is NULL"),
+    (dict(ctx=None), "ctx is NULL"),
+])
+def test_fit_adjoint_argument_validation(over, msg):
+    assert _adj_call(**over) == kf.KF_ERR_ARG
+    assert msg in kf.lib().kf_last_error().decode()
+
+
+def test_fit_adjoint_empty_batch_is_a_no_op():
+    assert _adj_call(n=0, ld=0, seed_state=None, grad_seed=None, grad_hit_pos=None, checkpoints=None) == kf.KF_OK
