@@ -180,39 +180,57 @@ int kf_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                   void *checkpoints, int32_t seg, int32_t max_len,
                   uint32_t *trk_status, void *stream);
 
-/* Combinatorial chi2 scoring of candidate hits (row a7): see the definition
- * of kf_search_params and kf_score_hits below. */
+/* Parameters of the combinatorial candidate search (kf_score_hits).  The
+ * paper makes the window, the chi2 cut, the missed-layer limit and the
+ * candidate score per-iteration parameters and standard functions (Sec. 3.2,
+ * 3.3); these are the ones this search takes. */
 typedef struct {
-  int32_t beam;          /* candidates kept per seed (<= 8) */
-  float chi2_max;        /* hits with chi2 above this are rejected */
-  float n_sigma;         /* window half-width in predicted standard deviations */
-  float hit_bonus;       /* score added per accepted hit (score = parent + bonus - chi2) */
-  float miss_penalty;    /* score subtracted for a layer with no accepted hit */
-  int32_t max_miss;      /* candidates with more misses are dropped */
-  float sigma_rphi, sigma_z;  /* hit resolutions added to the window */
-  const float *win_min_rphi, *win_max_rphi, *win_min_z, *win_max_z; /* [n_layers], HOST */
+  int32_t beam;          /* candidates kept per seed, 1..8 */
+  float chi2_max;        /* a hit is accepted iff its chi2 <= chi2_max (> 0) */
+  float n_sigma;         /* window half-width in predicted standard deviations (> 0) */
+  float hit_bonus;       /* child score = parent score + hit_bonus - chi2 */
+  float miss_penalty;    /* miss child score = parent score - miss_penalty (>= 0) */
+  int32_t max_miss;      /* a candidate with this many misses gets no miss child (0..100) */
+  float sigma_rphi, sigma_z;  /* nominal hit resolution added to the window (cm, >= 0) */
+  const float *win_min_rphi, *win_max_rphi, *win_min_z, *win_max_z; /* [n_layers] cm, HOST, 0 < min <= max */
 } kf_search_params;
 
-/* For every seed, run the per-layer candidate search over the layer plan
- * (barrel layers only): each live candidate is propagated to the layer and
- * gets its material; its window is w = clamp(n_sigma * sqrt(var + sigma^2),
- * win_min, win_max) in r-phi (dphi = w/R) and z; every pool hit inside the
- * window gets its chi2; hits with chi2 <= chi2_max become children scored
- * parent + hit_bonus - chi2; a candidate with no accepted hit gets one miss
- * child scored parent - miss_penalty (dropped beyond max_miss misses).  Per
- * seed the children are ranked by (score desc, hit id asc with a miss after
- * every hit, parent rank asc) and the best `beam` are kept and updated with
- * their hits.
- * Seeds: seed_state[6][ld], seed_cov[21][ld], seed_charge[n] (states on the
- * layer before the plan).  layer_plan[plan_len] (HOST).
- * Pools: pool_layer_offsets[n_layers+1] (HOST), pool_pos[3][n_pool],
- * pool_cov[6][n_pool], pool_hit_id[n_pool] (device; ids are what the output
- * reports and what breaks ties).
- * Outputs: cand_hits[n][beam][plan_len] (hit id, -1 = miss, -2 = no such
- * candidate), cand_score[n][beam], cand_state[6][ld*beam] (may be NULL),
- * trk_status[n] (overwritten). */
+/* Combinatorial candidate search with chi2 scoring of the candidate hits
+ * (row a7; the forward search of Sec. 2.2 over a layer plan, Sec. 3.1), FP32.
+ * Every seed starts with one candidate (score 0).  For each layer L of
+ * layer_plan (barrel layers), each live candidate is propagated to L with its
+ * material (kf_propagate's crossing rule; a candidate without a crossing ends)
+ * and opens the window
+ *   w_rphi = clamp(n_sigma sqrt(t^T C_pos t + sigma_rphi^2), win_min_rphi[L], win_max_rphi[L]),
+ *   w_z    = clamp(n_sigma sqrt(C_zz + sigma_z^2), win_min_z[L], win_max_z[L]),
+ * t the transverse tangent of the layer at the predicted point; a pool hit of
+ * L is inside iff |wrap(phi_hit - phi_pred)| <= w_rphi / R_L and
+ * |z_hit - z_pred| <= w_z.  Each hit inside with chi2 <= chi2_max (the update's
+ * chi2) gives a child scored parent + hit_bonus - chi2; a candidate with no
+ * accepted hit gives one miss child scored parent - miss_penalty unless it has
+ * max_miss misses already.  Per seed the children are ranked by (score
+ * descending, hit id ascending with a miss after every hit, parent rank
+ * ascending), the first `beam` are kept (their order is their rank) and the
+ * kept ones with a hit get the Kalman update (kf_update) with it.
+ * Seeds: seed_state[6][ld], seed_cov[21][ld], seed_charge[n], seed_layer[n]
+ * (the layer each seed state is on; device).  layer_plan[plan_len] (HOST,
+ * 1 <= plan_len <= 64).
+ * Pool: pool_layer_offsets[n_layers + 1] (HOST; layer l owns hits
+ * [off[l], off[l+1]), off[0] = 0, off[n_layers] = n_pool < 2^31),
+ * pool_pos[3][n_pool], pool_cov[6][n_pool], pool_hit_id[n_pool] (device; the
+ * ids, which must be distinct, are what the output reports and what breaks
+ * ties).  The call bins the pool by (layer, phi, z) into a context-owned
+ * workspace (about 64 bytes per pool hit and per candidate slot; grown on
+ * demand, KF_ERR_NOMEM if that fails).
+ * Outputs: cand_hits[n][beam][plan_len] (hit id, -1 = miss; -2 for every
+ * entry of a rank the seed has no candidate for), cand_score[n][beam]
+ * (-inf for none), cand_state[6][n*beam] (column seed*beam + rank; the final
+ * state after the last update; NaN for none; may be NULL), trk_status[n]
+ * (overwritten: OR of the status bits of the seed's propagations and
+ * updates).  n = 0 is a no-op. */
 int kf_score_hits(kf_ctx *ctx, int64_t n, int64_t ld,
                   const float *seed_state, const float *seed_cov, const int8_t *seed_charge,
+                  const int16_t *seed_layer,
                   const int16_t *layer_plan, int32_t plan_len,
                   const kf_geometry *geom, const kf_search_params *params,
                   const int32_t *pool_layer_offsets, int64_t n_pool,

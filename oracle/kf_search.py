@@ -1,0 +1,375 @@
+"""FP64 CPU oracle of the combinatorial candidate search (kf_score_hits).
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module; it shares no code with the HIP
+kernels.
+
+What the paper fixes (Sec. 2.2, forward search; Sec. 3.1, layers and layer
+plans): each seed proceeds outwards layer by layer along a layer plan; every
+candidate is propagated to the layer, the layer's hits compatible with it are
+selected, and the Kalman-filter calculations are done for them; a seed keeps
+at most a fixed number of concurrent candidates, a candidate may miss a
+limited number of layers, and the best-scoring candidate represents the seed.
+The window, the chi2 cut, the score function and the tie-break are
+per-iteration parameters and standard functions that the paper does not
+spell out (Sec. 3.2, 3.3).  Readings taken here, step by step, for every
+layer L of the plan and every live candidate of a seed:
+
+1. Propagate the candidate (state and covariance, with the layer's material)
+   to layer L (kf_oracle.propagate; `same` = the candidate is on L already).
+   A candidate without a crossing stops (see below).
+2. Window around the predicted point (x, y, z), phi_p = atan2(y, x):
+     w_rphi = clamp(n_sigma sqrt(t^T C_pos t + sigma_rphi^2), win_min_rphi, win_max_rphi)
+     w_z    = clamp(n_sigma sqrt(C_zz + sigma_z^2),            win_min_z,    win_max_z)
+   with t = (-sin phi_p, cos phi_p, 0) the transverse tangent of the layer.
+   A pool hit of layer L is inside iff |wrap(phi_h - phi_p)| <= w_rphi / R_L
+   and |z_h - z_p| <= w_z, phi_h = atan2(y_h, x_h).
+3. chi2 of every hit inside (the update's r^T S^-1 r, no update); the hit is
+   accepted iff chi2 <= chi2_max.
+4. Children: one per accepted hit with score = parent score + hit_bonus -
+   chi2.  If no hit is accepted, one miss child with score = parent score -
+   miss_penalty, unless the parent has already missed max_miss layers: then
+   the candidate stops.
+5. Per seed, all children of all its candidates are ranked by (score
+   descending; then hit id ascending, a miss after every hit and a stop
+   after a miss; then parent rank ascending) and the first `beam` are kept,
+   in that order (their ranks).
+6. A kept child with a hit gets the Kalman update with it (kf_oracle.update);
+   a miss child keeps the propagated state.
+
+Stopping (the search ends for a candidate at the tracker edge or when no
+more hits are found, Sec. 2.2): a candidate that stops keeps its score and
+the state it entered the layer with, and from then on has, at every layer,
+exactly one child -- itself, marked STOP (-3) in the hit list -- which
+competes in the ranking like any other child.
+
+A seed starts with one candidate (rank 0, score 0, no misses) holding the
+seed state, on the seed's layer.
+
+Several results are correct where FP32 and FP64 rounding can decide
+differently.  The oracle therefore flags a seed when any of its decisions is
+near, against an error model of FP32 at that decision:
+* position: a point at radius R predicted in FP32 is off by about
+  4 ulp32(R) (1 + 1/|cos a|) along the layer, a the incidence angle (the
+  crossing of a cylinder is resolved only to ulp/|cos a| near tangency);
+* chi2 of one hit: 2 sqrt(chi2 + 1) (position error) / s_r
+  + (1e-4 + COND_K eps32 kappa(S)) chi2, with s_r = sqrt(t^T C_pos t +
+  sigma_rphi^2) the residual's r-phi spread and kappa(S) the condition number
+  of the residual covariance (near a tangent crossing the predicted position
+  is spread along the layer, S is nearly singular and its FP32 form resolves
+  the small eigenvalue only to eps32 kappa);
+* window edge: a pool hit within EDGE_REL w + (position error) of an edge;
+* chi2 cut: a chi2 within the chi2 error (at the cut) of chi2_max;
+* ranking: two children adjacent in the ranking at positions up to `beam`
+  (order inside the kept set and the cut after it) whose scores differ by a
+  non-zero amount of at most the summed chi2 errors of the terms in which
+  they differ.  Two children whose histories agree up to some layer share
+  the score of that common ancestor (in any precision the same computed
+  value), so only the terms since they diverged count.  Exactly equal scores
+  are near too, unless every term since the divergence takes identical hits
+  (same position and covariance: a duplicated hit) or a miss or stop in both:
+  such a tie holds in every precision and step 5 breaks it the same way.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import kf_oracle as O
+
+MISS = -1        # hit id of a miss in the output
+NO_CAND = -2     # hit id where the seed has no candidate of that rank
+STOP = -3        # hit id of the layers after a candidate stopped
+_KEY = {MISS: np.iinfo(np.int64).max - 1, STOP: np.iinfo(np.int64).max}
+EDGE_REL = 1e-4      # relative error of a window half-width
+CHI2_REL = 1e-4      # relative error of a chi2 from the covariance
+ULP_FACTOR = 1.0     # FP32 position error in units of ulp32(R)
+RANK_SIGMAS = 3.0    # score margin: this many root-sum-squares of the term errors
+
+
+def ulp32(x):
+    x = np.float32(abs(x))
+    return float(np.spacing(x))
+
+
+def pos_error(R, cos_a):
+    """FP32 error of a predicted point at radius R along the layer."""
+    return ULP_FACTOR * ulp32(R) * (1.0 + 1.0 / max(abs(cos_a), 1e-6))
+
+
+COND_K = 4.0        # chi2 relative error per unit of eps32 * kappa(S)
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+def chi2_error(chi2, epos, sigma, kappa=1.0):
+    return 2.0 * math.sqrt(max(chi2, 0.0) + 1.0) * epos / sigma + (CHI2_REL + COND_K * EPS32 * kappa) * chi2
+
+
+@dataclasses.dataclass
+class SearchParams:
+    """Parameters of the search (defaults: the 20-layer barrel workload)."""
+    n_layers: int
+    beam: int = 6
+    chi2_max: float = 30.0
+    n_sigma: float = 5.0
+    hit_bonus: float = 10.0
+    miss_penalty: float = 5.0
+    max_miss: int = 3
+    win_min_rphi: np.ndarray = None   # [n_layers] cm
+    win_max_rphi: np.ndarray = None
+    win_min_z: np.ndarray = None
+    win_max_z: np.ndarray = None
+    sigma_rphi: np.ndarray = None     # [n_layers] nominal hit resolution, cm
+    sigma_z: np.ndarray = None
+
+    def __post_init__(self):
+        L = self.n_layers
+        d = dict(win_min_rphi=0.01, win_max_rphi=2.0, win_min_z=0.03, win_max_z=2.0, sigma_rphi=0.003, sigma_z=0.01)
+        for k, v in d.items():
+            if getattr(self, k) is None:
+                setattr(self, k, np.full(L, v))
+            else:
+                setattr(self, k, np.asarray(getattr(self, k), np.float64))
+
+
+def _wrap(a):
+    return a - 2.0 * math.pi * np.ceil((a - math.pi) / (2.0 * math.pi))
+
+
+class _LayerPool:
+    """Hits of one layer sorted by phi for window queries."""
+
+    def __init__(self, pos, cov, ids):
+        phi = np.arctan2(pos[1], pos[0])
+        o = np.argsort(phi, kind="stable")
+        self.phi = phi[o]
+        self.pos = pos[:, o]
+        self.cov = cov[:, o]
+        self.ids = ids[o]
+
+    def query(self, phi_c, half):
+        """Indices of hits with |wrap(phi - phi_c)| <= half (half < pi)."""
+        lo, hi = phi_c - half, phi_c + half
+        segs = []
+        if lo < -math.pi:
+            segs.append((lo + 2 * math.pi, math.pi))
+            lo = -math.pi
+        if hi > math.pi:
+            segs.append((-math.pi, hi - 2 * math.pi))
+            hi = math.pi
+        segs.append((lo, hi))
+        idx = [np.arange(np.searchsorted(self.phi, a, "left"), np.searchsorted(self.phi, b, "right")) for a, b in segs]
+        return np.unique(np.concatenate(idx))
+
+
+def _chi2(p_pos, C_pos, m, V6):
+    """r^T (C_pos + V)^-1 r for hits m [k, 3] with packed covariances V6 [6, k],
+    and the condition number of each C_pos + V."""
+    k = m.shape[0]
+    V = np.zeros((k, 3, 3))
+    il = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+    for c, (i, j) in enumerate(il):
+        V[:, i, j] = V[:, j, i] = V6[c]
+    S = C_pos[None] + V
+    r = m - p_pos[None]
+    ev = np.linalg.eigvalsh(S)
+    return np.einsum("ni,nij,nj->n", r, np.linalg.inv(S), r), ev[:, -1] / ev[:, 0]
+
+
+def _round(p, C, dtype):
+    return p.to(dtype).to(torch.float64), C.to(dtype).to(torch.float64)
+
+
+def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams, state_round=None):
+    """Run the search.  seed_p [n, 6], seed_C [n, 6, 6], seed_q [n], seed_layer
+    [n] (layer index the seed state is on), layer_plan: layer indices in
+    order, geom: a detector Geometry (barrel layers), pools: object with
+    layer_offsets [L+1], pos [3, np], cov [6, np], hit_id [np].
+    state_round: None, or a dtype for the conditioning probe.
+    Returns dict(hits [n, beam, P] int64, score [n, beam], p [n, beam, 6],
+    C [n, beam, 6, 6], status [n], flagged [n] bool, flags [n] (near
+    decisions: 1 window edge, 2 chi2 cut, 4 ranking), score_err [n, beam]
+    (root-sum-square of the FP32 error model over the candidate's terms),
+    n_window_hits)."""
+    seed_p = np.asarray(seed_p, np.float64)
+    seed_C = np.asarray(seed_C, np.float64)
+    n, B, P = seed_p.shape[0], prm.beam, len(layer_plan)
+    lp = {}
+    for L in set(int(x) for x in layer_plan):
+        a, b = int(pools.layer_offsets[L]), int(pools.layer_offsets[L + 1])
+        lp[L] = _LayerPool(np.asarray(pools.pos[:, a:b], np.float64), np.asarray(pools.cov[:, a:b], np.float64),
+                           np.asarray(pools.hit_id[a:b], np.int64))
+    # live candidates: parallel lists
+    c_seed = list(range(n))
+    c_rank = [0] * n
+    c_p = [seed_p[i] for i in range(n)]
+    c_C = [seed_C[i] for i in range(n)]
+    c_q = [float(seed_q[i]) for i in range(n)]
+    c_score = [0.0] * n
+    c_miss = [0] * n
+    c_layer = [int(seed_layer[i]) for i in range(n)]
+    c_hist = [[] for _ in range(n)]
+    c_err = [[] for _ in range(n)]   # FP32 error of each score term
+    where = {}   # hit id -> index into pools, for comparing the inputs of exact ties
+
+    def _same_input(x, y):
+        if x == y:
+            return True
+        if x < 0 or y < 0:
+            return False
+        if not where:
+            where.update({int(h): k for k, h in enumerate(np.asarray(pools.hit_id))})
+        i, j = where[int(x)], where[int(y)]
+        return bool(np.array_equal(pools.pos[:, i], pools.pos[:, j]) and np.array_equal(pools.cov[:, i], pools.cov[:, j]))
+
+    status = np.zeros(n, np.int64)
+    flags = np.zeros(n, np.int64)   # near decisions: 1 window edge, 2 chi2 cut, 4 ranking
+    n_window = 0
+    c_stop = [False] * n
+    for step, L in enumerate(layer_plan):
+        L = int(L)
+        m = len(c_seed)
+        if m == 0:
+            break
+        R = float(geom.pos[L])
+        live = [i for i in range(m) if not c_stop[i]]
+        p2 = np.zeros((m, 6))
+        C2 = np.zeros((m, 6, 6))
+        st = np.zeros(m, np.int64)
+        if live:
+            k_ = len(live)
+            pp, CC, _, ss = O.propagate(torch.tensor(np.stack([c_p[i] for i in live])),
+                                        torch.tensor(np.stack([c_C[i] for i in live])),
+                                        torch.tensor([c_q[i] for i in live], dtype=torch.float64),
+                                        torch.full((k_,), int(geom.kind[L]), dtype=torch.int64),
+                                        torch.full((k_,), R, dtype=torch.float64),
+                                        torch.full((k_,), float(geom.x_over_x0[L]), dtype=torch.float64), geom,
+                                        same=torch.tensor([c_layer[i] == L for i in live]))
+            if state_round is not None:
+                pp, CC = _round(pp, CC, state_round)
+            p2[live], C2[live], st[live] = pp.numpy(), CC.numpy(), ss.numpy()
+        children = {}
+        pool = lp[L]
+        for i in range(m):
+            s = c_seed[i]
+            stop_child = (c_score[i], STOP, c_rank[i], i, -1, 0.0)
+            if c_stop[i]:
+                children.setdefault(s, []).append(stop_child)
+                continue
+            status[s] |= st[i]
+            if st[i] & O.NO_CROSSING:
+                children.setdefault(s, []).append(stop_child)
+                continue
+            x, y, z = p2[i, 0], p2[i, 1], p2[i, 2]
+            phi_p = math.atan2(y, x)
+            cos_a = math.sin(p2[i, 5]) * (math.cos(p2[i, 4]) * x + math.sin(p2[i, 4]) * y) / math.hypot(x, y)
+            epos = pos_error(R, cos_a)
+            t = np.array([-math.sin(phi_p), math.cos(phi_p), 0.0])
+            Cp = C2[i, :3, :3]
+            w_r = min(max(prm.n_sigma * math.sqrt(t @ Cp @ t + prm.sigma_rphi[L] ** 2), prm.win_min_rphi[L]),
+                      prm.win_max_rphi[L])
+            w_z = min(max(prm.n_sigma * math.sqrt(Cp[2, 2] + prm.sigma_z[L] ** 2), prm.win_min_z[L]), prm.win_max_z[L])
+            # hits up to the edge margin beyond the window, for the near-decision flags
+            mr = EDGE_REL * w_r + epos
+            mz = EDGE_REL * w_z + epos
+            cand = pool.query(phi_p, (w_r + mr) / R)
+            if cand.size:
+                dz = np.abs(pool.pos[2, cand] - z)
+                cand = cand[dz <= w_z + mz]
+            kids = []
+            if cand.size:
+                darc = np.abs(_wrap(pool.phi[cand] - phi_p)) * R
+                dz = np.abs(pool.pos[2, cand] - z)
+                if (np.abs(darc - w_r) <= mr).any() or (np.abs(dz - w_z) <= mz).any():
+                    flags[s] |= 1
+                inside = cand[(darc <= w_r) & (dz <= w_z)]
+                n_window += int(inside.size)
+                if inside.size:
+                    chi2, kap = _chi2(p2[i, :3], Cp, pool.pos[:, inside].T, pool.cov[:, inside])
+                    sig = math.sqrt(t @ Cp @ t + prm.sigma_rphi[L] ** 2)
+                    for c2, kp in zip(chi2, kap):
+                        if abs(c2 - prm.chi2_max) <= chi2_error(prm.chi2_max, epos, sig, kp):
+                            flags[s] |= 2
+                    for h, c2, kp in zip(inside, chi2, kap):
+                        if c2 <= prm.chi2_max:
+                            kids.append((c_score[i] + prm.hit_bonus - c2, int(pool.ids[h]), c_rank[i], i, int(h),
+                                         chi2_error(c2, epos, sig, kp)))
+            if not kids:
+                if c_miss[i] < prm.max_miss:
+                    kids.append((c_score[i] - prm.miss_penalty, MISS, c_rank[i], i, -1, 0.0))
+                else:
+                    kids.append(stop_child)
+            children.setdefault(s, []).extend(kids)
+        # ranking and selection per seed
+        n_p, n_C, n_q, n_score, n_miss, n_hist, n_seed, n_rank, n_err, n_stop = [], [], [], [], [], [], [], [], [], []
+        upd = []
+        for s in sorted(children):
+            kids = children[s]
+            kids.sort(key=lambda k: (-k[0], _KEY.get(k[1], k[1]), k[2]))
+            for a in range(min(B, len(kids) - 1)):
+                ka, kb = kids[a], kids[a + 1]
+                d = abs(ka[0] - kb[0])
+                ha, hb = c_hist[ka[3]] + [ka[1]], c_hist[kb[3]] + [kb[1]]
+                ea, eb = c_err[ka[3]] + [ka[5]], c_err[kb[3]] + [kb[5]]
+                d0 = next((k for k in range(len(ha)) if ha[k] != hb[k]), len(ha))
+                if d == 0.0:
+                    if not all(_same_input(x, y) for x, y in zip(ha[d0:], hb[d0:])):
+                        flags[s] |= 4
+                elif d <= RANK_SIGMAS * math.sqrt(sum(e * e for e in ea[d0:] + eb[d0:])):
+                    flags[s] |= 4
+            for r, (sc, hid, prank, i, h, err) in enumerate(kids[:B]):
+                n_seed.append(s)
+                n_rank.append(r)
+                n_score.append(sc)
+                n_miss.append(c_miss[i] + (1 if hid == MISS else 0))
+                n_hist.append(c_hist[i] + [hid])
+                n_err.append(c_err[i] + [err])
+                n_stop.append(hid == STOP)
+                if hid == STOP:
+                    # the state it entered the layer with (unchanged after a stop)
+                    n_p.append(c_p[i])
+                    n_C.append(c_C[i])
+                else:
+                    n_p.append(p2[i])
+                    n_C.append(C2[i])
+                n_q.append(c_q[i])
+                if hid >= 0:
+                    upd.append((len(n_p) - 1, h))
+        if upd:
+            k = [u[0] for u in upd]
+            hs = np.array([u[1] for u in upd])
+            il = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+            V = np.zeros((len(k), 3, 3))
+            for c, (a, b) in enumerate(il):
+                V[:, a, b] = V[:, b, a] = pool.cov[c, hs]
+            pu, Cu, qu, _, su = O.update(torch.tensor(np.stack([n_p[j] for j in k])),
+                                         torch.tensor(np.stack([n_C[j] for j in k])),
+                                         torch.tensor([n_q[j] for j in k], dtype=torch.float64),
+                                         torch.tensor(pool.pos[:, hs].T), torch.tensor(V))
+            if state_round is not None:
+                pu, Cu = _round(pu, Cu, state_round)
+            for a, j in enumerate(k):
+                n_p[j] = pu[a].numpy()
+                n_C[j] = Cu[a].numpy()
+                n_q[j] = float(qu[a])
+                status[n_seed[j]] |= int(su[a])
+        c_seed, c_rank, c_p, c_C, c_q = n_seed, n_rank, n_p, n_C, n_q
+        c_score, c_miss, c_hist, c_err, c_stop = n_score, n_miss, n_hist, n_err, n_stop
+        c_layer = [L] * len(c_seed)
+    hits = np.full((n, B, P), NO_CAND, np.int64)
+    score = np.full((n, B), -np.inf)
+    pout = np.full((n, B, 6), np.nan)
+    Cout = np.full((n, B, 6, 6), np.nan)
+    serr = np.zeros((n, B))
+    for j, s in enumerate(c_seed):
+        r = c_rank[j]
+        h = c_hist[j]
+        hits[s, r, :len(h)] = h
+        score[s, r] = c_score[j]
+        pout[s, r] = c_p[j]
+        Cout[s, r] = c_C[j]
+        serr[s, r] = math.sqrt(sum(e * e for e in c_err[j]))
+    return dict(hits=hits, score=score, p=pout, C=Cout, status=status, flagged=flags != 0, flags=flags,
+                score_err=serr, n_window_hits=n_window)

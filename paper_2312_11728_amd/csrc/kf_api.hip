@@ -8,9 +8,12 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "kf.h"
 #include "kf_kernels.hpp"
+#include "kf_search_launch.hpp"
 
 struct kf_ctx {
   int device = 0;
@@ -28,6 +31,9 @@ struct kf_ctx {
   // block partials of the alignment-gradient reduction (grown on demand)
   void* red_mem = nullptr;
   size_t red_bytes = 0;
+  // workspace of the candidate search (grown on demand)
+  void* search_mem = nullptr;
+  size_t search_bytes = 0;
 };
 
 namespace {
@@ -146,6 +152,7 @@ int kf_destroy(kf_ctx* c) {
   if (c->d_counter) hipFree(c->d_counter);
   if (c->work_mem) hipFree(c->work_mem);
   if (c->red_mem) hipFree(c->red_mem);
+  if (c->search_mem) hipFree(c->search_mem);
   hipSetDevice(prev);
   delete c;
   return ok();
@@ -437,10 +444,195 @@ int kf_device_cu_count(const kf_ctx* ctx, int32_t* n_cu) {
   return ok();
 }
 
-int kf_score_hits(kf_ctx*, int64_t, int64_t, const float*, const float*, const int8_t*, const int16_t*, int32_t,
-                  const kf_geometry*, const kf_search_params*, const int32_t*, int64_t, const float*, const float*,
-                  const int32_t*, int32_t*, float*, float*, uint32_t*, void*) {
-  return fail(KF_ERR_UNSUPPORTED, "kf_score_hits: not built yet");
+int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, const float* seed_cov,
+                  const int8_t* seed_charge, const int16_t* seed_layer, const int16_t* layer_plan, int32_t plan_len,
+                  const kf_geometry* geom, const kf_search_params* prm, const int32_t* pool_layer_offsets,
+                  int64_t n_pool, const float* pool_pos, const float* pool_cov, const int32_t* pool_hit_id,
+                  int32_t* cand_hits, float* cand_score, float* cand_state, uint32_t* trk_status, void* stream) {
+  KF_TRY(check_sizes(n, ld));
+  kf::GeomArgs g;
+  KF_TRY(check_geometry(geom, &g));
+  KF_REQUIRE(prm);
+  if (prm->beam < 1 || prm->beam > kf::kMaxBeam) return fail(KF_ERR_ARG, "beam = %d outside [1, %d]", prm->beam, kf::kMaxBeam);
+  if (!(prm->chi2_max > 0.f) || !std::isfinite(prm->chi2_max)) return fail(KF_ERR_ARG, "chi2_max must be finite and > 0");
+  if (!(prm->n_sigma > 0.f) || !std::isfinite(prm->n_sigma)) return fail(KF_ERR_ARG, "n_sigma must be finite and > 0");
+  if (!std::isfinite(prm->hit_bonus)) return fail(KF_ERR_ARG, "hit_bonus must be finite");
+  if (!(prm->miss_penalty >= 0.f) || !std::isfinite(prm->miss_penalty)) return fail(KF_ERR_ARG, "miss_penalty must be >= 0");
+  if (prm->max_miss < 0 || prm->max_miss > 100) return fail(KF_ERR_ARG, "max_miss = %d outside [0, 100]", prm->max_miss);
+  if (!(prm->sigma_rphi >= 0.f) || !(prm->sigma_z >= 0.f)) return fail(KF_ERR_ARG, "sigma_rphi / sigma_z must be >= 0");
+  KF_REQUIRE(prm->win_min_rphi);
+  KF_REQUIRE(prm->win_max_rphi);
+  KF_REQUIRE(prm->win_min_z);
+  KF_REQUIRE(prm->win_max_z);
+  const int nl = geom->n_layers;
+  for (int l = 0; l < nl; ++l) {
+    if (!(prm->win_min_rphi[l] > 0.f) || !(prm->win_min_rphi[l] <= prm->win_max_rphi[l]) ||
+        !std::isfinite(prm->win_max_rphi[l]) || !(prm->win_min_z[l] > 0.f) ||
+        !(prm->win_min_z[l] <= prm->win_max_z[l]) || !std::isfinite(prm->win_max_z[l]))
+      return fail(KF_ERR_ARG, "window limits of layer %d invalid (need 0 < min <= max)", l);
+  }
+  if (plan_len < 1 || plan_len > 64) return fail(KF_ERR_ARG, "plan_len = %d outside [1, 64]", plan_len);
+  KF_REQUIRE(layer_plan);
+  for (int k = 0; k < plan_len; ++k) {
+    const int L = layer_plan[k];
+    if (L < 0 || L >= nl) return fail(KF_ERR_ARG, "layer_plan[%d] = %d is not a layer", k, L);
+    if (g.kind[L] != 0) return fail(KF_ERR_ARG, "layer_plan[%d] = %d is not a barrel layer", k, L);
+  }
+  KF_REQUIRE(pool_layer_offsets);
+  if (n_pool < 0 || n_pool >= (int64_t(1) << 31)) return fail(KF_ERR_ARG, "n_pool = %lld outside [0, 2^31)", (long long)n_pool);
+  if (pool_layer_offsets[0] != 0 || pool_layer_offsets[nl] != n_pool)
+    return fail(KF_ERR_ARG, "pool_layer_offsets must start at 0 and end at n_pool");
+  for (int l = 0; l < nl; ++l)
+    if (pool_layer_offsets[l + 1] < pool_layer_offsets[l]) return fail(KF_ERR_ARG, "pool_layer_offsets decrease at %d", l);
+  KF_REQUIRE(ctx);
+  if (n == 0) return ok();
+  KF_REQUIRE(seed_state);
+  KF_REQUIRE(seed_cov);
+  KF_REQUIRE(seed_charge);
+  KF_REQUIRE(seed_layer);
+  KF_REQUIRE(cand_hits);
+  KF_REQUIRE(cand_score);
+  KF_REQUIRE(trk_status);
+  if (n_pool > 0) {
+    KF_REQUIRE(pool_pos);
+    KF_REQUIRE(pool_cov);
+    KF_REQUIRE(pool_hit_id);
+  }
+  // bins of every layer
+  kf::BinTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.n_layers = nl;
+  int64_t n_bins = 0;
+  for (int l = 0; l <= nl; ++l) t.off[l] = pool_layer_offsets[l];
+  for (int l = 0; l < nl; ++l) {
+    int64_t np = 1, nz = 1;
+    const bool used = pool_layer_offsets[l + 1] > pool_layer_offsets[l];
+    if (g.kind[l] == 0 && used) {
+      np = std::max<int64_t>(1, int64_t(std::ceil(2.0 * M_PI * geom->pos[l] / kf::kBinArc)));
+      nz = std::max<int64_t>(1, int64_t(std::ceil((geom->hi[l] - geom->lo[l]) / kf::kBinZ)));
+    }
+    t.base[l] = int32_t(n_bins);
+    t.nphi[l] = int32_t(np);
+    t.nz[l] = int32_t(nz);
+    t.lo[l] = float(geom->lo[l]);
+    t.hi[l] = float(geom->hi[l]);
+    if (!(t.hi[l] > t.lo[l])) t.hi[l] = t.lo[l] + 1.f;
+    n_bins += np * nz;
+    if (n_bins >= (int64_t(1) << 31)) return fail(KF_ERR_ARG, "too many pool bins (layer %d)", l);
+  }
+  // workspace
+  const int64_t S = n * prm->beam, P = plan_len;
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t nsum = n_bins / 2048 + 2;
+  const int64_t b_bins = up(n_bins * 4), b_pool4 = up(n_pool * 4), b_sum = up(nsum * 4) + 256;
+  const int64_t b_pool = 4 * b_pool4 + up(n_pool * 6 * 4) + b_pool4 + up((n_bins + 1) * 4);
+  const int64_t b_slot = 2 * (up(S * 6 * 4) + up(S * 21 * 4) + up(S)) + 3 * up(S * kf::kMaxBeam * 4) + up(S * 4) +
+                         up(S) + up(S) + up(S * 4) + up(S * 4) + up(S) + up(P * S) + up(P * S * 4);
+  const int64_t total = b_bins + 2 * b_pool4 + b_sum + b_pool + b_slot;
+  if (size_t(total) > ctx->search_bytes) {
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    if (ctx->search_mem) hipFree(ctx->search_mem);
+    ctx->search_mem = nullptr;
+    ctx->search_bytes = 0;
+    hipError_t e = hipMalloc(&ctx->search_mem, size_t(total));
+    hipSetDevice(prev);
+    if (e != hipSuccess) {
+      ctx->search_mem = nullptr;
+      return fail(KF_ERR_NOMEM, "kf_score_hits: %lld bytes: %s", (long long)total, hipGetErrorString(e));
+    }
+    ctx->search_bytes = size_t(total);
+  }
+  char* q = (char*)ctx->search_mem;
+  auto take = [&q](int64_t b) {
+    char* r = q;
+    q += b;
+    return (void*)r;
+  };
+  kf::SearchWork w;
+  w.count = (int32_t*)take(b_bins);
+  w.bin_of = (int32_t*)take(b_pool4);
+  w.rank = (int32_t*)take(b_pool4);
+  w.block_sum = (int32_t*)take(up(nsum * 4));
+  w.total = (int32_t*)take(256);
+  w.pool.x = (float*)take(b_pool4);
+  w.pool.y = (float*)take(b_pool4);
+  w.pool.z = (float*)take(b_pool4);
+  w.pool.phi = (float*)take(b_pool4);
+  w.pool.cov = (float*)take(up(n_pool * 6 * 4));
+  w.pool.id = (int32_t*)take(b_pool4);
+  w.pool.bin_off = (int32_t*)take(up((n_bins + 1) * 4));
+  kf::SearchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.ld = ld;
+  a.beam = prm->beam;
+  a.plan_len = plan_len;
+  a.seed_state = seed_state;
+  a.seed_cov = seed_cov;
+  a.seed_charge = seed_charge;
+  a.seed_layer = seed_layer;
+  a.chi2_max = prm->chi2_max;
+  a.n_sigma = prm->n_sigma;
+  a.hit_bonus = prm->hit_bonus;
+  a.miss_penalty = prm->miss_penalty;
+  a.max_miss = prm->max_miss;
+  a.bz = float(geom->bz_tesla);
+  a.mass = float(geom->particle_mass_gev);
+  a.px = w.pool.x;
+  a.py = w.pool.y;
+  a.pz = w.pool.z;
+  a.pphi = w.pool.phi;
+  a.pcov = w.pool.cov;
+  a.pid = w.pool.id;
+  a.bin_off = w.pool.bin_off;
+  a.n_pool = n_pool;
+  for (int k = 0; k < 2; ++k) {
+    a.pred_p[k] = (float*)take(up(S * 6 * 4));
+    a.pred_c[k] = (float*)take(up(S * 21 * 4));
+    a.pred_q[k] = (int8_t*)take(up(S));
+  }
+  a.kid_score = (float*)take(up(S * kf::kMaxBeam * 4));
+  a.kid_id = (int32_t*)take(up(S * kf::kMaxBeam * 4));
+  a.kid_idx = (int32_t*)take(up(S * kf::kMaxBeam * 4));
+  a.kid_n = (int32_t*)take(up(S * 4));
+  a.cur_miss = (int8_t*)take(up(S));
+  a.sel_parent = (int8_t*)take(up(S));
+  a.sel_idx = (int32_t*)take(up(S * 4));
+  a.sel_score = (float*)take(up(S * 4));
+  a.sel_miss = (int8_t*)take(up(S));
+  a.hist_parent = (int8_t*)take(up(P * S));
+  a.hist_id = (int32_t*)take(up(P * S * 4));
+  a.status = trk_status;
+  a.cand_hits = cand_hits;
+  a.cand_score = cand_score;
+  a.cand_state = cand_state;
+  std::vector<kf::SearchLayer> layers(plan_len);
+  for (int k = 0; k < plan_len; ++k) {
+    const int L = layer_plan[k];
+    kf::SearchLayer& sl = layers[k];
+    sl.layer = L;
+    sl.prev_layer = k > 0 ? layer_plan[k - 1] : -1;
+    sl.R = float(geom->pos[L]);
+    sl.x0 = float(geom->x_over_x0[L]);
+    sl.base = t.base[L];
+    sl.nphi = t.nphi[L];
+    sl.nz = t.nz[L];
+    sl.lo = t.lo[L];
+    sl.hi = t.hi[L];
+    sl.wmin_r = prm->win_min_rphi[L];
+    sl.wmax_r = prm->win_max_rphi[L];
+    sl.wmin_z = prm->win_min_z[L];
+    sl.wmax_z = prm->win_max_z[L];
+    sl.sig_r = prm->sigma_rphi;
+    sl.sig_z = prm->sigma_z;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = kf::launch_bin_pool(t, pool_pos, pool_cov, pool_hit_id, n_pool, n_bins, w, s);
+  if (e == hipSuccess) e = kf::launch_search(a, layers.data(), plan_len, s);
+  if (e != hipSuccess) return hip_fail(e, "kf_score_hits");
+  return ok();
 }
 
 int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state,

@@ -67,6 +67,10 @@ KF_HD inline float k_ceil(float x) { return ceilf(x); }
 KF_HD inline double k_ceil(double x) { return ceil(x); }
 KF_HD inline bool k_finite(float x) { return x - x == 0.0f; }
 KF_HD inline bool k_finite(double x) { return x - x == 0.0; }
+template <typename T>
+KF_HD inline T k_inf() { return T(__builtin_huge_val()); }
+template <typename T>
+KF_HD inline T k_nan() { return T(__builtin_nan("")); }
 KF_HD inline float k_copysign(float a, float b) { return copysignf(a, b); }
 KF_HD inline double k_copysign(double a, double b) { return copysign(a, b); }
 

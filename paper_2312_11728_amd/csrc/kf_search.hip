@@ -1,0 +1,180 @@
+// HIP kernels of the combinatorial candidate search: binning of the hit pool
+// by (layer, phi, z), then per layer of the plan the extend kernel (one
+// thread per candidate slot) and the select kernel (one thread per seed), and
+// a final pass that writes the kept candidates.
+#include "kf_kernels.hpp"
+#include "kf_search.hpp"
+#include "kf_search_launch.hpp"
+
+namespace kf {
+
+// ---- binning -------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+__device__ __forceinline__ int layer_of_hit(const BinTable& t, int32_t h) {
+  int lo = 0, hi = t.n_layers;   // off[lo] <= h < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (t.off[mid] <= h) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int32_t bin_of_hit(const BinTable& t, int L, float x, float y, float z) {
+  const float phi = atan2f(y, x);
+  return t.base[L] + phi_bin(phi, t.nphi[L]) * t.nz[L] + z_bin(z, t.lo[L], t.hi[L], t.nz[L]);
+}
+
+// count hits per bin; each hit keeps its rank inside its bin
+__global__ void __launch_bounds__(256) bin_count_kernel(BinTable t, const float* pos, int64_t n, int32_t* count,
+                                                        int32_t* bin_of, int32_t* rank) {
+  const int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (h >= n) return;
+  const int L = layer_of_hit(t, int32_t(h));
+  const int32_t b = bin_of_hit(t, L, pos[h], pos[n + h], pos[2 * n + h]);
+  bin_of[h] = b;
+  rank[h] = atomicAdd(&count[b], 1);
+}
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;   // per thread
+
+// exclusive scan of counts[0..n) into off, block by block; block totals out
+__global__ void __launch_bounds__(kScanBlock) scan_blocks_kernel(const int32_t* in, int64_t n, int32_t* out,
+                                                                 int32_t* block_sum) {
+  __shared__ int32_t s[kScanBlock];
+  const int64_t base = int64_t(blockIdx.x) * kScanBlock * kScanItems + int64_t(threadIdx.x) * kScanItems;
+  int32_t v[kScanItems];
+  int32_t tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    tot += v[k];
+  }
+  s[threadIdx.x] = tot;
+  __syncthreads();
+  for (int o = 1; o < kScanBlock; o <<= 1) {
+    const int32_t add = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int32_t run = s[threadIdx.x] - tot;   // exclusive prefix of this thread
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kScanBlock - 1) block_sum[blockIdx.x] = s[threadIdx.x];
+}
+
+// exclusive scan of the block totals (one block, chunks with a carry);
+// total[0] = grand total
+__global__ void __launch_bounds__(1024) scan_sums_kernel(int32_t* sums, int64_t nb, int32_t* total) {
+  __shared__ int32_t s[1024];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+    const int64_t i = c0 + threadIdx.x;
+    const int32_t v = i < nb ? sums[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int32_t add = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+      __syncthreads();
+      s[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < nb) sums[i] = carry + s[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += s[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) total[0] = carry;
+}
+
+__global__ void __launch_bounds__(256) scan_add_kernel(int32_t* out, int64_t n, const int32_t* sums,
+                                                       const int32_t* total) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += sums[i / (kScanBlock * kScanItems)];
+  if (i == n) out[n] = total[0];
+}
+
+// copy every hit to its binned position (x, y, z, phi, covariance, id)
+__global__ void __launch_bounds__(256) bin_scatter_kernel(BinTable t, const float* pos, const float* cov,
+                                                          const int32_t* id, int64_t n, const int32_t* bin_off,
+                                                          const int32_t* bin_of, const int32_t* rank, PoolBins o) {
+  const int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (h >= n) return;
+  const int64_t d = int64_t(bin_off[bin_of[h]]) + rank[h];
+  const float x = pos[h], y = pos[n + h];
+  o.x[d] = x;
+  o.y[d] = y;
+  o.z[d] = pos[2 * n + h];
+  o.phi[d] = atan2f(y, x);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) o.cov[int64_t(i) * n + d] = cov[int64_t(i) * n + h];
+  o.id[d] = id[h];
+}
+
+// ---- search ------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) extend_kernel(SearchArgs a, SearchLayer L) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= a.n * a.beam) return;
+  const uint32_t st = extend_slot(a, L, s);
+  if (st) atomicOr(&a.status[s / a.beam], st);
+}
+
+__global__ void __launch_bounds__(256) select_kernel(SearchArgs a) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= a.n) return;
+  select_seed(a, t);
+}
+
+__global__ void __launch_bounds__(256) finish_kernel(SearchArgs a) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= a.n * a.beam) return;
+  const uint32_t st = finish_slot(a, s);
+  if (st) atomicOr(&a.status[s / a.beam], st);
+}
+
+static unsigned blocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+hipError_t launch_bin_pool(const BinTable& t, const float* pos, const float* cov, const int32_t* id, int64_t n,
+                           int64_t n_bins, const SearchWork& w, hipStream_t s) {
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1024), dim3(256), 0, s, w.count, n_bins, 0);
+  if (n > 0)
+    hipLaunchKernelGGL(bin_count_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, t, pos, n, w.count, w.bin_of,
+                       w.rank);
+  const int64_t nb = (n_bins + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(unsigned(nb)), dim3(kScanBlock), 0, s, w.count, n_bins,
+                     w.pool.bin_off, w.block_sum);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, w.block_sum, nb, w.total);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(n_bins + 1, 256)), dim3(256), 0, s, w.pool.bin_off, n_bins,
+                     w.block_sum, w.total);
+  if (n > 0)
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, t, pos, cov, id, n,
+                       w.pool.bin_off, w.bin_of, w.rank, w.pool);
+  return hipGetLastError();
+}
+
+hipError_t launch_search(SearchArgs a, const SearchLayer* layers, int plan_len, hipStream_t s) {
+  const int64_t S = a.n * a.beam;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks(a.n, 256)), dim3(256), 0, s, (int32_t*)a.status, a.n, 0);
+  for (int k = 0; k < plan_len; ++k) {
+    a.step = k;
+    hipLaunchKernelGGL(extend_kernel, dim3(blocks(S, 256)), dim3(256), 0, s, a, layers[k]);
+    hipLaunchKernelGGL(select_kernel, dim3(blocks(a.n, 256)), dim3(256), 0, s, a);
+  }
+  hipLaunchKernelGGL(finish_kernel, dim3(blocks(S, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace kf

@@ -1,0 +1,392 @@
+// Combinatorial candidate search (forward search of the paper's track finding,
+// Sec. 2.2; layers and layer plans, Sec. 3.1): per-slot and per-seed steps,
+// callable from device and host code.
+//
+// A seed owns `beam` candidate slots.  At every layer of the plan:
+//   extend (one thread per slot): apply the update with the hit the slot's
+//     candidate took at the previous layer, propagate to the layer with its
+//     material, open the window, compute chi2 for every pool hit inside it
+//     and keep the slot's best `beam` children (a child per accepted hit, or
+//     one miss child when none is accepted and the miss budget allows, or
+//     else one stop child: a candidate that stops -- no crossing, or no hit
+//     within its miss budget -- keeps its score and the state it entered the
+//     layer with, and from then on is carried from layer to layer unchanged);
+//   select (one thread per seed): merge the slots' sorted child lists into
+//     the seed's best `beam` children, which become the next layer's slots.
+// Children are ranked by (score descending; hit id ascending, a miss after
+// every hit and a stop after a miss; parent rank ascending) -- a total order,
+// so the result does not depend on the order in which hits are visited.
+#pragma once
+
+#include "kf_kernels.hpp"
+#include "kf_math.hpp"
+
+namespace kf {
+
+constexpr int kMaxBeam = 8;
+constexpr float kBinArc = 0.5f;   // pool bin size along r-phi (cm)
+constexpr float kBinZ = 1.0f;     // pool bin size along z (cm)
+constexpr int32_t kMissKey = 0x7ffffffe;   // ranking keys of a miss and a stop
+constexpr int32_t kStopKey = 0x7fffffff;
+constexpr int32_t kMissIdx = -1;           // hit codes of a miss and a stop
+constexpr int32_t kStopIdx = -3;
+
+// Per-layer binning of the hit pool: the hits of layer l sit in bins
+// base[l] + pb * nz[l] + zb, pb in [0, nphi[l]) over phi in [-pi, pi),
+// zb in [0, nz[l]) over z in [lo[l], hi[l]] (hits beyond clamp to the edge
+// bins).  off: the caller's pool CSR by layer.
+struct BinTable {
+  int32_t n_layers;
+  int32_t off[kMaxLayers + 1];
+  int32_t base[kMaxLayers];
+  int32_t nphi[kMaxLayers];
+  int32_t nz[kMaxLayers];
+  float lo[kMaxLayers];
+  float hi[kMaxLayers];
+};
+
+// bin of a coordinate mapped to f in bin units, clamped to [0, n) (NaN -> 0)
+KF_HD inline int32_t clamp_bin(float f, int32_t n) {
+  if (!(f >= 0.f)) return 0;
+  if (f >= float(n)) return n - 1;
+  return int32_t(f);
+}
+
+KF_HD inline int32_t phi_bin(float phi, int32_t nphi) {
+  return clamp_bin((phi + float(kPi)) * (float(nphi) * float(0.5 / kPi)), nphi);
+}
+
+KF_HD inline int32_t z_bin(float z, float lo, float hi, int32_t nz) {
+  return clamp_bin((z - lo) * (float(nz) / (hi - lo)), nz);
+}
+
+// Scalars of the layer being searched (one launch per layer).
+struct SearchLayer {
+  int32_t layer;       // layer id
+  int32_t prev_layer;  // layer of the previous plan step (-1: the seeds' own)
+  float R, x0;         // radius, x / X0
+  int32_t base, nphi, nz;
+  float lo, hi;
+  float wmin_r, wmax_r, wmin_z, wmax_z, sig_r, sig_z;
+};
+
+struct SearchArgs {
+  int64_t n, ld;                 // seeds, leading dimension of the seed arrays
+  int32_t beam, plan_len, step;  // step: index of the layer in the plan
+  const float* seed_state;       // [6][ld]
+  const float* seed_cov;         // [21][ld]
+  const int8_t* seed_charge;     // [n]
+  const int16_t* seed_layer;     // [n]
+  float chi2_max, n_sigma, hit_bonus, miss_penalty;
+  int32_t max_miss;
+  float bz, mass;
+  // binned pool
+  const float* px;
+  const float* py;
+  const float* pz;
+  const float* pphi;
+  const float* pcov;             // [6][n_pool]
+  const int32_t* pid;            // caller's hit ids
+  const int32_t* bin_off;        // [n_bins + 1]
+  int64_t n_pool;
+  // slots (S = n * beam; slot = seed * beam + rank)
+  float* pred_p[2];              // [6][S] predicted state at the current / previous layer
+  float* pred_c[2];              // [21][S]
+  int8_t* pred_q[2];             // [S]
+  float* kid_score;              // [S][kMaxBeam] sorted child list of each slot
+  int32_t* kid_id;
+  int32_t* kid_idx;              // binned pool index, kMissIdx, kStopIdx
+  int32_t* kid_n;                // [S]
+  int8_t* cur_miss;              // [S] misses of the slot's candidate
+  int8_t* sel_parent;            // [S] parent rank of the slot's candidate, -1 = none
+  int32_t* sel_idx;              // [S] binned pool index of its hit, kMissIdx, kStopIdx
+  float* sel_score;              // [S]
+  int8_t* sel_miss;              // [S]
+  int8_t* hist_parent;           // [plan_len][S]
+  int32_t* hist_id;              // [plan_len][S] caller's hit id, -1 = miss, -3 = stopped
+  uint32_t* status;              // [n]
+  int32_t* cand_hits;            // [n][beam][plan_len]
+  float* cand_score;             // [n][beam]
+  float* cand_state;             // [6][S] or null
+};
+
+// a better than b in the ranking of children
+KF_HD inline bool child_before(float sa, int32_t ka, int32_t pa, float sb, int32_t kb, int32_t pb) {
+  if (sa != sb) return sa > sb;
+  if (ka != kb) return ka < kb;
+  return pa < pb;
+}
+
+KF_HD inline void load_pool_hit(const SearchArgs& a, int32_t h, float m[3], float V[6]) {
+  m[0] = a.px[h];
+  m[1] = a.py[h];
+  m[2] = a.pz[h];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) V[i] = a.pcov[int64_t(i) * a.n_pool + h];
+}
+
+KF_HD inline void load_slot(const float* P, const float* C, const int8_t* Q, int64_t S, int64_t s, float p[6],
+                            float c[21], int& q) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) p[i] = P[i * S + s];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) c[i] = C[i * S + s];
+  q = Q[s];
+}
+
+// chi2 = r^T (C_pos + V)^-1 r of the predicted state (p, c) and hit (m, V).
+KF_HD inline float hit_chi2(const float p[6], const float c[21], const float m[3], const float V[6], uint32_t& st) {
+  float S[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) S[sym(i, j)] = c[sym(i, j)] + V[sym(i, j)];
+  float Si[6];
+  inverse_checked<float>(S, Si, st);
+  const float r[3] = {m[0] - p[0], m[1] - p[1], m[2] - p[2]};
+  float acc = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) acc += r[i] * (Si[sym(i, 0)] * r[0] + Si[sym(i, 1)] * r[1] + Si[sym(i, 2)] * r[2]);
+  return acc;
+}
+
+// Extend the candidate of slot s (see the file comment).  Returns the status
+// bits of its steps.
+KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, int64_t s) {
+  const int64_t S = a.n * a.beam;
+  const int64_t seed = s / a.beam;
+  const int r = int(s % a.beam);
+  const int cur = a.step & 1, prv = cur ^ 1;
+  float p[6], c[21];
+  int q = 1, prev;
+  float score;
+  int miss;
+  uint32_t st = 0;
+  bool stopped = false;
+  a.kid_n[s] = 0;
+  if (a.step == 0) {
+    if (r != 0) return 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * a.ld + seed];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * a.ld + seed];
+    q = a.seed_charge[seed];
+    prev = a.seed_layer[seed];
+    score = 0.f;
+    miss = 0;
+  } else {
+    const int par = a.sel_parent[s];
+    if (par < 0) return 0;
+    load_slot(a.pred_p[prv], a.pred_c[prv], a.pred_q[prv], S, seed * a.beam + par, p, c, q);
+    const int32_t h = a.sel_idx[s];
+    if (h >= 0) {
+      float m[3], V[6], c2;
+      load_pool_hit(a, h, m, V);
+      update(p, c, q, m, V, c2, st);
+    }
+    prev = L.prev_layer;
+    score = a.sel_score[s];
+    miss = a.sel_miss[s];
+    stopped = h == kStopIdx;   // carried unchanged
+  }
+  // the state entering the layer, kept if the candidate stops here
+#pragma unroll
+  for (int i = 0; i < 6; ++i) a.pred_p[cur][i * S + s] = p[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) a.pred_c[cur][i * S + s] = c[i];
+  a.pred_q[cur][s] = int8_t(q);
+  a.cur_miss[s] = int8_t(miss);
+  if (stopped || !propagate(p, c, q, 0, L.R, L.x0, prev == L.layer, true, a.bz, a.mass, st)) {
+    a.kid_score[s * kMaxBeam] = score;
+    a.kid_id[s * kMaxBeam] = kStopKey;
+    a.kid_idx[s * kMaxBeam] = kStopIdx;
+    a.kid_n[s] = 1;
+    return st;
+  }
+  // window
+  const float phi_p = k_atan2(p[1], p[0]);
+  const float ir = 1.f / k_sqrt(p[0] * p[0] + p[1] * p[1]);
+  const float sp = p[1] * ir, cp = p[0] * ir;
+  const float var_r = sp * sp * c[sym(0, 0)] - 2.f * sp * cp * c[sym(1, 0)] + cp * cp * c[sym(1, 1)];
+  float w_r = a.n_sigma * k_sqrt(var_r + L.sig_r * L.sig_r);
+  w_r = w_r < L.wmin_r ? L.wmin_r : (w_r > L.wmax_r ? L.wmax_r : w_r);
+  float w_z = a.n_sigma * k_sqrt(c[sym(2, 2)] + L.sig_z * L.sig_z);
+  w_z = w_z < L.wmin_z ? L.wmin_z : (w_z > L.wmax_z ? L.wmax_z : w_z);
+  const float dphi = w_r / L.R;
+  // child list of this slot, best first (empty entries rank last)
+  float ks[kMaxBeam];
+  int32_t kk[kMaxBeam], ki[kMaxBeam];
+#pragma unroll
+  for (int j = 0; j < kMaxBeam; ++j) {
+    ks[j] = -k_inf<float>();
+    kk[j] = kMissKey;
+    ki[j] = -2;
+  }
+  int nk = 0;
+  // bin ranges, widened slightly so that the exact test below decides; a
+  // non-finite prediction scans nothing (the range test below is false)
+  const float zp = p[2];
+  const float bw = float(L.nphi) * float(0.5 / kPi);
+  const float fb0 = k_floor((phi_p - dphi - 1e-5f + float(kPi)) * bw);
+  const float fb1 = k_floor((phi_p + dphi + 1e-5f + float(kPi)) * bw);
+  if (fb0 >= -float(L.nphi) && fb1 <= 2.f * float(L.nphi) && fb1 >= fb0 && k_finite(zp) && k_finite(w_z)) {
+    int32_t b0 = int32_t(fb0), b1 = int32_t(fb1);
+    if (b1 - b0 + 1 > L.nphi) {
+      b0 = 0;
+      b1 = L.nphi - 1;
+    }
+    const int32_t z0 = z_bin(zp - w_z - 1e-4f, L.lo, L.hi, L.nz);
+    const int32_t z1 = z_bin(zp + w_z + 1e-4f, L.lo, L.hi, L.nz);
+    for (int32_t b = b0; b <= b1; ++b) {
+      const int32_t pb = b < 0 ? b + L.nphi : (b >= L.nphi ? b - L.nphi : b);
+      const int32_t h0 = a.bin_off[L.base + pb * L.nz + z0];
+      const int32_t h1 = a.bin_off[L.base + pb * L.nz + z1 + 1];
+      for (int32_t h = h0; h < h1; ++h) {
+        float d = a.pphi[h] - phi_p;
+        d = d > float(kPi) ? d - float(2 * kPi) : (d < -float(kPi) ? d + float(2 * kPi) : d);
+        if (!(k_abs(d) <= dphi) || !(k_abs(a.pz[h] - zp) <= w_z)) continue;
+        float m[3], V[6];
+        load_pool_hit(a, h, m, V);
+        const float c2 = hit_chi2(p, c, m, V, st);
+        if (!(c2 <= a.chi2_max)) continue;
+        // insert (score, id) into the sorted list; the last entry drops out
+        float ns = score + a.hit_bonus - c2;
+        int32_t nkey = a.pid[h], nidx = h;
+#pragma unroll
+        for (int j = 0; j < kMaxBeam; ++j) {
+          if (j < a.beam && child_before(ns, nkey, 0, ks[j], kk[j], 0)) {
+            const float ts = ks[j];
+            const int32_t tk = kk[j], ti = ki[j];
+            ks[j] = ns;
+            kk[j] = nkey;
+            ki[j] = nidx;
+            ns = ts;
+            nkey = tk;
+            nidx = ti;
+          }
+        }
+        ++nk;
+      }
+    }
+  }
+  if (nk == 0) {
+    const bool can_miss = miss < a.max_miss;
+    ks[0] = can_miss ? score - a.miss_penalty : score;
+    kk[0] = can_miss ? kMissKey : kStopKey;
+    ki[0] = can_miss ? kMissIdx : kStopIdx;
+    nk = 1;
+  }
+  if (ki[0] != kStopIdx) {
+    // the candidate goes on from the predicted state
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a.pred_p[cur][i * S + s] = p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) a.pred_c[cur][i * S + s] = c[i];
+    a.pred_q[cur][s] = int8_t(q);
+  }
+  const int n_out = nk < a.beam ? nk : a.beam;
+#pragma unroll
+  for (int j = 0; j < kMaxBeam; ++j) {
+    if (j < n_out) {
+      a.kid_score[s * kMaxBeam + j] = ks[j];
+      a.kid_id[s * kMaxBeam + j] = kk[j];
+      a.kid_idx[s * kMaxBeam + j] = ki[j];
+    }
+  }
+  a.kid_n[s] = n_out;
+  return st;
+}
+
+// Merge the child lists of seed t's slots into its next candidates.
+KF_HD inline void select_seed(const SearchArgs& a, int64_t t) {
+  const int64_t S = a.n * a.beam;
+  const int64_t s0 = t * a.beam;
+  int head[kMaxBeam], cnt[kMaxBeam];
+#pragma unroll
+  for (int r = 0; r < kMaxBeam; ++r) {
+    head[r] = 0;
+    cnt[r] = r < a.beam ? a.kid_n[s0 + r] : 0;
+  }
+  int out = 0;
+  for (; out < a.beam; ++out) {
+    int best = -1;
+    float bs = 0.f;
+    int32_t bk = 0;
+#pragma unroll
+    for (int r = 0; r < kMaxBeam; ++r) {
+      if (head[r] < cnt[r]) {
+        const int64_t k = (s0 + r) * kMaxBeam + head[r];
+        const float sc = a.kid_score[k];
+        const int32_t key = a.kid_id[k];
+        if (best < 0 || child_before(sc, key, r, bs, bk, best)) {
+          best = r;
+          bs = sc;
+          bk = key;
+        }
+      }
+    }
+    if (best < 0) break;
+    int hb = 0;
+#pragma unroll
+    for (int r = 0; r < kMaxBeam; ++r)
+      if (r == best) hb = head[r];
+    const int64_t k = (s0 + best) * kMaxBeam + hb;
+    const int32_t idx = a.kid_idx[k];
+    const int64_t so = s0 + out;
+    a.sel_parent[so] = int8_t(best);
+    a.sel_idx[so] = idx;
+    a.sel_score[so] = bs;
+    a.sel_miss[so] = int8_t(a.cur_miss[s0 + best] + (idx == kMissIdx ? 1 : 0));
+    a.hist_parent[int64_t(a.step) * S + so] = int8_t(best);
+    a.hist_id[int64_t(a.step) * S + so] = idx >= 0 ? bk : idx;
+#pragma unroll
+    for (int r = 0; r < kMaxBeam; ++r)
+      if (r == best) ++head[r];
+  }
+  for (; out < a.beam; ++out) a.sel_parent[s0 + out] = -1;
+}
+
+// After the last layer: the kept candidates' final states (update with their
+// last hit), scores and hit lists (backtracked through the parents).
+KF_HD inline uint32_t finish_slot(const SearchArgs& a, int64_t s) {
+  const int64_t S = a.n * a.beam;
+  const int64_t seed = s / a.beam;
+  const int r = int(s % a.beam);
+  const int P = a.plan_len;
+  int32_t* out = a.cand_hits + s * P;
+  const int par = a.sel_parent[s];
+  uint32_t st = 0;
+  if (par < 0) {
+    for (int k = 0; k < P; ++k) out[k] = -2;
+    a.cand_score[s] = -k_inf<float>();
+    if (a.cand_state)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) a.cand_state[i * S + s] = k_nan<float>();
+    return 0;
+  }
+  {
+    const int last = (P - 1) & 1;
+    float p[6], c[21];
+    int q;
+    load_slot(a.pred_p[last], a.pred_c[last], a.pred_q[last], S, seed * a.beam + par, p, c, q);
+    const int32_t h = a.sel_idx[s];
+    if (h >= 0) {
+      float m[3], V[6], c2;
+      load_pool_hit(a, h, m, V);
+      update(p, c, q, m, V, c2, st);
+    }
+    if (a.cand_state)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) a.cand_state[i * S + s] = p[i];
+  }
+  a.cand_score[s] = a.sel_score[s];
+  int rr = r;
+  for (int k = P - 1; k >= 0; --k) {
+    const int64_t hs = int64_t(k) * S + seed * a.beam + rr;
+    out[k] = a.hist_id[hs];
+    rr = a.hist_parent[hs];
+  }
+  return st;
+}
+
+}  // namespace kf

@@ -46,6 +46,25 @@ class KfSearchParams(ctypes.Structure):
                 ("win_min_rphi", _vp), ("win_max_rphi", _vp), ("win_min_z", _vp), ("win_max_z", _vp)]
 
 
+class SearchParams:
+    """Parameters of kf_score_hits (see kf_search_params in include/kf.h);
+    per-layer window limits as arrays of n_layers (cm)."""
+
+    def __init__(self, n_layers, beam=6, chi2_max=30.0, n_sigma=5.0, hit_bonus=10.0, miss_penalty=5.0, max_miss=3,
+                 sigma_rphi=0.003, sigma_z=0.01, win_min_rphi=0.01, win_max_rphi=2.0, win_min_z=0.03, win_max_z=2.0):
+        self.n_layers = n_layers
+        self.beam, self.chi2_max, self.n_sigma = beam, chi2_max, n_sigma
+        self.hit_bonus, self.miss_penalty, self.max_miss = hit_bonus, miss_penalty, max_miss
+        self.sigma_rphi, self.sigma_z = sigma_rphi, sigma_z
+        f = lambda v: np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float32), (n_layers,)))
+        self.win_min_rphi, self.win_max_rphi = f(win_min_rphi), f(win_max_rphi)
+        self.win_min_z, self.win_max_z = f(win_min_z), f(win_max_z)
+        p = lambda a: a.ctypes.data_as(_vp)
+        self.struct = KfSearchParams(beam, chi2_max, n_sigma, hit_bonus, miss_penalty, max_miss, sigma_rphi, sigma_z,
+                                     p(self.win_min_rphi), p(self.win_max_rphi), p(self.win_min_z),
+                                     p(self.win_max_z))
+
+
 class KfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libkf error {code}: {msg}")
@@ -67,7 +86,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_update.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                   ctypes.POINTER(KfGeometry), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp]
-    lib.kf_score_hits.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(KfGeometry),
+    lib.kf_score_hits.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(KfGeometry),
                                   ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_adjoint.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                    ctypes.POINTER(KfGeometry), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -270,6 +289,35 @@ class Context:
                                    _ptr(out["status"]), _stream(dev)))
         return out
 
+
+    def score_hits(self, seed_state, seed_cov, seed_charge, seed_layer, layer_plan, geom: Geometry,
+                   params: SearchParams, pool_layer_offsets, pool_pos, pool_cov, pool_hit_id, want_state=True):
+        """Combinatorial candidate search (kf_score_hits, FP32).  layer_plan and
+        pool_layer_offsets are host sequences; the rest device tensors.
+        Returns (hits [n, beam, plan_len] int32, score [n, beam], state
+        [6, n * beam] or None, status [n])."""
+        dev = self.device
+        n = seed_state.shape[1]
+        _need(seed_state, "seed_state", torch.float32, dev, rows=6)
+        _need(seed_cov, "seed_cov", torch.float32, dev, rows=21)
+        _need(seed_charge, "seed_charge", torch.int8, dev)
+        _need(seed_layer, "seed_layer", torch.int16, dev)
+        _need(pool_pos, "pool_pos", torch.float32, dev, rows=3)
+        _need(pool_cov, "pool_cov", torch.float32, dev, rows=6)
+        _need(pool_hit_id, "pool_hit_id", torch.int32, dev)
+        plan = np.ascontiguousarray(np.asarray(layer_plan, np.int16))
+        off = np.ascontiguousarray(np.asarray(pool_layer_offsets, np.int32))
+        B, P = params.beam, plan.shape[0]
+        hits = torch.empty(n, B, P, dtype=torch.int32, device=dev)
+        score = torch.empty(n, B, dtype=torch.float32, device=dev)
+        state = torch.empty(6, n * B, dtype=torch.float32, device=dev) if want_state else None
+        status = torch.empty(n, dtype=torch.int32, device=dev)
+        _check(lib().kf_score_hits(self.handle, n, seed_state.stride(0), _ptr(seed_state), _ptr(seed_cov),
+                                   _ptr(seed_charge), _ptr(seed_layer), plan.ctypes.data_as(_vp), P,
+                                   ctypes.byref(geom.struct), ctypes.byref(params.struct), off.ctypes.data_as(_vp),
+                                   pool_pos.shape[1], _ptr(pool_pos), _ptr(pool_cov), _ptr(pool_hit_id), _ptr(hits),
+                                   _ptr(score), _ptr(state), _ptr(status), _stream(dev)))
+        return hits, score, state, status
 
     def fit_adjoint(self, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov,
                     geom: Geometry, checkpoints, seg, max_len, fwd_status, align=None, dL_dchi2=None,

@@ -128,3 +128,46 @@ def test_fit_adjoint_argument_validation(over, msg):
 
 def test_fit_adjoint_empty_batch_is_a_no_op():
     assert _adj_call(n=0, ld=0, seed_state=None, grad_seed=None, grad_hit_pos=None, checkpoints=None) == kf.KF_OK
+
+
+def _search_call(**over):
+    nl = 3
+    g = _geom(nl)
+    wmin = (ctypes.c_float * nl)(*([0.01] * nl))
+    wmax = (ctypes.c_float * nl)(*([2.0] * nl))
+    prm = kf.KfSearchParams(6, 30.0, 5.0, 10.0, 5.0, 3, 0.003, 0.01, ctypes.cast(wmin, ctypes.c_void_p),
+                            ctypes.cast(wmax, ctypes.c_void_p), ctypes.cast(wmin, ctypes.c_void_p),
+                            ctypes.cast(wmax, ctypes.c_void_p))
+    for k in [k for k in over if k.startswith("prm_")]:
+        setattr(prm, k[4:], over.pop(k))
+    plan = (ctypes.c_int16 * 2)(1, 2)
+    off = (ctypes.c_int32 * (nl + 1))(0, 0, 5, 10)
+    args = dict(ctx=P, n=10, ld=10, seed_state=P, seed_cov=P, seed_charge=P, seed_layer=P,
+                layer_plan=ctypes.cast(plan, ctypes.c_void_p), plan_len=2, geom=ctypes.byref(g.struct),
+                params=ctypes.byref(prm), pool_layer_offsets=ctypes.cast(off, ctypes.c_void_p), n_pool=10,
+                pool_pos=P, pool_cov=P, pool_hit_id=P, cand_hits=P, cand_score=P, cand_state=None, trk_status=P,
+                stream=None)
+    args.update(over)
+    return kf.lib().kf_score_hits(*args.values())
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(prm_beam=0), "beam = 0"),
+    (dict(prm_beam=9), "beam = 9"),
+    (dict(prm_chi2_max=0.0), "chi2_max"),
+    (dict(prm_max_miss=-1), "max_miss"),
+    (dict(plan_len=0), "plan_len = 0"),
+    (dict(n_pool=11), "pool_layer_offsets"),
+    (dict(seed_layer=None), "seed_layer is NULL"),
+    (dict(cand_hits=None), "cand_hits is NULL"),
+    (dict(n=-2), "n = -2"),
+])
+def test_score_hits_argument_validation(over, msg):
+    assert _search_call(**over) == kf.KF_ERR_ARG
+    assert msg in kf.lib().kf_last_error().decode()
+
+
+def test_score_hits_rejects_disk_layers_in_the_plan():
+    g = kf.Geometry([0, 1, 0], [4.0, 30.0, 6.0], [-150.0, 2.0, -150.0], [150.0, 100.0, 150.0], [0.02] * 3)
+    assert _search_call(geom=ctypes.byref(g.struct)) == kf.KF_ERR_ARG
+    assert "not a barrel layer" in kf.lib().kf_last_error().decode()

@@ -1,0 +1,162 @@
+"""GPU parity of the combinatorial candidate search (kf_score_hits, FP32,
+through the C interface) against the FP64 search oracle on identical inputs
+(FP32-representable seeds and pools).
+
+Bar: for every seed the oracle does not flag (no decision within the FP32
+error model of a window edge, the chi2 cut or the ranking; see
+oracle/kf_search.py), the hit-id lists of all ranks are identical, bit for
+bit; scores agree within 1e-3 + 3 x the oracle's FP32 error estimate of the
+candidate's score (root-sum-square of its terms' errors); the status bits
+agree except FP64_FALLBACK (a GPU-only bit).  The flagged fraction is
+reported and bounded (the error model is conservative: about a tenth of the
+flagged seeds actually differ)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import kf_oracle as O
+from oracle import kf_search as KS
+from search_common import PLAN, SEED_LAYER, default_params, search_inputs
+from test_oracle_search import _drop_layers, _tiny_pools
+
+pytestmark = pytest.mark.gpu
+IL = [(i, j) for i in range(6) for j in range(i + 1)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_11728_amd import kf as _kf
+    return _kf
+
+
+@pytest.fixture(scope="module")
+def ctx(kf):
+    c = kf.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_search(ctx, kf, g, pools, p, C, q, plan=PLAN, beam=6, seeds=None):
+    dev = ctx.device
+    idx = np.arange(p.shape[0]) if seeds is None else np.asarray(seeds)
+    f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt).contiguous()
+    st = f(p[idx].T, torch.float32)
+    cv = f(np.stack([C[idx][:, i, j] for i, j in IL]), torch.float32)
+    qq = f(q[idx], torch.int8)
+    sl = f(np.full(idx.size, SEED_LAYER), torch.int16)
+    prm = kf.SearchParams(g.n_layers, beam=beam)
+    geom = kf.Geometry.from_toy(g)
+    hits, score, state, status = ctx.score_hits(st, cv, qq, sl, plan, geom, prm, pools.layer_offsets,
+                                                f(pools.pos, torch.float32), f(pools.cov, torch.float32),
+                                                f(pools.hit_id, torch.int32))
+    torch.cuda.synchronize()
+    return dict(hits=hits.cpu().numpy().astype(np.int64), score=score.cpu().numpy().astype(np.float64),
+                state=state.cpu().numpy().astype(np.float64), status=status.cpu().numpy().astype(np.int64))
+
+
+def compare(gs, o, max_flag_frac=0.2):
+    n = o["hits"].shape[0]
+    fl = o["flagged"]
+    same = np.all(gs["hits"] == o["hits"], axis=(1, 2))
+    bad = np.nonzero(~same & ~fl)[0]
+    say("  seeds %d flagged %.4f identical %.4f unflagged mismatches %d" % (n, fl.mean(), same.mean(), bad.size))
+    assert bad.size == 0, (bad[:10], gs["hits"][bad[0]], o["hits"][bad[0]])
+    assert fl.mean() <= max_flag_frac
+    ok = ~fl[:, None] & np.isfinite(o["score"])
+    d = np.abs(np.where(ok, gs["score"], 0.0) - np.where(ok, o["score"], 0.0))
+    lim = 1e-3 + KS.RANK_SIGMAS * o["score_err"]
+    assert (d <= lim).all(), (d.max(), np.unravel_index(np.argmax(d - lim), d.shape))
+    mask = ~O.FP64_FALLBACK
+    assert np.array_equal((gs["status"] & mask)[~fl], (o["status"] & mask)[~fl])
+    return same
+
+
+def test_search_parity_2000_seeds(ctx, kf):
+    say("search parity 2000 seeds")
+    wl, ev, g, pools, p, C, q = search_inputs(2000)
+    o = KS.score_hits(p, C, q, np.full(2000, SEED_LAYER), PLAN, g, pools, default_params(g))
+    gs = gpu_search(ctx, kf, g, pools, p, C, q)
+    compare(gs, o)
+    # final states of the unflagged rank-0 candidates
+    n = 2000
+    ok = ~o["flagged"] & np.isfinite(o["score"][:, 0])
+    st = gs["state"].reshape(6, n, 6)[:, :, 0].T
+    d = np.abs(st - o["p"][:, 0])
+    d[:, 4] = np.abs(np.angle(np.exp(1j * (st[:, 4] - o["p"][:, 0, 4]))))
+    rel = d / np.maximum(np.abs(o["p"][:, 0]), [1, 1, 1, 0.1, 1, 1])
+    assert rel[ok].max() <= 1e-4, rel[ok].max()
+
+
+def test_search_full_size_sampled(ctx, kf):
+    """20,000 seeds against the full pools on the GPU; the oracle runs a
+    sample of the seeds (each seed's search is independent of the others)."""
+    say("search full size")
+    wl, ev, g, pools, p, C, q = search_inputs()
+    assert p.shape[0] == 20000
+    gs = gpu_search(ctx, kf, g, pools, p, C, q)
+    pick = np.random.default_rng(4).choice(20000, 400, replace=False)
+    o = KS.score_hits(p[pick], C[pick], q[pick], np.full(pick.size, SEED_LAYER), PLAN, g, pools, default_params(g))
+    sub = {k: v[pick] for k, v in gs.items() if k != "state"}
+    compare(sub, o)
+
+
+def test_duplicated_hits_rank_by_id_on_the_gpu(ctx, kf):
+    say("search duplicate ties")
+    wl, ev, g, pools, p, C, q = search_inputs(60, noise=False)
+    P = _tiny_pools(ev, pools, list(range(60)), set(PLAN), offsets=(0.0,))
+    o = KS.score_hits(p, C, q, np.full(60, SEED_LAYER), PLAN, g, P, default_params(g))
+    gs = gpu_search(ctx, kf, g, P, p, C, q)
+    assert not o["flagged"].any()
+    assert np.array_equal(gs["hits"], o["hits"])
+    for t in range(60):
+        assert (gs["score"][t] == gs["score"][t, 0]).all()
+
+
+def test_misses_and_stops_on_the_gpu(ctx, kf):
+    say("search misses / stops")
+    wl, ev, g, pools, p, C, q = search_inputs(200, noise=False)
+    for drop in ([6, 7], [6, 7, 8, 9], [18, 19]):
+        P = _drop_layers(pools, drop)
+        o = KS.score_hits(p, C, q, np.full(200, SEED_LAYER), PLAN, g, P, default_params(g))
+        gs = gpu_search(ctx, kf, g, P, p, C, q)
+        compare(gs, o)
+        if len(drop) == 4:
+            assert (gs["hits"] == KS.STOP).any()
+
+
+@pytest.mark.parametrize("beam,plan", [(1, PLAN), (8, PLAN), (6, PLAN[:1]), (3, PLAN[::2])])
+def test_search_beams_and_plans(ctx, kf, beam, plan):
+    say("search beam", beam, "plan", len(plan))
+    wl, ev, g, pools, p, C, q = search_inputs(500)
+    prm = default_params(g, beam=beam)
+    o = KS.score_hits(p, C, q, np.full(500, SEED_LAYER), plan, g, pools, prm)
+    gs = gpu_search(ctx, kf, g, pools, p, C, q, plan=plan, beam=beam)
+    compare(gs, o)
+
+
+def test_search_is_deterministic(ctx, kf):
+    wl, ev, g, pools, p, C, q = search_inputs(3000)
+    a = gpu_search(ctx, kf, g, pools, p, C, q)
+    b = gpu_search(ctx, kf, g, pools, p, C, q)
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_search_empty_pool_and_empty_batch(ctx, kf):
+    wl, ev, g, pools, p, C, q = search_inputs(50, noise=False)
+    P = _drop_layers(pools, PLAN)
+    o = KS.score_hits(p, C, q, np.full(50, SEED_LAYER), PLAN, g, P, default_params(g))
+    gs = gpu_search(ctx, kf, g, P, p, C, q)
+    assert np.array_equal(gs["hits"], o["hits"])
+    assert (gs["hits"][:, 0, :3] == KS.MISS).all() and (gs["hits"][:, 0, 3:] == KS.STOP).all()
+    e = gpu_search(ctx, kf, g, pools, p[:0], C[:0], q[:0])
+    assert e["hits"].shape == (0, 6, len(PLAN))
