@@ -103,13 +103,17 @@ def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
 
     best, table = tune_fit(ctx, fit_step, torch.float32, n, use_cache=not args.retune, cache_path=args.tune_cache)
     log("autotune mixed26", best, [(s_, round(ms, 4)) for s_, ms in table])
+    ms_direct = time_loop(fit_step, args.steps, args.warmup)
+    ctx.set_fit_graph(True)
     ms = time_loop(fit_step, args.steps, args.warmup)
+    ctx.set_fit_graph(False)
     flops = algorithmic_flops(ev)
     lens = ev.lengths()
     return {"tracks": n, "entries": int(ev.n_hits), "valid": int(ev.hit_valid.sum()),
             "length_min": int(lens.min()), "length_max": int(lens.max()), "ms_fit": ms,
             "tracks_per_s": n / (ms * 1e-3), "achieved_tflops": flops / (ms * 1e-3) / 1e12,
-            "frac_fp32_peak": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, "launch": list(best)}
+            "frac_fp32_peak": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, "launch": list(best), "graph": True,
+            "ms_fit_direct_launches": ms_direct}
 
 
 def bench_adjoint(ctx, K, generate, workloads, args, seg=5):
@@ -163,6 +167,48 @@ def bench_adjoint(ctx, K, generate, workloads, args, seg=5):
             "checkpoint_bytes": ck.numel() * 4, "grad_align_finite": bool(torch.isfinite(ga).all().item())}
 
 
+def bench_search(ctx, K, args, sample=300):
+    """Combinatorial candidate search: 20,000 seeds (Kalman fit of each
+    track's first three hits) over 17 barrel layers whose pools hold the true
+    hits plus uniform noise at 2 hits/cm^2, beam 6.  The timed call includes
+    the binning of the pools.  A sample of the seeds is checked against the
+    FP64 search oracle (bit-exact hit lists on the seeds it does not flag)."""
+    import torch
+    from oracle import kf_search as KS
+    from search_common import PLAN, SEED_LAYER, default_params, search_inputs
+    dev = torch.device("cuda", 0)
+    log("generating search20")
+    wl, ev, g, pools, p, C, q = search_inputs()
+    n = p.shape[0]
+    IL = [(i, j) for i in range(6) for j in range(i + 1)]
+    f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt).contiguous()
+    st, cv = f(p.T, torch.float32), f(np.stack([C[:, i, j] for i, j in IL]), torch.float32)
+    qq, sl = f(q, torch.int8), f(np.full(n, SEED_LAYER), torch.int16)
+    pp, pc, pid = f(pools.pos, torch.float32), f(pools.cov, torch.float32), f(pools.hit_id, torch.int32)
+    prm = K.SearchParams(g.n_layers, beam=6)
+    geom = K.Geometry.from_toy(g)
+    out = []
+
+    def step():
+        out[:] = ctx.score_hits(st, cv, qq, sl, PLAN, geom, prm, pools.layer_offsets, pp, pc, pid)
+
+    ms = time_loop(step, args.steps, args.warmup)
+    hits = out[0].cpu().numpy()
+    res = {"seeds": n, "layers": len(PLAN), "beam": prm.beam, "pool_hits": int(pools.pos.shape[1]), "ms": ms,
+           "seeds_per_s": n / (ms * 1e-3)}
+    if not args.no_accuracy:
+        pick = np.random.default_rng(7).choice(n, sample, replace=False)
+        o = KS.score_hits(p[pick], C[pick], q[pick], np.full(sample, SEED_LAYER), PLAN, g, pools, default_params(g))
+        same = np.all(hits[pick] == o["hits"], axis=(1, 2))
+        fl = o["flagged"]
+        true_frac = float(np.mean([[h >= 0 and pools.track[h] == t for h in hits[t, 0]] for t in pick]))
+        res["parity_sample"] = {"seeds": sample, "flagged": int(fl.sum()), "identical": int(same.sum()),
+                                "unflagged_mismatch": int((~same & ~fl).sum()),
+                                "rank0_true_hit_fraction": true_frac,
+                                "window_hits_per_candidate_layer": o["n_window_hits"] / (sample * len(PLAN))}
+    return res
+
+
 def profile_only(args, K, tune_fit, generate, workloads):
     """Launch one fit configuration --steps times and nothing else (the
     launch shape comes from the autotune cache when present)."""
@@ -206,6 +252,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 500k-track barrel+endcap workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint workload")
+    ap.add_argument("--no-search", action="store_true", help="skip the combinatorial search workload")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "kf_autotune.json"))
     ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32"],
@@ -254,9 +301,12 @@ def main():
         best, table = tune_fit(ctx, fit_step, dt, n, use_cache=not args.retune, cache_path=args.tune_cache)
         log("autotune", dt, "best", best, "table", [(s_, round(ms, 4)) for s_, ms in table])
         log("timing", dt)
+        ms_fit_direct = time_loop(fit_step, args.steps, args.warmup)
+        ctx.set_fit_graph(True)
         ms_step = time_loop(step, args.steps, args.warmup)
         ms_fit = time_loop(fit_step, args.steps, args.warmup)
-        res[dt] = dict(ms_step=ms_step, ms_fit=ms_fit, out=out, seeds=seeds, launch=best)
+        ctx.set_fit_graph(False)
+        res[dt] = dict(ms_step=ms_step, ms_fit=ms_fit, ms_fit_direct=ms_fit_direct, out=out, seeds=seeds, launch=best)
         log(dt, "ms/step", ms_step, "fit kernel ms", ms_fit)
 
     r32, r64 = res[torch.float32], res[torch.float64]
@@ -281,7 +331,8 @@ def main():
         "fp64_gpu": {"value": n / (r64["ms_step"] * 1e-3), "unit": "tracks/s", "ms_per_step": r64["ms_step"]},
         "fp32_over_fp64": r64["ms_step"] / r32["ms_step"],
         "launch": {"fp32": list(r32["launch"]), "fp64": list(r64["launch"]),
-                   "fields": ["block", "persistent", "blocks_per_cu", "waves_per_simd"]},
+                   "fields": ["block", "persistent", "blocks_per_cu", "waves_per_simd", "layout"],
+                   "graph": True, "ms_fit_fp32_direct_launches": r32["ms_fit_direct"]},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP32_PEAK_TFLOPS, "traffic": None,
                      "kernel": "fit_kernel<float>", "kernel_ms": r32["ms_fit"],
@@ -302,6 +353,8 @@ def main():
         line["uneven_mixed26"] = bench_uneven(ctx, K, tune_fit, generate, workloads, args)
     if not args.no_adjoint:
         line["fwd_adjoint_align20"] = bench_adjoint(ctx, K, generate, workloads, args)
+    if not args.no_search:
+        line["search20"] = bench_search(ctx, K, args)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(ev)

@@ -292,6 +292,16 @@ int kf_set_fit_launch(kf_ctx *ctx, kf_precision prec, int32_t block, int32_t per
                       int32_t waves, int32_t layout);
 int kf_get_fit_launch(const kf_ctx *ctx, kf_precision prec, int32_t *block, int32_t *persistent,
                       int32_t *blocks_per_cu, int32_t *waves, int32_t *layout);
+/* Graph replay of kf_fit_tracks (enable = 1; 0 turns it off and frees the
+ * cached graphs).  The first call with a given set of arguments (pointers,
+ * sizes, precision, launch shape, layout) captures its whole launch sequence
+ * -- sort and pack passes, counter reset, fit kernel -- into a hipGraph on a
+ * context-owned stream; later calls with the same arguments replay it on the
+ * caller's stream as one graph launch.  Any change of an argument captures
+ * again; kf_reserve drops the cached graphs.  Results are identical to the
+ * direct launches. */
+int kf_set_fit_graph(kf_ctx *ctx, int32_t enable);
+
 /* Number of compute units of the context's device. */
 int kf_device_cu_count(const kf_ctx *ctx, int32_t *n_cu);
 

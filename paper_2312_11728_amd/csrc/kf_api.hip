@@ -24,7 +24,7 @@ struct kf_ctx {
   bool use_graph[2] = {false, false};
   hipStream_t capture = nullptr;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
-  std::string key[2];
+  std::vector<unsigned char> key[2];   // launch arguments the graph was captured with
   // workspace of the packed hit layout (kf_reserve)
   void* work_mem = nullptr;
   kf::PackWork work{};
@@ -262,6 +262,7 @@ kf::FitArgs<T> make_fit_args(int64_t n, int64_t ld, const void* seed_state, cons
                              int32_t* ndf, void* ckpt, int32_t seg, int32_t n_seg, uint32_t* trk_status,
                              int32_t* counter) {
   kf::FitArgs<T> a;
+  std::memset(&a, 0, sizeof(a));   // padding too: the bytes key the graph cache
   a.n = n;
   a.ld = ld;
   a.n_hits = n_hits;
@@ -291,9 +292,70 @@ kf::FitArgs<T> make_fit_args(int64_t n, int64_t ld, const void* seed_state, cons
   return a;
 }
 
+// The launch sequence of one fit: the optional sort / pack passes, then the
+// fit kernel (with the tile-counter reset of the persistent form).
+template <typename T>
+hipError_t run_fit(kf_ctx* ctx, kf::FitArgs<T> a, const kf::GeomArgs& g, const kf::FitLaunch& l, int layout,
+                   hipStream_t s) {
+  if (layout != 0) {
+    hipError_t e = kf::launch_pack(a, ctx->work, layout, &a.pk, s);
+    if (e != hipSuccess) return e;
+  }
+  a.packed = layout;
+  return kf::launch_fit(a, g, l, ctx->n_cu, s);
+}
+
+// With graphs enabled, the sequence is captured once on the context's
+// capture stream and replayed on the caller's stream while every launch
+// argument stays the same (any change re-captures).  The sequence clears its
+// counters with kernels, so a replay needs no host-side work.
+template <typename T>
+hipError_t run_fit_graph(kf_ctx* ctx, int pi, const kf::FitArgs<T>& a, const kf::GeomArgs& g,
+                         const kf::FitLaunch& l, int layout, hipStream_t s) {
+  std::vector<unsigned char> key(sizeof(a) + sizeof(g) + sizeof(l) + sizeof(layout));
+  unsigned char* k = key.data();
+  std::memcpy(k, &a, sizeof(a));
+  std::memcpy(k + sizeof(a), &g, sizeof(g));
+  std::memcpy(k + sizeof(a) + sizeof(g), &l, sizeof(l));
+  std::memcpy(k + sizeof(a) + sizeof(g) + sizeof(l), &layout, sizeof(layout));
+  if (!ctx->exec[pi] || key != ctx->key[pi]) {
+    if (ctx->exec[pi]) hipGraphExecDestroy(ctx->exec[pi]);
+    ctx->exec[pi] = nullptr;
+    ctx->key[pi].clear();
+    hipError_t e = hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t er = run_fit(ctx, a, g, l, layout, ctx->capture);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->capture, &graph);
+    if (er == hipSuccess) er = e;
+    if (er == hipSuccess) er = hipGraphInstantiate(&ctx->exec[pi], graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (er != hipSuccess) {
+      ctx->exec[pi] = nullptr;
+      return er;
+    }
+    ctx->key[pi] = key;
+  }
+  return hipGraphLaunch(ctx->exec[pi], s);
+}
+
 }  // namespace
 
 extern "C" {
+
+int kf_set_fit_graph(kf_ctx* ctx, int32_t enable) {
+  KF_REQUIRE(ctx);
+  if (enable != 0 && enable != 1) return fail(KF_ERR_ARG, "enable must be 0 or 1");
+  for (int i = 0; i < 2; ++i) {
+    ctx->use_graph[i] = enable != 0;
+    if (!enable && ctx->exec[i]) {
+      hipGraphExecDestroy(ctx->exec[i]);
+      ctx->exec[i] = nullptr;
+      ctx->key[i].clear();
+    }
+  }
+  return ok();
+}
 
 int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state, const void* seed_cov,
                   const int8_t* seed_charge, const int32_t* hit_offsets, const int16_t* hit_layer,
@@ -334,24 +396,19 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   const kf::FitLaunch l = ctx->fit[pi];
   const bool room = ctx->work.cap > 0 && n <= ctx->work.max_tracks && max_len <= ctx->work.max_len;
   const int layout = room ? l.layout : 0;
-  const bool packed = layout != 0;
   hipError_t e;
   if (prec == KF_F32) {
     auto a = make_fit_args<float>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, n_hits,
                                   hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf, checkpoints, seg,
                                   n_seg, trk_status, ctx->d_counter);
     a.max_len = max_len;
-    if (packed && (e = kf::launch_pack(a, ctx->work, layout, &a.pk, s)) != hipSuccess) return hip_fail(e, "kf_fit_tracks");
-    a.packed = layout;
-    e = kf::launch_fit(a, g, l, ctx->n_cu, s);
+    e = ctx->use_graph[pi] ? run_fit_graph(ctx, pi, a, g, l, layout, s) : run_fit(ctx, a, g, l, layout, s);
   } else {
     auto a = make_fit_args<double>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
                                    n_hits, hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf,
                                    checkpoints, seg, n_seg, trk_status, ctx->d_counter);
     a.max_len = max_len;
-    if (packed && (e = kf::launch_pack(a, ctx->work, layout, &a.pk, s)) != hipSuccess) return hip_fail(e, "kf_fit_tracks");
-    a.packed = layout;
-    e = kf::launch_fit(a, g, l, ctx->n_cu, s);
+    e = ctx->use_graph[pi] ? run_fit_graph(ctx, pi, a, g, l, layout, s) : run_fit(ctx, a, g, l, layout, s);
   }
   if (e != hipSuccess) return hip_fail(e, "kf_fit_tracks");
   return ok();
@@ -364,6 +421,12 @@ int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {
   int prev = 0;
   hipGetDevice(&prev);
   hipSetDevice(ctx->device);
+  // captured fit graphs point into the old workspace
+  for (int i = 0; i < 2; ++i) {
+    if (ctx->exec[i]) hipGraphExecDestroy(ctx->exec[i]);
+    ctx->exec[i] = nullptr;
+    ctx->key[i].clear();
+  }
   if (ctx->work_mem) {
     hipFree(ctx->work_mem);
     ctx->work_mem = nullptr;

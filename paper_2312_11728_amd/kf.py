@@ -26,7 +26,7 @@ MAX_LAYERS = 64
 
 EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_propagate", "kf_update",
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
-           "kf_device_cu_count", "kf_reserve"]
+           "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph"]
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
     lib.kf_device_cu_count.argtypes = [_vp, ctypes.POINTER(_i32)]
     lib.kf_reserve.argtypes = [_vp, _i64, _i32]
+    lib.kf_set_fit_graph.argtypes = [_vp, _i32]
     return lib
 
 
@@ -194,6 +195,10 @@ class Context:
     # ---- tuning -----------------------------------------------------------
     def set_fit_launch(self, dtype, block, persistent, blocks_per_cu, waves=1, layout=0):
         _check(lib().kf_set_fit_launch(self.handle, _prec(dtype), block, persistent, blocks_per_cu, waves, layout))
+
+    def set_fit_graph(self, enable=True):
+        """Replay kf_fit_tracks from a captured hipGraph (see kf_set_fit_graph)."""
+        _check(lib().kf_set_fit_graph(self.handle, int(bool(enable))))
 
     def get_fit_launch(self, dtype):
         b, p, k, w, l = _i32(), _i32(), _i32(), _i32(), _i32()

@@ -361,3 +361,51 @@ def test_fit_alignment_parity(ctx, kf):
         o = oracle_fit(ev, dt, 0, align=al)
         mask = ~ill_conditioned(ev, dt, o, 0, *tol, align=al)
         say(compare_fit(g, o, tol[0], tol[1], mask, tail_frac=0.002 if dt == torch.float32 else 0.0))
+
+
+@pytest.mark.parametrize("layout,persistent", [(2, 1), (0, 1), (1, 0)])
+def test_fit_graph_replay_matches_direct_launches(kf, layout, persistent):
+    """Graph replays (several, with the program's own eager work and
+    synchronisations between them) give the direct launches' results bit for
+    bit; changing an argument captures a new graph."""
+    say("fit graph replay", layout, persistent)
+    ev = generate(workloads()["mixed26"], 30_000)
+    dev = torch.device("cuda", 0)
+    t = kf.event_tensors(ev, torch.float32, dev)
+    geom = kf.Geometry.from_toy(ev.geometry)
+    c = kf.Context(0)
+    try:
+        c.reserve(ev.n_tracks, 26)
+        c.set_fit_launch(torch.float32, 128, persistent, 4, 1, layout)
+        st, cov, q, _ = c.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"], ev.geometry.bz, 1)
+        args = (st, cov, q, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"], geom)
+        ref = c.fit_tracks(*args)
+        ref = {k: v.clone() for k, v in ref.items()}
+        c.set_fit_graph(True)
+        out = kf.fit_outputs(ev.n_tracks, torch.float32, dev)
+        for rep in range(4):
+            for v in out.values():
+                v.fill_(-7)
+            c.fit_tracks(*args, out=out)
+            junk = torch.randn(1 << 20, device=dev).sum()   # eager work between replays
+            torch.cuda.synchronize()
+            for k in ref:
+                assert torch.equal(ref[k], out[k]), (rep, k)
+        # a different output buffer: captured again, same results
+        out2 = c.fit_tracks(*args)
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(ref[k], out2[k]), k
+        # a smaller batch through the same graph cache
+        n2 = 1000
+        sub = c.fit_tracks(st[:, :n2].contiguous(), cov[:, :n2].contiguous(), q[:n2].contiguous(),
+                           t["hit_offsets"][:n2 + 1].contiguous(), t["hit_layer"], t["hit_valid"], t["hit_pos"],
+                           t["hit_cov"], geom)
+        torch.cuda.synchronize()
+        assert torch.equal(sub["chi2"], ref["chi2"][:n2])
+        c.set_fit_graph(False)
+        again = c.fit_tracks(*args)
+        torch.cuda.synchronize()
+        assert torch.equal(again["state"], ref["state"])
+    finally:
+        c.close()
