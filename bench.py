@@ -210,10 +210,19 @@ def bench_search(ctx, K, args, sample=300):
 
 
 def profile_only(args, K, tune_fit, generate, workloads):
-    """Launch one fit configuration --steps times and nothing else (the
+    """Launch one configuration --steps times and nothing else (the fit's
     launch shape comes from the autotune cache when present)."""
     import torch
     dev = torch.device("cuda", 0)
+    if args.profile_only in ("adjoint", "search"):
+        ctx = K.Context(0)
+        a = argparse.Namespace(**vars(args))
+        a.warmup = 1
+        a.no_accuracy = True
+        r = bench_adjoint(ctx, K, generate, workloads, a) if args.profile_only == "adjoint" else \
+            bench_search(ctx, K, a)
+        log("profile-only", args.profile_only, json.dumps(r))
+        return
     name = "mixed26" if args.profile_only == "mixed32" else "barrel20"
     dt = torch.float64 if args.profile_only == "fit64" else torch.float32
     wl = workloads()[name]
@@ -255,7 +264,7 @@ def main():
     ap.add_argument("--no-search", action="store_true", help="skip the combinatorial search workload")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "kf_autotune.json"))
-    ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32"],
+    ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32", "adjoint", "search"],
                     help="only launch the named fit --steps times (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
