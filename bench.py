@@ -170,9 +170,10 @@ def bench_adjoint(ctx, K, generate, workloads, args, seg=5):
 def bench_search(ctx, K, args, sample=300):
     """Combinatorial candidate search: 20,000 seeds (Kalman fit of each
     track's first three hits) over 17 barrel layers whose pools hold the true
-    hits plus uniform noise at 2 hits/cm^2, beam 6.  The timed call includes
-    the binning of the pools.  A sample of the seeds is checked against the
-    FP64 search oracle (bit-exact hit lists on the seeds it does not flag)."""
+    hits plus uniform noise at 2 hits/cm^2, beam 6.  Timed with the pool's
+    bins reused (the search proper) and with the binning.  A sample of the
+    seeds is checked against the FP64 search oracle (bit-exact hit lists on
+    the seeds it does not flag)."""
     import torch
     from oracle import kf_search as KS
     from search_common import PLAN, SEED_LAYER, default_params, search_inputs
@@ -185,17 +186,19 @@ def bench_search(ctx, K, args, sample=300):
     st, cv = f(p.T, torch.float32), f(np.stack([C[:, i, j] for i, j in IL]), torch.float32)
     qq, sl = f(q, torch.int8), f(np.full(n, SEED_LAYER), torch.int16)
     pp, pc, pid = f(pools.pos, torch.float32), f(pools.cov, torch.float32), f(pools.hit_id, torch.int32)
-    prm = K.SearchParams(g.n_layers, beam=6)
     geom = K.Geometry.from_toy(g)
     out = []
 
-    def step():
+    def run(prm):
         out[:] = ctx.score_hits(st, cv, qq, sl, PLAN, geom, prm, pools.layer_offsets, pp, pc, pid)
 
-    ms = time_loop(step, args.steps, args.warmup)
+    prm_bin = K.SearchParams(g.n_layers, beam=6)
+    prm_reuse = K.SearchParams(g.n_layers, beam=6, reuse_bins=True)
+    ms_total = time_loop(lambda: run(prm_bin), args.steps, args.warmup)
+    ms = time_loop(lambda: run(prm_reuse), args.steps, args.warmup)
     hits = out[0].cpu().numpy()
-    res = {"seeds": n, "layers": len(PLAN), "beam": prm.beam, "pool_hits": int(pools.pos.shape[1]), "ms": ms,
-           "seeds_per_s": n / (ms * 1e-3)}
+    res = {"seeds": n, "layers": len(PLAN), "beam": 6, "pool_hits": int(pools.pos.shape[1]), "ms": ms,
+           "seeds_per_s": n / (ms * 1e-3), "ms_with_binning": ms_total, "ms_binning": ms_total - ms}
     if not args.no_accuracy:
         pick = np.random.default_rng(7).choice(n, sample, replace=False)
         o = KS.score_hits(p[pick], C[pick], q[pick], np.full(sample, SEED_LAYER), PLAN, g, pools, default_params(g))

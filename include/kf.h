@@ -193,6 +193,9 @@ typedef struct {
   int32_t max_miss;      /* a candidate with this many misses gets no miss child (0..100) */
   float sigma_rphi, sigma_z;  /* nominal hit resolution added to the window (cm, >= 0) */
   const float *win_min_rphi, *win_max_rphi, *win_min_z, *win_max_z; /* [n_layers] cm, HOST, 0 < min <= max */
+  int32_t reuse_bins;    /* 1: the caller promises the pool's contents are unchanged since the last
+                            call on this context; the pool is then binned again only if its
+                            pointers, sizes, layer offsets or the geometry differ.  0: always bin. */
 } kf_search_params;
 
 /* Combinatorial candidate search with chi2 scoring of the candidate hits
@@ -221,7 +224,8 @@ typedef struct {
  * ids, which must be distinct, are what the output reports and what breaks
  * ties).  The call bins the pool by (layer, phi, z) into a context-owned
  * workspace (about 64 bytes per pool hit and per candidate slot; grown on
- * demand, KF_ERR_NOMEM if that fails).
+ * demand, KF_ERR_NOMEM if that fails), unless params->reuse_bins allows the
+ * bins of the previous call to be used.
  * Outputs: cand_hits[n][beam][plan_len] (hit id, -1 = miss; -2 for every
  * entry of a rank the seed has no candidate for), cand_score[n][beam]
  * (-inf for none), cand_state[6][n*beam] (column seed*beam + rank; the final
@@ -258,9 +262,9 @@ int kf_score_hits(kf_ctx *ctx, int64_t n, int64_t ld,
  * align NULL it is the gradient at zero offsets).
  * trk_status[n]: the status kf_fit_tracks returned; tracks it stopped
  * (NO_CROSSING, NONFINITE, bad layer id) contribute only up to the entry
- * where they stopped.  Uses a context-owned buffer of
- * 2 * 64 * ceil(n_hits / 4096) values for the alignment reduction (allocated
- * on first need, KF_ERR_NOMEM if that fails). */
+ * where they stopped.  Uses a context-owned buffer of 2 * 64 * ceil(n / 64)
+ * values for the alignment reduction (allocated on first need, KF_ERR_NOMEM
+ * if that fails). */
 int kf_fit_adjoint(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                    const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
                    const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,

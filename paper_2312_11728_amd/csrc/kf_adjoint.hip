@@ -22,74 +22,59 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs<T> a, GeomArgs g) 
                 t, acc, len, e0);
 }
 
-// Sum over the 64 lanes of a wave by a fixed butterfly.
+// Stage 1: one wave per 64 consecutive tracks.  A barrel hit h with gradient
+// hb contributes (h_x hb_y - h_y hb_x)/R to the r-phi offset of its layer (the
+// rotation m = R(a/R) h keeps the cross product) and hb_z to the z offset;
+// disk hits and holes contribute 0.  Each lane walks its track's entries and
+// adds into its own LDS column; then lane l adds the 64 columns of layer l in
+// lane order.  Fixed order throughout: the result does not depend on
+// scheduling.
 template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Stage 1: block b sums the contributions of hits [b, b+1) * kAlignChunk per
-// layer.  A barrel hit h with gradient hb contributes (h_x hb_y - h_y hb_x)/R
-// to the r-phi offset of its layer (the rotation m = R(a/R) h keeps the
-// cross product) and hb_z to the z offset; disk hits and holes contribute 0.
-// Each wave takes 64 consecutive hits at a time and, for every layer present
-// among them, adds the wave sum of that layer's contributions into its own
-// LDS row; the four rows are then added in a fixed order.
-template <typename T>
-__global__ void __launch_bounds__(256) align_partial_kernel(AdjArgs<T> a, GeomArgs g) {
-  __shared__ T part[4][2][kMaxLayers];
-  for (int i = threadIdx.x; i < 4 * 2 * kMaxLayers; i += blockDim.x) (&part[0][0][0])[i] = T(0);
-  __syncthreads();
-  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+__global__ void __launch_bounds__(64) align_partial_kernel(AdjArgs<T> a, GeomArgs g) {
+  __shared__ T part[2][kMaxLayers][64];
+  const int lane = threadIdx.x;
+  for (int l = 0; l < kMaxLayers; ++l) {
+    part[0][l][lane] = T(0);
+    part[1][l][lane] = T(0);
+  }
+  const int64_t t = int64_t(blockIdx.x) * 64 + lane;
   const int64_t nh = a.f.n_hits;
-  const int64_t base = int64_t(blockIdx.x) * kAlignChunk + int64_t(wv) * (kAlignChunk / 4);
-  for (int b = 0; b < kAlignChunk / 4; b += 64) {
-    const int64_t e = base + b + lane;
-    int lay = -1;
-    T cr = T(0), cz = T(0);
-    if (e < nh && a.f.hit_valid[e]) {
+  if (t < a.f.n) {
+    const int64_t e0 = a.f.hit_offsets[t], e1 = a.f.hit_offsets[t + 1];
+    for (int64_t e = e0; e < e1; ++e) {
+      if (!a.f.hit_valid[e]) continue;
       const int l = a.f.hit_layer[e];
-      if (l >= 0 && l < g.n_layers && g.kind[l] == 0) {
-        lay = l;
-        const T hx = a.f.hit_pos[e], hy = a.f.hit_pos[nh + e];
-        const T gx = a.grad_hit[e], gy = a.grad_hit[nh + e], gz = a.grad_hit[2 * nh + e];
-        cr = (hx * gy - hy * gx) / T(g.pos[l]);
-        cz = gz;
-      }
-    }
-    uint64_t rem = __ballot(lay >= 0);
-    while (rem) {
-      const int leader = __ffsll((unsigned long long)rem) - 1;
-      const int L = __shfl(lay, leader, 64);
-      const bool mine = (lay == L);
-      const T sr = wave_sum(mine ? cr : T(0));
-      const T sz = wave_sum(mine ? cz : T(0));
-      if (lane == 0) {
-        part[wv][0][L] += sr;
-        part[wv][1][L] += sz;
-      }
-      rem &= ~__ballot(mine);
+      if (l < 0 || l >= g.n_layers || g.kind[l] != 0) continue;
+      const T hx = a.f.hit_pos[e], hy = a.f.hit_pos[nh + e];
+      const T gx = a.grad_hit[e], gy = a.grad_hit[nh + e], gz = a.grad_hit[2 * nh + e];
+      part[0][l][lane] += (hx * gy - hy * gx) / T(g.pos[l]);
+      part[1][l][lane] += gz;
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 2 * kMaxLayers; i += blockDim.x) {
-    const int c = i / kMaxLayers, l = i % kMaxLayers;
-    a.partial[int64_t(blockIdx.x) * 2 * kMaxLayers + i] = ((part[0][c][l] + part[1][c][l]) + part[2][c][l]) + part[3][c][l];
+  T* out = a.partial + int64_t(blockIdx.x) * 2 * kMaxLayers;
+  for (int c = 0; c < 2; ++c) {
+    T acc = T(0);
+    for (int k = 0; k < 64; ++k) acc += part[c][lane][k];
+    out[c * kMaxLayers + lane] = acc;
   }
 }
 
-// Stage 2: one thread per (component, layer) adds the block partials in
-// block order.
+// Stage 2: one block per (component, layer): thread k adds the partials of
+// blocks k, k + 256, ... in order, then a fixed tree over the threads.
 template <typename T>
-__global__ void __launch_bounds__(128) align_final_kernel(AdjArgs<T> a, int32_t n_layers, int64_t n_blocks) {
-  const int i = threadIdx.x;
-  const int c = i / kMaxLayers, l = i % kMaxLayers;
-  if (c >= 2 || l >= n_layers) return;
+__global__ void __launch_bounds__(256) align_final_kernel(AdjArgs<T> a, int32_t n_layers, int64_t n_blocks) {
+  __shared__ T red[256];
+  const int c = blockIdx.x / n_layers, l = blockIdx.x % n_layers;
   T acc = T(0);
-  for (int64_t b = 0; b < n_blocks; ++b) acc += a.partial[b * 2 * kMaxLayers + i];
-  a.grad_align[c * n_layers + l] = acc;
+  for (int64_t b = threadIdx.x; b < n_blocks; b += 256) acc += a.partial[b * 2 * kMaxLayers + c * kMaxLayers + l];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.grad_align[c * n_layers + l] = red[0];
 }
 
 template <typename T>
@@ -101,9 +86,9 @@ hipError_t launch_adjoint(const AdjArgs<T>& a, const GeomArgs& g, hipStream_t s)
     if (e != hipSuccess) return e;
   }
   if (a.grad_align) {
-    const int64_t nb = adjoint_partial_blocks(a.f.n_hits);
-    if (nb > 0) hipLaunchKernelGGL(align_partial_kernel<T>, dim3(unsigned(nb)), dim3(256), 0, s, a, g);
-    hipLaunchKernelGGL(align_final_kernel<T>, dim3(1), dim3(128), 0, s, a, g.n_layers, nb);
+    const int64_t nb = adjoint_partial_blocks(a.f.n);
+    if (nb > 0) hipLaunchKernelGGL(align_partial_kernel<T>, dim3(unsigned(nb)), dim3(64), 0, s, a, g);
+    hipLaunchKernelGGL(align_final_kernel<T>, dim3(unsigned(2 * g.n_layers)), dim3(256), 0, s, a, g.n_layers, nb);
   }
   return hipGetLastError();
 }

@@ -31,9 +31,11 @@ struct kf_ctx {
   // block partials of the alignment-gradient reduction (grown on demand)
   void* red_mem = nullptr;
   size_t red_bytes = 0;
-  // workspace of the candidate search (grown on demand)
+  // workspace of the candidate search (grown on demand) and the identity of
+  // the pool its bins were built from
   void* search_mem = nullptr;
   size_t search_bytes = 0;
+  std::vector<unsigned char> bins_key;
 };
 
 namespace {
@@ -588,7 +590,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
   const int64_t nsum = n_bins / 2048 + 2;
   const int64_t b_bins = up(n_bins * 4), b_pool4 = up(n_pool * 4), b_sum = up(nsum * 4) + 256;
-  const int64_t b_pool = 4 * b_pool4 + up(n_pool * 6 * 4) + b_pool4 + up((n_bins + 1) * 4);
+  const int64_t b_pool = up(n_pool * int64_t(sizeof(kf::PoolHit))) + up((n_bins + 1) * 4);
   const int64_t b_slot = 2 * (up(S * 6 * 4) + up(S * 21 * 4) + up(S)) + 3 * up(S * kf::kMaxBeam * 4) + up(S * 4) +
                          up(S) + up(S) + up(S * 4) + up(S * 4) + up(S) + up(P * S) + up(P * S * 4);
   const int64_t total = b_bins + 2 * b_pool4 + b_sum + b_pool + b_slot;
@@ -599,6 +601,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
     if (ctx->search_mem) hipFree(ctx->search_mem);
     ctx->search_mem = nullptr;
     ctx->search_bytes = 0;
+    ctx->bins_key.clear();
     hipError_t e = hipMalloc(&ctx->search_mem, size_t(total));
     hipSetDevice(prev);
     if (e != hipSuccess) {
@@ -607,6 +610,16 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
     }
     ctx->search_bytes = size_t(total);
   }
+  // identity of the binned pool: pointers, sizes, layer offsets, bin table
+  std::vector<unsigned char> key(3 * sizeof(void*) + sizeof(n_pool) + sizeof(t));
+  {
+    unsigned char* k = key.data();
+    const void* ptrs[3] = {pool_pos, pool_cov, pool_hit_id};
+    std::memcpy(k, ptrs, sizeof(ptrs));
+    std::memcpy(k + sizeof(ptrs), &n_pool, sizeof(n_pool));
+    std::memcpy(k + sizeof(ptrs) + sizeof(n_pool), &t, sizeof(t));
+  }
+  const bool rebin = !(prm->reuse_bins == 1 && key == ctx->bins_key);
   char* q = (char*)ctx->search_mem;
   auto take = [&q](int64_t b) {
     char* r = q;
@@ -619,12 +632,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   w.rank = (int32_t*)take(b_pool4);
   w.block_sum = (int32_t*)take(up(nsum * 4));
   w.total = (int32_t*)take(256);
-  w.pool.x = (float*)take(b_pool4);
-  w.pool.y = (float*)take(b_pool4);
-  w.pool.z = (float*)take(b_pool4);
-  w.pool.phi = (float*)take(b_pool4);
-  w.pool.cov = (float*)take(up(n_pool * 6 * 4));
-  w.pool.id = (int32_t*)take(b_pool4);
+  w.pool.hits = (kf::PoolHit*)take(up(n_pool * int64_t(sizeof(kf::PoolHit))));
   w.pool.bin_off = (int32_t*)take(up((n_bins + 1) * 4));
   kf::SearchArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -643,12 +651,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   a.max_miss = prm->max_miss;
   a.bz = float(geom->bz_tesla);
   a.mass = float(geom->particle_mass_gev);
-  a.px = w.pool.x;
-  a.py = w.pool.y;
-  a.pz = w.pool.z;
-  a.pphi = w.pool.phi;
-  a.pcov = w.pool.cov;
-  a.pid = w.pool.id;
+  a.pool = w.pool.hits;
   a.bin_off = w.pool.bin_off;
   a.n_pool = n_pool;
   for (int k = 0; k < 2; ++k) {
@@ -692,7 +695,12 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
     sl.sig_z = prm->sigma_z;
   }
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = kf::launch_bin_pool(t, pool_pos, pool_cov, pool_hit_id, n_pool, n_bins, w, s);
+  hipError_t e = hipSuccess;
+  if (rebin) {
+    ctx->bins_key.clear();
+    e = kf::launch_bin_pool(t, pool_pos, pool_cov, pool_hit_id, n_pool, n_bins, w, s);
+    if (e == hipSuccess) ctx->bins_key = key;
+  }
   if (e == hipSuccess) e = kf::launch_search(a, layers.data(), plan_len, s);
   if (e != hipSuccess) return hip_fail(e, "kf_score_hits");
   return ok();
@@ -739,7 +747,7 @@ int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const 
   hipStream_t s = (hipStream_t)stream;
   const size_t esz = prec == KF_F32 ? 4 : 8;
   if (grad_align) {
-    const size_t need = size_t(kf::adjoint_partial_blocks(n_hits)) * 2 * kf::kMaxLayers * esz;
+    const size_t need = size_t(kf::adjoint_partial_blocks(n)) * 2 * kf::kMaxLayers * esz;
     if (need > ctx->red_bytes) {
       int prev = 0;
       hipGetDevice(&prev);

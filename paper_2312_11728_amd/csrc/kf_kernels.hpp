@@ -149,10 +149,10 @@ struct AdjArgs {
   T* grad_seed;                // [6][ld]
   T* grad_hit;                 // [3][n_hits]
   T* grad_align;               // [2][n_layers] or null
-  T* partial;                  // [adjoint_partial_blocks(n_hits)][2][kMaxLayers] when grad_align is set
+  T* partial;                  // [adjoint_partial_blocks(n)][2][kMaxLayers] when grad_align is set
 };
-constexpr int kAlignChunk = 4096;  // hits per block of the alignment reduction
-inline int64_t adjoint_partial_blocks(int64_t n_hits) { return (n_hits + kAlignChunk - 1) / kAlignChunk; }
+// blocks (64 tracks each) of the alignment reduction
+inline int64_t adjoint_partial_blocks(int64_t n_tracks) { return (n_tracks + 63) / 64; }
 template <typename T>
 hipError_t launch_adjoint(const AdjArgs<T>& a, const GeomArgs& g, hipStream_t s);
 

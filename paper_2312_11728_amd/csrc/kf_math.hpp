@@ -628,6 +628,68 @@ KF_HD void update_core(T p[6], T c[21], int& q, const T m[3], const T V[6], T& c
     st |= TRK_COV_NOT_PSD;
 }
 
+// The same update in FP64 for one FP32 lane, with fewer live values: the
+// Joseph form expanded element by element, (I-KH) C (I-KH)^T + K V K^T =
+// C - K B^T - B K^T + K S K^T with B = C H^T (it holds for any K), so only K,
+// S and the packed C are kept.
+KF_HD inline void update_lane_fp64(float p[6], float c[21], int& q, const float m[3], const float V[6], float& chi2,
+                                   uint32_t& st) {
+  double S[6], Si[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) S[sym(i, j)] = double(c[sym(i, j)]) + double(V[sym(i, j)]);
+  inv3(S, Si);
+  const double r[3] = {double(m[0]) - p[0], double(m[1]) - p[1], double(m[2]) - p[2]};
+  double K[6][3];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      K[i][k] = double(c[sym(i, 0)]) * Si[sym(0, k)] + double(c[sym(i, 1)]) * Si[sym(1, k)] +
+                double(c[sym(i, 2)]) * Si[sym(2, k)];
+  double c2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) c2 += r[i] * (Si[sym(i, 0)] * r[0] + Si[sym(i, 1)] * r[1] + Si[sym(i, 2)] * r[2]);
+  chi2 = float(c2);
+  // entry (i, j) of C' needs c(i, j) and rows i, j of B = C[:, 0:3]: B is
+  // copied first, then C is overwritten in place
+  float B[6][3];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) B[i][k] = c[sym(i, k)];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double KSj[3];   // row j of K S
+#pragma unroll
+    for (int k = 0; k < 3; ++k) KSj[k] = K[j][0] * S[sym(0, k)] + K[j][1] * S[sym(1, k)] + K[j][2] * S[sym(2, k)];
+#pragma unroll
+    for (int i = j; i < 6; ++i) {
+      double v = double(c[sym(i, j)]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v += -K[i][k] * double(B[j][k]) - double(B[i][k]) * K[j][k] + K[i][k] * KSj[k];
+      c[sym(i, j)] = float(v);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) p[i] = float(double(p[i]) + K[i][0] * r[0] + K[i][1] * r[1] + K[i][2] * r[2]);
+  if (p[3] < 0.f) {
+    p[3] = -p[3];
+    q = -q;
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (j != 3) c[sym(3, j)] = -c[sym(3, j)];
+    st |= TRK_CHARGE_FLIP;
+  }
+  p[4] = wrap_phi(p[4]);
+  const float tr = c[0] + c[2] + c[5];
+  if (!(c[sym(3, 3)] > 0.f) || !(c[sym(4, 4)] > 0.f) || !(c[sym(5, 5)] > 0.f) || c[0] < -1e-3f * tr ||
+      c[2] < -1e-3f * tr || c[5] < -1e-3f * tr)
+    st |= TRK_COV_NOT_PSD;
+  st |= TRK_FP64_FALLBACK;
+}
+
 // Kalman update.  The FP32 form moves a lane to FP64 when the prior position
 // variance exceeds the hit variance by more than kRatioMax on any axis (then the
 // FP32 posterior would keep fewer than ~3 significant digits).
@@ -636,22 +698,7 @@ KF_HD void update(T p[6], T c[21], int& q, const T m[3], const T V[6], T& chi2, 
   if constexpr (std::is_same<T, float>::value) {
     const float R = float(kRatioMax);
     if (c[0] > R * V[0] || c[2] > R * V[2] || c[5] > R * V[5]) {
-      double pd[6], cd[21], md[3], Vd[6], c2;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) pd[i] = double(p[i]);
-#pragma unroll
-      for (int i = 0; i < 21; ++i) cd[i] = double(c[i]);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) md[i] = double(m[i]);
-#pragma unroll
-      for (int i = 0; i < 6; ++i) Vd[i] = double(V[i]);
-      update_core<double>(pd, cd, q, md, Vd, c2, st);
-#pragma unroll
-      for (int i = 0; i < 6; ++i) p[i] = float(pd[i]);
-#pragma unroll
-      for (int i = 0; i < 21; ++i) c[i] = float(cd[i]);
-      chi2 = float(c2);
-      st |= TRK_FP64_FALLBACK;
+      update_lane_fp64(p, c, q, m, V, chi2, st);
       return;
     }
   }

@@ -106,7 +106,8 @@ __global__ void __launch_bounds__(256) scan_add_kernel(int32_t* out, int64_t n, 
   if (i == n) out[n] = total[0];
 }
 
-// copy every hit to its binned position (x, y, z, phi, covariance, id)
+// copy every hit to its binned position (x, y, z, phi, covariance, id: three
+// 16-byte stores)
 __global__ void __launch_bounds__(256) bin_scatter_kernel(BinTable t, const float* pos, const float* cov,
                                                           const int32_t* id, int64_t n, const int32_t* bin_off,
                                                           const int32_t* bin_of, const int32_t* rank, PoolBins o) {
@@ -114,13 +115,10 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(BinTable t, const floa
   if (h >= n) return;
   const int64_t d = int64_t(bin_off[bin_of[h]]) + rank[h];
   const float x = pos[h], y = pos[n + h];
-  o.x[d] = x;
-  o.y[d] = y;
-  o.z[d] = pos[2 * n + h];
-  o.phi[d] = atan2f(y, x);
-#pragma unroll
-  for (int i = 0; i < 6; ++i) o.cov[int64_t(i) * n + d] = cov[int64_t(i) * n + h];
-  o.id[d] = id[h];
+  float4* dst = reinterpret_cast<float4*>(o.hits + d);
+  dst[0] = make_float4(x, y, pos[2 * n + h], atan2f(y, x));
+  dst[1] = make_float4(cov[h], cov[n + h], cov[2 * n + h], cov[3 * n + h]);
+  dst[2] = make_float4(cov[4 * n + h], cov[5 * n + h], __int_as_float(id[h]), 0.f);
 }
 
 // ---- search ------------------------------------------------------------------

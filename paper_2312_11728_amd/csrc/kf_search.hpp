@@ -60,6 +60,15 @@ KF_HD inline int32_t z_bin(float z, float lo, float hi, int32_t nz) {
   return clamp_bin((z - lo) * (float(nz) / (hi - lo)), nz);
 }
 
+// One hit of the binned pool, 48 bytes: the window test reads the first 16,
+// the chi2 the rest.
+struct alignas(16) PoolHit {
+  float x, y, z, phi;
+  float cov[6];
+  int32_t id;
+  int32_t pad;
+};
+
 // Scalars of the layer being searched (one launch per layer).
 struct SearchLayer {
   int32_t layer;       // layer id
@@ -81,12 +90,7 @@ struct SearchArgs {
   int32_t max_miss;
   float bz, mass;
   // binned pool
-  const float* px;
-  const float* py;
-  const float* pz;
-  const float* pphi;
-  const float* pcov;             // [6][n_pool]
-  const int32_t* pid;            // caller's hit ids
+  const PoolHit* pool;           // [n_pool] in bin order
   const int32_t* bin_off;        // [n_bins + 1]
   int64_t n_pool;
   // slots (S = n * beam; slot = seed * beam + rank)
@@ -118,11 +122,12 @@ KF_HD inline bool child_before(float sa, int32_t ka, int32_t pa, float sb, int32
 }
 
 KF_HD inline void load_pool_hit(const SearchArgs& a, int32_t h, float m[3], float V[6]) {
-  m[0] = a.px[h];
-  m[1] = a.py[h];
-  m[2] = a.pz[h];
+  const PoolHit& ph = a.pool[h];
+  m[0] = ph.x;
+  m[1] = ph.y;
+  m[2] = ph.z;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) V[i] = a.pcov[int64_t(i) * a.n_pool + h];
+  for (int i = 0; i < 6; ++i) V[i] = ph.cov[i];
 }
 
 KF_HD inline void load_slot(const float* P, const float* C, const int8_t* Q, int64_t S, int64_t s, float p[6],
@@ -242,16 +247,17 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, int
       const int32_t h0 = a.bin_off[L.base + pb * L.nz + z0];
       const int32_t h1 = a.bin_off[L.base + pb * L.nz + z1 + 1];
       for (int32_t h = h0; h < h1; ++h) {
-        float d = a.pphi[h] - phi_p;
+        const PoolHit& ph = a.pool[h];
+        float d = ph.phi - phi_p;
         d = d > float(kPi) ? d - float(2 * kPi) : (d < -float(kPi) ? d + float(2 * kPi) : d);
-        if (!(k_abs(d) <= dphi) || !(k_abs(a.pz[h] - zp) <= w_z)) continue;
+        if (!(k_abs(d) <= dphi) || !(k_abs(ph.z - zp) <= w_z)) continue;
         float m[3], V[6];
         load_pool_hit(a, h, m, V);
         const float c2 = hit_chi2(p, c, m, V, st);
         if (!(c2 <= a.chi2_max)) continue;
         // insert (score, id) into the sorted list; the last entry drops out
         float ns = score + a.hit_bonus - c2;
-        int32_t nkey = a.pid[h], nidx = h;
+        int32_t nkey = ph.id, nidx = h;
 #pragma unroll
         for (int j = 0; j < kMaxBeam; ++j) {
           if (j < a.beam && child_before(ns, nkey, 0, ks[j], kk[j], 0)) {

@@ -9,12 +9,7 @@ namespace kf {
 
 // The binned copy of the hit pool.
 struct PoolBins {
-  float* x;
-  float* y;
-  float* z;
-  float* phi;
-  float* cov;        // [6][n]
-  int32_t* id;
+  PoolHit* hits;     // [n] in bin order
   int32_t* bin_off;  // [n_bins + 1]
 };
 

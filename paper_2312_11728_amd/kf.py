@@ -43,7 +43,8 @@ class KfSearchParams(ctypes.Structure):
     _fields_ = [("beam", ctypes.c_int32), ("chi2_max", ctypes.c_float), ("n_sigma", ctypes.c_float),
                 ("hit_bonus", ctypes.c_float), ("miss_penalty", ctypes.c_float), ("max_miss", ctypes.c_int32),
                 ("sigma_rphi", ctypes.c_float), ("sigma_z", ctypes.c_float),
-                ("win_min_rphi", _vp), ("win_max_rphi", _vp), ("win_min_z", _vp), ("win_max_z", _vp)]
+                ("win_min_rphi", _vp), ("win_max_rphi", _vp), ("win_min_z", _vp), ("win_max_z", _vp),
+                ("reuse_bins", ctypes.c_int32)]
 
 
 class SearchParams:
@@ -51,7 +52,8 @@ class SearchParams:
     per-layer window limits as arrays of n_layers (cm)."""
 
     def __init__(self, n_layers, beam=6, chi2_max=30.0, n_sigma=5.0, hit_bonus=10.0, miss_penalty=5.0, max_miss=3,
-                 sigma_rphi=0.003, sigma_z=0.01, win_min_rphi=0.01, win_max_rphi=2.0, win_min_z=0.03, win_max_z=2.0):
+                 sigma_rphi=0.003, sigma_z=0.01, win_min_rphi=0.01, win_max_rphi=2.0, win_min_z=0.03, win_max_z=2.0,
+                 reuse_bins=False):
         self.n_layers = n_layers
         self.beam, self.chi2_max, self.n_sigma = beam, chi2_max, n_sigma
         self.hit_bonus, self.miss_penalty, self.max_miss = hit_bonus, miss_penalty, max_miss
@@ -62,7 +64,7 @@ class SearchParams:
         p = lambda a: a.ctypes.data_as(_vp)
         self.struct = KfSearchParams(beam, chi2_max, n_sigma, hit_bonus, miss_penalty, max_miss, sigma_rphi, sigma_z,
                                      p(self.win_min_rphi), p(self.win_max_rphi), p(self.win_min_z),
-                                     p(self.win_max_z))
+                                     p(self.win_max_z), int(bool(reuse_bins)))
 
 
 class KfError(RuntimeError):

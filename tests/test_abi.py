@@ -137,7 +137,7 @@ def _search_call(**over):
     wmax = (ctypes.c_float * nl)(*([2.0] * nl))
     prm = kf.KfSearchParams(6, 30.0, 5.0, 10.0, 5.0, 3, 0.003, 0.01, ctypes.cast(wmin, ctypes.c_void_p),
                             ctypes.cast(wmax, ctypes.c_void_p), ctypes.cast(wmin, ctypes.c_void_p),
-                            ctypes.cast(wmax, ctypes.c_void_p))
+                            ctypes.cast(wmax, ctypes.c_void_p), 0)
     for k in [k for k in over if k.startswith("prm_")]:
         setattr(prm, k[4:], over.pop(k))
     plan = (ctypes.c_int16 * 2)(1, 2)

@@ -45,7 +45,7 @@ def ctx(kf):
     c.close()
 
 
-def gpu_search(ctx, kf, g, pools, p, C, q, plan=PLAN, beam=6, seeds=None):
+def gpu_search(ctx, kf, g, pools, p, C, q, plan=PLAN, beam=6, seeds=None, reuse=False, dev_pool=None):
     dev = ctx.device
     idx = np.arange(p.shape[0]) if seeds is None else np.asarray(seeds)
     f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt).contiguous()
@@ -53,11 +53,11 @@ def gpu_search(ctx, kf, g, pools, p, C, q, plan=PLAN, beam=6, seeds=None):
     cv = f(np.stack([C[idx][:, i, j] for i, j in IL]), torch.float32)
     qq = f(q[idx], torch.int8)
     sl = f(np.full(idx.size, SEED_LAYER), torch.int16)
-    prm = kf.SearchParams(g.n_layers, beam=beam)
+    prm = kf.SearchParams(g.n_layers, beam=beam, reuse_bins=reuse)
     geom = kf.Geometry.from_toy(g)
-    hits, score, state, status = ctx.score_hits(st, cv, qq, sl, plan, geom, prm, pools.layer_offsets,
-                                                f(pools.pos, torch.float32), f(pools.cov, torch.float32),
-                                                f(pools.hit_id, torch.int32))
+    if dev_pool is None:
+        dev_pool = (f(pools.pos, torch.float32), f(pools.cov, torch.float32), f(pools.hit_id, torch.int32))
+    hits, score, state, status = ctx.score_hits(st, cv, qq, sl, plan, geom, prm, pools.layer_offsets, *dev_pool)
     torch.cuda.synchronize()
     return dict(hits=hits.cpu().numpy().astype(np.int64), score=score.cpu().numpy().astype(np.float64),
                 state=state.cpu().numpy().astype(np.float64), status=status.cpu().numpy().astype(np.int64))
@@ -160,3 +160,22 @@ def test_search_empty_pool_and_empty_batch(ctx, kf):
     assert (gs["hits"][:, 0, :3] == KS.MISS).all() and (gs["hits"][:, 0, 3:] == KS.STOP).all()
     e = gpu_search(ctx, kf, g, pools, p[:0], C[:0], q[:0])
     assert e["hits"].shape == (0, 6, len(PLAN))
+
+
+def test_search_reuses_bins_only_for_the_same_pool(ctx, kf):
+    """reuse_bins skips the binning when the pool (pointers, sizes, offsets)
+    is the one last binned, and bins again for any other pool."""
+    wl, ev, g, pools, p, C, q = search_inputs(2000)
+    dev = ctx.device
+    f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt).contiguous()
+    dp = (f(pools.pos, torch.float32), f(pools.cov, torch.float32), f(pools.hit_id, torch.int32))
+    fresh = gpu_search(ctx, kf, g, pools, p, C, q, dev_pool=dp)
+    again = gpu_search(ctx, kf, g, pools, p, C, q, dev_pool=dp, reuse=True)
+    for k in fresh:
+        assert np.array_equal(fresh[k], again[k], equal_nan=True), k
+    # another pool (noise-free): a different identity, so it is binned
+    wl2, ev2, g2, pools2, p2, C2, q2 = search_inputs(2000, noise=False)
+    other = gpu_search(ctx, kf, g2, pools2, p2, C2, q2, reuse=True)
+    ref = gpu_search(ctx, kf, g2, pools2, p2, C2, q2)
+    for k in ref:
+        assert np.array_equal(ref[k], other[k], equal_nan=True), k
