@@ -10,8 +10,10 @@ kernel and the oracle's own rate on the host cores."""
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,8 +35,40 @@ FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
+# sources of fit_kernel<float>: a traffic figure taken on other sources is stale
+FIT_SOURCES = ["kf_math.hpp", "kf_track.hpp", "kf_kernels.hip", "kf_kernels.hpp", "kf_stage.hpp"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fit_kernel_barrel20_traffic.md")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def fit_source_hash():
+    h = hashlib.sha256()
+    for f in FIT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_11728_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch):
+    """HBM bytes per launch of fit_kernel<float> on barrel20 from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by its reading for a
+    plain copy of known size), if it was taken on the current kernel sources
+    and launch shape; else None."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            txt = f.read()
+    except OSError:
+        return None
+    m = dict(re.findall(r"^- (\w+): (.+)$", txt, re.M))
+    if m.get("source_hash") != fit_source_hash() or m.get("launch") != json.dumps(list(launch)):
+        return None
+    try:
+        return float(m["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def algorithmic_flops(ev):
@@ -238,9 +272,14 @@ def profile_only(args, K, tune_fit, generate, workloads):
                            1 if name == "mixed26" else 0)
     out = K.fit_outputs(ev.n_tracks, dt, dev)
     from paper_2312_11728_amd.autotune import load_cache, _key
-    cached = load_cache(args.tune_cache).get(_key(dt, ev.n_tracks, torch.cuda.get_device_name(dev)))
-    if cached:
-        ctx.set_fit_launch(dt, *cached["shape"])
+    # the tuned shape for this precision and size (any device name: a
+    # profiler can change the name the runtime reports)
+    prefix = _key(dt, ev.n_tracks, "").rstrip("|")
+    cached = [v for k, v in sorted(load_cache(args.tune_cache).items()) if k.startswith(prefix + "|")]
+    if args.launch:
+        ctx.set_fit_launch(dt, *[int(x) for x in args.launch.split(",")])
+    elif cached:
+        ctx.set_fit_launch(dt, *cached[0]["shape"])
     # a plain device copy of known size (128 MiB read, 128 MiB written) in the
     # same process: it calibrates the HBM byte counters of a counter run
     src = torch.ones(32 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -267,6 +306,8 @@ def main():
     ap.add_argument("--no-search", action="store_true", help="skip the combinatorial search workload")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "kf_autotune.json"))
+    ap.add_argument("--launch", default=None,
+                    help="profile-only: fit launch shape block,persistent,blocks_per_cu,waves,layout")
     ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32", "adjoint", "search"],
                     help="only launch the named fit --steps times (for hardware-counter runs)")
     args = ap.parse_args()
@@ -346,7 +387,8 @@ def main():
                    "fields": ["block", "persistent", "blocks_per_cu", "waves_per_simd", "layout"],
                    "graph": True, "ms_fit_fp32_direct_launches": r32["ms_fit_direct"]},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved_tf / FP32_PEAK_TFLOPS, "traffic": measured_traffic(r32["launch"]),
+                     "traffic_unit": "bytes per launch (HBM, counters)", "fit_source_hash": fit_source_hash(),
                      "kernel": "fit_kernel<float>", "kernel_ms": r32["ms_fit"],
                      "algorithmic_flop_per_launch": flops,
                      "algorithmic_bytes_per_launch": algorithmic_bytes(ev, 4)},

@@ -170,14 +170,55 @@ __global__ void __launch_bounds__(256) length_hist_kernel(const int32_t* off, in
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-// cursors for a descending-length order: longest tracks take the first slots
-__global__ void length_cursor_kernel(const int32_t* hist, int32_t max_len, int32_t* cursor) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int acc = 0;
-  for (int L = max_len; L >= 0; --L) {
-    cursor[L] = acc;
-    acc += hist[L];
+// Cursors of the length-sorted order (longest first) and, for the packed
+// layout, the first element of every tile: the tracks of tile tau are slots
+// tau*64 ... tau*64+63 of that order, the first of them is the longest, and its
+// length -- read off the histogram -- is the tile's number of rows.
+__global__ void __launch_bounds__(1024) cursor_tiles_kernel(const int32_t* hist, int32_t max_len, int64_t n,
+                                                             int32_t* cursor, int64_t* tile_base) {
+  __shared__ int32_t cur[kMaxLen + 1];
+  __shared__ int32_t cnt[kMaxLen + 1];
+  __shared__ int64_t part[1024];
+  __shared__ int64_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    int acc = 0;
+    for (int L = max_len; L >= 0; --L) {
+      cur[L] = acc;
+      cursor[L] = acc;
+      cnt[L] = hist[L];
+      acc += hist[L];
+    }
+    carry = 0;
   }
+  __syncthreads();
+  if (!tile_base) return;
+  const int64_t n_tiles = (n + kTile - 1) / kTile;
+  for (int64_t c0 = 0; c0 < n_tiles; c0 += 1024) {
+    const int64_t tau = c0 + tid;
+    int64_t v = 0;
+    if (tau < n_tiles) {
+      const int64_t slot = tau * kTile;
+      for (int L = max_len; L >= 0; --L)
+        if (slot < int64_t(cur[L]) + cnt[L]) {
+          v = int64_t(L) * kTile;
+          break;
+        }
+    }
+    part[tid] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int64_t add = tid >= d ? part[tid - d] : 0;
+      __syncthreads();
+      part[tid] += add;
+      __syncthreads();
+    }
+    if (tau < n_tiles) tile_base[tau] = carry + part[tid] - v;
+    __syncthreads();
+    if (tid == 1023) carry += part[1023];
+    __syncthreads();
+  }
+  if (tid == 0) tile_base[n_tiles] = carry;
 }
 
 // slot of every track: each block reserves a range per length with one global
@@ -206,75 +247,97 @@ __global__ void __launch_bounds__(256) length_scatter_kernel(const int32_t* off,
   }
 }
 
-// tile_base = exclusive scan over tiles of kTile * (entry count of the tile's
-// first, i.e. longest, track); one block of 1024 threads, each summing a
-// contiguous run of tiles, then a Hillis-Steele scan of the run sums in LDS
-__global__ void __launch_bounds__(1024) tile_base_kernel(const int32_t* off, const int32_t* order, int64_t n,
-                                                       int32_t max_len, int64_t* tile_base) {
-  __shared__ int64_t part[1024];
-  const int64_t n_tiles = (n + kTile - 1) / kTile;
-  const int64_t per = (n_tiles + blockDim.x - 1) / blockDim.x;
-  const int64_t b = int64_t(threadIdx.x) * per;
-  const int64_t e = b + per < n_tiles ? b + per : n_tiles;
-  int64_t sum = 0;
-  for (int64_t tau = b; tau < e; ++tau) {
-    const int64_t t = order[tau * kTile];
-    int len = off[t + 1] - off[t];
-    len = len < 0 ? 0 : (len > max_len ? max_len : len);
-    sum += int64_t(len) * kTile;
-  }
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int d = 1; d < int(blockDim.x); d <<= 1) {
-    const int64_t v = threadIdx.x >= unsigned(d) ? part[threadIdx.x - d] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  int64_t acc = part[threadIdx.x] - sum;   // exclusive prefix of this thread's run
-  if (threadIdx.x == blockDim.x - 1) tile_base[n_tiles] = part[threadIdx.x];
-  for (int64_t tau = b; tau < e; ++tau) {
-    tile_base[tau] = acc;
-    const int64_t t = order[tau * kTile];
-    int len = off[t + 1] - off[t];
-    len = len < 0 ? 0 : (len > max_len ? max_len : len);
-    acc += int64_t(len) * kTile;
-  }
-}
 
-// entry -> track by binary search in the CSR offsets
-__device__ __forceinline__ int64_t track_of_entry(const int32_t* off, int64_t n, int64_t e) {
-  int64_t lo = 0, hi = n;   // off[lo] <= e < off[hi]
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (off[mid] <= e)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
+// Fill the packed layout, one block per tile, through an LDS transpose: the
+// tile's entries are read track by track (each track's entries are contiguous
+// in the CSR arrays) into buffers [k][slot], then written row by row (entry k
+// of the tile's 64 slots is contiguous in the packed layout).  The buffers
+// hold `group` components at a time (sized by max_len), so that a typical
+// tile needs two passes.  Entries beyond a track's length are never read by
+// the fit and are left unwritten.
+constexpr int kPackBlock = 256;
+constexpr int kPackPer = (kTile * kMaxLen + kPackBlock - 1) / kPackBlock;   // entries per thread, at most
+constexpr int kPackLds = 48 * 1024;                                         // dynamic LDS budget
 
-// copy every CSR entry to its place in the packed layout (one thread per
-// entry: the reads are contiguous)
 template <typename T>
-__global__ void __launch_bounds__(256) pack_kernel(const int32_t* off, const int16_t* layer, const uint8_t* valid,
-                                                   const T* pos, const T* cov, int64_t n_hits, int64_t n,
-                                                   int32_t max_len, const int32_t* slot_of,
-                                                   const int64_t* tile_base, int32_t* lv, T* hit, int64_t stride) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= n_hits) return;
-  const int64_t t = track_of_entry(off, n, e);
-  if (e < off[t] || e >= off[t + 1]) return;   // entry outside every track's range
-  const int k = int(e - off[t]);
-  if (k >= max_len) return;
-  const int64_t s = slot_of[t];
-  const int64_t i = tile_base[s / kTile] + s % kTile + int64_t(k) * kTile;
-  lv[i] = int32_t(uint16_t(layer[e])) | (int32_t(valid[e] != 0) << 16);
+__global__ void __launch_bounds__(kPackBlock) pack_kernel(const int32_t* off, const int16_t* layer,
+                                                          const uint8_t* valid, const T* pos, const T* cov,
+                                                          int64_t n_hits, int64_t n, int32_t max_len, int32_t group,
+                                                          const int32_t* order, const int64_t* tile_base, int32_t* lv,
+                                                          T* hit, int64_t stride) {
+  extern __shared__ __align__(16) unsigned char pack_smem[];
+  __shared__ int32_t len_s[kTile];
+  __shared__ int32_t pre_s[kTile + 1];   // exclusive prefix of the lengths
+  __shared__ int64_t e0_s[kTile];
+  const int cap = max_len * kTile;       // elements of one buffer
+  int32_t* lbuf = reinterpret_cast<int32_t*>(pack_smem);
+  T* buf = reinterpret_cast<T*>(pack_smem + ((cap * 4 + 15) / 16) * 16);
+  const int64_t tile = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (tid < kTile) {
+    const int64_t slot = tile * kTile + tid;
+    int len = 0;
+    int64_t e0 = 0;
+    if (slot < n) {
+      const int64_t t = order[slot];
+      e0 = off[t];
+      len = int(off[t + 1] - e0);
+      len = len < 0 ? 0 : (len > max_len ? max_len : len);
+    }
+    len_s[tid] = len;
+    e0_s[tid] = e0;
+  }
+  __syncthreads();
+  if (tid < kTile) {
+    // exclusive prefix of the 64 lengths (wave-wide, in LDS)
+    int acc = 0;
+    for (int j = 0; j < tid; ++j) acc += len_s[j];
+    pre_s[tid] = acc;
+    if (tid == kTile - 1) pre_s[kTile] = acc + len_s[tid];
+  }
+  __syncthreads();
+  const int total = pre_s[kTile];
+  const int rows = len_s[0];   // the longest track leads its tile
+  int64_t src[kPackPer];
+  int dst[kPackPer];   // k * kTile + slot, or -1
 #pragma unroll
-  for (int c = 0; c < 3; ++c) hit[c * stride + i] = pos[c * n_hits + e];
+  for (int m = 0; m < kPackPer; ++m) {
+    const int f = tid + m * kPackBlock;
+    src[m] = 0;
+    dst[m] = -1;
+    if (f < total) {
+      int lo = 0, hi = kTile;   // pre_s[lo] <= f < pre_s[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre_s[mid] <= f) lo = mid;
+        else hi = mid;
+      }
+      const int k = f - pre_s[lo];
+      src[m] = e0_s[lo] + k;
+      dst[m] = k * kTile + lo;
+    }
+  }
+  const int64_t base = tile_base[tile];
+  for (int c0 = 0; c0 < 9; c0 += group) {
+    const int gn = c0 + group <= 9 ? group : 9 - c0;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) hit[(3 + c) * stride + i] = cov[c * n_hits + e];
+    for (int m = 0; m < kPackPer; ++m) {
+      if (dst[m] < 0) continue;
+      if (c0 == 0) lbuf[dst[m]] = int32_t(uint16_t(layer[src[m]])) | (int32_t(valid[src[m]] != 0) << 16);
+      for (int g = 0; g < gn; ++g) {
+        const int c = c0 + g;
+        const T* srcc = c < 3 ? pos + int64_t(c) * n_hits : cov + int64_t(c - 3) * n_hits;
+        buf[g * cap + dst[m]] = srcc[src[m]];
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < rows * kTile; i += kPackBlock) {
+      if (i / kTile >= len_s[i % kTile]) continue;
+      if (c0 == 0) lv[base + i] = lbuf[i];
+      for (int g = 0; g < gn; ++g) hit[int64_t(c0 + g) * stride + base + i] = buf[g * cap + i];
+    }
+    __syncthreads();
+  }
 }
 
 template <typename T>
@@ -284,7 +347,8 @@ hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, int layout, Packe
   const int nh = kMaxLen + 2;
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(128), 0, s, w.hist, nh);
   hipLaunchKernelGGL(length_hist_kernel, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.n, a.max_len, w.hist);
-  hipLaunchKernelGGL(length_cursor_kernel, dim3(1), dim3(64), 0, s, w.hist, a.max_len, w.cursor);
+  hipLaunchKernelGGL(cursor_tiles_kernel, dim3(1), dim3(1024), 0, s, w.hist, a.max_len, a.n, w.cursor,
+                     layout == 2 ? w.tile_base : nullptr);
   hipLaunchKernelGGL(length_scatter_kernel, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.n, a.max_len, w.cursor,
                      w.order, w.slot_of);
   out->order = w.order;
@@ -293,13 +357,17 @@ hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, int layout, Packe
   out->hit = nullptr;
   out->stride = 0;
   if (layout == 2) {
-    hipLaunchKernelGGL(tile_base_kernel, dim3(1), dim3(1024), 0, s, a.hit_offsets, w.order, a.n, a.max_len,
-                       w.tile_base);
-    const unsigned gh = unsigned((a.n_hits + B - 1) / B);
+    const unsigned n_tiles = unsigned((a.n + kTile - 1) / kTile);
+    // components per pass: as many [max_len][64] buffers as the LDS budget holds
+    const int cap = a.max_len * kTile;
+    const int lbytes = ((cap * 4 + 15) / 16) * 16;
+    int group = (kPackLds - lbytes) / (cap * int(sizeof(T)));
+    group = group < 1 ? 1 : (group > 9 ? 9 : group);
+    const size_t smem = size_t(lbytes) + size_t(group) * cap * sizeof(T);
     if (a.n_hits > 0)
-      hipLaunchKernelGGL(pack_kernel<T>, dim3(gh), dim3(B), 0, s, a.hit_offsets, a.hit_layer, a.hit_valid,
-                         a.hit_pos, a.hit_cov, a.n_hits, a.n, a.max_len, w.slot_of, w.tile_base, w.lv, (T*)w.hit,
-                         w.cap);
+      hipLaunchKernelGGL(pack_kernel<T>, dim3(n_tiles), dim3(kPackBlock), smem, s, a.hit_offsets, a.hit_layer,
+                         a.hit_valid, a.hit_pos, a.hit_cov, a.n_hits, a.n, a.max_len, group, w.order, w.tile_base,
+                         w.lv, (T*)w.hit, w.cap);
     out->tile_base = w.tile_base;
     out->lv = w.lv;
     out->hit = (const T*)w.hit;
