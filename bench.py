@@ -100,6 +100,31 @@ def time_loop(fn, steps, warmup):
     return start.elapsed_time(stop) / steps   # ms
 
 
+def fit_kernel_name(launch):
+    """The kernel that one fit launch of this shape runs."""
+    block, persistent, _, waves, layout = launch
+    base = "fit_staged" if layout >= 3 else "fit"
+    return "%s%s_kernel<float, %d, %s>" % (base, "_persistent" if persistent else "", waves,
+                                            ("true" if layout == 4 else "false") if layout >= 3 else str(layout))
+
+
+def time_fit_kernel(ctx, fit_step, steps, warmup):
+    """Times `steps` direct fit calls (ms per call, torch events on the
+    current stream) and, from the library's own event pairs recorded around
+    each fit-kernel launch on the same stream, the fit kernel's average
+    duration (ms per launch, sort and pack passes excluded)."""
+    for _ in range(warmup):
+        fit_step()
+    ctx.set_kernel_timing(steps)
+    try:
+        ms_call = time_loop(fit_step, steps, 0)
+        total, launches, dropped = ctx.fit_kernel_time()
+    finally:
+        ctx.set_kernel_timing(0)
+    assert launches == steps and dropped == 0, (launches, dropped)
+    return ms_call, total / launches
+
+
 def cpu_baseline(ev, seconds=10.0):
     import torch
     from oracle import kf_oracle as O
@@ -138,7 +163,7 @@ def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
 
     best, table = tune_fit(ctx, fit_step, torch.float32, n, use_cache=not args.retune, cache_path=args.tune_cache)
     log("autotune mixed26", best, [(s_, round(ms, 4)) for s_, ms in table])
-    ms_direct = time_loop(fit_step, args.steps, args.warmup)
+    ms_direct, kernel_ms = time_fit_kernel(ctx, fit_step, args.steps, args.warmup)
     ctx.set_fit_graph(True)
     ms = time_loop(fit_step, args.steps, args.warmup)
     ctx.set_fit_graph(False)
@@ -146,9 +171,9 @@ def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
     lens = ev.lengths()
     return {"tracks": n, "entries": int(ev.n_hits), "valid": int(ev.hit_valid.sum()),
             "length_min": int(lens.min()), "length_max": int(lens.max()), "ms_fit": ms,
-            "tracks_per_s": n / (ms * 1e-3), "achieved_tflops": flops / (ms * 1e-3) / 1e12,
-            "frac_fp32_peak": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, "launch": list(best), "graph": True,
-            "ms_fit_direct_launches": ms_direct}
+            "tracks_per_s": n / (ms * 1e-3), "achieved_tflops": flops / (kernel_ms * 1e-3) / 1e12,
+            "frac_fp32_peak": flops / (kernel_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, "launch": list(best), "graph": True,
+            "ms_fit_direct_launches": ms_direct, "fit_kernel_ms": kernel_ms}
 
 
 def bench_adjoint(ctx, K, generate, workloads, args, seg=5):
@@ -355,18 +380,19 @@ def main():
         best, table = tune_fit(ctx, fit_step, dt, n, use_cache=not args.retune, cache_path=args.tune_cache)
         log("autotune", dt, "best", best, "table", [(s_, round(ms, 4)) for s_, ms in table])
         log("timing", dt)
-        ms_fit_direct = time_loop(fit_step, args.steps, args.warmup)
+        ms_fit_direct, kernel_ms = time_fit_kernel(ctx, fit_step, args.steps, args.warmup)
         ctx.set_fit_graph(True)
         ms_step = time_loop(step, args.steps, args.warmup)
         ms_fit = time_loop(fit_step, args.steps, args.warmup)
         ctx.set_fit_graph(False)
-        res[dt] = dict(ms_step=ms_step, ms_fit=ms_fit, ms_fit_direct=ms_fit_direct, out=out, seeds=seeds, launch=best)
+        res[dt] = dict(ms_step=ms_step, ms_fit=ms_fit, ms_fit_direct=ms_fit_direct, kernel_ms=kernel_ms, out=out,
+                       seeds=seeds, launch=best)
         log(dt, "ms/step", ms_step, "fit kernel ms", ms_fit)
 
     r32, r64 = res[torch.float32], res[torch.float64]
     n = ev.n_tracks
     flops = algorithmic_flops(ev)
-    achieved_tf = flops / (r32["ms_fit"] * 1e-3) / 1e12
+    achieved_tf = flops / (r32["kernel_ms"] * 1e-3) / 1e12
     line = {
         "metric": "fitted tracks/s FP32 batched vs plain FP64 GPU at stated error; fwd+adjoint tracks/s",
         "value": n / (r32["ms_step"] * 1e-3),
@@ -382,7 +408,8 @@ def main():
         "data": "synthetic (seeded toy helices, 3.8 T, 0.02 X0 per layer)",
         "config": {"workload": "barrel20: 100000 tracks x 20 barrel layers, seeded from the first 3 hits",
                    "tracks": n, "entries": int(ev.n_hits)},
-        "fp64_gpu": {"value": n / (r64["ms_step"] * 1e-3), "unit": "tracks/s", "ms_per_step": r64["ms_step"]},
+        "fp64_gpu": {"value": n / (r64["ms_step"] * 1e-3), "unit": "tracks/s", "ms_per_step": r64["ms_step"],
+                     "fit_kernel_ms": r64["kernel_ms"]},
         "fp32_over_fp64": r64["ms_step"] / r32["ms_step"],
         "launch": {"fp32": list(r32["launch"]), "fp64": list(r64["launch"]),
                    "fields": ["block", "persistent", "blocks_per_cu", "waves_per_simd", "layout"],
@@ -390,7 +417,10 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP32_PEAK_TFLOPS, "traffic": measured_traffic(r32["launch"]),
                      "traffic_unit": "bytes per launch (HBM, counters)", "fit_source_hash": fit_source_hash(),
-                     "kernel": "fit_kernel<float>", "kernel_ms": r32["ms_fit"],
+                     "kernel": fit_kernel_name(r32["launch"]), "kernel_ms": r32["kernel_ms"],
+                     "kernel_ms_source": "HIP events around each fit-kernel launch on the launching stream, "
+                                         "direct launches of the timed fit loop",
+                     "fit_call_ms": r32["ms_fit"],
                      "algorithmic_flop_per_launch": flops,
                      "algorithmic_bytes_per_launch": algorithmic_bytes(ev, 4)},
     }
@@ -401,9 +431,13 @@ def main():
         bad = ill_conditioned(ev, torch.float32, o, 0)
         ep = param_error(g["p"], o["p"]).max(axis=1)
         ec = chi2_error(g["chi2"], o["chi2"])
-        line["accuracy_vs_oracle"] = {"max_param_err": float(ep[~bad].max()), "max_chi2_err": float(ec[~bad].max()),
-                                      "tracks_compared": int((~bad).sum()), "ill_conditioned": int(bad.sum()),
-                                      "tolerance": {"param": 1e-4, "chi2": 1e-3}}
+        ok = ~bad
+        line["accuracy_vs_oracle"] = {
+            "max_param_err": float(ep[ok].max()), "max_chi2_err": float(ec[ok].max()),
+            "frac_within_tolerance": {"param": float((ep[ok] <= 1e-4).mean()), "chi2": float((ec[ok] <= 1e-3).mean())},
+            "tracks_compared": int(ok.sum()), "ill_conditioned": int(bad.sum()),
+            "tolerance": {"param": 1e-4, "chi2": 1e-3,
+                          "tail": "at most 0.1% of the tracks may exceed it, by < 10x (param) / 20x (chi2)"}}
     if not args.no_uneven:
         line["uneven_mixed26"] = bench_uneven(ctx, K, tune_fit, generate, workloads, args)
     if not args.no_adjoint:

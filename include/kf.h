@@ -168,8 +168,12 @@ int kf_update(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
  * the tracks by entry count (longest first, so that the lanes of a wave run
  * similar loops) and optionally copy the hits into a tile-transposed layout
  * (entry k of 64 tracks contiguous, every hit load of a wave one coalesced
- * read); without a workspace the fit reads the CSR arrays in track order.
- * Results are identical for every layout. */
+ * read); the fit can also stage the CSR entries of each wave's 64 tracks
+ * through LDS itself, a few entries per track at a time (no pass before the
+ * fit; with the sort, if a workspace is there).  Without a workspace the fit
+ * reads the CSR arrays in track order.  Results are bit-identical within each
+ * family of layouts (direct reads: 0-2; LDS staging: 3, 4) and agree to
+ * rounding across the two (see kf_set_fit_launch). */
 int kf_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                   const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
                   const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
@@ -288,10 +292,16 @@ int kf_reserve(kf_ctx *ctx, int64_t max_tracks, int32_t max_len);
  * track), blocks_per_cu (1..32), waves (1 or 2: the kernel variant whose
  * register allocation allows at least that many waves per SIMD) and layout
  * (0: CSR in track order; 1: CSR in length-sorted order; 2: length-sorted
- * and packed -- 1 and 2 need a workspace from kf_reserve, else 0 is used).
- * Every launch shape computes bit-identical results; the choice is made by
- * the autotuner of the Python package and only changes speed.  Stored in the
- * context. */
+ * and packed; 3: CSR in track order staged through LDS by each wave; 4: CSR
+ * in length-sorted order staged through LDS -- 1, 2 and 4 need a workspace
+ * from kf_reserve, else 0 is used for 1 and 2 and 3 for 4).
+ * Within a family of layouts (0-2 read the hits directly, 3-4 stage them
+ * through LDS) every launch shape computes bit-identical results.  The two
+ * families run the same arithmetic compiled into different loops, where the
+ * compiler fuses different multiply-adds, so across them results agree to
+ * rounding (FP64: about 1e-12 relative) and each meets the same accuracy
+ * against the FP64 reference.  The choice is made by the autotuner of the
+ * Python package for speed.  Stored in the context. */
 int kf_set_fit_launch(kf_ctx *ctx, kf_precision prec, int32_t block, int32_t persistent, int32_t blocks_per_cu,
                       int32_t waves, int32_t layout);
 int kf_get_fit_launch(const kf_ctx *ctx, kf_precision prec, int32_t *block, int32_t *persistent,
@@ -305,6 +315,21 @@ int kf_get_fit_launch(const kf_ctx *ctx, kf_precision prec, int32_t *block, int3
  * again; kf_reserve drops the cached graphs.  Results are identical to the
  * direct launches. */
 int kf_set_fit_graph(kf_ctx *ctx, int32_t enable);
+
+/* Kernel timing of kf_fit_tracks.  max_launches > 0 creates that many HIP
+ * event pairs (at most 4096) and, from then on, records one pair on the
+ * caller's stream around the fit kernel of each kf_fit_tracks call -- the
+ * sort and pack passes are outside the pair; the persistent form's one-thread
+ * tile-counter reset is inside -- until the pairs are used up (further calls
+ * count as dropped).  While timing is on, kf_fit_tracks launches directly
+ * even with graph replay enabled (the results are the same).  0 turns timing
+ * off and frees the events.  Creating the events allocates; call it before a
+ * timed region. */
+int kf_set_kernel_timing(kf_ctx *ctx, int32_t max_launches);
+/* Waits for the recorded fit kernels, returns the sum of their durations in
+ * milliseconds and their number (dropped: the calls past the last pair; may
+ * be NULL), and starts a new count with the same events. */
+int kf_fit_kernel_time(kf_ctx *ctx, double *total_ms, int64_t *launches, int64_t *dropped);
 
 /* Number of compute units of the context's device. */
 int kf_device_cu_count(const kf_ctx *ctx, int32_t *n_cu);

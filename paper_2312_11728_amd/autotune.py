@@ -1,12 +1,14 @@
 """Autotuner for the fused fit launch.
 
-Every launch shape of kf_fit_tracks computes bit-identical results, so the
-tuner only measures: it times each candidate (threads per block, plain or
+Within a family of hit layouts every launch shape of kf_fit_tracks computes
+bit-identical results, and the two families (direct reads, LDS staging) agree
+to rounding, so the tuner only measures: it times each candidate (threads per block, plain or
 persistent grid, blocks per compute unit for the persistent grid, and the
 kernel variant compiled for one or two waves per SIMD) on the caller's own
 inputs with HIP events on the current stream, together with the hit layout
-(track order, length-sorted, or length-sorted and packed -- the sorting and
-packing passes are part of the timed call), keeps the fastest, sets it in
+(track order, length-sorted, length-sorted and packed, or either order
+staged through LDS by the fit kernel -- the sorting and packing passes are
+part of the timed call), keeps the fastest, sets it in
 the context and records it in a JSON cache keyed by (operation, precision,
 track-count class, device name)."""
 from __future__ import annotations
@@ -22,7 +24,7 @@ from . import kf as K
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "kf_autotune.json")
 
 
-def candidates(layouts=(0, 1, 2)):
+def candidates(layouts=(0, 1, 2, 3, 4)):
     """(block, persistent, blocks_per_cu, waves, layout) shapes to time."""
     out = []
     for layout in layouts:

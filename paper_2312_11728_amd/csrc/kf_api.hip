@@ -36,11 +36,18 @@ struct kf_ctx {
   void* search_mem = nullptr;
   size_t search_bytes = 0;
   std::vector<unsigned char> bins_key;
+  // event pairs around the fit kernel of direct launches (kf_set_kernel_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> t_start, t_stop;
+  int t_used = 0;
+  int64_t t_dropped = 0;
 };
 
 namespace {
 
 thread_local std::string g_err;
+
+constexpr int32_t kMaxTimedLaunches = 4096;
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -104,6 +111,15 @@ int check_prec(int prec) {
     if (!(ptr)) return fail(KF_ERR_ARG, "%s is NULL", #ptr);              \
   } while (0)
 
+void drop_timing_events(kf_ctx* ctx) {
+  for (hipEvent_t ev : ctx->t_start) hipEventDestroy(ev);
+  for (hipEvent_t ev : ctx->t_stop) hipEventDestroy(ev);
+  ctx->t_start.clear();
+  ctx->t_stop.clear();
+  ctx->t_used = 0;
+  ctx->t_dropped = 0;
+}
+
 #define KF_TRY(expr)                 \
   do {                               \
     int rc_ = (expr);                \
@@ -150,6 +166,7 @@ int kf_destroy(kf_ctx* c) {
   hipSetDevice(c->device);
   for (int i = 0; i < 2; ++i)
     if (c->exec[i]) hipGraphExecDestroy(c->exec[i]);
+  drop_timing_events(c);
   if (c->capture) hipStreamDestroy(c->capture);
   if (c->d_counter) hipFree(c->d_counter);
   if (c->work_mem) hipFree(c->work_mem);
@@ -299,13 +316,24 @@ kf::FitArgs<T> make_fit_args(int64_t n, int64_t ld, const void* seed_state, cons
 template <typename T>
 hipError_t run_fit(kf_ctx* ctx, kf::FitArgs<T> a, const kf::GeomArgs& g, const kf::FitLaunch& l, int layout,
                    hipStream_t s) {
-  if (layout != 0) {
+  if (layout == 1 || layout == 2 || layout == 4) {
     hipError_t e = kf::launch_pack(a, ctx->work, layout, &a.pk, s);
     if (e != hipSuccess) return e;
   }
   a.packed = layout;
-  return kf::launch_fit(a, g, l, ctx->n_cu, s);
+  // graph captures (on the context's capture stream) carry no timing events
+  const bool timed = ctx->timing && s != ctx->capture;
+  if (timed && ctx->t_used >= int(ctx->t_start.size())) ++ctx->t_dropped;
+  const int slot = timed && ctx->t_used < int(ctx->t_start.size()) ? ctx->t_used++ : -1;
+  if (slot >= 0) {
+    hipError_t e = hipEventRecord(ctx->t_start[slot], s);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = kf::launch_fit(a, g, l, ctx->n_cu, s);
+  if (e == hipSuccess && slot >= 0) e = hipEventRecord(ctx->t_stop[slot], s);
+  return e;
 }
+
 
 // With graphs enabled, the sequence is captured once on the context's
 // capture stream and replayed on the caller's stream while every launch
@@ -359,6 +387,53 @@ int kf_set_fit_graph(kf_ctx* ctx, int32_t enable) {
   return ok();
 }
 
+int kf_set_kernel_timing(kf_ctx* ctx, int32_t max_launches) {
+  KF_REQUIRE(ctx);
+  if (max_launches < 0 || max_launches > kMaxTimedLaunches)
+    return fail(KF_ERR_ARG, "max_launches = %d outside [0, %d]", max_launches, kMaxTimedLaunches);
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(ctx->device);
+  drop_timing_events(ctx);
+  ctx->timing = max_launches > 0;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < max_launches && e == hipSuccess; ++i) {
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (a) ctx->t_start.push_back(a);
+    if (b) ctx->t_stop.push_back(b);
+    if (e == hipSuccess && (!a || !b)) e = hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) {
+    drop_timing_events(ctx);
+    ctx->timing = false;
+  }
+  hipSetDevice(prev);
+  if (e != hipSuccess) return hip_fail(e, "kf_set_kernel_timing");
+  return ok();
+}
+
+int kf_fit_kernel_time(kf_ctx* ctx, double* total_ms, int64_t* launches, int64_t* dropped) {
+  KF_REQUIRE(ctx);
+  KF_REQUIRE(total_ms);
+  KF_REQUIRE(launches);
+  double sum = 0.0;
+  for (int i = 0; i < ctx->t_used; ++i) {
+    hipError_t e = hipEventSynchronize(ctx->t_stop[i]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->t_start[i], ctx->t_stop[i]);
+    if (e != hipSuccess) return hip_fail(e, "kf_fit_kernel_time");
+    sum += double(ms);
+  }
+  *total_ms = sum;
+  *launches = ctx->t_used;
+  if (dropped) *dropped = ctx->t_dropped;
+  ctx->t_used = 0;
+  ctx->t_dropped = 0;
+  return ok();
+}
+
 int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state, const void* seed_cov,
                   const int8_t* seed_charge, const int32_t* hit_offsets, const int16_t* hit_layer,
                   const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos, const void* hit_cov,
@@ -397,20 +472,22 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   const int pi = prec == KF_F32 ? 0 : 1;
   const kf::FitLaunch l = ctx->fit[pi];
   const bool room = ctx->work.cap > 0 && n <= ctx->work.max_tracks && max_len <= ctx->work.max_len;
-  const int layout = room ? l.layout : 0;
+  const int layout = room || l.layout == 3 ? l.layout : (l.layout == 4 ? 3 : 0);
   hipError_t e;
   if (prec == KF_F32) {
     auto a = make_fit_args<float>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, n_hits,
                                   hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf, checkpoints, seg,
                                   n_seg, trk_status, ctx->d_counter);
     a.max_len = max_len;
-    e = ctx->use_graph[pi] ? run_fit_graph(ctx, pi, a, g, l, layout, s) : run_fit(ctx, a, g, l, layout, s);
+    e = ctx->use_graph[pi] && !ctx->timing ? run_fit_graph(ctx, pi, a, g, l, layout, s)
+                                           : run_fit(ctx, a, g, l, layout, s);
   } else {
     auto a = make_fit_args<double>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
                                    n_hits, hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf,
                                    checkpoints, seg, n_seg, trk_status, ctx->d_counter);
     a.max_len = max_len;
-    e = ctx->use_graph[pi] ? run_fit_graph(ctx, pi, a, g, l, layout, s) : run_fit(ctx, a, g, l, layout, s);
+    e = ctx->use_graph[pi] && !ctx->timing ? run_fit_graph(ctx, pi, a, g, l, layout, s)
+                                           : run_fit(ctx, a, g, l, layout, s);
   }
   if (e != hipSuccess) return hip_fail(e, "kf_fit_tracks");
   return ok();
@@ -475,7 +552,7 @@ int kf_set_fit_launch(kf_ctx* ctx, kf_precision prec, int32_t block, int32_t per
                       int32_t waves, int32_t layout) {
   KF_TRY(check_prec(prec));
   if (waves != 1 && waves != 2) return fail(KF_ERR_ARG, "waves = %d (1 or 2)", waves);
-  if (layout < 0 || layout > 2) return fail(KF_ERR_ARG, "layout = %d (0, 1 or 2)", layout);
+  if (layout < 0 || layout > 4) return fail(KF_ERR_ARG, "layout = %d (0 to 4)", layout);
   if (block < 64 || block > 256 || block % 64 != 0) return fail(KF_ERR_ARG, "block = %d (64, 128, 192 or 256)", block);
   if (persistent != 0 && persistent != 1) return fail(KF_ERR_ARG, "persistent must be 0 or 1");
   if (blocks_per_cu < 1 || blocks_per_cu > 32) return fail(KF_ERR_ARG, "blocks_per_cu = %d outside [1, 32]", blocks_per_cu);

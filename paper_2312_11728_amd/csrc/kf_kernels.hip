@@ -143,6 +143,159 @@ __global__ void __launch_bounds__(kFitBlock, WAVES) fit_persistent_kernel(FitArg
   }
 }
 
+// ---- CSR hits staged through LDS by each wave (layouts 3 and 4) ------------------
+//
+// A lane reading its own track's entries from the CSR arrays touches one cache
+// line per lane and per load, and the lines are evicted before the next entry
+// reuses them.  Here the 64 lanes of a wave first copy the next J entries of
+// all 64 tracks into LDS together -- consecutive lanes read consecutive entries
+// of one track, so a load instruction covers 64 / J runs of J contiguous
+// values -- and then each lane steps through its own J entries from LDS.  The
+// entry loop is uniform over the wave (the longest track of the wave sets its
+// length); lanes whose track has ended or stopped sit out the steps but still
+// take part in the staging.  No pass over the hits before the fit.
+
+// entries per track and chunk: the LDS of a 256-thread block (4 waves) plus
+// the state backup must allow the WAVES blocks per CU the register budget
+// allows
+template <typename T, int WAVES>
+constexpr int stage_entries() {
+  return sizeof(T) == 4 ? (WAVES == 1 ? 8 : 4) : (WAVES == 1 ? 4 : 1);
+}
+
+template <typename T, int J>
+struct StageBuf {
+  T v[9][J][64];        // hit x, y, z, then the 6 covariance terms
+  int32_t lv[J][64];    // layer (low 16 bits) | valid << 16
+  int64_t e0[64];       // first entry of each lane's track
+  int32_t len[64];      // entries of each lane's track (0: no track)
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Forward fit of the tracks in slots [w0, w0 + 64) (one wave; slot i holds
+// track order[i] when sorted, else track i; slots >= n hold no track).  Every
+// lane of the wave must call it.
+template <typename T, int J, bool SORTED>
+__device__ void fit_wave_staged(const FitArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t w0,
+                                StageBuf<T, J>& sb, T* bk, int bk_stride) {
+  static_assert((J & (J - 1)) == 0 && J <= 64, "J must be a power of two <= 64");
+  const int lane = int(threadIdx.x) & 63;
+  const int64_t i = w0 + lane;
+  const bool in_range = i < a.n;
+  int64_t t = 0, e0 = 0;
+  int len = 0;
+  if (in_range) {
+    t = SORTED ? int64_t(a.pk.order[i]) : i;
+    e0 = a.hit_offsets[t];
+    len = int(a.hit_offsets[t + 1] - e0);
+  }
+  uint32_t st = 0;
+  if (len > a.max_len) {
+    st |= TRK_BAD_INPUT;
+    len = a.max_len;
+  }
+  sb.e0[lane] = e0;
+  sb.len[lane] = len;
+  const int kmax = wave_max(len);
+  T p[6], c[21];
+  int q = 0;
+  if (in_range) load_seed(a, t, p, c, q);
+  T chi2 = T(0);
+  int nval = 0, prev = 0, k0 = -1;
+  bool live = in_range;
+  const int64_t nh = a.n_hits;
+  wave_sync();
+  for (int j0 = 0; j0 < kmax; j0 += J) {
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+      const int idx = r * 64 + lane;
+      const int l = idx / J, jj = idx % J;
+      if (j0 + jj < sb.len[l]) {
+        const int64_t e = sb.e0[l] + j0 + jj;
+        sb.lv[jj][l] = int32_t(uint16_t(a.hit_layer[e])) | (a.hit_valid[e] ? (1 << 16) : 0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sb.v[k][jj][l] = a.hit_pos[k * nh + e];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sb.v[3 + k][jj][l] = a.hit_cov[k * nh + e];
+      }
+    }
+    wave_sync();
+    const int jn = min(J, kmax - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      const int k = j0 + jj;
+      if (!live || k >= len) continue;
+      const int32_t lv = sb.lv[jj][lane];
+      const bool valid = (lv >> 16) != 0;
+      const int lay = int16_t(lv & 0xffff);
+      if (k0 < 0) {
+        if (!valid) continue;   // leading holes: the fit starts at the first valid entry
+        k0 = k;
+        prev = lay;
+      }
+      T m[3], V[6];
+#pragma unroll
+      for (int x = 0; x < 3; ++x) m[x] = sb.v[x][jj][lane];
+#pragma unroll
+      for (int x = 0; x < 6; ++x) V[x] = sb.v[3 + x][jj][lane];
+      live = fit_entry(a, g, sal, t, k - k0, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
+    }
+    wave_sync();   // every lane has read the chunk before the next one is staged
+  }
+  if (in_range) {
+    if (k0 < 0) st |= TRK_BAD_INPUT;
+    store_fit(a, t, p, c, q, chi2, nval, st);
+  }
+}
+
+template <typename T, int WAVES, bool SORTED>
+__global__ void __launch_bounds__(kFitBlock, WAVES) fit_staged_kernel(FitArgs<T> a, GeomArgs g) {
+  constexpr int J = stage_entries<T, WAVES>();
+  __shared__ GeomLds<T> sg;
+  __shared__ T sal[2 * kMaxLayers];
+  __shared__ T bk[28 * kFitBlock];
+  __shared__ StageBuf<T, J> sb[kFitBlock / 64];
+  stage_align(sal, a, g);
+  stage_geometry(sg, g);
+  const int64_t w0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
+  fit_wave_staged<T, J, SORTED>(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)},
+                                a.align ? sal : nullptr, w0, sb[threadIdx.x >> 6], bk + threadIdx.x,
+                                int(blockDim.x));
+}
+
+template <typename T, int WAVES, bool SORTED>
+__global__ void __launch_bounds__(kFitBlock, WAVES) fit_staged_persistent_kernel(FitArgs<T> a, GeomArgs g) {
+  constexpr int J = stage_entries<T, WAVES>();
+  __shared__ GeomLds<T> sg;
+  __shared__ T sal[2 * kMaxLayers];
+  __shared__ T bk[28 * kFitBlock];
+  __shared__ StageBuf<T, J> sb[kFitBlock / 64];
+  __shared__ int64_t tile;
+  stage_align(sal, a, g);
+  stage_geometry(sg, g);
+  for (;;) {
+    if (threadIdx.x == 0) tile = atomicAdd(a.tile_counter, 1);
+    __syncthreads();
+    const int64_t my = tile;
+    __syncthreads();
+    if (my >= a.n_tiles) break;
+    const int64_t w0 = my * blockDim.x + (threadIdx.x & ~63u);
+    fit_wave_staged<T, J, SORTED>(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)},
+                                  a.align ? sal : nullptr, w0, sb[threadIdx.x >> 6], bk + threadIdx.x,
+                                  int(blockDim.x));
+  }
+}
+
 __global__ void reset_counter_kernel(int32_t* c) { *c = 0; }
 
 // ---- packed, length-sorted hit layout ------------------------------------------
@@ -381,7 +534,10 @@ hipError_t launch_fit_w(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch&
   const int block = l.block;
   if (!l.persistent) {
     const int64_t grid = (a.n + block - 1) / block;
-    hipLaunchKernelGGL((fit_kernel<T, WAVES, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s, a, g);
+    if constexpr (LAYOUT >= 3)
+      hipLaunchKernelGGL((fit_staged_kernel<T, WAVES, LAYOUT == 4>), dim3(unsigned(grid)), dim3(block), 0, s, a, g);
+    else
+      hipLaunchKernelGGL((fit_kernel<T, WAVES, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s, a, g);
     return hipGetLastError();
   }
   FitArgs<T> b = a;
@@ -389,13 +545,19 @@ hipError_t launch_fit_w(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch&
   int64_t grid = int64_t(n_cu) * l.blocks_per_cu;
   if (grid > b.n_tiles) grid = b.n_tiles;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, a.tile_counter);
-  hipLaunchKernelGGL((fit_persistent_kernel<T, WAVES, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s, b, g);
+  if constexpr (LAYOUT >= 3)
+    hipLaunchKernelGGL((fit_staged_persistent_kernel<T, WAVES, LAYOUT == 4>), dim3(unsigned(grid)), dim3(block), 0,
+                       s, b, g);
+  else
+    hipLaunchKernelGGL((fit_persistent_kernel<T, WAVES, LAYOUT>), dim3(unsigned(grid)), dim3(block), 0, s, b, g);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
+  if (a.packed == 4) return l.waves == 2 ? launch_fit_w<T, 2, 4>(a, g, l, n_cu, s) : launch_fit_w<T, 1, 4>(a, g, l, n_cu, s);
+  if (a.packed == 3) return l.waves == 2 ? launch_fit_w<T, 2, 3>(a, g, l, n_cu, s) : launch_fit_w<T, 1, 3>(a, g, l, n_cu, s);
   if (a.packed == 2) return l.waves == 2 ? launch_fit_w<T, 2, 2>(a, g, l, n_cu, s) : launch_fit_w<T, 1, 2>(a, g, l, n_cu, s);
   if (a.packed == 1) return l.waves == 2 ? launch_fit_w<T, 2, 1>(a, g, l, n_cu, s) : launch_fit_w<T, 1, 1>(a, g, l, n_cu, s);
   return l.waves == 2 ? launch_fit_w<T, 2, 0>(a, g, l, n_cu, s) : launch_fit_w<T, 1, 0>(a, g, l, n_cu, s);

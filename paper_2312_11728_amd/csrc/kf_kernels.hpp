@@ -100,7 +100,8 @@ struct FitArgs {
   uint32_t* trk_status;
   int32_t* tile_counter;  // persistent mode
   int64_t n_tiles;
-  int32_t packed;         // layout: 0 CSR, 1 CSR in length-sorted order, 2 sorted and packed (pk)
+  int32_t packed;         // layout: 0 CSR, 1 CSR in length-sorted order, 2 sorted and packed (pk),
+                          // 3 CSR staged through LDS, 4 length-sorted CSR staged through LDS
   PackedHits<T> pk;
 };
 
@@ -135,7 +136,8 @@ struct FitLaunch {
   int persistent;   // 0: one thread per track; 1: persistent blocks pulling tiles
   int blocks_per_cu;
   int waves;        // register budget: at least this many waves per SIMD (1 or 2)
-  int layout;       // 0 CSR, 1 length-sorted CSR, 2 length-sorted packed (needs a workspace)
+  int layout;       // 0 CSR, 1 length-sorted CSR, 2 length-sorted packed, 3 LDS-staged CSR,
+                    // 4 LDS-staged length-sorted CSR (1, 2, 4 need a workspace)
 };
 template <typename T>
 hipError_t launch_fit(const FitArgs<T>& a, const GeomArgs& g, const FitLaunch& l, int n_cu, hipStream_t s);

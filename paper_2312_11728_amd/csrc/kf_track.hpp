@@ -147,21 +147,79 @@ KF_HD inline bool step_forward(T p[6], T c[21], int& q, int j, int lay, int prev
   return true;
 }
 
+// The work of one entry of the forward fit, shared by every entry source:
+// layer check, checkpoint, backup of the state (bk: room for 28 values at
+// bk[k * bk_stride], kept out of registers -- in LDS on the device), the step,
+// and the roll-back to the backup when the step turns non-finite.  j: index
+// relative to the first valid entry.  Returns false when the track stops here
+// (the reason is in st).
+template <typename T>
+KF_HD inline bool fit_entry(const FitArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t t, int j,
+                            int lay, int& prev, bool valid, T m[3], const T V[6], T p[6], T c[21], int& q,
+                            uint32_t& st, T& chi2, int& nval, T* bk, int bk_stride) {
+  if (lay < 0 || lay >= g.n_layers) {
+    st |= TRK_BAD_INPUT;
+    return false;
+  }
+  if (a.ckpt && j >= 1 && ((j - 1) % a.seg) == 0) write_checkpoint(a, t, (j - 1) / a.seg, p, c, q);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) bk[i * bk_stride] = p[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) bk[(6 + i) * bk_stride] = c[i];
+  const int qq = q;
+  uint32_t sst = 0;
+  T c2;
+  if (!step_forward(p, c, q, j, lay, prev, valid, m, V, g, sal, c2, sst)) {
+    st |= sst;
+    return false;
+  }
+  if (!all_finite(p, c, c2)) {
+    st |= sst | TRK_NONFINITE;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) p[i] = bk[i * bk_stride];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = bk[(6 + i) * bk_stride];
+    q = qq;
+    return false;
+  }
+  st |= sst;
+  chi2 += c2;
+  nval += valid ? 1 : 0;
+  prev = lay;
+  return true;
+}
+
+template <typename T>
+KF_HD inline void load_seed(const FitArgs<T>& a, int64_t t, T p[6], T c[21], int& q) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * a.ld + t];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * a.ld + t];
+  q = a.seed_charge[t];
+}
+
+template <typename T>
+KF_HD inline void store_fit(const FitArgs<T>& a, int64_t t, const T p[6], const T c[21], int q, T chi2, int nval,
+                            uint32_t st) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) a.state_out[i * a.ld + t] = p[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) a.cov_out[i * a.ld + t] = c[i];
+  a.charge_out[t] = int8_t(q);
+  a.chi2[t] = chi2;
+  a.ndf[t] = 2 * nval - 5;
+  a.trk_status[t] = st;
+}
+
 // Forward fit of track t whose entries are read through `acc` (len entries).
 // sal: alignment staged as [rphi x kMaxLayers][z x kMaxLayers] or null.
-// bk: room for 28 values at bk[k * bk_stride] (k = 0..27) holding the state
-// before the current entry, read back only if that entry turns non-finite
-// (kept out of registers: in LDS on the device).
+// Leading holes are skipped: the fit starts at the first valid entry.
 template <typename T, typename Acc>
 KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t t,
                             const Acc& acc, int len, T* bk, int bk_stride) {
-  const int64_t ld = a.ld;
   T p[6], c[21];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * ld + t];
-#pragma unroll
-  for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * ld + t];
-  int q = a.seed_charge[t];
+  int q;
+  load_seed(a, t, p, c, q);
   uint32_t st = 0;
   if (len > a.max_len) {
     st |= TRK_BAD_INPUT;
@@ -190,46 +248,10 @@ KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
 #pragma unroll
       for (int i = 0; i < 6; ++i) V[i] = V_n[i];
       if (k + 1 < len) acc.load(k + 1, lay_n, valid_n, m_n, V_n);
-      if (lay < 0 || lay >= g.n_layers) {
-        st |= TRK_BAD_INPUT;
-        break;
-      }
-      const int j = k - k0;
-      if (a.ckpt && j >= 1 && ((j - 1) % a.seg) == 0) write_checkpoint(a, t, (j - 1) / a.seg, p, c, q);
-#pragma unroll
-      for (int i = 0; i < 6; ++i) bk[i * bk_stride] = p[i];
-#pragma unroll
-      for (int i = 0; i < 21; ++i) bk[(6 + i) * bk_stride] = c[i];
-      const int qq = q;
-      uint32_t sst = 0;
-      T c2;
-      if (!step_forward(p, c, q, j, lay, prev, valid, m, V, g, sal, c2, sst)) {
-        st |= sst;
-        break;
-      }
-      if (!all_finite(p, c, c2)) {
-        st |= sst | TRK_NONFINITE;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) p[i] = bk[i * bk_stride];
-#pragma unroll
-        for (int i = 0; i < 21; ++i) c[i] = bk[(6 + i) * bk_stride];
-        q = qq;
-        break;
-      }
-      st |= sst;
-      chi2 += c2;
-      nval += valid ? 1 : 0;
-      prev = lay;
+      if (!fit_entry(a, g, sal, t, k - k0, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride)) break;
     }
   }
-#pragma unroll
-  for (int i = 0; i < 6; ++i) a.state_out[i * ld + t] = p[i];
-#pragma unroll
-  for (int i = 0; i < 21; ++i) a.cov_out[i * ld + t] = c[i];
-  a.charge_out[t] = int8_t(q);
-  a.chi2[t] = chi2;
-  a.ndf[t] = 2 * nval - 5;
-  a.trk_status[t] = st;
+  store_fit(a, t, p, c, q, chi2, nval, st);
 }
 
 // Fit of the track in slot / index `i`: LAYOUT 2 reads the packed layout,

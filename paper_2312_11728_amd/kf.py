@@ -26,7 +26,8 @@ MAX_LAYERS = 64
 
 EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_propagate", "kf_update",
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
-           "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph"]
+           "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph",
+           "kf_set_kernel_timing", "kf_fit_kernel_time"]
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -98,6 +99,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_device_cu_count.argtypes = [_vp, ctypes.POINTER(_i32)]
     lib.kf_reserve.argtypes = [_vp, _i64, _i32]
     lib.kf_set_fit_graph.argtypes = [_vp, _i32]
+    lib.kf_set_kernel_timing.argtypes = [_vp, _i32]
+    lib.kf_fit_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64)]
     return lib
 
 
@@ -197,6 +201,18 @@ class Context:
     # ---- tuning -----------------------------------------------------------
     def set_fit_launch(self, dtype, block, persistent, blocks_per_cu, waves=1, layout=0):
         _check(lib().kf_set_fit_launch(self.handle, _prec(dtype), block, persistent, blocks_per_cu, waves, layout))
+
+    def set_kernel_timing(self, max_launches):
+        """Record HIP events around the fit kernel of the next `max_launches`
+        fit_tracks calls (0 turns it off; see kf_set_kernel_timing)."""
+        _check(lib().kf_set_kernel_timing(self.handle, int(max_launches)))
+
+    def fit_kernel_time(self):
+        """(total ms, launches, dropped) of the fit kernels recorded since the
+        last query; waits for them."""
+        ms, n, d = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().kf_fit_kernel_time(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(d)))
+        return ms.value, n.value, d.value
 
     def set_fit_graph(self, enable=True):
         """Replay kf_fit_tracks from a captured hipGraph (see kf_set_fit_graph)."""

@@ -96,8 +96,14 @@ def test_other_entry_points_validate():
     assert lib.kf_set_fit_launch(P, 0, 100, 0, 4, 1, 0) == kf.KF_ERR_ARG
     assert lib.kf_set_fit_launch(P, 0, 128, 2, 4, 1, 0) == kf.KF_ERR_ARG
     assert lib.kf_set_fit_launch(P, 0, 128, 0, 4, 3, 0) == kf.KF_ERR_ARG
-    assert lib.kf_set_fit_launch(P, 0, 128, 0, 4, 1, 3) == kf.KF_ERR_ARG
+    assert lib.kf_set_fit_launch(P, 0, 128, 0, 4, 1, 5) == kf.KF_ERR_ARG
     assert lib.kf_reserve(P, -1, 26) == kf.KF_ERR_ARG
+    assert lib.kf_set_kernel_timing(P, -1) == kf.KF_ERR_ARG
+    assert lib.kf_set_kernel_timing(P, 4097) == kf.KF_ERR_ARG
+    assert "max_launches" in lib.kf_last_error().decode()
+    assert lib.kf_set_kernel_timing(None, 8) == kf.KF_ERR_ARG
+    assert lib.kf_fit_kernel_time(P, None, None, None) == kf.KF_ERR_ARG
+    assert "total_ms" in lib.kf_last_error().decode()
     assert lib.kf_reserve(P, 10, 65) == kf.KF_ERR_ARG
 
 
