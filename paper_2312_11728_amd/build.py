@@ -17,6 +17,11 @@ ARCH = os.environ.get("KF_OFFLOAD_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # no -ffp-contract option: the compiler's default contraction is
+         # kept.  With -ffp-contract=on or =fast the FP64 adjoint kernel gave
+         # non-finite gradients on the GPU (cause not found; the same sources
+         # run correctly on the host); rerun the adjoint GPU tests before
+         # changing this.
          "-Wno-unused-command-line-argument"]
 
 
