@@ -205,8 +205,11 @@ KF_HD inline void helix_eval(const T p[6], T sphi, T cphi, T cot, T w, T s, Heli
   o.cmid = cmid;
 }
 
-// Move a helix point by a small extra path ds (first order; used for the
-// Newton correction of the crossing, |w ds| ~ 1e-6).
+// Move a helix point by a small extra path ds, to first order in w ds: the
+// position and chord move along the direction at s, the direction turns by
+// w ds, and the half-angle quantities (h = u/2) turn by w ds / 2, so every
+// identity between the fields keeps holding to second order.  The dropped
+// terms are (w ds)^2 / 2 in the angles and |w| ds^2 / 2 in the position.
 template <typename T>
 KF_HD inline void helix_nudge(HelixPt<T>& o, T w, T cot, T ds) {
   o.x += ds * o.cphm;
@@ -215,10 +218,21 @@ KF_HD inline void helix_nudge(HelixPt<T>& o, T w, T cot, T ds) {
   o.dy += ds * o.sphm;
   o.z += ds * cot;
   const T dphi = w * ds;
+  const T h = T(0.5) * o.u;
   o.phi += dphi;
+  o.u += dphi;
   const T sp = o.sphm, cp = o.cphm;
   o.sphm = sp + dphi * cp;
   o.cphm = cp - dphi * sp;
+  const T dh = T(0.5) * dphi;
+  // d sinc(h) / dh = (cos h - sinc h) / h, = -h/3 to O(h^3) near 0
+  const T dshc = k_abs(h) < T(0.05) ? -h * T(1.0 / 3.0) : (o.ch - o.shc) * k_rcp(h);
+  const T sh = o.sh, ch = o.ch, sm = o.smid, cm = o.cmid;
+  o.sh = sh + dh * ch;
+  o.ch = ch - dh * sh;
+  o.smid = sm + dh * cm;
+  o.cmid = cm - dh * sm;
+  o.shc += dh * dshc;
 }
 
 // First admissible crossing of the layer surface.  Barrel: roots of
@@ -274,10 +288,16 @@ KF_HD bool crossing(const T p[6], T sphi, T cphi, T cot, T w, int kind, T pos, b
     }
   }
   if (!found) return false;
-  // Newton polish on h(s) = r(s)^2 - R^2: two steps, the point moved along
-  // the helix to first order in the correction (the second step matters near
-  // tangency, where h'(s) is small and the closed-form root is least accurate)
+  // Newton polish on h(s) = r(s)^2 - R^2: two steps (the second matters near
+  // tangency, where h'(s) is small and the closed-form root is least
+  // accurate).  In FP32 a correction whose second-order terms stay below a
+  // hundredth of a unit in the last place, (w ds)^2 in the angles and
+  // |w| ds^2 against R in the position, moves the point to first order
+  // (helix_nudge); otherwise, and always in FP64, the point is evaluated
+  // afresh.
   helix_eval(p, sphi, cphi, cot, w, best, hp);
+  constexpr bool kNudge = sizeof(T) == 4;
+  const T tiny = T(0.01 * 1.1920929e-7);
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     const T f = (hp.x * hp.x + hp.y * hp.y - pos * pos);
@@ -285,7 +305,11 @@ KF_HD bool crossing(const T p[6], T sphi, T cphi, T cot, T w, int kind, T pos, b
     if (k_abs(df) > T(1e-20)) {
       const T ds = -f * k_rcp(df);
       best += ds;
-      helix_eval(p, sphi, cphi, cot, w, best, hp);
+      const T wd = w * ds;
+      if (kNudge && wd * wd <= tiny && k_abs(w) * ds * ds <= tiny * pos)
+        helix_nudge(hp, w, cot, ds);
+      else
+        helix_eval(p, sphi, cphi, cot, w, best, hp);
     }
   }
   s_out = best;
