@@ -305,18 +305,30 @@ __global__ void zero_ints_kernel(int32_t* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// Tracks of the length sort per block: a contiguous range, walked in steps of
+// the block size, so that a 500k-track batch needs a few hundred blocks and
+// the per-block global atomics stay few.
+constexpr int kSortPerBlock = 2048;
+
+__device__ __forceinline__ int clamped_length(const int32_t* off, int64_t t, int32_t max_len) {
+  const int len = off[t + 1] - off[t];
+  return len < 0 ? 0 : (len > max_len ? max_len : len);
+}
+
 // entry count of every track (clamped to max_len) into a histogram: per-block
 // counts in LDS, then one global atomic per block and length
-__global__ void __launch_bounds__(256) length_hist_kernel(const int32_t* off, int64_t n, int32_t max_len,
+constexpr int kSortBlock = 1024;
+
+__global__ void __launch_bounds__(kSortBlock) length_hist_kernel(const int32_t* off, int64_t n, int32_t max_len,
                                                           int32_t* hist) {
   __shared__ int32_t h[kMaxLen + 1];
   for (int i = threadIdx.x; i <= kMaxLen; i += blockDim.x) h[i] = 0;
   __syncthreads();
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < n) {
-    int len = off[t + 1] - off[t];
-    len = len < 0 ? 0 : (len > max_len ? max_len : len);
-    atomicAdd(&h[len], 1);
+  const int64_t b0 = int64_t(blockIdx.x) * kSortPerBlock;
+  const int64_t b1 = b0 + kSortPerBlock < n ? b0 + kSortPerBlock : n;
+  for (int64_t base = b0; base < b1; base += blockDim.x) {
+    const int64_t t = base + threadIdx.x;
+    if (t < b1) atomicAdd(&h[clamped_length(off, t, max_len)], 1);
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= kMaxLen; i += blockDim.x)
@@ -374,29 +386,38 @@ __global__ void __launch_bounds__(1024) cursor_tiles_kernel(const int32_t* hist,
   if (tid == 0) tile_base[n_tiles] = carry;
 }
 
-// slot of every track: each block reserves a range per length with one global
-// atomic, and ranks its tracks inside it through LDS atomics
-__global__ void __launch_bounds__(256) length_scatter_kernel(const int32_t* off, int64_t n, int32_t max_len,
-                                                             int32_t* cursor, int32_t* order, int32_t* slot_of) {
+// Slots of the length-sorted order: the block counts its tracks per length,
+// reserves its places with one global atomic per length on the cursors, then
+// hands them out through LDS atomics.  The order of tracks of equal length
+// depends on scheduling; no result does (every track is fitted by its own
+// lane with the same arithmetic, wherever it sits).
+__global__ void __launch_bounds__(kSortBlock) length_scatter_kernel(const int32_t* off, int64_t n, int32_t max_len,
+                                                                    int32_t* cursor, int32_t* order,
+                                                                    int32_t* slot_of) {
   __shared__ int32_t h[kMaxLen + 1];
   __shared__ int32_t base[kMaxLen + 1];
   for (int i = threadIdx.x; i <= kMaxLen; i += blockDim.x) h[i] = 0;
   __syncthreads();
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  int len = 0, rank = 0;
-  if (t < n) {
-    len = off[t + 1] - off[t];
-    len = len < 0 ? 0 : (len > max_len ? max_len : len);
-    rank = atomicAdd(&h[len], 1);
+  const int64_t b0 = int64_t(blockIdx.x) * kSortPerBlock;
+  const int64_t b1 = b0 + kSortPerBlock < n ? b0 + kSortPerBlock : n;
+  for (int64_t s0 = b0; s0 < b1; s0 += blockDim.x) {
+    const int64_t t = s0 + threadIdx.x;
+    if (t < b1) atomicAdd(&h[clamped_length(off, t, max_len)], 1);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i <= kMaxLen; i += blockDim.x)
+  for (int i = threadIdx.x; i <= kMaxLen; i += blockDim.x) {
     base[i] = h[i] ? atomicAdd(&cursor[i], h[i]) : 0;
+    h[i] = 0;
+  }
   __syncthreads();
-  if (t < n) {
-    const int slot = base[len] + rank;
-    order[slot] = int32_t(t);
-    slot_of[t] = slot;
+  for (int64_t s0 = b0; s0 < b1; s0 += blockDim.x) {
+    const int64_t t = s0 + threadIdx.x;
+    if (t < b1) {
+      const int len = clamped_length(off, t, max_len);
+      const int slot = base[len] + atomicAdd(&h[len], 1);
+      order[slot] = int32_t(t);
+      slot_of[t] = slot;
+    }
   }
 }
 
@@ -496,14 +517,15 @@ __global__ void __launch_bounds__(kPackBlock) pack_kernel(const int32_t* off, co
 template <typename T>
 hipError_t launch_pack(const FitArgs<T>& a, const PackWork& w, int layout, PackedHits<T>* out, hipStream_t s) {
   const int B = 256;
-  const unsigned grid = unsigned((a.n + B - 1) / B);
   const int nh = kMaxLen + 2;
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(128), 0, s, w.hist, nh);
-  hipLaunchKernelGGL(length_hist_kernel, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.n, a.max_len, w.hist);
+  const unsigned sort_grid = unsigned((a.n + kSortPerBlock - 1) / kSortPerBlock);
+  hipLaunchKernelGGL(length_hist_kernel, dim3(sort_grid), dim3(kSortBlock), 0, s, a.hit_offsets, a.n, a.max_len,
+                     w.hist);
   hipLaunchKernelGGL(cursor_tiles_kernel, dim3(1), dim3(1024), 0, s, w.hist, a.max_len, a.n, w.cursor,
                      layout == 2 ? w.tile_base : nullptr);
-  hipLaunchKernelGGL(length_scatter_kernel, dim3(grid), dim3(B), 0, s, a.hit_offsets, a.n, a.max_len, w.cursor,
-                     w.order, w.slot_of);
+  hipLaunchKernelGGL(length_scatter_kernel, dim3(sort_grid), dim3(kSortBlock), 0, s, a.hit_offsets, a.n,
+                     a.max_len, w.cursor, w.order, w.slot_of);
   out->order = w.order;
   out->tile_base = nullptr;
   out->lv = nullptr;
