@@ -242,17 +242,34 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, int
     }
     const int32_t z0 = z_bin(zp - w_z - 1e-4f, L.lo, L.hi, L.nz);
     const int32_t z1 = z_bin(zp + w_z + 1e-4f, L.lo, L.hi, L.nz);
-    for (int32_t b = b0; b <= b1; ++b) {
+    // Every phi bin's z range [z0, z1] is one contiguous run of the binned
+    // pool.  Reads run one step ahead, so that a load is in flight while the
+    // previous hit is scored: the next bin's run bounds while a bin is
+    // scanned, the next hit while a hit is scored (the index is clamped to
+    // the run, the last read repeats the current hit and is not used; an
+    // empty run reads nothing).
+    auto run_of = [&](int32_t b, int32_t& lo, int32_t& hi) {
       const int32_t pb = b < 0 ? b + L.nphi : (b >= L.nphi ? b - L.nphi : b);
-      const int32_t h0 = a.bin_off[L.base + pb * L.nz + z0];
-      const int32_t h1 = a.bin_off[L.base + pb * L.nz + z1 + 1];
+      lo = a.bin_off[L.base + pb * L.nz + z0];
+      hi = a.bin_off[L.base + pb * L.nz + z1 + 1];
+    };
+    int32_t h0, h1;
+    run_of(b0, h0, h1);
+    for (int32_t b = b0; b <= b1; ++b) {
+      int32_t n0 = 0, n1 = 0;
+      if (b < b1) run_of(b + 1, n0, n1);
+      PoolHit cur;
+      if (h0 < h1) cur = a.pool[h0];
       for (int32_t h = h0; h < h1; ++h) {
-        const PoolHit& ph = a.pool[h];
+        const PoolHit ph = cur;
+        cur = a.pool[h + 1 < h1 ? h + 1 : h];
         float d = ph.phi - phi_p;
         d = d > float(kPi) ? d - float(2 * kPi) : (d < -float(kPi) ? d + float(2 * kPi) : d);
         if (!(k_abs(d) <= dphi) || !(k_abs(ph.z - zp) <= w_z)) continue;
-        float m[3], V[6];
-        load_pool_hit(a, h, m, V);
+        const float m[3] = {ph.x, ph.y, ph.z};
+        float V[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) V[i] = ph.cov[i];
         const float c2 = hit_chi2(p, c, m, V, st);
         if (!(c2 <= a.chi2_max)) continue;
         // insert (score, id) into the sorted list; the last entry drops out
@@ -273,6 +290,8 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, int
         }
         ++nk;
       }
+      h0 = n0;
+      h1 = n1;
     }
   }
   if (nk == 0) {
