@@ -611,6 +611,41 @@ KF_HD void update_core(T p[6], T c[21], int& q, const T m[3], const T V[6], T& c
       K[i][j] = c[sym(i, 0)] * Si[sym(0, j)] + c[sym(i, 1)] * Si[sym(1, j)] + c[sym(i, 2)] * Si[sym(2, j)];
 #pragma unroll
   for (int i = 0; i < 6; ++i) p[i] += K[i][0] * r[0] + K[i][1] * r[1] + K[i][2] * r[2];
+  if constexpr (std::is_same<T, float>::value) {
+    // The Joseph form (I - K H) C (I - K H)^T + K V K^T, expanded: with
+    // B = C H^T (the first three columns of C) and S = H C H^T + V it equals
+    // C - K B^T - B K^T + K S K^T = C - K B^T - E K^T, E = B - K S, for any
+    // gain K.  E vanishes for the exact optimal gain and carries the rounding
+    // of K, which so enters C' at second order only, as in the factored
+    // form.  B is copied first (C is overwritten in place).
+    T B[6][3], E[6][3];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) B[i][k] = c[sym(i, k)];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T e = B[i][k];
+        e = e - K[i][0] * S[sym(0, k)];
+        e = e - K[i][1] * S[sym(1, k)];
+        e = e - K[i][2] * S[sym(2, k)];
+        E[i][k] = e;
+      }
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+      for (int i = j; i < 6; ++i) {
+        T v = c[sym(i, j)];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          v = v - K[i][k] * B[j][k];
+          v = v - E[i][k] * K[j][k];
+        }
+        c[sym(i, j)] = v;
+      }
+  } else {
   // Joseph form C' = A C A^T + K V K^T with A = I - K H, column by column:
   // (A C)_ij = c_ij - sum_k K_ik c_kj, C'_ij = (A C)_ij - sum_k (A C)_ik K_jk + (K V)_i . K_j.
   // Only (A C)[:, 0:3], K and K V stay live; columns are done from the last
@@ -637,6 +672,7 @@ KF_HD void update_core(T p[6], T c[21], int& q, const T m[3], const T V[6], T& c
       const T kvk = KV[i][0] * K[j][0] + KV[i][1] * K[j][1] + KV[i][2] * K[j][2];
       c[sym(i, j)] = aca + kvk;
     }
+  }
   if (p[3] < T(0)) {
     p[3] = -p[3];
     q = -q;
