@@ -101,11 +101,12 @@ def time_loop(fn, steps, warmup):
 
 
 def fit_kernel_name(launch):
-    """The kernel that one fit launch of this shape runs."""
+    """The kernel that one FP32 fit launch of this shape runs."""
     block, persistent, _, waves, layout = launch
-    base = "fit_staged" if layout >= 3 else "fit"
-    return "%s%s_kernel<float, %d, %s>" % (base, "_persistent" if persistent else "", waves,
-                                            ("true" if layout == 4 else "false") if layout >= 3 else str(layout))
+    if layout >= 3:
+        return "fit_staged%s_kernel<float, %d, %s>" % ("_persistent" if persistent else "", waves,
+                                                         "true" if layout == 4 else "false")
+    return "fit%s_kernel<float, %d, %d>" % ("_persistent" if persistent else "", waves, layout)
 
 
 def time_fit_kernel(ctx, fit_step, steps, warmup):
@@ -176,12 +177,16 @@ def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
             "ms_fit_direct_launches": ms_direct, "fit_kernel_ms": kernel_ms}
 
 
-def bench_adjoint(ctx, K, generate, workloads, args, seg=5):
+def bench_adjoint(ctx, K, generate, workloads, args, seg=1):
     """d(sum chi2)/d(seed states, hit positions, alignment offsets) for
     100,000 FP32 tracks x 20 barrel layers: the forward fit writing
     checkpoints every `seg` entries, then the reverse pass (which recomputes
     the states inside each segment) and the alignment reduction.  The
-    gradient is taken at zero alignment offsets (the nominal geometry)."""
+    gradient is taken at zero alignment offsets (the nominal geometry).
+    seg = 1 stores the state before every entry (213 MB here, nothing
+    against 288 GB of HBM) so that the reverse pass recomputes no segment;
+    the larger spacings trade memory for recomputation (seg 5: 45 MB,
+    adjoint kernel ~1.5x slower)."""
     import torch
     dev = torch.device("cuda", 0)
     wl = workloads()["align20"]
@@ -279,6 +284,10 @@ def profile_only(args, K, tune_fit, generate, workloads):
     dev = torch.device("cuda", 0)
     if args.profile_only in ("adjoint", "search"):
         ctx = K.Context(0)
+        if args.launch:
+            # the forward fit of the adjoint step, in the given FP32 launch shape
+            ctx.reserve(100_000, 26)
+            ctx.set_fit_launch(torch.float32, *[int(v) for v in args.launch.split(",")])
         a = argparse.Namespace(**vars(args))
         a.warmup = 1
         a.no_accuracy = True
