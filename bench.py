@@ -162,19 +162,26 @@ def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
         ctx.fit_tracks(seeds[0], seeds[1], seeds[2], t["hit_offsets"], t["hit_layer"], t["hit_valid"],
                        t["hit_pos"], t["hit_cov"], geom, out=out)
 
-    best, table = tune_fit(ctx, fit_step, torch.float32, n, use_cache=not args.retune, cache_path=args.tune_cache)
+    def step():
+        # spaced seeding and fit in one launch, as the headline step
+        ctx.seed_fit_tracks(t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"], geom, 1,
+                            out=out)
+
+    best, table = tune_fit(ctx, step, torch.float32, n, use_cache=not args.retune, cache_path=args.tune_cache)
     log("autotune mixed26", best, [(s_, round(ms, 4)) for s_, ms in table])
-    ms_direct, kernel_ms = time_fit_kernel(ctx, fit_step, args.steps, args.warmup)
+    ms_direct, kernel_ms = time_fit_kernel(ctx, step, args.steps, args.warmup)
     ctx.set_fit_graph(True)
-    ms = time_loop(fit_step, args.steps, args.warmup)
+    ms = time_loop(step, args.steps, args.warmup)
+    ms_fit = time_loop(fit_step, args.steps, args.warmup)
     ctx.set_fit_graph(False)
     flops = algorithmic_flops(ev)
     lens = ev.lengths()
     return {"tracks": n, "entries": int(ev.n_hits), "valid": int(ev.hit_valid.sum()),
-            "length_min": int(lens.min()), "length_max": int(lens.max()), "ms_fit": ms,
+            "length_min": int(lens.min()), "length_max": int(lens.max()), "ms_step": ms,
             "tracks_per_s": n / (ms * 1e-3), "achieved_tflops": flops / (kernel_ms * 1e-3) / 1e12,
             "frac_fp32_peak": flops / (kernel_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, "launch": list(best), "graph": True,
-            "ms_fit_direct_launches": ms_direct, "fit_kernel_ms": kernel_ms}
+            "ms_step_direct_launches": ms_direct, "fit_kernel_ms": kernel_ms, "ms_fit_tracks_given_seeds": ms_fit,
+            "step": "kf_seed_fit_tracks, spaced seeding"}
 
 
 def bench_adjoint(ctx, K, generate, workloads, args, seg=1):
@@ -321,9 +328,11 @@ def profile_only(args, K, tune_fit, generate, workloads):
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
+    mode = 1 if name == "mixed26" else 0
     for _ in range(args.steps):
-        ctx.fit_tracks(seeds[0], seeds[1], seeds[2], t["hit_offsets"], t["hit_layer"], t["hit_valid"],
-                       t["hit_pos"], t["hit_cov"], geom, out=out)
+        # the call the benchmark times: seeding and fit in one launch
+        ctx.seed_fit_tracks(t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"], geom,
+                            mode, out=out)
     torch.cuda.synchronize()
     log("profile-only", args.profile_only, "launch", ctx.get_fit_launch(dt), "steps", args.steps,
         "calibration copy bytes", src.numel() * 4)
@@ -381,21 +390,28 @@ def main():
             ctx.fit_tracks(seeds[0], seeds[1], seeds[2], t["hit_offsets"], t["hit_layer"], t["hit_valid"],
                            t["hit_pos"], t["hit_cov"], geom, out=out)
 
-        def step():
+        def two_calls():
             seed_step()
             fit_step()
 
+        def step():
+            # seeding and fit in one launch (kf_seed_fit_tracks): the same
+            # bits as the two calls above, without the seeds' round trip
+            ctx.seed_fit_tracks(t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"],
+                                geom, 0, out=out)
+
         seed_step()
-        best, table = tune_fit(ctx, fit_step, dt, n, use_cache=not args.retune, cache_path=args.tune_cache)
+        best, table = tune_fit(ctx, step, dt, n, use_cache=not args.retune, cache_path=args.tune_cache)
         log("autotune", dt, "best", best, "table", [(s_, round(ms, 4)) for s_, ms in table])
         log("timing", dt)
-        ms_fit_direct, kernel_ms = time_fit_kernel(ctx, fit_step, args.steps, args.warmup)
+        ms_fit_direct, kernel_ms = time_fit_kernel(ctx, step, args.steps, args.warmup)
         ctx.set_fit_graph(True)
         ms_step = time_loop(step, args.steps, args.warmup)
+        ms_two = time_loop(two_calls, args.steps, args.warmup)
         ms_fit = time_loop(fit_step, args.steps, args.warmup)
         ctx.set_fit_graph(False)
         res[dt] = dict(ms_step=ms_step, ms_fit=ms_fit, ms_fit_direct=ms_fit_direct, kernel_ms=kernel_ms, out=out,
-                       seeds=seeds, launch=best)
+                       seeds=seeds, launch=best, ms_two_calls=ms_two)
         log(dt, "ms/step", ms_step, "fit kernel ms", ms_fit)
 
     r32, r64 = res[torch.float32], res[torch.float64]
@@ -422,13 +438,16 @@ def main():
         "fp32_over_fp64": r64["ms_step"] / r32["ms_step"],
         "launch": {"fp32": list(r32["launch"]), "fp64": list(r64["launch"]),
                    "fields": ["block", "persistent", "blocks_per_cu", "waves_per_simd", "layout"],
-                   "graph": True, "ms_fit_fp32_direct_launches": r32["ms_fit_direct"]},
+                   "graph": True, "ms_fit_fp32_direct_launches": r32["ms_fit_direct"],
+                   "step": "kf_seed_fit_tracks (seeding and fit in one launch)",
+                   "ms_step_fp32_make_seeds_then_fit_tracks": r32["ms_two_calls"],
+                   "ms_fit_tracks_fp32_given_seeds": r32["ms_fit"]},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP32_PEAK_TFLOPS, "traffic": measured_traffic(r32["launch"]),
                      "traffic_unit": "bytes per launch (HBM, counters)", "fit_source_hash": fit_source_hash(),
                      "kernel": fit_kernel_name(r32["launch"]), "kernel_ms": r32["kernel_ms"],
                      "kernel_ms_source": "HIP events around each fit-kernel launch on the launching stream, "
-                                         "direct launches of the timed fit loop",
+                                         "direct launches of the timed seed-and-fit loop",
                      "fit_call_ms": r32["ms_fit"],
                      "algorithmic_flop_per_launch": flops,
                      "algorithmic_bytes_per_launch": algorithmic_bytes(ev, 4)},

@@ -184,6 +184,28 @@ int kf_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                   void *checkpoints, int32_t seg, int32_t max_len,
                   uint32_t *trk_status, void *stream);
 
+/* Seeding and fit in one launch: every track is seeded from its own hits
+ * exactly as kf_make_seeds does in seed_mode (0: the first three valid hits;
+ * 1: spaced by >= 3 cm in the transverse plane), with geom->bz_tesla as the
+ * field and the same wide diagonal covariance, then fitted as kf_fit_tracks
+ * fits it; results are bit-identical to kf_make_seeds followed by
+ * kf_fit_tracks with the same arguments, except that trk_status[t] holds
+ * the seeding bits (KF_TRK_BAD_INPUT: fewer than three usable hits) and the
+ * fit's together.  seed_state_out [6][ld], seed_cov_out [21][ld] and
+ * seed_charge_out [n] (device, each may be NULL) receive the seeds, for a
+ * later kf_fit_adjoint.  The other arguments, the layout and launch choices
+ * of the context, graph replay and kernel timing are those of kf_fit_tracks;
+ * KF_ERR_ARG for a seed_mode other than 0 or 1. */
+int kf_seed_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld, int32_t seed_mode,
+                       const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
+                       int64_t n_hits, const void *hit_pos, const void *hit_cov,
+                       const kf_geometry *geom, const void *align,
+                       void *seed_state_out, void *seed_cov_out, int8_t *seed_charge_out,
+                       void *state_out, void *cov_out, int8_t *charge_out,
+                       void *chi2, int32_t *ndf,
+                       void *checkpoints, int32_t seg, int32_t max_len,
+                       uint32_t *trk_status, void *stream);
+
 /* Parameters of the combinatorial candidate search (kf_score_hits).  The
  * paper makes the window, the chi2 cut, the missed-layer limit and the
  * candidate score per-iteration parameters and standard functions (Sec. 3.2,

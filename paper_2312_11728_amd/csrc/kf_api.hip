@@ -434,12 +434,19 @@ int kf_fit_kernel_time(kf_ctx* ctx, double* total_ms, int64_t* launches, int64_t
   return ok();
 }
 
-int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state, const void* seed_cov,
-                  const int8_t* seed_charge, const int32_t* hit_offsets, const int16_t* hit_layer,
-                  const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos, const void* hit_cov,
-                  const kf_geometry* geom, const void* align, void* state_out, void* cov_out, int8_t* charge_out,
-                  void* chi2, int32_t* ndf, void* checkpoints, int32_t seg, int32_t max_len, uint32_t* trk_status,
-                  void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The fit call shared by kf_fit_tracks (given seeds) and kf_seed_fit_tracks
+// (seed_mode >= 0: every track seeded from its hits inside the fit kernel).
+int fit_tracks_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state,
+                    const void* seed_cov, const int8_t* seed_charge, int32_t seed_mode, void* seed_state_out,
+                    void* seed_cov_out, int8_t* seed_charge_out, const int32_t* hit_offsets,
+                    const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
+                    const void* hit_cov, const kf_geometry* geom, const void* align, void* state_out, void* cov_out,
+                    int8_t* charge_out, void* chi2, int32_t* ndf, void* checkpoints, int32_t seg, int32_t max_len,
+                    uint32_t* trk_status, void* stream) {
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
@@ -447,10 +454,13 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
   if (checkpoints && seg < 1) return fail(KF_ERR_ARG, "seg = %d < 1", seg);
   if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);
+  if (seed_mode < -1 || seed_mode > 1) return fail(KF_ERR_ARG, "seed mode %d unknown (0 first three, 1 spaced)", seed_mode);
   if (n == 0) return ok();
-  KF_REQUIRE(seed_state);
-  KF_REQUIRE(seed_cov);
-  KF_REQUIRE(seed_charge);
+  if (seed_mode < 0) {
+    KF_REQUIRE(seed_state);
+    KF_REQUIRE(seed_cov);
+    KF_REQUIRE(seed_charge);
+  }
   KF_REQUIRE(hit_offsets);
   KF_REQUIRE(hit_layer);
   KF_REQUIRE(hit_valid);
@@ -479,6 +489,10 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
                                   hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf, checkpoints, seg,
                                   n_seg, trk_status, ctx->d_counter);
     a.max_len = max_len;
+    a.make_seeds = seed_mode + 1;
+    a.seed_state_out = (float*)seed_state_out;
+    a.seed_cov_out = (float*)seed_cov_out;
+    a.seed_charge_out = seed_charge_out;
     e = ctx->use_graph[pi] && !ctx->timing ? run_fit_graph(ctx, pi, a, g, l, layout, s)
                                            : run_fit(ctx, a, g, l, layout, s);
   } else {
@@ -486,11 +500,42 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
                                    n_hits, hit_pos, hit_cov, align, state_out, cov_out, charge_out, chi2, ndf,
                                    checkpoints, seg, n_seg, trk_status, ctx->d_counter);
     a.max_len = max_len;
+    a.make_seeds = seed_mode + 1;
+    a.seed_state_out = (double*)seed_state_out;
+    a.seed_cov_out = (double*)seed_cov_out;
+    a.seed_charge_out = seed_charge_out;
     e = ctx->use_graph[pi] && !ctx->timing ? run_fit_graph(ctx, pi, a, g, l, layout, s)
                                            : run_fit(ctx, a, g, l, layout, s);
   }
-  if (e != hipSuccess) return hip_fail(e, "kf_fit_tracks");
+  if (e != hipSuccess) return hip_fail(e, seed_mode < 0 ? "kf_fit_tracks" : "kf_seed_fit_tracks");
   return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state, const void* seed_cov,
+                  const int8_t* seed_charge, const int32_t* hit_offsets, const int16_t* hit_layer,
+                  const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos, const void* hit_cov,
+                  const kf_geometry* geom, const void* align, void* state_out, void* cov_out, int8_t* charge_out,
+                  void* chi2, int32_t* ndf, void* checkpoints, int32_t seg, int32_t max_len, uint32_t* trk_status,
+                  void* stream) {
+  return fit_tracks_impl(ctx, prec, n, ld, seed_state, seed_cov, seed_charge, -1, nullptr, nullptr, nullptr,
+                         hit_offsets, hit_layer, hit_valid, n_hits, hit_pos, hit_cov, geom, align, state_out, cov_out,
+                         charge_out, chi2, ndf, checkpoints, seg, max_len, trk_status, stream);
+}
+
+int kf_seed_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, int32_t seed_mode,
+                       const int32_t* hit_offsets, const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits,
+                       const void* hit_pos, const void* hit_cov, const kf_geometry* geom, const void* align,
+                       void* seed_state_out, void* seed_cov_out, int8_t* seed_charge_out, void* state_out,
+                       void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf, void* checkpoints, int32_t seg,
+                       int32_t max_len, uint32_t* trk_status, void* stream) {
+  if (seed_mode != 0 && seed_mode != 1) return fail(KF_ERR_ARG, "seed mode %d unknown (0 first three, 1 spaced)", seed_mode);
+  return fit_tracks_impl(ctx, prec, n, ld, nullptr, nullptr, nullptr, seed_mode, seed_state_out, seed_cov_out,
+                         seed_charge_out, hit_offsets, hit_layer, hit_valid, n_hits, hit_pos, hit_cov, geom, align,
+                         state_out, cov_out, charge_out, chi2, ndf, checkpoints, seg, max_len, trk_status, stream);
 }
 
 int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {

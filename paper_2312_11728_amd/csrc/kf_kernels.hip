@@ -210,7 +210,7 @@ __device__ void fit_wave_staged(const FitArgs<T>& a, const TrackGeom<T>& g, cons
   const int kmax = wave_max(len);
   T p[6], c[21];
   int q = 0;
-  if (in_range) load_seed(a, t, p, c, q);
+  if (in_range) load_seed(a, t, g.bz, p, c, q, st);
   T chi2 = T(0);
   int nval = 0, prev = 0, k0 = -1;
   bool live = in_range;

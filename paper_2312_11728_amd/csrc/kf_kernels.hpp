@@ -103,6 +103,13 @@ struct FitArgs {
   int32_t packed;         // layout: 0 CSR, 1 CSR in length-sorted order, 2 sorted and packed (pk),
                           // 3 CSR staged through LDS, 4 length-sorted CSR staged through LDS
   PackedHits<T> pk;
+  // seeding inside the fit: 0 reads seed_state / seed_cov / seed_charge;
+  // 1 + m seeds every track from its hits as the seeding kernel does in mode
+  // m, and writes the seeds to the *_out arrays that are not null
+  int32_t make_seeds;
+  T* seed_state_out;        // [6][ld] or null
+  T* seed_cov_out;          // [21][ld] or null
+  int8_t* seed_charge_out;  // [n] or null
 };
 
 // Workspace of the packed layout (carved out of one device allocation).

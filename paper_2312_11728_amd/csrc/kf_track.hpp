@@ -9,20 +9,32 @@ namespace kf {
 
 // Seed of track t from three of its valid hits (mode 0: the first three;
 // mode 1: the first, then each next one >= 3 cm away in the transverse plane
-// from the previously chosen one).
+// from the previously chosen one), with the charge and the status
+// (KF_TRK_BAD_INPUT without three such hits; the state is then zero).
 template <typename T>
-KF_HD inline void seed_track(const SeedArgs<T>& a, int64_t t) {
-  const int64_t e0 = a.hit_offsets[t], e1 = a.hit_offsets[t + 1];
-  const int64_t nh = a.n_hits;
+struct SeedOut {
+  T p[6];
+  int q;
+  uint32_t st;
+};
+
+// Not inlined: the seeding kernel and the fits that seed their own tracks
+// call one compiled copy, so both give the same bits.
+template <typename T>
+KF_HD __attribute__((noinline)) SeedOut<T> seed_of_track(const int32_t* __restrict__ off,
+                                                        const uint8_t* __restrict__ valid,
+                                                        const T* __restrict__ pos, int64_t nh, int64_t t, int mode,
+                                                        T bz) {
+  const int64_t e0 = off[t], e1 = off[t + 1];
   int64_t pick[3] = {-1, -1, -1};
   int cnt = 0;
   T lx = T(0), ly = T(0);
   for (int64_t e = e0; e < e1 && cnt < 3; ++e) {
-    if (!a.hit_valid[e]) continue;
-    const T hx = a.hit_pos[e], hy = a.hit_pos[nh + e];
+    if (!valid[e]) continue;
+    const T hx = pos[e], hy = pos[nh + e];
     bool take = (cnt == 0);
     if (!take) {
-      if (a.mode == 0) {
+      if (mode == 0) {
         take = true;
       } else {
         const T dx = hx - lx, dy = hy - ly;
@@ -35,28 +47,45 @@ KF_HD inline void seed_track(const SeedArgs<T>& a, int64_t t) {
       ly = hy;
     }
   }
-  T p[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  int q = 1;
-  uint32_t st = 0;
+  SeedOut<T> o;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) o.p[i] = T(0);
+  o.q = 1;
+  o.st = 0;
   if (cnt == 3) {
     T h[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) h[k][c] = a.hit_pos[c * nh + pick[k]];
-    seed_from_hits(h[0], h[1], h[2], T(a.bz), p, q);
+      for (int c = 0; c < 3; ++c) h[k][c] = pos[c * nh + pick[k]];
+    seed_from_hits(h[0], h[1], h[2], bz, o.p, o.q);
   } else {
-    st |= TRK_BAD_INPUT;
+    o.st |= TRK_BAD_INPUT;
   }
+  return o;
+}
+
+// the seed covariance: wide and diagonal, so that the first hits decide
+template <typename T>
+KF_HD inline void seed_covariance(T c[21]) {
   const T diag[6] = {T(1), T(1), T(1), T(1), T(0.01), T(0.01)};
-#pragma unroll
-  for (int i = 0; i < 6; ++i) a.seed_state[i * a.ld + t] = p[i];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j) a.seed_cov[sym(i, j) * a.ld + t] = (i == j) ? diag[i] : T(0);
-  a.seed_charge[t] = int8_t(q);
-  a.trk_status[t] = st;
+    for (int j = 0; j <= i; ++j) c[sym(i, j)] = (i == j) ? diag[i] : T(0);
+}
+
+template <typename T>
+KF_HD inline void seed_track(const SeedArgs<T>& a, int64_t t) {
+  const SeedOut<T> o = seed_of_track(a.hit_offsets, a.hit_valid, a.hit_pos, a.n_hits, t, int(a.mode), T(a.bz));
+  T c[21];
+  seed_covariance(c);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) a.seed_state[i * a.ld + t] = o.p[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) a.seed_cov[i * a.ld + t] = c[i];
+  a.seed_charge[t] = int8_t(o.q);
+  a.trk_status[t] = o.st;
 }
 
 template <typename T>
@@ -189,13 +218,33 @@ KF_HD inline bool fit_entry(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
   return true;
 }
 
+// The starting state of track t: the given seed, or (make_seeds) the seed
+// made from its hits, whose status bits go to st.
 template <typename T>
-KF_HD inline void load_seed(const FitArgs<T>& a, int64_t t, T p[6], T c[21], int& q) {
+KF_HD inline void load_seed(const FitArgs<T>& a, int64_t t, T bz, T p[6], T c[21], int& q, uint32_t& st) {
+  if (a.make_seeds == 0) {
 #pragma unroll
-  for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * a.ld + t];
+    for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * a.ld + t];
 #pragma unroll
-  for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * a.ld + t];
-  q = a.seed_charge[t];
+    for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * a.ld + t];
+    q = a.seed_charge[t];
+    return;
+  }
+  const SeedOut<T> o = seed_of_track(a.hit_offsets, a.hit_valid, a.hit_pos, a.n_hits, t, a.make_seeds - 1, bz);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) p[i] = o.p[i];
+  q = o.q;
+  st |= o.st;
+  seed_covariance(c);
+  if (a.seed_state_out) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a.seed_state_out[i * a.ld + t] = p[i];
+  }
+  if (a.seed_cov_out) {
+#pragma unroll
+    for (int i = 0; i < 21; ++i) a.seed_cov_out[i * a.ld + t] = c[i];
+  }
+  if (a.seed_charge_out) a.seed_charge_out[t] = int8_t(q);
 }
 
 template <typename T>
@@ -219,8 +268,8 @@ KF_HD inline void fit_track(const FitArgs<T>& a, const TrackGeom<T>& g, const T*
                             const Acc& acc, int len, T* bk, int bk_stride) {
   T p[6], c[21];
   int q;
-  load_seed(a, t, p, c, q);
   uint32_t st = 0;
+  load_seed(a, t, g.bz, p, c, q, st);
   if (len > a.max_len) {
     st |= TRK_BAD_INPUT;
     len = a.max_len;

@@ -27,7 +27,7 @@ MAX_LAYERS = 64
 EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_propagate", "kf_update",
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
            "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph",
-           "kf_set_kernel_timing", "kf_fit_kernel_time"]
+           "kf_set_kernel_timing", "kf_fit_kernel_time", "kf_seed_fit_tracks"]
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -89,6 +89,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_update.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                   ctypes.POINTER(KfGeometry), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp]
+    lib.kf_seed_fit_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _i32, _vp, _vp, _vp, _i64, _vp, _vp,
+                                       ctypes.POINTER(KfGeometry), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                       _i32, _i32, _vp, _vp]
     lib.kf_score_hits.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(KfGeometry),
                                   ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_adjoint.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
@@ -312,6 +315,42 @@ class Context:
                                    _ptr(out["status"]), _stream(dev)))
         return out
 
+
+    def seed_fit_tracks(self, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry, seed_mode,
+                        align=None, seeds=None, checkpoints=None, seg=1, max_len=26, out=None):
+        """Seeding and fit in one launch (kf_seed_fit_tracks).  seeds: None,
+        or a (state [6, n], cov [21, n], charge [n]) triple of device tensors
+        that receive the seeds.  Returns the fit outputs as fit_tracks does;
+        status holds the seeding and the fit bits."""
+        dev = self.device
+        dt = hit_pos.dtype
+        n = hit_offsets.shape[0] - 1
+        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need(hit_layer, "hit_layer", torch.int16, dev)
+        _need(hit_valid, "hit_valid", torch.uint8, dev)
+        _need(hit_pos, "hit_pos", dt, dev, rows=3)
+        _need(hit_cov, "hit_cov", dt, dev, rows=6)
+        if align is not None:
+            _need(align, "align", dt, dev, rows=2)
+        if checkpoints is not None:
+            _need(checkpoints, "checkpoints", dt, dev, rows=28)
+        ss = sc = sq = None
+        if seeds is not None:
+            ss, sc, sq = seeds
+            _need(ss, "seed_state", dt, dev, rows=6)
+            _need(sc, "seed_cov", dt, dev, rows=21)
+            _need(sq, "seed_charge", torch.int8, dev)
+            if ss.stride(0) != n or sc.stride(0) != n:
+                raise ValueError("seed outputs must have leading dimension n")
+        if out is None:
+            out = fit_outputs(n, dt, dev)
+        _check(lib().kf_seed_fit_tracks(self.handle, _prec(dt), n, n, int(seed_mode), _ptr(hit_offsets),
+                                        _ptr(hit_layer), _ptr(hit_valid), hit_pos.shape[1], _ptr(hit_pos),
+                                        _ptr(hit_cov), ctypes.byref(geom.struct), _ptr(align), _ptr(ss), _ptr(sc),
+                                        _ptr(sq), _ptr(out["state"]), _ptr(out["cov"]), _ptr(out["charge"]),
+                                        _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(checkpoints), int(seg),
+                                        int(max_len), _ptr(out["status"]), _stream(dev)))
+        return out
 
     def score_hits(self, seed_state, seed_cov, seed_charge, seed_layer, layer_plan, geom: Geometry,
                    params: SearchParams, pool_layer_offsets, pool_pos, pool_cov, pool_hit_id, want_state=True):

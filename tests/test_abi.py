@@ -98,6 +98,15 @@ def test_other_entry_points_validate():
     assert lib.kf_set_fit_launch(P, 0, 128, 0, 4, 3, 0) == kf.KF_ERR_ARG
     assert lib.kf_set_fit_launch(P, 0, 128, 0, 4, 1, 5) == kf.KF_ERR_ARG
     assert lib.kf_reserve(P, -1, 26) == kf.KF_ERR_ARG
+    g2 = ctypes.byref(g.struct)
+    assert lib.kf_seed_fit_tracks(P, 0, 5, 5, 2, P, P, P, 10, P, P, g2, None, None, None, None, P, P, P, P, P,
+                                  None, 1, 26, P, None) == kf.KF_ERR_ARG
+    assert "seed mode" in lib.kf_last_error().decode()
+    assert lib.kf_seed_fit_tracks(P, 0, 5, 5, 0, P, P, P, 10, None, P, g2, None, None, None, None, P, P, P, P, P,
+                                  None, 1, 26, P, None) == kf.KF_ERR_ARG
+    assert "hit_pos" in lib.kf_last_error().decode()
+    assert lib.kf_seed_fit_tracks(P, 0, 0, 0, 0, None, None, None, 0, None, None, g2, None, None, None, None, None,
+                                  None, None, None, None, None, 1, 26, None, None) == kf.KF_OK
     assert lib.kf_set_kernel_timing(P, -1) == kf.KF_ERR_ARG
     assert lib.kf_set_kernel_timing(P, 4097) == kf.KF_ERR_ARG
     assert "max_launches" in lib.kf_last_error().decode()

@@ -516,6 +516,62 @@ def test_fit_layouts_agree_on_irregular_entries(kf, dtype):
         c.close()
 
 
+@pytest.mark.parametrize("name,mode,dtype", [("barrel20", 0, torch.float32), ("mixed26", 1, torch.float32),
+                                             ("mixed26", 1, torch.float64)])
+def test_seed_fit_matches_seeding_then_fit(kf, name, mode, dtype):
+    """kf_seed_fit_tracks gives the bits of kf_make_seeds followed by
+    kf_fit_tracks, in both layout families, with and without checkpoints and
+    under graph replay: the same fit outputs, the same seeds written out, and
+    the status of the two calls or-ed.  Some tracks keep a single valid hit
+    (no seed: KF_TRK_BAD_INPUT from the seeding)."""
+    say("seed + fit", name, mode, dtype)
+    ev = generate(workloads()[name], 4000 + 17)
+    valid = ev.hit_valid.copy()
+    off = ev.hit_offsets
+    for tr in range(0, 80, 8):
+        valid[off[tr] + 1:off[tr + 1]] = 0
+    ev.hit_valid = valid
+    dev = torch.device("cuda", 0)
+    t = kf.event_tensors(ev, dtype, dev)
+    geom = kf.Geometry.from_toy(ev.geometry)
+    hits = (t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"])
+    n = ev.n_tracks
+    c = kf.Context(0)
+    try:
+        c.reserve(n, 26)
+        for shape in [(256, 0, 1, 1, 0), (256, 1, 4, 2, 2), (256, 0, 1, 2, 3), (128, 1, 4, 1, 4)]:
+            c.set_fit_launch(dtype, *shape)
+            for graph in (False, True):
+                c.set_fit_graph(graph)
+                for seg in (None, 3):
+                    ck = None if seg is None else torch.full((28, n * kf.n_checkpoint_segments(26, seg)), 7.0,
+                                                             dtype=dtype, device=dev)
+                    ck2 = None if ck is None else ck.clone()
+                    st, cov, q, sst = c.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"],
+                                                   ev.geometry.bz, mode)
+                    ref = c.fit_tracks(st, cov, q, *hits, geom, checkpoints=ck, seg=seg or 1)
+                    seeds = (torch.full_like(st, 5.0), torch.full_like(cov, 5.0), torch.full_like(q, 5))
+                    fused = c.seed_fit_tracks(*hits, geom, mode, seeds=seeds, checkpoints=ck2, seg=seg or 1)
+                    torch.cuda.synchronize()
+                    for k in ("state", "cov", "charge", "chi2", "ndf"):
+                        a_, b_ = ref[k].cpu().numpy(), fused[k].cpu().numpy()
+                        assert np.array_equal(a_, b_, equal_nan=a_.dtype.kind == "f"), (shape, graph, seg, k)
+                    assert torch.equal(fused["status"], ref["status"] | sst), (shape, graph, seg)
+                    assert torch.equal(seeds[0], st) and torch.equal(seeds[1], cov) and torch.equal(seeds[2], q)
+                    if ck is not None:
+                        assert torch.equal(ck.isnan(), ck2.isnan())
+                        assert torch.equal(ck.nan_to_num(0.0), ck2.nan_to_num(0.0)), (shape, graph)
+            c.set_fit_graph(False)
+        bad = ((sst.cpu().numpy() & kf.TRK_BAD_INPUT) != 0)
+        assert bad[:80:8].all()
+        # without seed outputs
+        plain = c.seed_fit_tracks(*hits, geom, mode)
+        torch.cuda.synchronize()
+        assert torch.equal(plain["chi2"].nan_to_num(0.0), fused["chi2"].nan_to_num(0.0))
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("layout,persistent", [(2, 1), (0, 1), (1, 0), (3, 1), (4, 0)])
 def test_fit_graph_replay_matches_direct_launches(kf, layout, persistent):
     """Graph replays (several, with the program's own eager work and
