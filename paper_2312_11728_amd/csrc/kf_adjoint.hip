@@ -22,13 +22,15 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs<T> a, GeomArgs g) 
                 t, acc, len, e0);
 }
 
-// Stage 1: one wave per 64 consecutive tracks.  A barrel hit h with gradient
-// hb contributes (h_x hb_y - h_y hb_x)/R to the r-phi offset of its layer (the
-// rotation m = R(a/R) h keeps the cross product) and hb_z to the z offset;
-// disk hits and holes contribute 0.  Each lane walks its track's entries and
-// adds into its own LDS column; then lane l adds the 64 columns of layer l in
-// lane order.  Fixed order throughout: the result does not depend on
-// scheduling.
+// Stage 1: one wave per kAlignPerBlock consecutive entries of the batch
+// (entries hit_offsets[0] .. hit_offsets[n]), lane l taking entries l,
+// l + 64, ... of the block's range, so that every load of the wave is
+// coalesced.  A barrel hit h with gradient hb contributes
+// (h_x hb_y - h_y hb_x)/R to the r-phi offset of its layer (the rotation
+// m = R(a/R) h keeps the cross product) and hb_z to the z offset; disk hits
+// and holes contribute 0.  Each lane adds into its own LDS column; then lane
+// l adds the 64 columns of layer l in lane order.  Fixed order throughout:
+// the result does not depend on scheduling.
 template <typename T>
 __global__ void __launch_bounds__(64) align_partial_kernel(AdjArgs<T> a, GeomArgs g) {
   __shared__ T part[2][kMaxLayers][64];
@@ -37,16 +39,21 @@ __global__ void __launch_bounds__(64) align_partial_kernel(AdjArgs<T> a, GeomArg
     part[0][l][lane] = T(0);
     part[1][l][lane] = T(0);
   }
-  const int64_t t = int64_t(blockIdx.x) * 64 + lane;
   const int64_t nh = a.f.n_hits;
-  if (t < a.f.n) {
-    const int64_t e0 = a.f.hit_offsets[t], e1 = a.f.hit_offsets[t + 1];
-    for (int64_t e = e0; e < e1; ++e) {
-      if (!a.f.hit_valid[e]) continue;
-      const int l = a.f.hit_layer[e];
-      if (l < 0 || l >= g.n_layers || g.kind[l] != 0) continue;
-      const T hx = a.f.hit_pos[e], hy = a.f.hit_pos[nh + e];
-      const T gx = a.grad_hit[e], gy = a.grad_hit[nh + e], gz = a.grad_hit[2 * nh + e];
+  const int64_t first = a.f.hit_offsets[0], last = a.f.hit_offsets[a.f.n];
+  const int64_t b0 = first + int64_t(blockIdx.x) * kAlignPerBlock;
+  // loads from a clamped index and predicates instead of early exits, so
+  // that the loads of several iterations are in flight together
+#pragma unroll 8
+  for (int k = 0; k < kAlignPerBlock / 64; ++k) {
+    const int64_t e = b0 + int64_t(k) * 64 + lane;
+    const bool in = e < last;
+    const int64_t ee = in ? e : first;
+    const bool v = a.f.hit_valid[ee] != 0;
+    const int l = a.f.hit_layer[ee];
+    const T hx = a.f.hit_pos[ee], hy = a.f.hit_pos[nh + ee];
+    const T gx = a.grad_hit[ee], gy = a.grad_hit[nh + ee], gz = a.grad_hit[2 * nh + ee];
+    if (in && v && l >= 0 && l < g.n_layers && g.kind[l] == 0) {
       part[0][l][lane] += (hx * gy - hy * gx) / T(g.pos[l]);
       part[1][l][lane] += gz;
     }
@@ -86,7 +93,8 @@ hipError_t launch_adjoint(const AdjArgs<T>& a, const GeomArgs& g, hipStream_t s)
     if (e != hipSuccess) return e;
   }
   if (a.grad_align) {
-    const int64_t nb = adjoint_partial_blocks(a.f.n);
+    // no tracks: nothing contributes (and the offsets may be absent)
+    const int64_t nb = a.f.n > 0 ? adjoint_partial_blocks(a.f.n_hits) : 0;
     if (nb > 0) hipLaunchKernelGGL(align_partial_kernel<T>, dim3(unsigned(nb)), dim3(64), 0, s, a, g);
     hipLaunchKernelGGL(align_final_kernel<T>, dim3(unsigned(2 * g.n_layers)), dim3(256), 0, s, a, g.n_layers, nb);
   }

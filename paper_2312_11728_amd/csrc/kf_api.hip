@@ -869,7 +869,7 @@ int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const 
   hipStream_t s = (hipStream_t)stream;
   const size_t esz = prec == KF_F32 ? 4 : 8;
   if (grad_align) {
-    const size_t need = size_t(kf::adjoint_partial_blocks(n)) * 2 * kf::kMaxLayers * esz;
+    const size_t need = size_t(kf::adjoint_partial_blocks(n_hits)) * 2 * kf::kMaxLayers * esz;
     if (need > ctx->red_bytes) {
       int prev = 0;
       hipGetDevice(&prev);

@@ -158,10 +158,11 @@ struct AdjArgs {
   T* grad_seed;                // [6][ld]
   T* grad_hit;                 // [3][n_hits]
   T* grad_align;               // [2][n_layers] or null
-  T* partial;                  // [adjoint_partial_blocks(n)][2][kMaxLayers] when grad_align is set
+  T* partial;                  // [adjoint_partial_blocks(n_hits)][2][kMaxLayers] when grad_align is set
 };
-// blocks (64 tracks each) of the alignment reduction
-inline int64_t adjoint_partial_blocks(int64_t n_tracks) { return (n_tracks + 63) / 64; }
+// blocks of the alignment reduction (kAlignPerBlock entries each)
+constexpr int kAlignPerBlock = 64 * 32;
+inline int64_t adjoint_partial_blocks(int64_t n_hits) { return (n_hits + kAlignPerBlock - 1) / kAlignPerBlock; }
 template <typename T>
 hipError_t launch_adjoint(const AdjArgs<T>& a, const GeomArgs& g, hipStream_t s);
 
