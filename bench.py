@@ -469,6 +469,9 @@ def main():
     if not args.no_uneven:
         line["uneven_mixed26"] = bench_uneven(ctx, K, tune_fit, generate, workloads, args)
     if not args.no_adjoint:
+        # the forward fit in the launch shape tuned for 100k tracks x 20 layers
+        # (the mixed26 leg retunes the context for its own batch)
+        ctx.set_fit_launch(torch.float32, *r32["launch"])
         line["fwd_adjoint_align20"] = bench_adjoint(ctx, K, generate, workloads, args)
     if not args.no_search:
         line["search20"] = bench_search(ctx, K, args)
