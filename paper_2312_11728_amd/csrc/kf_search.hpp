@@ -326,49 +326,88 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, int
 KF_HD inline void select_seed(const SearchArgs& a, int64_t t) {
   const int64_t S = a.n * a.beam;
   const int64_t s0 = t * a.beam;
-  int head[kMaxBeam], cnt[kMaxBeam];
+  // The child lists of the seed's slots, read at once: each is sorted best
+  // first, so only its first `beam` entries can be chosen; absent entries
+  // rank last.  The heads of the lists compete (ties by child id, then by
+  // the parent's rank), and the chosen list moves up by one place; every
+  // index is static, so the lists stay in registers.
+  float ks[kMaxBeam][kMaxBeam];
+  int32_t kk[kMaxBeam][kMaxBeam];
+  int cnt[kMaxBeam], taken[kMaxBeam];
 #pragma unroll
   for (int r = 0; r < kMaxBeam; ++r) {
-    head[r] = 0;
     cnt[r] = r < a.beam ? a.kid_n[s0 + r] : 0;
+    taken[r] = 0;
   }
-  int out = 0;
-  for (; out < a.beam; ++out) {
-    int best = -1;
+#pragma unroll
+  for (int r = 0; r < kMaxBeam; ++r)
+#pragma unroll
+    for (int j = 0; j < kMaxBeam; ++j) {
+      const bool in = j < cnt[r] && j < a.beam;
+      const int64_t k = (s0 + (in ? r : 0)) * kMaxBeam + (in ? j : 0);
+      ks[r][j] = in ? a.kid_score[k] : -k_inf<float>();
+      kk[r][j] = in ? a.kid_id[k] : kStopKey;
+    }
+  int o_par[kMaxBeam], o_pos[kMaxBeam];
+  float o_score[kMaxBeam];
+  int32_t o_key[kMaxBeam];
+  int n_out = 0;
+#pragma unroll
+  for (int out = 0; out < kMaxBeam; ++out) {
+    o_par[out] = -1;
+    o_pos[out] = 0;
+    o_score[out] = 0.f;
+    o_key[out] = 0;
+    if (out >= a.beam || n_out < out) continue;
+    int best = -1, bpos = 0;
     float bs = 0.f;
     int32_t bk = 0;
 #pragma unroll
     for (int r = 0; r < kMaxBeam; ++r) {
-      if (head[r] < cnt[r]) {
-        const int64_t k = (s0 + r) * kMaxBeam + head[r];
-        const float sc = a.kid_score[k];
-        const int32_t key = a.kid_id[k];
-        if (best < 0 || child_before(sc, key, r, bs, bk, best)) {
-          best = r;
-          bs = sc;
-          bk = key;
-        }
+      if (taken[r] < cnt[r] && (best < 0 || child_before(ks[r][0], kk[r][0], r, bs, bk, best))) {
+        best = r;
+        bpos = taken[r];
+        bs = ks[r][0];
+        bk = kk[r][0];
       }
     }
-    if (best < 0) break;
-    int hb = 0;
+    if (best < 0) continue;
+    o_par[out] = best;
+    o_pos[out] = bpos;
+    o_score[out] = bs;
+    o_key[out] = bk;
+    n_out = out + 1;
 #pragma unroll
-    for (int r = 0; r < kMaxBeam; ++r)
-      if (r == best) hb = head[r];
-    const int64_t k = (s0 + best) * kMaxBeam + hb;
-    const int32_t idx = a.kid_idx[k];
+    for (int r = 0; r < kMaxBeam; ++r) {
+      if (r == best) {
+#pragma unroll
+        for (int j = 0; j + 1 < kMaxBeam; ++j) {
+          ks[r][j] = ks[r][j + 1];
+          kk[r][j] = kk[r][j + 1];
+        }
+        ++taken[r];
+      }
+    }
+  }
+  // the chosen children's pool indices and their parents' misses, read at
+  // once, then the selection
+#pragma unroll
+  for (int out = 0; out < kMaxBeam; ++out) {
+    if (out >= a.beam) continue;
     const int64_t so = s0 + out;
+    if (out >= n_out) {
+      a.sel_parent[so] = -1;
+      continue;
+    }
+    const int best = o_par[out];
+    const int32_t idx = a.kid_idx[(s0 + best) * kMaxBeam + o_pos[out]];
     a.sel_parent[so] = int8_t(best);
     a.sel_idx[so] = idx;
-    a.sel_score[so] = bs;
+    a.sel_score[so] = o_score[out];
     a.sel_miss[so] = int8_t(a.cur_miss[s0 + best] + (idx == kMissIdx ? 1 : 0));
     a.hist_parent[int64_t(a.step) * S + so] = int8_t(best);
-    a.hist_id[int64_t(a.step) * S + so] = idx >= 0 ? bk : idx;
-#pragma unroll
-    for (int r = 0; r < kMaxBeam; ++r)
-      if (r == best) ++head[r];
+    a.hist_id[int64_t(a.step) * S + so] = idx >= 0 ? o_key[out] : idx;
   }
-  for (; out < a.beam; ++out) a.sel_parent[s0 + out] = -1;
 }
 
 // After the last layer: the kept candidates' final states (update with their
