@@ -217,18 +217,31 @@ __device__ void fit_wave_staged(const FitArgs<T>& a, const TrackGeom<T>& g, cons
   const int64_t nh = a.n_hits;
   wave_sync();
   for (int j0 = 0; j0 < kmax; j0 += J) {
+    // All J rows are loaded before any is written to LDS, so the chunk costs
+    // one memory round trip.  A slot past the end of its track loads the
+    // track's last entry instead (an address that is always valid: kmax > 0
+    // means some track has an entry, so n_hits > 0); that slot is never read.
+    int32_t lvr[J];
+    T vr[J][9];
 #pragma unroll
     for (int r = 0; r < J; ++r) {
       const int idx = r * 64 + lane;
       const int l = idx / J, jj = idx % J;
-      if (j0 + jj < sb.len[l]) {
-        const int64_t e = sb.e0[l] + j0 + jj;
-        sb.lv[jj][l] = int32_t(uint16_t(a.hit_layer[e])) | (a.hit_valid[e] ? (1 << 16) : 0);
+      const int ln = sb.len[l];
+      const int64_t e = ln > 0 ? sb.e0[l] + min(j0 + jj, ln - 1) : 0;
+      lvr[r] = int32_t(uint16_t(a.hit_layer[e])) | (a.hit_valid[e] ? (1 << 16) : 0);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) sb.v[k][jj][l] = a.hit_pos[k * nh + e];
+      for (int k = 0; k < 3; ++k) vr[r][k] = a.hit_pos[k * nh + e];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) sb.v[3 + k][jj][l] = a.hit_cov[k * nh + e];
-      }
+      for (int k = 0; k < 6; ++k) vr[r][3 + k] = a.hit_cov[k * nh + e];
+    }
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+      const int idx = r * 64 + lane;
+      const int l = idx / J, jj = idx % J;
+      sb.lv[jj][l] = lvr[r];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sb.v[k][jj][l] = vr[r][k];
     }
     wave_sync();
     const int jn = min(J, kmax - j0);
