@@ -361,3 +361,66 @@ def test_adjoint_empty_batch(ctx, kf):
     torch.cuda.synchronize()
     assert gs.shape == (6, 0) and gh.shape == (3, 0)
     assert not ga.any()
+
+
+def test_adjoint_full_size_sampled(kf):
+    """align20 at its full size (100,000 FP32 tracks x 20 barrel layers) in the
+    benchmark's configuration: the forward fit in the staged launch shape with
+    the state checkpointed before every entry (seg 1), zero alignment
+    offsets, the adjoint and the alignment reduction.  Tracks are independent,
+    so 40 sampled tracks are held to the FP64 oracle's gradient computed on
+    those tracks alone, within the FP32 bounds above.  The alignment gradient
+    sums over all 2,000,000 entries; it is held to the same sum formed in FP64
+    from the returned hit-position gradients (d(hit)/d(offset) at zero
+    offsets: (-y, x, 0) / R for the r-phi offset, (0, 0, 1) for z), to 2e-5 of
+    the sum of the terms' magnitudes (FP32 sums of 100,000 terms per layer)."""
+    from toygen import subset
+    say("adjoint full size align20")
+    wl = workloads()["align20"]
+    ev = generate(wl)
+    n, nh = ev.n_tracks, ev.n_hits
+    dev = torch.device("cuda", 0)
+    dt = torch.float32
+    c = kf.Context(0)
+    try:
+        c.set_fit_launch(dt, 256, 0, 1, 2, 3)
+        t = kf.event_tensors(ev, dt, dev)
+        geom = kf.Geometry.from_toy(wl.geometry)
+        max_len = int(ev.lengths().max())
+        st, cov, q, _ = c.make_seeds(t["hit_offsets"], t["hit_valid"], t["hit_pos"], wl.geometry.bz, 0)
+        al = torch.zeros(2, wl.geometry.n_layers, dtype=dt, device=dev)
+        ck = torch.empty(28, n * kf.n_checkpoint_segments(max_len, 1), dtype=dt, device=dev)
+        out = c.fit_tracks(st, cov, q, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"],
+                           geom, align=al, checkpoints=ck, seg=1, max_len=max_len)
+        gs, gh, ga = c.fit_adjoint(st, cov, q, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"],
+                                   t["hit_cov"], geom, ck, 1, max_len, out["status"], align=al)
+        torch.cuda.synchronize()
+        f = lambda x: x.double().cpu().numpy()
+        gs, gh, ga, hp = f(gs).T, f(gh), f(ga), f(t["hit_pos"])
+        seed, seed_cov, seed_q = f(st).T, unpack(f(cov)), q.cpu().numpy().astype(np.float64)
+    finally:
+        c.close()
+    assert np.isfinite(gs).all() and np.isfinite(gh).all() and np.isfinite(ga).all()
+    # alignment gradient: the full-size sum against the FP64 sum of its terms
+    R = wl.geometry.pos[ev.hit_layer].astype(np.float64)
+    v = ev.hit_valid.astype(bool)
+    terms_rphi = np.where(v, (hp[0] * gh[1] - hp[1] * gh[0]) / R, 0.0)
+    terms_z = np.where(v, gh[2], 0.0)
+    L = wl.geometry.n_layers
+    for row, terms in ((0, terms_rphi), (1, terms_z)):
+        ref = np.bincount(ev.hit_layer, weights=terms, minlength=L)
+        mag = np.bincount(ev.hit_layer, weights=np.abs(terms), minlength=L)
+        err = np.abs(ga[row] - ref)
+        say("  alignment row %d: max |err| / sum|terms| = %.2e" % (row, (err / np.maximum(mag, 1e-300)).max()))
+        assert (err <= 2e-5 * mag + 1e-30).all(), (row, int(np.argmax(err / np.maximum(mag, 1e-300))))
+    # sampled tracks against the oracle on those tracks alone
+    idx = np.sort(np.random.default_rng(2025).choice(n, 40, replace=False))
+    sub = subset(ev, idx)
+    g = dict(seed=seed[idx], seed_cov=seed_cov[idx], seed_q=seed_q[idx], gs=gs[idx],
+             gh=np.concatenate([gh[:, ev.hit_offsets[i]:ev.hit_offsets[i + 1]] for i in idx], axis=1))
+    o = oracle_grad(sub, g, dt)
+    es, eh = per_track_rel(sub, g, o)
+    ps, ph = fp32_probes(sub, g, o, None, None)
+    say("  sampled tracks: seed grad rel L2 max %.2e median %.2e; hit grad max %.2e median %.2e"
+        % (es.max(), np.median(es), eh.max(), np.median(eh)))
+    check_fp32(es, eh, (ps, ph))
