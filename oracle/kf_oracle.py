@@ -645,6 +645,131 @@ def fit_event(ev, align=None, seed_mode=SEED_FIRST_THREE):
 
 
 # --------------------------------------------------------------------------
+# f1: backward fit
+# --------------------------------------------------------------------------
+
+# The backward pass restarts from the forward fit's last state with its
+# covariance scaled up by this factor, so that the hits the forward pass
+# already used count (almost) once only.  The paper gives no value.
+BACKWARD_COV_SCALE = 100.0
+# forward status bits after which a track is not refitted (the forward pass
+# stopped before its last entry); such a track keeps its input and gets
+# NOT_REFITTED, the value of the C interface's bad-input bit
+NOT_REFITTED = 64
+
+
+def reverse_direction(p, C, q):
+    """The same track moving the opposite way along its helix: direction
+    (phi, theta) -> (phi + pi, pi - theta) and charge -q, position and ipt
+    unchanged.  The helix then turns the other way (omega = -q c_B B_z ipt
+    changes sign) and climbs the other way (cot theta changes sign), so it
+    traces the same curve backwards.  The Jacobian of the map is
+    J = diag(1, 1, 1, 1, 1, -1), hence C' = J C J.  p [n,6], C [n,6,6],
+    q [n]."""
+    p2 = torch.cat([p[:, :4], wrap_phi(p[:, 4:5] + math.pi), math.pi - p[:, 5:6]], dim=1)
+    J = torch.diag(torch.tensor([1.0, 1.0, 1.0, 1.0, 1.0, -1.0], dtype=DT))
+    return p2, J @ C @ J, -q
+
+
+def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
+                 cov_scale=BACKWARD_COV_SCALE):
+    """Backward fit (Sec. 2.2, step 4): every track is traversed again, from
+    its last entry back to its first valid entry, and refitted.
+
+    Input: the forward fit's result (fwd_p [n,6], fwd_C [n,6,6], fwd_q [n],
+    fwd_status [n]), which sits on the track's last entry.  Its covariance is
+    multiplied by cov_scale and the direction of motion reversed
+    (reverse_direction); the entries are then taken in reverse order with the
+    forward pass's rules: the first (the last entry) adds its layer's material
+    at the current state, every later one is propagated to (the re-crossing
+    window when the entry before it in this order was on the same layer),
+    gets its layer's material and, if valid, an update; a failed crossing or a
+    non-finite result freezes the track.  The result, on the first valid
+    entry, is turned back to the outward direction.  Tracks the forward pass
+    stopped (NO_CROSSING or NONFINITE in fwd_status) or with no valid entry
+    keep their input, with status NOT_REFITTED.  Returns dict(p, C, q, chi2,
+    ndf, status): chi2 and ndf (= 2 * used hits - 5) of the backward pass."""
+    off = torch.as_tensor(hit_offsets, dtype=torch.int64)
+    lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
+    val_all = torch.as_tensor(hit_valid, dtype=torch.int64)
+    V_all = unpack_sym(hit_cov, 3)
+    m_all = hit_pos if torch.is_tensor(hit_pos) else _t(hit_pos)
+    m_all = m_all.T
+    kind_l = torch.as_tensor(geom.kind, dtype=torch.int64)
+    pos_l = _t(geom.pos)
+    x0_l = _t(geom.x_over_x0)
+    n = off.shape[0] - 1
+    fwd_status = torch.as_tensor(fwd_status, dtype=torch.int64)
+
+    # first valid entry of each track (forward order); the pass runs from the
+    # last entry down to it
+    k0 = torch.full((n,), -1, dtype=torch.int64)
+    lens = off[1:] - off[:-1]
+    maxlen = int(lens.max()) if n > 0 else 0
+    for j in range(maxlen - 1, -1, -1):
+        e = off[:-1] + j
+        has = j < lens
+        ev = torch.where(has, e, torch.zeros_like(e))
+        k0 = torch.where(has & (val_all[ev] == 1), e, k0)
+    last = off[1:] - 1
+    run = (k0 >= 0) & ((fwd_status & (NO_CROSSING | NONFINITE | NOT_REFITTED)) == 0)
+
+    p, C, q = reverse_direction(_t(fwd_p), _t(fwd_C) * cov_scale, _t(fwd_q))
+    chi2 = torch.zeros(n, dtype=DT)
+    nval = torch.zeros(n, dtype=torch.int64)
+    status = torch.zeros(n, dtype=torch.int64)
+    alive = run.clone()
+    prev_e = last.clone()
+    for j in range(maxlen):
+        e = last - j
+        act = alive & (e >= k0)
+        idx = torch.nonzero(act)[:, 0]
+        if idx.numel() == 0:
+            break
+        ei = e[idx]
+        lay = lay_all[ei]
+        kind = kind_l[lay]
+        pp, CC, qq = p[idx], C[idx], q[idx]
+        if j > 0:
+            same = lay == lay_all[prev_e[idx]]
+            pp2, CC2, _, st = propagate(pp, CC, qq, kind, pos_l[lay], x0_l[lay], geom, apply_material=True, same=same)
+        else:
+            Q, grazing = process_noise(pp, kind, x0_l[lay], geom.mass)
+            pp2, CC2 = pp, CC + Q
+            st = torch.where(grazing, GRAZING, 0).to(torch.int64)
+        good = (st & NO_CROSSING) == 0
+        valid = (val_all[ei] == 1) & good
+        pu, Cu, qu, c2, st_u = update(pp2, CC2, qq, m_all[ei], V_all[ei])
+        pn = torch.where(valid[:, None], pu, pp2)
+        Cn = torch.where(valid[:, None, None], Cu, CC2)
+        qn = torch.where(valid, qu, qq)
+        c2n = torch.where(valid, c2, torch.zeros_like(c2))
+        st = st | torch.where(valid, st_u, 0)
+        finite = torch.isfinite(pn).all(dim=1) & torch.isfinite(Cn).flatten(1).all(dim=1) & torch.isfinite(c2n)
+        st = st | torch.where(finite, 0, NONFINITE)
+        keep = good & finite
+        pn = torch.where(keep[:, None], pn, pp)
+        Cn = torch.where(keep[:, None, None], Cn, CC)
+        qn = torch.where(keep, qn, qq)
+        c2n = torch.where(keep, c2n, torch.zeros_like(c2n))
+        p = p.index_put((idx,), pn)
+        C = C.index_put((idx,), Cn)
+        q = q.index_put((idx,), qn)
+        chi2 = chi2.index_put((idx,), chi2[idx] + c2n)
+        nval = nval.index_put((idx,), nval[idx] + (valid & keep).to(torch.int64))
+        status = status.index_put((idx,), status[idx] | st)
+        alive = alive.index_put((idx,), keep)
+        prev_e = prev_e.index_put((idx,), ei)
+    p, C, q = reverse_direction(p, C, q)
+    # tracks not refitted keep their input
+    p = torch.where(run[:, None], p, _t(fwd_p))
+    C = torch.where(run[:, None, None], C, _t(fwd_C))
+    q = torch.where(run, q, _t(fwd_q))
+    status = torch.where(run, status, torch.full_like(status, NOT_REFITTED))
+    return dict(p=p, C=C, q=q, chi2=chi2, ndf=2 * nval - 5, status=status)
+
+
+# --------------------------------------------------------------------------
 # a8: gradient of sum_t w_t chi2_t (reverse-mode autodiff of the oracle)
 # --------------------------------------------------------------------------
 

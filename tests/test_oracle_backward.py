@@ -1,0 +1,204 @@
+"""Pins for the oracle's backward fit (Sec. 2.2, step 4): the direction
+reversal against the helix itself, the reversal of the covariance against the
+Jacobian of the state map, exact recovery of the true state at the first hit
+on noise-free tracks, agreement with the forward least-squares estimate when
+there is no material, and the statistical signature of a correctly weighted
+filter (pulls against the generator's truth at the first hit, chi2/ndf)."""
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from oracle import kf_oracle as O
+from toygen import generate, workloads
+
+DT = torch.float64
+
+
+def _random_states(n, seed=5):
+    g = torch.Generator().manual_seed(seed)
+    u = lambda lo, hi: lo + (hi - lo) * torch.rand(n, generator=g, dtype=DT)
+    p = torch.stack([u(-50, 50), u(-50, 50), u(-100, 100), u(0.1, 2.0), u(-math.pi, math.pi), u(0.2, 2.9)], 1)
+    q = torch.where(torch.rand(n, generator=g) < 0.5, -1.0, 1.0).to(DT)
+    A = torch.randn(n, 6, 6, generator=g, dtype=DT)
+    C = A @ A.transpose(1, 2) + 0.1 * torch.eye(6, dtype=DT)
+    return p, C, q
+
+
+def test_reversal_is_an_involution():
+    p, C, q = _random_states(200)
+    p2, C2, q2 = O.reverse_direction(*O.reverse_direction(p, C, q))
+    d = p2 - p
+    d[:, 4] = O.wrap_phi(d[:, 4])
+    assert d.abs().max() < 1e-13
+    assert torch.equal(C2, C) and torch.equal(q2, q)
+
+
+def test_reversed_state_runs_the_same_helix_backwards():
+    """helix_at is pinned against an RK4 integration of the Lorentz force
+    elsewhere; here the reversed state's helix over +s must be the original
+    helix over -s, point by point, and its direction the reversed one."""
+    p, C, q = _random_states(300)
+    pr, _, qr = O.reverse_direction(p, C, q)
+    for s in (0.5, 7.0, 40.0):
+        fwd = O.helix_at(pr, qr, torch.full((300,), s, dtype=DT), 3.8)
+        back = O.helix_at(p, q, torch.full((300,), -s, dtype=DT), 3.8)
+        assert (fwd[:, :3] - back[:, :3]).abs().max() < 1e-9 * max(1.0, s)
+        back_rev, _, _ = O.reverse_direction(back, C, q)
+        d = fwd[:, 3:] - back_rev[:, 3:]
+        d[:, 1] = O.wrap_phi(d[:, 1])
+        assert d.abs().max() < 1e-12
+
+
+def test_reversed_covariance_is_the_jacobian_transform():
+    p, C, q = _random_states(50)
+    _, C2, _ = O.reverse_direction(p, C, q)
+    for i in range(50):
+        J = torch.autograd.functional.jacobian(lambda x: O.reverse_direction(x[None], C[i:i + 1], q[i:i + 1])[0][0],
+                                               p[i])
+        assert torch.allclose(C2[i], J @ C[i] @ J.T, rtol=0, atol=1e-12)
+
+
+def _backward_from(ev, fwd, cov_scale=O.BACKWARD_COV_SCALE, geom=None):
+    return O.backward_fit(fwd["p"], fwd["C"], fwd["q"], fwd["status"], ev.hit_offsets, ev.hit_layer, ev.hit_valid,
+                          torch.tensor(ev.hit_pos), ev.hit_cov, ev.geometry if geom is None else geom,
+                          cov_scale=cov_scale)
+
+
+def _first_valid(ev):
+    off = ev.hit_offsets
+    return np.array([off[t] + int(np.argmax(ev.hit_valid[off[t]:off[t + 1]])) for t in range(ev.n_tracks)])
+
+
+def test_noise_free_tracks_return_the_truth_at_the_first_hit():
+    """Hits exactly on the generated helices, no scattering: started from the
+    true state at the last entry, every residual is zero, so the backward
+    pass must carry the truth unchanged to the first valid entry (barrels,
+    disks, holes)."""
+    for name in ("barrel10", "mixed26"):
+        wl = workloads()[name]
+        ev = generate(wl, 300, smear=False, scatter=False)
+        last = ev.hit_offsets[1:] - 1
+        C = torch.diag(torch.tensor([1e-4, 1e-4, 1e-4, 1e-4, 1e-6, 1e-6], dtype=DT)).expand(ev.n_tracks, 6, 6)
+        fwd = dict(p=torch.tensor(ev.truth[last]), C=C.clone(), q=torch.tensor(ev.charge, dtype=DT),
+                   status=torch.zeros(ev.n_tracks, dtype=torch.int64))
+        out = _backward_from(ev, fwd)
+        assert (out["status"].numpy() & (O.NO_CROSSING | O.NONFINITE | O.NOT_REFITTED)).sum() == 0
+        tr = torch.tensor(ev.truth[_first_valid(ev)])
+        d = out["p"] - tr
+        d[:, 4] = O.wrap_phi(d[:, 4])
+        assert d[:, :3].abs().max() < 1e-8, name
+        assert (d[:, 3].abs() / tr[:, 3]).max() < 1e-10, name
+        assert d[:, 4:].abs().max() < 1e-10, name
+        assert torch.equal(out["q"], fwd["q"])
+        nvalid = np.add.reduceat(ev.hit_valid.astype(np.int64), ev.hit_offsets[:-1])
+        assert np.array_equal(out["ndf"].numpy(), 2 * nvalid - 5)
+        assert out["chi2"].abs().max() < 1e-12
+
+
+def test_backward_estimate_equals_the_forward_one_without_material():
+    """Smeared hits, no scattering, (almost) no material, diffuse priors: the
+    forward estimate at the last entry and the backward estimate at the first
+    entry carried forward to the last one use the same hits, so they are the
+    same least-squares estimate up to the linearisation of each pass.  A
+    pass linearises along its own running estimate, and the first forward
+    pass starts from a three-hit seed (its estimate moves by up to ~0.4 sigma
+    when restarted elsewhere), so the comparison is made one round later:
+    forward, backward, forward again from the backward result, backward
+    again.  Tracks with a near-tangent crossing (the filter visibly
+    non-linear) are left out, as in the forward pins."""
+    wl = workloads()["barrel10"]
+    g = dataclasses.replace(wl.geometry, x_over_x0=np.full(wl.geometry.n_layers, 1e-10))
+    wl2 = dataclasses.replace(wl, geometry=g)
+    ev = generate(wl2, 200, scatter=False, holes=False)
+    hp = torch.tensor(ev.hit_pos)
+    sp, sC, sq, _ = O.make_seeds(ev.hit_offsets, ev.hit_valid, ev.hit_pos, g.bz)
+    f1 = O.fit_tracks(sp, sC * 1e4, sq, ev.hit_offsets, ev.hit_layer, ev.hit_valid, hp, ev.hit_cov, g)
+    b1 = _backward_from(ev, f1, cov_scale=1e8)
+    fwd = O.fit_tracks(b1["p"], b1["C"] * 1e8, b1["q"], ev.hit_offsets, ev.hit_layer, ev.hit_valid, hp, ev.hit_cov, g)
+    bwd = _backward_from(ev, fwd, cov_scale=1e8)
+    for o in (f1, b1, fwd, bwd):
+        assert (o["status"].numpy() & (O.NO_CROSSING | O.NONFINITE | O.NOT_REFITTED)).sum() == 0
+    # tracks crossing every layer, away from tangent crossings: carry the
+    # backward estimate from the first layer to the last (no material, no hits)
+    L = g.n_layers
+    t = ev.truth
+    cb = np.abs(np.cos(t[:, 4] - np.arctan2(t[:, 1], t[:, 0])))
+    sel = np.nonzero((ev.lengths() == L) & (np.minimum.reduceat(cb, ev.hit_offsets[:-1]) > 0.3))[0]
+    assert sel.size > 100
+    fwd = {k: v[sel] for k, v in fwd.items()}
+    bwd = {k: v[sel] for k, v in bwd.items()}
+    p, C, q = bwd["p"], bwd["C"], bwd["q"]
+    m = sel.size
+    for l in range(1, L):
+        kind = torch.full((m,), int(g.kind[l]), dtype=torch.int64)
+        p, C, _, st = O.propagate(p, C, q, kind, torch.full((m,), g.pos[l], dtype=DT),
+                                  torch.full((m,), 1e-10, dtype=DT), g, apply_material=False)
+        assert (st & O.NO_CROSSING).sum() == 0
+    sig = torch.sqrt(torch.diagonal(fwd["C"], dim1=1, dim2=2))
+    d = p - fwd["p"]
+    d[:, 4] = O.wrap_phi(d[:, 4])
+    # the position lies on the last surface: its tangent and z offsets
+    ph = torch.atan2(fwd["p"][:, 1], fwd["p"][:, 0])
+    tv = torch.stack([-torch.sin(ph), torch.cos(ph)], 1)
+    tang = (d[:, :2] * tv).sum(1) / torch.sqrt(torch.einsum("ni,nij,nj->n", tv, fwd["C"][:, :2, :2], tv))
+    assert tang.abs().max() < 1e-2
+    assert (d[:, 2:].abs() / sig[:, 2:]).max() < 0.1
+    sd = torch.sqrt(torch.diagonal(C, dim1=1, dim2=2))
+    rel = (C - fwd["C"]).abs() / (sd[:, :, None] * sd[:, None, :])
+    assert rel[:, 2:, 2:].max() < 1e-2
+    # the two passes see the same hits: equal chi2 up to the linearisation
+    assert np.abs(bwd["chi2"].numpy() - fwd["chi2"].numpy()).max() < 0.3
+
+
+def test_backward_statistics_at_the_first_hit():
+    """Smeared hits and scattering (barrel10): the backward estimate at the
+    first hit against the generator's state there, before that layer's kick
+    (the backward pass crosses the kick the other way round), gives pulls
+    N(0, 1); sum chi2 / sum ndf ~ 1."""
+    wl = workloads()["barrel10"]
+    n = 2000
+    ev = generate(wl, n, holes=False)
+    fwd = O.fit_event(ev)
+    out = _backward_from(ev, fwd)
+    first = ev.hit_offsets[:-1]
+    ok = (out["status"].numpy() & (O.NO_CROSSING | O.NONFINITE | O.NOT_REFITTED)) == 0
+    # away from near-tangent crossings (as the forward statistical pins)
+    t = ev.truth
+    cb = np.abs(np.cos(t[:, 4] - np.arctan2(t[:, 1], t[:, 0])))
+    sel = ok & (np.minimum.reduceat(cb, ev.hit_offsets[:-1]) > 0.3)
+    assert sel.sum() > 0.6 * n
+    ratio = out["chi2"].numpy()[sel].sum() / out["ndf"].numpy()[sel].sum()
+    assert abs(ratio - 1.0) < 4.0 * math.sqrt(2.0 / out["ndf"].numpy()[sel].sum()), ratio
+    tr = torch.tensor(ev.truth[first])
+    p, C = out["p"], out["C"]
+    d = p - tr
+    d[:, 4] = O.wrap_phi(d[:, 4])
+    sig = torch.sqrt(torch.diagonal(C, dim1=1, dim2=2))
+    ph = torch.atan2(tr[:, 1], tr[:, 0])
+    tv = torch.stack([-torch.sin(ph), torch.cos(ph)], 1)
+    pulls = {"t": (d[:, :2] * tv).sum(1) / torch.sqrt(torch.einsum("ni,nij,nj->n", tv, C[:, :2, :2], tv)),
+             "z": d[:, 2] / sig[:, 2], "ipt": d[:, 3] / sig[:, 3], "phi": d[:, 4] / sig[:, 4],
+             "theta": d[:, 5] / sig[:, 5]}
+    for k, v in pulls.items():
+        vv = v.numpy()[sel]
+        mu, sd = vv.mean(), vv.std()
+        assert abs(mu) < 5.0 / math.sqrt(vv.size), (k, mu)
+        assert abs(sd - 1.0) < 0.06, (k, sd)
+
+
+def test_stopped_or_empty_tracks_keep_their_input():
+    wl = workloads()["barrel10"]
+    ev = generate(wl, 40)
+    fwd = O.fit_event(ev)
+    st = fwd["status"].clone()
+    st[[3, 17]] |= O.NO_CROSSING
+    st[[5]] |= O.NONFINITE
+    fwd2 = dict(fwd, status=st)
+    out = _backward_from(ev, fwd2)
+    for t in (3, 5, 17):
+        assert out["status"][t] == O.NOT_REFITTED
+        assert torch.equal(out["p"][t], fwd["p"][t]) and torch.equal(out["C"][t], fwd["C"][t])
+    others = [t for t in range(40) if t not in (3, 5, 17)]
+    assert ((out["status"][others] & O.NOT_REFITTED) == 0).all()
