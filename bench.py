@@ -239,6 +239,42 @@ def bench_adjoint(ctx, K, generate, workloads, args, seg=1):
             "checkpoint_bytes": ck.numel() * 4, "grad_align_finite": bool(torch.isfinite(ga).all().item())}
 
 
+def bench_backward(ctx, K, ev, args, steps=None):
+    """Backward fit of barrel20 (100,000 FP32 tracks x 20 layers): the
+    forward result of the fused seed-and-fit call, then kf_backward_fit from
+    it (covariance scaled by 100, hits staged through LDS per wave).  Timed
+    alone and as a forward + backward step; the same algorithmic FLOP count
+    per entry as the forward pass (the same entries are stepped through)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    dt = torch.float32
+    n = ev.n_tracks
+    t = K.event_tensors(ev, dt, dev)
+    geom = K.Geometry.from_toy(ev.geometry)
+    hits = (t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"])
+    fwd = K.fit_outputs(n, dt, dev)
+    out = K.fit_outputs(n, dt, dev)
+    ctx.seed_fit_tracks(*hits, geom, 0, out=fwd)
+
+    def bwd():
+        ctx.backward_fit(fwd, *hits, geom, cov_scale=K.BACKWARD_COV_SCALE, max_len=26, out=out)
+
+    def step():
+        ctx.seed_fit_tracks(*hits, geom, 0, out=fwd)
+        bwd()
+
+    k = args.steps if steps is None else steps
+    ms_b = time_loop(bwd, k, args.warmup)
+    ms_s = time_loop(step, k, args.warmup)
+    flops = algorithmic_flops(ev)
+    tf = flops / (ms_b * 1e-3) / 1e12
+    st = out["status"].cpu().numpy()
+    return {"tracks": n, "layers": ev.geometry.n_layers, "cov_scale": K.BACKWARD_COV_SCALE, "ms_backward": ms_b,
+            "tracks_per_s_backward": n / (ms_b * 1e-3), "ms_forward_backward_step": ms_s,
+            "achieved_tflops_backward": tf, "frac_fp32_peak_backward": tf / FP32_PEAK_TFLOPS,
+            "kernel": "backward_kernel<float, 2>", "refitted": int(((st & 64) == 0).sum())}
+
+
 def bench_search(ctx, K, args, sample=300):
     """Combinatorial candidate search: 20,000 seeds (Kalman fit of each
     track's first three hits) over 17 barrel layers whose pools hold the true
@@ -289,6 +325,15 @@ def profile_only(args, K, tune_fit, generate, workloads):
     launch shape comes from the autotune cache when present)."""
     import torch
     dev = torch.device("cuda", 0)
+    if args.profile_only == "backward":
+        ctx = K.Context(0)
+        ctx.set_fit_launch(torch.float32, *[int(v) for v in (args.launch or "256,0,1,2,3").split(",")])
+        ev = generate(workloads()["barrel20"])
+        a = argparse.Namespace(**vars(args))
+        a.warmup = 1
+        r = bench_backward(ctx, K, ev, a)
+        log("profile-only", args.profile_only, json.dumps(r))
+        return
     if args.profile_only in ("adjoint", "search"):
         ctx = K.Context(0)
         if args.launch:
@@ -348,11 +393,12 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the 500k-track barrel+endcap workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint workload")
     ap.add_argument("--no-search", action="store_true", help="skip the combinatorial search workload")
+    ap.add_argument("--no-backward", action="store_true", help="skip the backward-fit workload")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "kf_autotune.json"))
     ap.add_argument("--launch", default=None,
                     help="profile-only: fit launch shape block,persistent,blocks_per_cu,waves,layout")
-    ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32", "adjoint", "search"],
+    ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32", "adjoint", "search", "backward"],
                     help="only launch the named fit --steps times (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -466,6 +512,9 @@ def main():
             "tracks_compared": int(ok.sum()), "ill_conditioned": int(bad.sum()),
             "tolerance": {"param": 1e-4, "chi2": 1e-3,
                           "tail": "at most 0.1% of the tracks may exceed it, by < 10x (param) / 20x (chi2)"}}
+    if not args.no_backward:
+        # the forward pass in the launch shape tuned for this batch
+        line["backward_barrel20"] = bench_backward(ctx, K, ev, args)
     if not args.no_uneven:
         line["uneven_mixed26"] = bench_uneven(ctx, K, tune_fit, generate, workloads, args)
     if not args.no_adjoint:

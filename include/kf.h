@@ -64,7 +64,7 @@ enum {
   KF_TRK_NONFINITE = 4u,     /* a step produced a non-finite value; track frozen before it */
   KF_TRK_FP64_FALLBACK = 8u, /* a 3x3 inverse was recomputed in FP64 (FP32 path only) */
   KF_TRK_CHARGE_FLIP = 16u,  /* an update turned 1/pT negative; charge flipped */
-  KF_TRK_COV_NOT_PSD = 32u,  /* a variance became negative after an update */
+  KF_TRK_COV_NOT_PSD = 32u,  /* a variance became negative after an update (FP32: beyond the rounding of the prior) */
   KF_TRK_BAD_INPUT = 64u     /* layer id out of range or fewer than 3 valid hits for seeding */
 };
 
@@ -205,6 +205,41 @@ int kf_seed_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld, in
                        void *chi2, int32_t *ndf,
                        void *checkpoints, int32_t seg, int32_t max_len,
                        uint32_t *trk_status, void *stream);
+
+/* Backward fit (the paper's Sec. 2.2, step 4: each found track is traversed
+ * again backwards and its parameters refitted).  Input: the result of
+ * kf_fit_tracks / kf_seed_fit_tracks on the same hits (state_in[6][ld],
+ * cov_in[21][ld], charge_in[n]: the state on each track's last entry) and its
+ * fwd_status[n] (may be NULL: every track is taken as complete).  The
+ * covariance is multiplied by cov_scale (>= 1; 100 is the value the tests and
+ * the benchmark use), the surface of the last entry's layer imposed on it
+ * again (its normal made a null vector, as after every propagation), the
+ * direction of motion reversed (phi + pi, pi - theta, -q; the theta terms of
+ * the covariance change sign), and the entries are
+ * taken in reverse order, from the last one down to the first valid one, with
+ * kf_fit_tracks's rules per entry (the first adds its layer's material at the
+ * current state; every later one is propagated to, gets its layer's material
+ * and, if valid, an update; a failed crossing or a non-finite step freezes
+ * the track).  The result, on the track's first valid entry, is turned back
+ * to the outward direction.
+ * Outputs: state_out[6][ld], cov_out[21][ld], charge_out[n] (must not alias
+ * the inputs), chi2[n] (sum over the backward pass), ndf[n] (= 2 * used
+ * hits - 5), trk_status[n] (overwritten with the backward pass's bits).
+ * Tracks the forward fit stopped (KF_TRK_NO_CROSSING, KF_TRK_NONFINITE or
+ * KF_TRK_BAD_INPUT in fwd_status) or with no valid entry are not refitted:
+ * the input is copied out, chi2 = 0, ndf = -5, trk_status = KF_TRK_BAD_INPUT.
+ * max_len (1..64) as in kf_fit_tracks.  Hit arrays, layout and precision as
+ * in kf_fit_tracks; no alignment correction.  The hits of each wave's 64
+ * tracks are staged through LDS.  KF_ERR_ARG for cov_scale < 1 or not finite,
+ * aliased outputs, or the argument errors of kf_fit_tracks. */
+int kf_backward_fit(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                    const void *state_in, const void *cov_in, const int8_t *charge_in,
+                    const uint32_t *fwd_status,
+                    const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
+                    int64_t n_hits, const void *hit_pos, const void *hit_cov,
+                    const kf_geometry *geom, double cov_scale, int32_t max_len,
+                    void *state_out, void *cov_out, int8_t *charge_out,
+                    void *chi2, int32_t *ndf, uint32_t *trk_status, void *stream);
 
 /* Parameters of the combinatorial candidate search (kf_score_hits).  The
  * paper makes the window, the chi2 cut, the missed-layer limit and the

@@ -671,15 +671,37 @@ def reverse_direction(p, C, q):
     return p2, J @ C @ J, -q
 
 
+def impose_surface(p, C, kind, pos):
+    """The covariance of a state on a surface has the surface normal as a null
+    vector (a state confined to the surface cannot move along it): C <- P C P
+    with P = I - n n^T on the position block, n = (x, y, 0) / R for a barrel
+    of radius R = pos, n = (0, 0, 1) for a disk.  Exact arithmetic leaves such
+    a covariance unchanged; it removes the rounding residue along n that a
+    stored covariance carries."""
+    p, C = _t(p), _t(C)
+    n = p.shape[0]
+    isb = torch.as_tensor(kind) == BARREL
+    R = _t(pos)
+    nx = torch.where(isb, p[:, 0] / R, torch.zeros_like(R))
+    ny = torch.where(isb, p[:, 1] / R, torch.zeros_like(R))
+    nz = torch.where(isb, torch.zeros_like(R), torch.ones_like(R))
+    nv = torch.zeros(n, 6, dtype=DT)
+    nv[:, 0], nv[:, 1], nv[:, 2] = nx, ny, nz
+    P = torch.eye(6, dtype=DT).expand(n, 6, 6) - nv[:, :, None] * nv[:, None, :]
+    return P @ C @ P
+
+
 def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
-                 cov_scale=BACKWARD_COV_SCALE):
+                 cov_scale=BACKWARD_COV_SCALE, state_round=None, state_jitter=None):
     """Backward fit (Sec. 2.2, step 4): every track is traversed again, from
     its last entry back to its first valid entry, and refitted.
 
     Input: the forward fit's result (fwd_p [n,6], fwd_C [n,6,6], fwd_q [n],
     fwd_status [n]), which sits on the track's last entry.  Its covariance is
-    multiplied by cov_scale and the direction of motion reversed
-    (reverse_direction); the entries are then taken in reverse order with the
+    multiplied by cov_scale, the surface of the last entry's layer imposed on
+    it (impose_surface: scaled up, the rounding residue along the normal of a
+    stored covariance would no longer be negligible) and the direction of
+    motion reversed (reverse_direction); the entries are then taken in reverse order with the
     forward pass's rules: the first (the last entry) adds its layer's material
     at the current state, every later one is propagated to (the re-crossing
     window when the entry before it in this order was on the same layer),
@@ -687,7 +709,9 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     non-finite result freezes the track.  The result, on the first valid
     entry, is turned back to the outward direction.  Tracks the forward pass
     stopped (NO_CROSSING or NONFINITE in fwd_status) or with no valid entry
-    keep their input, with status NOT_REFITTED.  Returns dict(p, C, q, chi2,
+    keep their input, with status NOT_REFITTED.  state_round, state_jitter:
+    the conditioning probes of fit_tracks, applied after every propagation
+    and update.  Returns dict(p, C, q, chi2,
     ndf, status): chi2 and ndf (= 2 * used hits - 5) of the backward pass."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
@@ -714,7 +738,9 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     last = off[1:] - 1
     run = (k0 >= 0) & ((fwd_status & (NO_CROSSING | NONFINITE | NOT_REFITTED)) == 0)
 
-    p, C, q = reverse_direction(_t(fwd_p), _t(fwd_C) * cov_scale, _t(fwd_q))
+    lay_last = lay_all[torch.clamp(last, min=0)] if n > 0 else lay_all[:0]
+    C0 = impose_surface(fwd_p, _t(fwd_C) * cov_scale, kind_l[lay_last], pos_l[lay_last])
+    p, C, q = reverse_direction(_t(fwd_p), C0, _t(fwd_q))
     chi2 = torch.zeros(n, dtype=DT)
     nval = torch.zeros(n, dtype=torch.int64)
     status = torch.zeros(n, dtype=torch.int64)
@@ -737,6 +763,11 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
             Q, grazing = process_noise(pp, kind, x0_l[lay], geom.mass)
             pp2, CC2 = pp, CC + Q
             st = torch.where(grazing, GRAZING, 0).to(torch.int64)
+        if state_round is not None:
+            pp2 = pp2.to(state_round).to(DT)
+            CC2 = CC2.to(state_round).to(DT)
+        if state_jitter is not None:
+            pp2, CC2 = _jitter(pp2, CC2, idx + j, state_jitter)
         good = (st & NO_CROSSING) == 0
         valid = (val_all[ei] == 1) & good
         pu, Cu, qu, c2, st_u = update(pp2, CC2, qq, m_all[ei], V_all[ei])
@@ -752,6 +783,11 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
         Cn = torch.where(keep[:, None, None], Cn, CC)
         qn = torch.where(keep, qn, qq)
         c2n = torch.where(keep, c2n, torch.zeros_like(c2n))
+        if state_round is not None:
+            pn = pn.to(state_round).to(DT)
+            Cn = Cn.to(state_round).to(DT)
+        if state_jitter is not None:
+            pn, Cn = _jitter(pn, Cn, idx + j + 1, state_jitter)
         p = p.index_put((idx,), pn)
         C = C.index_put((idx,), Cn)
         q = q.index_put((idx,), qn)

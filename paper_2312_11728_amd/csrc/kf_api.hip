@@ -538,6 +538,62 @@ int kf_seed_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, in
                          state_out, cov_out, charge_out, chi2, ndf, checkpoints, seg, max_len, trk_status, stream);
 }
 
+int kf_backward_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* state_in,
+                    const void* cov_in, const int8_t* charge_in, const uint32_t* fwd_status,
+                    const int32_t* hit_offsets, const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits,
+                    const void* hit_pos, const void* hit_cov, const kf_geometry* geom, double cov_scale,
+                    int32_t max_len, void* state_out, void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf,
+                    uint32_t* trk_status, void* stream) {
+  KF_TRY(check_prec(prec));
+  KF_TRY(check_sizes(n, ld));
+  kf::GeomArgs g;
+  KF_TRY(check_geometry(geom, &g));
+  if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
+  if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);
+  if (!std::isfinite(cov_scale) || !(cov_scale >= 1.0)) return fail(KF_ERR_ARG, "cov_scale must be finite and >= 1");
+  if (n == 0) return ok();
+  KF_REQUIRE(state_in);
+  KF_REQUIRE(cov_in);
+  KF_REQUIRE(charge_in);
+  KF_REQUIRE(hit_offsets);
+  KF_REQUIRE(hit_layer);
+  KF_REQUIRE(hit_valid);
+  KF_REQUIRE(hit_pos);
+  KF_REQUIRE(hit_cov);
+  KF_REQUIRE(state_out);
+  KF_REQUIRE(cov_out);
+  KF_REQUIRE(charge_out);
+  KF_REQUIRE(chi2);
+  KF_REQUIRE(ndf);
+  KF_REQUIRE(trk_status);
+  KF_REQUIRE(ctx);
+  if (state_out == state_in || cov_out == cov_in || (const void*)charge_out == (const void*)charge_in)
+    return fail(KF_ERR_ARG, "the outputs must not alias the inputs");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == KF_F32) {
+    kf::BwdArgs<float> b;
+    b.f = make_fit_args<float>(n, ld, state_in, cov_in, charge_in, hit_offsets, hit_layer, hit_valid, n_hits, hit_pos,
+                               hit_cov, nullptr, state_out, cov_out, charge_out, chi2, ndf, nullptr, 1, 0, trk_status,
+                               ctx->d_counter);
+    b.f.max_len = max_len;
+    b.fwd_status = fwd_status;
+    b.cov_scale = float(cov_scale);
+    e = kf::launch_backward(b, g, s);
+  } else {
+    kf::BwdArgs<double> b;
+    b.f = make_fit_args<double>(n, ld, state_in, cov_in, charge_in, hit_offsets, hit_layer, hit_valid, n_hits,
+                                hit_pos, hit_cov, nullptr, state_out, cov_out, charge_out, chi2, ndf, nullptr, 1, 0,
+                                trk_status, ctx->d_counter);
+    b.f.max_len = max_len;
+    b.fwd_status = fwd_status;
+    b.cov_scale = cov_scale;
+    e = kf::launch_backward(b, g, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "kf_backward_fit");
+  return ok();
+}
+
 int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {
   if (max_tracks < 0) return fail(KF_ERR_ARG, "max_tracks = %lld < 0", (long long)max_tracks);
   if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);

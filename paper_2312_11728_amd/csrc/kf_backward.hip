@@ -1,0 +1,149 @@
+// HIP kernel of the backward fit: every track is traversed again from its last
+// entry down to its first valid entry and refitted, starting from the forward
+// fit's result with its covariance scaled up and the direction of motion
+// reversed, so that the forward step (propagation, material, update) runs
+// unchanged on the reversed entry list.  One track per lane; the entries of a
+// wave's 64 tracks are staged through LDS a few at a time, as in the forward
+// fit.
+#include "kf_kernels.hpp"
+#include "kf_stage.hpp"
+#include "kf_track.hpp"
+
+namespace kf {
+
+namespace {
+
+constexpr int kBwdBlock = 256;
+
+// Backward fit of tracks [w0, w0 + 64) (one wave; every lane must call it).
+// Entry k of a track's backward pass is CSR entry last - k; the pass has
+// n_entries - k0 entries (k0: the first valid entry in crossing order).
+template <typename T, int J>
+__device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g, int64_t w0, StageBuf<T, J>& sb,
+                                     T* bk, int bk_stride) {
+  const FitArgs<T>& a = b.f;
+  const int lane = int(threadIdx.x) & 63;
+  const int64_t t = w0 + lane;
+  const bool in_range = t < a.n;
+  int64_t last = 0;
+  int len = 0;
+  T p[6], c[21];
+  int q = 0;
+  uint32_t st = 0;
+  bool run = false;
+  if (in_range) {
+    const int64_t e0 = a.hit_offsets[t];
+    int n_e = int(a.hit_offsets[t + 1] - e0);
+    if (n_e > a.max_len) n_e = a.max_len;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * a.ld + t];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * a.ld + t];
+    q = a.seed_charge[t];
+    int k0 = 0;
+    while (k0 < n_e && a.hit_valid[e0 + k0] == 0) ++k0;
+    const uint32_t stop = TRK_NO_CROSSING | TRK_NONFINITE | TRK_BAD_INPUT;
+    run = k0 < n_e && !(b.fwd_status && (b.fwd_status[t] & stop));
+    if (run) {
+      last = e0 + n_e - 1;
+      len = n_e - k0;
+#pragma unroll
+      for (int i = 0; i < 21; ++i) c[i] *= b.cov_scale;
+      // the surface of the last entry's layer, imposed again: scaled up, the
+      // rounding residue of the stored covariance along its normal would no
+      // longer be negligible (a bad layer id is caught by the first step)
+      const int ll = a.hit_layer[last];
+      if (ll >= 0 && ll < g.n_layers) impose_surface(c, p, g.kind[ll], g.pos[ll]);
+      reverse_direction(p, c, q);
+    } else {
+      st = TRK_BAD_INPUT;   // not refitted: the input is returned
+    }
+  }
+  sb.e0[lane] = last;
+  sb.len[lane] = len;
+  const int kmax = wave_max(len);
+  T chi2 = T(0);
+  int nval = 0, prev = 0;
+  bool live = run;
+  const int64_t nh = a.n_hits;
+  wave_sync();
+  for (int j0 = 0; j0 < kmax; j0 += J) {
+    // all J rows are loaded before any is written to LDS (one memory round
+    // trip per chunk); a slot past the end of its pass loads the pass's last
+    // entry (the track's first valid one) and is never read; kmax > 0 means
+    // some track has an entry, so entry 0 exists for the slots of no track
+    int32_t lvr[J];
+    T vr[J][9];
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+      const int idx = r * 64 + lane;
+      const int l = idx / J, jj = idx % J;
+      const int ln = sb.len[l];
+      const int64_t e = ln > 0 ? sb.e0[l] - min(j0 + jj, ln - 1) : 0;
+      lvr[r] = int32_t(uint16_t(a.hit_layer[e])) | (a.hit_valid[e] ? (1 << 16) : 0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) vr[r][k] = a.hit_pos[k * nh + e];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) vr[r][3 + k] = a.hit_cov[k * nh + e];
+    }
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+      const int idx = r * 64 + lane;
+      const int l = idx / J, jj = idx % J;
+      sb.lv[jj][l] = lvr[r];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sb.v[k][jj][l] = vr[r][k];
+    }
+    wave_sync();
+    const int jn = min(J, kmax - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      const int k = j0 + jj;
+      if (!live || k >= len) continue;
+      const int32_t lv = sb.lv[jj][lane];
+      const bool valid = (lv >> 16) != 0;
+      const int lay = int16_t(lv & 0xffff);
+      if (k == 0) prev = lay;
+      T m[3], V[6];
+#pragma unroll
+      for (int x = 0; x < 3; ++x) m[x] = sb.v[x][jj][lane];
+#pragma unroll
+      for (int x = 0; x < 6; ++x) V[x] = sb.v[3 + x][jj][lane];
+      live = fit_entry(a, g, static_cast<const T*>(nullptr), t, k, lay, prev, valid, m, V, p, c, q, st, chi2, nval,
+                       bk, bk_stride);
+    }
+    wave_sync();   // every lane has read the chunk before the next one is staged
+  }
+  if (in_range) {
+    if (run) reverse_direction(p, c, q);
+    store_fit(a, t, p, c, q, chi2, nval, st);
+  }
+}
+
+// WAVES: waves per SIMD the register allocation must allow (2 in FP32, 1 in
+// FP64, the forward fit's tuned choices).
+template <typename T, int WAVES>
+__global__ void __launch_bounds__(kBwdBlock, WAVES) backward_kernel(BwdArgs<T> b, GeomArgs g) {
+  constexpr int J = stage_entries<T, WAVES>();
+  __shared__ GeomLds<T> sg;
+  __shared__ T bk[28 * kBwdBlock];
+  __shared__ StageBuf<T, J> sb[kBwdBlock / 64];
+  stage_geometry(sg, g);
+  const int64_t w0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
+  backward_wave_staged<T, J>(b, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, w0,
+                             sb[threadIdx.x >> 6], bk + threadIdx.x, int(blockDim.x));
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_backward(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s) {
+  if (a.f.n == 0) return hipSuccess;
+  const int64_t grid = (a.f.n + kBwdBlock - 1) / kBwdBlock;
+  hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1>), dim3(unsigned(grid)), dim3(kBwdBlock), 0, s, a, g);
+  return hipGetLastError();
+}
+
+template hipError_t launch_backward<float>(const BwdArgs<float>&, const GeomArgs&, hipStream_t);
+template hipError_t launch_backward<double>(const BwdArgs<double>&, const GeomArgs&, hipStream_t);
+
+}  // namespace kf

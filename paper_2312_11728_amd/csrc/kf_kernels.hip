@@ -155,34 +155,6 @@ __global__ void __launch_bounds__(kFitBlock, WAVES) fit_persistent_kernel(FitArg
 // length); lanes whose track has ended or stopped sit out the steps but still
 // take part in the staging.  No pass over the hits before the fit.
 
-// entries per track and chunk: the LDS of a 256-thread block (4 waves) plus
-// the state backup must allow the WAVES blocks per CU the register budget
-// allows
-template <typename T, int WAVES>
-constexpr int stage_entries() {
-  return sizeof(T) == 4 ? (WAVES == 1 ? 8 : 4) : (WAVES == 1 ? 4 : 1);
-}
-
-template <typename T, int J>
-struct StageBuf {
-  T v[9][J][64];        // hit x, y, z, then the 6 covariance terms
-  int32_t lv[J][64];    // layer (low 16 bits) | valid << 16
-  int64_t e0[64];       // first entry of each lane's track
-  int32_t len[64];      // entries of each lane's track (0: no track)
-};
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
-}
-
 // Forward fit of the tracks in slots [w0, w0 + 64) (one wave; slot i holds
 // track order[i] when sorted, else track i; slots >= n hold no track).  Every
 // lane of the wave must call it.

@@ -166,4 +166,16 @@ inline int64_t adjoint_partial_blocks(int64_t n_hits) { return (n_hits + kAlignP
 template <typename T>
 hipError_t launch_adjoint(const AdjArgs<T>& a, const GeomArgs& g, hipStream_t s);
 
+// Backward fit: f.seed_state / seed_cov / seed_charge hold the forward fit's
+// result (the state on each track's last entry), f.state_out ... the result
+// on its first valid entry.  f.ckpt and f.align are unused (null).
+template <typename T>
+struct BwdArgs {
+  FitArgs<T> f;
+  const uint32_t* fwd_status;  // [n] status of the forward fit, or null
+  T cov_scale;                 // the forward covariance is multiplied by this first
+};
+template <typename T>
+hipError_t launch_backward(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s);
+
 }  // namespace kf

@@ -34,6 +34,15 @@ constexpr double kKappaMax = 1e6;  // condition estimate that triggers the FP64 
 // (the posterior variance is a difference of nearly equal numbers) and the
 // lane's update is done in FP64 instead
 constexpr double kRatioMax = 1e4;
+// A position variance counts as negative (TRK_COV_NOT_PSD) below -1e-3 of the
+// position trace.  An FP32 covariance also carries rounding of the order of
+// its own scale before the update; a prior far larger than the posterior (the
+// first steps after a restart from a scaled-up covariance) leaves residues of
+// that order along the surface normal, whose true variance is zero.  In FP32
+// the threshold is therefore widened by kPsdUlps units of 2^-23 of the prior's
+// position trace; in FP64 that term is negligible and left out.
+constexpr double kPsdUlps = 16.0;
+constexpr double kEpsF32 = 1.1920928955078125e-7;   // 2^-23
 
 enum : uint32_t {
   TRK_NO_CROSSING = 1u,
@@ -89,6 +98,46 @@ template <typename T>
 KF_HD inline T wrap_phi(T phi) {
   // to (-pi, pi]
   return phi - T(kTwoPi) * k_ceil((phi - T(kPi)) * T(1.0 / kTwoPi));
+}
+
+// The same track moving the opposite way along its helix: direction
+// (phi, theta) -> (phi + pi, pi - theta) and charge -q, position and ipt
+// unchanged (omega = -q c_B B_z ipt and cot(theta) change sign, so the helix
+// is traced backwards).  The map's Jacobian is diag(1, 1, 1, 1, 1, -1): the
+// covariance terms of theta with the other five change sign.
+template <typename T>
+KF_HD inline void reverse_direction(T p[6], T c[21], int& q) {
+  p[4] = wrap_phi(p[4] + T(kPi));
+  p[5] = T(kPi) - p[5];
+  q = -q;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) c[sym(5, j)] = -c[sym(5, j)];
+}
+
+// The covariance of a state on a surface has the surface normal as a null
+// vector: C <- (I - n n^T) C (I - n n^T) on the position block, n = (x, y) / R
+// for a barrel of radius R, the z row and column cleared for a disk (the same
+// projection propagate() applies after a crossing).  A covariance that already
+// has the null vector is unchanged up to rounding; a stored and scaled-up one
+// loses its rounding residue along n.
+template <typename T>
+KF_HD inline void impose_surface(T c[21], const T p[6], int kind, T pos) {
+  if (kind == 1) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) c[sym(2, j)] = T(0);
+    return;
+  }
+  const T rinv = k_rcp(pos);
+  const T nx = p[0] * rinv, ny = p[1] * rinv;
+  T cn[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) cn[i] = c[sym(i, 0)] * nx + c[sym(i, 1)] * ny;
+  const T nn = cn[0] * nx + cn[1] * ny;
+  const T nv[6] = {nx, ny, T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) c[sym(i, j)] += -cn[i] * nv[j] - nv[i] * cn[j] + nn * nv[i] * nv[j];
 }
 
 // sin(h)/h
@@ -590,6 +639,7 @@ KF_HD inline void inverse_checked<float>(const float S[6], float Si[6], uint32_t
 // Kalman update with hit m (3) and covariance V (packed 3x3), in type T.
 template <typename T>
 KF_HD void update_core(T p[6], T c[21], int& q, const T m[3], const T V[6], T& chi2, uint32_t& st) {
+  const T tr_prior = c[0] + c[2] + c[5];
   T S[6];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -683,8 +733,9 @@ KF_HD void update_core(T p[6], T c[21], int& q, const T m[3], const T V[6], T& c
   }
   p[4] = wrap_phi(p[4]);
   const T tr = c[0] + c[2] + c[5];
-  if (!(c[sym(3, 3)] > T(0)) || !(c[sym(4, 4)] > T(0)) || !(c[sym(5, 5)] > T(0)) || c[0] < T(-1e-3) * tr ||
-      c[2] < T(-1e-3) * tr || c[5] < T(-1e-3) * tr)
+  const T tol = T(1e-3) * tr + T(kPsdUlps * (sizeof(T) == 4 ? kEpsF32 : 0.0)) * tr_prior;
+  if (!(c[sym(3, 3)] > T(0)) || !(c[sym(4, 4)] > T(0)) || !(c[sym(5, 5)] > T(0)) || c[0] < -tol ||
+      c[2] < -tol || c[5] < -tol)
     st |= TRK_COV_NOT_PSD;
 }
 
@@ -694,6 +745,7 @@ KF_HD void update_core(T p[6], T c[21], int& q, const T m[3], const T V[6], T& c
 // S and the packed C are kept.
 KF_HD inline void update_lane_fp64(float p[6], float c[21], int& q, const float m[3], const float V[6], float& chi2,
                                    uint32_t& st) {
+  const float tr_prior = c[0] + c[2] + c[5];
   double S[6], Si[6];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -744,8 +796,9 @@ KF_HD inline void update_lane_fp64(float p[6], float c[21], int& q, const float 
   }
   p[4] = wrap_phi(p[4]);
   const float tr = c[0] + c[2] + c[5];
-  if (!(c[sym(3, 3)] > 0.f) || !(c[sym(4, 4)] > 0.f) || !(c[sym(5, 5)] > 0.f) || c[0] < -1e-3f * tr ||
-      c[2] < -1e-3f * tr || c[5] < -1e-3f * tr)
+  const float tol = 1e-3f * tr + float(kPsdUlps * kEpsF32) * tr_prior;
+  if (!(c[sym(3, 3)] > 0.f) || !(c[sym(4, 4)] > 0.f) || !(c[sym(5, 5)] > 0.f) || c[0] < -tol || c[2] < -tol ||
+      c[5] < -tol)
     st |= TRK_COV_NOT_PSD;
   st |= TRK_FP64_FALLBACK;
 }

@@ -27,7 +27,9 @@ MAX_LAYERS = 64
 EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_propagate", "kf_update",
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
            "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph",
-           "kf_set_kernel_timing", "kf_fit_kernel_time", "kf_seed_fit_tracks"]
+           "kf_set_kernel_timing", "kf_fit_kernel_time", "kf_seed_fit_tracks", "kf_backward_fit"]
+
+BACKWARD_COV_SCALE = 100.0   # forward covariance scale at the start of the backward fit
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -92,6 +94,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_seed_fit_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _i32, _vp, _vp, _vp, _i64, _vp, _vp,
                                        ctypes.POINTER(KfGeometry), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _i32, _i32, _vp, _vp]
+    lib.kf_backward_fit.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
+                                    ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_score_hits.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(KfGeometry),
                                   ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_adjoint.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
@@ -315,6 +319,39 @@ class Context:
                                    _ptr(out["status"]), _stream(dev)))
         return out
 
+
+    def backward_fit(self, fwd, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry,
+                     cov_scale=BACKWARD_COV_SCALE, max_len=26, out=None, use_status=True):
+        """Backward fit (kf_backward_fit) from a forward fit's outputs `fwd`
+        (state [6, n], cov [21, n], charge [n], status [n] as fit_tracks
+        returns them; status is passed unless use_status is False).  Returns
+        the outputs of fit_tracks' form, on each track's first valid entry."""
+        dev = self.device
+        st_in, cov_in, q_in = fwd["state"], fwd["cov"], fwd["charge"]
+        dt = st_in.dtype
+        n = st_in.shape[1]
+        _need(st_in, "state", dt, dev, rows=6)
+        _need(cov_in, "cov", dt, dev, rows=21)
+        _need(q_in, "charge", torch.int8, dev)
+        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need(hit_layer, "hit_layer", torch.int16, dev)
+        _need(hit_valid, "hit_valid", torch.uint8, dev)
+        _need(hit_pos, "hit_pos", dt, dev, rows=3)
+        _need(hit_cov, "hit_cov", dt, dev, rows=6)
+        status = fwd["status"] if use_status else None
+        if status is not None:
+            _need(status, "status", torch.int32, dev)
+        if st_in.stride(0) != cov_in.stride(0):
+            raise ValueError("state and cov must share their leading dimension")
+        if out is None:
+            out = fit_outputs(n, dt, dev)
+        _check(lib().kf_backward_fit(self.handle, _prec(dt), n, st_in.stride(0), _ptr(st_in), _ptr(cov_in), _ptr(q_in),
+                                     _ptr(status), _ptr(hit_offsets), _ptr(hit_layer), _ptr(hit_valid),
+                                     hit_pos.shape[1], _ptr(hit_pos), _ptr(hit_cov), ctypes.byref(geom.struct),
+                                     float(cov_scale), int(max_len), _ptr(out["state"]), _ptr(out["cov"]),
+                                     _ptr(out["charge"]), _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(out["status"]),
+                                     _stream(dev)))
+        return out
 
     def seed_fit_tracks(self, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry, seed_mode,
                         align=None, seeds=None, checkpoints=None, seg=1, max_len=26, out=None):

@@ -186,3 +186,39 @@ def test_score_hits_rejects_disk_layers_in_the_plan():
     g = kf.Geometry([0, 1, 0], [4.0, 30.0, 6.0], [-150.0, 2.0, -150.0], [150.0, 100.0, 150.0], [0.02] * 3)
     assert _search_call(geom=ctypes.byref(g.struct)) == kf.KF_ERR_ARG
     assert "not a barrel layer" in kf.lib().kf_last_error().decode()
+
+
+def _backward_call(**over):
+    Q = ctypes.c_void_p(0x2000)   # a second fake address (outputs distinct from inputs)
+    args = dict(ctx=P, prec=kf.KF_F32, n=10, ld=10, state_in=P, cov_in=P, charge_in=P, fwd_status=P, hit_offsets=P,
+                hit_layer=P, hit_valid=P, n_hits=100, hit_pos=P, hit_cov=P, geom=ctypes.byref(_geom().struct),
+                cov_scale=100.0, max_len=26, state_out=Q, cov_out=Q, charge_out=Q, chi2=Q, ndf=Q, trk_status=Q,
+                stream=None)
+    args.update(over)
+    return kf.lib().kf_backward_fit(*args.values())
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(n=-1), "n = -1"),
+    (dict(ld=5), "ld = 5 < n = 10"),
+    (dict(prec=3), "precision 3"),
+    (dict(cov_scale=0.5), "cov_scale"),
+    (dict(cov_scale=float("nan")), "cov_scale"),
+    (dict(cov_scale=float("inf")), "cov_scale"),
+    (dict(max_len=0), "max_len = 0"),
+    (dict(max_len=65), "max_len = 65"),
+    (dict(n_hits=-1), "n_hits < 0"),
+    (dict(state_in=None), "state_in is NULL"),
+    (dict(hit_cov=None), "hit_cov is NULL"),
+    (dict(ndf=None), "ndf is NULL"),
+    (dict(ctx=None), "ctx is NULL"),
+    (dict(state_out=P), "alias"),
+    (dict(charge_out=P), "alias"),
+])
+def test_backward_fit_argument_validation(over, msg):
+    assert _backward_call(**over) == kf.KF_ERR_ARG
+    assert msg in kf.lib().kf_last_error().decode()
+
+
+def test_backward_fit_empty_batch_is_a_no_op():
+    assert _backward_call(n=0, ld=0, ctx=None, state_in=None) == kf.KF_OK

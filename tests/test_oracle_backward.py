@@ -202,3 +202,32 @@ def test_stopped_or_empty_tracks_keep_their_input():
         assert torch.equal(out["p"][t], fwd["p"][t]) and torch.equal(out["C"][t], fwd["C"][t])
     others = [t for t in range(40) if t not in (3, 5, 17)]
     assert ((out["status"][others] & O.NOT_REFITTED) == 0).all()
+
+
+def test_impose_surface_keeps_a_surface_covariance_and_removes_the_normal():
+    """A covariance propagated to a layer by the exact surface-to-surface
+    Jacobian already has the normal as a null vector: the projection leaves it
+    unchanged.  Applied to any covariance, it makes the normal a null vector
+    and is idempotent."""
+    wl = workloads()["barrel10"]
+    g = wl.geometry
+    ev = generate(wl, 200, holes=False)
+    sp, sC, sq, _ = O.make_seeds(ev.hit_offsets, ev.hit_valid, ev.hit_pos, g.bz)
+    lay = ev.hit_layer[ev.hit_offsets[:-1] + 1]
+    kind = torch.tensor(g.kind[lay], dtype=torch.int64)
+    pos = torch.tensor(g.pos[lay], dtype=DT)
+    p2, C2, _, st = O.propagate(sp, sC, sq, kind, pos, torch.tensor(g.x_over_x0[lay], dtype=DT), g)
+    ok = (st & O.NO_CROSSING) == 0
+    P = O.impose_surface(p2, C2, kind, pos)
+    scale = torch.sqrt(torch.diagonal(C2, dim1=1, dim2=2))
+    rel = (P - C2).abs() / (scale[:, :, None] * scale[:, None, :])
+    assert rel[ok].max() < 1e-10
+    p, C, _ = _random_states(100)
+    kind = torch.zeros(100, dtype=torch.int64)
+    R = torch.sqrt(p[:, 0] ** 2 + p[:, 1] ** 2)
+    P1 = O.impose_surface(p, C, kind, R)
+    nv = torch.stack([p[:, 0] / R, p[:, 1] / R] + [torch.zeros(100, dtype=DT)] * 4, 1)
+    assert (P1 @ nv[:, :, None]).abs().max() < 1e-12 * C.abs().max()
+    assert torch.allclose(O.impose_surface(p, P1, kind, R), P1, rtol=0, atol=1e-12)
+    Pd = O.impose_surface(p, C, torch.ones(100, dtype=torch.int64), R)
+    assert Pd[:, 2, :].abs().max() == 0 and Pd[:, :, 2].abs().max() == 0
