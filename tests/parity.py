@@ -158,3 +158,77 @@ def sym_unpack(packed_rows):
     return M
 
 
+
+
+# ---- backward fit ------------------------------------------------------------------
+
+BACKWARD_SCALE = 100.0   # covariance scale at the start of the backward pass
+IL = [(i, j) for i in range(6) for j in range(i + 1)]
+
+
+def pack21(C):
+    return np.stack([C[:, i, j] for i, j in IL])
+
+
+def unpack21(P):
+    n = P.shape[1]
+    M = np.zeros((n, 6, 6))
+    for k, (i, j) in enumerate(IL):
+        M[:, i, j] = M[:, j, i] = P[k]
+    return M
+
+
+def outputs_np(out):
+    return dict(p=out["state"].double().cpu().numpy().T, C=unpack21(out["cov"].double().cpu().numpy()),
+                q=out["charge"].cpu().numpy().astype(np.float64), chi2=out["chi2"].double().cpu().numpy(),
+                ndf=out["ndf"].cpu().numpy(), status=out["status"].cpu().numpy().astype(np.int64))
+
+
+def oracle_backward(ev, dtype, fwd, hit_pos=None, state_round=None, state_jitter=None):
+    hp = rounded(ev.hit_pos, dtype) if hit_pos is None else np.asarray(hit_pos, np.float64)
+    b = O.backward_fit(torch.tensor(fwd["p"]), torch.tensor(fwd["C"]), torch.tensor(fwd["q"]),
+                       torch.tensor(fwd["status"]), ev.hit_offsets, ev.hit_layer, ev.hit_valid, torch.tensor(hp),
+                       rounded(ev.hit_cov, dtype), ev.geometry, cov_scale=BACKWARD_SCALE, state_round=state_round,
+                       state_jitter=state_jitter)
+    return dict(p=b["p"].numpy(), C=b["C"].numpy(), q=b["q"].numpy(), chi2=b["chi2"].numpy(), ndf=b["ndf"].numpy(),
+                status=b["status"].numpy())
+
+
+def gpu_backward(c, kf, ev, dtype, fwd, use_status=True, max_len=26):
+    """The GPU backward pass from a forward result given as numpy arrays."""
+    dev = c.device
+    t = kf.event_tensors(ev, dtype, dev)
+    geom = kf.Geometry.from_toy(ev.geometry)
+    f = dict(state=torch.tensor(np.ascontiguousarray(fwd["p"].T), dtype=dtype, device=dev),
+             cov=torch.tensor(np.ascontiguousarray(pack21(fwd["C"])), dtype=dtype, device=dev),
+             charge=torch.tensor(fwd["q"].astype(np.int8), device=dev),
+             status=torch.tensor(fwd["status"].astype(np.int32), device=dev))
+    out = c.backward_fit(f, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"], geom,
+                         cov_scale=BACKWARD_SCALE, max_len=max_len, use_status=use_status)
+    torch.cuda.synchronize()
+    return outputs_np(out)
+
+
+def backward_probes(ev, dtype, run, ref, tol, seed=99):
+    """Tracks whose oracle result moves by more than half the tolerance under
+    the rounding-level probes (see the module docstring); run(hit_pos=...,
+    state_round=...) is the oracle computation being probed."""
+    rng = np.random.default_rng(seed)
+    hp = rounded(ev.hit_pos, dtype)
+    if dtype == torch.float32:
+        ulp = np.spacing(np.abs(hp).astype(np.float32)).astype(np.float64)
+        probes = [dict(hit_pos=hp + ulp * rng.choice([-1.0, 1.0], size=hp.shape)), dict(state_round=torch.float32)]
+    else:
+        ulp = 1e-13 * np.maximum(np.abs(hp), 1.0)
+        probes = [dict(hit_pos=hp + ulp * rng.choice([-1.0, 1.0], size=hp.shape)), dict(state_jitter=4e-16)]
+    bad = np.zeros(ev.n_tracks, bool)
+    for kw in probes:
+        o2 = run(**kw)
+        ep = param_error(o2["p"], ref["p"]).max(axis=1)
+        ec = chi2_error(o2["chi2"], ref["chi2"])
+        bad |= (ep > 0.5 * tol[0]) | (ec > 0.5 * tol[1]) | (o2["status"] != ref["status"])
+    return bad
+
+
+def rounded_forward(o, dtype):
+    return dict(p=rounded(o["p"], dtype), C=rounded(o["C"], dtype), q=o["q"], status=o["status"])

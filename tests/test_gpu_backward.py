@@ -24,14 +24,13 @@ import torch
 from oracle import kf_oracle as O
 from toygen import generate, subset, workloads
 
-from parity import compare_fit, oracle_fit, param_error, chi2_error, rounded
+from parity import (BACKWARD_SCALE, backward_probes, compare_fit, gpu_backward, oracle_backward, oracle_fit,
+                    outputs_np, rounded_forward)
 
 pytestmark = pytest.mark.gpu
 
 TOL32 = (1e-4, 1e-3)
 TOL64 = (1e-8, 1e-8)
-SCALE = 100.0
-IL = [(i, j) for i in range(6) for j in range(i + 1)]
 
 
 def say(*a):
@@ -56,78 +55,10 @@ def ctx(kf):
     c.close()
 
 
-def _pack(C):
-    return np.stack([C[:, i, j] for i, j in IL])
-
-
-def _unpack(P):
-    n = P.shape[1]
-    M = np.zeros((n, 6, 6))
-    for k, (i, j) in enumerate(IL):
-        M[:, i, j] = M[:, j, i] = P[k]
-    return M
-
-
-def _np(out):
-    return dict(p=out["state"].double().cpu().numpy().T, C=_unpack(out["cov"].double().cpu().numpy()),
-                q=out["charge"].cpu().numpy().astype(np.float64), chi2=out["chi2"].double().cpu().numpy(),
-                ndf=out["ndf"].cpu().numpy(), status=out["status"].cpu().numpy().astype(np.int64))
-
-
-def oracle_backward(ev, dtype, fwd, hit_pos=None, state_round=None, state_jitter=None):
-    hp = rounded(ev.hit_pos, dtype) if hit_pos is None else np.asarray(hit_pos, np.float64)
-    b = O.backward_fit(torch.tensor(fwd["p"]), torch.tensor(fwd["C"]), torch.tensor(fwd["q"]),
-                       torch.tensor(fwd["status"]), ev.hit_offsets, ev.hit_layer, ev.hit_valid, torch.tensor(hp),
-                       rounded(ev.hit_cov, dtype), ev.geometry, cov_scale=SCALE, state_round=state_round,
-                       state_jitter=state_jitter)
-    return dict(p=b["p"].numpy(), C=b["C"].numpy(), q=b["q"].numpy(), chi2=b["chi2"].numpy(), ndf=b["ndf"].numpy(),
-                status=b["status"].numpy())
-
-
-def gpu_backward(c, kf, ev, dtype, fwd, use_status=True, max_len=26):
-    """The GPU backward pass from a forward result given as numpy arrays."""
-    dev = c.device
-    t = kf.event_tensors(ev, dtype, dev)
-    geom = kf.Geometry.from_toy(ev.geometry)
-    f = dict(state=torch.tensor(np.ascontiguousarray(fwd["p"].T), dtype=dtype, device=dev),
-             cov=torch.tensor(np.ascontiguousarray(_pack(fwd["C"])), dtype=dtype, device=dev),
-             charge=torch.tensor(fwd["q"].astype(np.int8), device=dev),
-             status=torch.tensor(fwd["status"].astype(np.int32), device=dev))
-    out = c.backward_fit(f, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"], geom,
-                         cov_scale=SCALE, max_len=max_len, use_status=use_status)
-    torch.cuda.synchronize()
-    return _np(out)
-
-
-def _probes(ev, dtype, run, ref, tol, seed=99):
-    """Tracks whose oracle result moves by more than half the tolerance under
-    the rounding-level probes (see the module docstring); run(hit_pos=...,
-    state_round=...) is the oracle computation being probed."""
-    rng = np.random.default_rng(seed)
-    hp = rounded(ev.hit_pos, dtype)
-    if dtype == torch.float32:
-        ulp = np.spacing(np.abs(hp).astype(np.float32)).astype(np.float64)
-        probes = [dict(hit_pos=hp + ulp * rng.choice([-1.0, 1.0], size=hp.shape)), dict(state_round=torch.float32)]
-    else:
-        ulp = 1e-13 * np.maximum(np.abs(hp), 1.0)
-        probes = [dict(hit_pos=hp + ulp * rng.choice([-1.0, 1.0], size=hp.shape)), dict(state_jitter=4e-16)]
-    bad = np.zeros(ev.n_tracks, bool)
-    for kw in probes:
-        o2 = run(**kw)
-        ep = param_error(o2["p"], ref["p"]).max(axis=1)
-        ec = chi2_error(o2["chi2"], ref["chi2"])
-        bad |= (ep > 0.5 * tol[0]) | (ec > 0.5 * tol[1]) | (o2["status"] != ref["status"])
-    return bad
-
-
-def _rounded_fwd(o, dtype):
-    return dict(p=rounded(o["p"], dtype), C=rounded(o["C"], dtype), q=o["q"], status=o["status"])
-
-
 def _backward_only(c, kf, ev, dtype, seed_mode, tol, max_bad_frac, tail_frac):
-    fwd = _rounded_fwd(oracle_fit(ev, dtype, seed_mode), dtype)
+    fwd = rounded_forward(oracle_fit(ev, dtype, seed_mode), dtype)
     ob = oracle_backward(ev, dtype, fwd)
-    bad = _probes(ev, dtype, lambda **kw: oracle_backward(ev, dtype, fwd, **kw), ob, tol)
+    bad = backward_probes(ev, dtype, lambda **kw: oracle_backward(ev, dtype, fwd, **kw), ob, tol)
     assert bad.mean() <= max(max_bad_frac, 0.005), bad.mean()
     gb = gpu_backward(c, kf, ev, dtype, fwd)
     s = compare_fit(gb, ob, tol[0], tol[1], ~bad, tail_frac=tail_frac)
@@ -159,9 +90,9 @@ def _chain(c, kf, ev, dtype, seed_mode):
     fwd = c.seed_fit_tracks(t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"], geom,
                             seed_mode)
     out = c.backward_fit(fwd, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"], geom,
-                         cov_scale=SCALE)
+                         cov_scale=BACKWARD_SCALE)
     torch.cuda.synchronize()
-    return _np(out)
+    return outputs_np(out)
 
 
 def _oracle_chain(ev, dtype, seed_mode, hit_pos=None, state_round=None, state_jitter=None):
@@ -172,7 +103,7 @@ def _oracle_chain(ev, dtype, seed_mode, hit_pos=None, state_round=None, state_ji
 
 def _chain_case(c, kf, ev, dtype, seed_mode, tol, max_bad_frac, tail_frac):
     ob = _oracle_chain(ev, dtype, seed_mode)
-    bad = _probes(ev, dtype, lambda **kw: _oracle_chain(ev, dtype, seed_mode, **kw), ob, tol)
+    bad = backward_probes(ev, dtype, lambda **kw: _oracle_chain(ev, dtype, seed_mode, **kw), ob, tol)
     assert bad.mean() <= max(max_bad_frac, 0.005), bad.mean()
     gb = _chain(c, kf, ev, dtype, seed_mode)
     s = compare_fit(gb, ob, tol[0], tol[1], ~bad, tail_frac=tail_frac)
@@ -204,7 +135,7 @@ def test_not_refitted_tracks_keep_their_input(ctx, kf):
     say("backward stopped tracks")
     ev = generate(workloads()["mixed26"], 300)
     for dt in (torch.float32, torch.float64):
-        fwd = _rounded_fwd(oracle_fit(ev, dt, 1), dt)
+        fwd = rounded_forward(oracle_fit(ev, dt, 1), dt)
         base = gpu_backward(ctx, kf, ev, dt, fwd)
         st = fwd["status"].copy()
         stop = {3: O.NO_CROSSING, 40: O.NONFINITE, 41: O.NOT_REFITTED, 299: O.NO_CROSSING | O.GRAZING}
@@ -232,20 +163,20 @@ def test_backward_ragged_sizes(ctx, kf, n):
     if n == 0:
         ev = subset(ev, [])
     dt = torch.float32
-    fwd = _rounded_fwd(oracle_fit(ev, dt, 1), dt) if n else dict(p=np.zeros((0, 6)), C=np.zeros((0, 6, 6)),
+    fwd = rounded_forward(oracle_fit(ev, dt, 1), dt) if n else dict(p=np.zeros((0, 6)), C=np.zeros((0, 6, 6)),
                                                                  q=np.zeros(0), status=np.zeros(0, np.int64))
     g = gpu_backward(ctx, kf, ev, dt, fwd)
     assert g["chi2"].shape == (n,)
     if n:
         o = oracle_backward(ev, dt, fwd)
-        bad = _probes(ev, dt, lambda **kw: oracle_backward(ev, dt, fwd, **kw), o, TOL32)
+        bad = backward_probes(ev, dt, lambda **kw: oracle_backward(ev, dt, fwd, **kw), o, TOL32)
         compare_fit(g, o, TOL32[0], TOL32[1], ~bad, tail_frac=0.01)
 
 
 def test_backward_is_deterministic(ctx, kf):
     ev = generate(workloads()["barrel20"], 3000)
     for dt in (torch.float32, torch.float64):
-        fwd = _rounded_fwd(oracle_fit(ev, dt, 0), dt)
+        fwd = rounded_forward(oracle_fit(ev, dt, 0), dt)
         a = gpu_backward(ctx, kf, ev, dt, fwd)
         b = gpu_backward(ctx, kf, ev, dt, fwd)
         for k in a:
