@@ -521,7 +521,7 @@ def _jitter(p, C, key, r):
 
 
 def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
-               align=None, state_round=None, state_jitter=None):
+               align=None, state_round=None, state_jitter=None, record=False):
     """kf_fit_tracks: forward Kalman fit of every track.
 
     Each track starts at its seed, which sits on its first valid entry k0
@@ -545,7 +545,9 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
     update every element of the state and covariance is scaled by (1 + r) or
     (1 - r) (alternating by element, track and entry) -- the same probe at
     float64 rounding.
-    Returns dict(p, C, q, chi2, ndf, status)."""
+    record: also return the filtered state after every entry (pe [nh,6],
+    Ce [nh,6,6], qe [nh]; NaN for entries the fit did not reach).
+    Returns dict(p, C, q, chi2, ndf, status[, pe, Ce, qe])."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
     val_all = torch.as_tensor(hit_valid, dtype=torch.int64)
@@ -577,6 +579,11 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
     end = off[1:]
 
     prev_e = k0.clone()
+    nh = lay_all.shape[0]
+    if record:
+        pe = torch.full((nh, 6), float("nan"), dtype=DT)
+        Ce = torch.full((nh, 6, 6), float("nan"), dtype=DT)
+        qe = torch.full((nh,), float("nan"), dtype=DT)
     for j in range(maxlen):
         e = k0 + j
         act = alive & (e < end)
@@ -632,7 +639,15 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
         status = status.index_put((idx,), status[idx] | st)
         alive = alive.index_put((idx,), keep)
         prev_e = prev_e.index_put((idx,), ei)
-    return dict(p=p, C=C, q=q, chi2=chi2, ndf=2 * nval - 5, status=status)
+        if record:
+            k = torch.nonzero(keep)[:, 0]
+            pe = pe.index_put((ei[k],), pn[k])
+            Ce = Ce.index_put((ei[k],), Cn[k])
+            qe = qe.index_put((ei[k],), qn[k])
+    out = dict(p=p, C=C, q=q, chi2=chi2, ndf=2 * nval - 5, status=status)
+    if record:
+        out.update(pe=pe, Ce=Ce, qe=qe)
+    return out
 
 
 def fit_event(ev, align=None, seed_mode=SEED_FIRST_THREE):
@@ -691,8 +706,45 @@ def impose_surface(p, C, kind, pos):
     return P @ C @ P
 
 
+def surface_frame(p, kind, pos):
+    """[n,6,5] orthonormal basis of the directions a state on its surface can
+    move in: (tangent, z) for a barrel of radius pos (tangent = (-y, x)/R),
+    (x, y) for a disk, then ipt, phi, theta."""
+    p = _t(p)
+    n = p.shape[0]
+    isb = torch.as_tensor(kind) == BARREL
+    R = _t(pos)
+    B = torch.zeros(n, 6, 5, dtype=DT)
+    B[:, 0, 0] = torch.where(isb, -p[:, 1] / R, torch.ones_like(R))
+    B[:, 1, 0] = torch.where(isb, p[:, 0] / R, torch.zeros_like(R))
+    B[:, 2, 1] = torch.where(isb, torch.ones_like(R), torch.zeros_like(R))
+    B[:, 1, 1] = torch.where(isb, torch.zeros_like(R), torch.ones_like(R))
+    B[:, 3, 2] = B[:, 4, 3] = B[:, 5, 4] = 1.0
+    return B
+
+
+def combine_on_surface(pf, Cf, pb, Cb, kind, pos):
+    """Two estimates of one state on a surface, from disjoint sets of hits,
+    combined (the two-filter smoother): x = x_f + C_f (C_f + C_b)^+ (x_b - x_f),
+    C = C_f - C_f (C_f + C_b)^+ C_f, where ^+ inverts on the 5-dimensional
+    space the state can move in (the surface normal is a null vector of both
+    covariances): (C_f + C_b)^+ = B (B^T (C_f + C_b) B)^-1 B^T with the frame
+    B of surface_frame.  phi differences are wrapped."""
+    B = surface_frame(pf, kind, pos)
+    Bt = B.transpose(1, 2)
+    d = pb - pf
+    d = torch.cat([d[:, :4], wrap_phi(d[:, 4:5]), d[:, 5:]], dim=1)
+    M = Bt @ (Cf + Cb) @ B
+    G = Cf @ B
+    Minv = torch.linalg.inv(M)
+    ps = pf + (G @ Minv @ (Bt @ d[:, :, None]))[:, :, 0]
+    ps = torch.cat([ps[:, :4], wrap_phi(ps[:, 4:5]), ps[:, 5:]], dim=1)
+    Cs = Cf - G @ Minv @ G.transpose(1, 2)
+    return ps, 0.5 * (Cs + Cs.transpose(1, 2))
+
+
 def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
-                 cov_scale=BACKWARD_COV_SCALE, state_round=None, state_jitter=None):
+                 cov_scale=BACKWARD_COV_SCALE, state_round=None, state_jitter=None, smooth_from=None):
     """Backward fit (Sec. 2.2, step 4): every track is traversed again, from
     its last entry back to its first valid entry, and refitted.
 
@@ -711,7 +763,19 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     stopped (NO_CROSSING or NONFINITE in fwd_status) or with no valid entry
     keep their input, with status NOT_REFITTED.  state_round, state_jitter:
     the conditioning probes of fit_tracks, applied after every propagation
-    and update.  Returns dict(p, C, q, chi2,
+    and update.
+
+    smooth_from: None, or the forward fit's filtered state after every entry
+    (dict(pe, Ce) of fit_tracks(record=True)); then the smoothed state of
+    every entry from the first valid one to the last is returned as well
+    (ps [nh,6], Cs [nh,6,6], NaN elsewhere).  The forward filtered state of an
+    entry holds its layer's scattering and hit and those before; the
+    backward pass's state on arriving at the entry, before that layer's
+    material, holds the hits after it; both describe the track just outside
+    the layer, and combine_on_surface combines them.  The last entry's
+    smoothed state is its forward filtered state.  With smoothing, the
+    backward pass propagates without material, combines, then adds the
+    layer's material (the same arithmetic as propagate with material).  Returns dict(p, C, q, chi2,
     ndf, status): chi2 and ndf (= 2 * used hits - 5) of the backward pass."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
@@ -741,6 +805,12 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     lay_last = lay_all[torch.clamp(last, min=0)] if n > 0 else lay_all[:0]
     C0 = impose_surface(fwd_p, _t(fwd_C) * cov_scale, kind_l[lay_last], pos_l[lay_last])
     p, C, q = reverse_direction(_t(fwd_p), C0, _t(fwd_q))
+    smooth = smooth_from is not None
+    if smooth:
+        nh = lay_all.shape[0]
+        ps_all = torch.full((nh, 6), float("nan"), dtype=DT)
+        Cs_all = torch.full((nh, 6, 6), float("nan"), dtype=DT)
+        pe_f, Ce_f = _t(smooth_from["pe"]), _t(smooth_from["Ce"])
     chi2 = torch.zeros(n, dtype=DT)
     nval = torch.zeros(n, dtype=torch.int64)
     status = torch.zeros(n, dtype=torch.int64)
@@ -756,10 +826,26 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
         lay = lay_all[ei]
         kind = kind_l[lay]
         pp, CC, qq = p[idx], C[idx], q[idx]
-        if j > 0:
+        if j > 0 and smooth:
+            same = lay == lay_all[prev_e[idx]]
+            pp2, CC2, _, st = propagate(pp, CC, qq, kind, pos_l[lay], x0_l[lay], geom, apply_material=False,
+                                        same=same)
+            reach = (st & NO_CROSSING) == 0
+            pb, Cb, _ = reverse_direction(pp2, CC2, qq)
+            ps, Cs = combine_on_surface(pe_f[ei], Ce_f[ei], pb, Cb, kind, pos_l[lay])
+            r = torch.nonzero(reach)[:, 0]
+            ps_all = ps_all.index_put((ei[r],), ps[r])
+            Cs_all = Cs_all.index_put((ei[r],), Cs[r])
+            Q, grazing = process_noise(pp2, kind, x0_l[lay], geom.mass)
+            CC2 = CC2 + Q
+            st = st | torch.where(grazing & reach, GRAZING, 0)
+        elif j > 0:
             same = lay == lay_all[prev_e[idx]]
             pp2, CC2, _, st = propagate(pp, CC, qq, kind, pos_l[lay], x0_l[lay], geom, apply_material=True, same=same)
         else:
+            if smooth:
+                ps_all = ps_all.index_put((ei,), pe_f[ei])
+                Cs_all = Cs_all.index_put((ei,), Ce_f[ei])
             Q, grazing = process_noise(pp, kind, x0_l[lay], geom.mass)
             pp2, CC2 = pp, CC + Q
             st = torch.where(grazing, GRAZING, 0).to(torch.int64)
@@ -802,7 +888,11 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     C = torch.where(run[:, None, None], C, _t(fwd_C))
     q = torch.where(run, q, _t(fwd_q))
     status = torch.where(run, status, torch.full_like(status, NOT_REFITTED))
-    return dict(p=p, C=C, q=q, chi2=chi2, ndf=2 * nval - 5, status=status)
+    out = dict(p=p, C=C, q=q, chi2=chi2, ndf=2 * nval - 5, status=status)
+    if smooth:
+        # the entries the backward pass reached
+        out.update(ps=ps_all, Cs=Cs_all)
+    return out
 
 
 # --------------------------------------------------------------------------
