@@ -241,6 +241,40 @@ int kf_backward_fit(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                     void *state_out, void *cov_out, int8_t *charge_out,
                     void *chi2, int32_t *ndf, uint32_t *trk_status, void *stream);
 
+/* Backward fit with smoothing (the backward fit of kf_backward_fit, completed
+ * by a two-filter smoother): in addition to the backward fit's outputs (the
+ * same arguments and rules), the smoothed state of every entry of a refitted
+ * track from its first valid entry to its last.  At each entry the forward
+ * filtered state (from fwd_checkpoints) and the backward pass's state on
+ * arriving there, before that layer's material (turned outward), both
+ * describe the track just outside the layer; they are combined on the five
+ * directions the state can move in on the surface:
+ *   x = x_f + C_f (C_f + C_b)^+ (x_b - x_f),  C = C_f - C_f (C_f + C_b)^+ C_f
+ * (the 5x5 system solved by Cholesky in FP64).  The last entry's smoothed
+ * state is its forward filtered state (state_in).  The backward pass adds
+ * each layer's material after the combination (the same arithmetic as
+ * kf_backward_fit, apart from rounding).
+ * fwd_checkpoints: the [28][ld * (max_len - 1)] checkpoints written by the
+ * forward fit (kf_fit_tracks / kf_seed_fit_tracks) of the same tracks with
+ * seg = 1 and the same max_len (slot m holds the filtered state after the
+ * track's first valid entry + m).  smooth_state [6][ld * max_len],
+ * smooth_cov [21][ld * max_len] (device, caller-owned): the smoothed state of
+ * entry r (0-based within track t) at [i][r * ld + t]; entries that are not
+ * smoothed (before the first valid entry, beyond max_len, of tracks not
+ * refitted, after a stop of the backward pass) are not written.  An entry
+ * whose 5x5 system is not positive definite is not written either, and its
+ * track gets KF_TRK_COV_NOT_PSD.  KF_ERR_ARG as kf_backward_fit, and for a
+ * missing or aliased smoothing buffer. */
+int kf_smooth_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                     const void *state_in, const void *cov_in, const int8_t *charge_in,
+                     const uint32_t *fwd_status, const void *fwd_checkpoints,
+                     const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
+                     int64_t n_hits, const void *hit_pos, const void *hit_cov,
+                     const kf_geometry *geom, double cov_scale, int32_t max_len,
+                     void *state_out, void *cov_out, int8_t *charge_out,
+                     void *chi2, int32_t *ndf, uint32_t *trk_status,
+                     void *smooth_state, void *smooth_cov, void *stream);
+
 /* Parameters of the combinatorial candidate search (kf_score_hits).  The
  * paper makes the window, the chi2 cut, the missed-layer limit and the
  * candidate score per-iteration parameters and standard functions (Sec. 3.2,

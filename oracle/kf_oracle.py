@@ -725,21 +725,25 @@ def surface_frame(p, kind, pos):
 
 def combine_on_surface(pf, Cf, pb, Cb, kind, pos):
     """Two estimates of one state on a surface, from disjoint sets of hits,
-    combined (the two-filter smoother): x = x_f + C_f (C_f + C_b)^+ (x_b - x_f),
-    C = C_f - C_f (C_f + C_b)^+ C_f, where ^+ inverts on the 5-dimensional
-    space the state can move in (the surface normal is a null vector of both
-    covariances): (C_f + C_b)^+ = B (B^T (C_f + C_b) B)^-1 B^T with the frame
-    B of surface_frame.  phi differences are wrapped."""
+    combined (the two-filter smoother): with the gain K = C_f (C_f + C_b)^+,
+    x = x_f + K (x_b - x_f) and C = (I - K) C_f (I - K)^T + K C_b K^T, where
+    ^+ inverts on the 5-dimensional space the state can move in (the surface
+    normal is a null vector of both covariances):
+    (C_f + C_b)^+ = B (B^T (C_f + C_b) B)^-1 B^T with the frame B of
+    surface_frame.  C equals C_f - C_f (C_f + C_b)^+ C_f; the symmetric form
+    is used because that difference loses digits where C_f is much larger
+    than the result (the first layers, where the forward state is still near
+    its diffuse seed).  phi differences are wrapped."""
     B = surface_frame(pf, kind, pos)
     Bt = B.transpose(1, 2)
     d = pb - pf
     d = torch.cat([d[:, :4], wrap_phi(d[:, 4:5]), d[:, 5:]], dim=1)
     M = Bt @ (Cf + Cb) @ B
-    G = Cf @ B
-    Minv = torch.linalg.inv(M)
-    ps = pf + (G @ Minv @ (Bt @ d[:, :, None]))[:, :, 0]
+    K = Cf @ B @ torch.linalg.inv(M) @ Bt
+    ps = pf + (K @ d[:, :, None])[:, :, 0]
     ps = torch.cat([ps[:, :4], wrap_phi(ps[:, 4:5]), ps[:, 5:]], dim=1)
-    Cs = Cf - G @ Minv @ G.transpose(1, 2)
+    A = torch.eye(6, dtype=DT) - K
+    Cs = A @ Cf @ A.transpose(1, 2) + K @ Cb @ K.transpose(1, 2)
     return ps, 0.5 * (Cs + Cs.transpose(1, 2))
 
 

@@ -538,12 +538,18 @@ int kf_seed_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, in
                          state_out, cov_out, charge_out, chi2, ndf, checkpoints, seg, max_len, trk_status, stream);
 }
 
-int kf_backward_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* state_in,
-                    const void* cov_in, const int8_t* charge_in, const uint32_t* fwd_status,
-                    const int32_t* hit_offsets, const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits,
-                    const void* hit_pos, const void* hit_cov, const kf_geometry* geom, double cov_scale,
-                    int32_t max_len, void* state_out, void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf,
-                    uint32_t* trk_status, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// kf_backward_fit and kf_smooth_tracks (fwd_checkpoints and the smooth_*
+// outputs set).
+int backward_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* state_in, const void* cov_in,
+                  const int8_t* charge_in, const uint32_t* fwd_status, const void* fwd_checkpoints,
+                  const int32_t* hit_offsets, const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits,
+                  const void* hit_pos, const void* hit_cov, const kf_geometry* geom, double cov_scale,
+                  int32_t max_len, void* state_out, void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf,
+                  uint32_t* trk_status, void* smooth_state, void* smooth_cov, const char* name, void* stream) {
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
@@ -569,6 +575,15 @@ int kf_backward_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const
   KF_REQUIRE(ctx);
   if (state_out == state_in || cov_out == cov_in || (const void*)charge_out == (const void*)charge_in)
     return fail(KF_ERR_ARG, "the outputs must not alias the inputs");
+  const bool smooth = fwd_checkpoints != nullptr || smooth_state != nullptr || smooth_cov != nullptr;
+  if (smooth) {
+    KF_REQUIRE(fwd_checkpoints);
+    KF_REQUIRE(smooth_state);
+    KF_REQUIRE(smooth_cov);
+    if (smooth_state == smooth_cov || smooth_state == state_out || smooth_cov == cov_out)
+      return fail(KF_ERR_ARG, "the smoothed outputs must not alias each other or the outputs");
+  }
+  const int32_t n_seg_f = max_len > 1 ? max_len - 1 : 1;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if (prec == KF_F32) {
@@ -579,6 +594,10 @@ int kf_backward_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const
     b.f.max_len = max_len;
     b.fwd_status = fwd_status;
     b.cov_scale = float(cov_scale);
+    b.fwd_ckpt = (const float*)fwd_checkpoints;
+    b.n_seg_f = n_seg_f;
+    b.smooth_state = (float*)smooth_state;
+    b.smooth_cov = (float*)smooth_cov;
     e = kf::launch_backward(b, g, s);
   } else {
     kf::BwdArgs<double> b;
@@ -588,10 +607,43 @@ int kf_backward_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const
     b.f.max_len = max_len;
     b.fwd_status = fwd_status;
     b.cov_scale = cov_scale;
+    b.fwd_ckpt = (const double*)fwd_checkpoints;
+    b.n_seg_f = n_seg_f;
+    b.smooth_state = (double*)smooth_state;
+    b.smooth_cov = (double*)smooth_cov;
     e = kf::launch_backward(b, g, s);
   }
-  if (e != hipSuccess) return hip_fail(e, "kf_backward_fit");
+  if (e != hipSuccess) return hip_fail(e, name);
   return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_backward_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* state_in,
+                    const void* cov_in, const int8_t* charge_in, const uint32_t* fwd_status,
+                    const int32_t* hit_offsets, const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits,
+                    const void* hit_pos, const void* hit_cov, const kf_geometry* geom, double cov_scale,
+                    int32_t max_len, void* state_out, void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf,
+                    uint32_t* trk_status, void* stream) {
+  return backward_impl(ctx, prec, n, ld, state_in, cov_in, charge_in, fwd_status, nullptr, hit_offsets, hit_layer,
+                       hit_valid, n_hits, hit_pos, hit_cov, geom, cov_scale, max_len, state_out, cov_out, charge_out,
+                       chi2, ndf, trk_status, nullptr, nullptr, "kf_backward_fit", stream);
+}
+
+int kf_smooth_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* state_in,
+                     const void* cov_in, const int8_t* charge_in, const uint32_t* fwd_status,
+                     const void* fwd_checkpoints, const int32_t* hit_offsets, const int16_t* hit_layer,
+                     const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos, const void* hit_cov,
+                     const kf_geometry* geom, double cov_scale, int32_t max_len, void* state_out, void* cov_out,
+                     int8_t* charge_out, void* chi2, int32_t* ndf, uint32_t* trk_status, void* smooth_state,
+                     void* smooth_cov, void* stream) {
+  if (!fwd_checkpoints || !smooth_state || !smooth_cov)
+    return fail(KF_ERR_ARG, "kf_smooth_tracks needs fwd_checkpoints, smooth_state and smooth_cov");
+  return backward_impl(ctx, prec, n, ld, state_in, cov_in, charge_in, fwd_status, fwd_checkpoints, hit_offsets,
+                       hit_layer, hit_valid, n_hits, hit_pos, hit_cov, geom, cov_scale, max_len, state_out, cov_out,
+                       charge_out, chi2, ndf, trk_status, smooth_state, smooth_cov, "kf_smooth_tracks", stream);
 }
 
 int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {

@@ -15,10 +15,89 @@ namespace {
 
 constexpr int kBwdBlock = 256;
 
+// One step of the smoothing backward pass (backward index k >= 1, entry r of
+// the track): propagation to the entry's layer without its material; there
+// the backward prediction, turned outward, is combined with the forward
+// filtered state of the entry (both describe the track just outside the
+// layer) and the smoothed state stored; then the layer's material and, for a
+// valid hit, the update.  The rest as in fit_entry (layer check, backup,
+// roll-back of a non-finite step).
+template <typename T>
+__device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, int64_t t, int r, int k0, int lay,
+                                   int& prev, bool valid, const T m[3], const T V[6], T p[6], T c[21], int& q,
+                                   uint32_t& st, T& chi2, int& nval, T* bk, int bk_stride) {
+  const FitArgs<T>& a = b.f;
+  if (lay < 0 || lay >= g.n_layers) {
+    st |= TRK_BAD_INPUT;
+    return false;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) bk[i * bk_stride] = p[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) bk[(6 + i) * bk_stride] = c[i];
+  const int qq = q;
+  uint32_t sst = 0;
+  const int kind = g.kind[lay];
+  if (!propagate(p, c, q, kind, g.pos[lay], g.x0[lay], lay == prev, false, g.bz, g.mass, sst)) {
+    st |= sst;
+    return false;
+  }
+  {
+    T pb[6], cb[21];
+    int qb = q;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) pb[i] = p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) cb[i] = c[i];
+    reverse_direction(pb, cb, qb);
+    const int64_t ld = a.ld, cst = ld * int64_t(b.n_seg_f);
+    const T* f = b.fwd_ckpt + int64_t(r - k0) * ld + t;
+    T pf[6], cf[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) pf[i] = f[i * cst];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) cf[i] = f[(6 + i) * cst];
+    T ps[6], cs[21];
+    if (combine_on_surface(pf, cf, pb, cb, kind, g.pos[lay], ps, cs)) {
+      const int64_t os = ld * int64_t(a.max_len);
+      T* so = b.smooth_state + int64_t(r) * ld + t;
+      T* co = b.smooth_cov + int64_t(r) * ld + t;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) so[i * os] = ps[i];
+#pragma unroll
+      for (int i = 0; i < 21; ++i) co[i * os] = cs[i];
+    } else {
+      sst |= TRK_COV_NOT_PSD;
+    }
+  }
+  add_material_here(p, c, kind, g.x0[lay], g.mass, sst);
+  T c2 = T(0);
+  if (valid) {
+    T mm[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) mm[i] = m[i];
+    update(p, c, q, mm, V, c2, sst);
+  }
+  if (!all_finite(p, c, c2)) {
+    st |= sst | TRK_NONFINITE;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) p[i] = bk[i * bk_stride];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = bk[(6 + i) * bk_stride];
+    q = qq;
+    return false;
+  }
+  st |= sst;
+  chi2 += c2;
+  nval += valid ? 1 : 0;
+  prev = lay;
+  return true;
+}
+
 // Backward fit of tracks [w0, w0 + 64) (one wave; every lane must call it).
 // Entry k of a track's backward pass is CSR entry last - k; the pass has
 // n_entries - k0 entries (k0: the first valid entry in crossing order).
-template <typename T, int J>
+template <typename T, int J, bool SMOOTH>
 __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g, int64_t w0, StageBuf<T, J>& sb,
                                      T* bk, int bk_stride) {
   const FitArgs<T>& a = b.f;
@@ -26,21 +105,20 @@ __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g,
   const int64_t t = w0 + lane;
   const bool in_range = t < a.n;
   int64_t last = 0;
-  int len = 0;
+  int len = 0, n_e = 0, k0 = 0;
   T p[6], c[21];
   int q = 0;
   uint32_t st = 0;
   bool run = false;
   if (in_range) {
     const int64_t e0 = a.hit_offsets[t];
-    int n_e = int(a.hit_offsets[t + 1] - e0);
+    n_e = int(a.hit_offsets[t + 1] - e0);
     if (n_e > a.max_len) n_e = a.max_len;
 #pragma unroll
     for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * a.ld + t];
 #pragma unroll
     for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * a.ld + t];
     q = a.seed_charge[t];
-    int k0 = 0;
     while (k0 < n_e && a.hit_valid[e0 + k0] == 0) ++k0;
     const uint32_t stop = TRK_NO_CROSSING | TRK_NONFINITE | TRK_BAD_INPUT;
     run = k0 < n_e && !(b.fwd_status && (b.fwd_status[t] & stop));
@@ -108,8 +186,24 @@ __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g,
       for (int x = 0; x < 3; ++x) m[x] = sb.v[x][jj][lane];
 #pragma unroll
       for (int x = 0; x < 6; ++x) V[x] = sb.v[3 + x][jj][lane];
-      live = fit_entry(a, g, static_cast<const T*>(nullptr), t, k, lay, prev, valid, m, V, p, c, q, st, chi2, nval,
-                       bk, bk_stride);
+      if constexpr (SMOOTH) {
+        const int r = n_e - 1 - k;
+        if (k == 0) {
+          // the last entry's smoothed state is its forward filtered state
+          const int64_t os = a.ld * int64_t(a.max_len);
+#pragma unroll
+          for (int i = 0; i < 6; ++i) b.smooth_state[i * os + int64_t(r) * a.ld + t] = a.seed_state[i * a.ld + t];
+#pragma unroll
+          for (int i = 0; i < 21; ++i) b.smooth_cov[i * os + int64_t(r) * a.ld + t] = a.seed_cov[i * a.ld + t];
+          live = fit_entry(a, g, static_cast<const T*>(nullptr), t, k, lay, prev, valid, m, V, p, c, q, st, chi2,
+                           nval, bk, bk_stride);
+        } else {
+          live = smooth_step(b, g, t, r, k0, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
+        }
+      } else {
+        live = fit_entry(a, g, static_cast<const T*>(nullptr), t, k, lay, prev, valid, m, V, p, c, q, st, chi2,
+                         nval, bk, bk_stride);
+      }
     }
     wave_sync();   // every lane has read the chunk before the next one is staged
   }
@@ -120,8 +214,9 @@ __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g,
 }
 
 // WAVES: waves per SIMD the register allocation must allow (2 in FP32, 1 in
-// FP64, the forward fit's tuned choices).
-template <typename T, int WAVES>
+// FP64, the forward fit's tuned choices; 1 with smoothing, whose FP64 5x5
+// combination needs the registers).
+template <typename T, int WAVES, bool SMOOTH>
 __global__ void __launch_bounds__(kBwdBlock, WAVES) backward_kernel(BwdArgs<T> b, GeomArgs g) {
   constexpr int J = stage_entries<T, WAVES>();
   __shared__ GeomLds<T> sg;
@@ -129,7 +224,7 @@ __global__ void __launch_bounds__(kBwdBlock, WAVES) backward_kernel(BwdArgs<T> b
   __shared__ StageBuf<T, J> sb[kBwdBlock / 64];
   stage_geometry(sg, g);
   const int64_t w0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
-  backward_wave_staged<T, J>(b, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, w0,
+  backward_wave_staged<T, J, SMOOTH>(b, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, w0,
                              sb[threadIdx.x >> 6], bk + threadIdx.x, int(blockDim.x));
 }
 
@@ -139,7 +234,11 @@ template <typename T>
 hipError_t launch_backward(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s) {
   if (a.f.n == 0) return hipSuccess;
   const int64_t grid = (a.f.n + kBwdBlock - 1) / kBwdBlock;
-  hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1>), dim3(unsigned(grid)), dim3(kBwdBlock), 0, s, a, g);
+  if (a.smooth_state)
+    hipLaunchKernelGGL((backward_kernel<T, 1, true>), dim3(unsigned(grid)), dim3(kBwdBlock), 0, s, a, g);
+  else
+    hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, false>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
+                       s, a, g);
   return hipGetLastError();
 }
 

@@ -174,6 +174,14 @@ struct BwdArgs {
   FitArgs<T> f;
   const uint32_t* fwd_status;  // [n] status of the forward fit, or null
   T cov_scale;                 // the forward covariance is multiplied by this first
+  // smoothing (all null / 0 for the plain backward fit): the forward fit's
+  // filtered state after every entry, as its checkpoints with seg = 1
+  // ([28][ld * n_seg_f], slot m = after entry k0 + m), and the smoothed
+  // state of entry r of track t at [6 or 21][r * ld + t] (ld * max_len)
+  const T* fwd_ckpt;
+  int32_t n_seg_f;
+  T* smooth_state;
+  T* smooth_cov;
 };
 template <typename T>
 hipError_t launch_backward(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s);

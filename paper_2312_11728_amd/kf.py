@@ -27,7 +27,8 @@ MAX_LAYERS = 64
 EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_propagate", "kf_update",
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
            "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph",
-           "kf_set_kernel_timing", "kf_fit_kernel_time", "kf_seed_fit_tracks", "kf_backward_fit"]
+           "kf_set_kernel_timing", "kf_fit_kernel_time", "kf_seed_fit_tracks", "kf_backward_fit",
+           "kf_smooth_tracks"]
 
 BACKWARD_COV_SCALE = 100.0   # forward covariance scale at the start of the backward fit
 
@@ -96,6 +97,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        _i32, _i32, _vp, _vp]
     lib.kf_backward_fit.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                     ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_smooth_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
+                                     _vp, ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                     _vp, _vp]
     lib.kf_score_hits.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(KfGeometry),
                                   ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_adjoint.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
@@ -352,6 +356,47 @@ class Context:
                                      _ptr(out["charge"]), _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(out["status"]),
                                      _stream(dev)))
         return out
+
+    def smooth_tracks(self, fwd, checkpoints, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry,
+                      cov_scale=BACKWARD_COV_SCALE, max_len=26, out=None, smooth=None, use_status=True):
+        """Backward fit with smoothing (kf_smooth_tracks): `fwd` and
+        `checkpoints` from fit_tracks / seed_fit_tracks called with
+        checkpoints=[28, n * (max_len - 1)], seg=1 and the same max_len.
+        Returns (out, smooth): the backward fit's outputs, and the smoothed
+        state [6, max_len, n] and covariance [21, max_len, n] of entry r of
+        track t at [:, r, t] (entries not smoothed are not written; smooth
+        may pass preallocated tensors)."""
+        dev = self.device
+        st_in, cov_in, q_in = fwd["state"], fwd["cov"], fwd["charge"]
+        dt = st_in.dtype
+        n = st_in.shape[1]
+        for t_, nm, rows in ((st_in, "state", 6), (cov_in, "cov", 21), (hit_pos, "hit_pos", 3), (hit_cov, "hit_cov", 6),
+                             (checkpoints, "checkpoints", 28)):
+            _need(t_, nm, dt, dev, rows=rows)
+        _need(q_in, "charge", torch.int8, dev)
+        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need(hit_layer, "hit_layer", torch.int16, dev)
+        _need(hit_valid, "hit_valid", torch.uint8, dev)
+        if st_in.stride(0) != n or cov_in.stride(0) != n:
+            raise ValueError("state and cov must have leading dimension n")
+        if checkpoints.shape[1] != n * max(1, max_len - 1):
+            raise ValueError("checkpoints must be [28, n * (max_len - 1)] (seg = 1)")
+        status = fwd["status"] if use_status else None
+        if out is None:
+            out = fit_outputs(n, dt, dev)
+        if smooth is None:
+            smooth = dict(state=torch.full((6, max_len, n), float("nan"), dtype=dt, device=dev),
+                          cov=torch.full((21, max_len, n), float("nan"), dtype=dt, device=dev))
+        for k, rows in (("state", 6), ("cov", 21)):
+            if smooth[k].shape != (rows, max_len, n) or smooth[k].dtype != dt or not smooth[k].is_contiguous():
+                raise ValueError(f"smooth[{k!r}] must be a contiguous [{rows}, {max_len}, {n}] tensor of {dt}")
+        _check(lib().kf_smooth_tracks(self.handle, _prec(dt), n, n, _ptr(st_in), _ptr(cov_in), _ptr(q_in),
+                                      _ptr(status), _ptr(checkpoints), _ptr(hit_offsets), _ptr(hit_layer),
+                                      _ptr(hit_valid), hit_pos.shape[1], _ptr(hit_pos), _ptr(hit_cov),
+                                      ctypes.byref(geom.struct), float(cov_scale), int(max_len), _ptr(out["state"]),
+                                      _ptr(out["cov"]), _ptr(out["charge"]), _ptr(out["chi2"]), _ptr(out["ndf"]),
+                                      _ptr(out["status"]), _ptr(smooth["state"]), _ptr(smooth["cov"]), _stream(dev)))
+        return out, smooth
 
     def seed_fit_tracks(self, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry, seed_mode,
                         align=None, seeds=None, checkpoints=None, seg=1, max_len=26, out=None):

@@ -222,3 +222,30 @@ def test_backward_fit_argument_validation(over, msg):
 
 def test_backward_fit_empty_batch_is_a_no_op():
     assert _backward_call(n=0, ld=0, ctx=None, state_in=None) == kf.KF_OK
+
+
+def _smooth_call(**over):
+    Q = ctypes.c_void_p(0x2000)
+    R = ctypes.c_void_p(0x3000)
+    S = ctypes.c_void_p(0x4000)
+    args = dict(ctx=P, prec=kf.KF_F32, n=10, ld=10, state_in=P, cov_in=P, charge_in=P, fwd_status=P,
+                fwd_checkpoints=P, hit_offsets=P, hit_layer=P, hit_valid=P, n_hits=100, hit_pos=P, hit_cov=P,
+                geom=ctypes.byref(_geom().struct), cov_scale=100.0, max_len=26, state_out=Q, cov_out=Q, charge_out=Q,
+                chi2=Q, ndf=Q, trk_status=Q, smooth_state=R, smooth_cov=S, stream=None)
+    args.update(over)
+    return kf.lib().kf_smooth_tracks(*args.values())
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(fwd_checkpoints=None), "needs fwd_checkpoints"),
+    (dict(smooth_state=None), "needs fwd_checkpoints"),
+    (dict(smooth_cov=None), "needs fwd_checkpoints"),
+    (dict(smooth_cov=ctypes.c_void_p(0x3000)), "must not alias"),
+    (dict(smooth_state=ctypes.c_void_p(0x2000)), "must not alias"),
+    (dict(cov_scale=0.0), "cov_scale"),
+    (dict(n=-2), "n = -2"),
+    (dict(max_len=0), "max_len = 0"),
+])
+def test_smooth_tracks_argument_validation(over, msg):
+    assert _smooth_call(**over) == kf.KF_ERR_ARG
+    assert msg in kf.lib().kf_last_error().decode()
