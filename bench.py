@@ -27,6 +27,10 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 # operation count of the per-entry step in the design notes
 FLOP_VALID_ENTRY = 1280
 FLOP_HOLE_ENTRY = 475
+# the smoother's combination per entry (FP64, counted from its operations:
+# the projected 5x5 system, its Cholesky factor, six solves, the gain and the
+# symmetric covariance form)
+FLOP_SMOOTH_COMBINE = 1900
 # reverse of one entry (update, material and transport adjoints), excluding
 # the recomputation of forward states from checkpoints
 FLOP_VJP_VALID_ENTRY = 2660
@@ -263,16 +267,40 @@ def bench_backward(ctx, K, ev, args, steps=None):
         ctx.seed_fit_tracks(*hits, geom, 0, out=fwd)
         bwd()
 
+    # smoothing: the forward pass writes its filtered state after every entry
+    max_len = 26
+    ck = torch.empty(28, n * (max_len - 1), dtype=dt, device=dev)
+    fwd_ck = K.fit_outputs(n, dt, dev)
+    ctx.seed_fit_tracks(*hits, geom, 0, checkpoints=ck, seg=1, max_len=max_len, out=fwd_ck)
+    sm = dict(state=torch.empty(6, max_len, n, dtype=dt, device=dev), cov=torch.empty(21, max_len, n, dtype=dt,
+                                                                                         device=dev))
+    out_s = K.fit_outputs(n, dt, dev)
+
+    def smooth():
+        ctx.smooth_tracks(fwd_ck, ck, *hits, geom, cov_scale=K.BACKWARD_COV_SCALE, max_len=max_len, out=out_s,
+                          smooth=sm)
+
+    def smooth_step():
+        ctx.seed_fit_tracks(*hits, geom, 0, checkpoints=ck, seg=1, max_len=max_len, out=fwd_ck)
+        smooth()
+
     k = args.steps if steps is None else steps
     ms_b = time_loop(bwd, k, args.warmup)
     ms_s = time_loop(step, k, args.warmup)
+    ms_sm = time_loop(smooth, k, args.warmup)
+    ms_sms = time_loop(smooth_step, k, args.warmup)
     flops = algorithmic_flops(ev)
     tf = flops / (ms_b * 1e-3) / 1e12
     st = out["status"].cpu().numpy()
+    smoothed = int(ev.n_hits - n)   # every entry but the last of each track (the last keeps its filtered state)
+    tf_sm = (flops + smoothed * FLOP_SMOOTH_COMBINE) / (ms_sm * 1e-3) / 1e12
     return {"tracks": n, "layers": ev.geometry.n_layers, "cov_scale": K.BACKWARD_COV_SCALE, "ms_backward": ms_b,
             "tracks_per_s_backward": n / (ms_b * 1e-3), "ms_forward_backward_step": ms_s,
             "achieved_tflops_backward": tf, "frac_fp32_peak_backward": tf / FP32_PEAK_TFLOPS,
-            "kernel": "backward_kernel<float, 2>", "refitted": int(((st & 64) == 0).sum())}
+            "kernel": "backward_kernel<float, 2>", "refitted": int(((st & 64) == 0).sum()),
+            "ms_smooth": ms_sm, "tracks_per_s_smooth": n / (ms_sm * 1e-3),
+            "ms_forward_with_checkpoints_and_smooth_step": ms_sms, "achieved_tflops_smooth": tf_sm,
+            "smooth_kernel": "backward_kernel<float, 2, true> + smooth_combine_kernel<float> (FP64 5x5 combination per entry)"}
 
 
 def bench_search(ctx, K, args, sample=300):

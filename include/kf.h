@@ -259,12 +259,15 @@ int kf_backward_fit(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
  * seg = 1 and the same max_len (slot m holds the filtered state after the
  * track's first valid entry + m).  smooth_state [6][ld * max_len],
  * smooth_cov [21][ld * max_len] (device, caller-owned): the smoothed state of
- * entry r (0-based within track t) at [i][r * ld + t]; entries that are not
- * smoothed (before the first valid entry, beyond max_len, of tracks not
- * refitted, after a stop of the backward pass) are not written.  An entry
- * whose 5x5 system is not positive definite is not written either, and its
- * track gets KF_TRK_COV_NOT_PSD.  KF_ERR_ARG as kf_backward_fit, and for a
- * missing or aliased smoothing buffer. */
+ * entry r (0-based within track t) at [i][r * ld + t].  Entries before the
+ * first valid one, beyond max_len or of tracks not refitted are not written;
+ * entries of a refitted track that its backward pass did not reach (it
+ * stopped), or whose 5x5 system is not positive definite (the track then
+ * gets KF_TRK_COV_NOT_PSD), hold NaN in smooth_state[0].  The smoothing runs
+ * as two launches: the backward pass stores its prediction at every entry,
+ * then one thread per (entry, track) combines it with the filtered state.
+ * KF_ERR_ARG as kf_backward_fit, and for a missing or aliased smoothing
+ * buffer. */
 int kf_smooth_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                      const void *state_in, const void *cov_in, const int8_t *charge_in,
                      const uint32_t *fwd_status, const void *fwd_checkpoints,

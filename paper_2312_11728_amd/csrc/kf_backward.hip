@@ -15,17 +15,33 @@ namespace {
 
 constexpr int kBwdBlock = 256;
 
-// One step of the smoothing backward pass (backward index k >= 1, entry r of
-// the track): propagation to the entry's layer without its material; there
-// the backward prediction, turned outward, is combined with the forward
-// filtered state of the entry (both describe the track just outside the
-// layer) and the smoothed state stored; then the layer's material and, for a
-// valid hit, the update.  The rest as in fit_entry (layer check, backup,
-// roll-back of a non-finite step).
+// The backward prediction at an entry, turned outward (phi - pi, pi - theta;
+// the theta terms of the covariance change sign), stored in the smoothed-state
+// arrays as propagate() hands it over, before the layer's material.
 template <typename T>
-__device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, int64_t t, int r, int k0, int lay,
-                                   int& prev, bool valid, const T m[3], const T V[6], T p[6], T c[21], int& q,
-                                   uint32_t& st, T& chi2, int& nval, T* bk, int bk_stride) {
+struct StorePrediction {
+  T* so;
+  T* co;
+  int64_t os;
+  KF_HD void operator()(const T* p, const T* c) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) so[i * os] = p[i];
+    so[4 * os] = wrap_phi(p[4] + T(kPi));
+    so[5 * os] = T(kPi) - p[5];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) co[i * os] = (i >= 15 && i < 20) ? -c[i] : c[i];
+  }
+};
+
+// One step of the smoothing backward pass (backward index k >= 1, entry r of
+// the track): the step of the plain backward pass, with the backward
+// prediction stored on the way (the combination with the forward filtered
+// state is a separate, entry-parallel pass: smooth_combine_kernel).  The rest
+// as in fit_entry (layer check, backup, roll-back of a non-finite step).
+template <typename T>
+__device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, int64_t t, int r, int lay, int& prev,
+                                   bool valid, const T m[3], const T V[6], T p[6], T c[21], int& q, uint32_t& st,
+                                   T& chi2, int& nval, T* bk, int bk_stride) {
   const FitArgs<T>& a = b.f;
   if (lay < 0 || lay >= g.n_layers) {
     st |= TRK_BAD_INPUT;
@@ -38,39 +54,13 @@ __device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, i
   const int qq = q;
   uint32_t sst = 0;
   const int kind = g.kind[lay];
-  if (!propagate(p, c, q, kind, g.pos[lay], g.x0[lay], lay == prev, false, g.bz, g.mass, sst)) {
+  const int64_t at = int64_t(r) * a.ld + t;
+  const StorePrediction<T> store{b.smooth_state + at, b.smooth_cov + at, a.ld * int64_t(a.max_len)};
+  if (!propagate(p, c, q, kind, g.pos[lay], g.x0[lay], lay == prev, true, g.bz, g.mass, sst, static_cast<T*>(nullptr),
+                 static_cast<PropTape<T>*>(nullptr), store)) {
     st |= sst;
     return false;
   }
-  {
-    T pb[6], cb[21];
-    int qb = q;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) pb[i] = p[i];
-#pragma unroll
-    for (int i = 0; i < 21; ++i) cb[i] = c[i];
-    reverse_direction(pb, cb, qb);
-    const int64_t ld = a.ld, cst = ld * int64_t(b.n_seg_f);
-    const T* f = b.fwd_ckpt + int64_t(r - k0) * ld + t;
-    T pf[6], cf[21];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) pf[i] = f[i * cst];
-#pragma unroll
-    for (int i = 0; i < 21; ++i) cf[i] = f[(6 + i) * cst];
-    T ps[6], cs[21];
-    if (combine_on_surface(pf, cf, pb, cb, kind, g.pos[lay], ps, cs)) {
-      const int64_t os = ld * int64_t(a.max_len);
-      T* so = b.smooth_state + int64_t(r) * ld + t;
-      T* co = b.smooth_cov + int64_t(r) * ld + t;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) so[i * os] = ps[i];
-#pragma unroll
-      for (int i = 0; i < 21; ++i) co[i * os] = cs[i];
-    } else {
-      sst |= TRK_COV_NOT_PSD;
-    }
-  }
-  add_material_here(p, c, kind, g.x0[lay], g.mass, sst);
   T c2 = T(0);
   if (valid) {
     T mm[3];
@@ -92,6 +82,55 @@ __device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, i
   nval += valid ? 1 : 0;
   prev = lay;
   return true;
+}
+
+// Smoothing, entry-parallel: thread (r, t) combines the backward prediction
+// stored at entry r of track t with the forward filtered state of that entry
+// (forward checkpoint slot r - k0) and overwrites it with the smoothed state.
+// Entries from the first valid one to the last but one of refitted tracks
+// whose prediction is finite; the last entry already holds its filtered state.
+template <typename T>
+__global__ void __launch_bounds__(256, 2) smooth_combine_kernel(BwdArgs<T> b, GeomArgs g) {
+  const FitArgs<T>& a = b.f;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int r = int(blockIdx.y);
+  if (t >= a.n) return;
+  if (a.trk_status[t] & TRK_BAD_INPUT) return;   // not refitted
+  const int64_t e0 = a.hit_offsets[t];
+  int n_e = int(a.hit_offsets[t + 1] - e0);
+  if (n_e > a.max_len) n_e = a.max_len;
+  if (r >= n_e - 1) return;
+  int k0 = 0;
+  while (k0 <= r && a.hit_valid[e0 + k0] == 0) ++k0;
+  if (r < k0) return;
+  const int64_t os = a.ld * int64_t(a.max_len), at = int64_t(r) * a.ld + t;
+  T* so = b.smooth_state + at;
+  T* co = b.smooth_cov + at;
+  T pb[6], cb[21];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) pb[i] = so[i * os];
+  if (!(pb[0] == pb[0])) return;   // NaN: the backward pass stopped before this entry
+#pragma unroll
+  for (int i = 0; i < 21; ++i) cb[i] = co[i * os];
+  const int64_t cst = a.ld * int64_t(b.n_seg_f);
+  const T* f = b.fwd_ckpt + int64_t(r - k0) * a.ld + t;
+  T pf[6], cf[21];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) pf[i] = f[i * cst];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) cf[i] = f[(6 + i) * cst];
+  const int lay = a.hit_layer[e0 + r];
+  if (lay < 0 || lay >= g.n_layers) return;
+  T ps[6], cs[21];
+  if (combine_on_surface(pf, cf, pb, cb, int(g.kind[lay]), T(g.pos[lay]), ps, cs)) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) so[i * os] = ps[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) co[i * os] = cs[i];
+  } else {
+    so[0] = k_nan<T>();
+    atomicOr(&a.trk_status[t], uint32_t(TRK_COV_NOT_PSD));
+  }
 }
 
 // Backward fit of tracks [w0, w0 + 64) (one wave; every lane must call it).
@@ -125,6 +164,14 @@ __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g,
     if (run) {
       last = e0 + n_e - 1;
       len = n_e - k0;
+      if constexpr (SMOOTH) {
+        // the last entry's smoothed state is its forward filtered state: the input
+        const int64_t os = a.ld * int64_t(a.max_len), at = int64_t(n_e - 1) * a.ld + t;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) b.smooth_state[i * os + at] = p[i];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) b.smooth_cov[i * os + at] = c[i];
+      }
 #pragma unroll
       for (int i = 0; i < 21; ++i) c[i] *= b.cov_scale;
       // the surface of the last entry's layer, imposed again: scaled up, the
@@ -186,23 +233,19 @@ __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g,
       for (int x = 0; x < 3; ++x) m[x] = sb.v[x][jj][lane];
 #pragma unroll
       for (int x = 0; x < 6; ++x) V[x] = sb.v[3 + x][jj][lane];
-      if constexpr (SMOOTH) {
-        const int r = n_e - 1 - k;
-        if (k == 0) {
-          // the last entry's smoothed state is its forward filtered state
-          const int64_t os = a.ld * int64_t(a.max_len);
-#pragma unroll
-          for (int i = 0; i < 6; ++i) b.smooth_state[i * os + int64_t(r) * a.ld + t] = a.seed_state[i * a.ld + t];
-#pragma unroll
-          for (int i = 0; i < 21; ++i) b.smooth_cov[i * os + int64_t(r) * a.ld + t] = a.seed_cov[i * a.ld + t];
-          live = fit_entry(a, g, static_cast<const T*>(nullptr), t, k, lay, prev, valid, m, V, p, c, q, st, chi2,
-                           nval, bk, bk_stride);
-        } else {
-          live = smooth_step(b, g, t, r, k0, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
-        }
-      } else {
+      const int r = n_e - 1 - k;   // entry index within the track
+      if (SMOOTH && k > 0)
+        live = smooth_step(b, g, t, r, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
+      else
         live = fit_entry(a, g, static_cast<const T*>(nullptr), t, k, lay, prev, valid, m, V, p, c, q, st, chi2,
                          nval, bk, bk_stride);
+      if (SMOOTH && !live) {
+        // the pass stops here: the entries it will not reach get no
+        // prediction (NaN), so that the combination skips them; a step that
+        // failed in its update had stored its prediction already; a failed
+        // first step or a bad layer id leaves the track unsmoothed
+        const int first = (k == 0 || (st & TRK_BAD_INPUT)) ? n_e - 2 : ((st & TRK_NONFINITE) ? r - 1 : r);
+        for (int rr = first; rr >= k0; --rr) b.smooth_state[int64_t(rr) * a.ld + t] = k_nan<T>();
       }
     }
     wave_sync();   // every lane has read the chunk before the next one is staged
@@ -214,8 +257,7 @@ __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g,
 }
 
 // WAVES: waves per SIMD the register allocation must allow (2 in FP32, 1 in
-// FP64, the forward fit's tuned choices; 1 with smoothing, whose FP64 5x5
-// combination needs the registers).
+// FP64, the forward fit's tuned choices).
 template <typename T, int WAVES, bool SMOOTH>
 __global__ void __launch_bounds__(kBwdBlock, WAVES) backward_kernel(BwdArgs<T> b, GeomArgs g) {
   constexpr int J = stage_entries<T, WAVES>();
@@ -234,9 +276,14 @@ template <typename T>
 hipError_t launch_backward(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s) {
   if (a.f.n == 0) return hipSuccess;
   const int64_t grid = (a.f.n + kBwdBlock - 1) / kBwdBlock;
-  if (a.smooth_state)
-    hipLaunchKernelGGL((backward_kernel<T, 1, true>), dim3(unsigned(grid)), dim3(kBwdBlock), 0, s, a, g);
-  else
+  if (a.smooth_state) {
+    hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, true>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
+                       s, a, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(smooth_combine_kernel<T>, dim3(unsigned((a.f.n + 255) / 256), unsigned(a.f.max_len)), dim3(256),
+                       0, s, a, g);
+  } else
     hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, false>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
                        s, a, g);
   return hipGetLastError();

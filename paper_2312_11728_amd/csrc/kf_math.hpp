@@ -551,9 +551,17 @@ struct PropTape {
 // Propagate (p, c) to the surface (kind, pos) and add its scattering noise.
 // Returns false (p, c untouched) if there is no admissible crossing.  If
 // `tape` is given, the intermediates needed by the reverse pass are stored.
-template <typename T>
+// The hook propagate() calls with the state on the surface just before the
+// layer's material is added (the default does nothing).
+struct NoPreMaterial {
+  template <typename T>
+  KF_HD void operator()(const T*, const T*) const {}
+};
+
+template <typename T, typename PreMaterial = NoPreMaterial>
 KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool same, bool material, T bz,
-                     T mass, uint32_t& st, T* path = nullptr, PropTape<T>* tape = nullptr) {
+                     T mass, uint32_t& st, T* path = nullptr, PropTape<T>* tape = nullptr,
+                     const PreMaterial& pre = PreMaterial()) {
   const T dw_dipt = -T(q) * T(kCLight) * bz;
   const T w = dw_dipt * p[3];
   T sphi, cphi, sth, cth;
@@ -700,6 +708,7 @@ KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool 
   p[1] = y;
   p[2] = hp.z;
   p[4] = wrap_phi(hp.phi);
+  pre(p, c);
   if (material) {
     // Highland angle at the propagated state; x/X0 scaled by 1/|cos(incidence)|
     const T ca = (kind == 0) ? k_abs(sth * (cphm * x + sphm * y) * rinv) : k_abs(cth);
