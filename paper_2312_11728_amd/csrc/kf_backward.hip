@@ -15,6 +15,152 @@ namespace {
 
 constexpr int kBwdBlock = 256;
 
+// Two estimates of one state on a surface, from disjoint sets of hits,
+// combined (two-filter smoother): with the gain K = C_f (C_f + C_b)^+,
+// x = x_f + K (x_b - x_f) and C = (I - K) C_f (I - K)^T + K C_b K^T (equal to
+// C_f - C_f (C_f + C_b)^+ C_f, without its cancellation where C_f is much
+// larger than the result).  ^+ inverts on the 5 directions the state can
+// move in (the surface normal is a null vector of both): the frame
+// (u, w, ipt, phi, theta) with u, w the unit position directions along the
+// surface (barrel: the tangent (-y, x)/R and z; disk: x and y), so
+// K = C_f B (B^T (C_f + C_b) B)^-1 B^T.  The 5x5 system is solved by
+// Cholesky in FP64, with divisions only on its 5 pivots.  Returns false
+// (outputs untouched) when it is not positive definite.
+template <typename T>
+__device__ inline bool combine_on_surface(const T pf[6], const T cf[21], const T pb[6], const T cb[21], int kind,
+                                          T pos, T ps[6], T cs[21]) {
+  double u[3], w[3];
+  if (kind == 1) {
+    u[0] = 1.0; u[1] = 0.0; u[2] = 0.0;
+    w[0] = 0.0; w[1] = 1.0; w[2] = 0.0;
+  } else {
+    const double ri = 1.0 / double(pos);
+    u[0] = -double(pf[1]) * ri; u[1] = double(pf[0]) * ri; u[2] = 0.0;
+    w[0] = 0.0; w[1] = 0.0; w[2] = 1.0;
+  }
+  // S = C_f + C_b; G = C_f B (6 x 5); M = B^T S B (5 x 5, packed)
+  double S[21];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) S[i] = double(cf[i]) + double(cb[i]);
+  double G[6][5];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double gu = 0.0, gw = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      gu += double(cf[sym(i, k)]) * u[k];
+      gw += double(cf[sym(i, k)]) * w[k];
+    }
+    G[i][0] = gu;
+    G[i][1] = gw;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) G[i][2 + k] = double(cf[sym(i, 3 + k)]);
+  }
+  double Su[6], Sw[6];   // S u, S w over the position block
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    Su[i] = 0.0;
+    Sw[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Su[i] += S[sym(i, k)] * u[k];
+      Sw[i] += S[sym(i, k)] * w[k];
+    }
+  }
+  double M[5][5];
+  M[0][0] = u[0] * Su[0] + u[1] * Su[1] + u[2] * Su[2];
+  M[1][0] = w[0] * Su[0] + w[1] * Su[1] + w[2] * Su[2];
+  M[1][1] = w[0] * Sw[0] + w[1] * Sw[1] + w[2] * Sw[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    M[2 + k][0] = Su[3 + k];
+    M[2 + k][1] = Sw[3 + k];
+#pragma unroll
+    for (int l = 0; l <= k; ++l) M[2 + k][2 + l] = S[sym(3 + k, 3 + l)];
+  }
+  // Cholesky M = L L^T (lower triangle in place), inverse pivots kept
+  double il[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    double dj = M[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= M[j][k] * M[j][k];
+    if (!(dj > 0.0)) return false;
+    il[j] = 1.0 / sqrt(dj);
+#pragma unroll
+    for (int i = j + 1; i < 5; ++i) {
+      double v = M[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= M[i][k] * M[j][k];
+      M[i][j] = v * il[j];
+    }
+  }
+  // W = G M^-1 (each row of G solved in place), then the gain K = W B^T
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+      double v = G[i][a];
+#pragma unroll
+      for (int k = 0; k < a; ++k) v -= M[a][k] * G[i][k];
+      G[i][a] = v * il[a];
+    }
+#pragma unroll
+    for (int a = 4; a >= 0; --a) {
+      double v = G[i][a];
+#pragma unroll
+      for (int k = a + 1; k < 5; ++k) v -= M[k][a] * G[i][k];
+      G[i][a] = v * il[a];
+    }
+  }
+  double K[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) K[i][k] = G[i][0] * u[k] + G[i][1] * w[k];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) K[i][3 + l] = G[i][2 + l];
+  }
+  // x = x_f + K (x_b - x_f)
+  double d[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) d[i] = double(pb[i]) - double(pf[i]);
+  d[4] = wrap_phi(d[4]);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double v = double(pf[i]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v += K[i][k] * d[k];
+    ps[i] = T(v);
+  }
+  ps[4] = wrap_phi(ps[4]);
+  // C = (I - K) C_f (I - K)^T + K C_b K^T, row by row: with t1 = row i of
+  // (I - K) C_f and t2 = row i of K C_b, C_ij = t1_j - t1 . K_j + t2 . K_j
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    double t1[6], t2[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      double a1 = double(cf[sym(i, j)]), a2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        a1 -= K[i][k] * double(cf[sym(k, j)]);
+        a2 += K[i][k] * double(cb[sym(k, j)]);
+      }
+      t1[j] = a1;
+      t2[j] = a2;
+    }
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double v = t1[j];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v += (t2[k] - t1[k]) * K[j][k];
+      cs[sym(i, j)] = T(v);
+    }
+  }
+  return true;
+}
+
 // The backward prediction at an entry, turned outward (phi - pi, pi - theta;
 // the theta terms of the covariance change sign), stored in the smoothed-state
 // arrays as propagate() hands it over, before the layer's material.
