@@ -232,3 +232,77 @@ def backward_probes(ev, dtype, run, ref, tol, seed=99):
 
 def rounded_forward(o, dtype):
     return dict(p=rounded(o["p"], dtype), C=rounded(o["C"], dtype), q=o["q"], status=o["status"])
+
+
+# ---- smoothing ------------------------------------------------------------------------
+
+def first_valid(ev):
+    off = ev.hit_offsets
+    return np.array([int(np.argmax(ev.hit_valid[off[t]:off[t + 1]])) for t in range(ev.n_tracks)])
+
+
+def forward_checkpoints(ev, rec, dtype, max_len):
+    """The seg = 1 checkpoints the GPU smoother reads, from the oracle forward
+    fit's recorded filtered states (rounded to dtype): slot m of track t holds
+    the filtered state after entry k0_t + m."""
+    n = ev.n_tracks
+    nseg = max(1, max_len - 1)
+    ck = np.zeros((28, nseg, n))
+    off, lens, k0 = ev.hit_offsets, ev.lengths(), first_valid(ev)
+    pe, Ce, qe = rec["pe"].numpy(), rec["Ce"].numpy(), rec["qe"].numpy()
+    for t in range(n):
+        for m in range(min(lens[t] - k0[t] - 1, nseg)):
+            e = off[t] + k0[t] + m
+            ck[:6, m, t] = pe[e]
+            ck[6:27, m, t] = [Ce[e][i, j] for i, j in [(i, j) for i in range(6) for j in range(i + 1)]]
+            ck[27, m, t] = qe[e]
+    return rounded(ck.reshape(28, nseg * n), dtype)
+
+
+def oracle_forward_recorded(ev, dtype, seed_mode, hit_pos=None, state_round=None, state_jitter=None):
+    hp = rounded(ev.hit_pos, dtype) if hit_pos is None else np.asarray(hit_pos, np.float64)
+    sp, sC, sq, _ = O.make_seeds(ev.hit_offsets, ev.hit_valid, hp, ev.geometry.bz, mode=seed_mode)
+    return O.fit_tracks(sp, sC, sq, ev.hit_offsets, ev.hit_layer, ev.hit_valid, torch.tensor(hp),
+                        rounded(ev.hit_cov, dtype), ev.geometry, state_round=state_round, state_jitter=state_jitter,
+                        record=True)
+
+
+def oracle_smooth(ev, dtype, rec, hit_pos=None, state_round=None, state_jitter=None):
+    """Oracle smoothing from the recorded forward fit `rec`, its inputs rounded to dtype."""
+    hp = rounded(ev.hit_pos, dtype) if hit_pos is None else np.asarray(hit_pos, np.float64)
+    r = lambda x: torch.tensor(rounded(x.numpy(), dtype))
+    return O.backward_fit(r(rec["p"]), r(rec["C"]), rec["q"], rec["status"], ev.hit_offsets, ev.hit_layer,
+                          ev.hit_valid, torch.tensor(hp), rounded(ev.hit_cov, dtype), ev.geometry,
+                          cov_scale=BACKWARD_SCALE, state_round=state_round, state_jitter=state_jitter,
+                          smooth_from=dict(pe=r(rec["pe"]), Ce=r(rec["Ce"])))
+
+
+def gpu_smooth(c, kf, ev, dtype, rec, max_len=26):
+    dev = c.device
+    t = kf.event_tensors(ev, dtype, dev)
+    geom = kf.Geometry.from_toy(ev.geometry)
+    r = lambda x: rounded(x.numpy(), dtype)
+    fwd = dict(state=torch.tensor(np.ascontiguousarray(r(rec["p"]).T), dtype=dtype, device=dev),
+               cov=torch.tensor(np.ascontiguousarray(pack21(r(rec["C"]))), dtype=dtype, device=dev),
+               charge=torch.tensor(rec["q"].numpy().astype(np.int8), device=dev),
+               status=torch.tensor(rec["status"].numpy().astype(np.int32), device=dev))
+    ck = torch.tensor(forward_checkpoints(ev, rec, dtype, max_len), dtype=dtype, device=dev)
+    out, sm = c.smooth_tracks(fwd, ck, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"],
+                              geom, cov_scale=BACKWARD_SCALE, max_len=max_len)
+    torch.cuda.synchronize()
+    return outputs_np(out), sm["state"].double().cpu().numpy(), sm["cov"].double().cpu().numpy()
+
+
+def per_entry(ev, sm_state):
+    """GPU smoothed states [6, max_len, n] -> [n_hits, 6] by CSR entry."""
+    off, lens = ev.hit_offsets, ev.lengths()
+    t = np.repeat(np.arange(ev.n_tracks), lens)
+    r = np.arange(ev.n_hits) - off[t]
+    return sm_state[:, r, t].T
+
+
+def smooth_errors(ev, ps_a, ps_b):
+    """Per-track maximum over entries of the scaled parameter error (NaN where either is NaN)."""
+    ep = param_error(ps_a, ps_b).max(axis=1)
+    ep = np.where(np.isnan(ep), 0.0, ep)
+    return np.maximum.reduceat(ep, ev.hit_offsets[:-1]) if ev.n_hits else np.zeros(ev.n_tracks)

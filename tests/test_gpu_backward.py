@@ -24,8 +24,9 @@ import torch
 from oracle import kf_oracle as O
 from toygen import generate, subset, workloads
 
-from parity import (BACKWARD_SCALE, backward_probes, compare_fit, gpu_backward, oracle_backward, oracle_fit,
-                    outputs_np, pack21, param_error, rounded, rounded_forward)
+from parity import (BACKWARD_SCALE, backward_probes, compare_fit, gpu_backward, gpu_smooth,
+                    oracle_backward, oracle_fit, oracle_forward_recorded, oracle_smooth, outputs_np,
+                    param_error, per_entry, rounded, rounded_forward, smooth_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -185,81 +186,9 @@ def test_backward_is_deterministic(ctx, kf):
 
 # ---- smoothing -----------------------------------------------------------------------
 
-def _first_valid(ev):
-    off = ev.hit_offsets
-    return np.array([int(np.argmax(ev.hit_valid[off[t]:off[t + 1]])) for t in range(ev.n_tracks)])
-
-
-def _forward_checkpoints(ev, rec, dtype, max_len):
-    """The seg = 1 checkpoints the GPU smoother reads, from the oracle forward
-    fit's recorded filtered states (rounded to dtype): slot m of track t holds
-    the filtered state after entry k0_t + m."""
-    n = ev.n_tracks
-    nseg = max(1, max_len - 1)
-    ck = np.zeros((28, nseg, n))
-    off, lens, k0 = ev.hit_offsets, ev.lengths(), _first_valid(ev)
-    pe, Ce, qe = rec["pe"].numpy(), rec["Ce"].numpy(), rec["qe"].numpy()
-    for t in range(n):
-        for m in range(min(lens[t] - k0[t] - 1, nseg)):
-            e = off[t] + k0[t] + m
-            ck[:6, m, t] = pe[e]
-            ck[6:27, m, t] = [Ce[e][i, j] for i, j in [(i, j) for i in range(6) for j in range(i + 1)]]
-            ck[27, m, t] = qe[e]
-    return rounded(ck.reshape(28, nseg * n), dtype)
-
-
-def _oracle_forward_recorded(ev, dtype, seed_mode, hit_pos=None, state_round=None, state_jitter=None):
-    hp = rounded(ev.hit_pos, dtype) if hit_pos is None else np.asarray(hit_pos, np.float64)
-    sp, sC, sq, _ = O.make_seeds(ev.hit_offsets, ev.hit_valid, hp, ev.geometry.bz, mode=seed_mode)
-    return O.fit_tracks(sp, sC, sq, ev.hit_offsets, ev.hit_layer, ev.hit_valid, torch.tensor(hp),
-                        rounded(ev.hit_cov, dtype), ev.geometry, state_round=state_round, state_jitter=state_jitter,
-                        record=True)
-
-
-def _oracle_smooth(ev, dtype, rec, hit_pos=None, state_round=None, state_jitter=None):
-    """Oracle smoothing from the recorded forward fit `rec`, its inputs rounded to dtype."""
-    hp = rounded(ev.hit_pos, dtype) if hit_pos is None else np.asarray(hit_pos, np.float64)
-    r = lambda x: torch.tensor(rounded(x.numpy(), dtype))
-    return O.backward_fit(r(rec["p"]), r(rec["C"]), rec["q"], rec["status"], ev.hit_offsets, ev.hit_layer,
-                          ev.hit_valid, torch.tensor(hp), rounded(ev.hit_cov, dtype), ev.geometry,
-                          cov_scale=BACKWARD_SCALE, state_round=state_round, state_jitter=state_jitter,
-                          smooth_from=dict(pe=r(rec["pe"]), Ce=r(rec["Ce"])))
-
-
-def _gpu_smooth(c, kf, ev, dtype, rec, max_len=26):
-    dev = c.device
-    t = kf.event_tensors(ev, dtype, dev)
-    geom = kf.Geometry.from_toy(ev.geometry)
-    r = lambda x: rounded(x.numpy(), dtype)
-    fwd = dict(state=torch.tensor(np.ascontiguousarray(r(rec["p"]).T), dtype=dtype, device=dev),
-               cov=torch.tensor(np.ascontiguousarray(pack21(r(rec["C"]))), dtype=dtype, device=dev),
-               charge=torch.tensor(rec["q"].numpy().astype(np.int8), device=dev),
-               status=torch.tensor(rec["status"].numpy().astype(np.int32), device=dev))
-    ck = torch.tensor(_forward_checkpoints(ev, rec, dtype, max_len), dtype=dtype, device=dev)
-    out, sm = c.smooth_tracks(fwd, ck, t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"],
-                              geom, cov_scale=BACKWARD_SCALE, max_len=max_len)
-    torch.cuda.synchronize()
-    return outputs_np(out), sm["state"].double().cpu().numpy(), sm["cov"].double().cpu().numpy()
-
-
-def _per_entry(ev, sm_state):
-    """GPU smoothed states [6, max_len, n] -> [n_hits, 6] by CSR entry."""
-    off, lens = ev.hit_offsets, ev.lengths()
-    t = np.repeat(np.arange(ev.n_tracks), lens)
-    r = np.arange(ev.n_hits) - off[t]
-    return sm_state[:, r, t].T
-
-
-def _smooth_errors(ev, ps_a, ps_b):
-    """Per-track maximum over entries of the scaled parameter error (NaN where either is NaN)."""
-    ep = param_error(ps_a, ps_b).max(axis=1)
-    ep = np.where(np.isnan(ep), 0.0, ep)
-    return np.maximum.reduceat(ep, ev.hit_offsets[:-1]) if ev.n_hits else np.zeros(ev.n_tracks)
-
-
 def _smooth_case(c, kf, ev, dtype, seed_mode, tol, max_bad_frac, tail_frac):
-    rec = _oracle_forward_recorded(ev, dtype, seed_mode)
-    o = _oracle_smooth(ev, dtype, rec)
+    rec = oracle_forward_recorded(ev, dtype, seed_mode)
+    o = oracle_smooth(ev, dtype, rec)
     ops = o["ps"].numpy()
     # conditioning probes on the smoothed states
     rng = np.random.default_rng(7)
@@ -272,17 +201,17 @@ def _smooth_case(c, kf, ev, dtype, seed_mode, tol, max_bad_frac, tail_frac):
                   dict(state_jitter=4e-16)]
     bad = np.zeros(ev.n_tracks, bool)
     for kw in probes:
-        rec2 = _oracle_forward_recorded(ev, dtype, seed_mode, **kw)
-        o2 = _oracle_smooth(ev, dtype, rec2, **kw)
-        bad |= _smooth_errors(ev, o2["ps"].numpy(), ops) > 0.5 * tol[0]
+        rec2 = oracle_forward_recorded(ev, dtype, seed_mode, **kw)
+        o2 = oracle_smooth(ev, dtype, rec2, **kw)
+        bad |= smooth_errors(ev, o2["ps"].numpy(), ops) > 0.5 * tol[0]
         bad |= param_error(o2["p"].numpy(), o["p"].numpy()).max(axis=1) > 0.5 * tol[0]
         bad |= o2["status"].numpy() != o["status"].numpy()
     assert bad.mean() <= max(max_bad_frac, 0.005), bad.mean()
-    g, gstate, gcov = _gpu_smooth(c, kf, ev, dtype, rec)
+    g, gstate, gcov = gpu_smooth(c, kf, ev, dtype, rec)
     ob = dict(p=o["p"].numpy(), C=o["C"].numpy(), q=o["q"].numpy(), chi2=o["chi2"].numpy(), ndf=o["ndf"].numpy(),
               status=o["status"].numpy())
     s = compare_fit(g, ob, tol[0], tol[1], ~bad, tail_frac=tail_frac)
-    gps = _per_entry(ev, gstate)
+    gps = per_entry(ev, gstate)
     ok_e = np.repeat(~bad, ev.lengths())
     # the same entries are smoothed
     assert np.array_equal(np.isnan(gps[ok_e]).any(axis=1), np.isnan(ops[ok_e]).any(axis=1))
@@ -292,7 +221,7 @@ def _smooth_case(c, kf, ev, dtype, seed_mode, tol, max_bad_frac, tail_frac):
     assert over.mean() <= max(tail_frac, 0.0) + 1e-12 and (ep <= 10 * tol[0]).all(), (ep.max(), over.sum())
     # covariance on the surface (5 coordinates), in correlation units
     e = np.nonzero(have)[0]
-    gC = np.stack([sym_unpack_from_packed(_per_entry(ev, gcov)[e])])[0]
+    gC = np.stack([sym_unpack_from_packed(per_entry(ev, gcov)[e])])[0]
     kind = torch.tensor(ev.geometry.kind[ev.hit_layer[e]], dtype=torch.int64)
     pos = torch.tensor(ev.geometry.pos[ev.hit_layer[e]], dtype=torch.float64)
     B = O.surface_frame(torch.tensor(ops[e]), kind, pos).numpy()
