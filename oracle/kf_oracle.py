@@ -671,6 +671,11 @@ BACKWARD_COV_SCALE = 100.0
 # stopped before its last entry); such a track keeps its input and gets
 # NOT_REFITTED, the value of the C interface's bad-input bit
 NOT_REFITTED = 64
+# final fit: at least one hit was rejected as an outlier
+OUTLIER = 128
+# the final fit's chi2 cut for one hit (3 measured coordinates, one of them
+# the layer's thickness; the paper gives no value)
+FINAL_CHI2_CUT = 30.0
 
 
 def reverse_direction(p, C, q):
@@ -748,7 +753,8 @@ def combine_on_surface(pf, Cf, pb, Cb, kind, pos):
 
 
 def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
-                 cov_scale=BACKWARD_COV_SCALE, state_round=None, state_jitter=None, smooth_from=None):
+                 cov_scale=BACKWARD_COV_SCALE, state_round=None, state_jitter=None, smooth_from=None,
+                 chi2_cut=None):
     """Backward fit (Sec. 2.2, step 4): every track is traversed again, from
     its last entry back to its first valid entry, and refitted.
 
@@ -779,8 +785,15 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     the layer, and combine_on_surface combines them.  The last entry's
     smoothed state is its forward filtered state.  With smoothing, the
     backward pass propagates without material, combines, then adds the
-    layer's material (the same arithmetic as propagate with material).  Returns dict(p, C, q, chi2,
-    ndf, status): chi2 and ndf (= 2 * used hits - 5) of the backward pass."""
+    layer's material (the same arithmetic as propagate with material).
+
+    chi2_cut: None, or the final fit's outlier rejection: a valid hit whose
+    chi2 against the backward prediction (the increment the update would
+    add) exceeds chi2_cut is not used; its entry is taken as a hole (the
+    layer's material only), marked in outlier [nh] (bool), and the track gets
+    OUTLIER.  A NaN chi2 is not above the cut (the step then fails as
+    non-finite).  Returns dict(p, C, q, chi2, ndf, status): chi2 and ndf
+    (= 2 * used hits - 5) of the backward pass."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
     val_all = torch.as_tensor(hit_valid, dtype=torch.int64)
@@ -820,6 +833,8 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     status = torch.zeros(n, dtype=torch.int64)
     alive = run.clone()
     prev_e = last.clone()
+    if chi2_cut is not None:
+        outlier = torch.zeros(lay_all.shape[0], dtype=torch.bool)
     for j in range(maxlen):
         e = last - j
         act = alive & (e >= k0)
@@ -861,6 +876,10 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
         good = (st & NO_CROSSING) == 0
         valid = (val_all[ei] == 1) & good
         pu, Cu, qu, c2, st_u = update(pp2, CC2, qq, m_all[ei], V_all[ei])
+        if chi2_cut is not None:
+            rej = valid & (c2 > chi2_cut)
+            valid = valid & ~rej
+            st = st | torch.where(rej, OUTLIER, 0)
         pn = torch.where(valid[:, None], pu, pp2)
         Cn = torch.where(valid[:, None, None], Cu, CC2)
         qn = torch.where(valid, qu, qq)
@@ -886,6 +905,9 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
         status = status.index_put((idx,), status[idx] | st)
         alive = alive.index_put((idx,), keep)
         prev_e = prev_e.index_put((idx,), ei)
+        if chi2_cut is not None:
+            k = torch.nonzero(rej & keep)[:, 0]
+            outlier = outlier.index_put((ei[k],), torch.ones_like(k, dtype=torch.bool))
     p, C, q = reverse_direction(p, C, q)
     # tracks not refitted keep their input
     p = torch.where(run[:, None], p, _t(fwd_p))
@@ -896,6 +918,8 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     if smooth:
         # the entries the backward pass reached
         out.update(ps=ps_all, Cs=Cs_all)
+    if chi2_cut is not None:
+        out.update(outlier=outlier)
     return out
 
 
