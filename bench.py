@@ -248,7 +248,10 @@ def bench_backward(ctx, K, ev, args, steps=None):
     forward result of the fused seed-and-fit call, then kf_backward_fit from
     it (covariance scaled by 100, hits staged through LDS per wave).  Timed
     alone and as a forward + backward step; the same algorithmic FLOP count
-    per entry as the forward pass (the same entries are stepped through)."""
+    per entry as the forward pass (the same entries are stepped through).
+    Then the smoother (forward fit with seg = 1 checkpoints, kf_smooth_tracks)
+    and the final fit with outlier rejection (kf_final_fit) on the same
+    batch."""
     import torch
     dev = torch.device("cuda", 0)
     dt = torch.float32
@@ -284,11 +287,20 @@ def bench_backward(ctx, K, ev, args, steps=None):
         ctx.seed_fit_tracks(*hits, geom, 0, checkpoints=ck, seg=1, max_len=max_len, out=fwd_ck)
         smooth()
 
+    # final fit with outlier rejection (the default cut) on the same batch
+    out_f = K.fit_outputs(n, dt, dev)
+    mask = torch.empty(ev.n_hits, dtype=torch.uint8, device=dev)
+
+    def final():
+        ctx.final_fit(fwd, *hits, geom, chi2_cut=K.FINAL_CHI2_CUT, cov_scale=K.BACKWARD_COV_SCALE, max_len=26,
+                      out=out_f, outlier=mask)
+
     k = args.steps if steps is None else steps
     ms_b = time_loop(bwd, k, args.warmup)
     ms_s = time_loop(step, k, args.warmup)
     ms_sm = time_loop(smooth, k, args.warmup)
     ms_sms = time_loop(smooth_step, k, args.warmup)
+    ms_f = time_loop(final, k, args.warmup)
     flops = algorithmic_flops(ev)
     tf = flops / (ms_b * 1e-3) / 1e12
     st = out["status"].cpu().numpy()
@@ -297,10 +309,15 @@ def bench_backward(ctx, K, ev, args, steps=None):
     return {"tracks": n, "layers": ev.geometry.n_layers, "cov_scale": K.BACKWARD_COV_SCALE, "ms_backward": ms_b,
             "tracks_per_s_backward": n / (ms_b * 1e-3), "ms_forward_backward_step": ms_s,
             "achieved_tflops_backward": tf, "frac_fp32_peak_backward": tf / FP32_PEAK_TFLOPS,
-            "kernel": "backward_kernel<float, 2>", "refitted": int(((st & 64) == 0).sum()),
+            "kernel": "backward_kernel<float, 2, 0>", "refitted": int(((st & 64) == 0).sum()),
             "ms_smooth": ms_sm, "tracks_per_s_smooth": n / (ms_sm * 1e-3),
             "ms_forward_with_checkpoints_and_smooth_step": ms_sms, "achieved_tflops_smooth": tf_sm,
-            "smooth_kernel": "backward_kernel<float, 2, true> + smooth_combine_kernel<float> (FP64 5x5 combination per entry)"}
+            "smooth_kernel": "backward_kernel<float, 2, 1> + smooth_combine_kernel<float> (FP64 5x5 combination "
+                             "per entry)",
+            "final_kernel": "backward_kernel<float, 2, 2>",
+            "ms_final_fit": ms_f, "tracks_per_s_final_fit": n / (ms_f * 1e-3),
+            "achieved_tflops_final_fit": flops / (ms_f * 1e-3) / 1e12, "final_chi2_cut": K.FINAL_CHI2_CUT,
+            "final_rejected_hits": int(mask.sum().item())}
 
 
 def bench_search(ctx, K, args, sample=300):

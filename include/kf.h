@@ -65,7 +65,8 @@ enum {
   KF_TRK_FP64_FALLBACK = 8u, /* a 3x3 inverse was recomputed in FP64 (FP32 path only) */
   KF_TRK_CHARGE_FLIP = 16u,  /* an update turned 1/pT negative; charge flipped */
   KF_TRK_COV_NOT_PSD = 32u,  /* a variance became negative after an update (FP32: beyond the rounding of the prior) */
-  KF_TRK_BAD_INPUT = 64u     /* layer id out of range or fewer than 3 valid hits for seeding */
+  KF_TRK_BAD_INPUT = 64u,    /* layer id out of range or fewer than 3 valid hits for seeding */
+  KF_TRK_OUTLIER = 128u      /* kf_final_fit: at least one hit was rejected as an outlier */
 };
 
 /* Detector description.  HOST struct and HOST arrays, read during the call
@@ -277,6 +278,28 @@ int kf_smooth_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                      void *state_out, void *cov_out, int8_t *charge_out,
                      void *chi2, int32_t *ndf, uint32_t *trk_status,
                      void *smooth_state, void *smooth_cov, void *stream);
+
+/* Final fit with outlier rejection (the backward fit of Sec. 2.2, step 4,
+ * with the hit rejection the paper names for the final fit): the backward
+ * fit of kf_backward_fit (the same arguments and rules) in which a valid hit
+ * whose chi2 against the backward prediction (the increment its update would
+ * add) exceeds chi2_cut is not used.  Its entry is taken as a hole (the
+ * layer's material only): its chi2 is not added, ndf does not count it, and
+ * the track gets KF_TRK_OUTLIER.  A NaN chi2 is not above the cut (the step
+ * then stops the track as non-finite).  One pass: a hit once accepted is not
+ * reconsidered.  chi2_cut > 0; +inf gives kf_backward_fit's result.
+ * outlier [n_hits] (device, caller-owned, may be NULL): for every entry of
+ * the n tracks (hit_offsets[0] .. hit_offsets[n] - 1), 1 if its hit was
+ * rejected, else 0.
+ * KF_ERR_ARG as kf_backward_fit, and for chi2_cut not > 0 (NaN included). */
+int kf_final_fit(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                 const void *state_in, const void *cov_in, const int8_t *charge_in,
+                 const uint32_t *fwd_status,
+                 const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
+                 int64_t n_hits, const void *hit_pos, const void *hit_cov,
+                 const kf_geometry *geom, double cov_scale, double chi2_cut, int32_t max_len,
+                 void *state_out, void *cov_out, int8_t *charge_out,
+                 void *chi2, int32_t *ndf, uint32_t *trk_status, uint8_t *outlier, void *stream);
 
 /* Parameters of the combinatorial candidate search (kf_score_hits).  The
  * paper makes the window, the chi2 cut, the missed-layer limit and the

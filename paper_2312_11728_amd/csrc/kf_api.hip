@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "kf.h"
+#include "kf_backward.hpp"
 #include "kf_kernels.hpp"
 #include "kf_search_launch.hpp"
 
@@ -549,7 +550,8 @@ int backward_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
                   const int32_t* hit_offsets, const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits,
                   const void* hit_pos, const void* hit_cov, const kf_geometry* geom, double cov_scale,
                   int32_t max_len, void* state_out, void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf,
-                  uint32_t* trk_status, void* smooth_state, void* smooth_cov, const char* name, void* stream) {
+                  uint32_t* trk_status, void* smooth_state, void* smooth_cov, const char* name, void* stream,
+                  bool final_fit = false, double chi2_cut = 0.0, uint8_t* outlier = nullptr) {
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
@@ -557,6 +559,7 @@ int backward_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
   if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);
   if (!std::isfinite(cov_scale) || !(cov_scale >= 1.0)) return fail(KF_ERR_ARG, "cov_scale must be finite and >= 1");
+  if (final_fit && !(chi2_cut > 0.0)) return fail(KF_ERR_ARG, "chi2_cut must be > 0");
   if (n == 0) return ok();
   KF_REQUIRE(state_in);
   KF_REQUIRE(cov_in);
@@ -598,7 +601,8 @@ int backward_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
     b.n_seg_f = n_seg_f;
     b.smooth_state = (float*)smooth_state;
     b.smooth_cov = (float*)smooth_cov;
-    e = kf::launch_backward(b, g, s);
+    e = final_fit ? kf::launch_final_fit(kf::FinalArgs<float>{b, float(chi2_cut), outlier}, g, s)
+                  : kf::launch_backward(b, g, s);
   } else {
     kf::BwdArgs<double> b;
     b.f = make_fit_args<double>(n, ld, state_in, cov_in, charge_in, hit_offsets, hit_layer, hit_valid, n_hits,
@@ -611,7 +615,8 @@ int backward_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
     b.n_seg_f = n_seg_f;
     b.smooth_state = (double*)smooth_state;
     b.smooth_cov = (double*)smooth_cov;
-    e = kf::launch_backward(b, g, s);
+    e = final_fit ? kf::launch_final_fit(kf::FinalArgs<double>{b, chi2_cut, outlier}, g, s)
+                  : kf::launch_backward(b, g, s);
   }
   if (e != hipSuccess) return hip_fail(e, name);
   return ok();
@@ -644,6 +649,17 @@ int kf_smooth_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, cons
   return backward_impl(ctx, prec, n, ld, state_in, cov_in, charge_in, fwd_status, fwd_checkpoints, hit_offsets,
                        hit_layer, hit_valid, n_hits, hit_pos, hit_cov, geom, cov_scale, max_len, state_out, cov_out,
                        charge_out, chi2, ndf, trk_status, smooth_state, smooth_cov, "kf_smooth_tracks", stream);
+}
+
+int kf_final_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* state_in, const void* cov_in,
+                 const int8_t* charge_in, const uint32_t* fwd_status, const int32_t* hit_offsets,
+                 const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
+                 const void* hit_cov, const kf_geometry* geom, double cov_scale, double chi2_cut, int32_t max_len,
+                 void* state_out, void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf,
+                 uint32_t* trk_status, uint8_t* outlier, void* stream) {
+  return backward_impl(ctx, prec, n, ld, state_in, cov_in, charge_in, fwd_status, nullptr, hit_offsets, hit_layer,
+                       hit_valid, n_hits, hit_pos, hit_cov, geom, cov_scale, max_len, state_out, cov_out, charge_out,
+                       chi2, ndf, trk_status, nullptr, nullptr, "kf_final_fit", stream, true, chi2_cut, outlier);
 }
 
 int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {

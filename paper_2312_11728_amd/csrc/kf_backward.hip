@@ -5,6 +5,7 @@
 // unchanged on the reversed entry list.  One track per lane; the entries of a
 // wave's 64 tracks are staged through LDS a few at a time, as in the forward
 // fit.
+#include "kf_backward.hpp"
 #include "kf_kernels.hpp"
 #include "kf_stage.hpp"
 #include "kf_track.hpp"
@@ -230,6 +231,79 @@ __device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, i
   return true;
 }
 
+// One entry of the final fit: the backward fit's step (propagation or, on the
+// first entry, the layer's material at the current state), whose update is
+// kept only if the hit's chi2 (the increment the update adds) is at most the
+// cut; a rejected hit leaves the entry a hole (the layer's material only), is
+// marked in the outlier mask and flags the track.  A NaN chi2 is not above
+// the cut.  Layer check, backup and roll-back as in fit_entry.
+template <typename T>
+__device__ inline bool reject_step(const FinalArgs<T>& fa, const TrackGeom<T>& g, int64_t e, int k, int lay,
+                                   int& prev, bool valid, const T m[3], const T V[6], T p[6], T c[21], int& q,
+                                   uint32_t& st, T& chi2, int& nval, T* bk, int bk_stride) {
+  if (lay < 0 || lay >= g.n_layers) {
+    st |= TRK_BAD_INPUT;
+    return false;
+  }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) bk[i * bk_stride] = p[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) bk[(6 + i) * bk_stride] = c[i];
+  const int qq = q;
+  uint32_t sst = 0;
+  const int kind = g.kind[lay];
+  if (k > 0) {
+    if (!propagate(p, c, q, kind, g.pos[lay], g.x0[lay], lay == prev, true, g.bz, g.mass, sst)) {
+      st |= sst;
+      return false;
+    }
+  } else {
+    add_material_here(p, c, kind, g.x0[lay], g.mass, sst);
+  }
+  T c2 = T(0);
+  bool used = false, rejected = false;
+  if (valid) {
+    T pu[6], cu[21], mm[3];
+    int qu = q;
+    uint32_t ust = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) pu[i] = p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) cu[i] = c[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) mm[i] = m[i];
+    update(pu, cu, qu, mm, V, c2, ust);
+    if (c2 > fa.chi2_cut) {
+      c2 = T(0);
+      sst |= TRK_OUTLIER;
+      rejected = true;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) p[i] = pu[i];
+#pragma unroll
+      for (int i = 0; i < 21; ++i) c[i] = cu[i];
+      q = qu;
+      sst |= ust;
+      used = true;
+    }
+  }
+  if (!all_finite(p, c, c2)) {
+    st |= sst | TRK_NONFINITE;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) p[i] = bk[i * bk_stride];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = bk[(6 + i) * bk_stride];
+    q = qq;
+    return false;
+  }
+  st |= sst;
+  chi2 += c2;
+  nval += used ? 1 : 0;
+  prev = lay;
+  if (rejected && fa.outlier) fa.outlier[e] = 1;
+  return true;
+}
+
 // Smoothing, entry-parallel: thread (r, t) combines the backward prediction
 // stored at entry r of track t with the forward filtered state of that entry
 // (forward checkpoint slot r - k0) and overwrites it with the smoothed state.
@@ -282,9 +356,15 @@ __global__ void __launch_bounds__(256, 2) smooth_combine_kernel(BwdArgs<T> b, Ge
 // Backward fit of tracks [w0, w0 + 64) (one wave; every lane must call it).
 // Entry k of a track's backward pass is CSR entry last - k; the pass has
 // n_entries - k0 entries (k0: the first valid entry in crossing order).
-template <typename T, int J, bool SMOOTH>
-__device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g, int64_t w0, StageBuf<T, J>& sb,
+// MODE: kPlain (the backward fit), kSmooth (the backward pass of the
+// smoother), kReject (the final fit with outlier rejection).
+constexpr int kPlain = 0, kSmooth = 1, kReject = 2;
+
+template <typename T, int J, int MODE>
+__device__ void backward_wave_staged(const FinalArgs<T>& fa, const TrackGeom<T>& g, int64_t w0, StageBuf<T, J>& sb,
                                      T* bk, int bk_stride) {
+  constexpr bool SMOOTH = MODE == kSmooth;
+  const BwdArgs<T>& b = fa.b;
   const FitArgs<T>& a = b.f;
   const int lane = int(threadIdx.x) & 63;
   const int64_t t = w0 + lane;
@@ -304,6 +384,10 @@ __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g,
 #pragma unroll
     for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * a.ld + t];
     q = a.seed_charge[t];
+    if (MODE == kReject && fa.outlier) {
+      const int64_t e1 = a.hit_offsets[t + 1];
+      for (int64_t e = e0; e < e1; ++e) fa.outlier[e] = 0;
+    }
     while (k0 < n_e && a.hit_valid[e0 + k0] == 0) ++k0;
     const uint32_t stop = TRK_NO_CROSSING | TRK_NONFINITE | TRK_BAD_INPUT;
     run = k0 < n_e && !(b.fwd_status && (b.fwd_status[t] & stop));
@@ -382,6 +466,8 @@ __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g,
       const int r = n_e - 1 - k;   // entry index within the track
       if (SMOOTH && k > 0)
         live = smooth_step(b, g, t, r, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
+      else if (MODE == kReject)
+        live = reject_step(fa, g, last - k, k, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
       else
         live = fit_entry(a, g, static_cast<const T*>(nullptr), t, k, lay, prev, valid, m, V, p, c, q, st, chi2,
                          nval, bk, bk_stride);
@@ -404,15 +490,15 @@ __device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g,
 
 // WAVES: waves per SIMD the register allocation must allow (2 in FP32, 1 in
 // FP64, the forward fit's tuned choices).
-template <typename T, int WAVES, bool SMOOTH>
-__global__ void __launch_bounds__(kBwdBlock, WAVES) backward_kernel(BwdArgs<T> b, GeomArgs g) {
+template <typename T, int WAVES, int MODE>
+__global__ void __launch_bounds__(kBwdBlock, WAVES) backward_kernel(FinalArgs<T> fa, GeomArgs g) {
   constexpr int J = stage_entries<T, WAVES>();
   __shared__ GeomLds<T> sg;
   __shared__ T bk[28 * kBwdBlock];
   __shared__ StageBuf<T, J> sb[kBwdBlock / 64];
   stage_geometry(sg, g);
   const int64_t w0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
-  backward_wave_staged<T, J, SMOOTH>(b, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, w0,
+  backward_wave_staged<T, J, MODE>(fa, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, w0,
                              sb[threadIdx.x >> 6], bk + threadIdx.x, int(blockDim.x));
 }
 
@@ -422,20 +508,32 @@ template <typename T>
 hipError_t launch_backward(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s) {
   if (a.f.n == 0) return hipSuccess;
   const int64_t grid = (a.f.n + kBwdBlock - 1) / kBwdBlock;
+  const FinalArgs<T> fa{a, k_inf<T>(), nullptr};
   if (a.smooth_state) {
-    hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, true>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
-                       s, a, g);
+    hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, kSmooth>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
+                       s, fa, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(smooth_combine_kernel<T>, dim3(unsigned((a.f.n + 255) / 256), unsigned(a.f.max_len)), dim3(256),
                        0, s, a, g);
   } else
-    hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, false>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
-                       s, a, g);
+    hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, kPlain>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
+                       s, fa, g);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_final_fit(const FinalArgs<T>& a, const GeomArgs& g, hipStream_t s) {
+  if (a.b.f.n == 0) return hipSuccess;
+  const int64_t grid = (a.b.f.n + kBwdBlock - 1) / kBwdBlock;
+  hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, kReject>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
+                     s, a, g);
   return hipGetLastError();
 }
 
 template hipError_t launch_backward<float>(const BwdArgs<float>&, const GeomArgs&, hipStream_t);
 template hipError_t launch_backward<double>(const BwdArgs<double>&, const GeomArgs&, hipStream_t);
+template hipError_t launch_final_fit<float>(const FinalArgs<float>&, const GeomArgs&, hipStream_t);
+template hipError_t launch_final_fit<double>(const FinalArgs<double>&, const GeomArgs&, hipStream_t);
 
 }  // namespace kf

@@ -19,18 +19,19 @@ KF_OK, KF_ERR_ARG, KF_ERR_DEVICE, KF_ERR_NOMEM, KF_ERR_UNSUPPORTED = 0, -1, -2, 
 KF_F32, KF_F64 = 0, 1
 # per-track status bits (kf_status of include/kf.h)
 (KF_TRK_NO_CROSSING, KF_TRK_GRAZING, KF_TRK_NONFINITE, KF_TRK_FP64_FALLBACK, KF_TRK_CHARGE_FLIP, KF_TRK_COV_NOT_PSD,
- KF_TRK_BAD_INPUT) = 1, 2, 4, 8, 16, 32, 64
+ KF_TRK_BAD_INPUT, KF_TRK_OUTLIER) = 1, 2, 4, 8, 16, 32, 64, 128
 TRK_NO_CROSSING, TRK_GRAZING, TRK_NONFINITE, TRK_FP64_FALLBACK = 1, 2, 4, 8
-TRK_CHARGE_FLIP, TRK_COV_NOT_PSD, TRK_BAD_INPUT = 16, 32, 64
+TRK_CHARGE_FLIP, TRK_COV_NOT_PSD, TRK_BAD_INPUT, TRK_OUTLIER = 16, 32, 64, 128
 MAX_LAYERS = 64
 
 EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_propagate", "kf_update",
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
            "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph",
            "kf_set_kernel_timing", "kf_fit_kernel_time", "kf_seed_fit_tracks", "kf_backward_fit",
-           "kf_smooth_tracks"]
+           "kf_smooth_tracks", "kf_final_fit"]
 
 BACKWARD_COV_SCALE = 100.0   # forward covariance scale at the start of the backward fit
+FINAL_CHI2_CUT = 30.0        # the final fit's default chi2 cut for one hit
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -97,6 +98,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        _i32, _i32, _vp, _vp]
     lib.kf_backward_fit.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                     ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_final_fit.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
+                                 ctypes.POINTER(KfGeometry), _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_smooth_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                      _vp, ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                      _vp, _vp]
@@ -356,6 +359,45 @@ class Context:
                                      _ptr(out["charge"]), _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(out["status"]),
                                      _stream(dev)))
         return out
+
+    def final_fit(self, fwd, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry,
+                  chi2_cut=FINAL_CHI2_CUT, cov_scale=BACKWARD_COV_SCALE, max_len=26, out=None, outlier=None,
+                  use_status=True):
+        """Final fit with outlier rejection (kf_final_fit): the backward fit of
+        backward_fit, in which a hit whose chi2 against the backward
+        prediction exceeds chi2_cut is not used.  Returns (out, outlier):
+        fit_tracks-form outputs and the uint8 mask [n_hits] of rejected
+        entries."""
+        dev = self.device
+        st_in, cov_in, q_in = fwd["state"], fwd["cov"], fwd["charge"]
+        dt = st_in.dtype
+        n = st_in.shape[1]
+        _need(st_in, "state", dt, dev, rows=6)
+        _need(cov_in, "cov", dt, dev, rows=21)
+        _need(q_in, "charge", torch.int8, dev)
+        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need(hit_layer, "hit_layer", torch.int16, dev)
+        _need(hit_valid, "hit_valid", torch.uint8, dev)
+        _need(hit_pos, "hit_pos", dt, dev, rows=3)
+        _need(hit_cov, "hit_cov", dt, dev, rows=6)
+        status = fwd["status"] if use_status else None
+        if status is not None:
+            _need(status, "status", torch.int32, dev)
+        if st_in.stride(0) != cov_in.stride(0):
+            raise ValueError("state and cov must share their leading dimension")
+        if out is None:
+            out = fit_outputs(n, dt, dev)
+        n_hits = hit_pos.shape[1]
+        if outlier is None:
+            outlier = torch.empty(n_hits, dtype=torch.uint8, device=dev)
+        _need(outlier, "outlier", torch.uint8, dev)
+        _check(lib().kf_final_fit(self.handle, _prec(dt), n, st_in.stride(0), _ptr(st_in), _ptr(cov_in), _ptr(q_in),
+                                  _ptr(status), _ptr(hit_offsets), _ptr(hit_layer), _ptr(hit_valid), n_hits,
+                                  _ptr(hit_pos), _ptr(hit_cov), ctypes.byref(geom.struct), float(cov_scale),
+                                  float(chi2_cut), int(max_len), _ptr(out["state"]), _ptr(out["cov"]),
+                                  _ptr(out["charge"]), _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(out["status"]),
+                                  _ptr(outlier), _stream(dev)))
+        return out, outlier
 
     def smooth_tracks(self, fwd, checkpoints, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry,
                       cov_scale=BACKWARD_COV_SCALE, max_len=26, out=None, smooth=None, use_status=True):

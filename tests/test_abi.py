@@ -249,3 +249,33 @@ def _smooth_call(**over):
 def test_smooth_tracks_argument_validation(over, msg):
     assert _smooth_call(**over) == kf.KF_ERR_ARG
     assert msg in kf.lib().kf_last_error().decode()
+
+
+def _final_call(**over):
+    Q = ctypes.c_void_p(0x2000)
+    args = dict(ctx=P, prec=kf.KF_F32, n=10, ld=10, state_in=P, cov_in=P, charge_in=P, fwd_status=P, hit_offsets=P,
+                hit_layer=P, hit_valid=P, n_hits=100, hit_pos=P, hit_cov=P, geom=ctypes.byref(_geom().struct),
+                cov_scale=100.0, chi2_cut=30.0, max_len=26, state_out=Q, cov_out=Q, charge_out=Q, chi2=Q, ndf=Q,
+                trk_status=Q, outlier=None, stream=None)
+    args.update(over)
+    return kf.lib().kf_final_fit(*args.values())
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(chi2_cut=0.0), "chi2_cut"),
+    (dict(chi2_cut=-1.0), "chi2_cut"),
+    (dict(chi2_cut=float("nan")), "chi2_cut"),
+    (dict(cov_scale=0.5), "cov_scale"),
+    (dict(n=-1), "n = -1"),
+    (dict(max_len=0), "max_len = 0"),
+    (dict(hit_pos=None), "hit_pos is NULL"),
+    (dict(ctx=None), "ctx is NULL"),
+    (dict(cov_out=P), "alias"),
+])
+def test_final_fit_argument_validation(over, msg):
+    assert _final_call(**over) == kf.KF_ERR_ARG
+    assert msg in kf.lib().kf_last_error().decode()
+
+
+def test_final_fit_empty_batch_is_a_no_op():
+    assert _final_call(n=0, ld=0, ctx=None, state_in=None, chi2_cut=float("inf")) == kf.KF_OK
