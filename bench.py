@@ -350,8 +350,17 @@ def bench_search(ctx, K, args, sample=300):
     ms_total = time_loop(lambda: run(prm_bin), args.steps, args.warmup)
     ms = time_loop(lambda: run(prm_reuse), args.steps, args.warmup)
     hits = out[0].cpu().numpy()
+    # duplicate removal over the seeds' best candidates (rank 0)
+    cand_h, cand_s = out[0], out[1]
+    dd = []
+
+    def dedup():
+        dd[:] = ctx.remove_duplicates(cand_h[:, 0, :], cand_s[:, 0], 0.5)
+
+    ms_dd = time_loop(dedup, args.steps, args.warmup)
     res = {"seeds": n, "layers": len(PLAN), "beam": 6, "pool_hits": int(pools.pos.shape[1]), "ms": ms,
-           "seeds_per_s": n / (ms * 1e-3), "ms_with_binning": ms_total, "ms_binning": ms_total - ms}
+           "seeds_per_s": n / (ms * 1e-3), "ms_with_binning": ms_total, "ms_binning": ms_total - ms,
+           "ms_dedup": ms_dd, "dedup_kept": int(dd[0].sum().item()), "dedup_frac": 0.5}
     if not args.no_accuracy:
         pick = np.random.default_rng(7).choice(n, sample, replace=False)
         o = KS.score_hits(p[pick], C[pick], q[pick], np.full(sample, SEED_LAYER), PLAN, g, pools, default_params(g))

@@ -301,6 +301,32 @@ int kf_final_fit(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                  void *state_out, void *cov_out, int8_t *charge_out,
                  void *chi2, int32_t *ndf, uint32_t *trk_status, uint8_t *outlier, void *stream);
 
+/* Duplicate removal among found tracks (the end of track finding, Sec. 2.2:
+ * each seed is represented by its best candidate, and tracks found from
+ * different seeds that share their hits are duplicates).  Track t carries one
+ * hit id per layer of the plan, track_hits[t * hit_stride + l] for
+ * l < n_layers (-1 a miss, -2 no candidate; ids >= 0 as kf_score_hits reports
+ * them), and score[t * score_stride] (-inf: no candidate).  The best
+ * candidates of kf_score_hits are rank 0: hit_stride = beam * plan_len,
+ * score_stride = beam.  n(t) is the number of ids >= 0 of t; shared(t, u) the
+ * number of layers at which t and u carry the same id >= 0.  t and u are
+ * duplicates iff shared >= 1 and shared >= frac * min(n(t), n(u)) (exact: frac
+ * as the float given, no rounding of the product); u outranks
+ * t iff score(u) > score(t), or the scores are equal and u < t; t is removed
+ * iff an outranking track is its duplicate (whether or not that one is
+ * removed itself).  keep[n] (device, caller-owned): 1 kept, 0 removed (also
+ * for a track without a candidate).  dup_of[n] (device, may be NULL): the
+ * highest-ranked outranking duplicate of a removed track, else -1.  No two
+ * kept tracks are duplicates.  The call sorts (hit id, track) pairs in a
+ * context-owned workspace (about 16 bytes per track and layer plus the
+ * sort's own; grown on demand, KF_ERR_NOMEM if that fails).  n = 0 is a
+ * no-op.  KF_ERR_ARG for n < 0, n_layers outside [1, 64], hit_stride <
+ * n_layers, score_stride < 1, frac outside (0, 1], n * n_layers >= 2^31, or
+ * a missing pointer. */
+int kf_remove_duplicates(kf_ctx *ctx, int64_t n, const int32_t *track_hits, int64_t hit_stride,
+                         int32_t n_layers, const float *score, int64_t score_stride, float frac,
+                         uint8_t *keep, int32_t *dup_of, void *stream);
+
 /* Parameters of the combinatorial candidate search (kf_score_hits).  The
  * paper makes the window, the chi2 cut, the missed-layer limit and the
  * candidate score per-iteration parameters and standard functions (Sec. 3.2,

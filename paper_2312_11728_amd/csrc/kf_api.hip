@@ -13,6 +13,7 @@
 
 #include "kf.h"
 #include "kf_backward.hpp"
+#include "kf_dedup.hpp"
 #include "kf_kernels.hpp"
 #include "kf_search_launch.hpp"
 
@@ -37,6 +38,9 @@ struct kf_ctx {
   void* search_mem = nullptr;
   size_t search_bytes = 0;
   std::vector<unsigned char> bins_key;
+  // workspace of duplicate removal (grown on demand)
+  void* dedup_mem = nullptr;
+  size_t dedup_bytes = 0;
   // event pairs around the fit kernel of direct launches (kf_set_kernel_timing)
   bool timing = false;
   std::vector<hipEvent_t> t_start, t_stop;
@@ -173,6 +177,7 @@ int kf_destroy(kf_ctx* c) {
   if (c->work_mem) hipFree(c->work_mem);
   if (c->red_mem) hipFree(c->red_mem);
   if (c->search_mem) hipFree(c->search_mem);
+  if (c->dedup_mem) hipFree(c->dedup_mem);
   hipSetDevice(prev);
   delete c;
   return ok();
@@ -660,6 +665,42 @@ int kf_final_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const vo
   return backward_impl(ctx, prec, n, ld, state_in, cov_in, charge_in, fwd_status, nullptr, hit_offsets, hit_layer,
                        hit_valid, n_hits, hit_pos, hit_cov, geom, cov_scale, max_len, state_out, cov_out, charge_out,
                        chi2, ndf, trk_status, nullptr, nullptr, "kf_final_fit", stream, true, chi2_cut, outlier);
+}
+
+int kf_remove_duplicates(kf_ctx* ctx, int64_t n, const int32_t* track_hits, int64_t hit_stride, int32_t n_layers,
+                         const float* score, int64_t score_stride, float frac, uint8_t* keep, int32_t* dup_of,
+                         void* stream) {
+  if (n < 0) return fail(KF_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (n_layers < 1 || n_layers > 64) return fail(KF_ERR_ARG, "n_layers = %d outside [1, 64]", n_layers);
+  if (hit_stride < n_layers) return fail(KF_ERR_ARG, "hit_stride = %lld < n_layers", (long long)hit_stride);
+  if (score_stride < 1) return fail(KF_ERR_ARG, "score_stride = %lld < 1", (long long)score_stride);
+  if (!(frac > 0.0f && frac <= 1.0f)) return fail(KF_ERR_ARG, "frac must be in (0, 1]");
+  if (n * int64_t(n_layers) >= (int64_t(1) << 31)) return fail(KF_ERR_ARG, "n * n_layers must be < 2^31");
+  if (n == 0) return ok();
+  KF_REQUIRE(ctx);
+  KF_REQUIRE(track_hits);
+  KF_REQUIRE(score);
+  KF_REQUIRE(keep);
+  const size_t need = kf::dedup_workspace_bytes(n, n_layers);
+  if (need > ctx->dedup_bytes) {
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    if (ctx->dedup_mem) hipFree(ctx->dedup_mem);
+    ctx->dedup_mem = nullptr;
+    ctx->dedup_bytes = 0;
+    hipError_t e = hipMalloc(&ctx->dedup_mem, need);
+    hipSetDevice(prev);
+    if (e != hipSuccess) {
+      ctx->dedup_mem = nullptr;
+      return fail(KF_ERR_NOMEM, "kf_remove_duplicates: %zu bytes: %s", need, hipGetErrorString(e));
+    }
+    ctx->dedup_bytes = need;
+  }
+  kf::DedupArgs a{n, track_hits, hit_stride, n_layers, score, score_stride, frac, keep, dup_of};
+  hipError_t e = kf::launch_dedup(a, ctx->dedup_mem, ctx->dedup_bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "kf_remove_duplicates");
+  return ok();
 }
 
 int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {

@@ -28,7 +28,7 @@ EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_prop
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
            "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph",
            "kf_set_kernel_timing", "kf_fit_kernel_time", "kf_seed_fit_tracks", "kf_backward_fit",
-           "kf_smooth_tracks", "kf_final_fit"]
+           "kf_smooth_tracks", "kf_final_fit", "kf_remove_duplicates"]
 
 BACKWARD_COV_SCALE = 100.0   # forward covariance scale at the start of the backward fit
 FINAL_CHI2_CUT = 30.0        # the final fit's default chi2 cut for one hit
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_final_fit.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                  ctypes.POINTER(KfGeometry), _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_remove_duplicates.argtypes = [_vp, _i64, _vp, _i64, _i32, _vp, _i64, ctypes.c_float, _vp, _vp, _vp]
     lib.kf_smooth_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                      _vp, ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                      _vp, _vp]
@@ -398,6 +399,32 @@ class Context:
                                   _ptr(out["charge"]), _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(out["status"]),
                                   _ptr(outlier), _stream(dev)))
         return out, outlier
+
+    def remove_duplicates(self, track_hits, score, frac=0.5, keep=None, dup_of=None):
+        """Duplicate removal (kf_remove_duplicates) over n tracks:
+        track_hits int32 [n, L] or a view with unit stride along L (e.g. the
+        rank-0 slice cand_hits[:, 0, :] of score_hits), score float32 [n]
+        (strided views allowed).  Returns (keep uint8 [n], dup_of int32 [n])."""
+        dev = self.device
+        if track_hits.dtype != torch.int32 or track_hits.dim() != 2 or track_hits.stride(1) != 1:
+            raise ValueError("track_hits must be int32 [n, L] with unit stride along L")
+        if score.dtype != torch.float32 or score.dim() != 1:
+            raise ValueError("score must be float32 [n]")
+        n, L = track_hits.shape
+        if score.shape[0] != n:
+            raise ValueError("score and track_hits disagree on n")
+        if track_hits.device != dev or score.device != dev:
+            raise ValueError("inputs must be on the context's device")
+        if keep is None:
+            keep = torch.empty(n, dtype=torch.uint8, device=dev)
+        if dup_of is None:
+            dup_of = torch.empty(n, dtype=torch.int32, device=dev)
+        _need(keep, "keep", torch.uint8, dev)
+        _need(dup_of, "dup_of", torch.int32, dev)
+        _check(lib().kf_remove_duplicates(self.handle, n, _ptr(track_hits), max(track_hits.stride(0), L), L,
+                                          _ptr(score), max(score.stride(0), 1), float(frac), _ptr(keep),
+                                          _ptr(dup_of), _stream(dev)))
+        return keep, dup_of
 
     def smooth_tracks(self, fwd, checkpoints, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry,
                       cov_scale=BACKWARD_COV_SCALE, max_len=26, out=None, smooth=None, use_status=True):

@@ -279,3 +279,33 @@ def test_final_fit_argument_validation(over, msg):
 
 def test_final_fit_empty_batch_is_a_no_op():
     assert _final_call(n=0, ld=0, ctx=None, state_in=None, chi2_cut=float("inf")) == kf.KF_OK
+
+
+def _dedup_call(**over):
+    args = dict(ctx=P, n=10, track_hits=P, hit_stride=17, n_layers=17, score=P, score_stride=1, frac=0.5, keep=P,
+                dup_of=None, stream=None)
+    args.update(over)
+    return kf.lib().kf_remove_duplicates(*args.values())
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(n=-1), "n = -1"),
+    (dict(n_layers=0), "n_layers = 0"),
+    (dict(n_layers=65, hit_stride=65), "n_layers = 65"),
+    (dict(hit_stride=16), "hit_stride = 16"),
+    (dict(score_stride=0), "score_stride = 0"),
+    (dict(frac=0.0), "frac"),
+    (dict(frac=1.5), "frac"),
+    (dict(frac=float("nan")), "frac"),
+    (dict(n=1 << 30, n_layers=2, hit_stride=2), "2^31"),
+    (dict(track_hits=None), "track_hits is NULL"),
+    (dict(keep=None), "keep is NULL"),
+    (dict(ctx=None), "ctx is NULL"),
+])
+def test_remove_duplicates_argument_validation(over, msg):
+    assert _dedup_call(**over) == kf.KF_ERR_ARG
+    assert msg in kf.lib().kf_last_error().decode()
+
+
+def test_remove_duplicates_empty_is_a_no_op():
+    assert _dedup_call(n=0, ctx=None, track_hits=None) == kf.KF_OK
