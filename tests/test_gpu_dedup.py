@@ -48,7 +48,7 @@ def _gpu(ctx, hits, score, frac):
 
 
 @pytest.mark.parametrize("n,frac,seed", [(1, 0.5, 1), (63, 0.5, 2), (300, 0.3, 3), (5000, 0.5, 4), (5000, 1.0, 5),
-                                         (20000, 0.5, 6), (50000, 0.75, 7)])
+                                         (20000, 0.5, 6), (50000, 0.75, 7), (200000, 0.5, 12)])
 def test_dedup_parity(ctx, kf, n, frac, seed):
     say("dedup", n, frac)
     hits, score = duplicate_candidates(n, seed=seed)

@@ -187,3 +187,24 @@ def test_final_fit_ragged_sizes(ctx, kf):
         ep = param_error(g["p"], of["p"]).max(axis=1)
         assert (ep <= 1e-7).all(), (n, ep.max())
     say("ragged ok")
+
+
+def test_tiny_cut_rejects_every_hit(ctx, kf):
+    """The degenerate cut: every valid hit a refitted track reaches is
+    rejected (a positive chi2 is above 1e-30), so the pass only carries the
+    restart through the material: ndf = -5, chi2 = 0, the mask equals the
+    valid entries, and the oracle agrees."""
+    say("final fit, tiny cut")
+    ev = generate(workloads()["barrel10"], 500)
+    dt = torch.float64
+    fwd = rounded_forward(oracle_fit(ev, dt, 0), dt)
+    of = oracle_final(ev, dt, fwd, chi2_cut=1e-30)
+    g = gpu_final(ctx, kf, ev, dt, fwd, chi2_cut=1e-30, prefill=5)
+    refit = (of["status"] & O.NOT_REFITTED) == 0
+    assert refit.mean() > 0.99
+    assert (g["ndf"][refit] == -5).all() and (g["chi2"][refit] == 0).all()
+    assert ((g["status"][refit] & O.OUTLIER) != 0).all()
+    assert np.array_equal(g["outlier"], of["outlier"])
+    ok_e = np.repeat(refit, ev.lengths())
+    assert np.array_equal(g["outlier"][ok_e].astype(bool), (ev.hit_valid == 1)[ok_e])
+    assert (param_error(g["p"], of["p"]).max(axis=1) <= 1e-8).all()
