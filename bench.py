@@ -15,6 +15,7 @@ import json
 import os
 import re
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -449,7 +450,7 @@ def main():
     ap.add_argument("--no-search", action="store_true", help="skip the combinatorial search workload")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward-fit workload")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "kf_autotune.json"))
+    ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "kf_autotune.json"))
     ap.add_argument("--launch", default=None,
                     help="profile-only: fit launch shape block,persistent,blocks_per_cu,waves,layout")
     ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32", "adjoint", "search", "backward"],
