@@ -319,6 +319,7 @@ class Context:
             _need(checkpoints, "checkpoints", dt, dev, rows=28)
         if out is None:
             out = fit_outputs(n, dt, dev)
+        _need_outputs(out, n, dt, dev)
         _check(lib().kf_fit_tracks(self.handle, _prec(dt), n, seed_state.stride(0), _ptr(seed_state), _ptr(seed_cov),
                                    _ptr(seed_charge), _ptr(hit_offsets), _ptr(hit_layer), _ptr(hit_valid),
                                    hit_pos.shape[1], _ptr(hit_pos), _ptr(hit_cov), ctypes.byref(geom.struct),
@@ -349,10 +350,11 @@ class Context:
         status = fwd["status"] if use_status else None
         if status is not None:
             _need(status, "status", torch.int32, dev)
-        if st_in.stride(0) != cov_in.stride(0):
-            raise ValueError("state and cov must share their leading dimension")
+        if st_in.stride(0) != n or cov_in.stride(0) != n:
+            raise ValueError("state and cov must have leading dimension n (the outputs are [rows, n])")
         if out is None:
             out = fit_outputs(n, dt, dev)
+        _need_outputs(out, n, dt, dev)
         _check(lib().kf_backward_fit(self.handle, _prec(dt), n, st_in.stride(0), _ptr(st_in), _ptr(cov_in), _ptr(q_in),
                                      _ptr(status), _ptr(hit_offsets), _ptr(hit_layer), _ptr(hit_valid),
                                      hit_pos.shape[1], _ptr(hit_pos), _ptr(hit_cov), ctypes.byref(geom.struct),
@@ -384,14 +386,17 @@ class Context:
         status = fwd["status"] if use_status else None
         if status is not None:
             _need(status, "status", torch.int32, dev)
-        if st_in.stride(0) != cov_in.stride(0):
-            raise ValueError("state and cov must share their leading dimension")
+        if st_in.stride(0) != n or cov_in.stride(0) != n:
+            raise ValueError("state and cov must have leading dimension n (the outputs are [rows, n])")
         if out is None:
             out = fit_outputs(n, dt, dev)
+        _need_outputs(out, n, dt, dev)
         n_hits = hit_pos.shape[1]
         if outlier is None:
             outlier = torch.empty(n_hits, dtype=torch.uint8, device=dev)
         _need(outlier, "outlier", torch.uint8, dev)
+        if outlier.numel() < n_hits:
+            raise ValueError(f"outlier must hold n_hits = {n_hits} entries")
         _check(lib().kf_final_fit(self.handle, _prec(dt), n, st_in.stride(0), _ptr(st_in), _ptr(cov_in), _ptr(q_in),
                                   _ptr(status), _ptr(hit_offsets), _ptr(hit_layer), _ptr(hit_valid), n_hits,
                                   _ptr(hit_pos), _ptr(hit_cov), ctypes.byref(geom.struct), float(cov_scale),
@@ -421,6 +426,8 @@ class Context:
             dup_of = torch.empty(n, dtype=torch.int32, device=dev)
         _need(keep, "keep", torch.uint8, dev)
         _need(dup_of, "dup_of", torch.int32, dev)
+        if keep.numel() < n or dup_of.numel() < n:
+            raise ValueError(f"keep and dup_of must hold n = {n} entries")
         _check(lib().kf_remove_duplicates(self.handle, n, _ptr(track_hits), max(track_hits.stride(0), L), L,
                                           _ptr(score), max(score.stride(0), 1), float(frac), _ptr(keep),
                                           _ptr(dup_of), _stream(dev)))
@@ -453,6 +460,7 @@ class Context:
         status = fwd["status"] if use_status else None
         if out is None:
             out = fit_outputs(n, dt, dev)
+        _need_outputs(out, n, dt, dev)
         if smooth is None:
             smooth = dict(state=torch.full((6, max_len, n), float("nan"), dtype=dt, device=dev),
                           cov=torch.full((21, max_len, n), float("nan"), dtype=dt, device=dev))
@@ -495,6 +503,7 @@ class Context:
                 raise ValueError("seed outputs must have leading dimension n")
         if out is None:
             out = fit_outputs(n, dt, dev)
+        _need_outputs(out, n, dt, dev)
         _check(lib().kf_seed_fit_tracks(self.handle, _prec(dt), n, n, int(seed_mode), _ptr(hit_offsets),
                                         _ptr(hit_layer), _ptr(hit_valid), hit_pos.shape[1], _ptr(hit_pos),
                                         _ptr(hit_cov), ctypes.byref(geom.struct), _ptr(align), _ptr(ss), _ptr(sc),
@@ -617,6 +626,17 @@ def fit_outputs(n, dtype, device):
     return dict(state=torch.empty(6, n, dtype=dtype, device=device), cov=torch.empty(21, n, dtype=dtype, device=device),
                 charge=torch.empty(n, dtype=torch.int8, device=device), chi2=torch.empty(n, dtype=dtype, device=device),
                 ndf=torch.empty(n, dtype=torch.int32, device=device), status=torch.empty(n, dtype=torch.int32, device=device))
+
+
+def _need_outputs(out, n, dtype, device):
+    """The caller's output dict has the shapes and types fit_outputs makes."""
+    spec = (("state", 6, dtype), ("cov", 21, dtype), ("charge", 0, torch.int8), ("chi2", 0, dtype),
+            ("ndf", 0, torch.int32), ("status", 0, torch.int32))
+    for k, rows, dt in spec:
+        t = out.get(k) if isinstance(out, dict) else None
+        shape = (rows, n) if rows else (n,)
+        if t is None or t.dtype != dt or t.device != device or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"out[{k!r}] must be a contiguous {list(shape)} tensor of {dt} on {device}")
 
 
 def n_checkpoint_segments(max_len, seg):
