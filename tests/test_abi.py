@@ -309,3 +309,18 @@ def test_remove_duplicates_argument_validation(over, msg):
 
 def test_remove_duplicates_empty_is_a_no_op():
     assert _dedup_call(n=0, ctx=None, track_hits=None) == kf.KF_OK
+
+
+def test_output_dict_is_checked_before_any_launch():
+    """A caller's output dict of the wrong size, type or layout is refused
+    in the binding (a short buffer would be written past its end)."""
+    import torch
+    dev = torch.device("cpu")
+    good = kf.fit_outputs(5, torch.float32, dev)
+    kf._need_outputs(good, 5, torch.float32, dev)
+    bad = [kf.fit_outputs(4, torch.float32, dev), kf.fit_outputs(5, torch.float64, dev),
+           dict(good, ndf=torch.empty(5, dtype=torch.int64)), dict(good, cov=torch.empty(5, 21).T),
+           {k: v for k, v in good.items() if k != "status"}]
+    for out in bad:
+        with pytest.raises(ValueError):
+            kf._need_outputs(out, 5, torch.float32, dev)
