@@ -186,9 +186,9 @@ struct StorePrediction {
 // state is a separate, entry-parallel pass: smooth_combine_kernel).  The rest
 // as in fit_entry (layer check, backup, roll-back of a non-finite step).
 template <typename T>
-__device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, int64_t t, int r, int lay, int& prev,
-                                   bool valid, const T m[3], const T V[6], T p[6], T c[21], int& q, uint32_t& st,
-                                   T& chi2, int& nval, T* bk, int bk_stride) {
+__device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, int64_t t, int k, int r, int lay,
+                                   int& prev, bool valid, const T m[3], const T V[6], T p[6], T c[21], int& q,
+                                   uint32_t& st, T& chi2, int& nval, T* bk, int bk_stride) {
   const FitArgs<T>& a = b.f;
   if (lay < 0 || lay >= g.n_layers) {
     st |= TRK_BAD_INPUT;
@@ -203,8 +203,10 @@ __device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, i
   const int kind = g.kind[lay];
   const int64_t at = int64_t(r) * a.ld + t;
   const StorePrediction<T> store{b.smooth_state + at, b.smooth_cov + at, a.ld * int64_t(a.max_len)};
-  if (!propagate(p, c, q, kind, g.pos[lay], g.x0[lay], lay == prev, true, g.bz, g.mass, sst, static_cast<T*>(nullptr),
-                 static_cast<PropTape<T>*>(nullptr), store)) {
+  if (k == 0) {
+    add_material_here(p, c, kind, g.x0[lay], g.mass, sst);   // the first entry: its prediction is the input
+  } else if (!propagate(p, c, q, kind, g.pos[lay], g.x0[lay], lay == prev, true, g.bz, g.mass, sst,
+                        static_cast<T*>(nullptr), static_cast<PropTape<T>*>(nullptr), store)) {
     st |= sst;
     return false;
   }
@@ -464,8 +466,8 @@ __device__ void backward_wave_staged(const FinalArgs<T>& fa, const TrackGeom<T>&
 #pragma unroll
       for (int x = 0; x < 6; ++x) V[x] = sb.v[3 + x][jj][lane];
       const int r = n_e - 1 - k;   // entry index within the track
-      if (SMOOTH && k > 0)
-        live = smooth_step(b, g, t, r, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
+      if (SMOOTH)
+        live = smooth_step(b, g, t, k, r, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
       else if (MODE == kReject)
         live = reject_step(fa, g, last - k, k, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
       else
