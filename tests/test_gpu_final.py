@@ -150,10 +150,13 @@ def test_final_fit_parity(ctx, kf, name, n, mode, dtype):
 
 
 def test_final_fit_barrel20_full_size(ctx, kf):
-    """100,000 FP32 tracks x 20 layers, one displaced hit on every tenth."""
+    """100,000 tracks x 20 layers, one displaced hit on every tenth, in FP32
+    and FP64."""
     say("final fit barrel20 100k fp32")
     ev = planted(generate(workloads()["barrel20"]))
     _case(ctx, kf, ev, torch.float32, 0, TOL32, 0.02, 0.002)
+    say("final fit barrel20 100k fp64")
+    _case(ctx, kf, ev, torch.float64, 0, TOL64, 0.0, 1e-4)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
