@@ -37,6 +37,7 @@ FLOP_SMOOTH_COMBINE = 1900
 FLOP_VJP_VALID_ENTRY = 2660
 FLOP_VJP_HOLE_ENTRY = 1550
 FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
@@ -131,9 +132,32 @@ def time_fit_kernel(ctx, fit_step, steps, warmup):
     return ms_call, total / launches
 
 
-def cpu_baseline(ev, seconds=10.0):
+def host_cpu():
+    """CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def cpu_baseline(ev, seconds=10.0, seconds_single=6.0, single_tracks=5000):
+    """The FP64 oracle (seeding + fit, torch CPU, vectorised over tracks) on
+    the host cores: the full batch repeated for ~`seconds` with torch's
+    default thread count, then a subset of `single_tracks` tracks on one
+    thread."""
     import torch
     from oracle import kf_oracle as O
+    from toygen import subset
     t0 = time.time()
     reps = 0
     while True:
@@ -142,8 +166,76 @@ def cpu_baseline(ev, seconds=10.0):
         if time.time() - t0 > seconds:
             break
     dt = time.time() - t0
-    return dict(value=reps * ev.n_tracks / dt, unit="tracks/s", cores=torch.get_num_threads(), kind="oracle",
-                sample=f"{reps} x full batch of {ev.n_tracks} tracks (seeding + fit, float64 torch CPU)")
+    threads = torch.get_num_threads()
+    sub = subset(ev, np.arange(min(single_tracks, ev.n_tracks)))
+    torch.set_num_threads(1)
+    try:
+        t1 = time.time()
+        reps1 = 0
+        while True:
+            O.fit_event(sub)
+            reps1 += 1
+            if time.time() - t1 > seconds_single:
+                break
+        dt1 = time.time() - t1
+    finally:
+        torch.set_num_threads(threads)
+    model, ncpu, avail = host_cpu()
+    return dict(value=reps * ev.n_tracks / dt, unit="tracks/s", cores=threads, kind="oracle",
+                sample=f"{reps} x full batch of {ev.n_tracks} tracks (seeding + fit, float64 torch CPU), "
+                       f"{threads} threads",
+                cpu_model=model, nproc=ncpu, cores_available=avail,
+                single_thread={"value": reps1 * sub.n_tracks / dt1, "unit": "tracks/s", "cores": 1,
+                               "sample": f"{reps1} x the first {sub.n_tracks} tracks, one torch thread"})
+
+
+def fp64_lane_fraction(ctx, K, ev, dt_out=None):
+    """How often the FP32 fit of a barrel batch (no holes) runs an update in
+    its FP64 lane: the prior position variance exceeds the hit variance by
+    more than 1e4 on an axis.  The prior at entry j >= 1 is the forward fit's
+    filtered state after entry j - 1 (its seg = 1 checkpoint) propagated to
+    entry j's layer with material (kf_propagate); entry 0 starts from the
+    diffuse seed covariance (unit position variances), which is always above
+    the ratio.  Also the fraction of tracks flagged KF_TRK_FP64_FALLBACK
+    (either FP64 form: this lane or the kappa > 1e6 inverse)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    dt = torch.float32
+    n = ev.n_tracks
+    t = K.event_tensors(ev, dt, dev)
+    geom = K.Geometry.from_toy(ev.geometry)
+    max_len = int(ev.lengths().max())
+    ck = torch.empty(28, n * max(1, max_len - 1), dtype=dt, device=dev)
+    out = K.fit_outputs(n, dt, dev)
+    ctx.seed_fit_tracks(t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"], geom, 0,
+                        checkpoints=ck, seg=1, max_len=max_len, out=out)
+    off = torch.as_tensor(ev.hit_offsets[:-1].astype(np.int64), device=dev)
+    lens = torch.as_tensor(ev.lengths().astype(np.int64), device=dev)
+    ok = (out["status"] & (K.TRK_BAD_INPUT | K.TRK_NO_CROSSING | K.TRK_NONFINITE)) == 0
+    lanes, updates = int((ok & (lens > 0)).sum().item()), int((ok & (lens > 0)).sum().item())
+    for j in range(1, max_len):
+        live = ok & (lens > j)
+        idx = torch.nonzero(live).flatten()
+        if idx.numel() == 0:
+            break
+        e = off[idx] + j
+        cols = idx + (j - 1) * n
+        st = ck[0:6, cols].contiguous()
+        cv = ck[6:27, cols].contiguous()
+        q = ck[27, cols].round().to(torch.int8).contiguous()
+        tgt = t["hit_layer"][e].contiguous()
+        frm = t["hit_layer"][e - 1].contiguous()
+        _, cp, _, _ = ctx.propagate(st, cv, q, tgt, geom, from_layer=frm, apply_material=True)
+        V = t["hit_cov"][:, e]
+        valid = t["hit_valid"][e] != 0
+        hi = (cp[0] > 1e4 * V[0]) | (cp[2] > 1e4 * V[2]) | (cp[5] > 1e4 * V[5])
+        lanes += int((hi & valid).sum().item())
+        updates += int(valid.sum().item())
+    flagged = int(((out["status"] & K.TRK_FP64_FALLBACK) != 0).sum().item())
+    return {"updates": updates, "fp64_lane_updates": lanes, "fp64_lane_fraction": lanes / max(updates, 1),
+            "tracks_flagged_fp64": flagged, "tracks_flagged_fp64_fraction": flagged / n,
+            "rule": "whole update in FP64 when a prior position variance > 1e4 x the hit variance on that axis; "
+                    "the 3x3 inverse alone in FP64 when kappa > 1e6, det <= 0 or non-finite"}
 
 
 def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
@@ -189,6 +281,9 @@ def bench_uneven(ctx, K, tune_fit, generate, workloads, args):
             "step": "kf_seed_fit_tracks, spaced seeding"}
 
 
+_EVENTS = {}
+
+
 def bench_adjoint(ctx, K, generate, workloads, args, seg=1):
     """d(sum chi2)/d(seed states, hit positions, alignment offsets) for
     100,000 FP32 tracks x 20 barrel layers: the forward fit writing
@@ -202,8 +297,10 @@ def bench_adjoint(ctx, K, generate, workloads, args, seg=1):
     import torch
     dev = torch.device("cuda", 0)
     wl = workloads()["align20"]
-    log("generating", wl.name, wl.n_tracks)
-    ev = generate(wl)
+    if "align20" not in _EVENTS:
+        log("generating", wl.name, wl.n_tracks)
+        _EVENTS["align20"] = generate(wl)
+    ev = _EVENTS["align20"]
     n = ev.n_tracks
     dt = torch.float32
     max_len = int(ev.lengths().max())
@@ -241,6 +338,9 @@ def bench_adjoint(ctx, K, generate, workloads, args, seg=1):
             "tracks_per_s": n / (ms_step * 1e-3), "ms_forward_with_checkpoints": ms_fwd, "ms_adjoint": ms_adj,
             "achieved_tflops_step": tf_step, "frac_fp32_peak_step": tf_step / FP32_PEAK_TFLOPS,
             "achieved_tflops_adjoint": tf_adj, "frac_fp32_peak_adjoint": tf_adj / FP32_PEAK_TFLOPS,
+            "frac_fp64_peak_adjoint": tf_adj / FP64_PEAK_TFLOPS,
+            "adjoint_arithmetic": "reverse pass in FP64 (FP32 forward recomputation), so its ceiling is the FP64 "
+                                  "vector peak",
             "checkpoint_bytes": ck.numel() * 4, "grad_align_finite": bool(torch.isfinite(ga).all().item())}
 
 
@@ -322,29 +422,45 @@ def bench_backward(ctx, K, ev, args, steps=None):
 
 
 def bench_search(ctx, K, args, sample=300):
-    """Combinatorial candidate search: 20,000 seeds (Kalman fit of each
-    track's first three hits) over 17 barrel layers whose pools hold the true
-    hits plus uniform noise at 2 hits/cm^2, beam 6.  Timed with the pool's
-    bins reused (the search proper) and with the binning.  A sample of the
-    seeds is checked against the FP64 search oracle (bit-exact hit lists on
-    the seeds it does not flag)."""
+    """Combinatorial candidate search: 20,000 seeds over 17 barrel layers whose
+    pools hold the true hits plus uniform noise at 2 hits/cm^2, beam 6.  The
+    seeds are made on the GPU: kf_seed_fit_tracks over each track's first three
+    hits (three-hit seed, then the Kalman fit of those hits, ending on the
+    third layer).  Timed with the pool's bins reused (the search proper) and
+    with the binning.  After timing, a sample of seeds is searched again from
+    the FP64 oracle's own seeds (rounded to FP32, so that both sides start
+    from identical values) and checked against the FP64 search oracle
+    (bit-exact hit lists on the seeds it does not flag)."""
     import torch
-    from oracle import kf_search as KS
-    from search_common import PLAN, SEED_LAYER, default_params, search_inputs
+    from toygen import generate, truncate, workloads
+    from toygen.generate import make_pools
     dev = torch.device("cuda", 0)
     log("generating search20")
-    wl, ev, g, pools, p, C, q = search_inputs()
-    n = p.shape[0]
-    IL = [(i, j) for i in range(6) for j in range(i + 1)]
-    f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt).contiguous()
-    st, cv = f(p.T, torch.float32), f(np.stack([C[:, i, j] for i, j in IL]), torch.float32)
-    qq, sl = f(q, torch.int8), f(np.full(n, SEED_LAYER), torch.int16)
-    pp, pc, pid = f(pools.pos, torch.float32), f(pools.cov, torch.float32), f(pools.hit_id, torch.int32)
+    wl = workloads()["search20"]
+    ev = generate(wl)
+    g = wl.geometry
+    pools = make_pools(wl, ev, first_layer=3, noise=True)
+    # pool positions and covariances as the FP32 the search takes (the oracle
+    # parity sample then sees the same values)
+    pools.pos = pools.pos.astype(np.float32).astype(np.float64)
+    pools.cov = pools.cov.astype(np.float32).astype(np.float64)
+    plan = list(range(3, g.n_layers))
+    n = ev.n_tracks
     geom = K.Geometry.from_toy(g)
+    f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt).contiguous()
+    # seeds on the GPU path: seeding + fit of the first three entries of every track
+    tr = truncate(ev, np.full(n, 3))
+    t3 = K.event_tensors(tr, torch.float32, dev)
+    seed_out = K.fit_outputs(n, torch.float32, dev)
+    ctx.seed_fit_tracks(t3["hit_offsets"], t3["hit_layer"], t3["hit_valid"], t3["hit_pos"], t3["hit_cov"], geom, 0,
+                        max_len=3, out=seed_out)
+    st, cv, qq = seed_out["state"], seed_out["cov"], seed_out["charge"]
+    sl = f(tr.hit_layer[tr.hit_offsets[1:] - 1], torch.int16)   # the layer of each seed's third hit
+    pp, pc, pid = f(pools.pos, torch.float32), f(pools.cov, torch.float32), f(pools.hit_id, torch.int32)
     out = []
 
-    def run(prm):
-        out[:] = ctx.score_hits(st, cv, qq, sl, PLAN, geom, prm, pools.layer_offsets, pp, pc, pid)
+    def run(prm, seeds=(st, cv, qq, sl)):
+        out[:] = ctx.score_hits(*seeds, plan, geom, prm, pools.layer_offsets, pp, pc, pid)
 
     prm_bin = K.SearchParams(g.n_layers, beam=6)
     prm_reuse = K.SearchParams(g.n_layers, beam=6, reuse_bins=True)
@@ -359,19 +475,32 @@ def bench_search(ctx, K, args, sample=300):
         dd[:] = ctx.remove_duplicates(cand_h[:, 0, :], cand_s[:, 0], 0.5)
 
     ms_dd = time_loop(dedup, args.steps, args.warmup)
-    res = {"seeds": n, "layers": len(PLAN), "beam": 6, "pool_hits": int(pools.pos.shape[1]), "ms": ms,
+    true_frac = float(np.mean([[h >= 0 and pools.track[h] == t for h in hits[t, 0]] for t in range(0, n, 10)]))
+    res = {"seeds": n, "layers": len(plan), "beam": 6, "pool_hits": int(pools.pos.shape[1]), "ms": ms,
            "seeds_per_s": n / (ms * 1e-3), "ms_with_binning": ms_total, "ms_binning": ms_total - ms,
-           "ms_dedup": ms_dd, "dedup_kept": int(dd[0].sum().item()), "dedup_frac": 0.5}
+           "ms_dedup": ms_dd, "dedup_kept": int(dd[0].sum().item()), "dedup_frac": 0.5,
+           "seeds_from": "kf_seed_fit_tracks over each track's first three hits (FP32, on the GPU)",
+           "rank0_true_hit_fraction": true_frac}
     if not args.no_accuracy:
-        pick = np.random.default_rng(7).choice(n, sample, replace=False)
-        o = KS.score_hits(p[pick], C[pick], q[pick], np.full(sample, SEED_LAYER), PLAN, g, pools, default_params(g))
-        same = np.all(hits[pick] == o["hits"], axis=(1, 2))
+        # parity sample: GPU and oracle searches from the oracle's seeds
+        from oracle import kf_search as KS
+        from search_common import default_params, seeds_from_three_hits
+        from toygen import subset
+        pick = np.sort(np.random.default_rng(7).choice(n, sample, replace=False))
+        evs = subset(ev, pick)
+        p, C, q = seeds_from_three_hits(evs, g)
+        IL = [(i, j) for i in range(6) for j in range(i + 1)]
+        seeds = (f(p.T, torch.float32), f(np.stack([C[:, i, j] for i, j in IL]), torch.float32), f(q, torch.int8),
+                 f(np.full(sample, 2), torch.int16))
+        run(prm_reuse, seeds)
+        hs = out[0].cpu().numpy()
+        o = KS.score_hits(p, C, q, np.full(sample, 2), plan, g, pools, default_params(g))
+        same = np.all(hs == o["hits"], axis=(1, 2))
         fl = o["flagged"]
-        true_frac = float(np.mean([[h >= 0 and pools.track[h] == t for h in hits[t, 0]] for t in pick]))
         res["parity_sample"] = {"seeds": sample, "flagged": int(fl.sum()), "identical": int(same.sum()),
                                 "unflagged_mismatch": int((~same & ~fl).sum()),
-                                "rank0_true_hit_fraction": true_frac,
-                                "window_hits_per_candidate_layer": o["n_window_hits"] / (sample * len(PLAN))}
+                                "seeds_from": "FP64 oracle three-hit fit rounded to FP32 (both sides)",
+                                "window_hits_per_candidate_layer": o["n_window_hits"] / (sample * len(plan))}
     return res
 
 
@@ -567,6 +696,7 @@ def main():
             "tracks_compared": int(ok.sum()), "ill_conditioned": int(bad.sum()),
             "tolerance": {"param": 1e-4, "chi2": 1e-3,
                           "tail": "at most 0.1% of the tracks may exceed it, by < 10x (param) / 20x (chi2)"}}
+    line["fp64_lanes_barrel20"] = fp64_lane_fraction(ctx, K, ev)
     if not args.no_backward:
         # the forward pass in the launch shape tuned for this batch
         line["backward_barrel20"] = bench_backward(ctx, K, ev, args)
@@ -576,7 +706,10 @@ def main():
         # the forward fit in the launch shape tuned for 100k tracks x 20 layers
         # (the mixed26 leg retunes the context for its own batch)
         ctx.set_fit_launch(torch.float32, *r32["launch"])
-        line["fwd_adjoint_align20"] = bench_adjoint(ctx, K, generate, workloads, args)
+        # segment recomputation (checkpoint every 5th entry: the configured
+        # form), and the checkpoint before every entry as a memory-for-speed point
+        line["fwd_adjoint_align20"] = bench_adjoint(ctx, K, generate, workloads, args, seg=5)
+        line["fwd_adjoint_align20_seg1"] = bench_adjoint(ctx, K, generate, workloads, args, seg=1)
     if not args.no_search:
         line["search20"] = bench_search(ctx, K, args)
     if not args.no_cpu_baseline:

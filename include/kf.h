@@ -25,8 +25,15 @@
  *   array is at base[i*ld + t]; ld >= n.  Float arrays hold float (KF_F32) or
  *   double (KF_F64) as selected by the precision argument.
  *   `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
- *   and return; none synchronises the stream.  No call allocates device
- *   memory except kf_create and kf_reserve.
+ *   and return; none synchronises the stream.
+ *   Device memory: kf_create allocates a few bytes of counters and
+ *   kf_reserve the packed-layout workspace.  kf_score_hits, kf_fit_adjoint
+ *   (its alignment reduction) and kf_remove_duplicates keep a context-owned
+ *   workspace that they grow on demand (hipMalloc, which can synchronise the
+ *   device and must not happen under graph capture); a call with sizes no
+ *   larger than an earlier call's on the same context allocates nothing.
+ *   kf_set_kernel_timing creates events and kf_set_fit_graph captures graphs.
+ *   No other call allocates device memory.
  *   n = 0 is a no-op (array pointers may then be NULL).
  *   Errors: every call returns a kf_status.  KF_ERR_ARG is returned before any
  *   device work for a null pointer, n < 0, ld < n, a bad geometry or another
@@ -113,7 +120,9 @@ int kf_make_seeds(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                   void *seed_state, void *seed_cov, int8_t *seed_charge,
                   uint32_t *trk_status, void *stream);
 
-/* Propagate n tracks to their target layers (rows a1-a3 of the hot path):
+/* Propagate n tracks to their target layers (the track-candidate propagation
+ * the paper names as a vectorised key computation, Sec. 3.1, and the
+ * propagation step of track finding, Sec. 2.2):
  * exact helix in the uniform field to the first admissible crossing of the
  * target surface, the surface-to-surface Jacobian F (including the dependence
  * of the path length on the state), C' = F C F^T, and, if apply_material, the
@@ -133,7 +142,9 @@ int kf_propagate(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                  void *state_out, void *cov_out, void *path_len,
                  uint32_t *trk_status, void *stream);
 
-/* Kalman update with one 3-D hit per track (rows a4-a5): r = m - (x, y, z),
+/* Kalman update with one 3-D hit per track (the Kalman-filter calculations of
+ * Sec. 2.2 and Sec. 3.1; the chi2 is the one the per-iteration cuts of
+ * Sec. 3.2 apply to): r = m - (x, y, z),
  * S = C_pos + V, S^-1 (FP32: cofactors, recomputed in FP64 when the condition
  * estimate ||S||inf ||S^-1||inf exceeds 1e6, det <= 0 or non-finite),
  * chi2 = r^T S^-1 r, K = C H^T S^-1, p += K r, symmetrised Joseph form
@@ -146,7 +157,9 @@ int kf_update(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
               const void *hit_pos, const void *hit_cov,
               void *chi2, uint32_t *trk_status, void *stream);
 
-/* Forward Kalman fit of n tracks with uneven hit lists (row a6).
+/* Forward Kalman fit of n tracks with uneven hit lists (the layer-by-layer
+ * propagate-and-update loop of Sec. 2.2 run over the hits of each track; a seed
+ * carries an estimate, Sec. 2.2, and layers are r-z boxes, Sec. 3.1).
  * Track t owns entries [hit_offsets[t], hit_offsets[t+1]) of the hit arrays,
  * in crossing order: hit_layer[e] (layer id), hit_valid[e] (0 = hole: the
  * layer's material is applied but no update), hit_pos[3][n_hits],
@@ -346,7 +359,8 @@ typedef struct {
 } kf_search_params;
 
 /* Combinatorial candidate search with chi2 scoring of the candidate hits
- * (row a7; the forward search of Sec. 2.2 over a layer plan, Sec. 3.1), FP32.
+ * (the forward search of Sec. 2.2 over a layer plan, Sec. 3.1, with the
+ * chi2 cut and candidate score of Sec. 3.2 and 3.3), FP32.
  * Every seed starts with one candidate (score 0).  For each layer L of
  * layer_plan (barrel layers), each live candidate is propagated to L with its
  * material (kf_propagate's crossing rule; a candidate without a crossing ends)
@@ -389,10 +403,11 @@ int kf_score_hits(kf_ctx *ctx, int64_t n, int64_t ld,
                   int32_t *cand_hits, float *cand_score, float *cand_state,
                   uint32_t *trk_status, void *stream);
 
-/* Gradient of L = sum_t w_t chi2_t of kf_fit_tracks (row a8) with respect to
- * the seed states, the hit positions and the per-layer alignment offsets, by
- * a hand-written reverse pass (the alignment application the paper's
- * differentiable fit builds on).  Every entry is reversed in three parts:
+/* Gradient of L = sum_t w_t chi2_t of kf_fit_tracks with respect to the seed
+ * states, the hit positions and the per-layer alignment offsets, by a
+ * hand-written reverse pass.  The paper has no such pass: it is an addition
+ * built on the fit of Sec. 2.2, for alignment and for training code that
+ * consumes the fit's chi2.  Every entry is reversed in three parts:
  * the update (whose Joseph form has the short form's derivative at the
  * optimal gain), the material noise Q(p), and the transport p' = g(p),
  * C' = F C F^T, where the path length s(p) enters by the implicit-function

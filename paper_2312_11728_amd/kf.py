@@ -185,6 +185,14 @@ def _need(t, name, dtype=None, dev=None, rows=None):
     return t
 
 
+def _need_offsets(hit_offsets, n, dev):
+    """CSR offsets of n tracks: int32 [n + 1] on the device."""
+    _need(hit_offsets, "hit_offsets", torch.int32, dev)
+    if hit_offsets.dim() != 1 or hit_offsets.numel() != n + 1:
+        raise ValueError(f"hit_offsets must hold n + 1 = {n + 1} entries, got {tuple(hit_offsets.shape)}")
+    return hit_offsets
+
+
 def _stream(dev):
     return _vp(torch.cuda.current_stream(dev).cuda_stream)
 
@@ -248,10 +256,12 @@ class Context:
     def make_seeds(self, hit_offsets, hit_valid, hit_pos, bz, mode=0, out=None):
         dev = self.device
         _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        if hit_offsets.dim() != 1 or hit_offsets.numel() < 1:
+            raise ValueError("hit_offsets must be a 1-D tensor of n + 1 entries")
+        n = hit_offsets.shape[0] - 1
         _need(hit_valid, "hit_valid", torch.uint8, dev)
         _need(hit_pos, "hit_pos", None, dev, rows=3)
         dt = hit_pos.dtype
-        n = hit_offsets.shape[0] - 1
         if out is None:
             out = (torch.empty(6, n, dtype=dt, device=dev), torch.empty(21, n, dtype=dt, device=dev),
                    torch.empty(n, dtype=torch.int8, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
@@ -308,7 +318,7 @@ class Context:
         _need(seed_state, "seed_state", dt, dev, rows=6)
         _need(seed_cov, "seed_cov", dt, dev, rows=21)
         _need(seed_charge, "seed_charge", torch.int8, dev)
-        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need_offsets(hit_offsets, n, dev)
         _need(hit_layer, "hit_layer", torch.int16, dev)
         _need(hit_valid, "hit_valid", torch.uint8, dev)
         _need(hit_pos, "hit_pos", dt, dev, rows=3)
@@ -342,7 +352,7 @@ class Context:
         _need(st_in, "state", dt, dev, rows=6)
         _need(cov_in, "cov", dt, dev, rows=21)
         _need(q_in, "charge", torch.int8, dev)
-        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need_offsets(hit_offsets, n, dev)
         _need(hit_layer, "hit_layer", torch.int16, dev)
         _need(hit_valid, "hit_valid", torch.uint8, dev)
         _need(hit_pos, "hit_pos", dt, dev, rows=3)
@@ -378,7 +388,7 @@ class Context:
         _need(st_in, "state", dt, dev, rows=6)
         _need(cov_in, "cov", dt, dev, rows=21)
         _need(q_in, "charge", torch.int8, dev)
-        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need_offsets(hit_offsets, n, dev)
         _need(hit_layer, "hit_layer", torch.int16, dev)
         _need(hit_valid, "hit_valid", torch.uint8, dev)
         _need(hit_pos, "hit_pos", dt, dev, rows=3)
@@ -450,7 +460,7 @@ class Context:
                              (checkpoints, "checkpoints", 28)):
             _need(t_, nm, dt, dev, rows=rows)
         _need(q_in, "charge", torch.int8, dev)
-        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need_offsets(hit_offsets, n, dev)
         _need(hit_layer, "hit_layer", torch.int16, dev)
         _need(hit_valid, "hit_valid", torch.uint8, dev)
         if st_in.stride(0) != n or cov_in.stride(0) != n:
@@ -458,6 +468,10 @@ class Context:
         if checkpoints.shape[1] != n * max(1, max_len - 1):
             raise ValueError("checkpoints must be [28, n * (max_len - 1)] (seg = 1)")
         status = fwd["status"] if use_status else None
+        if status is not None:
+            _need(status, "status", torch.int32, dev)
+            if status.numel() != n:
+                raise ValueError(f"status must hold n = {n} entries")
         if out is None:
             out = fit_outputs(n, dt, dev)
         _need_outputs(out, n, dt, dev)
@@ -465,8 +479,10 @@ class Context:
             smooth = dict(state=torch.full((6, max_len, n), float("nan"), dtype=dt, device=dev),
                           cov=torch.full((21, max_len, n), float("nan"), dtype=dt, device=dev))
         for k, rows in (("state", 6), ("cov", 21)):
-            if smooth[k].shape != (rows, max_len, n) or smooth[k].dtype != dt or not smooth[k].is_contiguous():
-                raise ValueError(f"smooth[{k!r}] must be a contiguous [{rows}, {max_len}, {n}] tensor of {dt}")
+            s_ = smooth.get(k) if isinstance(smooth, dict) else None
+            if (not torch.is_tensor(s_) or tuple(s_.shape) != (rows, max_len, n) or s_.dtype != dt
+                    or s_.device != dev or not s_.is_contiguous()):
+                raise ValueError(f"smooth[{k!r}] must be a contiguous [{rows}, {max_len}, {n}] tensor of {dt} on {dev}")
         _check(lib().kf_smooth_tracks(self.handle, _prec(dt), n, n, _ptr(st_in), _ptr(cov_in), _ptr(q_in),
                                       _ptr(status), _ptr(checkpoints), _ptr(hit_offsets), _ptr(hit_layer),
                                       _ptr(hit_valid), hit_pos.shape[1], _ptr(hit_pos), _ptr(hit_cov),
@@ -483,8 +499,10 @@ class Context:
         status holds the seeding and the fit bits."""
         dev = self.device
         dt = hit_pos.dtype
-        n = hit_offsets.shape[0] - 1
         _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        if hit_offsets.dim() != 1 or hit_offsets.numel() < 1:
+            raise ValueError("hit_offsets must be a 1-D tensor of n + 1 entries")
+        n = hit_offsets.shape[0] - 1
         _need(hit_layer, "hit_layer", torch.int16, dev)
         _need(hit_valid, "hit_valid", torch.uint8, dev)
         _need(hit_pos, "hit_pos", dt, dev, rows=3)
@@ -543,18 +561,20 @@ class Context:
 
     def fit_adjoint(self, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov,
                     geom: Geometry, checkpoints, seg, max_len, fwd_status, align=None, dL_dchi2=None,
-                    want_align=True):
+                    want_align=True, out=None):
         """Reverse pass of fit_tracks (kf_fit_adjoint): returns (grad_seed [6, n],
         grad_hit_pos [3, n_hits], grad_align [2, n_layers] or None).  The inputs,
         seg and max_len must be those of the fit_tracks call that wrote
-        `checkpoints` and `fwd_status`."""
+        `checkpoints` and `fwd_status`.  out:
+        None, or a (grad_seed, grad_hit_pos, grad_align or None) triple of
+        preallocated tensors of those shapes."""
         dev = self.device
         dt = seed_state.dtype
         n = seed_state.shape[1]
         _need(seed_state, "seed_state", dt, dev, rows=6)
         _need(seed_cov, "seed_cov", dt, dev, rows=21)
         _need(seed_charge, "seed_charge", torch.int8, dev)
-        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        _need_offsets(hit_offsets, n, dev)
         _need(hit_layer, "hit_layer", torch.int16, dev)
         _need(hit_valid, "hit_valid", torch.uint8, dev)
         _need(hit_pos, "hit_pos", dt, dev, rows=3)
@@ -565,9 +585,20 @@ class Context:
             _need(align, "align", dt, dev, rows=2)
         if dL_dchi2 is not None:
             _need(dL_dchi2, "dL_dchi2", dt, dev)
-        gs = torch.empty(6, n, dtype=dt, device=dev)
-        gh = torch.empty(3, hit_pos.shape[1], dtype=dt, device=dev)
-        ga = torch.empty(2, geom.n_layers, dtype=dt, device=dev) if want_align else None
+        if out is None:
+            gs = torch.empty(6, n, dtype=dt, device=dev)
+            gh = torch.empty(3, hit_pos.shape[1], dtype=dt, device=dev)
+            ga = torch.empty(2, geom.n_layers, dtype=dt, device=dev) if want_align else None
+        else:
+            gs, gh, ga = out
+            _need(gs, "grad_seed", dt, dev, rows=6)
+            _need(gh, "grad_hit_pos", dt, dev, rows=3)
+            if gs.shape[1] != n or gh.shape[1] != hit_pos.shape[1]:
+                raise ValueError("grad_seed must be [6, n] and grad_hit_pos [3, n_hits]")
+            if ga is not None:
+                _need(ga, "grad_align", dt, dev, rows=2)
+                if ga.shape[1] != geom.n_layers:
+                    raise ValueError("grad_align must be [2, n_layers]")
         _check(lib().kf_fit_adjoint(self.handle, _prec(dt), n, seed_state.stride(0), _ptr(seed_state),
                                     _ptr(seed_cov), _ptr(seed_charge), _ptr(hit_offsets), _ptr(hit_layer),
                                     _ptr(hit_valid), hit_pos.shape[1], _ptr(hit_pos), _ptr(hit_cov),

@@ -324,3 +324,53 @@ def test_output_dict_is_checked_before_any_launch():
     for out in bad:
         with pytest.raises(ValueError):
             kf._need_outputs(out, 5, torch.float32, dev)
+
+
+def _cpu_context():
+    """A binding object whose checks run on CPU tensors (no library context:
+    every case below is refused before any call into the library)."""
+    import torch
+    c = object.__new__(kf.Context)
+    c.device = torch.device("cpu")
+    c.handle = None
+    return c
+
+
+def _smooth_inputs(n=4, nh=12, max_len=5):
+    import torch
+    dt = torch.float32
+    fwd = kf.fit_outputs(n, dt, torch.device("cpu"))
+    hits = (torch.arange(0, nh + 1, nh // n, dtype=torch.int32), torch.zeros(nh, dtype=torch.int16),
+            torch.ones(nh, dtype=torch.uint8), torch.zeros(3, nh, dtype=dt), torch.zeros(6, nh, dtype=dt))
+    ck = torch.zeros(28, n * (max_len - 1), dtype=dt)
+    sm = dict(state=torch.zeros(6, max_len, n, dtype=dt), cov=torch.zeros(21, max_len, n, dtype=dt))
+    return fwd, ck, hits, sm
+
+
+def test_binding_checks_smoother_buffers_status_and_offsets():
+    """smooth_tracks refuses a smoothing buffer on another device, a status
+    of the wrong type or size, and every entry point refuses CSR offsets that
+    do not hold n + 1 entries."""
+    import torch
+    c = _cpu_context()
+    g = _geom(1)
+    fwd, ck, hits, sm = _smooth_inputs()
+    bad_sm = dict(sm, cov=torch.zeros(21, 5, 4, dtype=torch.float32, device="meta"))
+    with pytest.raises(ValueError, match="smooth"):
+        c.smooth_tracks(fwd, ck, *hits, g, max_len=5, smooth=bad_sm)
+    with pytest.raises(TypeError, match="status"):
+        c.smooth_tracks(dict(fwd, status=torch.zeros(4, dtype=torch.int64)), ck, *hits, g, max_len=5, smooth=sm)
+    with pytest.raises(ValueError, match="status"):
+        c.smooth_tracks(dict(fwd, status=torch.zeros(3, dtype=torch.int32)), ck, *hits, g, max_len=5, smooth=sm)
+    short = (hits[0][:-1],) + hits[1:]
+    with pytest.raises(ValueError, match="hit_offsets"):
+        c.smooth_tracks(fwd, ck, *short, g, max_len=5, smooth=sm)
+    with pytest.raises(ValueError, match="hit_offsets"):
+        c.backward_fit(fwd, *short, g)
+    with pytest.raises(ValueError, match="hit_offsets"):
+        c.final_fit(fwd, *short, g)
+    seeds = (fwd["state"], fwd["cov"], fwd["charge"])
+    with pytest.raises(ValueError, match="hit_offsets"):
+        c.fit_tracks(*seeds, *short, g)
+    with pytest.raises(ValueError, match="hit_offsets"):
+        c.fit_adjoint(*seeds, *short, g, ck, 1, 5, fwd["status"])

@@ -366,3 +366,208 @@ def test_smoothed_pulls_at_every_layer():
             mu, sd = vv.mean(), vv.std()
             assert abs(mu) < 5.0 / math.sqrt(vv.size), (l, k, mu)
             assert abs(sd - 1.0) < (0.06 if l >= 3 else 0.25), (l, k, sd)
+
+
+def _frame5(p, kind_b):
+    """[6, 5] surface basis at position p (barrel: tangent, z; disk: x, y),
+    built from the geometry alone."""
+    B = np.zeros((6, 5))
+    if kind_b:
+        r = math.hypot(p[0], p[1])
+        B[0, 0], B[1, 0], B[2, 1] = -p[1] / r, p[0] / r, 1.0
+    else:
+        B[0, 0], B[1, 1] = 1.0, 1.0
+    B[3, 2] = B[4, 3] = B[5, 4] = 1.0
+    return B
+
+
+def test_smoother_equals_batch_conditioning_at_every_entry():
+    """The two-filter smoother against Gaussian conditioning of the whole
+    linearised problem on all of a track's hits, entry by entry.
+
+    Tracks on exact helices (no scattering, no smearing), then every hit moved
+    along its surface by 1e-6 of its resolution: the filter's states stay
+    close enough to the truth for the helix model to be linear (the
+    backward pass restarts from a covariance scaled by 1e6, so its first
+    steps move its state by ~1e3 times the hit offset in units of the final
+    sigma; at offsets of 1e-4 sigma the covariances already differ by 2e-5
+    through the moved linearisation point), so the smoothed state is the
+    linear map of the hit offsets that conditioning fixes.  The linear model about the true trajectory T_k uses
+    the oracle's transport Jacobian F_k and material Q_k (pinned elsewhere
+    against finite differences and the kick covariance):
+    x_0 = seed + w_0, x_k = T_k + F_k (x_{k-1} - T_{k-1}) + w_k, hit
+    y_k = x_k[:3] + v_k, with the seed's prior covariance and V_k.  Then
+    E[x_k | y] and Cov[x_k | y] follow from the stacked Gaussian.  The
+    backward pass restarts from the forward result scaled by 1e6, so its
+    double use of the forward information enters at 1e-6.  Compared on the
+    surface's five directions (the normal is a null vector of both) for
+    every entry after the seed entry, whose forward state is a full 6-D
+    seed (the combination on the surface then drops the normal direction
+    that conditioning would keep).  Bounds: state error below 1e-3 of the
+    conditioned offset itself, covariance below 5e-6 in correlation units
+    (measured: ~5e-5 and ~1e-6)."""
+    worst_x, worst_c = _smoother_vs_batch()
+    assert worst_x < 1e-3, worst_x
+    assert worst_c < 5e-6, worst_c
+
+
+def test_smoother_batch_pin_is_sharp(monkeypatch):
+    """Mistakes planted in the oracle's smoother fail the pin above: the
+    combination without its K C_b K^T term, and the backward prediction
+    taken after the layer's material instead of before it."""
+    real = O.combine_on_surface
+
+    def no_kcbk(pf, Cf, pb, Cb, kind, pos):
+        ps, Cs = real(pf, Cf, pb, Cb, kind, pos)
+        B = O.surface_frame(pf, kind, pos)
+        K = Cf @ B @ torch.linalg.inv(B.transpose(1, 2) @ (Cf + Cb) @ B) @ B.transpose(1, 2)
+        return ps, Cs - K @ Cb @ K.transpose(1, 2)
+    monkeypatch.setattr(O, "combine_on_surface", no_kcbk)
+    wx, wc = _smoother_vs_batch()
+    assert wc > 1e-2
+    monkeypatch.setattr(O, "combine_on_surface", real)
+    real_prop = O.propagate
+
+    def prop_with_material(p, C, q, kind, pos, x0, geom, apply_material=True, same=None):
+        return real_prop(p, C, q, kind, pos, x0, geom, apply_material=True, same=same)
+    monkeypatch.setattr(O, "propagate", prop_with_material)
+    wx, wc = _smoother_vs_batch()
+    assert wc > 1e-3
+
+
+
+def _smoother_vs_batch():
+    wl = workloads()["barrel10"]
+    g = wl.geometry
+    ev = generate(wl, 12, smear=False, scatter=False, holes=False)
+    keep = np.nonzero(ev.lengths() == g.n_layers)[0][:6]
+    assert keep.size >= 4
+    rng = np.random.default_rng(11)
+    hp = ev.hit_pos.copy()
+    for e in range(ev.n_hits):
+        x, y = hp[0, e], hp[1, e]
+        r = math.hypot(x, y)
+        a, b = rng.normal(size=2) * 1e-6 * np.array([0.003, 0.01])
+        hp[0, e] += -y / r * a
+        hp[1, e] += x / r * a
+        hp[2, e] += b
+    sp, sC, sq, _ = O.make_seeds(ev.hit_offsets, ev.hit_valid, hp, g.bz)
+    fwd = O.fit_tracks(sp, sC, sq, ev.hit_offsets, ev.hit_layer, ev.hit_valid, torch.tensor(hp), ev.hit_cov, g,
+                       record=True)
+    out = O.backward_fit(fwd["p"], fwd["C"], fwd["q"], fwd["status"], ev.hit_offsets, ev.hit_layer, ev.hit_valid,
+                         torch.tensor(hp), ev.hit_cov, g, cov_scale=1e6, smooth_from=fwd)
+    H = np.concatenate([np.eye(3), np.zeros((3, 3))], 1)
+    worst_x, worst_c = 0.0, 0.0
+    for t in keep:
+        e0, e1 = int(ev.hit_offsets[t]), int(ev.hit_offsets[t + 1])
+        N = e1 - e0
+        q = torch.tensor([float(ev.charge[t])], dtype=DT)
+        T = ev.truth[e0:e1]
+        Fs, Qs, Vs = [], [], []
+        for k in range(N):
+            lay = int(ev.hit_layer[e0 + k])
+            kind = torch.tensor([int(g.kind[lay])])
+            pos = torch.tensor([float(g.pos[lay])], dtype=DT)
+            if k == 0:
+                F = np.eye(6)
+            else:
+                pk = torch.tensor(T[k - 1][None])
+                s, ok = O.crossing(pk, q, kind, pos, g.bz)
+                assert bool(ok[0])
+                F = O.jacobian(pk, q, s, kind, g.bz)[0].numpy()
+            Q, _ = O.process_noise(torch.tensor(T[k][None]), kind, torch.tensor([float(g.x_over_x0[lay])], dtype=DT),
+                                   g.mass)
+            Fs.append(F)
+            Qs.append(Q[0].numpy())
+            Vs.append(O.unpack_sym(ev.hit_cov[:, e0 + k:e0 + k + 1], 3)[0].numpy())
+        # z = (x_0 - T_0, w_0, ..., w_{N-1}); x_k - T_k = M_k z
+        nz = 6 * (N + 1)
+        Cz = np.zeros((nz, nz))
+        Cz[:6, :6] = sC[t].numpy()
+        for k in range(N):
+            Cz[6 * (k + 1):6 * (k + 2), 6 * (k + 1):6 * (k + 2)] = Qs[k]
+        maps = []
+        M = np.zeros((6, nz))
+        M[:, :6] = np.eye(6)
+        for k in range(N):
+            M = Fs[k] @ M
+            M[:, 6 * (k + 1):6 * (k + 2)] += np.eye(6)
+            maps.append(M.copy())
+        d0 = sp[t].numpy() - T[0]
+        d0[4] = math.remainder(d0[4], 2 * math.pi)
+        z0 = np.zeros(nz)
+        z0[:6] = d0
+        A = np.concatenate([H @ Mk for Mk in maps], 0)
+        Vy = np.zeros((3 * N, 3 * N))
+        for k in range(N):
+            Vy[3 * k:3 * k + 3, 3 * k:3 * k + 3] = Vs[k]
+        Syy = A @ Cz @ A.T + Vy
+        dy = (hp[:, e0:e1].T - T[:, :3]).reshape(-1) - A @ z0
+        sol = np.linalg.solve(Syy, dy)
+        for k in range(1, N):
+            Sxy = maps[k] @ Cz @ A.T
+            xb = maps[k] @ z0 + Sxy @ sol                          # E[x_k | y] - T_k
+            Cb = maps[k] @ Cz @ maps[k].T - Sxy @ np.linalg.solve(Syy, Sxy.T)
+            B = _frame5(T[k], int(g.kind[int(ev.hit_layer[e0 + k])]) == 0)
+            xs = out["ps"][e0 + k].numpy() - T[k]
+            xs[4] = math.remainder(xs[4], 2 * math.pi)
+            Cs = out["Cs"][e0 + k].numpy()
+            Cb5, Cs5 = B.T @ Cb @ B, B.T @ Cs @ B
+            sd = np.sqrt(np.diag(Cb5))
+            off = float(np.linalg.norm(B.T @ xb / sd))
+            worst_x = max(worst_x, float(np.linalg.norm(B.T @ (xs - xb) / sd)) / off)
+            worst_c = max(worst_c, float(np.abs((Cs5 - Cb5) / np.outer(sd, sd)).max()))
+            # the offsets are ~1e-6 sigma, far above the FP64 rounding of the states
+            assert off > 1e-8
+    return worst_x, worst_c
+
+
+def _mp_combination(pf, Cf, Cb, B):
+    """C_f - K C_f and (I - K) C_f (I - K)^T + K C_b K^T in 50-digit
+    arithmetic, K = C_f B (B^T (C_f + C_b) B)^-1 B^T."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    Cf_, Cb_, B_ = mp.matrix(Cf.tolist()), mp.matrix(Cb.tolist()), mp.matrix(B.tolist())
+    K = Cf_ * B_ * mp.inverse(B_.T * (Cf_ + Cb_) * B_) * B_.T
+    A = mp.eye(6) - K
+    short = Cf_ - K * Cf_
+    sym = A * Cf_ * A.T + K * Cb_ * K.T
+    return short, sym
+
+
+def test_combination_forms_agree_in_high_precision():
+    """The smoother's covariance C_f - C_f (C_f + C_b)^+ C_f and the symmetric
+    form (I - K) C_f (I - K)^T + K C_b K^T are the same matrix when the
+    surface normal is a null vector of both inputs: checked at 50 digits
+    (mpmath) on random surface covariances, including a forward covariance
+    10^6 times wider than the backward one (a state near its diffuse seed).
+    There the FP64 difference C_f - K C_f loses about six digits while the
+    symmetric form (the oracle's combine_on_surface) keeps the 50-digit
+    result to ~1e-12 in correlation units."""
+    import mpmath as mp
+    rng = np.random.default_rng(3)
+    for case in range(12):
+        R = 30.0
+        ph = rng.uniform(-3, 3)
+        pf = torch.tensor([[R * math.cos(ph), R * math.sin(ph), rng.uniform(-50, 50), 0.5, ph + 0.1, 1.2]],
+                          dtype=DT)
+        B = O.surface_frame(pf, torch.tensor([O.BARREL]), torch.tensor([R], dtype=DT))[0].numpy()
+        scale_f = 1e6 if case % 3 == 0 else 1.0
+        Af, Ab = rng.normal(size=(5, 5)), rng.normal(size=(5, 5))
+        Cf = B @ (scale_f * (Af @ Af.T + 0.1 * np.eye(5))) @ B.T * 1e-4
+        Cb = B @ (Ab @ Ab.T + 0.1 * np.eye(5)) @ B.T * 1e-4
+        short, sym = _mp_combination(pf, Cf, Cb, B)
+        diff = max(abs(short[i, j] - sym[i, j]) for i in range(6) for j in range(6))
+        big = max(abs(sym[i, j]) for i in range(6) for j in range(6))
+        assert diff <= mp.mpf("1e-40") * big
+        exact = np.array([[float(sym[i, j]) for j in range(6)] for i in range(6)])
+        _, Cs = O.combine_on_surface(pf, torch.tensor(Cf[None]), pf.clone(), torch.tensor(Cb[None]),
+                                     torch.tensor([O.BARREL]), torch.tensor([R], dtype=DT))
+        sd = np.sqrt(np.diag(B.T @ exact @ B))
+        err = np.abs(B.T @ (Cs[0].numpy() - exact) @ B) / np.outer(sd, sd)
+        assert err.max() < 1e-11, (case, err.max())
+        if scale_f > 1.0:
+            # the FP64 difference form, for contrast: it does lose digits here
+            K = Cf @ B @ np.linalg.inv(B.T @ (Cf + Cb) @ B) @ B.T
+            e_short = np.abs(B.T @ (Cf - K @ Cf - exact) @ B) / np.outer(sd, sd)
+            assert e_short.max() > 100 * err.max()

@@ -79,3 +79,34 @@ def test_grazing_flag():
     p = torch.tensor([[30.0, 0.0, 0.0, 1.0, math.pi / 2 - 0.01, math.pi / 2]], dtype=DT)
     th0, g = O.highland_theta0(p, kind, torch.tensor([0.02], dtype=DT), 0.13957)
     assert bool(g[0]) and math.isfinite(float(th0[0]))
+
+
+def test_highland_angle_hand_worked_values():
+    """theta0 at fixed momentum, velocity and thickness, against numbers
+    worked out by hand from the PDG/Highland form
+    theta0 = 13.6 MeV / (beta c p) sqrt(x) (1 + 0.038 ln(x / beta^2)):
+    (a) beta = 1 (a massless probe), p = 1 GeV/c, x = 0.01 X0:
+        13.6e-3 * 0.1 * (1 + 0.038 ln 0.01) = 1.36e-3 * (1 - 0.17499646)
+        = 1.1220048e-3 rad;
+    (b) a pion (0.13957 GeV) at p = 1 GeV/c, x = 0.02 X0: beta^2 =
+        1 / (1 + 0.13957^2) = 1 / 1.01947978 = 0.98089243, beta = 0.99040013;
+        13.6e-3 / 0.99040013 = 1.3731824e-2; * sqrt(0.02) = 1.9419731e-3;
+        ln(0.02 / 0.98089243) = -3.8927305, * 0.038 = -0.14792376;
+        theta0 = 1.9419731e-3 * 0.85207624 = 1.6547092e-3 rad;
+    (c) the same pion crossing a barrel at 60 degrees from the normal
+        (cos = 0.5): x = 0.04 X0; 1.3731824e-2 * 0.2 = 2.7463647e-3;
+        ln(0.04 / 0.98089243) = -3.1995833, * 0.038 = -0.12158417;
+        theta0 = 2.7463647e-3 * 0.87841583 = 2.4124503e-3 rad.
+    The literals carry 8 digits, so they are compared to 3e-10 rad."""
+    kind = torch.tensor([O.BARREL] * 3)
+    p = torch.zeros(3, 6, dtype=DT)
+    p[:, 0] = 25.0                       # on a barrel at phi_pos = 0
+    p[:, 3] = 1.0                        # pT = 1 GeV/c at theta = pi/2: |p| = 1 GeV/c
+    p[:, 5] = math.pi / 2
+    p[2, 4] = math.pi / 3                # direction 60 degrees from the radial normal
+    x0 = torch.tensor([0.01, 0.02, 0.02], dtype=DT)
+    th0_a, _ = O.highland_theta0(p[:1], kind[:1], x0[:1], 1e-12)
+    th0_bc, _ = O.highland_theta0(p[1:], kind[1:], x0[1:], 0.13957)
+    assert abs(float(th0_a[0]) - 1.1220048e-3) < 3e-10
+    assert abs(float(th0_bc[0]) - 1.6547092e-3) < 3e-10
+    assert abs(float(th0_bc[1]) - 2.4124503e-3) < 3e-10
