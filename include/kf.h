@@ -437,6 +437,29 @@ int kf_fit_adjoint(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                    void *grad_seed, void *grad_hit_pos, void *grad_align,
                    const uint32_t *trk_status, void *stream);
 
+/* kf_fit_adjoint for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and results (bit-identical), but the block partials
+ * of the alignment reduction live in a fixed device array of this library
+ * (4 MiB per device, held until the process ends) instead of the context's
+ * growing workspace.  No hipMalloc, hipFree or other allocating call is made.
+ * Limit: with grad_align != NULL, n_hits <= 16,777,216 (FP32) or 8,388,608
+ * (FP64); larger batches get KF_ERR_ARG (grad_align == NULL needs no
+ * scratch and has no limit).  Every call on one device shares that device's
+ * array, which keeps the last call's contents (each call writes every
+ * partial it reads, so nothing needs clearing): calls that overlap on one
+ * device -- on two streams, two contexts or two host threads -- race and
+ * must be serialised by the caller. */
+int kf_fit_adjoint_noalloc(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                           const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
+                           const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
+                           int64_t n_hits, const void *hit_pos, const void *hit_cov,
+                           const kf_geometry *geom, const void *align,
+                           const void *checkpoints, int32_t seg, int32_t max_len,
+                           const void *dL_dchi2,
+                           void *grad_seed, void *grad_hit_pos, void *grad_align,
+                           const uint32_t *trk_status, void *stream);
+
 /* Reserve the workspace of kf_fit_tracks' packed hit layout for up to
  * max_tracks tracks of up to max_len (1..64) entries (about
  * 80 * max_tracks * max_len bytes; replaces an earlier reservation;

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "kf.h"
 #include "kf_backward.hpp"
@@ -33,6 +34,8 @@ struct kf_ctx {
   // block partials of the alignment-gradient reduction (grown on demand)
   void* red_mem = nullptr;
   size_t red_bytes = 0;
+  // device address of this device's fixed scratch array (kf_fit_adjoint_noalloc)
+  void* scratch = nullptr;
   // workspace of the candidate search (grown on demand) and the identity of
   // the pool its bins were built from
   void* search_mem = nullptr;
@@ -48,9 +51,22 @@ struct kf_ctx {
   int64_t t_dropped = 0;
 };
 
+// Fixed device scratch of kf_fit_adjoint_noalloc: the block partials of the
+// alignment-gradient reduction, for callers that cannot allocate.  Each device
+// the library runs on holds its own copy until the process ends.  Host code
+// never passes `scratch` itself to a kernel (on the host it is only a stand-in
+// for the symbol): it uses the device address hipGetSymbolAddress returns,
+// looked up once per device by kf_create with that device current.
+constexpr size_t kScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
 
 constexpr int32_t kMaxTimedLaunches = 4096;
 
@@ -71,6 +87,23 @@ int ok() {
 
 int hip_fail(hipError_t e, const char* where) {
   return fail(KF_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// Device address of the scratch array on `device`, which must be current;
+// looked up on the first call for that device and kept.
+int scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return fail(KF_ERR_DEVICE, "device %d outside the scratch table", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(KF_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return KF_OK;
 }
 
 int check_geometry(const kf_geometry* g, kf::GeomArgs* out) {
@@ -154,11 +187,13 @@ int kf_create(kf_ctx** out, int hip_device) {
     c->n_cu = prop.multiProcessorCount;
   e = hipMalloc(&c->d_counter, 64);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
+  const int rc = e == hipSuccess ? scratch_address(hip_device, &c->scratch) : int(KF_OK);
   hipSetDevice(prev);
-  if (e != hipSuccess) {
+  if (e != hipSuccess || rc != KF_OK) {
+    if (c->capture) hipStreamDestroy(c->capture);
     if (c->d_counter) hipFree(c->d_counter);
     delete c;
-    return hip_fail(e, "kf_create");
+    return e != hipSuccess ? hip_fail(e, "kf_create") : rc;
   }
   *out = c;
   return ok();
@@ -993,12 +1028,19 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   return ok();
 }
 
-int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state,
+}  // extern "C"
+
+namespace {
+
+// kf_fit_adjoint and kf_fit_adjoint_noalloc: the block partials of the
+// alignment reduction go to the context-owned buffer (grown on demand) or to
+// the fixed scratch array (no allocation, bounded size).
+int fit_adjoint_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state,
                    const void* seed_cov, const int8_t* seed_charge, const int32_t* hit_offsets,
                    const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
                    const void* hit_cov, const kf_geometry* geom, const void* align, const void* checkpoints,
                    int32_t seg, int32_t max_len, const void* dL_dchi2, void* grad_seed, void* grad_hit_pos,
-                   void* grad_align, const uint32_t* trk_status, void* stream) {
+                   void* grad_align, const uint32_t* trk_status, void* stream, bool no_alloc) {
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
@@ -1033,7 +1075,19 @@ int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const 
   if (n_seg < 1) n_seg = 1;
   hipStream_t s = (hipStream_t)stream;
   const size_t esz = prec == KF_F32 ? 4 : 8;
-  if (grad_align) {
+  void* partial = nullptr;
+  if (grad_align && no_alloc) {
+    const size_t need = size_t(kf::adjoint_partial_blocks(n_hits)) * 2 * kf::kMaxLayers * esz;
+    if (need > kScratchBytes)
+      return fail(KF_ERR_ARG,
+                  "kf_fit_adjoint_noalloc: n_hits = %lld needs %zu bytes of scratch, more than its fixed %zu "
+                  "(at most %lld hits in %s)",
+                  (long long)n_hits, need, kScratchBytes,
+                  (long long)(kScratchBytes / (2 * kf::kMaxLayers * esz)) * kf::kAlignPerBlock,
+                  prec == KF_F32 ? "FP32" : "FP64");
+    if (!ctx->scratch) return fail(KF_ERR_DEVICE, "kf_fit_adjoint_noalloc: no scratch address for this context");
+    partial = ctx->scratch;
+  } else if (grad_align) {
     const size_t need = size_t(kf::adjoint_partial_blocks(n_hits)) * 2 * kf::kMaxLayers * esz;
     if (need > ctx->red_bytes) {
       int prev = 0;
@@ -1050,6 +1104,7 @@ int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const 
       }
       ctx->red_bytes = need;
     }
+    partial = ctx->red_mem;
   }
   hipError_t e;
   if (prec == KF_F32) {
@@ -1063,7 +1118,7 @@ int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const 
     a.grad_seed = (float*)grad_seed;
     a.grad_hit = (float*)grad_hit_pos;
     a.grad_align = (float*)grad_align;
-    a.partial = (float*)ctx->red_mem;
+    a.partial = (float*)partial;
     e = kf::launch_adjoint(a, g, s);
   } else {
     kf::AdjArgs<double> a;
@@ -1076,11 +1131,37 @@ int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const 
     a.grad_seed = (double*)grad_seed;
     a.grad_hit = (double*)grad_hit_pos;
     a.grad_align = (double*)grad_align;
-    a.partial = (double*)ctx->red_mem;
+    a.partial = (double*)partial;
     e = kf::launch_adjoint(a, g, s);
   }
-  if (e != hipSuccess) return hip_fail(e, "kf_fit_adjoint");
+  if (e != hipSuccess) return hip_fail(e, no_alloc ? "kf_fit_adjoint_noalloc" : "kf_fit_adjoint");
   return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state,
+                   const void* seed_cov, const int8_t* seed_charge, const int32_t* hit_offsets,
+                   const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
+                   const void* hit_cov, const kf_geometry* geom, const void* align, const void* checkpoints,
+                   int32_t seg, int32_t max_len, const void* dL_dchi2, void* grad_seed, void* grad_hit_pos,
+                   void* grad_align, const uint32_t* trk_status, void* stream) {
+  return fit_adjoint_impl(ctx, prec, n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
+                          n_hits, hit_pos, hit_cov, geom, align, checkpoints, seg, max_len, dL_dchi2, grad_seed,
+                          grad_hit_pos, grad_align, trk_status, stream, false);
+}
+
+int kf_fit_adjoint_noalloc(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state,
+                           const void* seed_cov, const int8_t* seed_charge, const int32_t* hit_offsets,
+                           const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
+                           const void* hit_cov, const kf_geometry* geom, const void* align, const void* checkpoints,
+                           int32_t seg, int32_t max_len, const void* dL_dchi2, void* grad_seed, void* grad_hit_pos,
+                           void* grad_align, const uint32_t* trk_status, void* stream) {
+  return fit_adjoint_impl(ctx, prec, n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
+                          n_hits, hit_pos, hit_cov, geom, align, checkpoints, seg, max_len, dL_dchi2, grad_seed,
+                          grad_hit_pos, grad_align, trk_status, stream, true);
 }
 
 }  // extern "C"

@@ -28,7 +28,7 @@ EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_prop
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
            "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph",
            "kf_set_kernel_timing", "kf_fit_kernel_time", "kf_seed_fit_tracks", "kf_backward_fit",
-           "kf_smooth_tracks", "kf_final_fit", "kf_remove_duplicates"]
+           "kf_smooth_tracks", "kf_final_fit", "kf_remove_duplicates", "kf_fit_adjoint_noalloc"]
 
 BACKWARD_COV_SCALE = 100.0   # forward covariance scale at the start of the backward fit
 FINAL_CHI2_CUT = 30.0        # the final fit's default chi2 cut for one hit
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_adjoint.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                    ctypes.POINTER(KfGeometry), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_fit_adjoint_noalloc.argtypes = lib.kf_fit_adjoint.argtypes
     lib.kf_set_fit_launch.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i32, _i32, _i32]
     lib.kf_get_fit_launch.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
@@ -561,11 +562,12 @@ class Context:
 
     def fit_adjoint(self, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov,
                     geom: Geometry, checkpoints, seg, max_len, fwd_status, align=None, dL_dchi2=None,
-                    want_align=True, out=None):
+                    want_align=True, no_alloc=False, out=None):
         """Reverse pass of fit_tracks (kf_fit_adjoint): returns (grad_seed [6, n],
         grad_hit_pos [3, n_hits], grad_align [2, n_layers] or None).  The inputs,
         seg and max_len must be those of the fit_tracks call that wrote
-        `checkpoints` and `fwd_status`.  out:
+        `checkpoints` and `fwd_status`.  no_alloc: call kf_fit_adjoint_noalloc
+        (the library's fixed scratch instead of its growing workspace).  out:
         None, or a (grad_seed, grad_hit_pos, grad_align or None) triple of
         preallocated tensors of those shapes."""
         dev = self.device
@@ -599,7 +601,8 @@ class Context:
                 _need(ga, "grad_align", dt, dev, rows=2)
                 if ga.shape[1] != geom.n_layers:
                     raise ValueError("grad_align must be [2, n_layers]")
-        _check(lib().kf_fit_adjoint(self.handle, _prec(dt), n, seed_state.stride(0), _ptr(seed_state),
+        fn = lib().kf_fit_adjoint_noalloc if no_alloc else lib().kf_fit_adjoint
+        _check(fn(self.handle, _prec(dt), n, seed_state.stride(0), _ptr(seed_state),
                                     _ptr(seed_cov), _ptr(seed_charge), _ptr(hit_offsets), _ptr(hit_layer),
                                     _ptr(hit_valid), hit_pos.shape[1], _ptr(hit_pos), _ptr(hit_cov),
                                     ctypes.byref(geom.struct), _ptr(align), _ptr(checkpoints), int(seg),
