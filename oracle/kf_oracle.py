@@ -187,12 +187,10 @@ def crossing(p, q, kind, pos, bz, same=None):
 # a2: transport Jacobian (surface to surface)
 # --------------------------------------------------------------------------
 
-def jacobian(p, q, s, kind, bz):
-    """F = dp'/dp of the map 'propagate p to the surface', including the
-    dependence of the path length on p:
-        F = G + g_s (ds/dp),  ds/dp = -(dh/dp)/(dh/ds),
-    G = partials of the helix at fixed s, g_s = d(state)/ds, and h the surface
-    equation (barrel: x^2 + y^2 - R^2, disk: z - Z)."""
+def helix_partials(p, q, s, bz):
+    """The helix map at fixed transverse path s, differentiated: G = dp'/dp
+    with s held fixed, and g_s = dp'/ds = (cos phi(s), sin phi(s), cot theta,
+    0, w, 0)."""
     p, q, s = _t(p), _t(q), _t(s)
     x0, y0, z0, ipt, phi0, th = p.unbind(-1)
     w = _safe_omega(omega(q, ipt, bz))
@@ -227,6 +225,19 @@ def jacobian(p, q, s, kind, bz):
     ]
     G = torch.stack([torch.stack(r, dim=-1) for r in rows], dim=-2)
     g_s = torch.stack([cp, sp, cot, 0 * one, w, 0 * one], dim=-1)
+    return G, g_s
+
+
+def jacobian(p, q, s, kind, bz):
+    """F = dp'/dp of the map 'propagate p to the surface', including the
+    dependence of the path length on p:
+        F = G + g_s (ds/dp),  ds/dp = -(dh/dp)/(dh/ds),
+    G = partials of the helix at fixed s, g_s = d(state)/ds, and h the surface
+    equation (barrel: x^2 + y^2 - R^2, disk: z - Z)."""
+    p, q, s = _t(p), _t(q), _t(s)
+    G, g_s = helix_partials(p, q, s, bz)
+    cp, sp = g_s[..., 0], g_s[..., 1]
+    cot = g_s[..., 2]
     h = helix_at(p, q, s, bz)
     xs, ys = h[..., 0], h[..., 1]
     dh_dp_b = 2.0 * xs[:, None] * G[:, 0, :] + 2.0 * ys[:, None] * G[:, 1, :]
@@ -258,8 +269,14 @@ def highland_theta0(p, kind, x_over_x0, mass):
     """Highland / PDG plane angle for unit charge:
     theta0 = 0.0136/(beta p) sqrt(x) (1 + 0.038 ln(x / beta^2)),
     x = t / |cos(incidence)|.  Returns (theta0, grazing)."""
+    return highland_theta0_at(p, cos_incidence(p, kind), x_over_x0, mass)
+
+
+def highland_theta0_at(p, cos_a, x_over_x0, mass):
+    """highland_theta0 for a given cosine of the incidence angle (any
+    surface): |cos_a| clamped at GRAZING_COS and flagged."""
     ipt, th = p[..., 3], p[..., 5]
-    ca = cos_incidence(p, kind).abs()
+    ca = _t(cos_a).abs()
     grazing = ca < GRAZING_COS
     ca = torch.clamp(ca, min=GRAZING_COS)
     pmag = 1.0 / (ipt * torch.sin(th))
@@ -275,6 +292,11 @@ def process_noise(p, kind, x_over_x0, mass):
     Q_ipt,ipt = (ipt cot)^2 th0^2, Q_ipt,th = -ipt cot th0^2 (rank 2)."""
     p = _t(p)
     th0, grazing = highland_theta0(p, kind, x_over_x0, mass)
+    return scattering_q(p, th0), grazing
+
+
+def scattering_q(p, th0):
+    """Q of process_noise for a given plane angle theta0 [n]."""
     ipt, th = p[..., 3], p[..., 5]
     v = th0 * th0
     cot = torch.cos(th) / torch.sin(th)
@@ -290,8 +312,7 @@ def process_noise(p, kind, x_over_x0, mass):
     rows[5][3] = q35
     rows[4][4] = q44
     rows[5][5] = q55
-    Q = torch.stack([torch.stack(r, dim=-1) for r in rows], dim=-2)
-    return Q, grazing
+    return torch.stack([torch.stack(r, dim=-1) for r in rows], dim=-2)
 
 
 def propagate(p, C, q, kind, pos, x_over_x0, geom, apply_material=True, same=None):
@@ -405,13 +426,20 @@ def first_three_valid(hit_offsets, hit_valid):
     return out
 
 
-SEED_MIN_SPACING = 3.0   # cm, transverse distance between chosen seed hits (mode 1)
+# cm, transverse distance between chosen seed hits (mode 1): below the 3 cm
+# between the two innermost barrel layers, so that no barrel hit pair sits at
+# the threshold, where rounding would decide the choice
+SEED_MIN_SPACING = 2.5
 
 
-def spaced_three_valid(hit_offsets, hit_valid, hit_pos, spacing=SEED_MIN_SPACING):
+def spaced_three_valid(hit_offsets, hit_valid, hit_pos, spacing=SEED_MIN_SPACING, return_margin=False):
     """Greedy choice along each track: the first valid entry, then each next
     valid entry whose transverse distance from the previously chosen hit is at
-    least ``spacing``; three entries, or -1 everywhere if fewer qualify."""
+    least ``spacing``; three entries, or -1 everywhere if fewer qualify.
+    return_margin: also return, per track, the smallest |d - spacing| /
+    spacing over the distances the choice compared (inf if none): a track
+    whose margin is at the rounding level of a precision can be seeded
+    either way in that precision."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     valid = torch.as_tensor(hit_valid, dtype=torch.int64)
     hp = _t(hit_pos)
@@ -423,11 +451,15 @@ def spaced_three_valid(hit_offsets, hit_valid, hit_pos, spacing=SEED_MIN_SPACING
     lasty = torch.zeros(n, dtype=DT)
     maxlen = int(lens.max()) if n else 0
     ar = torch.arange(n)
+    margin = torch.full((n,), math.inf, dtype=DT)
     for j in range(maxlen):
         has = j < lens
         e = torch.where(has, off[:-1] + j, torch.zeros_like(lens))
         hx, hy = hp[0, e], hp[1, e]
-        far = torch.sqrt((hx - lastx) ** 2 + (hy - lasty) ** 2) >= spacing
+        d = torch.sqrt((hx - lastx) ** 2 + (hy - lasty) ** 2)
+        far = d >= spacing
+        compared = has & (valid[e] == 1) & (cnt > 0) & (cnt < 3)
+        margin = torch.where(compared, torch.minimum(margin, (d - spacing).abs() / spacing), margin)
         take = has & (valid[e] == 1) & (cnt < 3) & ((cnt == 0) | far)
         t = ar[take]
         out[t, cnt[t]] = e[t]
@@ -435,7 +467,7 @@ def spaced_three_valid(hit_offsets, hit_valid, hit_pos, spacing=SEED_MIN_SPACING
         lasty = torch.where(take, hy, lasty)
         cnt = cnt + take.to(torch.int64)
     out[cnt < 3] = -1
-    return out
+    return (out, margin) if return_margin else out
 
 
 SEED_FIRST_THREE = 0
@@ -546,7 +578,9 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
     (1 - r) (alternating by element, track and entry) -- the same probe at
     float64 rounding.
     record: also return the filtered state after every entry (pe [nh,6],
-    Ce [nh,6,6], qe [nh]; NaN for entries the fit did not reach).
+    Ce [nh,6,6], qe [nh]; NaN for entries the fit did not reach) and the
+    predicted state of every entry, after its propagation and material and
+    before its update (pp [nh,6], Cp [nh,6,6]).
     Returns dict(p, C, q, chi2, ndf, status[, pe, Ce, qe])."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
@@ -584,6 +618,8 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
         pe = torch.full((nh, 6), float("nan"), dtype=DT)
         Ce = torch.full((nh, 6, 6), float("nan"), dtype=DT)
         qe = torch.full((nh,), float("nan"), dtype=DT)
+        ppe = torch.full((nh, 6), float("nan"), dtype=DT)
+        Cpe = torch.full((nh, 6, 6), float("nan"), dtype=DT)
     for j in range(maxlen):
         e = k0 + j
         act = alive & (e < end)
@@ -644,9 +680,11 @@ def fit_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_layer, hit_valid, hit_po
             pe = pe.index_put((ei[k],), pn[k])
             Ce = Ce.index_put((ei[k],), Cn[k])
             qe = qe.index_put((ei[k],), qn[k])
+            ppe = ppe.index_put((ei[k],), pp2[k])
+            Cpe = Cpe.index_put((ei[k],), CC2[k])
     out = dict(p=p, C=C, q=q, chi2=chi2, ndf=2 * nval - 5, status=status)
     if record:
-        out.update(pe=pe, Ce=Ce, qe=qe)
+        out.update(pe=pe, Ce=Ce, qe=qe, pp=ppe, Cp=Cpe)
     return out
 
 
@@ -676,6 +714,10 @@ OUTLIER = 128
 # the final fit's chi2 cut for one hit (3 measured coordinates, one of them
 # the layer's thickness; the paper gives no value)
 FINAL_CHI2_CUT = 30.0
+# rounds in which the final fit may reject a hit, and the number of used hits
+# a track keeps at the least (ndf = 2 * 4 - 5 = 3); the paper gives neither
+FINAL_MAX_REJECT = 3
+FINAL_MIN_KEEP = 4
 
 
 def reverse_direction(p, C, q):
@@ -753,8 +795,7 @@ def combine_on_surface(pf, Cf, pb, Cb, kind, pos):
 
 
 def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom,
-                 cov_scale=BACKWARD_COV_SCALE, state_round=None, state_jitter=None, smooth_from=None,
-                 chi2_cut=None):
+                 cov_scale=BACKWARD_COV_SCALE, state_round=None, state_jitter=None, smooth_from=None):
     """Backward fit (Sec. 2.2, step 4): every track is traversed again, from
     its last entry back to its first valid entry, and refitted.
 
@@ -787,12 +828,7 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     backward pass propagates without material, combines, then adds the
     layer's material (the same arithmetic as propagate with material).
 
-    chi2_cut: None, or the final fit's outlier rejection: a valid hit whose
-    chi2 against the backward prediction (the increment the update would
-    add) exceeds chi2_cut is not used; its entry is taken as a hole (the
-    layer's material only), marked in outlier [nh] (bool), and the track gets
-    OUTLIER.  A NaN chi2 is not above the cut (the step then fails as
-    non-finite).  Returns dict(p, C, q, chi2, ndf, status): chi2 and ndf
+    Returns dict(p, C, q, chi2, ndf, status): chi2 and ndf
     (= 2 * used hits - 5) of the backward pass."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
@@ -827,14 +863,14 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
         nh = lay_all.shape[0]
         ps_all = torch.full((nh, 6), float("nan"), dtype=DT)
         Cs_all = torch.full((nh, 6, 6), float("nan"), dtype=DT)
+        pb_all = torch.full((nh, 6), float("nan"), dtype=DT)
+        Cb_all = torch.full((nh, 6, 6), float("nan"), dtype=DT)
         pe_f, Ce_f = _t(smooth_from["pe"]), _t(smooth_from["Ce"])
     chi2 = torch.zeros(n, dtype=DT)
     nval = torch.zeros(n, dtype=torch.int64)
     status = torch.zeros(n, dtype=torch.int64)
     alive = run.clone()
     prev_e = last.clone()
-    if chi2_cut is not None:
-        outlier = torch.zeros(lay_all.shape[0], dtype=torch.bool)
     for j in range(maxlen):
         e = last - j
         act = alive & (e >= k0)
@@ -855,6 +891,8 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
             r = torch.nonzero(reach)[:, 0]
             ps_all = ps_all.index_put((ei[r],), ps[r])
             Cs_all = Cs_all.index_put((ei[r],), Cs[r])
+            pb_all = pb_all.index_put((ei[r],), pb[r])
+            Cb_all = Cb_all.index_put((ei[r],), Cb[r])
             Q, grazing = process_noise(pp2, kind, x0_l[lay], geom.mass)
             CC2 = CC2 + Q
             st = st | torch.where(grazing & reach, GRAZING, 0)
@@ -876,10 +914,6 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
         good = (st & NO_CROSSING) == 0
         valid = (val_all[ei] == 1) & good
         pu, Cu, qu, c2, st_u = update(pp2, CC2, qq, m_all[ei], V_all[ei])
-        if chi2_cut is not None:
-            rej = valid & (c2 > chi2_cut)
-            valid = valid & ~rej
-            st = st | torch.where(rej, OUTLIER, 0)
         pn = torch.where(valid[:, None], pu, pp2)
         Cn = torch.where(valid[:, None, None], Cu, CC2)
         qn = torch.where(valid, qu, qq)
@@ -905,9 +939,6 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
         status = status.index_put((idx,), status[idx] | st)
         alive = alive.index_put((idx,), keep)
         prev_e = prev_e.index_put((idx,), ei)
-        if chi2_cut is not None:
-            k = torch.nonzero(rej & keep)[:, 0]
-            outlier = outlier.index_put((ei[k],), torch.ones_like(k, dtype=torch.bool))
     p, C, q = reverse_direction(p, C, q)
     # tracks not refitted keep their input
     p = torch.where(run[:, None], p, _t(fwd_p))
@@ -917,10 +948,152 @@ def backward_fit(fwd_p, fwd_C, fwd_q, fwd_status, hit_offsets, hit_layer, hit_va
     out = dict(p=p, C=C, q=q, chi2=chi2, ndf=2 * nval - 5, status=status)
     if smooth:
         # the entries the backward pass reached
-        out.update(ps=ps_all, Cs=Cs_all)
-    if chi2_cut is not None:
-        out.update(outlier=outlier)
+        out.update(ps=ps_all, Cs=Cs_all, pb=pb_all, Cb=Cb_all)
     return out
+
+
+# --------------------------------------------------------------------------
+# f4: final fit with outlier rejection
+# --------------------------------------------------------------------------
+
+def unbiased_chi2(pp, Cp, pb, Cb, kind, pos, m, V):
+    """chi2 of a hit against the estimate of its track made from all the other
+    hits: that estimate is the forward prediction at the hit's entry (its
+    propagation and material, before its update: the hits before it)
+    combined with the backward pass's prediction there (the hits after it)
+    by combine_on_surface, or the forward prediction alone on the last entry
+    (pb NaN: the backward pass starts there from a result that holds the
+    hit).  With x, C that estimate: r = m - H x, S = V + H C H^T,
+    chi2 = r^T S^-1 r.  In the linear model this equals r_s^T (V - H C_s H^T)^-1
+    r_s of the smoothed residual r_s = m - H x_s, but it is formed from a sum
+    and a residual of full size, so it keeps its digits where the hit
+    dominates the smoothed state.  pp, pb [k,6], Cp, Cb [k,6,6], kind, pos [k]
+    (the entry's surface), m [k,3], V [k,3,3].  NaN where the forward
+    prediction is missing or the combination fails."""
+    pp, Cp, pb, Cb, m, V = _t(pp), _t(Cp), _t(pb), _t(Cb), _t(m), _t(V)
+    kind, pos = torch.as_tensor(kind), _t(pos)
+    have_f = torch.isfinite(pp).all(dim=1) & torch.isfinite(Cp).flatten(1).all(dim=1)
+    have_b = torch.isfinite(pb).all(dim=1) & torch.isfinite(Cb).flatten(1).all(dim=1)
+    px, Cx = pp.clone(), Cp.clone()            # the last entry: the forward prediction alone
+    both = torch.nonzero(have_f & have_b)[:, 0]
+    if both.numel():
+        B = surface_frame(pp[both], kind[both], pos[both])
+        M = B.transpose(1, 2) @ (Cp[both] + Cb[both]) @ B
+        _, info = torch.linalg.cholesky_ex(M)
+        good = info == 0
+        pc, Cc = combine_on_surface(pp[both], Cp[both], pb[both], Cb[both], kind[both], pos[both]) \
+            if bool(good.all()) else _combine_guarded(pp[both], Cp[both], pb[both], Cb[both], kind[both],
+                                                       pos[both], good)
+        px[both], Cx[both] = pc, Cc
+    r = m - px[:, :3]
+    S = V + Cx[:, :3, :3]
+    fin = have_f & torch.isfinite(r).all(dim=1) & torch.isfinite(S).flatten(1).all(dim=1)
+    Ss = torch.where(fin[:, None, None], S, torch.eye(3, dtype=DT).expand_as(S))
+    rs = torch.where(fin[:, None], r, torch.zeros_like(r))
+    chi2 = torch.einsum("ni,nij,nj->n", rs, torch.linalg.inv(Ss), rs)
+    return torch.where(fin, chi2, torch.full_like(chi2, float("nan")))
+
+
+def _combine_guarded(pf, Cf, pb, Cb, kind, pos, good):
+    """combine_on_surface where its 5x5 system is positive definite (good),
+    NaN elsewhere."""
+    n = pf.shape[0]
+    ps = torch.full((n, 6), float("nan"), dtype=DT)
+    Cs = torch.full((n, 6, 6), float("nan"), dtype=DT)
+    g = torch.nonzero(good)[:, 0]
+    if g.numel():
+        ps[g], Cs[g] = combine_on_surface(pf[g], Cf[g], pb[g], Cb[g], kind[g], pos[g])
+    return ps, Cs
+
+
+def final_fit(hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom, seed_mode=SEED_FIRST_THREE,
+              chi2_cut=FINAL_CHI2_CUT, max_reject=FINAL_MAX_REJECT, min_keep=FINAL_MIN_KEEP,
+              cov_scale=BACKWARD_COV_SCALE, state_round=None, state_jitter=None):
+    """Final fit with outlier rejection (the final fit the paper names in
+    Sec. 2.2 and Sec. 4, with a hit-rejection rule of this reading): rounds of
+    refit and reject-the-worst.
+
+    Round i (i = 0 .. max_reject), for every track still open: seed from its
+    used hits (its valid hits not yet rejected; seed_mode as make_seeds), the
+    forward fit over them recording the filtered state after every entry,
+    then the backward fit with the two-filter smoother (backward_fit with
+    smooth_from), which gives the backward predictions.  Each used hit gets
+    its unbiased chi2 (unbiased_chi2: against the estimate from the track's
+    other hits, the combination of the two predictions at its entry); the
+    hits of a track that the backward pass did not refit (NOT_REFITTED: its
+    forward fit stopped or could not be seeded) get NaN, as there is no such
+    estimate.  If i < max_reject, the track
+    was refitted, its worst used hit (largest chi2, the first entry among
+    equals; NaN never counts) has chi2 > chi2_cut and the track keeps at least
+    min_keep used hits without it, that hit is rejected (marked in outlier,
+    no longer used) and the track stays open; otherwise the track is closed
+    with this round's backward-fit result (state on its first used entry,
+    chi2 and ndf = 2 * used - 5 of the backward pass, its status, plus OUTLIER
+    if any hit was rejected).
+
+    Returns dict(p, C, q, chi2, ndf, status, outlier [nh] bool, hit_chi2 [nh]
+    (a used hit: its chi2 in the round its track closed; a rejected hit: its
+    chi2 in the round it was rejected; NaN for the rest), rounds [n] (the
+    round each track closed in)).  state_round / state_jitter: the
+    conditioning probes of fit_tracks, applied to the seeds and every pass."""
+    off = torch.as_tensor(hit_offsets, dtype=torch.int64)
+    n = off.shape[0] - 1
+    lay_all = torch.as_tensor(hit_layer, dtype=torch.int64)
+    nh = lay_all.shape[0]
+    lens = off[1:] - off[:-1]
+    track_of = torch.repeat_interleave(torch.arange(n), lens)
+    hp = hit_pos if torch.is_tensor(hit_pos) else _t(hit_pos)
+    m_all = hp.T
+    V_all = unpack_sym(hit_cov, 3)
+    used = torch.as_tensor(hit_valid, dtype=torch.int64).clone()
+    outlier = torch.zeros(nh, dtype=torch.bool)
+    hit_chi2 = torch.full((nh,), float("nan"), dtype=DT)
+    is_open = torch.ones(n, dtype=torch.bool)
+    rejected_any = torch.zeros(n, dtype=torch.bool)
+    res = dict(p=torch.zeros(n, 6, dtype=DT), C=torch.zeros(n, 6, 6, dtype=DT), q=torch.zeros(n, dtype=DT),
+               chi2=torch.zeros(n, dtype=DT), ndf=torch.zeros(n, dtype=torch.int64),
+               status=torch.zeros(n, dtype=torch.int64), rounds=torch.zeros(n, dtype=torch.int64))
+    idx = torch.arange(nh)
+    for rnd in range(max_reject + 1):
+        if not bool(is_open.any()):
+            break
+        sp, sC, sq, _ = make_seeds(hit_offsets, used, hp.detach(), geom.bz, mode=seed_mode)
+        if state_round is not None:
+            sp = sp.to(state_round).to(DT)
+        fwd = fit_tracks(sp, sC, sq, hit_offsets, hit_layer, used, hp, hit_cov, geom, state_round=state_round,
+                         state_jitter=state_jitter, record=True)
+        bwd = backward_fit(fwd["p"], fwd["C"], fwd["q"], fwd["status"], hit_offsets, hit_layer, used, hp, hit_cov,
+                           geom, cov_scale=cov_scale, state_round=state_round, state_jitter=state_jitter,
+                           smooth_from=fwd)
+        kind_e = torch.as_tensor(geom.kind, dtype=torch.int64)[lay_all]
+        pos_e = _t(geom.pos)[lay_all]
+        c2 = unbiased_chi2(fwd["pp"], fwd["Cp"], bwd["pb"], bwd["Cb"], kind_e, pos_e, m_all, V_all)
+        # a track the backward pass did not refit (its forward fit stopped or
+        # could not be seeded) has no estimate from its other hits
+        refitted = (bwd["status"] & NOT_REFITTED) == 0
+        c2 = torch.where(refitted[track_of], c2, torch.full_like(c2, float("nan")))
+        in_open = is_open[track_of] & (used == 1)
+        hit_chi2 = torch.where(in_open, c2, hit_chi2)
+        # the worst used hit of each track: the largest chi2, the first entry among equals
+        val = torch.where(in_open & torch.isfinite(c2), c2, torch.full_like(c2, -math.inf))
+        worst = torch.full((n,), -math.inf, dtype=DT).scatter_reduce(0, track_of, val, reduce="amax")
+        first = torch.where(val == worst[track_of], idx, torch.full_like(idx, nh))
+        e_w = torch.full((n,), nh, dtype=torch.int64).scatter_reduce(0, track_of, first, reduce="amin")
+        n_used = torch.zeros(n, dtype=torch.int64).index_add(0, track_of, (used == 1).to(torch.int64))
+        rej = is_open & refitted & (worst > chi2_cut) & (n_used - 1 >= min_keep) & (rnd < max_reject)
+        close = is_open & ~rej
+        for k in ("p", "C", "q", "chi2", "ndf", "status"):
+            sel = close.view(-1, *([1] * (bwd[k].dim() - 1)))
+            res[k] = torch.where(sel, bwd[k], res[k])
+        res["rounds"] = torch.where(close, rnd, res["rounds"])
+        t_rej = torch.nonzero(rej)[:, 0]
+        outlier[e_w[t_rej]] = True
+        used[e_w[t_rej]] = 0
+        rejected_any |= rej
+        is_open &= ~close
+    res["status"] = res["status"] | torch.where(rejected_any, OUTLIER, 0)
+    res.update(outlier=outlier, hit_chi2=hit_chi2)
+    return res
 
 
 # --------------------------------------------------------------------------

@@ -182,17 +182,26 @@ def _round(p, C, dtype):
     return p.to(dtype).to(torch.float64), C.to(dtype).to(torch.float64)
 
 
-def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams, state_round=None):
+def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams, state_round=None,
+               flips=None):
     """Run the search.  seed_p [n, 6], seed_C [n, 6, 6], seed_q [n], seed_layer
     [n] (layer index the seed state is on), layer_plan: layer indices in
     order, geom: a detector Geometry (barrel layers), pools: object with
     layer_offsets [L+1], pos [3, np], cov [6, np], hit_id [np].
     state_round: None, or a dtype for the conditioning probe.
+    flips: None, or a set of near-decision keys (as listed in `near`) to be
+    taken the other way: a hit near a window edge counted on the other side
+    of it, a chi2 near the cut accepted if it was rejected and the other way
+    round, two near-tied neighbours of a ranking swapped.  A key names the
+    layer step, the candidate by its history and the hit (or the two
+    children by their histories), so it names the same decision in any run
+    that reaches that candidate.
     Returns dict(hits [n, beam, P] int64, score [n, beam], p [n, beam, 6],
     C [n, beam, 6, 6], status [n], flagged [n] bool, flags [n] (near
-    decisions: 1 window edge, 2 chi2 cut, 4 ranking), score_err [n, beam]
-    (root-sum-square of the FP32 error model over the candidate's terms),
-    n_window_hits)."""
+    decisions: 1 window edge, 2 chi2 cut, 4 ranking), near [n] (list of the
+    seed's near-decision keys), score_err [n, beam] (root-sum-square of the
+    FP32 error model over the candidate's terms), n_window_hits)."""
+    flips = frozenset() if flips is None else frozenset(flips)
     seed_p = np.asarray(seed_p, np.float64)
     seed_C = np.asarray(seed_C, np.float64)
     n, B, P = seed_p.shape[0], prm.beam, len(layer_plan)
@@ -226,6 +235,7 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
 
     status = np.zeros(n, np.int64)
     flags = np.zeros(n, np.int64)   # near decisions: 1 window edge, 2 chi2 cut, 4 ranking
+    near = [[] for _ in range(n)]
     n_window = 0
     c_stop = [False] * n
     for step, L in enumerate(layer_plan):
@@ -279,21 +289,32 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
                 dz = np.abs(pool.pos[2, cand] - z)
                 cand = cand[dz <= w_z + mz]
             kids = []
+            hist = tuple(c_hist[i])
             if cand.size:
                 darc = np.abs(_wrap(pool.phi[cand] - phi_p)) * R
                 dz = np.abs(pool.pos[2, cand] - z)
-                if (np.abs(darc - w_r) <= mr).any() or (np.abs(dz - w_z) <= mz).any():
+                inside_m = (darc <= w_r) & (dz <= w_z)
+                edge = (np.abs(darc - w_r) <= mr) | (np.abs(dz - w_z) <= mz)
+                for a in np.nonzero(edge)[0]:
+                    key = ("edge", step, hist, int(pool.ids[cand[a]]))
                     flags[s] |= 1
-                inside = cand[(darc <= w_r) & (dz <= w_z)]
+                    near[s].append(key)
+                    if key in flips:
+                        inside_m[a] = not inside_m[a]
+                inside = cand[inside_m]
                 n_window += int(inside.size)
                 if inside.size:
                     chi2, kap = _chi2(p2[i, :3], Cp, pool.pos[:, inside].T, pool.cov[:, inside])
                     sig = math.sqrt(t @ Cp @ t + prm.sigma_rphi[L] ** 2)
-                    for c2, kp in zip(chi2, kap):
-                        if abs(c2 - prm.chi2_max) <= chi2_error(prm.chi2_max, epos, sig, kp):
-                            flags[s] |= 2
                     for h, c2, kp in zip(inside, chi2, kap):
-                        if c2 <= prm.chi2_max:
+                        accept = c2 <= prm.chi2_max
+                        if abs(c2 - prm.chi2_max) <= chi2_error(prm.chi2_max, epos, sig, kp):
+                            key = ("cut", step, hist, int(pool.ids[h]))
+                            flags[s] |= 2
+                            near[s].append(key)
+                            if key in flips:
+                                accept = not accept
+                        if accept:
                             kids.append((c_score[i] + prm.hit_bonus - c2, int(pool.ids[h]), c_rank[i], i, int(h),
                                          chi2_error(c2, epos, sig, kp)))
             if not kids:
@@ -315,10 +336,15 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
                 ea, eb = c_err[ka[3]] + [ka[5]], c_err[kb[3]] + [kb[5]]
                 d0 = next((k for k in range(len(ha)) if ha[k] != hb[k]), len(ha))
                 if d == 0.0:
-                    if not all(_same_input(x, y) for x, y in zip(ha[d0:], hb[d0:])):
-                        flags[s] |= 4
-                elif d <= RANK_SIGMAS * math.sqrt(sum(e * e for e in ea[d0:] + eb[d0:])):
+                    is_near = not all(_same_input(x, y) for x, y in zip(ha[d0:], hb[d0:]))
+                else:
+                    is_near = d <= RANK_SIGMAS * math.sqrt(sum(e * e for e in ea[d0:] + eb[d0:]))
+                if is_near:
+                    key = ("rank", step, tuple(ha), tuple(hb))
                     flags[s] |= 4
+                    near[s].append(key)
+                    if key in flips:
+                        kids[a], kids[a + 1] = kb, ka
             for r, (sc, hid, prank, i, h, err) in enumerate(kids[:B]):
                 n_seed.append(s)
                 n_rank.append(r)
@@ -371,5 +397,54 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
         pout[s, r] = c_p[j]
         Cout[s, r] = c_C[j]
         serr[s, r] = math.sqrt(sum(e * e for e in c_err[j]))
-    return dict(hits=hits, score=score, p=pout, C=Cout, status=status, flagged=flags != 0, flags=flags,
+    return dict(hits=hits, score=score, p=pout, C=Cout, status=status, flagged=flags != 0, flags=flags, near=near,
                 score_err=serr, n_window_hits=n_window)
+
+
+def _bears_on(key, target, current):
+    """Whether taking near decision `key` the other way could move the result
+    `current` [beam, P] towards `target`: an edge or cut decision on hit h
+    after history H matters when exactly one of the two results has a row
+    continuing H with h; a ranking between histories A and B matters when
+    the two results do not hold the same rows starting with A and with B."""
+    kind, step = key[0], key[1]
+    if kind in ("edge", "cut"):
+        hist, hid = key[2], key[3]
+        has = lambda rows: any(tuple(r[:step]) == hist and r[step] == hid for r in rows)
+        return has(target) != has(current)
+    pre = lambda rows, h: sorted(i for i, r in enumerate(rows) if tuple(r[:len(h)]) == h)
+    return any(pre(target, h) != pre(current, h) for h in (key[2], key[3]))
+
+
+def valid_alternative(hits, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams,
+                      budget=64):
+    """Whether the hit lists `hits` [beam, P] of one seed are one of the
+    results its near decisions allow: the search is re-run with sets of its
+    near decisions taken the other way, up to `budget` runs, fewest flips
+    first; from each run only the near decisions that bear on the difference
+    between its result and `hits` (_bears_on) are added to its flip set (all
+    of them when none does).  A decision that bears on no difference cannot
+    be the one that explains it, so this visits the runs that can reach
+    `hits` before the others.  Returns (found, runs)."""
+    one = lambda flips: score_hits(np.asarray(seed_p)[None], np.asarray(seed_C)[None], np.asarray([seed_q]),
+                                   np.asarray([seed_layer]), layer_plan, geom, pools, prm, flips=flips)
+    target = [tuple(int(x) for x in r) for r in np.asarray(hits)]
+    seen = {frozenset()}
+    queue = [frozenset()]
+    runs = 0
+    while queue and runs < budget:
+        queue.sort(key=len)
+        f = queue.pop(0)
+        o = one(f)
+        runs += 1
+        if np.array_equal(o["hits"][0], hits):
+            return True, runs
+        cur = [tuple(int(x) for x in r) for r in o["hits"][0]]
+        keys = [k for k in o["near"][0] if k not in f]
+        rel = [k for k in keys if _bears_on(k, target, cur)]
+        for key in (rel or keys):
+            g = f | {key}
+            if g not in seen:
+                seen.add(g)
+                queue.append(g)
+    return False, runs

@@ -243,3 +243,100 @@ def test_near_ties_are_flagged():
             assert res["flagged"][0], (t, s)   # equal or not, the two differ only by rounding
             flagged += 1
     assert flagged >= 5
+
+
+def test_flipped_near_ties_give_the_other_valid_order():
+    """The mirrored-hit near tie above, taken the other way (flips): the two
+    candidates trade ranks and nothing else changes; either order is a valid
+    result (valid_alternative finds both), while a made-up order is not."""
+    wl, ev, g, pools, p, C, q = search_inputs(20, noise=False)
+    prm = default_params(g)
+    plan = PLAN[:1]
+    L = plan[0]
+    checked = 0
+    for t in range(20):
+        p2, C2, _, _ = O.propagate(torch.tensor(p[t][None]), torch.tensor(C[t][None]), torch.tensor(q[t:t + 1]),
+                                   torch.tensor([0]), torch.tensor([float(g.pos[L])], dtype=torch.float64),
+                                   torch.tensor([float(g.x_over_x0[L])], dtype=torch.float64), g)
+        pp = p2[0].numpy()
+        P = _tiny_pools(ev, pools, [t], {L}, offsets=())
+        m1 = P.pos[:, 0]
+        P.pos = np.stack([m1, 2 * pp[:3] - m1], axis=1)
+        P.cov = np.stack([P.cov[:, 0], P.cov[:, 0]], axis=1)
+        P.hit_id = np.array([5, 3], np.int32)
+        P.track = np.array([t, t], np.int32)
+        P.layer_offsets = np.array([0] * (L + 1) + [2] * (g.n_layers - L), np.int32)
+        args = (p[t:t + 1], C[t:t + 1], q[t:t + 1], [SEED_LAYER], plan, g, P, prm)
+        base = KS.score_hits(*args)
+        if not np.isfinite(base["score"][0][1]):
+            continue
+        ranks = [k for k in base["near"][0] if k[0] == "rank"]
+        assert ranks
+        flipped = KS.score_hits(*args, flips={ranks[0]})
+        assert np.array_equal(flipped["hits"][0, 0], base["hits"][0, 1])
+        assert np.array_equal(flipped["hits"][0, 1], base["hits"][0, 0])
+        assert np.array_equal(flipped["hits"][0, 2:], base["hits"][0, 2:])
+        for h in (base["hits"][0], flipped["hits"][0]):
+            ok, runs = KS.valid_alternative(h, p[t], C[t], q[t], SEED_LAYER, plan, g, P, prm)
+            assert ok
+        bogus = base["hits"][0].copy()
+        bogus[0, 0] = 999999
+        assert not KS.valid_alternative(bogus, p[t], C[t], q[t], SEED_LAYER, plan, g, P, prm)[0]
+        checked += 1
+    assert checked >= 5
+
+
+def test_no_flips_is_the_plain_search_and_every_flagged_seed_has_its_own_result():
+    """flips = {} reproduces the plain run; the plain result of a flagged
+    seed is found by valid_alternative on its first run; a cut flip on a
+    flagged seed changes only what follows from that one decision."""
+    wl, ev, g, pools, p, C, q = search_inputs(150)
+    prm = default_params(g)
+    a = KS.score_hits(p, C, q, np.full(150, SEED_LAYER), PLAN, g, pools, prm)
+    b = KS.score_hits(p, C, q, np.full(150, SEED_LAYER), PLAN, g, pools, prm, flips=set())
+    assert np.array_equal(a["hits"], b["hits"]) and np.array_equal(a["score"], b["score"])
+    fl = np.nonzero(a["flagged"])[0]
+    assert fl.size > 0
+    for s in fl[:5]:
+        ok, runs = KS.valid_alternative(a["hits"][s], p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm)
+        assert ok and runs == 1
+    cuts = [(s, k) for s in fl for k in a["near"][s] if k[0] == "cut"]
+    if cuts:
+        s, key = cuts[0]
+        one = lambda fl_: KS.score_hits(p[s:s + 1], C[s:s + 1], q[s:s + 1], [SEED_LAYER], PLAN, g, pools, prm,
+                                        flips=fl_)
+        f = one({key})
+        # the decision named by the key is taken the other way: its hit is
+        # (or is no longer) among the children of that candidate at that layer
+        step, hist, hid = key[1], key[2], key[3]
+        had = any(tuple(x[:step]) == hist and x[step] == hid for x in a["hits"][s])
+        has = any(tuple(x[:step]) == hist and x[step] == hid for x in f["hits"][0])
+        assert not (had and has)
+
+
+def test_valid_alternative_finds_results_of_several_flips():
+    """A result made by taking two or three near decisions of a flagged seed
+    the other way is recognised as a valid alternative (the guided search
+    reaches it within its budget), and a result with one hit changed is not."""
+    wl, ev, g, pools, p, C, q = search_inputs(300)
+    prm = default_params(g)
+    a = KS.score_hits(p, C, q, np.full(300, SEED_LAYER), PLAN, g, pools, prm)
+    rng = np.random.default_rng(1)
+    cand = [s for s in np.nonzero(a["flagged"])[0] if len(a["near"][s]) >= 2]
+    checked = 0
+    for s in cand[:6]:
+        keys = a["near"][s]
+        k = min(len(keys), int(rng.integers(2, 4)))
+        pick = {keys[i] for i in rng.choice(len(keys), k, replace=False)}
+        tgt = KS.score_hits(p[s:s + 1], C[s:s + 1], q[s:s + 1], [SEED_LAYER], PLAN, g, pools, prm,
+                            flips=pick)["hits"][0]
+        ok, runs = KS.valid_alternative(tgt, p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm)
+        assert ok, (s, pick, runs)
+        checked += 1
+    assert checked >= 3
+    s = cand[0]
+    bogus = a["hits"][s].copy()
+    row = int(np.nonzero((bogus >= 0).any(axis=1))[0][0])
+    col = int(np.nonzero(bogus[row] >= 0)[0][0])
+    bogus[row, col] = 987654321
+    assert not KS.valid_alternative(bogus, p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm, budget=8)[0]
