@@ -12,9 +12,9 @@ needs.  It gives no formulas.  The readings here:
   the module is the pair of local coordinates (m_u, m_v) = ((x - c).u,
   (x - c).v) of its position x, with a 2x2 covariance.
 * Propagation: the helix of kf_oracle.helix_at to the plane, the path s the
-  root of h(s) = n.(x(s) - c) reached by Newton's method from the
-  straight-line estimate, taken if s > -1 cm (the window of a different
-  layer in kf_oracle).  The Jacobian is the surface-to-surface derivative
+  first root s > -1 cm (the window of a different layer in kf_oracle) of
+  h(s) = n.(x(s) - c) within one turn, found by steps that cannot pass a
+  root (crossing_plane).  The Jacobian is the surface-to-surface derivative
   F = G + g_s (ds/dp), ds/dp = -(n.G_pos)/(n.g_pos), with G and g_s the
   helix partials of kf_oracle.helix_partials.  After it the plane normal (in
   position) is a null vector of the covariance.
@@ -34,7 +34,7 @@ import torch
 from . import kf_oracle as O
 
 DT = torch.float64
-NEWTON_STEPS = 8
+SAFE_STEPS = 200    # bound on the steps of the crossing search (a near-tangent crossing needs ~60)
 CROSS_TOL = 1e-9   # cm: |h(s)| accepted as on the plane
 
 
@@ -52,26 +52,54 @@ def frames(modules):
 
 
 def crossing_plane(p, q, c, n, bz, lo=-O.S_BACK):
-    """Path s to the plane through c with normal n ([k,3] each): Newton's
-    method on h(s) = n.(x(s) - c) from the straight-line estimate
-    s0 = -h(0) / (n.d_xy), d_xy = (cos phi, sin phi, cot theta).
-    Returns (s, ok): ok iff converged to |h| < CROSS_TOL with s > lo."""
+    """Path s to the first crossing of the plane through c with normal n
+    ([k,3] each): the smallest root s > lo of h(s) = n.(x(s) - c), within
+    one turn of the helix (s <= lo + 2 pi / |w|).
+
+    Along the helix h'(s) = n.d(s), d = (cos phi(s), sin phi(s), cot theta),
+    and |h''(s)| <= M = |w| sqrt(n_x^2 + n_y^2).  From a point where
+    sigma h > 0 (sigma = the sign of h there), every root lies at least the
+    smallest positive root of sigma h + sigma h' t - M t^2 / 2 = 0 ahead, so
+    stepping by that amount never passes a root; the steps start at s = lo
+    and stop when they no longer move s (or when h changes sign, which in
+    exact arithmetic only happens at the root).  Near a simple root they
+    are Newton steps to second order.  Returns (s, ok): ok iff the last point
+    is within CROSS_TOL of the plane with s > lo."""
     p, q, c, n = _t(p), _t(q), _t(c), _t(n)
-    ph, th = p[:, 4], p[:, 5]
+    k = p.shape[0]
+    w = O._safe_omega(O.omega(q, p[:, 3], bz))
+    th = p[:, 5]
     cot = torch.cos(th) / torch.sin(th)
-    d0 = torch.stack([torch.cos(ph), torch.sin(ph), cot], dim=1)
-    h0 = ((p[:, :3] - c) * n).sum(1)
-    dh0 = (d0 * n).sum(1)
-    s = -h0 / torch.where(dh0.abs() < 1e-30, torch.full_like(dh0, 1e-30), dh0)
-    for _ in range(NEWTON_STEPS):
-        x = O.helix_at(p, q, s, bz)
+    M = w.abs() * torch.sqrt(n[:, 0] ** 2 + n[:, 1] ** 2)
+    s_max = lo + 2 * math.pi / w.abs()
+    s = torch.full((k,), float(lo), dtype=DT)
+
+    def h_and_slope(s_):
+        x = O.helix_at(p, q, s_, bz)
         h = ((x[:, :3] - c) * n).sum(1)
         d = torch.stack([torch.cos(x[:, 4]), torch.sin(x[:, 4]), cot], dim=1)
-        dh = (d * n).sum(1)
-        s = s - h / torch.where(dh.abs() < 1e-30, torch.full_like(dh, 1e-30), dh)
-    x = O.helix_at(p, q, s, bz)
-    h = ((x[:, :3] - c) * n).sum(1)
-    ok = torch.isfinite(s) & (h.abs() < CROSS_TOL) & (s > lo)
+        return h, (d * n).sum(1)
+
+    h, dh = h_and_slope(s)
+    sig = torch.where(h < 0, -1.0, 1.0).to(DT)
+    active = torch.ones(k, dtype=torch.bool)
+    for _ in range(SAFE_STEPS):
+        if not bool(active.any()):
+            break
+        hs, ds_ = sig * h, sig * dh
+        den = torch.sqrt(ds_ * ds_ + 2 * M * hs.clamp(min=0.0)) - ds_
+        step = torch.where(den > 0, 2 * hs.clamp(min=0.0) / torch.where(den > 0, den, torch.ones_like(den)),
+                           torch.full_like(den, math.inf))
+        step = torch.where(active, step, torch.zeros_like(step))
+        s_new = s + step
+        moved = active & (s_new != s)
+        s = torch.where(active, s_new, s)
+        active = moved & (s <= s_max) & torch.isfinite(s)
+        h2, dh2 = h_and_slope(torch.where(torch.isfinite(s), s, torch.zeros_like(s)))
+        h, dh = torch.where(torch.isfinite(s), h2, h), torch.where(torch.isfinite(s), dh2, dh)
+        active = active & (sig * h > 0)
+    h, _ = h_and_slope(torch.where(torch.isfinite(s), s, torch.zeros_like(s)))
+    ok = torch.isfinite(s) & (h.abs() < CROSS_TOL) & (s > lo) & (s <= s_max)
     return s, ok
 
 
@@ -174,7 +202,7 @@ def make_seeds_planes(hit_offsets, hit_module, hit_valid, hit_uv, modules, bz):
 
 
 def fit_plane_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_module, hit_valid, hit_uv, hit_cov_uv, modules, geom,
-                     state_round=None):
+                     state_round=None, state_jitter=None):
     """Forward fit over tilted modules, the rules of kf_oracle.fit_tracks
     with a module per entry: the seed sits on the first valid entry's hit
     and, like every later entry, is propagated to its module's plane
@@ -182,7 +210,10 @@ def fit_plane_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_module, hit_valid,
     seed covariance's component along the normal), gets the module's
     material and, if valid, the 2-D update; a failed crossing or a non-finite step freezes the track.
     hit_uv [2, nh], hit_cov_uv [3, nh] packed (uu, vu, vv), modules [10, M].
-    Returns dict(p, C, q, chi2, ndf, status)."""
+    state_round / state_jitter: the conditioning probes of
+    kf_oracle.fit_tracks (the state rounded to a precision, or scaled by
+    1 +- state_jitter element by element, after every propagation and
+    update).  Returns dict(p, C, q, chi2, ndf, status)."""
     off = torch.as_tensor(hit_offsets, dtype=torch.int64)
     mod_all = torch.as_tensor(hit_module, dtype=torch.int64)
     val_all = torch.as_tensor(hit_valid, dtype=torch.int64)
@@ -219,6 +250,8 @@ def fit_plane_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_module, hit_valid,
         pp2, CC2, _, st_p = propagate_plane(pp, CC, qq, c_m[md], n_m[md], x0_m[md], geom)
         if state_round is not None:
             pp2, CC2 = pp2.to(state_round).to(DT), CC2.to(state_round).to(DT)
+        if state_jitter is not None:
+            pp2, CC2 = O._jitter(pp2, CC2, idx + j, state_jitter)
         good = (st_p & O.NO_CROSSING) == 0
         valid = (val_all[ei] == 1) & good
         pu, Cu, qu, c2, st_u = update_local(pp2, CC2, qq, m_all[ei], V_all[ei], c_m[md], u_m[md], v_m[md])
@@ -236,6 +269,8 @@ def fit_plane_tracks(seed_p, seed_C, seed_q, hit_offsets, hit_module, hit_valid,
         c2n = torch.where(keep, c2n, torch.zeros_like(c2n))
         if state_round is not None:
             pn, Cn = pn.to(state_round).to(DT), Cn.to(state_round).to(DT)
+        if state_jitter is not None:
+            pn, Cn = O._jitter(pn, Cn, idx + j + 1, state_jitter)
         p = p.index_put((idx,), pn)
         C = C.index_put((idx,), Cn)
         q = q.index_put((idx,), qn)

@@ -448,3 +448,155 @@ def valid_alternative(hits, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom
                 seen.add(g)
                 queue.append(g)
     return False, runs
+
+
+def replay(row, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams):
+    """Follow one candidate history `row` [P] (hit ids, MISS, STOP, NO_CAND)
+    of one seed through the search's steps 1-6 and report whether every one
+    of its decisions is one the search can take, allowing each near decision
+    either way: the hit of a step lies inside its window (or near an edge)
+    and has chi2 <= chi2_max (or near the cut); a miss is taken only when no
+    hit of the window is accepted (up to near decisions) and the misses do
+    not exceed max_miss; a stop only where the candidate cannot continue
+    (no crossing, or no accepted hit with its misses spent).  Returns
+    dict(valid, reason, score, err): the score the search gives that history
+    and the root-sum-square of its FP32 term errors (RANK_SIGMAS of it is the
+    ranking margin)."""
+    p = torch.tensor(np.asarray(seed_p, np.float64))[None]
+    C = torch.tensor(np.asarray(seed_C, np.float64))[None]
+    q = torch.tensor([float(seed_q)], dtype=torch.float64)
+    layer, score, errs, misses, stopped = int(seed_layer), 0.0, [], 0, False
+    row = [int(x) for x in row]
+    if row and row[0] == NO_CAND:
+        return dict(valid=False, reason="no candidate", score=-math.inf, err=0.0)
+    for step, L in enumerate(layer_plan):
+        L = int(L)
+        hid = row[step]
+        if stopped:
+            if hid != STOP:
+                return dict(valid=False, reason="continues after a stop at step %d" % step, score=score, err=0.0)
+            continue
+        R = float(geom.pos[L])
+        p2, C2, _, st = O.propagate(p, C, q, torch.tensor([int(geom.kind[L])]), torch.tensor([R], dtype=torch.float64),
+                                    torch.tensor([float(geom.x_over_x0[L])], dtype=torch.float64), geom,
+                                    same=torch.tensor([layer == L]))
+        if int(st[0]) & O.NO_CROSSING:
+            if hid != STOP:
+                return dict(valid=False, reason="no crossing at step %d" % step, score=score, err=0.0)
+            stopped = True
+            continue
+        pp, Cp = p2[0].numpy(), C2[0].numpy()[:3, :3]
+        x, y, z = pp[0], pp[1], pp[2]
+        phi_p = math.atan2(y, x)
+        cos_a = math.sin(pp[5]) * (math.cos(pp[4]) * x + math.sin(pp[4]) * y) / math.hypot(x, y)
+        epos = pos_error(R, cos_a)
+        t = np.array([-math.sin(phi_p), math.cos(phi_p), 0.0])
+        sig = math.sqrt(t @ Cp @ t + prm.sigma_rphi[L] ** 2)
+        w_r = min(max(prm.n_sigma * sig, prm.win_min_rphi[L]), prm.win_max_rphi[L])
+        w_z = min(max(prm.n_sigma * math.sqrt(Cp[2, 2] + prm.sigma_z[L] ** 2), prm.win_min_z[L]), prm.win_max_z[L])
+        mr, mz = EDGE_REL * w_r + epos, EDGE_REL * w_z + epos
+        a, b = int(pools.layer_offsets[L]), int(pools.layer_offsets[L + 1])
+        pos = np.asarray(pools.pos[:, a:b], np.float64)
+        cov = np.asarray(pools.cov[:, a:b], np.float64)
+        ids = np.asarray(pools.hit_id[a:b], np.int64)
+        darc = np.abs(_wrap(np.arctan2(pos[1], pos[0]) - phi_p)) * R
+        dz = np.abs(pos[2] - z)
+        surely_in = (darc <= w_r - mr) & (dz <= w_z - mz)
+        maybe_in = (darc <= w_r + mr) & (dz <= w_z + mz)
+        sel = np.nonzero(maybe_in)[0]
+        chi2 = np.zeros(0)
+        kap = np.zeros(0)
+        if sel.size:
+            chi2, kap = _chi2(pp[:3], Cp, pos[:, sel].T, cov[:, sel])
+        cerr = np.array([chi2_error(prm.chi2_max, epos, sig, k_) for k_ in kap])
+        surely_acc = surely_in[sel] & (chi2 < prm.chi2_max - cerr)
+        if hid >= 0:
+            j = np.nonzero(ids[sel] == hid)[0]
+            if j.size == 0:
+                return dict(valid=False, reason="hit %d outside the window at step %d" % (hid, step), score=score,
+                            err=0.0)
+            j = int(j[0])
+            if not chi2[j] <= prm.chi2_max + cerr[j]:
+                return dict(valid=False, reason="hit %d above the cut at step %d" % (hid, step), score=score, err=0.0)
+            score += prm.hit_bonus - float(chi2[j])
+            errs.append(chi2_error(float(chi2[j]), epos, sig, float(kap[j])))
+            il = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+            V = torch.zeros(1, 3, 3, dtype=torch.float64)
+            for c_, (u, v) in enumerate(il):
+                V[0, u, v] = V[0, v, u] = float(cov[c_, sel[j]])
+            p, C, q, _, _ = O.update(p2, C2, q, torch.tensor(pos[:, sel[j]][None]), V)
+        elif hid == MISS:
+            if surely_acc.any():
+                return dict(valid=False, reason="miss at step %d with an accepted hit" % step, score=score, err=0.0)
+            if misses >= prm.max_miss:
+                return dict(valid=False, reason="miss beyond max_miss at step %d" % step, score=score, err=0.0)
+            misses += 1
+            score -= prm.miss_penalty
+            errs.append(0.0)
+            p, C = p2, C2
+        elif hid == STOP:
+            if surely_acc.any() or misses < prm.max_miss:
+                return dict(valid=False, reason="stop at step %d where the candidate can continue" % step,
+                            score=score, err=0.0)
+            stopped = True
+        else:
+            return dict(valid=False, reason="no candidate at step %d" % step, score=score, err=0.0)
+        layer = L
+    return dict(valid=True, reason="", score=score, err=math.sqrt(sum(e * e for e in errs)))
+
+
+def consistent_result(hits, scores, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams,
+                      oracle_hits, oracle_scores, oracle_err):
+    """Whether one seed's lists `hits` [beam, P] with their `scores` [beam]
+    are a result the search can give when its near decisions and its
+    rankings are resolved within the FP32 error model, against the oracle's
+    own result for that seed (oracle_hits, oracle_scores, oracle_err):
+    * every list is a history the search can take (replay), and its score
+      agrees with the replayed score to 1e-3 + RANK_SIGMAS * its error;
+    * the lists are distinct and in score order (descending, to the same
+      margin);
+    * an oracle list missing from `hits` scores no more than the lowest of
+      `hits` (replayed) plus the ranking margin of the two, and a list of
+      `hits` missing from the oracle's scores no less than the oracle's
+      lowest kept list minus that margin: within the error model either
+      could take the other's place.
+    Returns (ok, reason)."""
+    rows = [tuple(int(x) for x in r) for r in np.asarray(hits)]
+    live = [i for i, r in enumerate(rows) if r[0] != NO_CAND]
+    if len(set(rows[i] for i in live)) != len(live):
+        return False, "duplicate lists"
+    rep = {}
+    for i in live:
+        r = replay(rows[i], seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm)
+        if not r["valid"]:
+            return False, "list %d: %s" % (i, r["reason"])
+        if abs(float(scores[i]) - r["score"]) > 1e-3 + RANK_SIGMAS * r["err"]:
+            return False, "list %d: score %.6f against %.6f +- %.3g" % (i, float(scores[i]), r["score"], r["err"])
+        rep[rows[i]] = r
+    for a, b in zip(live[:-1], live[1:]):
+        m = 1e-3 + RANK_SIGMAS * math.hypot(rep[rows[a]]["err"], rep[rows[b]]["err"])
+        if float(scores[a]) < float(scores[b]) - m:
+            return False, "lists %d and %d out of score order" % (a, b)
+    orows = [tuple(int(x) for x in r) for r in np.asarray(oracle_hits)]
+    olive = [i for i, r in enumerate(orows) if r[0] != NO_CAND]
+    if len(olive) != len(live):
+        return False, "%d lists against the oracle's %d" % (len(live), len(olive))
+    if not live:
+        return True, ""
+    low = min(live, key=lambda i: rep[rows[i]]["score"])
+    olow = min(olive, key=lambda i: float(oracle_scores[i]))
+    for i in olive:
+        if orows[i] in rep:
+            continue
+        m = 1e-3 + RANK_SIGMAS * math.hypot(float(oracle_err[i]), rep[rows[low]]["err"])
+        if float(oracle_scores[i]) > rep[rows[low]]["score"] + m:
+            return False, "oracle list %d (score %.6f) missing above the lowest kept %.6f" % (
+                i, float(oracle_scores[i]), rep[rows[low]]["score"])
+    for i in live:
+        if rows[i] in orows:
+            continue
+        m = 1e-3 + RANK_SIGMAS * math.hypot(rep[rows[i]]["err"], float(oracle_err[olow]))
+        if rep[rows[i]]["score"] < float(oracle_scores[olow]) - m:
+            return False, "list %d (score %.6f) below the oracle's lowest kept %.6f" % (
+                i, rep[rows[i]]["score"], float(oracle_scores[olow]))
+    return True, ""

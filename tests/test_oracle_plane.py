@@ -56,6 +56,74 @@ def test_crossing_lands_on_the_generators_crossing():
     assert float((mu - torch.tensor(ev.hit_uv[0, e1])).abs().max()) < 1e-9
 
 
+def _first_root_by_scan(p, q, c, n, bz, lo=-O.S_BACK, step=0.05):
+    """The smallest root s > lo of n.(x(s) - c) within one turn, by brute
+    force: the first sign change on a grid of `step` cm, then bisection.
+    (nan, False) when h keeps its sign over the turn."""
+    w = float(O.omega(torch.tensor(q), torch.tensor(p[3]), bz))
+    s_max = lo + 2 * math.pi / abs(w)
+    grid = torch.arange(lo, s_max + step, step, dtype=DT)
+    grid = grid[grid <= s_max]
+    P_ = torch.tensor(p).expand(grid.numel(), 6)
+    Q_ = torch.full((grid.numel(),), float(q), dtype=DT)
+    h = ((O.helix_at(P_, Q_, grid, bz)[:, :3] - c) * n).sum(1)
+    ch = torch.nonzero(torch.sign(h[1:]) != torch.sign(h[:-1]))[:, 0]
+    if ch.numel() == 0:
+        return math.nan, False
+    a, b = float(grid[ch[0]]), float(grid[ch[0] + 1])
+    ha = float(h[ch[0]])
+    one = lambda s_: float(((O.helix_at(torch.tensor(p)[None], torch.tensor([float(q)], dtype=DT),
+                                        torch.tensor([s_], dtype=DT), bz)[0, :3] - c) * n).sum())
+    for _ in range(80):
+        m = 0.5 * (a + b)
+        hm = one(m)
+        if (hm < 0) == (ha < 0):
+            a, ha = m, hm
+        else:
+            b = m
+    return 0.5 * (a + b), True
+
+
+def test_crossing_is_the_first_root_found_by_brute_force():
+    """The crossing is the smallest root s > -1 cm within one turn, checked by
+    a scan and bisection: on the true states (the next module), with the
+    curvature raised so that low-pT tracks turn back before the module, and
+    with a module of the next layer a quarter turn away in phi (crossed far
+    from it, or not within the turn)."""
+    wl, ev = _event(300)
+    g = wl.geometry
+    c, n, u, v, x0 = P.frames(g.modules)
+    e0, e1 = _pairs(ev)
+    rng = np.random.default_rng(11)
+    pick = rng.choice(e0.size, 40, replace=False)
+    cases = []
+    for i in pick:
+        p = ev.truth_after[e0[i]].copy()
+        q = float(ev.charge[np.searchsorted(ev.hit_offsets, e0[i], side="right") - 1])
+        m = int(ev.hit_module[e1[i]])
+        lay = int(g.layer_of[m])
+        cases.append((p, q, m))
+        p2 = p.copy()
+        p2[3] *= 1.0 + 2.0 * rng.uniform()
+        cases.append((p2, q, m))
+        k = (m - g.base[lay]) % g.n_phi[lay]
+        j = (m - g.base[lay]) // g.n_phi[lay]
+        far = int(g.base[lay] + j * g.n_phi[lay] + (k + g.n_phi[lay] // 4) % g.n_phi[lay])
+        cases.append((p, q, far))
+    P_ = torch.tensor(np.array([x[0] for x in cases]))
+    Q_ = torch.tensor([x[1] for x in cases], dtype=DT)
+    M_ = torch.tensor([x[2] for x in cases])
+    s, ok = P.crossing_plane(P_, Q_, c[M_], n[M_], g.bz)
+    found = 0
+    for i, (p, q, m) in enumerate(cases):
+        sb, okb = _first_root_by_scan(p, q, c[m], n[m], g.bz)
+        assert bool(ok[i]) == okb, (i, float(s[i]), sb)
+        if okb:
+            found += 1
+            assert abs(float(s[i]) - sb) < 1e-8 * max(1.0, abs(sb)), (i, float(s[i]), sb)
+    assert 40 <= found < len(cases)
+
+
 def test_plane_jacobian_equals_central_differences():
     wl, ev = _event(60)
     g = wl.geometry

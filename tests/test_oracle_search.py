@@ -340,3 +340,46 @@ def test_valid_alternative_finds_results_of_several_flips():
     col = int(np.nonzero(bogus[row] >= 0)[0][0])
     bogus[row, col] = 987654321
     assert not KS.valid_alternative(bogus, p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm, budget=8)[0]
+
+
+def test_replay_reproduces_the_search_and_rejects_impossible_lists():
+    """replay of every list the search keeps gives that list's score
+    exactly, and consistent_result accepts the oracle's own result; a list
+    with a hit swapped for one outside the window, a miss where a hit is
+    surely accepted, or a score off by more than the margin is rejected."""
+    wl, ev, g, pools, p, C, q = search_inputs(40)
+    prm = default_params(g)
+    o = KS.score_hits(p, C, q, np.full(40, SEED_LAYER), PLAN, g, pools, prm)
+    checked = 0
+    for s in range(40):
+        rows = o["hits"][s]
+        for r in range(rows.shape[0]):
+            if rows[r, 0] == KS.NO_CAND:
+                continue
+            rp = KS.replay(rows[r], p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm)
+            assert rp["valid"], (s, r, rp["reason"])
+            assert abs(rp["score"] - o["score"][s, r]) <= 1e-9 * max(1.0, abs(o["score"][s, r]))
+            assert abs(rp["err"] - o["score_err"][s, r]) <= 1e-9 * max(1.0, o["score_err"][s, r])
+        ok, why = KS.consistent_result(rows, o["score"][s], p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm,
+                                       rows, o["score"][s], o["score_err"][s])
+        assert ok, (s, why)
+        checked += 1
+    assert checked == 40
+    # impossible lists on the first seed whose best list has hits on its first two steps
+    s = next(i for i in range(40) if (o["hits"][i, 0, :2] >= 0).all())
+    row = o["hits"][s, 0].copy()
+    # the pool hit of the first layer farthest from the seed in phi
+    a, b = int(pools.layer_offsets[PLAN[0]]), int(pools.layer_offsets[PLAN[0] + 1])
+    dphi = np.angle(np.exp(1j * (np.arctan2(pools.pos[1, a:b], pools.pos[0, a:b]) - np.arctan2(p[s, 1], p[s, 0]))))
+    far = int(pools.hit_id[a + int(np.argmax(np.abs(dphi)))])
+    bad = row.copy()
+    bad[0] = far
+    assert not KS.replay(bad, p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm)["valid"]
+    miss = row.copy()
+    miss[0] = KS.MISS
+    rp = KS.replay(miss, p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm)
+    assert not rp["valid"] and "accepted hit" in rp["reason"]
+    sc = o["score"][s].copy()
+    sc[0] += 1.0 + 10 * KS.RANK_SIGMAS * o["score_err"][s, 0]
+    assert not KS.consistent_result(o["hits"][s], sc, p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm,
+                                    o["hits"][s], o["score"][s], o["score_err"][s])[0]

@@ -121,7 +121,7 @@ class PlaneEvent:
 
 
 def plane_workloads() -> dict[str, PlaneWorkload]:
-    return {"tilted10": PlaneWorkload("tilted10", tilted_barrel(), 20_000, 1006)}
+    return {"tilted10": PlaneWorkload("tilted10", tilted_barrel(), 100_000, 1006)}
 
 
 def _plane_path(xa, ya, za, pha, cot, om, s0, c, n, steps=8):
@@ -163,7 +163,7 @@ def generate_planes(wl: PlaneWorkload, n_tracks: int | None = None, *, smear: bo
         phi0, theta0 = phi.copy(), theta.copy()
         x, y, z = vx.copy(), vy.copy(), vz.copy()
         ptot = pt / np.sin(theta)
-        recs = [[] for _ in range(m)]
+        recs = []           # per layer: arrays of the tracks that made a hit there
         alive = np.ones(m, bool)
         for l in range(L):
             act = np.nonzero(alive)[0]
@@ -216,32 +216,42 @@ def generate_planes(wl: PlaneWorkload, n_tracks: int | None = None, *, smear: bo
                 d_ps = np.zeros(act.size)
             new_th = np.clip(tha + d_th, 1e-3, np.pi - 1e-3)
             new_phi = nphi + d_ps / np.sin(tha)
-            for a in sel:
-                t = act[a]
-                truth = [nx[a], ny[a], nz[a], 1.0 / pta[a], _wrap(nphi[a]), tha[a]]
-                after = [nx[a], ny[a], nz[a], 1.0 / (p_[a] * np.sin(new_th[a])), _wrap(new_phi[a]), new_th[a]]
-                gpos = c_[:, a] + hu[a] * u_[:, a] + hv[a] * v_[:, a]
-                recs[t].append((int(mid[a]), l, hu[a], hv[a], gpos, truth, after))
+            truth = np.stack([nx, ny, nz, 1.0 / pta, _wrap(nphi), tha], axis=1)[sel]
+            after = np.stack([nx, ny, nz, 1.0 / (p_ * np.sin(new_th)), _wrap(new_phi), new_th], axis=1)[sel]
+            gpos = (c_ + hu * u_ + hv * v_)[:, sel]
+            recs.append(dict(t=act[sel], mid=mid[sel], layer=np.full(sel.size, l), hu=hu[sel], hv=hv[sel],
+                             gpos=gpos, truth=truth, after=after))
             t_ok = act[sel]
             x[t_ok], y[t_ok], z[t_ok] = nx[sel], ny[sel], nz[sel]
             phi[t_ok] = new_phi[sel]
             theta[t_ok] = new_th[sel]
-        for t in range(m):
-            if len(recs[t]) >= min_hits and have < n:
-                out.append((q[t], [vx[t], vy[t], vz[t], 1.0 / pt[t], _wrap(phi0[t]), theta0[t]], recs[t]))
-                have += 1
-    cnt = np.array([len(r[2]) for r in out])
+        # every track's records in layer order; tracks with enough hits are
+        # taken in generation order until n are had
+        if recs:
+            cat = {key: np.concatenate([r[key] for r in recs], axis=-1 if key == "gpos" else 0) for key in recs[0]}
+            order = np.argsort(cat["t"], kind="stable")
+            cnt = np.bincount(cat["t"], minlength=m)
+        else:
+            cat, order, cnt = None, np.zeros(0, np.int64), np.zeros(m, np.int64)
+        take = np.nonzero(cnt >= min_hits)[0][: n - have]
+        if take.size:
+            first = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+            idx = np.concatenate([order[first[t]:first[t] + cnt[t]] for t in take])
+            out.append(dict(q=q[take], vertex=np.stack([vx, vy, vz, 1.0 / pt, _wrap(phi0), theta0], axis=1)[take],
+                            cnt=cnt[take], mid=cat["mid"][idx], layer=cat["layer"][idx], hu=cat["hu"][idx],
+                            hv=cat["hv"][idx], gpos=cat["gpos"][:, idx], truth=cat["truth"][idx],
+                            after=cat["after"][idx]))
+            have += take.size
+    cat = lambda key, axis=0: np.concatenate([o[key] for o in out], axis=axis)
+    cnt = cat("cnt")
     off = np.zeros(n + 1, np.int32)
     off[1:] = np.cumsum(cnt)
-    flat = [h for r in out for h in r[2]]
+    nh = int(off[-1])
     cov1 = np.array([wl.sigma_u ** 2, 0.0, wl.sigma_v ** 2])
-    return PlaneEvent(geometry=g, charge=np.array([r[0] for r in out], np.int8),
-                      vertex=np.array([r[1] for r in out], np.float64), hit_offsets=off,
-                      hit_module=np.array([h[0] for h in flat], np.int32),
-                      hit_layer=np.array([h[1] for h in flat], np.int16),
-                      hit_valid=np.ones(len(flat), np.uint8),
-                      hit_uv=np.array([[h[2] for h in flat], [h[3] for h in flat]], np.float64),
-                      hit_cov_uv=np.repeat(cov1[:, None], len(flat), axis=1),
-                      hit_pos=np.array([h[4] for h in flat], np.float64).T.reshape(3, -1),
-                      truth=np.array([h[5] for h in flat], np.float64).reshape(-1, 6),
-                      truth_after=np.array([h[6] for h in flat], np.float64).reshape(-1, 6))
+    return PlaneEvent(geometry=g, charge=cat("q").astype(np.int8), vertex=cat("vertex").astype(np.float64),
+                      hit_offsets=off, hit_module=cat("mid").astype(np.int32),
+                      hit_layer=cat("layer").astype(np.int16), hit_valid=np.ones(nh, np.uint8),
+                      hit_uv=np.stack([cat("hu"), cat("hv")]).astype(np.float64),
+                      hit_cov_uv=np.repeat(cov1[:, None], nh, axis=1),
+                      hit_pos=np.ascontiguousarray(cat("gpos", 1), np.float64),
+                      truth=cat("truth").astype(np.float64), truth_after=cat("after").astype(np.float64))
