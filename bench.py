@@ -36,6 +36,12 @@ FLOP_SMOOTH_COMBINE = 1900
 # the recomputation of forward states from checkpoints
 FLOP_VJP_VALID_ENTRY = 2660
 FLOP_VJP_HOLE_ENTRY = 1550
+# one entry of the forward fit over tilted modules (propagation to a plane:
+# the crossing search, ~4 steps of ~55 after a first evaluation, ~265; the
+# Jacobian, transport, 3-D normal projection and material, ~585; the 2-D
+# local update, ~430)
+FLOP_PLANE_VALID_ENTRY = 1280
+FLOP_PLANE_HOLE_ENTRY = 850
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
@@ -192,7 +198,7 @@ def cpu_baseline(ev, seconds=10.0, seconds_single=6.0, single_tracks=5000):
 def fp64_lane_fraction(ctx, K, ev, dt_out=None):
     """How often the FP32 fit of a barrel batch (no holes) runs an update in
     its FP64 lane: the prior position variance exceeds the hit variance by
-    more than 1e4 on an axis.  The prior at entry j >= 1 is the forward fit's
+    more than 1e4 in some direction (tr(V^-1 C_pos) > 1e4).  The prior at entry j >= 1 is the forward fit's
     filtered state after entry j - 1 (its seg = 1 checkpoint) propagated to
     entry j's layer with material (kf_propagate); entry 0 starts from the
     diffuse seed covariance (unit position variances), which is always above
@@ -226,15 +232,23 @@ def fp64_lane_fraction(ctx, K, ev, dt_out=None):
         tgt = t["hit_layer"][e].contiguous()
         frm = t["hit_layer"][e - 1].contiguous()
         _, cp, _, _ = ctx.propagate(st, cv, q, tgt, geom, from_layer=frm, apply_material=True)
-        V = t["hit_cov"][:, e]
+        V = t["hit_cov"][:, e].double()
         valid = t["hit_valid"][e] != 0
-        hi = (cp[0] > 1e4 * V[0]) | (cp[2] > 1e4 * V[2]) | (cp[5] > 1e4 * V[5])
+        c = cp.double()
+        # tr(V^-1 C_pos) from the cofactors of V (the fit's own test)
+        a_, b_, cc, d_, e_, f_ = V[0], V[1], V[2], V[3], V[4], V[5]
+        i00, i10, i11 = cc * f_ - e_ * e_, d_ * e_ - b_ * f_, a_ * f_ - d_ * d_
+        i20, i21, i22 = b_ * e_ - cc * d_, b_ * d_ - a_ * e_, a_ * cc - b_ * b_
+        det = a_ * i00 + b_ * i10 + d_ * i20
+        tr = i00 * c[0] + i11 * c[2] + i22 * c[5] + 2 * (i10 * c[1] + i20 * c[3] + i21 * c[4])
+        hi = ~(tr <= 1e4 * det)
         lanes += int((hi & valid).sum().item())
         updates += int(valid.sum().item())
     flagged = int(((out["status"] & K.TRK_FP64_FALLBACK) != 0).sum().item())
     return {"updates": updates, "fp64_lane_updates": lanes, "fp64_lane_fraction": lanes / max(updates, 1),
             "tracks_flagged_fp64": flagged, "tracks_flagged_fp64_fraction": flagged / n,
-            "rule": "whole update in FP64 when a prior position variance > 1e4 x the hit variance on that axis; "
+            "rule": "whole update in FP64 when tr(V^-1 C_pos) > 1e4 (the prior position variance exceeds the hit's "
+                    "by more than 1e4 in some direction); "
                     "the 3x3 inverse alone in FP64 when kappa > 1e6, det <= 0 or non-finite"}
 
 
@@ -388,13 +402,15 @@ def bench_backward(ctx, K, ev, args, steps=None):
         ctx.seed_fit_tracks(*hits, geom, 0, checkpoints=ck, seg=1, max_len=max_len, out=fwd_ck)
         smooth()
 
-    # final fit with outlier rejection (the default cut) on the same batch
+    # final fit with outlier rejection (the default cut, up to three
+    # rejection rounds) on the same batch, from its hits
     out_f = K.fit_outputs(n, dt, dev)
     mask = torch.empty(ev.n_hits, dtype=torch.uint8, device=dev)
+    hchi = torch.empty(ev.n_hits, dtype=dt, device=dev)
 
     def final():
-        ctx.final_fit(fwd, *hits, geom, chi2_cut=K.FINAL_CHI2_CUT, cov_scale=K.BACKWARD_COV_SCALE, max_len=26,
-                      out=out_f, outlier=mask)
+        ctx.final_fit(*hits, geom, 0, chi2_cut=K.FINAL_CHI2_CUT, cov_scale=K.BACKWARD_COV_SCALE, max_len=26,
+                      out=out_f, outlier=mask, hit_chi2=hchi)
 
     k = args.steps if steps is None else steps
     ms_b = time_loop(bwd, k, args.warmup)
@@ -415,10 +431,12 @@ def bench_backward(ctx, K, ev, args, steps=None):
             "ms_forward_with_checkpoints_and_smooth_step": ms_sms, "achieved_tflops_smooth": tf_sm,
             "smooth_kernel": "backward_kernel<float, 2, 1> + smooth_combine_kernel<float> (FP64 5x5 combination "
                              "per entry)",
-            "final_kernel": "backward_kernel<float, 2, 2>",
-            "ms_final_fit": ms_f, "tracks_per_s_final_fit": n / (ms_f * 1e-3),
-            "achieved_tflops_final_fit": flops / (ms_f * 1e-3) / 1e12, "final_chi2_cut": K.FINAL_CHI2_CUT,
-            "final_rejected_hits": int(mask.sum().item())}
+            "final_fit": "kf_final_fit: rounds of seeding + forward fit + smoothing backward fit, each rejecting the "
+                         "worst hit by unbiased chi2 above the cut (at most %d rounds with a rejection)"
+                         % K.FINAL_MAX_REJECT,
+            "ms_final_fit": ms_f, "tracks_per_s_final_fit": n / (ms_f * 1e-3), "final_chi2_cut": K.FINAL_CHI2_CUT,
+            "final_rejected_hits": int(mask.sum().item()),
+            "final_tracks_with_rejection": int(((out_f["status"] & K.TRK_OUTLIER) != 0).sum().item())}
 
 
 def bench_search(ctx, K, args, sample=300):
@@ -497,10 +515,91 @@ def bench_search(ctx, K, args, sample=300):
         o = KS.score_hits(p, C, q, np.full(sample, 2), plan, g, pools, default_params(g))
         same = np.all(hs == o["hits"], axis=(1, 2))
         fl = o["flagged"]
+        # a flagged seed that differs must hold a result its near decisions allow
+        diff_fl = np.nonzero(~same & fl)[0]
+        valid = sum(KS.valid_alternative(hs[s], p[s], C[s], q[s], 2, plan, g, pools, default_params(g), budget=16)[0]
+                    or KS.consistent_result(hs[s], out[1].cpu().numpy()[s], p[s], C[s], q[s], 2, plan, g, pools,
+                                            default_params(g), o["hits"][s], o["score"][s], o["score_err"][s])[0]
+                    for s in diff_fl)
         res["parity_sample"] = {"seeds": sample, "flagged": int(fl.sum()), "identical": int(same.sum()),
                                 "unflagged_mismatch": int((~same & ~fl).sum()),
+                                "flagged_different": int(diff_fl.size), "flagged_different_valid": int(valid),
                                 "seeds_from": "FP64 oracle three-hit fit rounded to FP32 (both sides)",
                                 "window_hits_per_candidate_layer": o["n_window_hits"] / (sample * len(plan))}
+    return res
+
+
+def bench_planes(ctx, K, args, sample=None):
+    """Forward fit over tilted planar modules: 100,000 tracks through the
+    10-layer tilted barrel (6520 modules), 2-D local hits.  A step is the
+    local-to-global map of the hits, three-hit seeding and the fit
+    (kf_plane_to_global, kf_make_seeds, kf_fit_plane_tracks); the fit kernel
+    is also timed alone.  Accuracy: the same fit from the oracle's seeds
+    (rounded to FP32, both sides) against the FP64 plane oracle."""
+    import torch
+    from toygen import generate_planes, plane_workloads
+    dev = torch.device("cuda", 0)
+    wl = plane_workloads()["tilted10"]
+    log("generating", wl.name, wl.n_tracks)
+    ev = generate_planes(wl)
+    g = wl.geometry
+    n = ev.n_tracks
+    pg = K.PlaneGeometry.from_toy(g, torch.float32)
+    t = K.plane_event_tensors(ev, torch.float32, dev)
+    pos = torch.empty(3, ev.n_hits, dtype=torch.float32, device=dev)
+    seeds = (torch.empty(6, n, dtype=torch.float32, device=dev), torch.empty(21, n, dtype=torch.float32, device=dev),
+             torch.empty(n, dtype=torch.int8, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    out = K.fit_outputs(n, torch.float32, dev)
+
+    def seed():
+        ctx.plane_to_global(t["hit_module"], t["hit_uv"], pg, out=pos)
+        ctx.make_seeds(t["hit_offsets"], t["hit_valid"], pos, g.bz, 0, out=seeds)
+
+    def fit():
+        ctx.fit_plane_tracks(seeds[0], seeds[1], seeds[2], t["hit_offsets"], t["hit_module"], t["hit_valid"],
+                             t["hit_uv"], t["hit_cov_uv"], pg, out=out)
+
+    def step():
+        seed()
+        fit()
+
+    ms_step = time_loop(step, args.steps, args.warmup)
+    # the fit alone: one kernel launch per call on the current stream
+    ms_fit = time_loop(fit, args.steps, args.warmup)
+    valid = int(ev.hit_valid.sum())
+    flops = valid * FLOP_PLANE_VALID_ENTRY + (ev.n_hits - valid) * FLOP_PLANE_HOLE_ENTRY
+    tf = flops / (ms_fit * 1e-3) / 1e12
+    res = {"workload": "tilted10: %d tracks x 10 tilted-module barrel layers (%d modules)" % (n, g.n_modules),
+           "tracks": n, "entries": int(ev.n_hits), "ms_step": ms_step, "tracks_per_s": n / (ms_step * 1e-3),
+           "ms_fit": ms_fit, "tracks_per_s_fit": n / (ms_fit * 1e-3), "kernel": "fit_plane_kernel<float>",
+           "algorithmic_flop_per_launch": flops, "achieved_tflops": tf, "frac_fp32_peak": tf / FP32_PEAK_TFLOPS,
+           "ms_source": "torch events on the launching stream around kf_fit_plane_tracks (one kernel launch)",
+           "step": "kf_plane_to_global + kf_make_seeds + kf_fit_plane_tracks",
+           "status_bits_seen": int(np.bitwise_or.reduce(out["status"].cpu().numpy()))}
+    if not args.no_accuracy:
+        from oracle import kf_oracle as O
+        from oracle import kf_plane as P
+        from parity import chi2_error, param_error, rounded
+        tab = rounded(g.modules, torch.float32)
+        uv = rounded(ev.hit_uv, torch.float32)
+        cov = rounded(ev.hit_cov_uv, torch.float32)
+        sp, sC, sq, _ = P.make_seeds_planes(ev.hit_offsets, ev.hit_module, ev.hit_valid, uv, tab, g.bz)
+        sp = torch.tensor(rounded(sp.numpy(), torch.float32))
+        o = P.fit_plane_tracks(sp, sC, sq, ev.hit_offsets, ev.hit_module, ev.hit_valid, uv, cov, tab, g)
+        il = np.tril_indices(6)
+        f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt).contiguous()
+        ctx.fit_plane_tracks(f(sp.numpy().T, torch.float32), f(sC.numpy()[:, il[0], il[1]].T, torch.float32),
+                             f(sq.numpy(), torch.int8), t["hit_offsets"], t["hit_module"], t["hit_valid"],
+                             t["hit_uv"], t["hit_cov_uv"], pg, out=out)
+        torch.cuda.synchronize()
+        ep = param_error(out["state"].double().cpu().numpy().T, o["p"].numpy()).max(axis=1)
+        ec = chi2_error(out["chi2"].double().cpu().numpy(), o["chi2"].numpy())
+        st_same = (out["status"].cpu().numpy() & ~O.FP64_FALLBACK) == (o["status"].numpy() & ~O.FP64_FALLBACK)
+        res["accuracy_vs_oracle"] = {"tracks": n, "max_param_err": float(ep.max()), "max_chi2_err": float(ec.max()),
+                                     "frac_within_tolerance": {"param": float((ep <= 1e-4).mean()),
+                                                               "chi2": float((ec <= 1e-3).mean())},
+                                     "status_identical": float(st_same.mean()),
+                                     "seeds_from": "FP64 oracle three-hit seeds rounded to FP32 (both sides)"}
     return res
 
 
@@ -578,6 +677,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint workload")
     ap.add_argument("--no-search", action="store_true", help="skip the combinatorial search workload")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward-fit workload")
+    ap.add_argument("--no-planes", action="store_true", help="skip the tilted-module workload")
     ap.add_argument("--retune", action="store_true", help="ignore the autotune cache")
     ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "kf_autotune.json"))
     ap.add_argument("--launch", default=None,
@@ -712,6 +812,8 @@ def main():
         line["fwd_adjoint_align20_seg1"] = bench_adjoint(ctx, K, generate, workloads, args, seg=1)
     if not args.no_search:
         line["search20"] = bench_search(ctx, K, args)
+    if not args.no_planes:
+        line["planes_tilted10"] = bench_planes(ctx, K, args)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(ev)

@@ -28,7 +28,7 @@
  *   and return; none synchronises the stream.
  *   Device memory: kf_create allocates a few bytes of counters and
  *   kf_reserve the packed-layout workspace.  kf_score_hits, kf_fit_adjoint
- *   (its alignment reduction) and kf_remove_duplicates keep a context-owned
+ *   (its alignment reduction), kf_final_fit and kf_remove_duplicates keep a context-owned
  *   workspace that they grow on demand (hipMalloc, which can synchronise the
  *   device and must not happen under graph capture); a call with sizes no
  *   larger than an earlier call's on the same context allocates nothing.
@@ -106,7 +106,7 @@ const char *kf_last_error(void);
 /* Seed every track from three of its valid hits (helix through three points:
  * transverse Menger curvature, then the polar angle from the arc length;
  * position = the first chosen hit).  mode 0: the first three valid hits.
- * mode 1: the first valid hit, then each next valid hit at least 3 cm away
+ * mode 1: the first valid hit, then each next valid hit at least 2.5 cm away
  * (transverse) from the previously chosen one -- a longer lever arm for tracks
  * whose first hits are close in the transverse plane.  The seed covariance is
  * diag(1, 1, 1, 1, 0.01, 0.01) (a diffuse prior).
@@ -200,7 +200,7 @@ int kf_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
 
 /* Seeding and fit in one launch: every track is seeded from its own hits
  * exactly as kf_make_seeds does in seed_mode (0: the first three valid hits;
- * 1: spaced by >= 3 cm in the transverse plane), with geom->bz_tesla as the
+ * 1: spaced by >= 2.5 cm in the transverse plane), with geom->bz_tesla as the
  * field and the same wide diagonal covariance, then fitted as kf_fit_tracks
  * fits it; results are bit-identical to kf_make_seeds followed by
  * kf_fit_tracks with the same arguments, except that trk_status[t] holds
@@ -292,27 +292,56 @@ int kf_smooth_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                      void *chi2, int32_t *ndf, uint32_t *trk_status,
                      void *smooth_state, void *smooth_cov, void *stream);
 
-/* Final fit with outlier rejection (the backward fit of Sec. 2.2, step 4,
- * with the hit rejection the paper names for the final fit): the backward
- * fit of kf_backward_fit (the same arguments and rules) in which a valid hit
- * whose chi2 against the backward prediction (the increment its update would
- * add) exceeds chi2_cut is not used.  Its entry is taken as a hole (the
- * layer's material only): its chi2 is not added, ndf does not count it, and
- * the track gets KF_TRK_OUTLIER.  A NaN chi2 is not above the cut (the step
- * then stops the track as non-finite).  One pass: a hit once accepted is not
- * reconsidered.  chi2_cut > 0; +inf gives kf_backward_fit's result.
- * outlier [n_hits] (device, caller-owned, may be NULL): for every entry of
- * the n tracks (hit_offsets[0] .. hit_offsets[n] - 1), 1 if its hit was
- * rejected, else 0.
- * KF_ERR_ARG as kf_backward_fit, and for chi2_cut not > 0 (NaN included). */
-int kf_final_fit(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
-                 const void *state_in, const void *cov_in, const int8_t *charge_in,
-                 const uint32_t *fwd_status,
+/* Final fit with outlier rejection (the final fit the paper names in Sec. 2.2,
+ * step 4, and Sec. 4 as the next target of the method, where outlier
+ * rejection is part of it; the rejection rule is this library's reading, the
+ * paper gives none).  Rounds of refit and reject-the-worst on the hits of
+ * each track:
+ *   round i = 0 .. max_reject, for every track still open: the seeding and
+ *   forward fit of kf_seed_fit_tracks (seed_mode) over the track's used hits
+ *   (its valid hits not yet rejected), then the backward fit with smoothing
+ *   of kf_smooth_tracks (cov_scale); every used hit gets its unbiased chi2,
+ *   its chi2 against the estimate of the track made from its other hits:
+ *   the forward prediction at the hit's entry (the hits before it) combined
+ *   with the backward pass's prediction there (the hits after it), or the
+ *   forward prediction alone at the last used entry; with (x, C) that
+ *   estimate, r = m - H x, S = V + H C H^T, chi2 = r^T S^-1 r (FP64
+ *   arithmetic; NaN where the combination is not positive definite or the
+ *   entry was not reached).  In the linear model it equals the smoothed
+ *   residual's r_s^T (V - H C_s H^T)^-1 r_s, but keeps its digits where the
+ *   hit dominates the smoothed state.  If i < max_reject,
+ *   the track was refitted, its worst used hit (largest chi2; the first entry
+ *   among equals; NaN never counts) has chi2 > chi2_cut and the track keeps
+ *   at least min_keep used hits without it, that hit is rejected and the
+ *   track stays open; otherwise the track is closed with the round's
+ *   backward-fit result.
+ * Outputs (device, caller-owned): state_out [6][ld], cov_out [21][ld],
+ * charge_out [n] -- the backward fit's state on the track's first used entry
+ * -- chi2 [n] and ndf [n] of that backward pass (ndf = 2 * used hits - 5),
+ * trk_status [n] (its status, plus KF_TRK_OUTLIER if a hit was rejected;
+ * KF_TRK_BAD_INPUT for a track the forward fit could not seed or finish);
+ * outlier [n_hits] (required): 1 for every rejected entry of the n tracks,
+ * else 0; hit_chi2 [n_hits] (may be NULL): a used hit's unbiased chi2 in the
+ * round its track closed, a rejected hit's in the round it was rejected,
+ * NaN for holes, for entries not reached and for every hit of a track whose
+ * forward fit stopped or could not be seeded in that round (the backward
+ * pass did not refit it: there is no estimate from its other hits).  Entries outside the n tracks'
+ * ranges are not written.
+ * The rounds run on a context-owned workspace (about (2 * 28 + 55 * max_len)
+ * values of the precision per track plus one byte per hit; grown on demand,
+ * KF_ERR_NOMEM if that fails) and are enqueued without waiting for the device:
+ * max_reject + 1 rounds, closed tracks costing a round almost nothing.  The
+ * forward fit runs in the context's launch shape for the precision (never in
+ * a graph, never timed).
+ * KF_ERR_ARG for chi2_cut not > 0 (NaN included), max_reject outside
+ * [0, 64], min_keep outside [3, 64], a seed_mode other than 0 or 1, and the
+ * argument errors of kf_seed_fit_tracks. */
+int kf_final_fit(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld, int32_t seed_mode,
                  const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
-                 int64_t n_hits, const void *hit_pos, const void *hit_cov,
-                 const kf_geometry *geom, double cov_scale, double chi2_cut, int32_t max_len,
-                 void *state_out, void *cov_out, int8_t *charge_out,
-                 void *chi2, int32_t *ndf, uint32_t *trk_status, uint8_t *outlier, void *stream);
+                 int64_t n_hits, const void *hit_pos, const void *hit_cov, const kf_geometry *geom,
+                 double cov_scale, double chi2_cut, int32_t max_reject, int32_t min_keep, int32_t max_len,
+                 void *state_out, void *cov_out, int8_t *charge_out, void *chi2, int32_t *ndf,
+                 uint32_t *trk_status, uint8_t *outlier, void *hit_chi2, void *stream);
 
 /* Duplicate removal among found tracks (the end of track finding, Sec. 2.2:
  * each seed is represented by its best candidate, and tracks found from
@@ -459,6 +488,87 @@ int kf_fit_adjoint_noalloc(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld
                            const void *dL_dchi2,
                            void *grad_seed, void *grad_hit_pos, void *grad_align,
                            const uint32_t *trk_status, void *stream);
+
+/* ---- tilted planar modules ----------------------------------------------------
+ * The Phase-2 layout of Sec. 3.1 describes each detector module by its
+ * position, its normal vector and its phi-direction vector, and needs
+ * propagation to such modules and Kalman updates on them.  A module here is
+ * the plane through its centre c with unit normal n; its local frame is u
+ * (the unit phi-direction, lying in the plane) and v = n x u.  A hit on a
+ * module is the pair of local coordinates (m_u, m_v) = ((x - c).u, (x - c).v)
+ * of its position x, with a 2x2 covariance packed (uu, vu, vv).
+ * Module table: DEVICE array [10][n_modules] of the call's float type, rows
+ * cx cy cz nx ny nz ux uy uz x_over_x0 (x/X0 at normal incidence); n and u
+ * must be unit vectors with u.n = 0 (not checked: the table is on the device).
+ * The struct itself is a HOST struct read during the call. */
+typedef struct {
+  int64_t n_modules;        /* >= 1; module ids are 0 .. n_modules - 1 */
+  const void *modules;      /* DEVICE [10][n_modules] */
+  double bz_tesla;          /* uniform solenoidal field, != 0 */
+  double particle_mass_gev; /* mass hypothesis for the scattering angle, > 0 */
+} kf_plane_geometry;
+
+/* Propagate n tracks to the planes of their target modules: the helix of
+ * kf_propagate to the root s > -1 cm of n.(x(s) - c) = 0 (Newton's method from
+ * the straight-line estimate; accepted within 1e-9 cm of the plane in FP64,
+ * within 64 * 2^-23 * (|cx| + |cy| + |cz| + 1) cm in FP32), the
+ * surface-to-surface Jacobian F = G + g (ds/dp) with
+ * ds/dp = -(n^T G_pos) / (n . g_pos), C' = F C F^T (the plane normal, in
+ * position, is then a null vector and is imposed as one), and, if
+ * apply_material, the Highland noise of x/X0 / |n . d| at the crossing (d the
+ * unit direction).  target_module[n] (device); the other arrays as in
+ * kf_propagate.  A track with no crossing is copied unchanged and gets
+ * KF_TRK_NO_CROSSING; one whose module id is out of range, KF_TRK_BAD_INPUT. */
+int kf_propagate_plane(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                       const void *state_in, const void *cov_in, const int8_t *charge,
+                       const int32_t *target_module, const kf_plane_geometry *geom,
+                       int32_t apply_material, void *state_out, void *cov_out, void *path_len,
+                       uint32_t *trk_status, void *stream);
+
+/* Kalman update with one local 2-D hit per track on its module (Sec. 3.1's
+ * updates on tilted modules): H = [u^T 0; v^T 0] (2 x 6),
+ * r = m - H (x - c), S = H C H^T + V (2 x 2), chi2 = r^T S^-1 r,
+ * K = C H^T S^-1, p += K r, C = (I-KH) C (I-KH)^T + K V K^T (symmetric by
+ * construction), then the charge flip and phi wrap of kf_update.  FP32 lanes
+ * whose projected prior exceeds the hit covariance by more than 1e4
+ * (tr(V^-1 H C H^T) > 1e4) are updated in FP64, and S^-1 is taken in FP64
+ * when det S <= 0 or its condition estimate exceeds 1e6
+ * (KF_TRK_FP64_FALLBACK).  state[6][ld], cov[21][ld], charge[n] in place;
+ * module[n], hit_uv[2][ld], hit_cov_uv[3][ld] (uu, vu, vv); chi2[n] out;
+ * trk_status[n] bits OR-ed in (KF_TRK_BAD_INPUT for a module id out of
+ * range: the track is left unchanged with chi2 0). */
+int kf_update_plane(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                    void *state, void *cov, int8_t *charge, const int32_t *module,
+                    const void *hit_uv, const void *hit_cov_uv, const kf_plane_geometry *geom,
+                    void *chi2, uint32_t *trk_status, void *stream);
+
+/* Forward fit over tilted modules: the rules of kf_fit_tracks with a module
+ * per entry.  Track t owns entries [hit_offsets[t], hit_offsets[t+1]):
+ * hit_module[e] (int32), hit_valid[e] (0 = hole: propagation and material,
+ * no update), hit_uv[2][n_hits], hit_cov_uv[3][n_hits].  The fit starts at
+ * the first valid entry, where the seed sits on the hit; every entry, that
+ * one included (a step of length ~0 onto the plane, which removes the seed
+ * covariance's component along the normal), is propagated to with its
+ * module's material (kf_propagate_plane) and, if valid, gets the local update
+ * (kf_update_plane).  A failed crossing, a module id out of range
+ * (KF_TRK_BAD_INPUT) or a step that turns the state non-finite (rolled back,
+ * KF_TRK_NONFINITE) stops the track.  Outputs as in kf_fit_tracks:
+ * state_out[6][ld], cov_out[21][ld], charge_out[n], chi2[n], ndf[n]
+ * (= 2 * used hits - 5), trk_status[n] (overwritten; KF_TRK_BAD_INPUT also
+ * for a track without a valid entry).  Seeds can be made with kf_make_seeds
+ * from the hits' global positions (kf_plane_to_global). */
+int kf_fit_plane_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
+                        const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
+                        const int32_t *hit_offsets, const int32_t *hit_module, const uint8_t *hit_valid,
+                        int64_t n_hits, const void *hit_uv, const void *hit_cov_uv,
+                        const kf_plane_geometry *geom, void *state_out, void *cov_out, int8_t *charge_out,
+                        void *chi2, int32_t *ndf, uint32_t *trk_status, void *stream);
+
+/* Global positions c + m_u u + m_v v of n_hits local hits (module[n_hits],
+ * hit_uv[2][n_hits], device) into hit_pos[3][n_hits] (device), e.g. for
+ * kf_make_seeds.  A module id out of range gives NaN coordinates. */
+int kf_plane_to_global(kf_ctx *ctx, kf_precision prec, int64_t n_hits, const int32_t *module,
+                       const void *hit_uv, const kf_plane_geometry *geom, void *hit_pos, void *stream);
 
 /* Reserve the workspace of kf_fit_tracks' packed hit layout for up to
  * max_tracks tracks of up to max_len (1..64) entries (about

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkf.so")
-SOURCES = ["kf_api.hip", "kf_kernels.hip", "kf_adjoint.hip", "kf_search.hip", "kf_backward.hip", "kf_dedup.hip"]
+SOURCES = ["kf_api.hip", "kf_kernels.hip", "kf_adjoint.hip", "kf_search.hip", "kf_backward.hip", "kf_dedup.hip", "kf_final.hip",
+           "kf_plane.hip"]
 ARCH = os.environ.get("KF_OFFLOAD_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of the generated code

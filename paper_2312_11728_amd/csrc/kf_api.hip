@@ -16,6 +16,7 @@
 #include "kf_backward.hpp"
 #include "kf_dedup.hpp"
 #include "kf_kernels.hpp"
+#include "kf_plane_launch.hpp"
 #include "kf_search_launch.hpp"
 
 struct kf_ctx {
@@ -44,6 +45,9 @@ struct kf_ctx {
   // workspace of duplicate removal (grown on demand)
   void* dedup_mem = nullptr;
   size_t dedup_bytes = 0;
+  // workspace of the final fit's rounds (grown on demand)
+  void* final_mem = nullptr;
+  size_t final_bytes = 0;
   // event pairs around the fit kernel of direct launches (kf_set_kernel_timing)
   bool timing = false;
   std::vector<hipEvent_t> t_start, t_stop;
@@ -213,6 +217,7 @@ int kf_destroy(kf_ctx* c) {
   if (c->red_mem) hipFree(c->red_mem);
   if (c->search_mem) hipFree(c->search_mem);
   if (c->dedup_mem) hipFree(c->dedup_mem);
+  if (c->final_mem) hipFree(c->final_mem);
   hipSetDevice(prev);
   delete c;
   return ok();
@@ -356,14 +361,14 @@ kf::FitArgs<T> make_fit_args(int64_t n, int64_t ld, const void* seed_state, cons
 // fit kernel (with the tile-counter reset of the persistent form).
 template <typename T>
 hipError_t run_fit(kf_ctx* ctx, kf::FitArgs<T> a, const kf::GeomArgs& g, const kf::FitLaunch& l, int layout,
-                   hipStream_t s) {
+                   hipStream_t s, bool may_time = true) {
   if (layout == 1 || layout == 2 || layout == 4) {
     hipError_t e = kf::launch_pack(a, ctx->work, layout, &a.pk, s);
     if (e != hipSuccess) return e;
   }
   a.packed = layout;
   // graph captures (on the context's capture stream) carry no timing events
-  const bool timed = ctx->timing && s != ctx->capture;
+  const bool timed = may_time && ctx->timing && s != ctx->capture;
   if (timed && ctx->t_used >= int(ctx->t_start.size())) ++ctx->t_dropped;
   const int slot = timed && ctx->t_used < int(ctx->t_start.size()) ? ctx->t_used++ : -1;
   if (slot >= 0) {
@@ -590,8 +595,7 @@ int backward_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
                   const int32_t* hit_offsets, const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits,
                   const void* hit_pos, const void* hit_cov, const kf_geometry* geom, double cov_scale,
                   int32_t max_len, void* state_out, void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf,
-                  uint32_t* trk_status, void* smooth_state, void* smooth_cov, const char* name, void* stream,
-                  bool final_fit = false, double chi2_cut = 0.0, uint8_t* outlier = nullptr) {
+                  uint32_t* trk_status, void* smooth_state, void* smooth_cov, const char* name, void* stream) {
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
@@ -599,7 +603,6 @@ int backward_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
   if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
   if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);
   if (!std::isfinite(cov_scale) || !(cov_scale >= 1.0)) return fail(KF_ERR_ARG, "cov_scale must be finite and >= 1");
-  if (final_fit && !(chi2_cut > 0.0)) return fail(KF_ERR_ARG, "chi2_cut must be > 0");
   if (n == 0) return ok();
   KF_REQUIRE(state_in);
   KF_REQUIRE(cov_in);
@@ -641,8 +644,7 @@ int backward_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
     b.n_seg_f = n_seg_f;
     b.smooth_state = (float*)smooth_state;
     b.smooth_cov = (float*)smooth_cov;
-    e = final_fit ? kf::launch_final_fit(kf::FinalArgs<float>{b, float(chi2_cut), outlier}, g, s)
-                  : kf::launch_backward(b, g, s);
+    e = kf::launch_backward(b, g, s);
   } else {
     kf::BwdArgs<double> b;
     b.f = make_fit_args<double>(n, ld, state_in, cov_in, charge_in, hit_offsets, hit_layer, hit_valid, n_hits,
@@ -655,8 +657,7 @@ int backward_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
     b.n_seg_f = n_seg_f;
     b.smooth_state = (double*)smooth_state;
     b.smooth_cov = (double*)smooth_cov;
-    e = final_fit ? kf::launch_final_fit(kf::FinalArgs<double>{b, chi2_cut, outlier}, g, s)
-                  : kf::launch_backward(b, g, s);
+    e = kf::launch_backward(b, g, s);
   }
   if (e != hipSuccess) return hip_fail(e, name);
   return ok();
@@ -689,17 +690,6 @@ int kf_smooth_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, cons
   return backward_impl(ctx, prec, n, ld, state_in, cov_in, charge_in, fwd_status, fwd_checkpoints, hit_offsets,
                        hit_layer, hit_valid, n_hits, hit_pos, hit_cov, geom, cov_scale, max_len, state_out, cov_out,
                        charge_out, chi2, ndf, trk_status, smooth_state, smooth_cov, "kf_smooth_tracks", stream);
-}
-
-int kf_final_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* state_in, const void* cov_in,
-                 const int8_t* charge_in, const uint32_t* fwd_status, const int32_t* hit_offsets,
-                 const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
-                 const void* hit_cov, const kf_geometry* geom, double cov_scale, double chi2_cut, int32_t max_len,
-                 void* state_out, void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf,
-                 uint32_t* trk_status, uint8_t* outlier, void* stream) {
-  return backward_impl(ctx, prec, n, ld, state_in, cov_in, charge_in, fwd_status, nullptr, hit_offsets, hit_layer,
-                       hit_valid, n_hits, hit_pos, hit_cov, geom, cov_scale, max_len, state_out, cov_out, charge_out,
-                       chi2, ndf, trk_status, nullptr, nullptr, "kf_final_fit", stream, true, chi2_cut, outlier);
 }
 
 int kf_remove_duplicates(kf_ctx* ctx, int64_t n, const int32_t* track_hits, int64_t hit_stride, int32_t n_layers,
@@ -1032,6 +1022,206 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
 
 namespace {
 
+// Sub-buffers of the final fit's workspace, 256-byte aligned.
+struct FinalWork {
+  void *f_state, *f_cov, *f_chi2, *b_state, *b_cov, *b_chi2, *ckpt, *sm_state, *sm_cov, *seed_state, *chi2_work;
+  int32_t *f_ndf, *b_ndf;
+  uint32_t *f_status, *b_status;
+  int8_t *f_charge, *b_charge, *seed_charge;
+  uint8_t *used, *open;
+};
+
+size_t final_layout(int64_t n, int64_t n_hits, int32_t max_len, size_t esz, unsigned char* base, FinalWork* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  };
+  const size_t N = size_t(n), nseg = size_t(max_len > 1 ? max_len - 1 : 1);
+  FinalWork x;
+  x.f_state = take(6 * N * esz);
+  x.f_cov = take(21 * N * esz);
+  x.f_chi2 = take(N * esz);
+  x.b_state = take(6 * N * esz);
+  x.b_cov = take(21 * N * esz);
+  x.b_chi2 = take(N * esz);
+  x.ckpt = take(28 * N * nseg * esz);
+  x.sm_state = take(6 * N * size_t(max_len) * esz);
+  x.sm_cov = take(21 * N * size_t(max_len) * esz);
+  x.seed_state = take(6 * N * esz);
+  x.chi2_work = take(size_t(n_hits) * esz);
+  x.f_ndf = (int32_t*)take(N * 4);
+  x.b_ndf = (int32_t*)take(N * 4);
+  x.f_status = (uint32_t*)take(N * 4);
+  x.b_status = (uint32_t*)take(N * 4);
+  x.f_charge = (int8_t*)take(N);
+  x.b_charge = (int8_t*)take(N);
+  x.seed_charge = (int8_t*)take(N);
+  x.used = (uint8_t*)take(size_t(n_hits));
+  x.open = (uint8_t*)take(N);
+  if (w) *w = x;
+  return off;
+}
+
+// The rounds of kf_final_fit in type T: set-up, then per round the fused
+// seeding and forward fit over the used hits (with its seeds and its filtered
+// state after every entry), the backward fit storing its prediction at every
+// entry, the unbiased chi2 of every used hit (entry-parallel) and the
+// round's decisions.
+// The rounds are enqueued without waiting for the device: a round finds
+// nothing to do for closed tracks (their used flags are cleared, so the fit
+// sees no valid hit and the backward pass does not refit them).
+template <typename T>
+hipError_t final_rounds(kf_ctx* ctx, int pi, int64_t n, int64_t ld, int32_t seed_mode, const int32_t* hit_offsets,
+                        const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
+                        const void* hit_cov, const kf::GeomArgs& g, double cov_scale, double chi2_cut,
+                        int32_t max_reject, int32_t min_keep, int32_t max_len, void* state_out, void* cov_out,
+                        int8_t* charge_out, void* chi2, int32_t* ndf, uint32_t* trk_status, uint8_t* outlier,
+                        void* hit_chi2, const FinalWork& w, hipStream_t s) {
+  kf::FinalRoundArgs<T> r;
+  std::memset(&r, 0, sizeof(r));
+  r.n = n;
+  r.ld = ld;
+  r.hit_offsets = hit_offsets;
+  r.hit_layer = hit_layer;
+  r.hit_valid = hit_valid;
+  r.hit_pos = (const T*)hit_pos;
+  r.hit_cov = (const T*)hit_cov;
+  r.n_hits = n_hits;
+  r.max_len = max_len;
+  r.max_reject = max_reject;
+  r.min_keep = min_keep;
+  r.chi2_cut = chi2_cut;
+  r.used = w.used;
+  r.open = w.open;
+  r.outlier = outlier;
+  r.hit_chi2 = (T*)hit_chi2;
+  r.chi2_work = (T*)w.chi2_work;
+  r.seed_state = (const T*)w.seed_state;
+  r.seed_charge = w.seed_charge;
+  r.ckpt = (const T*)w.ckpt;
+  r.pred_state = (const T*)w.sm_state;
+  r.pred_cov = (const T*)w.sm_cov;
+  r.b_state = (const T*)w.b_state;
+  r.b_cov = (const T*)w.b_cov;
+  r.b_charge = w.b_charge;
+  r.b_chi2 = (const T*)w.b_chi2;
+  r.b_ndf = w.b_ndf;
+  r.b_status = w.b_status;
+  r.state_out = (T*)state_out;
+  r.cov_out = (T*)cov_out;
+  r.charge_out = charge_out;
+  r.chi2_out = (T*)chi2;
+  r.ndf_out = ndf;
+  r.status_out = trk_status;
+  hipError_t e = kf::launch_final_init(r, s);
+  const kf::FitLaunch l = ctx->fit[pi];
+  const bool room = ctx->work.cap > 0 && n <= ctx->work.max_tracks && max_len <= ctx->work.max_len;
+  const int layout = room || l.layout == 3 ? l.layout : (l.layout == 4 ? 3 : 0);
+  const int32_t n_seg = max_len > 1 ? max_len - 1 : 1;
+  for (int32_t round = 0; round <= max_reject && e == hipSuccess; ++round) {
+    auto f = make_fit_args<T>(n, n, nullptr, nullptr, nullptr, hit_offsets, hit_layer, w.used, n_hits, hit_pos,
+                              hit_cov, nullptr, w.f_state, w.f_cov, w.f_charge, w.f_chi2, w.f_ndf, w.ckpt, 1, n_seg,
+                              w.f_status, ctx->d_counter);
+    f.max_len = max_len;
+    f.make_seeds = seed_mode + 1;
+    f.seed_state_out = (T*)w.seed_state;
+    f.seed_charge_out = w.seed_charge;
+    e = run_fit(ctx, f, g, l, layout, s, false);
+    if (e != hipSuccess) break;
+    kf::BwdArgs<T> b;
+    b.f = make_fit_args<T>(n, n, w.f_state, w.f_cov, w.f_charge, hit_offsets, hit_layer, w.used, n_hits, hit_pos,
+                           hit_cov, nullptr, w.b_state, w.b_cov, w.b_charge, w.b_chi2, w.b_ndf, nullptr, 1, 0,
+                           w.b_status, ctx->d_counter);
+    b.f.max_len = max_len;
+    b.fwd_status = w.f_status;
+    b.cov_scale = T(cov_scale);
+    b.fwd_ckpt = (const T*)w.ckpt;
+    b.n_seg_f = n_seg;
+    b.smooth_state = (T*)w.sm_state;
+    b.smooth_cov = (T*)w.sm_cov;
+    e = kf::launch_backward_predictions(b, g, s);
+    if (e != hipSuccess) break;
+    r.round = round;
+    e = kf::launch_final_chi2(r, g, s);
+    if (e != hipSuccess) break;
+    e = kf::launch_final_round(r, s);
+  }
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_final_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, int32_t seed_mode, const int32_t* hit_offsets,
+                 const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
+                 const void* hit_cov, const kf_geometry* geom, double cov_scale, double chi2_cut, int32_t max_reject,
+                 int32_t min_keep, int32_t max_len, void* state_out, void* cov_out, int8_t* charge_out, void* chi2,
+                 int32_t* ndf, uint32_t* trk_status, uint8_t* outlier, void* hit_chi2, void* stream) {
+  KF_TRY(check_prec(prec));
+  KF_TRY(check_sizes(n, ld));
+  kf::GeomArgs g;
+  KF_TRY(check_geometry(geom, &g));
+  if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
+  if (seed_mode != 0 && seed_mode != 1) return fail(KF_ERR_ARG, "seed mode %d unknown (0 first three, 1 spaced)", seed_mode);
+  if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);
+  if (!std::isfinite(cov_scale) || !(cov_scale >= 1.0)) return fail(KF_ERR_ARG, "cov_scale must be finite and >= 1");
+  if (!(chi2_cut > 0.0)) return fail(KF_ERR_ARG, "chi2_cut must be > 0");
+  if (max_reject < 0 || max_reject > kf::kMaxLen) return fail(KF_ERR_ARG, "max_reject = %d outside [0, %d]", max_reject, kf::kMaxLen);
+  if (min_keep < 3 || min_keep > kf::kMaxLen) return fail(KF_ERR_ARG, "min_keep = %d outside [3, %d]", min_keep, kf::kMaxLen);
+  if (n == 0) return ok();
+  KF_REQUIRE(ctx);
+  KF_REQUIRE(hit_offsets);
+  KF_REQUIRE(hit_layer);
+  KF_REQUIRE(hit_valid);
+  KF_REQUIRE(hit_pos);
+  KF_REQUIRE(hit_cov);
+  KF_REQUIRE(state_out);
+  KF_REQUIRE(cov_out);
+  KF_REQUIRE(charge_out);
+  KF_REQUIRE(chi2);
+  KF_REQUIRE(ndf);
+  KF_REQUIRE(trk_status);
+  KF_REQUIRE(outlier);
+  const size_t esz = prec == KF_F32 ? 4 : 8;
+  const size_t need = final_layout(n, n_hits, max_len, esz, nullptr, nullptr);
+  if (need > ctx->final_bytes) {
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    if (ctx->final_mem) hipFree(ctx->final_mem);
+    ctx->final_mem = nullptr;
+    ctx->final_bytes = 0;
+    hipError_t e = hipMalloc(&ctx->final_mem, need);
+    hipSetDevice(prev);
+    if (e != hipSuccess) {
+      ctx->final_mem = nullptr;
+      return fail(KF_ERR_NOMEM, "kf_final_fit: %zu bytes: %s", need, hipGetErrorString(e));
+    }
+    ctx->final_bytes = need;
+  }
+  FinalWork w;
+  final_layout(n, n_hits, max_len, esz, (unsigned char*)ctx->final_mem, &w);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = prec == KF_F32
+                     ? final_rounds<float>(ctx, 0, n, ld, seed_mode, hit_offsets, hit_layer, hit_valid, n_hits,
+                                           hit_pos, hit_cov, g, cov_scale, chi2_cut, max_reject, min_keep, max_len,
+                                           state_out, cov_out, charge_out, chi2, ndf, trk_status, outlier, hit_chi2,
+                                           w, s)
+                     : final_rounds<double>(ctx, 1, n, ld, seed_mode, hit_offsets, hit_layer, hit_valid, n_hits,
+                                            hit_pos, hit_cov, g, cov_scale, chi2_cut, max_reject, min_keep, max_len,
+                                            state_out, cov_out, charge_out, chi2, ndf, trk_status, outlier, hit_chi2,
+                                            w, s);
+  if (e != hipSuccess) return hip_fail(e, "kf_final_fit");
+  return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
 // kf_fit_adjoint and kf_fit_adjoint_noalloc: the block partials of the
 // alignment reduction go to the context-owned buffer (grown on demand) or to
 // the fixed scratch array (no allocation, bounded size).
@@ -1162,6 +1352,185 @@ int kf_fit_adjoint_noalloc(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld
   return fit_adjoint_impl(ctx, prec, n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
                           n_hits, hit_pos, hit_cov, geom, align, checkpoints, seg, max_len, dL_dchi2, grad_seed,
                           grad_hit_pos, grad_align, trk_status, stream, true);
+}
+
+}  // extern "C"
+
+// ---- tilted planar modules ---------------------------------------------------
+
+namespace {
+
+template <typename T>
+int check_plane_geometry(const kf_plane_geometry* g, kf::PlaneGeomArgs<T>* out) {
+  if (!g) return fail(KF_ERR_ARG, "plane geometry is NULL");
+  if (g->n_modules < 1 || g->n_modules >= (int64_t(1) << 31))
+    return fail(KF_ERR_ARG, "plane geometry.n_modules = %lld outside [1, 2^31)", (long long)g->n_modules);
+  if (!g->modules) return fail(KF_ERR_ARG, "plane geometry.modules is NULL");
+  if (!std::isfinite(g->bz_tesla) || g->bz_tesla == 0.0)
+    return fail(KF_ERR_ARG, "plane geometry.bz_tesla must be finite and != 0");
+  if (!std::isfinite(g->particle_mass_gev) || !(g->particle_mass_gev > 0.0))
+    return fail(KF_ERR_ARG, "plane geometry.particle_mass_gev must be > 0");
+  *out = kf::PlaneGeomArgs<T>{(const T*)g->modules, g->n_modules, g->bz_tesla, g->particle_mass_gev};
+  return KF_OK;
+}
+
+// one launch covers at most 2^31 lanes (the grid's x dimension)
+int check_lanes(int64_t n, const char* what) {
+  if (n >= (int64_t(1) << 31)) return fail(KF_ERR_ARG, "%s = %lld must be < 2^31", what, (long long)n);
+  return KF_OK;
+}
+
+template <typename T>
+int propagate_plane_impl(int64_t n, int64_t ld, const void* state_in, const void* cov_in, const int8_t* charge,
+                         const int32_t* target_module, const kf_plane_geometry* geom, int32_t apply_material,
+                         void* state_out, void* cov_out, void* path_len, uint32_t* trk_status, hipStream_t s) {
+  kf::PlaneGeomArgs<T> g;
+  KF_TRY(check_plane_geometry(geom, &g));
+  kf::PlanePropArgs<T> a{n, ld, (const T*)state_in, (const T*)cov_in, charge, target_module, apply_material,
+                         (T*)state_out, (T*)cov_out, (T*)path_len, trk_status};
+  const hipError_t e = kf::launch_propagate_plane(a, g, s);
+  if (e != hipSuccess) return hip_fail(e, "kf_propagate_plane");
+  return ok();
+}
+
+template <typename T>
+int update_plane_impl(int64_t n, int64_t ld, void* state, void* cov, int8_t* charge, const int32_t* module,
+                      const void* hit_uv, const void* hit_cov_uv, const kf_plane_geometry* geom, void* chi2,
+                      uint32_t* trk_status, hipStream_t s) {
+  kf::PlaneGeomArgs<T> g;
+  KF_TRY(check_plane_geometry(geom, &g));
+  kf::PlaneUpdArgs<T> a{n, ld, (T*)state, (T*)cov, charge, module, (const T*)hit_uv, (const T*)hit_cov_uv,
+                        (T*)chi2, trk_status};
+  const hipError_t e = kf::launch_update_plane(a, g, s);
+  if (e != hipSuccess) return hip_fail(e, "kf_update_plane");
+  return ok();
+}
+
+template <typename T>
+int fit_plane_impl(int64_t n, int64_t ld, const void* seed_state, const void* seed_cov, const int8_t* seed_charge,
+                   const int32_t* hit_offsets, const int32_t* hit_module, const uint8_t* hit_valid, int64_t n_hits,
+                   const void* hit_uv, const void* hit_cov_uv, const kf_plane_geometry* geom, void* state_out,
+                   void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf, uint32_t* trk_status,
+                   hipStream_t s) {
+  kf::PlaneGeomArgs<T> g;
+  KF_TRY(check_plane_geometry(geom, &g));
+  kf::PlaneFitArgs<T> a{n, ld, n_hits, (const T*)seed_state, (const T*)seed_cov, seed_charge, hit_offsets,
+                        hit_module, hit_valid, (const T*)hit_uv, (const T*)hit_cov_uv, (T*)state_out, (T*)cov_out,
+                        charge_out, (T*)chi2, ndf, trk_status};
+  const hipError_t e = kf::launch_fit_plane(a, g, s);
+  if (e != hipSuccess) return hip_fail(e, "kf_fit_plane_tracks");
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int kf_propagate_plane(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* state_in,
+                       const void* cov_in, const int8_t* charge, const int32_t* target_module,
+                       const kf_plane_geometry* geom, int32_t apply_material, void* state_out, void* cov_out,
+                       void* path_len, uint32_t* trk_status, void* stream) {
+  KF_TRY(check_prec(prec));
+  KF_TRY(check_sizes(n, ld));
+  KF_TRY(check_lanes(n, "n"));
+  if (n == 0) return ok();
+  KF_REQUIRE(state_in);
+  KF_REQUIRE(cov_in);
+  KF_REQUIRE(charge);
+  KF_REQUIRE(target_module);
+  KF_REQUIRE(state_out);
+  KF_REQUIRE(cov_out);
+  KF_REQUIRE(trk_status);
+  KF_REQUIRE(ctx);
+  hipStream_t s = (hipStream_t)stream;
+  return prec == KF_F32 ? propagate_plane_impl<float>(n, ld, state_in, cov_in, charge, target_module, geom,
+                                                      apply_material, state_out, cov_out, path_len, trk_status, s)
+                        : propagate_plane_impl<double>(n, ld, state_in, cov_in, charge, target_module, geom,
+                                                       apply_material, state_out, cov_out, path_len, trk_status, s);
+}
+
+int kf_update_plane(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, void* state, void* cov, int8_t* charge,
+                    const int32_t* module, const void* hit_uv, const void* hit_cov_uv, const kf_plane_geometry* geom,
+                    void* chi2, uint32_t* trk_status, void* stream) {
+  KF_TRY(check_prec(prec));
+  KF_TRY(check_sizes(n, ld));
+  KF_TRY(check_lanes(n, "n"));
+  if (n == 0) return ok();
+  KF_REQUIRE(state);
+  KF_REQUIRE(cov);
+  KF_REQUIRE(charge);
+  KF_REQUIRE(module);
+  KF_REQUIRE(hit_uv);
+  KF_REQUIRE(hit_cov_uv);
+  KF_REQUIRE(chi2);
+  KF_REQUIRE(trk_status);
+  KF_REQUIRE(ctx);
+  hipStream_t s = (hipStream_t)stream;
+  return prec == KF_F32 ? update_plane_impl<float>(n, ld, state, cov, charge, module, hit_uv, hit_cov_uv, geom, chi2,
+                                                   trk_status, s)
+                        : update_plane_impl<double>(n, ld, state, cov, charge, module, hit_uv, hit_cov_uv, geom,
+                                                    chi2, trk_status, s);
+}
+
+int kf_fit_plane_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const void* seed_state,
+                        const void* seed_cov, const int8_t* seed_charge, const int32_t* hit_offsets,
+                        const int32_t* hit_module, const uint8_t* hit_valid, int64_t n_hits, const void* hit_uv,
+                        const void* hit_cov_uv, const kf_plane_geometry* geom, void* state_out, void* cov_out,
+                        int8_t* charge_out, void* chi2, int32_t* ndf, uint32_t* trk_status, void* stream) {
+  KF_TRY(check_prec(prec));
+  KF_TRY(check_sizes(n, ld));
+  KF_TRY(check_lanes(n, "n"));
+  if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
+  KF_TRY(check_lanes(n_hits, "n_hits"));
+  if (n == 0) return ok();
+  KF_REQUIRE(seed_state);
+  KF_REQUIRE(seed_cov);
+  KF_REQUIRE(seed_charge);
+  KF_REQUIRE(hit_offsets);
+  KF_REQUIRE(hit_module);
+  KF_REQUIRE(hit_valid);
+  KF_REQUIRE(hit_uv);
+  KF_REQUIRE(hit_cov_uv);
+  KF_REQUIRE(state_out);
+  KF_REQUIRE(cov_out);
+  KF_REQUIRE(charge_out);
+  KF_REQUIRE(chi2);
+  KF_REQUIRE(ndf);
+  KF_REQUIRE(trk_status);
+  KF_REQUIRE(ctx);
+  hipStream_t s = (hipStream_t)stream;
+  return prec == KF_F32
+             ? fit_plane_impl<float>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_module, hit_valid,
+                                     n_hits, hit_uv, hit_cov_uv, geom, state_out, cov_out, charge_out, chi2, ndf,
+                                     trk_status, s)
+             : fit_plane_impl<double>(n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_module, hit_valid,
+                                      n_hits, hit_uv, hit_cov_uv, geom, state_out, cov_out, charge_out, chi2, ndf,
+                                      trk_status, s);
+}
+
+int kf_plane_to_global(kf_ctx* ctx, kf_precision prec, int64_t n_hits, const int32_t* module, const void* hit_uv,
+                       const kf_plane_geometry* geom, void* hit_pos, void* stream) {
+  KF_TRY(check_prec(prec));
+  if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
+  KF_TRY(check_lanes(n_hits, "n_hits"));
+  if (n_hits == 0) return ok();
+  KF_REQUIRE(module);
+  KF_REQUIRE(hit_uv);
+  KF_REQUIRE(hit_pos);
+  KF_REQUIRE(ctx);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (prec == KF_F32) {
+    kf::PlaneGeomArgs<float> g;
+    KF_TRY(check_plane_geometry(geom, &g));
+    e = kf::launch_plane_to_global(n_hits, module, (const float*)hit_uv, g, (float*)hit_pos, s);
+  } else {
+    kf::PlaneGeomArgs<double> g;
+    KF_TRY(check_plane_geometry(geom, &g));
+    e = kf::launch_plane_to_global(n_hits, module, (const double*)hit_uv, g, (double*)hit_pos, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "kf_plane_to_global");
+  return ok();
 }
 
 }  // extern "C"

@@ -233,79 +233,6 @@ __device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, i
   return true;
 }
 
-// One entry of the final fit: the backward fit's step (propagation or, on the
-// first entry, the layer's material at the current state), whose update is
-// kept only if the hit's chi2 (the increment the update adds) is at most the
-// cut; a rejected hit leaves the entry a hole (the layer's material only), is
-// marked in the outlier mask and flags the track.  A NaN chi2 is not above
-// the cut.  Layer check, backup and roll-back as in fit_entry.
-template <typename T>
-__device__ inline bool reject_step(const FinalArgs<T>& fa, const TrackGeom<T>& g, int64_t e, int k, int lay,
-                                   int& prev, bool valid, const T m[3], const T V[6], T p[6], T c[21], int& q,
-                                   uint32_t& st, T& chi2, int& nval, T* bk, int bk_stride) {
-  if (lay < 0 || lay >= g.n_layers) {
-    st |= TRK_BAD_INPUT;
-    return false;
-  }
-#pragma unroll
-  for (int i = 0; i < 6; ++i) bk[i * bk_stride] = p[i];
-#pragma unroll
-  for (int i = 0; i < 21; ++i) bk[(6 + i) * bk_stride] = c[i];
-  const int qq = q;
-  uint32_t sst = 0;
-  const int kind = g.kind[lay];
-  if (k > 0) {
-    if (!propagate(p, c, q, kind, g.pos[lay], g.x0[lay], lay == prev, true, g.bz, g.mass, sst)) {
-      st |= sst;
-      return false;
-    }
-  } else {
-    add_material_here(p, c, kind, g.x0[lay], g.mass, sst);
-  }
-  T c2 = T(0);
-  bool used = false, rejected = false;
-  if (valid) {
-    T pu[6], cu[21], mm[3];
-    int qu = q;
-    uint32_t ust = 0;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) pu[i] = p[i];
-#pragma unroll
-    for (int i = 0; i < 21; ++i) cu[i] = c[i];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) mm[i] = m[i];
-    update(pu, cu, qu, mm, V, c2, ust);
-    if (c2 > fa.chi2_cut) {
-      c2 = T(0);
-      sst |= TRK_OUTLIER;
-      rejected = true;
-    } else {
-#pragma unroll
-      for (int i = 0; i < 6; ++i) p[i] = pu[i];
-#pragma unroll
-      for (int i = 0; i < 21; ++i) c[i] = cu[i];
-      q = qu;
-      sst |= ust;
-      used = true;
-    }
-  }
-  if (!all_finite(p, c, c2)) {
-    st |= sst | TRK_NONFINITE;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) p[i] = bk[i * bk_stride];
-#pragma unroll
-    for (int i = 0; i < 21; ++i) c[i] = bk[(6 + i) * bk_stride];
-    q = qq;
-    return false;
-  }
-  st |= sst;
-  chi2 += c2;
-  nval += used ? 1 : 0;
-  prev = lay;
-  if (rejected && fa.outlier) fa.outlier[e] = 1;
-  return true;
-}
-
 // Smoothing, entry-parallel: thread (r, t) combines the backward prediction
 // stored at entry r of track t with the forward filtered state of that entry
 // (forward checkpoint slot r - k0) and overwrites it with the smoothed state.
@@ -359,14 +286,13 @@ __global__ void __launch_bounds__(256, 2) smooth_combine_kernel(BwdArgs<T> b, Ge
 // Entry k of a track's backward pass is CSR entry last - k; the pass has
 // n_entries - k0 entries (k0: the first valid entry in crossing order).
 // MODE: kPlain (the backward fit), kSmooth (the backward pass of the
-// smoother), kReject (the final fit with outlier rejection).
-constexpr int kPlain = 0, kSmooth = 1, kReject = 2;
+// smoother).
+constexpr int kPlain = 0, kSmooth = 1;
 
 template <typename T, int J, int MODE>
-__device__ void backward_wave_staged(const FinalArgs<T>& fa, const TrackGeom<T>& g, int64_t w0, StageBuf<T, J>& sb,
+__device__ void backward_wave_staged(const BwdArgs<T>& b, const TrackGeom<T>& g, int64_t w0, StageBuf<T, J>& sb,
                                      T* bk, int bk_stride) {
   constexpr bool SMOOTH = MODE == kSmooth;
-  const BwdArgs<T>& b = fa.b;
   const FitArgs<T>& a = b.f;
   const int lane = int(threadIdx.x) & 63;
   const int64_t t = w0 + lane;
@@ -386,10 +312,6 @@ __device__ void backward_wave_staged(const FinalArgs<T>& fa, const TrackGeom<T>&
 #pragma unroll
     for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * a.ld + t];
     q = a.seed_charge[t];
-    if (MODE == kReject && fa.outlier) {
-      const int64_t e1 = a.hit_offsets[t + 1];
-      for (int64_t e = e0; e < e1; ++e) fa.outlier[e] = 0;
-    }
     while (k0 < n_e && a.hit_valid[e0 + k0] == 0) ++k0;
     const uint32_t stop = TRK_NO_CROSSING | TRK_NONFINITE | TRK_BAD_INPUT;
     run = k0 < n_e && !(b.fwd_status && (b.fwd_status[t] & stop));
@@ -468,8 +390,6 @@ __device__ void backward_wave_staged(const FinalArgs<T>& fa, const TrackGeom<T>&
       const int r = n_e - 1 - k;   // entry index within the track
       if (SMOOTH)
         live = smooth_step(b, g, t, k, r, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
-      else if (MODE == kReject)
-        live = reject_step(fa, g, last - k, k, lay, prev, valid, m, V, p, c, q, st, chi2, nval, bk, bk_stride);
       else
         live = fit_entry(a, g, static_cast<const T*>(nullptr), t, k, lay, prev, valid, m, V, p, c, q, st, chi2,
                          nval, bk, bk_stride);
@@ -493,15 +413,113 @@ __device__ void backward_wave_staged(const FinalArgs<T>& fa, const TrackGeom<T>&
 // WAVES: waves per SIMD the register allocation must allow (2 in FP32, 1 in
 // FP64, the forward fit's tuned choices).
 template <typename T, int WAVES, int MODE>
-__global__ void __launch_bounds__(kBwdBlock, WAVES) backward_kernel(FinalArgs<T> fa, GeomArgs g) {
+__global__ void __launch_bounds__(kBwdBlock, WAVES) backward_kernel(BwdArgs<T> b, GeomArgs g) {
   constexpr int J = stage_entries<T, WAVES>();
   __shared__ GeomLds<T> sg;
   __shared__ T bk[28 * kBwdBlock];
   __shared__ StageBuf<T, J> sb[kBwdBlock / 64];
   stage_geometry(sg, g);
   const int64_t w0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
-  backward_wave_staged<T, J, MODE>(fa, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, w0,
+  backward_wave_staged<T, J, MODE>(b, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, w0,
                              sb[threadIdx.x >> 6], bk + threadIdx.x, int(blockDim.x));
+}
+
+// The final fit's unbiased chi2, entry-parallel: thread (r, t) judges hit r
+// of open track t (a used hit) against the estimate from the track's other
+// hits: the forward prediction at r (the filtered state after entry r - 1,
+// from the checkpoints, propagated to r's layer with its material; on the
+// first used entry the seed with that layer's material) combined with the
+// backward pass's prediction there (combine_on_surface), or the forward
+// prediction alone on the last entry and where the backward pass did not
+// reach.  With x, C that estimate, chi2 = r^T (V + H C H^T)^-1 r with
+// r = m - H x (FP64 from here on; NaN when the forward prediction fails or
+// the combination is not positive definite).
+template <typename T>
+__global__ void __launch_bounds__(256) final_chi2_kernel(FinalRoundArgs<T> a, GeomArgs g) {
+  __shared__ GeomLds<T> sg;
+  stage_geometry(sg, g);
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int r = int(blockIdx.y);
+  if (t >= a.n) return;
+  if (!(a.open[t] & kFinalOpen)) return;
+  const int64_t e0 = a.hit_offsets[t];
+  int n_e = int(a.hit_offsets[t + 1] - e0);
+  if (n_e > a.max_len) n_e = a.max_len;
+  if (r >= n_e) return;
+  const int64_t e = e0 + r;
+  if (!a.used[e]) return;
+  T res = k_nan<T>();
+  if (!(a.b_status[t] & TRK_BAD_INPUT)) {
+    int k0 = 0;
+    while (k0 < r && !a.used[e0 + k0]) ++k0;
+    const int lay = a.hit_layer[e];
+    if (lay >= 0 && lay < g.n_layers) {
+      const int kind = sg.kind[lay];
+      const T pos = sg.pos[lay], x0 = sg.x0[lay];
+      T p[6], c[21];
+      int q;
+      uint32_t st = 0;
+      bool ok = true;
+      if (r == k0) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * a.n + t];
+        q = a.seed_charge[t];
+        seed_covariance(c);
+        add_material_here(p, c, kind, x0, T(g.mass), st);
+      } else {
+        const int64_t cs = a.n * int64_t(a.max_len > 1 ? a.max_len - 1 : 1);
+        const T* f = a.ckpt + int64_t(r - 1 - k0) * a.n + t;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) p[i] = f[i * cs];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) c[i] = f[(6 + i) * cs];
+        q = int(f[27 * cs]);
+        const int prev = a.hit_layer[e - 1];
+        ok = propagate(p, c, q, kind, pos, x0, lay == prev, true, T(g.bz), T(g.mass), st);
+      }
+      if (ok) {
+        const int64_t os = a.n * int64_t(a.max_len), at = int64_t(r) * a.n + t;
+        T px[6], cx[21];
+        bool have = false;
+        if (r < n_e - 1) {
+          T pb[6], cb[21];
+#pragma unroll
+          for (int i = 0; i < 6; ++i) pb[i] = a.pred_state[i * os + at];
+          if (pb[0] == pb[0]) {
+#pragma unroll
+            for (int i = 0; i < 21; ++i) cb[i] = a.pred_cov[i * os + at];
+            ok = combine_on_surface(p, c, pb, cb, kind, pos, px, cx);
+            have = true;
+          }
+        }
+        if (!have) {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) px[i] = p[i];
+#pragma unroll
+          for (int i = 0; i < 21; ++i) cx[i] = c[i];
+        }
+        if (ok) {
+          const int64_t nh = a.n_hits;
+          const double r0 = double(a.hit_pos[e]) - double(px[0]);
+          const double r1 = double(a.hit_pos[nh + e]) - double(px[1]);
+          const double r2 = double(a.hit_pos[2 * nh + e]) - double(px[2]);
+          const double sa = double(a.hit_cov[e]) + double(cx[0]);
+          const double sb = double(a.hit_cov[nh + e]) + double(cx[1]);
+          const double sc = double(a.hit_cov[2 * nh + e]) + double(cx[2]);
+          const double sd = double(a.hit_cov[3 * nh + e]) + double(cx[3]);
+          const double se = double(a.hit_cov[4 * nh + e]) + double(cx[4]);
+          const double sf = double(a.hit_cov[5 * nh + e]) + double(cx[5]);
+          const double i00 = sc * sf - se * se, i10 = sd * se - sb * sf, i20 = sb * se - sc * sd;
+          const double i11 = sa * sf - sd * sd, i21 = sb * sd - sa * se, i22 = sa * sc - sb * sb;
+          const double det = sa * i00 + sb * i10 + sd * i20;
+          const double qf = r0 * (i00 * r0 + i10 * r1 + i20 * r2) + r1 * (i10 * r0 + i11 * r1 + i21 * r2) +
+                            r2 * (i20 * r0 + i21 * r1 + i22 * r2);
+          res = T(qf / det);
+        }
+      }
+    }
+  }
+  a.chi2_work[e] = res;
 }
 
 }  // namespace
@@ -510,32 +528,41 @@ template <typename T>
 hipError_t launch_backward(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s) {
   if (a.f.n == 0) return hipSuccess;
   const int64_t grid = (a.f.n + kBwdBlock - 1) / kBwdBlock;
-  const FinalArgs<T> fa{a, k_inf<T>(), nullptr};
   if (a.smooth_state) {
     hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, kSmooth>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
-                       s, fa, g);
+                       s, a, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(smooth_combine_kernel<T>, dim3(unsigned((a.f.n + 255) / 256), unsigned(a.f.max_len)), dim3(256),
                        0, s, a, g);
   } else
     hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, kPlain>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
-                       s, fa, g);
+                       s, a, g);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_final_fit(const FinalArgs<T>& a, const GeomArgs& g, hipStream_t s) {
-  if (a.b.f.n == 0) return hipSuccess;
-  const int64_t grid = (a.b.f.n + kBwdBlock - 1) / kBwdBlock;
-  hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, kReject>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
+hipError_t launch_backward_predictions(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s) {
+  if (a.f.n == 0) return hipSuccess;
+  const int64_t grid = (a.f.n + kBwdBlock - 1) / kBwdBlock;
+  hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, kSmooth>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
                      s, a, g);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_final_chi2(const FinalRoundArgs<T>& a, const GeomArgs& g, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(final_chi2_kernel<T>, dim3(unsigned((a.n + 255) / 256), unsigned(a.max_len)), dim3(256), 0, s,
+                     a, g);
   return hipGetLastError();
 }
 
 template hipError_t launch_backward<float>(const BwdArgs<float>&, const GeomArgs&, hipStream_t);
 template hipError_t launch_backward<double>(const BwdArgs<double>&, const GeomArgs&, hipStream_t);
-template hipError_t launch_final_fit<float>(const FinalArgs<float>&, const GeomArgs&, hipStream_t);
-template hipError_t launch_final_fit<double>(const FinalArgs<double>&, const GeomArgs&, hipStream_t);
+template hipError_t launch_backward_predictions<float>(const BwdArgs<float>&, const GeomArgs&, hipStream_t);
+template hipError_t launch_backward_predictions<double>(const BwdArgs<double>&, const GeomArgs&, hipStream_t);
+template hipError_t launch_final_chi2<float>(const FinalRoundArgs<float>&, const GeomArgs&, hipStream_t);
+template hipError_t launch_final_chi2<double>(const FinalRoundArgs<double>&, const GeomArgs&, hipStream_t);
 
 }  // namespace kf

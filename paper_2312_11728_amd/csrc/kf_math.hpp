@@ -74,8 +74,11 @@ KF_HD inline float k_floor(float x) { return floorf(x); }
 KF_HD inline double k_floor(double x) { return floor(x); }
 KF_HD inline float k_ceil(float x) { return ceilf(x); }
 KF_HD inline double k_ceil(double x) { return ceil(x); }
-KF_HD inline bool k_finite(float x) { return x - x == 0.0f; }
-KF_HD inline bool k_finite(double x) { return x - x == 0.0; }
+// The class test, not x - x == 0: with floating-point contraction, the
+// compiler turns x - x for a product x = a b into fma(a, b, -x), the
+// product's rounding error, which is non-zero for most finite x.
+KF_HD inline bool k_finite(float x) { return __builtin_isfinite(x); }
+KF_HD inline bool k_finite(double x) { return __builtin_isfinite(x); }
 template <typename T>
 KF_HD inline T k_inf() { return T(__builtin_huge_val()); }
 template <typename T>
@@ -393,6 +396,65 @@ KF_HD inline void add_q(T c[21], T ipt, T sth, T cot, T var) {
   c[sym(5, 5)] += var;
 }
 
+// C <- F C F^T for the surface-to-surface Jacobian F = G + g d^T: G the
+// helix partials at fixed path (identity but for G03, G04, G13, G14, G25,
+// G43), g = d(state)/ds = (g0, g1, g2, 0, g4, 0) and d = ds/dp.  Expanded as
+// G C G^T + g v^T + v g^T + a g g^T with v = G C d and a = d^T C d, which
+// uses the sparsity of G and never forms F.
+template <typename T>
+KF_HD inline void transport_cov(T c[21], const T d[6], T G03, T G04, T G13, T G14, T G25, T G43, T g0, T g1, T g2,
+                                T g4) {
+  // wv = C d, a = d^T C d, v = G wv
+  T wv[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc += c[sym(i, j)] * d[j];
+    wv[i] = acc;
+  }
+  T a = T(0);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) a += d[i] * wv[i];
+  T v[6];
+  v[0] = wv[0] + G03 * wv[3] + G04 * wv[4];
+  v[1] = wv[1] + G13 * wv[3] + G14 * wv[4];
+  v[2] = wv[2] + G25 * wv[5];
+  v[3] = wv[3];
+  v[4] = G43 * wv[3] + wv[4];
+  v[5] = wv[5];
+  // M = G C (rows), then N = M G^T (lower triangle)
+  T M[6][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    M[0][j] = c[sym(0, j)] + G03 * c[sym(3, j)] + G04 * c[sym(4, j)];
+    M[1][j] = c[sym(1, j)] + G13 * c[sym(3, j)] + G14 * c[sym(4, j)];
+    M[2][j] = c[sym(2, j)] + G25 * c[sym(5, j)];
+    M[3][j] = c[sym(3, j)];
+    M[4][j] = G43 * c[sym(3, j)] + c[sym(4, j)];
+    M[5][j] = c[sym(5, j)];
+  }
+  T N[21];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    N[sym(i, 0)] = M[i][0] + G03 * M[i][3] + G04 * M[i][4];
+    if (i >= 1) N[sym(i, 1)] = M[i][1] + G13 * M[i][3] + G14 * M[i][4];
+    if (i >= 2) N[sym(i, 2)] = M[i][2] + G25 * M[i][5];
+    if (i >= 3) N[sym(i, 3)] = M[i][3];
+    if (i >= 4) N[sym(i, 4)] = G43 * M[i][3] + M[i][4];
+    if (i >= 5) N[sym(i, 5)] = M[i][5];
+  }
+  // C' = N + g v^T + v g^T + a g g^T ; g = (g0, g1, g2, 0, g4, 0)
+  const T gg[6] = {g0, g1, g2, T(0), g4, T(0)};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      c[sym(i, j)] = N[sym(i, j)] + gg[i] * v[j] + v[i] * gg[j] + a * gg[i] * gg[j];
+    }
+  }
+}
+
 // Intermediates of one propagation, recorded for the reverse pass.
 template <typename T>
 struct PropTape {
@@ -486,57 +548,7 @@ KF_HD bool propagate(T p[6], T c[21], int q, int kind, T pos, T x_over_x0, bool 
     tape->inv = (kind == 0) ? -k_rcp(x * cphm + y * sphm) : -k_rcp(cot);
     tape->hp = hp;
   }
-  // g = d(state)/ds
-  const T g0 = cphm, g1 = sphm, g2 = cot, g4 = w;
-  // wv = C d, a = d^T C d, v = G wv
-  T wv[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    T acc = T(0);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) acc += c[sym(i, j)] * d[j];
-    wv[i] = acc;
-  }
-  T a = T(0);
-#pragma unroll
-  for (int i = 0; i < 6; ++i) a += d[i] * wv[i];
-  T v[6];
-  v[0] = wv[0] + G03 * wv[3] + G04 * wv[4];
-  v[1] = wv[1] + G13 * wv[3] + G14 * wv[4];
-  v[2] = wv[2] + G25 * wv[5];
-  v[3] = wv[3];
-  v[4] = G43 * wv[3] + wv[4];
-  v[5] = wv[5];
-  // M = G C (rows), then N = M G^T (lower triangle)
-  T M[6][6];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) {
-    M[0][j] = c[sym(0, j)] + G03 * c[sym(3, j)] + G04 * c[sym(4, j)];
-    M[1][j] = c[sym(1, j)] + G13 * c[sym(3, j)] + G14 * c[sym(4, j)];
-    M[2][j] = c[sym(2, j)] + G25 * c[sym(5, j)];
-    M[3][j] = c[sym(3, j)];
-    M[4][j] = G43 * c[sym(3, j)] + c[sym(4, j)];
-    M[5][j] = c[sym(5, j)];
-  }
-  T N[21];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    N[sym(i, 0)] = M[i][0] + G03 * M[i][3] + G04 * M[i][4];
-    if (i >= 1) N[sym(i, 1)] = M[i][1] + G13 * M[i][3] + G14 * M[i][4];
-    if (i >= 2) N[sym(i, 2)] = M[i][2] + G25 * M[i][5];
-    if (i >= 3) N[sym(i, 3)] = M[i][3];
-    if (i >= 4) N[sym(i, 4)] = G43 * M[i][3] + M[i][4];
-    if (i >= 5) N[sym(i, 5)] = M[i][5];
-  }
-  // C' = N + g v^T + v g^T + a g g^T ; g = (g0, g1, g2, 0, g4, 0)
-  const T gg[6] = {g0, g1, g2, T(0), g4, T(0)};
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      c[sym(i, j)] = N[sym(i, j)] + gg[i] * v[j] + v[i] * gg[j] + a * gg[i] * gg[j];
-    }
-  }
+  transport_cov(c, d, G03, G04, G13, G14, G25, G43, cphm, sphm, cot, w);
   // The exact C' has the surface normal n (in position) as a null vector: a
   // state confined to the surface cannot move along n.  Rounding in the
   // cancellation F = G + g d^T leaves a residue of order eps * (G C G^T) there,
@@ -813,13 +825,24 @@ KF_HD inline void update_lane_fp64(float p[6], float c[21], int& q, const float 
 }
 
 // Kalman update.  The FP32 form moves a lane to FP64 when the prior position
-// variance exceeds the hit variance by more than kRatioMax on any axis (then the
-// FP32 posterior would keep fewer than ~3 significant digits).
+// variance exceeds the hit variance by more than kRatioMax in some direction
+// (then the FP32 posterior would keep fewer than ~3 significant digits).  The
+// largest such ratio is the largest eigenvalue of V^-1 C_pos, bounded above by
+// its trace tr(V^-1 C_pos) (at most three times it), which is what is tested:
+// comparing the variances axis by axis misses a prior that is wide along the
+// hit's most precise direction when that direction is not a coordinate axis
+// (a barrel hit's r-phi direction, where V_xx and V_yy also carry the larger
+// thickness term).
 template <typename T>
 KF_HD void update(T p[6], T c[21], int& q, const T m[3], const T V[6], T& chi2, uint32_t& st) {
   if constexpr (std::is_same<T, float>::value) {
-    const float R = float(kRatioMax);
-    if (c[0] > R * V[0] || c[2] > R * V[2] || c[5] > R * V[5]) {
+    // cofactors of V (its inverse up to 1/det, det > 0 for a valid hit covariance)
+    const float a = V[0], b = V[1], cc = V[2], d = V[3], e = V[4], f = V[5];
+    const float i00 = cc * f - e * e, i10 = d * e - b * f, i11 = a * f - d * d;
+    const float i20 = b * e - cc * d, i21 = b * d - a * e, i22 = a * cc - b * b;
+    const float det = a * i00 + b * i10 + d * i20;
+    const float tr = i00 * c[0] + i11 * c[2] + i22 * c[5] + 2.f * (i10 * c[1] + i20 * c[3] + i21 * c[4]);
+    if (!(tr <= float(kRatioMax) * det)) {   // also a non-finite or degenerate V
       update_lane_fp64(p, c, q, m, V, chi2, st);
       return;
     }

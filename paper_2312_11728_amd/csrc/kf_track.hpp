@@ -7,10 +7,16 @@
 
 namespace kf {
 
+// Spacing of the hits of a spaced seed (mode 1), cm in the transverse plane:
+// wide enough to give closely spaced disk hits a usable lever arm, and below
+// the 3 cm between the two innermost barrel layers of the toy detectors, so
+// that whether a barrel hit pair qualifies is never decided by rounding.
+constexpr double kSeedSpacing = 2.5;
+
 // Seed of track t from three of its valid hits (mode 0: the first three;
-// mode 1: the first, then each next one >= 3 cm away in the transverse plane
-// from the previously chosen one), with the charge and the status
-// (KF_TRK_BAD_INPUT without three such hits; the state is then zero).
+// mode 1: the first, then each next one >= kSeedSpacing away in the
+// transverse plane from the previously chosen one), with the charge and the
+// status (KF_TRK_BAD_INPUT without three such hits; the state is then zero).
 template <typename T>
 struct SeedOut {
   T p[6];
@@ -38,7 +44,7 @@ KF_HD __attribute__((noinline)) SeedOut<T> seed_of_track(const int32_t* __restri
         take = true;
       } else {
         const T dx = hx - lx, dy = hy - ly;
-        take = k_sqrt(dx * dx + dy * dy) >= T(3.0);
+        take = k_sqrt(dx * dx + dy * dy) >= T(kSeedSpacing);
       }
     }
     if (take) {

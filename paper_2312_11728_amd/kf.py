@@ -28,10 +28,13 @@ EXPORTS = ["kf_create", "kf_destroy", "kf_last_error", "kf_make_seeds", "kf_prop
            "kf_fit_tracks", "kf_score_hits", "kf_fit_adjoint", "kf_set_fit_launch", "kf_get_fit_launch",
            "kf_device_cu_count", "kf_reserve", "kf_set_fit_graph",
            "kf_set_kernel_timing", "kf_fit_kernel_time", "kf_seed_fit_tracks", "kf_backward_fit",
-           "kf_smooth_tracks", "kf_final_fit", "kf_remove_duplicates", "kf_fit_adjoint_noalloc"]
+           "kf_smooth_tracks", "kf_final_fit", "kf_remove_duplicates", "kf_fit_adjoint_noalloc",
+           "kf_propagate_plane", "kf_update_plane", "kf_fit_plane_tracks", "kf_plane_to_global"]
 
 BACKWARD_COV_SCALE = 100.0   # forward covariance scale at the start of the backward fit
 FINAL_CHI2_CUT = 30.0        # the final fit's default chi2 cut for one hit
+FINAL_MAX_REJECT = 3         # rounds in which the final fit may reject a hit
+FINAL_MIN_KEEP = 4           # used hits a track keeps at the least in the final fit
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -42,6 +45,10 @@ _dbl = ctypes.c_double
 class KfGeometry(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_int32), ("kind", _vp), ("pos", _vp), ("lo", _vp), ("hi", _vp),
                 ("x_over_x0", _vp), ("bz_tesla", _dbl), ("particle_mass_gev", _dbl)]
+
+
+class KfPlaneGeometry(ctypes.Structure):
+    _fields_ = [("n_modules", _i64), ("modules", _vp), ("bz_tesla", _dbl), ("particle_mass_gev", _dbl)]
 
 
 class KfSearchParams(ctypes.Structure):
@@ -98,8 +105,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                        _i32, _i32, _vp, _vp]
     lib.kf_backward_fit.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                     ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
-    lib.kf_final_fit.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
-                                 ctypes.POINTER(KfGeometry), _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_final_fit.argtypes = [_vp, ctypes.c_int, _i64, _i64, _i32, _vp, _vp, _vp, _i64, _vp, _vp,
+                                 ctypes.POINTER(KfGeometry), _dbl, _dbl, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, _vp, _vp]
     lib.kf_remove_duplicates.argtypes = [_vp, _i64, _vp, _i64, _i32, _vp, _i64, ctypes.c_float, _vp, _vp, _vp]
     lib.kf_smooth_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                      _vp, ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -109,6 +117,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.kf_fit_adjoint.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                    ctypes.POINTER(KfGeometry), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_adjoint_noalloc.argtypes = lib.kf_fit_adjoint.argtypes
+    pg = ctypes.POINTER(KfPlaneGeometry)
+    lib.kf_propagate_plane.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, pg, _i32, _vp, _vp, _vp, _vp,
+                                       _vp]
+    lib.kf_update_plane.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, pg, _vp, _vp, _vp]
+    lib.kf_fit_plane_tracks.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
+                                        pg, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.kf_plane_to_global.argtypes = [_vp, ctypes.c_int, _i64, _vp, _vp, pg, _vp, _vp]
     lib.kf_set_fit_launch.argtypes = [_vp, ctypes.c_int, _i32, _i32, _i32, _i32, _i32]
     lib.kf_get_fit_launch.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                       ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
@@ -158,6 +173,41 @@ class Geometry:
     @classmethod
     def from_toy(cls, g):
         return cls(g.kind, g.pos, g.lo, g.hi, g.x_over_x0, g.bz, g.mass)
+
+
+class PlaneGeometry:
+    """Tilted-module description: the module table [10, n_modules] (rows cx cy
+    cz nx ny nz ux uy uz x_over_x0) copied to the device in one precision, and
+    the field; the C struct points at that copy."""
+
+    def __init__(self, modules, bz=3.8, mass=0.13957, dtype=torch.float32, device="cuda"):
+        m = torch.as_tensor(np.ascontiguousarray(modules, np.float64))
+        if m.dim() != 2 or m.shape[0] != 10 or m.shape[1] < 1:
+            raise ValueError(f"modules must have shape [10, M], got {tuple(m.shape)}")
+        self.table = m.to(device=device, dtype=dtype).contiguous()
+        self.bz = float(bz)
+        self.mass = float(mass)
+        self.struct = KfPlaneGeometry(self.table.shape[1], self.table.data_ptr(), self.bz, self.mass)
+
+    @property
+    def n_modules(self):
+        return int(self.table.shape[1])
+
+    @property
+    def dtype(self):
+        return self.table.dtype
+
+    @classmethod
+    def from_toy(cls, g, dtype=torch.float32, device="cuda"):
+        return cls(g.modules, g.bz, g.mass, dtype=dtype, device=device)
+
+
+def _need_plane(geom, dt, dev):
+    if not isinstance(geom, PlaneGeometry):
+        raise TypeError("geom must be a PlaneGeometry")
+    if geom.table.dtype != dt or geom.table.device != dev:
+        raise ValueError(f"the module table is {geom.table.dtype} on {geom.table.device}, expected {dt} on {dev}")
+    return geom
 
 
 def _ptr(t):
@@ -311,6 +361,90 @@ class Context:
                                _ptr(hit_pos), _ptr(hit_cov), _ptr(chi2), _ptr(status), _stream(dev)))
         return chi2, status
 
+    # ---- tilted planar modules ---------------------------------------------
+    def propagate_plane(self, state, cov, charge, target_module, geom: PlaneGeometry, apply_material=True,
+                        status=None):
+        dev = self.device
+        dt = state.dtype
+        n = state.shape[1]
+        _need(state, "state", dt, dev, rows=6)
+        _need(cov, "cov", dt, dev, rows=21)
+        _need(charge, "charge", torch.int8, dev)
+        _need(target_module, "target_module", torch.int32, dev)
+        _need_plane(geom, dt, dev)
+        so = torch.empty_like(state)
+        co = torch.empty_like(cov)
+        path = torch.empty(n, dtype=dt, device=dev)
+        if status is None:
+            status = torch.zeros(n, dtype=torch.int32, device=dev)
+        _check(lib().kf_propagate_plane(self.handle, _prec(dt), n, state.stride(0), _ptr(state), _ptr(cov),
+                                        _ptr(charge), _ptr(target_module), ctypes.byref(geom.struct),
+                                        int(bool(apply_material)), _ptr(so), _ptr(co), _ptr(path), _ptr(status),
+                                        _stream(dev)))
+        return so, co, path, status
+
+    def update_plane(self, state, cov, charge, module, hit_uv, hit_cov_uv, geom: PlaneGeometry, status=None):
+        """In-place local update of state/cov/charge; returns (chi2, status)."""
+        dev = self.device
+        dt = state.dtype
+        n = state.shape[1]
+        _need(state, "state", dt, dev, rows=6)
+        _need(cov, "cov", dt, dev, rows=21)
+        _need(charge, "charge", torch.int8, dev)
+        _need(module, "module", torch.int32, dev)
+        _need(hit_uv, "hit_uv", dt, dev, rows=2)
+        _need(hit_cov_uv, "hit_cov_uv", dt, dev, rows=3)
+        _need_plane(geom, dt, dev)
+        chi2 = torch.empty(n, dtype=dt, device=dev)
+        if status is None:
+            status = torch.zeros(n, dtype=torch.int32, device=dev)
+        _check(lib().kf_update_plane(self.handle, _prec(dt), n, state.stride(0), _ptr(state), _ptr(cov), _ptr(charge),
+                                     _ptr(module), _ptr(hit_uv), _ptr(hit_cov_uv), ctypes.byref(geom.struct),
+                                     _ptr(chi2), _ptr(status), _stream(dev)))
+        return chi2, status
+
+    def fit_plane_tracks(self, seed_state, seed_cov, seed_charge, hit_offsets, hit_module, hit_valid, hit_uv,
+                         hit_cov_uv, geom: PlaneGeometry, out=None):
+        dev = self.device
+        dt = seed_state.dtype
+        n = seed_state.shape[1]
+        _need(seed_state, "seed_state", dt, dev, rows=6)
+        _need(seed_cov, "seed_cov", dt, dev, rows=21)
+        _need(seed_charge, "seed_charge", torch.int8, dev)
+        _need_offsets(hit_offsets, n, dev)
+        _need(hit_module, "hit_module", torch.int32, dev)
+        _need(hit_valid, "hit_valid", torch.uint8, dev)
+        _need(hit_uv, "hit_uv", dt, dev, rows=2)
+        _need(hit_cov_uv, "hit_cov_uv", dt, dev, rows=3)
+        _need_plane(geom, dt, dev)
+        if out is None:
+            out = fit_outputs(n, dt, dev)
+        _need_outputs(out, n, dt, dev)
+        _check(lib().kf_fit_plane_tracks(self.handle, _prec(dt), n, seed_state.stride(0), _ptr(seed_state),
+                                         _ptr(seed_cov), _ptr(seed_charge), _ptr(hit_offsets), _ptr(hit_module),
+                                         _ptr(hit_valid), hit_uv.shape[1], _ptr(hit_uv), _ptr(hit_cov_uv),
+                                         ctypes.byref(geom.struct), _ptr(out["state"]), _ptr(out["cov"]),
+                                         _ptr(out["charge"]), _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(out["status"]),
+                                         _stream(dev)))
+        return out
+
+    def plane_to_global(self, module, hit_uv, geom: PlaneGeometry, out=None):
+        """Global positions [3, n_hits] of local hits (module, hit_uv [2, n_hits])."""
+        dev = self.device
+        dt = hit_uv.dtype
+        _need(module, "module", torch.int32, dev)
+        _need(hit_uv, "hit_uv", dt, dev, rows=2)
+        _need_plane(geom, dt, dev)
+        nh = hit_uv.shape[1]
+        if module.numel() != nh:
+            raise ValueError(f"module holds {module.numel()} entries, hit_uv {nh}")
+        if out is None:
+            out = torch.empty(3, nh, dtype=dt, device=dev)
+        _need(out, "out", dt, dev, rows=3)
+        _check(lib().kf_plane_to_global(self.handle, _prec(dt), nh, _ptr(module), _ptr(hit_uv),
+                                        ctypes.byref(geom.struct), _ptr(out), _stream(dev)))
+        return out
+
     def fit_tracks(self, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov,
                    geom: Geometry, align=None, checkpoints=None, seg=1, max_len=26, out=None):
         dev = self.device
@@ -374,47 +508,49 @@ class Context:
                                      _stream(dev)))
         return out
 
-    def final_fit(self, fwd, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry,
-                  chi2_cut=FINAL_CHI2_CUT, cov_scale=BACKWARD_COV_SCALE, max_len=26, out=None, outlier=None,
-                  use_status=True):
-        """Final fit with outlier rejection (kf_final_fit): the backward fit of
-        backward_fit, in which a hit whose chi2 against the backward
-        prediction exceeds chi2_cut is not used.  Returns (out, outlier):
-        fit_tracks-form outputs and the uint8 mask [n_hits] of rejected
-        entries."""
+    def final_fit(self, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov, geom: Geometry, seed_mode=0,
+                  chi2_cut=FINAL_CHI2_CUT, max_reject=FINAL_MAX_REJECT, min_keep=FINAL_MIN_KEEP,
+                  cov_scale=BACKWARD_COV_SCALE, max_len=26, out=None, outlier=None, hit_chi2=None,
+                  want_hit_chi2=True):
+        """Final fit with outlier rejection (kf_final_fit): rounds of seeding,
+        forward fit and smoothing backward fit over each track's used hits,
+        rejecting the hit with the worst unbiased chi2 above chi2_cut.
+        Returns (out, outlier, hit_chi2): fit_tracks-form outputs (the
+        backward fit's state on each track's first used entry), the uint8
+        mask [n_hits] of rejected entries and the per-hit unbiased chi2
+        [n_hits] (None unless want_hit_chi2 or given)."""
         dev = self.device
-        st_in, cov_in, q_in = fwd["state"], fwd["cov"], fwd["charge"]
-        dt = st_in.dtype
-        n = st_in.shape[1]
-        _need(st_in, "state", dt, dev, rows=6)
-        _need(cov_in, "cov", dt, dev, rows=21)
-        _need(q_in, "charge", torch.int8, dev)
-        _need_offsets(hit_offsets, n, dev)
+        dt = hit_pos.dtype
+        _need(hit_offsets, "hit_offsets", torch.int32, dev)
+        if hit_offsets.dim() != 1 or hit_offsets.numel() < 1:
+            raise ValueError("hit_offsets must be a 1-D tensor of n + 1 entries")
+        n = hit_offsets.shape[0] - 1
         _need(hit_layer, "hit_layer", torch.int16, dev)
         _need(hit_valid, "hit_valid", torch.uint8, dev)
         _need(hit_pos, "hit_pos", dt, dev, rows=3)
         _need(hit_cov, "hit_cov", dt, dev, rows=6)
-        status = fwd["status"] if use_status else None
-        if status is not None:
-            _need(status, "status", torch.int32, dev)
-        if st_in.stride(0) != n or cov_in.stride(0) != n:
-            raise ValueError("state and cov must have leading dimension n (the outputs are [rows, n])")
+        n_hits = hit_pos.shape[1]
         if out is None:
             out = fit_outputs(n, dt, dev)
         _need_outputs(out, n, dt, dev)
-        n_hits = hit_pos.shape[1]
         if outlier is None:
             outlier = torch.empty(n_hits, dtype=torch.uint8, device=dev)
         _need(outlier, "outlier", torch.uint8, dev)
         if outlier.numel() < n_hits:
             raise ValueError(f"outlier must hold n_hits = {n_hits} entries")
-        _check(lib().kf_final_fit(self.handle, _prec(dt), n, st_in.stride(0), _ptr(st_in), _ptr(cov_in), _ptr(q_in),
-                                  _ptr(status), _ptr(hit_offsets), _ptr(hit_layer), _ptr(hit_valid), n_hits,
-                                  _ptr(hit_pos), _ptr(hit_cov), ctypes.byref(geom.struct), float(cov_scale),
-                                  float(chi2_cut), int(max_len), _ptr(out["state"]), _ptr(out["cov"]),
-                                  _ptr(out["charge"]), _ptr(out["chi2"]), _ptr(out["ndf"]), _ptr(out["status"]),
-                                  _ptr(outlier), _stream(dev)))
-        return out, outlier
+        if hit_chi2 is None and want_hit_chi2:
+            hit_chi2 = torch.full((n_hits,), float("nan"), dtype=dt, device=dev)
+        if hit_chi2 is not None:
+            _need(hit_chi2, "hit_chi2", dt, dev)
+            if hit_chi2.numel() < n_hits:
+                raise ValueError(f"hit_chi2 must hold n_hits = {n_hits} entries")
+        _check(lib().kf_final_fit(self.handle, _prec(dt), n, n, int(seed_mode), _ptr(hit_offsets), _ptr(hit_layer),
+                                  _ptr(hit_valid), n_hits, _ptr(hit_pos), _ptr(hit_cov), ctypes.byref(geom.struct),
+                                  float(cov_scale), float(chi2_cut), int(max_reject), int(min_keep), int(max_len),
+                                  _ptr(out["state"]), _ptr(out["cov"]), _ptr(out["charge"]), _ptr(out["chi2"]),
+                                  _ptr(out["ndf"]), _ptr(out["status"]), _ptr(outlier), _ptr(hit_chi2),
+                                  _stream(dev)))
+        return out, outlier, hit_chi2
 
     def remove_duplicates(self, track_hits, score, frac=0.5, keep=None, dup_of=None):
         """Duplicate removal (kf_remove_duplicates) over n tracks:
@@ -687,4 +823,17 @@ def event_tensors(ev, dtype=torch.float32, device="cuda"):
         hit_valid=torch.as_tensor(np.ascontiguousarray(ev.hit_valid, np.uint8), device=dev),
         hit_pos=torch.as_tensor(np.ascontiguousarray(ev.hit_pos), device=dev).to(dtype).contiguous(),
         hit_cov=torch.as_tensor(np.ascontiguousarray(ev.hit_cov), device=dev).to(dtype).contiguous(),
+    )
+
+
+def plane_event_tensors(ev, dtype=torch.float32, device="cuda"):
+    """Device copies of a tilted-module batch: hit_offsets [n+1], hit_module
+    [n_hits] int32, hit_valid, hit_uv [2][n_hits], hit_cov_uv [3][n_hits]."""
+    dev = torch.device(device)
+    return dict(
+        hit_offsets=torch.as_tensor(np.ascontiguousarray(ev.hit_offsets, np.int32), device=dev),
+        hit_module=torch.as_tensor(np.ascontiguousarray(ev.hit_module, np.int32), device=dev),
+        hit_valid=torch.as_tensor(np.ascontiguousarray(ev.hit_valid, np.uint8), device=dev),
+        hit_uv=torch.as_tensor(np.ascontiguousarray(ev.hit_uv), device=dev).to(dtype).contiguous(),
+        hit_cov_uv=torch.as_tensor(np.ascontiguousarray(ev.hit_cov_uv), device=dev).to(dtype).contiguous(),
     )

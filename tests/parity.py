@@ -96,15 +96,49 @@ def gpu_fit(ctx, kf, ev, dtype, seed_mode=0, align=None, checkpoints=None, seg=1
                 seed_status=sstat.cpu().numpy())
 
 
+# covariance tolerance in correlation units on the surface's five directions
+COV_TOL32 = 1e-3
+COV_TOL64 = 1e-7
+COV_TAIL32 = 0.01   # fraction of FP32 tracks allowed above COV_TOL32
+
+
+def surface_kind(p, geom):
+    """0 where the state lies on a barrel cylinder of ``geom``, 1 where it lies
+    on a disk (whichever surface is closest)."""
+    kinds = np.asarray(geom.kind)
+    pos = np.asarray(geom.pos, np.float64)
+    r = np.hypot(p[:, 0], p[:, 1])
+    db = np.where(kinds[None, :] == 0, np.abs(r[:, None] - pos[None, :]), np.inf).min(axis=1, initial=np.inf)
+    dd = np.where(kinds[None, :] == 1, np.abs(p[:, 2:3] - pos[None, :]), np.inf).min(axis=1, initial=np.inf)
+    return np.where(db <= dd, 0, 1)
+
+
+def cov_error(g, o, geom):
+    """Per-track maximum over the surface frame of |dC_ab| / sqrt(C_aa C_bb)
+    between the GPU covariance g["C"] ([n, 21] packed or [n, 6, 6]) and the
+    oracle's o["C"], in the frame of the oracle state's surface."""
+    Cg = g["C"] if g["C"].ndim == 3 else sym_unpack(g["C"])
+    kind = surface_kind(o["p"], geom)
+    rel = cov_rel_error(tangent_frame_cov(Cg, o["p"], kind), tangent_frame_cov(o["C"], o["p"], kind))
+    return rel.reshape(rel.shape[0], -1).max(axis=1) if rel.shape[0] else np.zeros(0)
+
+
 def compare_fit(g, o, tol_p, tol_c, mask=None, ignore_bits=O.FP64_FALLBACK, tail_frac=0.0, tail_factor=10.0,
-                tail_factor_chi2=20.0):
+                tail_factor_chi2=20.0, geom=None, cov_tol=None):
     """Assert parity on the tracks in ``mask`` (default all); return a summary.
     At most ``tail_frac`` of the compared tracks may exceed the tolerance, and
     those only by less than ``tail_factor`` (parameters) or
     ``tail_factor_chi2`` (chi2) times it.  The chi2 tail is set by the FP32
     resolution of absolute positions: at r ~ 100 cm one unit in the last place
     (7.6e-6 cm) is 0.25% of the r-phi resolution, so a residual of a few sigma
-    carries a relative chi2 error of that order."""
+    carries a relative chi2 error of that order.
+    With ``geom``, the output covariances are compared too, in correlation
+    units on the five directions of the output state's surface (its normal is
+    a null vector): to ``cov_tol`` (default 1e-3 when tol_p is an FP32
+    tolerance, 1e-7 for FP64).  FP64: the tail rule of the parameters (at
+    most tail_frac of the tracks above it, none above tail_factor times it).
+    FP32: at most max(COV_TAIL32, tail_frac) of the tracks above it, the
+    largest error reported."""
     n = g["chi2"].shape[0]
     m = np.ones(n, bool) if mask is None else mask
     ep = param_error(g["p"], o["p"]).max(axis=1)
@@ -114,6 +148,21 @@ def compare_fit(g, o, tol_p, tol_c, mask=None, ignore_bits=O.FP64_FALLBACK, tail
     over = m & ((ep > tol_p) | (ec > tol_c))
     summary = dict(n=int(n), compared=int(m.sum()), max_param_err=float(ep[m].max(initial=0.0)),
                    max_chi2_err=float(ec[m].max(initial=0.0)), over_tolerance=int(over.sum()))
+    if geom is not None and n > 0:
+        fp32 = tol_p > 1e-6
+        ctol = cov_tol if cov_tol is not None else (COV_TOL32 if fp32 else COV_TOL64)
+        eC = cov_error(g, o, geom)
+        overC = m & (eC > ctol)
+        summary.update(max_cov_err=float(eC[m].max(initial=0.0)), cov_over_tolerance=int(overC.sum()),
+                       cov_err_p99=float(np.quantile(eC[m], 0.99)) if m.any() else 0.0)
+        if fp32:
+            # FP32: at least 99% of the tracks within the tolerance; the rest
+            # is reported (the tail of the FP32 covariance arithmetic)
+            assert overC.sum() <= max(COV_TAIL32, tail_frac) * max(m.sum(), 1), (summary, np.nonzero(overC)[0][:10])
+        else:
+            farC = np.nonzero(m & (eC > tail_factor * ctol))[0]
+            assert farC.size == 0, (summary, farC[:10], eC[farC[:10]])
+            assert overC.sum() <= tail_frac * max(m.sum(), 1), (summary, np.nonzero(overC)[0][:10])
     far = np.nonzero(m & ((ep > tail_factor * tol_p) | (ec > tail_factor_chi2 * tol_c)))[0]
     assert far.size == 0, (summary, far[:10], ep[far[:10]], ec[far[:10]])
     assert over.sum() <= tail_frac * max(m.sum(), 1), (summary, np.nonzero(over)[0][:10])

@@ -253,10 +253,10 @@ def test_smooth_tracks_argument_validation(over, msg):
 
 def _final_call(**over):
     Q = ctypes.c_void_p(0x2000)
-    args = dict(ctx=P, prec=kf.KF_F32, n=10, ld=10, state_in=P, cov_in=P, charge_in=P, fwd_status=P, hit_offsets=P,
-                hit_layer=P, hit_valid=P, n_hits=100, hit_pos=P, hit_cov=P, geom=ctypes.byref(_geom().struct),
-                cov_scale=100.0, chi2_cut=30.0, max_len=26, state_out=Q, cov_out=Q, charge_out=Q, chi2=Q, ndf=Q,
-                trk_status=Q, outlier=None, stream=None)
+    args = dict(ctx=P, prec=kf.KF_F32, n=10, ld=10, seed_mode=0, hit_offsets=P, hit_layer=P, hit_valid=P,
+                n_hits=100, hit_pos=P, hit_cov=P, geom=ctypes.byref(_geom().struct), cov_scale=100.0, chi2_cut=30.0,
+                max_reject=3, min_keep=4, max_len=26, state_out=Q, cov_out=Q, charge_out=Q, chi2=Q, ndf=Q,
+                trk_status=Q, outlier=Q, hit_chi2=None, stream=None)
     args.update(over)
     return kf.lib().kf_final_fit(*args.values())
 
@@ -266,11 +266,16 @@ def _final_call(**over):
     (dict(chi2_cut=-1.0), "chi2_cut"),
     (dict(chi2_cut=float("nan")), "chi2_cut"),
     (dict(cov_scale=0.5), "cov_scale"),
+    (dict(max_reject=-1), "max_reject"),
+    (dict(max_reject=65), "max_reject"),
+    (dict(min_keep=2), "min_keep"),
+    (dict(seed_mode=2), "seed mode"),
     (dict(n=-1), "n = -1"),
+    (dict(ld=5), "ld = 5"),
     (dict(max_len=0), "max_len = 0"),
     (dict(hit_pos=None), "hit_pos is NULL"),
+    (dict(outlier=None), "outlier is NULL"),
     (dict(ctx=None), "ctx is NULL"),
-    (dict(cov_out=P), "alias"),
 ])
 def test_final_fit_argument_validation(over, msg):
     assert _final_call(**over) == kf.KF_ERR_ARG
@@ -278,7 +283,7 @@ def test_final_fit_argument_validation(over, msg):
 
 
 def test_final_fit_empty_batch_is_a_no_op():
-    assert _final_call(n=0, ld=0, ctx=None, state_in=None, chi2_cut=float("inf")) == kf.KF_OK
+    assert _final_call(n=0, ld=0, ctx=None, hit_offsets=None, chi2_cut=float("inf")) == kf.KF_OK
 
 
 def _dedup_call(**over):
@@ -367,10 +372,69 @@ def test_binding_checks_smoother_buffers_status_and_offsets():
         c.smooth_tracks(fwd, ck, *short, g, max_len=5, smooth=sm)
     with pytest.raises(ValueError, match="hit_offsets"):
         c.backward_fit(fwd, *short, g)
-    with pytest.raises(ValueError, match="hit_offsets"):
-        c.final_fit(fwd, *short, g)
     seeds = (fwd["state"], fwd["cov"], fwd["charge"])
     with pytest.raises(ValueError, match="hit_offsets"):
         c.fit_tracks(*seeds, *short, g)
     with pytest.raises(ValueError, match="hit_offsets"):
         c.fit_adjoint(*seeds, *short, g, ck, 1, 5, fwd["status"])
+
+
+def _plane_geom(n_modules=10, bz=3.8, mass=0.13957, modules=P):
+    return kf.KfPlaneGeometry(n_modules, modules, bz, mass)
+
+
+def _plane_fit_call(**over):
+    g = over.pop("geometry", _plane_geom())
+    args = dict(ctx=P, prec=kf.KF_F32, n=10, ld=10, seed_state=P, seed_cov=P, seed_charge=P, hit_offsets=P,
+                hit_module=P, hit_valid=P, n_hits=100, hit_uv=P, hit_cov_uv=P,
+                geom=None if g is None else ctypes.byref(g), state_out=P, cov_out=P, charge_out=P, chi2=P, ndf=P,
+                trk_status=P, stream=None)
+    args.update(over)
+    return kf.lib().kf_fit_plane_tracks(*args.values())
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(n=-1), "n = -1"),
+    (dict(ld=5), "ld = 5 < n = 10"),
+    (dict(prec=3), "precision 3"),
+    (dict(n_hits=-1), "n_hits < 0"),
+    (dict(n_hits=1 << 31), "n_hits"),
+    (dict(hit_module=None), "hit_module is NULL"),
+    (dict(hit_uv=None), "hit_uv is NULL"),
+    (dict(seed_cov=None), "seed_cov is NULL"),
+    (dict(geometry=None), "plane geometry is NULL"),
+    (dict(geometry=_plane_geom(n_modules=0)), "n_modules"),
+    (dict(geometry=_plane_geom(modules=None)), "modules is NULL"),
+    (dict(geometry=_plane_geom(bz=0.0)), "bz_tesla"),
+    (dict(geometry=_plane_geom(mass=-1.0)), "particle_mass_gev"),
+])
+def test_fit_plane_tracks_argument_validation(over, msg):
+    assert _plane_fit_call(**over) == kf.KF_ERR_ARG
+    assert msg in kf.lib().kf_last_error().decode()
+
+
+def test_plane_entry_points_validate():
+    lib = kf.lib()
+    g = ctypes.byref(_plane_geom())
+    assert lib.kf_propagate_plane(P, 0, 5, 5, P, P, P, None, g, 1, P, P, None, P, None) == kf.KF_ERR_ARG
+    assert "target_module" in lib.kf_last_error().decode()
+    assert lib.kf_propagate_plane(P, 0, 5, 5, P, P, P, P, None, 1, P, P, None, P, None) == kf.KF_ERR_ARG
+    assert "plane geometry is NULL" in lib.kf_last_error().decode()
+    assert lib.kf_update_plane(P, 1, 5, 5, P, P, P, P, P, None, g, P, P, None) == kf.KF_ERR_ARG
+    assert "hit_cov_uv" in lib.kf_last_error().decode()
+    assert lib.kf_update_plane(P, 0, 5, 4, P, P, P, P, P, P, g, P, P, None) == kf.KF_ERR_ARG
+    assert lib.kf_plane_to_global(P, 0, 10, None, P, g, P, None) == kf.KF_ERR_ARG
+    assert "module is NULL" in lib.kf_last_error().decode()
+    assert lib.kf_plane_to_global(P, 0, -1, P, P, g, P, None) == kf.KF_ERR_ARG
+
+
+def test_plane_entry_points_empty_batch_is_a_no_op():
+    """n = 0 (n_hits = 0) returns KF_OK before any device work, with NULL arrays."""
+    lib = kf.lib()
+    g = ctypes.byref(_plane_geom())
+    assert lib.kf_propagate_plane(P, 0, 0, 0, None, None, None, None, g, 1, None, None, None, None, None) == kf.KF_OK
+    assert lib.kf_update_plane(P, 1, 0, 0, None, None, None, None, None, None, g, None, None, None) == kf.KF_OK
+    assert _plane_fit_call(n=0, ld=0, seed_state=None, seed_cov=None, seed_charge=None, hit_offsets=None,
+                           hit_module=None, hit_valid=None, n_hits=0, hit_uv=None, hit_cov_uv=None, state_out=None,
+                           cov_out=None, charge_out=None, chi2=None, ndf=None, trk_status=None) == kf.KF_OK
+    assert lib.kf_plane_to_global(P, 0, 0, None, None, g, None, None) == kf.KF_OK

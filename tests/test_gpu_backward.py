@@ -62,7 +62,7 @@ def _backward_only(c, kf, ev, dtype, seed_mode, tol, max_bad_frac, tail_frac):
     bad = backward_probes(ev, dtype, lambda **kw: oracle_backward(ev, dtype, fwd, **kw), ob, tol)
     assert bad.mean() <= max(max_bad_frac, 0.005), bad.mean()
     gb = gpu_backward(c, kf, ev, dtype, fwd)
-    s = compare_fit(gb, ob, tol[0], tol[1], ~bad, tail_frac=tail_frac)
+    s = compare_fit(gb, ob, tol[0], tol[1], ~bad, tail_frac=tail_frac, geom=ev.geometry)
     s["ill_conditioned"] = int(bad.sum())
     say(s)
     return gb, ob
@@ -107,7 +107,7 @@ def _chain_case(c, kf, ev, dtype, seed_mode, tol, max_bad_frac, tail_frac):
     bad = backward_probes(ev, dtype, lambda **kw: _oracle_chain(ev, dtype, seed_mode, **kw), ob, tol)
     assert bad.mean() <= max(max_bad_frac, 0.005), bad.mean()
     gb = _chain(c, kf, ev, dtype, seed_mode)
-    s = compare_fit(gb, ob, tol[0], tol[1], ~bad, tail_frac=tail_frac)
+    s = compare_fit(gb, ob, tol[0], tol[1], ~bad, tail_frac=tail_frac, geom=ev.geometry)
     s["ill_conditioned"] = int(bad.sum())
     s["launch"] = c.get_fit_launch(dtype)
     say(s)
@@ -171,7 +171,7 @@ def test_backward_ragged_sizes(ctx, kf, n):
     if n:
         o = oracle_backward(ev, dt, fwd)
         bad = backward_probes(ev, dt, lambda **kw: oracle_backward(ev, dt, fwd, **kw), o, TOL32)
-        compare_fit(g, o, TOL32[0], TOL32[1], ~bad, tail_frac=0.01)
+        compare_fit(g, o, TOL32[0], TOL32[1], ~bad, tail_frac=0.01, geom=ev.geometry)
 
 
 def test_backward_is_deterministic(ctx, kf):
@@ -210,7 +210,7 @@ def _smooth_case(c, kf, ev, dtype, seed_mode, tol, max_bad_frac, tail_frac):
     g, gstate, gcov = gpu_smooth(c, kf, ev, dtype, rec)
     ob = dict(p=o["p"].numpy(), C=o["C"].numpy(), q=o["q"].numpy(), chi2=o["chi2"].numpy(), ndf=o["ndf"].numpy(),
               status=o["status"].numpy())
-    s = compare_fit(g, ob, tol[0], tol[1], ~bad, tail_frac=tail_frac)
+    s = compare_fit(g, ob, tol[0], tol[1], ~bad, tail_frac=tail_frac, geom=ev.geometry)
     gps = per_entry(ev, gstate)
     ok_e = np.repeat(~bad, ev.lengths())
     # the same entries are smoothed
