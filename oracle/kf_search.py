@@ -123,6 +123,8 @@ class SearchParams:
     win_max_z: np.ndarray = None
     sigma_rphi: np.ndarray = None     # [n_layers] nominal hit resolution, cm
     sigma_z: np.ndarray = None
+    overlap: bool = False             # pick up one overlap hit per layer (step 7)
+    overlap_bonus: float = 5.0        # score of an overlap hit: + overlap_bonus - chi2
 
     def __post_init__(self):
         L = self.n_layers
@@ -141,13 +143,14 @@ def _wrap(a):
 class _LayerPool:
     """Hits of one layer sorted by phi for window queries."""
 
-    def __init__(self, pos, cov, ids):
+    def __init__(self, pos, cov, ids, mods=None):
         phi = np.arctan2(pos[1], pos[0])
         o = np.argsort(phi, kind="stable")
         self.phi = phi[o]
         self.pos = pos[:, o]
         self.cov = cov[:, o]
         self.ids = ids[o]
+        self.mods = None if mods is None else mods[o]
 
     def query(self, phi_c, half):
         """Indices of hits with |wrap(phi - phi_c)| <= half (half < pi)."""
@@ -208,8 +211,12 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
     lp = {}
     for L in set(int(x) for x in layer_plan):
         a, b = int(pools.layer_offsets[L]), int(pools.layer_offsets[L + 1])
+        mods = getattr(pools, "module", None) if prm.overlap else None
+        if prm.overlap and mods is None:
+            raise ValueError("the overlap step needs the pools' module ids")
         lp[L] = _LayerPool(np.asarray(pools.pos[:, a:b], np.float64), np.asarray(pools.cov[:, a:b], np.float64),
-                           np.asarray(pools.hit_id[a:b], np.int64))
+                           np.asarray(pools.hit_id[a:b], np.int64),
+                           None if mods is None else np.asarray(mods[a:b], np.int64))
     # live candidates: parallel lists
     c_seed = list(range(n))
     c_rank = [0] * n
@@ -220,6 +227,7 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
     c_miss = [0] * n
     c_layer = [int(seed_layer[i]) for i in range(n)]
     c_hist = [[] for _ in range(n)]
+    c_ovl = [[] for _ in range(n)]   # overlap hit id of each step (MISS: none)
     c_err = [[] for _ in range(n)]   # FP32 error of each score term
     where = {}   # hit id -> index into pools, for comparing the inputs of exact ties
 
@@ -325,6 +333,7 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
             children.setdefault(s, []).extend(kids)
         # ranking and selection per seed
         n_p, n_C, n_q, n_score, n_miss, n_hist, n_seed, n_rank, n_err, n_stop = [], [], [], [], [], [], [], [], [], []
+        n_ovl = []
         upd = []
         for s in sorted(children):
             kids = children[s]
@@ -351,6 +360,7 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
                 n_score.append(sc)
                 n_miss.append(c_miss[i] + (1 if hid == MISS else 0))
                 n_hist.append(c_hist[i] + [hid])
+                n_ovl.append(c_ovl[i] + [MISS])
                 n_err.append(c_err[i] + [err])
                 n_stop.append(hid == STOP)
                 if hid == STOP:
@@ -381,10 +391,16 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
                 n_C[j] = Cu[a].numpy()
                 n_q[j] = float(qu[a])
                 status[n_seed[j]] |= int(su[a])
+            if prm.overlap:
+                for j, h in upd:
+                    _overlap_step(j, h, step, L, R, pool, prm, n_p, n_C, n_q, n_score, n_hist, n_ovl, n_err, n_seed,
+                                  flags, near, status, flips, state_round)
         c_seed, c_rank, c_p, c_C, c_q = n_seed, n_rank, n_p, n_C, n_q
         c_score, c_miss, c_hist, c_err, c_stop = n_score, n_miss, n_hist, n_err, n_stop
+        c_ovl = n_ovl
         c_layer = [L] * len(c_seed)
     hits = np.full((n, B, P), NO_CAND, np.int64)
+    ovl = np.full((n, B, P), NO_CAND, np.int64)
     score = np.full((n, B), -np.inf)
     pout = np.full((n, B, 6), np.nan)
     Cout = np.full((n, B, 6, 6), np.nan)
@@ -393,12 +409,108 @@ def score_hits(seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm:
         r = c_rank[j]
         h = c_hist[j]
         hits[s, r, :len(h)] = h
+        ovl[s, r, :len(h)] = c_ovl[j]
         score[s, r] = c_score[j]
         pout[s, r] = c_p[j]
         Cout[s, r] = c_C[j]
         serr[s, r] = math.sqrt(sum(e * e for e in c_err[j]))
     return dict(hits=hits, score=score, p=pout, C=Cout, status=status, flagged=flags != 0, flags=flags, near=near,
-                score_err=serr, n_window_hits=n_window)
+                score_err=serr, n_window_hits=n_window, overlap=ovl)
+
+
+def _window(p, C, L, R, prm):
+    """The window of steps 2 (or 7) around the state p with covariance C on
+    layer L of radius R: (phi_p, w_rphi, w_z, position error, r-phi spread)."""
+    x, y = p[0], p[1]
+    phi_p = math.atan2(y, x)
+    cos_a = math.sin(p[5]) * (math.cos(p[4]) * x + math.sin(p[4]) * y) / math.hypot(x, y)
+    epos = pos_error(R, cos_a)
+    t = np.array([-math.sin(phi_p), math.cos(phi_p), 0.0])
+    Cp = C[:3, :3]
+    sig = math.sqrt(t @ Cp @ t + prm.sigma_rphi[L] ** 2)
+    w_r = min(max(prm.n_sigma * sig, prm.win_min_rphi[L]), prm.win_max_rphi[L])
+    w_z = min(max(prm.n_sigma * math.sqrt(Cp[2, 2] + prm.sigma_z[L] ** 2), prm.win_min_z[L]), prm.win_max_z[L])
+    return phi_p, w_r, w_z, epos, sig
+
+
+def _overlap_step(j, h, step, L, R, pool, prm, n_p, n_C, n_q, n_score, n_hist, n_ovl, n_err, n_seed, flags, near,
+                  status, flips, state_round):
+    """Step 7: the kept child j took pool hit h (layer-pool index) at this
+    layer and has been updated with it.  Its overlap hit is, among the
+    layer's hits on a module other than h's that lie inside the window
+    around the updated state (step 2's formulas with the updated
+    covariance) and have chi2 <= chi2_max against it, the one with the
+    smallest chi2 (the lower hit id among equals).  If there is one, the
+    child is updated with it too, its score gains overlap_bonus - chi2 and
+    the hit is recorded as the step's overlap hit.  Near decisions: window
+    edges and the cut as in steps 2-3 (keys "ovl-edge", "ovl-cut"), and a
+    second-smallest chi2 within the chi2 errors of the smallest ("ovl-pick":
+    taken the other way, the second is picked)."""
+    s = n_seed[j]
+    p, C = n_p[j], n_C[j]
+    phi_p, w_r, w_z, epos, sig = _window(p, C, L, R, prm)
+    mr, mz = EDGE_REL * w_r + epos, EDGE_REL * w_z + epos
+    hist = tuple(n_hist[j])
+    cand = pool.query(phi_p, (w_r + mr) / R)
+    if cand.size:
+        cand = cand[(np.abs(pool.pos[2, cand] - p[2]) <= w_z + mz) & (pool.mods[cand] != pool.mods[h])]
+    if cand.size == 0:
+        return
+    darc = np.abs(_wrap(pool.phi[cand] - phi_p)) * R
+    dz = np.abs(pool.pos[2, cand] - p[2])
+    inside = (darc <= w_r) & (dz <= w_z)
+    for a in np.nonzero((np.abs(darc - w_r) <= mr) | (np.abs(dz - w_z) <= mz))[0]:
+        key = ("ovl-edge", step, hist, int(pool.ids[cand[a]]))
+        flags[s] |= 1
+        near[s].append(key)
+        if key in flips:
+            inside[a] = not inside[a]
+    cand = cand[inside]
+    if cand.size == 0:
+        return
+    chi2, kap = _chi2(p[:3], C[:3, :3], pool.pos[:, cand].T, pool.cov[:, cand])
+    acc = []
+    for hh, c2, kp in zip(cand, chi2, kap):
+        ok = c2 <= prm.chi2_max
+        if abs(c2 - prm.chi2_max) <= chi2_error(prm.chi2_max, epos, sig, kp):
+            key = ("ovl-cut", step, hist, int(pool.ids[hh]))
+            flags[s] |= 2
+            near[s].append(key)
+            if key in flips:
+                ok = not ok
+        if ok:
+            acc.append((float(c2), int(pool.ids[hh]), int(hh), chi2_error(c2, epos, sig, kp)))
+    if not acc:
+        return
+    acc.sort(key=lambda x: (x[0], x[1]))
+    pick = acc[0]
+    if len(acc) > 1:
+        a0, a1 = acc[0], acc[1]
+        d = a1[0] - a0[0]
+        if d <= RANK_SIGMAS * math.hypot(a0[3], a1[3]) and not (d == 0.0 and _same_hit(pool, a0[2], a1[2])):
+            key = ("ovl-pick", step, hist, (a0[1], a1[1]))
+            flags[s] |= 4
+            near[s].append(key)
+            if key in flips:
+                pick = a1
+    c2, hid, hh, err = pick
+    il = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+    V = np.zeros((1, 3, 3))
+    for c_, (u, v) in enumerate(il):
+        V[0, u, v] = V[0, v, u] = pool.cov[c_, hh]
+    pu, Cu, qu, _, su = O.update(torch.tensor(p[None]), torch.tensor(C[None]), torch.tensor([n_q[j]], dtype=torch.float64),
+                                 torch.tensor(pool.pos[:, hh][None]), torch.tensor(V))
+    if state_round is not None:
+        pu, Cu = _round(pu, Cu, state_round)
+    n_p[j], n_C[j], n_q[j] = pu[0].numpy(), Cu[0].numpy(), float(qu[0])
+    status[s] |= int(su[0])
+    n_score[j] = n_score[j] + prm.overlap_bonus - c2
+    n_ovl[j][-1] = hid
+    n_err[j][-1] = math.hypot(n_err[j][-1], err)
+
+
+def _same_hit(pool, i, j):
+    return bool(np.array_equal(pool.pos[:, i], pool.pos[:, j]) and np.array_equal(pool.cov[:, i], pool.cov[:, j]))
 
 
 def _bears_on(key, target, current):

@@ -23,14 +23,50 @@ def _V(cov6):
     return V
 
 
+def _window_scan(p2, C2, L, R, prm, pools, exclude_module=None):
+    """(pool index, chi2) of every hit of layer L inside the window of the
+    state (p2, C2) with chi2 <= chi2_max, by a scan over all of the layer's
+    hits (skipping those of module `exclude_module`)."""
+    phi = math.atan2(p2[1], p2[0])
+    t = np.array([-math.sin(phi), math.cos(phi), 0.0])
+    w_r = np.clip(prm.n_sigma * math.sqrt(t @ C2[:3, :3] @ t + prm.sigma_rphi[L] ** 2), prm.win_min_rphi[L],
+                  prm.win_max_rphi[L])
+    w_z = np.clip(prm.n_sigma * math.sqrt(C2[2, 2] + prm.sigma_z[L] ** 2), prm.win_min_z[L], prm.win_max_z[L])
+    kids = []
+    for h in range(int(pools.layer_offsets[L]), int(pools.layer_offsets[L + 1])):
+        if exclude_module is not None and pools.module[h] == exclude_module:
+            continue
+        m = pools.pos[:, h]
+        d = (math.atan2(m[1], m[0]) - phi + math.pi) % (2 * math.pi) - math.pi
+        if abs(d) * R > w_r or abs(m[2] - p2[2]) > w_z:
+            continue
+        r = m - p2[:3]
+        chi2 = float(r @ np.linalg.solve(C2[:3, :3] + _V(pools.cov[:, h]), r))
+        if chi2 <= prm.chi2_max:
+            kids.append((h, chi2))
+    return kids
+
+
+def _update(p, C, q, pools, h):
+    pu, Cu, qu, _, _ = O.update(torch.tensor(p[None]), torch.tensor(C[None]), torch.tensor([q], dtype=torch.float64),
+                                torch.tensor(pools.pos[:, h][None]), torch.tensor(_V(pools.cov[:, h])[None]))
+    return pu[0].numpy(), Cu[0].numpy(), float(qu[0])
+
+
 def enumerate_paths(p, C, q, plan, g, pools, prm):
     """Every path the search rules allow for one seed, by depth-first
-    recursion; windows by a scan over all pool hits of the layer."""
+    recursion; windows by a scan over all pool hits of the layer.  With
+    prm.overlap, a path that takes hit h then takes the overlap hit: of the
+    layer's hits on other modules inside the window of the updated state
+    with chi2 <= chi2_max, the smallest chi2 (lower id among equals); the
+    overlap hit's score term counts in the ranking from the next layer on.
+    Returns (score in the last ranking, final score, hits, overlap hits) per
+    path."""
     out = []
 
-    def rec(k, p, C, q, layer, score, misses, hist):
+    def rec(k, p, C, q, layer, score, misses, hist, ovl, last_ovl=0.0):
         if k == len(plan):
-            out.append((score, hist))
+            out.append((score - last_ovl, score, hist, ovl))
             return
         L = plan[k]
         R = float(g.pos[L])
@@ -40,42 +76,32 @@ def enumerate_paths(p, C, q, plan, g, pools, prm):
         if int(st[0]) & O.NO_CROSSING:
             return
         p2, C2 = p2[0].numpy(), C2[0].numpy()
-        phi = math.atan2(p2[1], p2[0])
-        t = np.array([-math.sin(phi), math.cos(phi), 0.0])
-        w_r = np.clip(prm.n_sigma * math.sqrt(t @ C2[:3, :3] @ t + prm.sigma_rphi[L] ** 2), prm.win_min_rphi[L],
-                      prm.win_max_rphi[L])
-        w_z = np.clip(prm.n_sigma * math.sqrt(C2[2, 2] + prm.sigma_z[L] ** 2), prm.win_min_z[L], prm.win_max_z[L])
-        kids = []
-        for h in range(int(pools.layer_offsets[L]), int(pools.layer_offsets[L + 1])):
-            m = pools.pos[:, h]
-            d = (math.atan2(m[1], m[0]) - phi + math.pi) % (2 * math.pi) - math.pi
-            if abs(d) * R > w_r or abs(m[2] - p2[2]) > w_z:
-                continue
-            r = m - p2[:3]
-            chi2 = float(r @ np.linalg.solve(C2[:3, :3] + _V(pools.cov[:, h]), r))
-            if chi2 <= prm.chi2_max:
-                kids.append((h, chi2))
+        kids = _window_scan(p2, C2, L, R, prm, pools)
         if not kids:
             if misses < prm.max_miss:
-                rec(k + 1, p2, C2, q, L, score - prm.miss_penalty, misses + 1, hist + [KS.MISS])
+                rec(k + 1, p2, C2, q, L, score - prm.miss_penalty, misses + 1, hist + [KS.MISS], ovl + [KS.MISS])
             return
         for h, chi2 in kids:
-            pu, Cu, qu, _, _ = O.update(torch.tensor(p2[None]), torch.tensor(C2[None]),
-                                        torch.tensor([q], dtype=torch.float64),
-                                        torch.tensor(pools.pos[:, h][None]), torch.tensor(_V(pools.cov[:, h])[None]))
-            rec(k + 1, pu[0].numpy(), Cu[0].numpy(), float(qu[0]), L, score + prm.hit_bonus - chi2, misses,
-                hist + [int(pools.hit_id[h])])
+            pu, Cu, qu = _update(p2, C2, q, pools, h)
+            sc, oid, term = score + prm.hit_bonus - chi2, KS.MISS, 0.0
+            if prm.overlap:
+                ok = _window_scan(pu, Cu, L, R, prm, pools, exclude_module=pools.module[h])
+                if ok:
+                    h2, c2 = min(ok, key=lambda x: (x[1], int(pools.hit_id[x[0]])))
+                    pu, Cu, qu = _update(pu, Cu, qu, pools, h2)
+                    term, oid = prm.overlap_bonus - c2, int(pools.hit_id[h2])
+            rec(k + 1, pu, Cu, qu, L, sc + term, misses, hist + [int(pools.hit_id[h])], ovl + [oid], term)
 
-    rec(0, p, C, q, SEED_LAYER, 0.0, 0, [])
+    rec(0, p, C, q, SEED_LAYER, 0.0, 0, [], [])
     return out
 
 
 def _tiny_pools(ev, pools, tracks, layers, offsets, rotate=0.0):
     """Pools of the given layers holding, for each listed track, its true hit
     and copies moved along the layer by each of `offsets` (cm); hit positions
-    rotated about z by `rotate`."""
+    rotated about z by `rotate`.  Copy c of a hit is on module c."""
     P = copy.copy(pools)
-    pos, cov, tid, off = [], [], [], [0]
+    pos, cov, tid, mod, off = [], [], [], [], [0]
     c, s = math.cos(rotate), math.sin(rotate)
     for L in range(int(ev.geometry.n_layers)):
         if L in layers:
@@ -85,7 +111,7 @@ def _tiny_pools(ev, pools, tracks, layers, offsets, rotate=0.0):
                 for h in sel:
                     m = pools.pos[:, h]
                     phi = math.atan2(m[1], m[0])
-                    for dl in [0.0] + list(offsets):
+                    for ci, dl in enumerate([0.0] + list(offsets)):
                         R = math.hypot(m[0], m[1])
                         ph = phi + dl / R + rotate
                         pos.append([R * math.cos(ph), R * math.sin(ph), m[2] + 0.3 * dl])
@@ -97,10 +123,12 @@ def _tiny_pools(ev, pools, tracks, layers, offsets, rotate=0.0):
                         V = Rm @ V @ Rm.T
                         cov.append([V[i, j] for i, j in IL])
                         tid.append(t)
+                        mod.append(ci)
         off.append(len(pos))
     P.pos = np.asarray(pos, np.float64).T.reshape(3, -1)
     P.cov = np.asarray(cov, np.float64).T.reshape(6, -1)
     P.track = np.asarray(tid, np.int32)
+    P.module = np.asarray(mod, np.int32)   # each copy of a hit on a module of its own
     P.hit_id = np.arange(len(pos), dtype=np.int32)[::-1].copy()   # ids not in pool order
     P.layer_offsets = np.asarray(off, np.int32)
     return P
@@ -135,7 +163,7 @@ def test_search_equals_exhaustive_enumeration_when_the_beam_holds_every_path(rot
         res = KS.score_hits(ps[None], Cs[None], q[t:t + 1], [SEED_LAYER], plan, g, P, prm)
         assert 1 <= len(paths) <= prm.beam
         paths.sort(key=lambda x: -x[0])
-        for r, (sc, hist) in enumerate(paths):
+        for r, (sc, _, hist, _) in enumerate(paths):
             assert list(res["hits"][0, r]) == hist, (t, r)
             assert abs(res["score"][0, r] - sc) <= 1e-9 * max(1.0, abs(sc))
         assert (res["hits"][0, len(paths):] == KS.NO_CAND).all()
@@ -383,3 +411,78 @@ def test_replay_reproduces_the_search_and_rejects_impossible_lists():
     sc[0] += 1.0 + 10 * KS.RANK_SIGMAS * o["score_err"][s, 0]
     assert not KS.consistent_result(o["hits"][s], sc, p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm,
                                     o["hits"][s], o["score"][s], o["score_err"][s])[0]
+
+
+@pytest.mark.parametrize("rotate", [0.0, "wrap"])
+def test_overlap_search_equals_exhaustive_enumeration(rotate):
+    """With the overlap step, every path (hits and overlap hits), its rank
+    (by the score of the last ranking, which does not hold that layer's
+    overlap term) and its final score equal the exhaustive enumeration of the
+    rules (each copy of a hit on a module of its own, so the copies are each
+    other's overlap candidates)."""
+    wl, ev, g, pools, p, C, q = search_inputs(40, noise=False)
+    plan = PLAN[:4]
+    prm = default_params(g, beam=200)
+    prm.overlap = True
+    checked = 0
+    for t in range(6):
+        a = 0.0
+        if rotate == "wrap":
+            h = int(np.nonzero((pools.track == t) & (np.arange(pools.track.size) >= pools.layer_offsets[plan[1]]) &
+                               (np.arange(pools.track.size) < pools.layer_offsets[plan[1] + 1]))[0][0])
+            a = math.pi - 1e-4 - math.atan2(pools.pos[1, h], pools.pos[0, h])
+        P = _tiny_pools(ev, pools, [t], set(plan), offsets=(0.004, -0.006), rotate=a)
+        ps, Cs = _rotate_seed(p[t], C[t], a)
+        paths = enumerate_paths(ps, Cs, float(q[t]), plan, g, P, prm)
+        res = KS.score_hits(ps[None], Cs[None], q[t:t + 1], [SEED_LAYER], plan, g, P, prm)
+        assert 1 <= len(paths) <= prm.beam
+        # the same set of paths with the same scores, in the order of the
+        # last ranking (taking a hit and its overlap hit in either order gives
+        # the same final state and, in the linear model, the same chi2 sum:
+        # such paths tie up to rounding, so only the scores' order is checked)
+        want = {(tuple(hist), tuple(ovl)): (rs, sc) for rs, sc, hist, ovl in paths}
+        got = [(tuple(int(x) for x in res["hits"][0, r]), tuple(int(x) for x in res["overlap"][0, r]))
+               for r in range(len(paths))]
+        assert set(got) == set(want), t
+        for r, key in enumerate(got):
+            assert abs(res["score"][0, r] - want[key][1]) <= 1e-9 * max(1.0, abs(want[key][1]))
+        rs = [want[key][0] for key in got]
+        assert all(a >= b - 1e-9 * max(1.0, abs(a)) for a, b in zip(rs[:-1], rs[1:])), t
+        assert (res["hits"][0, len(paths):] == KS.NO_CAND).all()
+        checked += sum(o >= 0 for o in max(paths)[3])
+    assert checked >= 6   # overlap hits are taken
+
+
+def test_overlap_hits_on_modules_with_overlaps():
+    """Pools split into modules with overlap hits (toygen.with_modules), no
+    noise: the best candidate of a seed takes, at the layers where its track
+    left a second hit on the overlapping module, that hit as its overlap hit
+    (>= 95%), every overlap hit it takes is on a module other than its
+    layer's hit and belongs to the same track, and without the overlap step
+    no overlap hit is reported."""
+    from toygen import with_modules, workloads
+    wl, ev, g, pools, p, C, q = search_inputs(150, noise=False)
+    P = with_modules(workloads()["search20"], ev, pools)
+    prm = default_params(g)
+    prm.overlap = True
+    res = KS.score_hits(p, C, q, np.full(150, SEED_LAYER), PLAN, g, P, prm)
+    idx = {int(h): k for k, h in enumerate(P.hit_id)}
+    avail = took = 0
+    for t in range(150):
+        for hid, oid in zip(res["hits"][t, 0], res["overlap"][t, 0]):
+            if hid < 0:
+                continue
+            k = idx[int(hid)]
+            L = int(np.searchsorted(P.layer_offsets, k, side="right") - 1)
+            a, b = int(P.layer_offsets[L]), int(P.layer_offsets[L + 1])
+            twins = [j for j in range(a, b) if P.track[j] == P.track[k] and j != k and P.module[j] != P.module[k]]
+            if oid >= 0:
+                j = idx[int(oid)]
+                assert P.module[j] != P.module[k] and P.track[j] == P.track[k]
+            if P.track[k] == t and twins:
+                avail += 1
+                took += oid >= 0
+    assert avail >= 50 and took >= 0.95 * avail, (took, avail)
+    prm.overlap = False
+    res0 = KS.score_hits(p, C, q, np.full(150, SEED_LAYER), PLAN, g, P, prm)
+    assert ((res0["overlap"] == KS.MISS) | (res0["overlap"] == KS.NO_CAND)).all()

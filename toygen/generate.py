@@ -392,6 +392,7 @@ class HitPools:
     cov: np.ndarray            # float64 [6, np]
     hit_id: np.ndarray         # int32 [np] (= index into these arrays; generator order)
     track: np.ndarray          # int32 [np] producing track, -1 for noise
+    module: np.ndarray = None  # int32 [np] detector module of each hit (with_modules), or None
 
 
 def make_pools(wl: Workload, ev: Event, first_layer: int = 3, noise: bool = True) -> HitPools:
@@ -430,3 +431,69 @@ def make_pools(wl: Workload, ev: Event, first_layer: int = 3, noise: bool = True
     trk = np.concatenate(trk_l) if trk_l else np.zeros(0, np.int32)
     return HitPools(layer_offsets=np.asarray(off, np.int32), pos=pos, cov=cov,
                     hit_id=np.arange(trk.shape[0], dtype=np.int32), track=trk.astype(np.int32))
+
+
+MODULE_WIDTH = 4.0     # cm of r-phi per barrel module (sets the module count of a layer)
+MODULE_OVERLAP = 0.4   # cm of r-phi by which a module overlaps the next one
+
+
+def with_modules(wl: Workload, ev: Event, pools: HitPools, width: float = MODULE_WIDTH,
+                 overlap: float = MODULE_OVERLAP) -> HitPools:
+    """The pools split into detector modules, with overlap hits.  Barrel layer
+    l of radius R holds n = max(12, ceil(2 pi R / width)) modules; module k
+    spans phi in [k d - pi, (k + 1) d - pi) plus `overlap` cm of r-phi beyond
+    its upper edge (d = 2 pi / n), so that it overlaps the first `overlap` cm
+    of module k + 1.  Modules are numbered layer by layer.  A pool hit belongs
+    to the module its phi falls in; a true hit whose crossing lies in an
+    overlap region is also measured by the overlapping module: a second hit,
+    at the true crossing point smeared anew along r-phi and z, with the next
+    free hit id, appended to the layer's hits.  The overlapping modules are
+    taken to lie on the layer's surface (no radial offset), so that both hits
+    are measurements of the same crossing."""
+    g = wl.geometry
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(wl.seed + 104729)))
+    trk_of_hit = np.repeat(np.arange(ev.n_tracks, dtype=np.int32), ev.lengths())
+    off = np.asarray(pools.layer_offsets, np.int64)
+    pos_l, cov_l, id_l, trk_l, mod_l, new_off = [], [], [], [], [], [0]
+    next_id = int(pools.hit_id.max()) + 1 if pools.hit_id.size else 0
+    base = 0
+    for lay in range(g.n_layers):
+        a, b = int(off[lay]), int(off[lay + 1])
+        pos, cov = pools.pos[:, a:b], pools.cov[:, a:b]
+        ids, trk = pools.hit_id[a:b], pools.track[a:b]
+        if g.kind[lay] != BARREL or b == a:
+            mods = np.full(b - a, -1, np.int64)
+            pos_l.append(pos), cov_l.append(cov), id_l.append(ids), trk_l.append(trk), mod_l.append(mods)
+            new_off.append(new_off[-1] + (b - a))
+            continue
+        R = float(g.pos[lay])
+        n_mod = max(12, int(np.ceil(2 * np.pi * R / width)))
+        d = 2 * np.pi / n_mod
+        k = np.minimum(((np.arctan2(pos[1], pos[0]) + np.pi) / d).astype(np.int64), n_mod - 1)
+        mods = base + k
+        # true crossings of this layer inside an overlap region
+        sel = np.nonzero((ev.hit_layer == lay) & (ev.hit_valid == 1))[0]
+        tx, ty, tz = ev.truth[sel, 0], ev.truth[sel, 1], ev.truth[sel, 2]
+        tphi = np.arctan2(ty, tx)
+        kt = np.minimum(((tphi + np.pi) / d).astype(np.int64), n_mod - 1)
+        into = (tphi + np.pi - kt * d) * R          # r-phi distance into module kt
+        dup = np.nonzero(into < overlap)[0]
+        g_r = rng.normal(0.0, 1.0, dup.size)
+        g_z = rng.normal(0.0, 1.0, dup.size)
+        ph2 = tphi[dup] + wl.sigma_rphi * g_r / R
+        npos = np.stack([R * np.cos(ph2), R * np.sin(ph2), tz[dup] + wl.sigma_z * g_z])
+        ncov = _hit_cov_barrel(ph2, wl.sigma_rphi, wl.sigma_z, wl.sigma_n)
+        nmod = base + (kt[dup] - 1) % n_mod          # the overlapping module below
+        nid = np.arange(next_id, next_id + dup.size, dtype=np.int32)
+        next_id += dup.size
+        pos_l.append(np.concatenate([pos, npos], axis=1))
+        cov_l.append(np.concatenate([cov, ncov], axis=1))
+        id_l.append(np.concatenate([ids, nid]))
+        trk_l.append(np.concatenate([trk, trk_of_hit[sel[dup]]]))
+        mod_l.append(np.concatenate([mods, nmod]))
+        new_off.append(new_off[-1] + (b - a) + dup.size)
+        base += n_mod
+    cat = lambda xs, ax=0: np.concatenate(xs, axis=ax)
+    return HitPools(layer_offsets=np.asarray(new_off, np.int32), pos=cat(pos_l, 1), cov=cat(cov_l, 1),
+                    hit_id=cat(id_l).astype(np.int32), track=cat(trk_l).astype(np.int32),
+                    module=cat(mod_l).astype(np.int32))
