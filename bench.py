@@ -493,12 +493,31 @@ def bench_search(ctx, K, args, sample=300):
         dd[:] = ctx.remove_duplicates(cand_h[:, 0, :], cand_s[:, 0], 0.5)
 
     ms_dd = time_loop(dedup, args.steps, args.warmup)
+    # the same seeds over the pools split into detector modules with overlap
+    # hits, with the overlap step (one overlap hit per kept candidate and layer)
+    from toygen import with_modules
+    mp = with_modules(wl, ev, pools)
+    mpp, mpc = f(mp.pos.astype(np.float32), torch.float32), f(mp.cov.astype(np.float32), torch.float32)
+    mid, mmod = f(mp.hit_id, torch.int32), f(mp.module, torch.int32)
+    prm_ovl = K.SearchParams(g.n_layers, beam=6, reuse_bins=True, overlap=True)
+    out_ovl = []
+
+    def run_ovl():
+        out_ovl[:] = ctx.score_hits(st, cv, qq, sl, plan, geom, prm_ovl, mp.layer_offsets, mpp, mpc, mid,
+                                    pool_module=mmod, want_overlap=True)
+
+    ms_ovl = time_loop(run_ovl, args.steps, args.warmup)
+    ovl_taken = int((out_ovl[4][:, 0] >= 0).sum().item())
     true_frac = float(np.mean([[h >= 0 and pools.track[h] == t for h in hits[t, 0]] for t in range(0, n, 10)]))
     res = {"seeds": n, "layers": len(plan), "beam": 6, "pool_hits": int(pools.pos.shape[1]), "ms": ms,
            "seeds_per_s": n / (ms * 1e-3), "ms_with_binning": ms_total, "ms_binning": ms_total - ms,
            "ms_dedup": ms_dd, "dedup_kept": int(dd[0].sum().item()), "dedup_frac": 0.5,
            "seeds_from": "kf_seed_fit_tracks over each track's first three hits (FP32, on the GPU)",
-           "rank0_true_hit_fraction": true_frac}
+           "rank0_true_hit_fraction": true_frac,
+           "overlap": {"ms": ms_ovl, "seeds_per_s": n / (ms_ovl * 1e-3), "pool_hits": int(mp.pos.shape[1]),
+                       "overlap_hits_in_pool": int(mp.pos.shape[1] - pools.pos.shape[1]),
+                       "rank0_overlap_hits": ovl_taken,
+                       "pools": "4 cm modules overlapping by 0.4 cm (toygen.with_modules), overlap step on"}}
     if not args.no_accuracy:
         # parity sample: GPU and oracle searches from the oracle's seeds
         from oracle import kf_search as KS
@@ -617,6 +636,14 @@ def profile_only(args, K, tune_fit, generate, workloads):
         r = bench_backward(ctx, K, ev, a)
         log("profile-only", args.profile_only, json.dumps(r))
         return
+    if args.profile_only == "planes":
+        ctx = K.Context(0)
+        a = argparse.Namespace(**vars(args))
+        a.warmup = 1
+        a.no_accuracy = True
+        r = bench_planes(ctx, K, a)
+        log("profile-only", args.profile_only, json.dumps(r))
+        return
     if args.profile_only in ("adjoint", "search"):
         ctx = K.Context(0)
         if args.launch:
@@ -682,7 +709,8 @@ def main():
     ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "kf_autotune.json"))
     ap.add_argument("--launch", default=None,
                     help="profile-only: fit launch shape block,persistent,blocks_per_cu,waves,layout")
-    ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32", "adjoint", "search", "backward"],
+    ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32", "adjoint", "search", "backward",
+                                               "planes"],
                     help="only launch the named fit --steps times (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:

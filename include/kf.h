@@ -385,6 +385,9 @@ typedef struct {
   int32_t reuse_bins;    /* 1: the caller promises the pool's contents are unchanged since the last
                             call on this context; the pool is then binned again only if its
                             pointers, sizes, layer offsets or the geometry differ.  0: always bin. */
+  int32_t overlap;       /* 1: each kept candidate picks up one detector-overlap hit per layer
+                            (needs pool_module); 0: off */
+  float overlap_bonus;   /* score of an overlap hit: + overlap_bonus - its chi2 (finite) */
 } kf_search_params;
 
 /* Combinatorial candidate search with chi2 scoring of the candidate hits
@@ -405,6 +408,17 @@ typedef struct {
  * descending, hit id ascending with a miss after every hit, parent rank
  * ascending), the first `beam` are kept (their order is their rank) and the
  * kept ones with a hit get the Kalman update (kf_update) with it.
+ * Overlap hits (params->overlap = 1; the single additional detector-overlap
+ * hit a candidate may add on a layer, Sec. 2.2, picked from overlapping
+ * modules of the layer, Sec. 3.1): right after a kept candidate's update
+ * with its hit h, the hits of the same layer on a module with a higher id
+ * than h's (pool_module; the order counts each pair of overlapping hits
+ * once) inside the window around the updated state (the window
+ * formulas above with the updated covariance) with chi2 <= chi2_max are its
+ * overlap candidates; the one with the smallest chi2 (the lower hit id among
+ * equals) is taken: a second update with it, and the candidate's score
+ * gains overlap_bonus - chi2, which counts from the next layer's ranking on
+ * (and in cand_score).
  * Seeds: seed_state[6][ld], seed_cov[21][ld], seed_charge[n], seed_layer[n]
  * (the layer each seed state is on; device).  layer_plan[plan_len] (HOST,
  * 1 <= plan_len <= 64).
@@ -412,12 +426,15 @@ typedef struct {
  * [off[l], off[l+1]), off[0] = 0, off[n_layers] = n_pool < 2^31),
  * pool_pos[3][n_pool], pool_cov[6][n_pool], pool_hit_id[n_pool] (device; the
  * ids, which must be distinct, are what the output reports and what breaks
- * ties).  The call bins the pool by (layer, phi, z) into a context-owned
+ * ties), pool_module[n_pool] (device, the detector module of each hit; may
+ * be NULL when params->overlap is 0).  The call bins the pool by (layer, phi, z) into a context-owned
  * workspace (about 64 bytes per pool hit and per candidate slot; grown on
  * demand, KF_ERR_NOMEM if that fails), unless params->reuse_bins allows the
  * bins of the previous call to be used.
  * Outputs: cand_hits[n][beam][plan_len] (hit id, -1 = miss; -2 for every
- * entry of a rank the seed has no candidate for), cand_score[n][beam]
+ * entry of a rank the seed has no candidate for), cand_overlap
+ * [n][beam][plan_len] (may be NULL: the overlap hit id of each layer, -1 for
+ * none, -2 where cand_hits has -2), cand_score[n][beam]
  * (-inf for none), cand_state[6][n*beam] (column seed*beam + rank; the final
  * state after the last update; NaN for none; may be NULL), trk_status[n]
  * (overwritten: OR of the status bits of the seed's propagations and
@@ -429,7 +446,8 @@ int kf_score_hits(kf_ctx *ctx, int64_t n, int64_t ld,
                   const kf_geometry *geom, const kf_search_params *params,
                   const int32_t *pool_layer_offsets, int64_t n_pool,
                   const float *pool_pos, const float *pool_cov, const int32_t *pool_hit_id,
-                  int32_t *cand_hits, float *cand_score, float *cand_state,
+                  const int32_t *pool_module,
+                  int32_t *cand_hits, int32_t *cand_overlap, float *cand_score, float *cand_state,
                   uint32_t *trk_status, void *stream);
 
 /* Gradient of L = sum_t w_t chi2_t of kf_fit_tracks with respect to the seed

@@ -437,10 +437,14 @@ def _overlap_step(j, h, step, L, R, pool, prm, n_p, n_C, n_q, n_score, n_hist, n
                   status, flips, state_round):
     """Step 7: the kept child j took pool hit h (layer-pool index) at this
     layer and has been updated with it.  Its overlap hit is, among the
-    layer's hits on a module other than h's that lie inside the window
-    around the updated state (step 2's formulas with the updated
+    layer's hits on a module with a higher id than h's that lie inside the
+    window around the updated state (step 2's formulas with the updated
     covariance) and have chi2 <= chi2_max against it, the one with the
-    smallest chi2 (the lower hit id among equals).  If there is one, the
+    smallest chi2 (the lower hit id among equals).  The module order counts
+    each pair of overlapping hits once: the child that took the pair's hit
+    on the lower module can add the other, the child that took the other
+    cannot add it back (two such children would carry the same two hits and,
+    to rounding, the same state and score).  If there is one, the
     child is updated with it too, its score gains overlap_bonus - chi2 and
     the hit is recorded as the step's overlap hit.  Near decisions: window
     edges and the cut as in steps 2-3 (keys "ovl-edge", "ovl-cut"), and a
@@ -453,7 +457,7 @@ def _overlap_step(j, h, step, L, R, pool, prm, n_p, n_C, n_q, n_score, n_hist, n
     hist = tuple(n_hist[j])
     cand = pool.query(phi_p, (w_r + mr) / R)
     if cand.size:
-        cand = cand[(np.abs(pool.pos[2, cand] - p[2]) <= w_z + mz) & (pool.mods[cand] != pool.mods[h])]
+        cand = cand[(np.abs(pool.pos[2, cand] - p[2]) <= w_z + mz) & (pool.mods[cand] > pool.mods[h])]
     if cand.size == 0:
         return
     darc = np.abs(_wrap(pool.phi[cand] - phi_p)) * R
@@ -513,13 +517,23 @@ def _same_hit(pool, i, j):
     return bool(np.array_equal(pool.pos[:, i], pool.pos[:, j]) and np.array_equal(pool.cov[:, i], pool.cov[:, j]))
 
 
-def _bears_on(key, target, current):
+def _bears_on(key, target, current, target_ovl=None, current_ovl=None):
     """Whether taking near decision `key` the other way could move the result
     `current` [beam, P] towards `target`: an edge or cut decision on hit h
     after history H matters when exactly one of the two results has a row
     continuing H with h; a ranking between histories A and B matters when
-    the two results do not hold the same rows starting with A and with B."""
+    the two results do not hold the same rows starting with A and with B; an
+    overlap decision at step k after history H (its hit at k included)
+    matters when the two results' rows continuing H differ in their overlap
+    hit at k (or only one has such a row)."""
     kind, step = key[0], key[1]
+    if kind.startswith("ovl"):
+        if target_ovl is None:
+            return True
+        hist = key[2]
+        n = len(hist)
+        at = lambda rows, ov: sorted(int(o[n - 1]) for r, o in zip(rows, ov) if tuple(r[:n]) == hist)
+        return at(target, target_ovl) != at(current, current_ovl)
     if kind in ("edge", "cut"):
         hist, hid = key[2], key[3]
         has = lambda rows: any(tuple(r[:step]) == hist and r[step] == hid for r in rows)
@@ -529,7 +543,7 @@ def _bears_on(key, target, current):
 
 
 def valid_alternative(hits, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams,
-                      budget=64):
+                      budget=64, overlap=None):
     """Whether the hit lists `hits` [beam, P] of one seed are one of the
     results its near decisions allow: the search is re-run with sets of its
     near decisions taken the other way, up to `budget` runs, fewest flips
@@ -537,10 +551,13 @@ def valid_alternative(hits, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom
     between its result and `hits` (_bears_on) are added to its flip set (all
     of them when none does).  A decision that bears on no difference cannot
     be the one that explains it, so this visits the runs that can reach
-    `hits` before the others.  Returns (found, runs)."""
+    `hits` before the others.  With `overlap` [beam, P] (the overlap hits of
+    the result, prm.overlap on) the overlap hits must match too.  Returns
+    (found, runs)."""
     one = lambda flips: score_hits(np.asarray(seed_p)[None], np.asarray(seed_C)[None], np.asarray([seed_q]),
                                    np.asarray([seed_layer]), layer_plan, geom, pools, prm, flips=flips)
     target = [tuple(int(x) for x in r) for r in np.asarray(hits)]
+    t_ovl = None if overlap is None else [tuple(int(x) for x in r) for r in np.asarray(overlap)]
     seen = {frozenset()}
     queue = [frozenset()]
     runs = 0
@@ -549,11 +566,12 @@ def valid_alternative(hits, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom
         f = queue.pop(0)
         o = one(f)
         runs += 1
-        if np.array_equal(o["hits"][0], hits):
+        if np.array_equal(o["hits"][0], hits) and (overlap is None or np.array_equal(o["overlap"][0], overlap)):
             return True, runs
         cur = [tuple(int(x) for x in r) for r in o["hits"][0]]
+        c_ovl = [tuple(int(x) for x in r) for r in o["overlap"][0]]
         keys = [k for k in o["near"][0] if k not in f]
-        rel = [k for k in keys if _bears_on(k, target, cur)]
+        rel = [k for k in keys if _bears_on(k, target, cur, t_ovl, c_ovl)]
         for key in (rel or keys):
             g = f | {key}
             if g not in seen:
@@ -562,7 +580,7 @@ def valid_alternative(hits, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom
     return False, runs
 
 
-def replay(row, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams):
+def replay(row, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams, ovl_row=None):
     """Follow one candidate history `row` [P] (hit ids, MISS, STOP, NO_CAND)
     of one seed through the search's steps 1-6 and report whether every one
     of its decisions is one the search can take, allowing each near decision
@@ -573,11 +591,18 @@ def replay(row, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm
     (no crossing, or no accepted hit with its misses spent).  Returns
     dict(valid, reason, score, err): the score the search gives that history
     and the root-sum-square of its FP32 term errors (RANK_SIGMAS of it is the
-    ranking margin)."""
+    ranking margin).  With prm.overlap, `ovl_row` [P] gives the overlap hit
+    of every step (MISS for none), checked by step 7's rule with the same
+    allowance: an overlap hit must be a candidate (a higher module than the
+    step's hit, inside the window up to an edge, chi2 within the cut up to
+    near) whose chi2 is not surely above another candidate's (by more than
+    the ranking margin of the two); none may be taken only when no candidate
+    is surely accepted."""
     p = torch.tensor(np.asarray(seed_p, np.float64))[None]
     C = torch.tensor(np.asarray(seed_C, np.float64))[None]
     q = torch.tensor([float(seed_q)], dtype=torch.float64)
     layer, score, errs, misses, stopped = int(seed_layer), 0.0, [], 0, False
+    last_term = 0.0   # the last step's overlap term (not in the last ranking)
     row = [int(x) for x in row]
     if row and row[0] == NO_CAND:
         return dict(valid=False, reason="no candidate", score=-math.inf, err=0.0)
@@ -637,6 +662,18 @@ def replay(row, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm
             for c_, (u, v) in enumerate(il):
                 V[0, u, v] = V[0, v, u] = float(cov[c_, sel[j]])
             p, C, q, _, _ = O.update(p2, C2, q, torch.tensor(pos[:, sel[j]][None]), V)
+            if prm.overlap:
+                mods = np.asarray(pools.module[a:b], np.int64)
+                r_ = _replay_overlap(int(ovl_row[step]) if ovl_row is not None else MISS, int(mods[sel[j]]), p, C, q,
+                                     L, R, pos, cov, ids, mods, prm)
+                if not r_["valid"]:
+                    return dict(valid=False, reason="%s at step %d" % (r_["reason"], step), score=score, err=0.0)
+                if r_["taken"]:
+                    p, C, q = r_["p"], r_["C"], r_["q"]
+                    score += prm.overlap_bonus - r_["chi2"]
+                    errs[-1] = math.hypot(errs[-1], r_["err"])
+                    if step == len(layer_plan) - 1:
+                        last_term = prm.overlap_bonus - r_["chi2"]
         elif hid == MISS:
             if surely_acc.any():
                 return dict(valid=False, reason="miss at step %d with an accepted hit" % step, score=score, err=0.0)
@@ -654,11 +691,52 @@ def replay(row, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm
         else:
             return dict(valid=False, reason="no candidate at step %d" % step, score=score, err=0.0)
         layer = L
-    return dict(valid=True, reason="", score=score, err=math.sqrt(sum(e * e for e in errs)))
+    return dict(valid=True, reason="", score=score, err=math.sqrt(sum(e * e for e in errs)),
+                rank_score=score - last_term)
+
+
+def _replay_overlap(oid, mod_h, p, C, q, L, R, pos, cov, ids, mods, prm):
+    """Step 7 for replay: whether overlap hit `oid` (MISS: none) is one the
+    step can take after the update (p, C, q) with a hit on module mod_h."""
+    pp, Cp = p[0].numpy(), C[0].numpy()
+    phi_p, w_r, w_z, epos, sig = _window(pp, Cp, L, R, prm)
+    mr, mz = EDGE_REL * w_r + epos, EDGE_REL * w_z + epos
+    darc = np.abs(_wrap(np.arctan2(pos[1], pos[0]) - phi_p)) * R
+    dz = np.abs(pos[2] - pp[2])
+    maybe = np.nonzero((darc <= w_r + mr) & (dz <= w_z + mz) & (mods > mod_h))[0]
+    surely_in = (darc[maybe] <= w_r - mr) & (dz[maybe] <= w_z - mz)
+    if maybe.size:
+        chi2, kap = _chi2(pp[:3], Cp[:3, :3], pos[:, maybe].T, cov[:, maybe])
+    else:
+        chi2, kap = np.zeros(0), np.zeros(0)
+    cerr = np.array([chi2_error(prm.chi2_max, epos, sig, k_) for k_ in kap])
+    terr = np.array([chi2_error(float(c_), epos, sig, float(k_)) for c_, k_ in zip(chi2, kap)])
+    maybe_acc = chi2 <= prm.chi2_max + cerr
+    surely_acc = surely_in & (chi2 < prm.chi2_max - cerr)
+    if oid == MISS:
+        if surely_acc.any():
+            return dict(valid=False, reason="no overlap hit with one surely accepted", taken=False)
+        return dict(valid=True, taken=False)
+    j = np.nonzero(ids[maybe] == oid)[0]
+    if j.size == 0:
+        return dict(valid=False, reason="overlap hit %d not a candidate" % oid, taken=False)
+    j = int(j[0])
+    if not maybe_acc[j]:
+        return dict(valid=False, reason="overlap hit %d above the cut" % oid, taken=False)
+    for k in np.nonzero(surely_acc)[0]:
+        if chi2[k] < chi2[j] - RANK_SIGMAS * math.hypot(terr[k], terr[j]):
+            return dict(valid=False, reason="overlap hit %d surely worse than %d" % (oid, int(ids[maybe][k])),
+                        taken=False)
+    il = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
+    V = torch.zeros(1, 3, 3, dtype=torch.float64)
+    for c_, (u, v) in enumerate(il):
+        V[0, u, v] = V[0, v, u] = float(cov[c_, maybe[j]])
+    p2, C2, q2, _, _ = O.update(p, C, q, torch.tensor(pos[:, maybe[j]][None]), V)
+    return dict(valid=True, taken=True, p=p2, C=C2, q=q2, chi2=float(chi2[j]), err=float(terr[j]))
 
 
 def consistent_result(hits, scores, seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm: SearchParams,
-                      oracle_hits, oracle_scores, oracle_err):
+                      oracle_hits, oracle_scores, oracle_err, overlap=None, oracle_overlap=None):
     """Whether one seed's lists `hits` [beam, P] with their `scores` [beam]
     are a result the search can give when its near decisions and its
     rankings are resolved within the FP32 error model, against the oracle's
@@ -672,24 +750,36 @@ def consistent_result(hits, scores, seed_p, seed_C, seed_q, seed_layer, layer_pl
       `hits` missing from the oracle's scores no less than the oracle's
       lowest kept list minus that margin: within the error model either
       could take the other's place.
+    With prm.overlap, a list is its hits and overlap hits together
+    (`overlap`, `oracle_overlap` [beam, P]).
     Returns (ok, reason)."""
-    rows = [tuple(int(x) for x in r) for r in np.asarray(hits)]
+    if overlap is not None:
+        rows = [tuple(int(x) for x in r) + tuple(int(x) for x in o) for r, o in zip(np.asarray(hits), overlap)]
+        orows_ = [tuple(int(x) for x in r) + tuple(int(x) for x in o)
+                  for r, o in zip(np.asarray(oracle_hits), oracle_overlap)]
+    else:
+        rows = [tuple(int(x) for x in r) for r in np.asarray(hits)]
+        orows_ = None
+    P_ = np.asarray(hits).shape[1]
     live = [i for i, r in enumerate(rows) if r[0] != NO_CAND]
     if len(set(rows[i] for i in live)) != len(live):
         return False, "duplicate lists"
     rep = {}
     for i in live:
-        r = replay(rows[i], seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm)
+        r = replay(rows[i][:P_], seed_p, seed_C, seed_q, seed_layer, layer_plan, geom, pools, prm,
+                   ovl_row=rows[i][P_:] if overlap is not None else None)
         if not r["valid"]:
             return False, "list %d: %s" % (i, r["reason"])
         if abs(float(scores[i]) - r["score"]) > 1e-3 + RANK_SIGMAS * r["err"]:
             return False, "list %d: score %.6f against %.6f +- %.3g" % (i, float(scores[i]), r["score"], r["err"])
         rep[rows[i]] = r
     for a, b in zip(live[:-1], live[1:]):
+        # the order of the last ranking (its scores hold no overlap term of
+        # the last layer)
         m = 1e-3 + RANK_SIGMAS * math.hypot(rep[rows[a]]["err"], rep[rows[b]]["err"])
-        if float(scores[a]) < float(scores[b]) - m:
+        if rep[rows[a]]["rank_score"] < rep[rows[b]]["rank_score"] - m:
             return False, "lists %d and %d out of score order" % (a, b)
-    orows = [tuple(int(x) for x in r) for r in np.asarray(oracle_hits)]
+    orows = orows_ if orows_ is not None else [tuple(int(x) for x in r) for r in np.asarray(oracle_hits)]
     olive = [i for i, r in enumerate(orows) if r[0] != NO_CAND]
     if len(olive) != len(live):
         return False, "%d lists against the oracle's %d" % (len(live), len(olive))

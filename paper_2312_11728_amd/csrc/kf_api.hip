@@ -825,7 +825,8 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
                   const int8_t* seed_charge, const int16_t* seed_layer, const int16_t* layer_plan, int32_t plan_len,
                   const kf_geometry* geom, const kf_search_params* prm, const int32_t* pool_layer_offsets,
                   int64_t n_pool, const float* pool_pos, const float* pool_cov, const int32_t* pool_hit_id,
-                  int32_t* cand_hits, float* cand_score, float* cand_state, uint32_t* trk_status, void* stream) {
+                  const int32_t* pool_module, int32_t* cand_hits, int32_t* cand_overlap, float* cand_score,
+                  float* cand_state, uint32_t* trk_status, void* stream) {
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
   KF_TRY(check_geometry(geom, &g));
@@ -837,6 +838,8 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   if (!(prm->miss_penalty >= 0.f) || !std::isfinite(prm->miss_penalty)) return fail(KF_ERR_ARG, "miss_penalty must be >= 0");
   if (prm->max_miss < 0 || prm->max_miss > 100) return fail(KF_ERR_ARG, "max_miss = %d outside [0, 100]", prm->max_miss);
   if (!(prm->sigma_rphi >= 0.f) || !(prm->sigma_z >= 0.f)) return fail(KF_ERR_ARG, "sigma_rphi / sigma_z must be >= 0");
+  if (prm->overlap != 0 && prm->overlap != 1) return fail(KF_ERR_ARG, "overlap = %d (0 off, 1 on)", prm->overlap);
+  if (prm->overlap && !std::isfinite(prm->overlap_bonus)) return fail(KF_ERR_ARG, "overlap_bonus must be finite");
   KF_REQUIRE(prm->win_min_rphi);
   KF_REQUIRE(prm->win_max_rphi);
   KF_REQUIRE(prm->win_min_z);
@@ -874,6 +877,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
     KF_REQUIRE(pool_pos);
     KF_REQUIRE(pool_cov);
     KF_REQUIRE(pool_hit_id);
+    if (prm->overlap) KF_REQUIRE(pool_module);
   }
   // bins of every layer
   kf::BinTable t;
@@ -904,7 +908,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   const int64_t b_bins = up(n_bins * 4), b_pool4 = up(n_pool * 4), b_sum = up(nsum * 4) + 256;
   const int64_t b_pool = up(n_pool * int64_t(sizeof(kf::PoolHit))) + up((n_bins + 1) * 4);
   const int64_t b_slot = 2 * (up(S * 6 * 4) + up(S * 21 * 4) + up(S)) + 3 * up(S * kf::kMaxBeam * 4) + up(S * 4) +
-                         up(S) + up(S) + up(S * 4) + up(S * 4) + up(S) + up(P * S) + up(P * S * 4);
+                         up(S) + up(S) + up(S * 4) + up(S * 4) + up(S) + up(P * S) + 2 * up(P * S * 4);
   const int64_t total = b_bins + 2 * b_pool4 + b_sum + b_pool + b_slot;
   if (size_t(total) > ctx->search_bytes) {
     int prev = 0;
@@ -923,10 +927,11 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
     ctx->search_bytes = size_t(total);
   }
   // identity of the binned pool: pointers, sizes, layer offsets, bin table
-  std::vector<unsigned char> key(3 * sizeof(void*) + sizeof(n_pool) + sizeof(t));
+  const int32_t* module = prm->overlap ? pool_module : nullptr;
+  std::vector<unsigned char> key(4 * sizeof(void*) + sizeof(n_pool) + sizeof(t));
   {
     unsigned char* k = key.data();
-    const void* ptrs[3] = {pool_pos, pool_cov, pool_hit_id};
+    const void* ptrs[4] = {pool_pos, pool_cov, pool_hit_id, module};
     std::memcpy(k, ptrs, sizeof(ptrs));
     std::memcpy(k + sizeof(ptrs), &n_pool, sizeof(n_pool));
     std::memcpy(k + sizeof(ptrs) + sizeof(n_pool), &t, sizeof(t));
@@ -982,6 +987,10 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   a.sel_miss = (int8_t*)take(up(S));
   a.hist_parent = (int8_t*)take(up(P * S));
   a.hist_id = (int32_t*)take(up(P * S * 4));
+  a.hist_ovl = (int32_t*)take(up(P * S * 4));
+  a.overlap = prm->overlap;
+  a.overlap_bonus = prm->overlap_bonus;
+  a.cand_ovl = cand_overlap;
   a.status = trk_status;
   a.cand_hits = cand_hits;
   a.cand_score = cand_score;
@@ -1010,7 +1019,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   hipError_t e = hipSuccess;
   if (rebin) {
     ctx->bins_key.clear();
-    e = kf::launch_bin_pool(t, pool_pos, pool_cov, pool_hit_id, n_pool, n_bins, w, s);
+    e = kf::launch_bin_pool(t, pool_pos, pool_cov, pool_hit_id, module, n_pool, n_bins, w, s);
     if (e == hipSuccess) ctx->bins_key = key;
   }
   if (e == hipSuccess) e = kf::launch_search(a, layers.data(), plan_len, s);

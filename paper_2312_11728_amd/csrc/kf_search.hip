@@ -106,11 +106,12 @@ __global__ void __launch_bounds__(256) scan_add_kernel(int32_t* out, int64_t n, 
   if (i == n) out[n] = total[0];
 }
 
-// copy every hit to its binned position (x, y, z, phi, covariance, id: three
-// 16-byte stores)
+// copy every hit to its binned position (x, y, z, phi, covariance, id,
+// module: three 16-byte stores)
 __global__ void __launch_bounds__(256) bin_scatter_kernel(BinTable t, const float* pos, const float* cov,
-                                                          const int32_t* id, int64_t n, const int32_t* bin_off,
-                                                          const int32_t* bin_of, const int32_t* rank, PoolBins o) {
+                                                          const int32_t* id, const int32_t* module, int64_t n,
+                                                          const int32_t* bin_off, const int32_t* bin_of,
+                                                          const int32_t* rank, PoolBins o) {
   const int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (h >= n) return;
   const int64_t d = int64_t(bin_off[bin_of[h]]) + rank[h];
@@ -118,15 +119,15 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(BinTable t, const floa
   float4* dst = reinterpret_cast<float4*>(o.hits + d);
   dst[0] = make_float4(x, y, pos[2 * n + h], atan2f(y, x));
   dst[1] = make_float4(cov[h], cov[n + h], cov[2 * n + h], cov[3 * n + h]);
-  dst[2] = make_float4(cov[4 * n + h], cov[5 * n + h], __int_as_float(id[h]), 0.f);
+  dst[2] = make_float4(cov[4 * n + h], cov[5 * n + h], __int_as_float(id[h]), __int_as_float(module ? module[h] : -1));
 }
 
 // ---- search ------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) extend_kernel(SearchArgs a, SearchLayer L) {
+__global__ void __launch_bounds__(256) extend_kernel(SearchArgs a, SearchLayer L, SearchLayer Lp) {
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= a.n * a.beam) return;
-  const uint32_t st = extend_slot(a, L, s);
+  const uint32_t st = extend_slot(a, L, Lp, s);
   if (st) atomicOr(&a.status[s / a.beam], st);
 }
 
@@ -136,17 +137,17 @@ __global__ void __launch_bounds__(256) select_kernel(SearchArgs a) {
   select_seed(a, t);
 }
 
-__global__ void __launch_bounds__(256) finish_kernel(SearchArgs a) {
+__global__ void __launch_bounds__(256) finish_kernel(SearchArgs a, SearchLayer Llast) {
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s >= a.n * a.beam) return;
-  const uint32_t st = finish_slot(a, s);
+  const uint32_t st = finish_slot(a, Llast, s);
   if (st) atomicOr(&a.status[s / a.beam], st);
 }
 
 static unsigned blocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
-hipError_t launch_bin_pool(const BinTable& t, const float* pos, const float* cov, const int32_t* id, int64_t n,
-                           int64_t n_bins, const SearchWork& w, hipStream_t s) {
+hipError_t launch_bin_pool(const BinTable& t, const float* pos, const float* cov, const int32_t* id,
+                           const int32_t* module, int64_t n, int64_t n_bins, const SearchWork& w, hipStream_t s) {
   hipLaunchKernelGGL(fill_i32_kernel, dim3(1024), dim3(256), 0, s, w.count, n_bins, 0);
   if (n > 0)
     hipLaunchKernelGGL(bin_count_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, t, pos, n, w.count, w.bin_of,
@@ -158,7 +159,7 @@ hipError_t launch_bin_pool(const BinTable& t, const float* pos, const float* cov
   hipLaunchKernelGGL(scan_add_kernel, dim3(blocks(n_bins + 1, 256)), dim3(256), 0, s, w.pool.bin_off, n_bins,
                      w.block_sum, w.total);
   if (n > 0)
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, t, pos, cov, id, n,
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, t, pos, cov, id, module, n,
                        w.pool.bin_off, w.bin_of, w.rank, w.pool);
   return hipGetLastError();
 }
@@ -168,10 +169,10 @@ hipError_t launch_search(SearchArgs a, const SearchLayer* layers, int plan_len, 
   hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks(a.n, 256)), dim3(256), 0, s, (int32_t*)a.status, a.n, 0);
   for (int k = 0; k < plan_len; ++k) {
     a.step = k;
-    hipLaunchKernelGGL(extend_kernel, dim3(blocks(S, 256)), dim3(256), 0, s, a, layers[k]);
+    hipLaunchKernelGGL(extend_kernel, dim3(blocks(S, 256)), dim3(256), 0, s, a, layers[k], layers[k > 0 ? k - 1 : 0]);
     hipLaunchKernelGGL(select_kernel, dim3(blocks(a.n, 256)), dim3(256), 0, s, a);
   }
-  hipLaunchKernelGGL(finish_kernel, dim3(blocks(S, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(finish_kernel, dim3(blocks(S, 256)), dim3(256), 0, s, a, layers[plan_len - 1]);
   return hipGetLastError();
 }
 

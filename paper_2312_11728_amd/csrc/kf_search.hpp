@@ -12,7 +12,13 @@
 //     within its miss budget -- keeps its score and the state it entered the
 //     layer with, and from then on is carried from layer to layer unchanged);
 //   select (one thread per seed): merge the slots' sorted child lists into
-//     the seed's best `beam` children, which become the next layer's slots.
+//     the seed's best `beam` children, which become the next layer's slots;
+//   overlap (with the overlap step on; at the next layer's extend, or in the
+//     final pass): right after a kept child's update with its hit, the best
+//     hit of a higher-numbered module of the same layer inside the window
+//     around the updated state (smallest chi2 <= chi2_max, lower id first)
+//     is taken as its overlap hit -- a second update, and a score term
+//     overlap_bonus - chi2 that counts from the next ranking on.
 // Children are ranked by (score descending; hit id ascending, a miss after
 // every hit and a stop after a miss; parent rank ascending) -- a total order,
 // so the result does not depend on the order in which hits are visited.
@@ -66,7 +72,7 @@ struct alignas(16) PoolHit {
   float x, y, z, phi;
   float cov[6];
   int32_t id;
-  int32_t pad;
+  int32_t module;   // detector module (-1 if the caller gave none)
 };
 
 // Scalars of the layer being searched (one launch per layer).
@@ -112,6 +118,11 @@ struct SearchArgs {
   int32_t* cand_hits;            // [n][beam][plan_len]
   float* cand_score;             // [n][beam]
   float* cand_state;             // [6][S] or null
+  // overlap step
+  int32_t overlap;               // 0 off, 1 on
+  float overlap_bonus;
+  int32_t* hist_ovl;             // [plan_len][S] overlap hit id of the slot's candidate, -1 none
+  int32_t* cand_ovl;             // [n][beam][plan_len] or null
 };
 
 // a better than b in the ranking of children
@@ -155,9 +166,75 @@ KF_HD inline float hit_chi2(const float p[6], const float c[21], const float m[3
   return acc;
 }
 
+// The overlap step for a candidate that took binned pool hit h on layer L
+// and has just been updated with it (p, c, q): among the hits of L on a
+// module with a higher id than h's inside the window around the updated
+// state (the extend step's window formulas with the updated covariance), the
+// one with the smallest chi2 <= chi2_max (the lower id among equals).  The
+// module order counts each pair of overlapping hits once.  If there is
+// one, the state gets a second update with it and its id is returned with
+// its chi2 in c2_out; else -1.
+KF_HD inline int32_t pick_overlap(const SearchArgs& a, const SearchLayer& L, int32_t h, float p[6], float c[21],
+                                  int& q, float& c2_out, uint32_t& st) {
+  const int32_t mod = a.pool[h].module;
+  const float phi_p = k_atan2(p[1], p[0]);
+  const float ir = 1.f / k_sqrt(p[0] * p[0] + p[1] * p[1]);
+  const float sp = p[1] * ir, cp = p[0] * ir;
+  const float var_r = sp * sp * c[sym(0, 0)] - 2.f * sp * cp * c[sym(1, 0)] + cp * cp * c[sym(1, 1)];
+  float w_r = a.n_sigma * k_sqrt(var_r + L.sig_r * L.sig_r);
+  w_r = w_r < L.wmin_r ? L.wmin_r : (w_r > L.wmax_r ? L.wmax_r : w_r);
+  float w_z = a.n_sigma * k_sqrt(c[sym(2, 2)] + L.sig_z * L.sig_z);
+  w_z = w_z < L.wmin_z ? L.wmin_z : (w_z > L.wmax_z ? L.wmax_z : w_z);
+  const float dphi = w_r / L.R;
+  const float zp = p[2];
+  const float bw = float(L.nphi) * float(0.5 / kPi);
+  const float fb0 = k_floor((phi_p - dphi - 1e-5f + float(kPi)) * bw);
+  const float fb1 = k_floor((phi_p + dphi + 1e-5f + float(kPi)) * bw);
+  int32_t best = -1, best_id = 0;
+  float best_c2 = 0.f;
+  if (fb0 >= -float(L.nphi) && fb1 <= 2.f * float(L.nphi) && fb1 >= fb0 && k_finite(zp) && k_finite(w_z)) {
+    int32_t b0 = int32_t(fb0), b1 = int32_t(fb1);
+    if (b1 - b0 + 1 > L.nphi) {
+      b0 = 0;
+      b1 = L.nphi - 1;
+    }
+    const int32_t z0 = z_bin(zp - w_z - 1e-4f, L.lo, L.hi, L.nz);
+    const int32_t z1 = z_bin(zp + w_z + 1e-4f, L.lo, L.hi, L.nz);
+    for (int32_t b = b0; b <= b1; ++b) {
+      const int32_t pb = b < 0 ? b + L.nphi : (b >= L.nphi ? b - L.nphi : b);
+      const int32_t h0 = a.bin_off[L.base + pb * L.nz + z0];
+      const int32_t h1 = a.bin_off[L.base + pb * L.nz + z1 + 1];
+      for (int32_t k = h0; k < h1; ++k) {
+        const PoolHit ph = a.pool[k];
+        if (ph.module <= mod) continue;
+        float d = ph.phi - phi_p;
+        d = d > float(kPi) ? d - float(2 * kPi) : (d < -float(kPi) ? d + float(2 * kPi) : d);
+        if (!(k_abs(d) <= dphi) || !(k_abs(ph.z - zp) <= w_z)) continue;
+        const float m[3] = {ph.x, ph.y, ph.z};
+        float V[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) V[i] = ph.cov[i];
+        const float c2 = hit_chi2(p, c, m, V, st);
+        if (!(c2 <= a.chi2_max)) continue;
+        if (best < 0 || c2 < best_c2 || (c2 == best_c2 && ph.id < best_id)) {
+          best = k;
+          best_id = ph.id;
+          best_c2 = c2;
+        }
+      }
+    }
+  }
+  if (best < 0) return -1;
+  float m[3], V[6], c2u;
+  load_pool_hit(a, best, m, V);
+  update(p, c, q, m, V, c2u, st);
+  c2_out = best_c2;
+  return best_id;
+}
+
 // Extend the candidate of slot s (see the file comment).  Returns the status
 // bits of its steps.
-KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, int64_t s) {
+KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, const SearchLayer& Lp, int64_t s) {
   const int64_t S = a.n * a.beam;
   const int64_t seed = s / a.beam;
   const int r = int(s % a.beam);
@@ -184,13 +261,20 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, int
     if (par < 0) return 0;
     load_slot(a.pred_p[prv], a.pred_c[prv], a.pred_q[prv], S, seed * a.beam + par, p, c, q);
     const int32_t h = a.sel_idx[s];
+    float ovl = 0.f;
     if (h >= 0) {
       float m[3], V[6], c2;
       load_pool_hit(a, h, m, V);
       update(p, c, q, m, V, c2, st);
+      if (a.overlap) {
+        float oc2 = 0.f;
+        const int32_t oid = pick_overlap(a, Lp, h, p, c, q, oc2, st);
+        a.hist_ovl[int64_t(a.step - 1) * S + s] = oid;
+        if (oid >= 0) ovl = a.overlap_bonus - oc2;
+      }
     }
     prev = L.prev_layer;
-    score = a.sel_score[s];
+    score = a.sel_score[s] + ovl;
     miss = a.sel_miss[s];
     stopped = h == kStopIdx;   // carried unchanged
   }
@@ -407,12 +491,13 @@ KF_HD inline void select_seed(const SearchArgs& a, int64_t t) {
     a.sel_miss[so] = int8_t(a.cur_miss[s0 + best] + (idx == kMissIdx ? 1 : 0));
     a.hist_parent[int64_t(a.step) * S + so] = int8_t(best);
     a.hist_id[int64_t(a.step) * S + so] = idx >= 0 ? o_key[out] : idx;
+    if (a.overlap) a.hist_ovl[int64_t(a.step) * S + so] = kMissIdx;
   }
 }
 
 // After the last layer: the kept candidates' final states (update with their
 // last hit), scores and hit lists (backtracked through the parents).
-KF_HD inline uint32_t finish_slot(const SearchArgs& a, int64_t s) {
+KF_HD inline uint32_t finish_slot(const SearchArgs& a, const SearchLayer& Llast, int64_t s) {
   const int64_t S = a.n * a.beam;
   const int64_t seed = s / a.beam;
   const int r = int(s % a.beam);
@@ -420,8 +505,11 @@ KF_HD inline uint32_t finish_slot(const SearchArgs& a, int64_t s) {
   int32_t* out = a.cand_hits + s * P;
   const int par = a.sel_parent[s];
   uint32_t st = 0;
+  int32_t* ovl_out = a.cand_ovl ? a.cand_ovl + s * P : nullptr;
   if (par < 0) {
     for (int k = 0; k < P; ++k) out[k] = -2;
+    if (ovl_out)
+      for (int k = 0; k < P; ++k) ovl_out[k] = -2;
     a.cand_score[s] = -k_inf<float>();
     if (a.cand_state)
 #pragma unroll
@@ -434,20 +522,28 @@ KF_HD inline uint32_t finish_slot(const SearchArgs& a, int64_t s) {
     int q;
     load_slot(a.pred_p[last], a.pred_c[last], a.pred_q[last], S, seed * a.beam + par, p, c, q);
     const int32_t h = a.sel_idx[s];
+    float ovl = 0.f;
     if (h >= 0) {
       float m[3], V[6], c2;
       load_pool_hit(a, h, m, V);
       update(p, c, q, m, V, c2, st);
+      if (a.overlap) {
+        float oc2 = 0.f;
+        const int32_t oid = pick_overlap(a, Llast, h, p, c, q, oc2, st);
+        a.hist_ovl[int64_t(P - 1) * S + s] = oid;
+        if (oid >= 0) ovl = a.overlap_bonus - oc2;
+      }
     }
     if (a.cand_state)
 #pragma unroll
       for (int i = 0; i < 6; ++i) a.cand_state[i * S + s] = p[i];
+    a.cand_score[s] = a.sel_score[s] + ovl;
   }
-  a.cand_score[s] = a.sel_score[s];
   int rr = r;
   for (int k = P - 1; k >= 0; --k) {
     const int64_t hs = int64_t(k) * S + seed * a.beam + rr;
     out[k] = a.hist_id[hs];
+    if (ovl_out) ovl_out[k] = a.overlap ? a.hist_ovl[hs] : kMissIdx;
     rr = a.hist_parent[hs];
   }
   return st;

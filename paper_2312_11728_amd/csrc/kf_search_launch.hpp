@@ -23,8 +23,8 @@ struct SearchWork {
   PoolBins pool;
 };
 
-hipError_t launch_bin_pool(const BinTable& t, const float* pos, const float* cov, const int32_t* id, int64_t n,
-                           int64_t n_bins, const SearchWork& w, hipStream_t s);
+hipError_t launch_bin_pool(const BinTable& t, const float* pos, const float* cov, const int32_t* id,
+                           const int32_t* module, int64_t n, int64_t n_bins, const SearchWork& w, hipStream_t s);
 hipError_t launch_search(SearchArgs a, const SearchLayer* layers, int plan_len, hipStream_t s);
 
 }  // namespace kf

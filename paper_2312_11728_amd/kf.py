@@ -56,7 +56,7 @@ class KfSearchParams(ctypes.Structure):
                 ("hit_bonus", ctypes.c_float), ("miss_penalty", ctypes.c_float), ("max_miss", ctypes.c_int32),
                 ("sigma_rphi", ctypes.c_float), ("sigma_z", ctypes.c_float),
                 ("win_min_rphi", _vp), ("win_max_rphi", _vp), ("win_min_z", _vp), ("win_max_z", _vp),
-                ("reuse_bins", ctypes.c_int32)]
+                ("reuse_bins", ctypes.c_int32), ("overlap", ctypes.c_int32), ("overlap_bonus", ctypes.c_float)]
 
 
 class SearchParams:
@@ -65,7 +65,7 @@ class SearchParams:
 
     def __init__(self, n_layers, beam=6, chi2_max=30.0, n_sigma=5.0, hit_bonus=10.0, miss_penalty=5.0, max_miss=3,
                  sigma_rphi=0.003, sigma_z=0.01, win_min_rphi=0.01, win_max_rphi=2.0, win_min_z=0.03, win_max_z=2.0,
-                 reuse_bins=False):
+                 reuse_bins=False, overlap=False, overlap_bonus=5.0):
         self.n_layers = n_layers
         self.beam, self.chi2_max, self.n_sigma = beam, chi2_max, n_sigma
         self.hit_bonus, self.miss_penalty, self.max_miss = hit_bonus, miss_penalty, max_miss
@@ -74,9 +74,10 @@ class SearchParams:
         self.win_min_rphi, self.win_max_rphi = f(win_min_rphi), f(win_max_rphi)
         self.win_min_z, self.win_max_z = f(win_min_z), f(win_max_z)
         p = lambda a: a.ctypes.data_as(_vp)
+        self.overlap, self.overlap_bonus = bool(overlap), overlap_bonus
         self.struct = KfSearchParams(beam, chi2_max, n_sigma, hit_bonus, miss_penalty, max_miss, sigma_rphi, sigma_z,
                                      p(self.win_min_rphi), p(self.win_max_rphi), p(self.win_min_z),
-                                     p(self.win_max_z), int(bool(reuse_bins)))
+                                     p(self.win_max_z), int(bool(reuse_bins)), int(bool(overlap)), overlap_bonus)
 
 
 class KfError(RuntimeError):
@@ -113,7 +114,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                      _vp, ctypes.POINTER(KfGeometry), _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                      _vp, _vp]
     lib.kf_score_hits.argtypes = [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(KfGeometry),
-                                  ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+                                  ctypes.POINTER(KfSearchParams), _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  _vp, _vp]
     lib.kf_fit_adjoint.argtypes = [_vp, ctypes.c_int, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp,
                                    ctypes.POINTER(KfGeometry), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.kf_fit_adjoint_noalloc.argtypes = lib.kf_fit_adjoint.argtypes
@@ -668,11 +670,14 @@ class Context:
         return out
 
     def score_hits(self, seed_state, seed_cov, seed_charge, seed_layer, layer_plan, geom: Geometry,
-                   params: SearchParams, pool_layer_offsets, pool_pos, pool_cov, pool_hit_id, want_state=True):
+                   params: SearchParams, pool_layer_offsets, pool_pos, pool_cov, pool_hit_id, want_state=True,
+                   pool_module=None, want_overlap=False):
         """Combinatorial candidate search (kf_score_hits, FP32).  layer_plan and
-        pool_layer_offsets are host sequences; the rest device tensors.
+        pool_layer_offsets are host sequences; the rest device tensors
+        (pool_module: int32 [n_pool], needed with params.overlap).
         Returns (hits [n, beam, plan_len] int32, score [n, beam], state
-        [6, n * beam] or None, status [n])."""
+        [6, n * beam] or None, status [n]), and with want_overlap the overlap
+        hits [n, beam, plan_len] int32 as a fifth element."""
         dev = self.device
         n = seed_state.shape[1]
         _need(seed_state, "seed_state", torch.float32, dev, rows=6)
@@ -682,6 +687,10 @@ class Context:
         _need(pool_pos, "pool_pos", torch.float32, dev, rows=3)
         _need(pool_cov, "pool_cov", torch.float32, dev, rows=6)
         _need(pool_hit_id, "pool_hit_id", torch.int32, dev)
+        if pool_module is not None:
+            _need(pool_module, "pool_module", torch.int32, dev)
+            if pool_module.numel() != pool_hit_id.numel():
+                raise ValueError("pool_module must hold one module id per pool hit")
         plan = np.ascontiguousarray(np.asarray(layer_plan, np.int16))
         off = np.ascontiguousarray(np.asarray(pool_layer_offsets, np.int32))
         B, P = params.beam, plan.shape[0]
@@ -689,12 +698,14 @@ class Context:
         score = torch.empty(n, B, dtype=torch.float32, device=dev)
         state = torch.empty(6, n * B, dtype=torch.float32, device=dev) if want_state else None
         status = torch.empty(n, dtype=torch.int32, device=dev)
+        ovl = torch.empty(n, B, P, dtype=torch.int32, device=dev) if want_overlap else None
         _check(lib().kf_score_hits(self.handle, n, seed_state.stride(0), _ptr(seed_state), _ptr(seed_cov),
                                    _ptr(seed_charge), _ptr(seed_layer), plan.ctypes.data_as(_vp), P,
                                    ctypes.byref(geom.struct), ctypes.byref(params.struct), off.ctypes.data_as(_vp),
-                                   pool_pos.shape[1], _ptr(pool_pos), _ptr(pool_cov), _ptr(pool_hit_id), _ptr(hits),
-                                   _ptr(score), _ptr(state), _ptr(status), _stream(dev)))
-        return hits, score, state, status
+                                   pool_pos.shape[1], _ptr(pool_pos), _ptr(pool_cov), _ptr(pool_hit_id),
+                                   _ptr(pool_module), _ptr(hits), _ptr(ovl), _ptr(score), _ptr(state), _ptr(status),
+                                   _stream(dev)))
+        return (hits, score, state, status, ovl) if want_overlap else (hits, score, state, status)
 
     def fit_adjoint(self, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid, hit_pos, hit_cov,
                     geom: Geometry, checkpoints, seg, max_len, fwd_status, align=None, dL_dchi2=None,

@@ -10,7 +10,7 @@ import torch
 
 from oracle import kf_oracle as O
 from oracle.kf_search import SearchParams
-from toygen import generate, truncate, workloads
+from toygen import generate, truncate, with_modules, workloads
 from toygen.generate import make_pools
 
 PLAN = list(range(3, 20))
@@ -44,3 +44,13 @@ def search_inputs(n=None, noise=True):
 
 def default_params(g, beam=6):
     return SearchParams(g.n_layers, beam=beam)
+
+
+def module_inputs(n=None, noise=True):
+    """search_inputs with the pools split into detector modules with overlap
+    hits (toygen.with_modules), FP32-representable."""
+    wl, ev, g, pools, p, C, q = search_inputs(n, noise)
+    P = with_modules(wl, ev, pools)
+    P.pos = f32(P.pos)
+    P.cov = f32(P.cov)
+    return wl, ev, g, P, p, C, q

@@ -160,8 +160,8 @@ def _search_call(**over):
     args = dict(ctx=P, n=10, ld=10, seed_state=P, seed_cov=P, seed_charge=P, seed_layer=P,
                 layer_plan=ctypes.cast(plan, ctypes.c_void_p), plan_len=2, geom=ctypes.byref(g.struct),
                 params=ctypes.byref(prm), pool_layer_offsets=ctypes.cast(off, ctypes.c_void_p), n_pool=10,
-                pool_pos=P, pool_cov=P, pool_hit_id=P, cand_hits=P, cand_score=P, cand_state=None, trk_status=P,
-                stream=None)
+                pool_pos=P, pool_cov=P, pool_hit_id=P, pool_module=None, cand_hits=P, cand_overlap=None,
+                cand_score=P, cand_state=None, trk_status=P, stream=None)
     args.update(over)
     return kf.lib().kf_score_hits(*args.values())
 
@@ -176,6 +176,9 @@ def _search_call(**over):
     (dict(seed_layer=None), "seed_layer is NULL"),
     (dict(cand_hits=None), "cand_hits is NULL"),
     (dict(n=-2), "n = -2"),
+    (dict(prm_overlap=2), "overlap = 2"),
+    (dict(prm_overlap=1, prm_overlap_bonus=float("nan")), "overlap_bonus"),
+    (dict(prm_overlap=1, prm_overlap_bonus=5.0), "pool_module is NULL"),
 ])
 def test_score_hits_argument_validation(over, msg):
     assert _search_call(**over) == kf.KF_ERR_ARG

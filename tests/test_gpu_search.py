@@ -47,7 +47,8 @@ def ctx(kf):
     c.close()
 
 
-def gpu_search(ctx, kf, g, pools, p, C, q, plan=PLAN, beam=6, seeds=None, reuse=False, dev_pool=None):
+def gpu_search(ctx, kf, g, pools, p, C, q, plan=PLAN, beam=6, seeds=None, reuse=False, dev_pool=None,
+               overlap=False):
     dev = ctx.device
     idx = np.arange(p.shape[0]) if seeds is None else np.asarray(seeds)
     f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(dt).contiguous()
@@ -55,14 +56,17 @@ def gpu_search(ctx, kf, g, pools, p, C, q, plan=PLAN, beam=6, seeds=None, reuse=
     cv = f(np.stack([C[idx][:, i, j] for i, j in IL]), torch.float32)
     qq = f(q[idx], torch.int8)
     sl = f(np.full(idx.size, SEED_LAYER), torch.int16)
-    prm = kf.SearchParams(g.n_layers, beam=beam, reuse_bins=reuse)
+    prm = kf.SearchParams(g.n_layers, beam=beam, reuse_bins=reuse, overlap=overlap)
     geom = kf.Geometry.from_toy(g)
     if dev_pool is None:
         dev_pool = (f(pools.pos, torch.float32), f(pools.cov, torch.float32), f(pools.hit_id, torch.int32))
-    hits, score, state, status = ctx.score_hits(st, cv, qq, sl, plan, geom, prm, pools.layer_offsets, *dev_pool)
+    mod = f(pools.module, torch.int32) if overlap else None
+    hits, score, state, status, ovl = ctx.score_hits(st, cv, qq, sl, plan, geom, prm, pools.layer_offsets, *dev_pool,
+                                                     pool_module=mod, want_overlap=True)
     torch.cuda.synchronize()
     return dict(hits=hits.cpu().numpy().astype(np.int64), score=score.cpu().numpy().astype(np.float64),
-                state=state.cpu().numpy().astype(np.float64), status=status.cpu().numpy().astype(np.int64))
+                state=state.cpu().numpy().astype(np.float64), status=status.cpu().numpy().astype(np.int64),
+                overlap=ovl.cpu().numpy().astype(np.int64))
 
 
 def compare(gs, o, max_flag_frac=0.2, inputs=None):
@@ -208,3 +212,53 @@ def test_search_reuses_bins_only_for_the_same_pool(ctx, kf):
     ref = gpu_search(ctx, kf, g2, pools2, p2, C2, q2)
     for k in ref:
         assert np.array_equal(ref[k], other[k], equal_nan=True), k
+
+
+@pytest.mark.parametrize("noise", [False, True])
+def test_overlap_search_parity(ctx, kf, noise):
+    """The search with the overlap step over pools split into detector modules
+    with overlap hits: on every seed the oracle does not flag, the hit lists,
+    the overlap hits of every layer and the status are identical and the
+    scores agree within the error model; a flagged seed that differs must be
+    a result its near decisions allow (hits and overlap hits), or else one
+    that the oracle's replay finds consistent within the FP32 error model;
+    without the overlap step no overlap hit is reported."""
+    from search_common import module_inputs
+    n = 1500
+    say("overlap search", n, "noise", noise)
+    wl, ev, g, pools, p, C, q = module_inputs(n, noise=noise)
+    prm = default_params(g)
+    prm.overlap = True
+    o = KS.score_hits(p, C, q, np.full(n, SEED_LAYER), PLAN, g, pools, prm)
+    gs = gpu_search(ctx, kf, g, pools, p, C, q, overlap=True)
+    fl = o["flagged"]
+    same = np.all(gs["hits"] == o["hits"], axis=(1, 2)) & np.all(gs["overlap"] == o["overlap"], axis=(1, 2))
+    bad = np.nonzero(~same & ~fl)[0]
+    diff_fl = np.nonzero(~same & fl)[0]
+    took = int((o["overlap"][:, 0] >= 0).sum())
+    say("  flagged %.4f identical %.4f unflagged mismatches %d flagged and different %d overlap hits (rank 0) %d"
+        % (fl.mean(), same.mean(), bad.size, diff_fl.size, took))
+    assert took > 0.05 * n * len(PLAN) * 0.1
+    assert bad.size == 0, (bad[:10], gs["hits"][bad[0]], o["hits"][bad[0]], gs["overlap"][bad[0]], o["overlap"][bad[0]])
+    for s_ in diff_fl:
+        ok, runs = KS.valid_alternative(gs["hits"][s_], p[s_], C[s_], q[s_], SEED_LAYER, PLAN, g, pools, prm,
+                                        budget=16, overlap=gs["overlap"][s_])
+        how = "reproduced by flips after %d oracle runs" % runs
+        if not ok:
+            ok, why = KS.consistent_result(gs["hits"][s_], gs["score"][s_], p[s_], C[s_], q[s_], SEED_LAYER, PLAN, g,
+                                           pools, prm, o["hits"][s_], o["score"][s_], o["score_err"][s_],
+                                           overlap=gs["overlap"][s_], oracle_overlap=o["overlap"][s_])
+            how = "consistent with the oracle's replay" if ok else "NOT valid: " + why
+        say("  flagged seed %d: GPU result %s" % (s_, how))
+        assert ok, s_
+    assert fl.mean() <= 0.2
+    okm = ~fl[:, None] & np.isfinite(o["score"])
+    d = np.abs(np.where(okm, gs["score"], 0.0) - np.where(okm, o["score"], 0.0))
+    assert (d <= 1e-3 + KS.RANK_SIGMAS * o["score_err"]).all(), d.max()
+    mask = ~O.FP64_FALLBACK
+    assert np.array_equal((gs["status"] & mask)[~fl], (o["status"] & mask)[~fl])
+    # the same pools with the overlap step off: no overlap hit, and the
+    # plain search's result
+    g0 = gpu_search(ctx, kf, g, pools, p, C, q, overlap=False)
+    assert ((g0["overlap"] == KS.MISS) | (g0["overlap"] == KS.NO_CAND)).all()
+    assert np.array_equal(g0["overlap"] == KS.NO_CAND, g0["hits"] == KS.NO_CAND)

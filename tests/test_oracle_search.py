@@ -23,10 +23,10 @@ def _V(cov6):
     return V
 
 
-def _window_scan(p2, C2, L, R, prm, pools, exclude_module=None):
+def _window_scan(p2, C2, L, R, prm, pools):
     """(pool index, chi2) of every hit of layer L inside the window of the
     state (p2, C2) with chi2 <= chi2_max, by a scan over all of the layer's
-    hits (skipping those of module `exclude_module`)."""
+    hits."""
     phi = math.atan2(p2[1], p2[0])
     t = np.array([-math.sin(phi), math.cos(phi), 0.0])
     w_r = np.clip(prm.n_sigma * math.sqrt(t @ C2[:3, :3] @ t + prm.sigma_rphi[L] ** 2), prm.win_min_rphi[L],
@@ -34,8 +34,6 @@ def _window_scan(p2, C2, L, R, prm, pools, exclude_module=None):
     w_z = np.clip(prm.n_sigma * math.sqrt(C2[2, 2] + prm.sigma_z[L] ** 2), prm.win_min_z[L], prm.win_max_z[L])
     kids = []
     for h in range(int(pools.layer_offsets[L]), int(pools.layer_offsets[L + 1])):
-        if exclude_module is not None and pools.module[h] == exclude_module:
-            continue
         m = pools.pos[:, h]
         d = (math.atan2(m[1], m[0]) - phi + math.pi) % (2 * math.pi) - math.pi
         if abs(d) * R > w_r or abs(m[2] - p2[2]) > w_z:
@@ -57,7 +55,7 @@ def enumerate_paths(p, C, q, plan, g, pools, prm):
     """Every path the search rules allow for one seed, by depth-first
     recursion; windows by a scan over all pool hits of the layer.  With
     prm.overlap, a path that takes hit h then takes the overlap hit: of the
-    layer's hits on other modules inside the window of the updated state
+    layer's hits on modules with a higher id inside the window of the updated state
     with chi2 <= chi2_max, the smallest chi2 (lower id among equals); the
     overlap hit's score term counts in the ranking from the next layer on.
     Returns (score in the last ranking, final score, hits, overlap hits) per
@@ -85,7 +83,7 @@ def enumerate_paths(p, C, q, plan, g, pools, prm):
             pu, Cu, qu = _update(p2, C2, q, pools, h)
             sc, oid, term = score + prm.hit_bonus - chi2, KS.MISS, 0.0
             if prm.overlap:
-                ok = _window_scan(pu, Cu, L, R, prm, pools, exclude_module=pools.module[h])
+                ok = [x for x in _window_scan(pu, Cu, L, R, prm, pools) if pools.module[x[0]] > pools.module[h]]
                 if ok:
                     h2, c2 = min(ok, key=lambda x: (x[1], int(pools.hit_id[x[0]])))
                     pu, Cu, qu = _update(pu, Cu, qu, pools, h2)
@@ -455,11 +453,12 @@ def test_overlap_search_equals_exhaustive_enumeration(rotate):
 
 def test_overlap_hits_on_modules_with_overlaps():
     """Pools split into modules with overlap hits (toygen.with_modules), no
-    noise: the best candidate of a seed takes, at the layers where its track
-    left a second hit on the overlapping module, that hit as its overlap hit
-    (>= 95%), every overlap hit it takes is on a module other than its
-    layer's hit and belongs to the same track, and without the overlap step
-    no overlap hit is reported."""
+    noise: where the best candidate of a seed took its track's hit on the
+    lower of two overlapping modules, it takes the track's second hit (on
+    the higher module) as its overlap hit (>= 95%);
+    every overlap hit it takes is on a higher module than its layer's hit and
+    belongs to the same track; and without the overlap step no overlap hit
+    is reported."""
     from toygen import with_modules, workloads
     wl, ev, g, pools, p, C, q = search_inputs(150, noise=False)
     P = with_modules(workloads()["search20"], ev, pools)
@@ -475,10 +474,10 @@ def test_overlap_hits_on_modules_with_overlaps():
             k = idx[int(hid)]
             L = int(np.searchsorted(P.layer_offsets, k, side="right") - 1)
             a, b = int(P.layer_offsets[L]), int(P.layer_offsets[L + 1])
-            twins = [j for j in range(a, b) if P.track[j] == P.track[k] and j != k and P.module[j] != P.module[k]]
+            twins = [j for j in range(a, b) if P.track[j] == P.track[k] and j != k and P.module[j] > P.module[k]]
             if oid >= 0:
                 j = idx[int(oid)]
-                assert P.module[j] != P.module[k] and P.track[j] == P.track[k]
+                assert P.module[j] > P.module[k] and P.track[j] == P.track[k]
             if P.track[k] == t and twins:
                 avail += 1
                 took += oid >= 0
@@ -486,3 +485,36 @@ def test_overlap_hits_on_modules_with_overlaps():
     prm.overlap = False
     res0 = KS.score_hits(p, C, q, np.full(150, SEED_LAYER), PLAN, g, P, prm)
     assert ((res0["overlap"] == KS.MISS) | (res0["overlap"] == KS.NO_CAND)).all()
+
+
+def test_replay_with_overlap_hits_reproduces_the_search():
+    """With the overlap step, replay of every kept list (hits and overlap
+    hits) gives its score and error exactly and consistent_result accepts
+    the oracle's own result; a list whose overlap hit is dropped where one
+    is surely accepted is rejected."""
+    from search_common import module_inputs
+    wl, ev, g, pools, p, C, q = module_inputs(40)
+    prm = default_params(g)
+    prm.overlap = True
+    o = KS.score_hits(p, C, q, np.full(40, SEED_LAYER), PLAN, g, pools, prm)
+    dropped = 0
+    for s in range(40):
+        rows, ov = o["hits"][s], o["overlap"][s]
+        for r in range(rows.shape[0]):
+            if rows[r, 0] == KS.NO_CAND:
+                continue
+            rp = KS.replay(rows[r], p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm, ovl_row=ov[r])
+            assert rp["valid"], (s, r, rp["reason"])
+            assert abs(rp["score"] - o["score"][s, r]) <= 1e-9 * max(1.0, abs(o["score"][s, r]))
+            assert abs(rp["err"] - o["score_err"][s, r]) <= 1e-9 * max(1.0, o["score_err"][s, r])
+        ok, why = KS.consistent_result(rows, o["score"][s], p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm, rows,
+                                       o["score"][s], o["score_err"][s], overlap=ov, oracle_overlap=ov)
+        assert ok, (s, why)
+        k = np.nonzero(ov[0] >= 0)[0]
+        if k.size and not o["flagged"][s]:
+            bad = ov[0].copy()
+            bad[k[0]] = KS.MISS
+            rp = KS.replay(rows[0], p[s], C[s], q[s], SEED_LAYER, PLAN, g, pools, prm, ovl_row=bad)
+            assert not rp["valid"] and "surely accepted" in rp["reason"], rp
+            dropped += 1
+    assert dropped >= 5
