@@ -15,15 +15,17 @@ LIB = os.path.join(HERE, "libkf.so")
 SOURCES = ["kf_api.hip", "kf_kernels.hip", "kf_adjoint.hip", "kf_search.hip", "kf_backward.hip", "kf_dedup.hip", "kf_final.hip",
            "kf_plane.hip"]
 ARCH = os.environ.get("KF_OFFLOAD_ARCH", "gfx950")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+# roctx ranges name each interface call on a profiler's timeline
+LIBS = ["-L", os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         # no -ffp-contract option: the compiler's default contraction is
-         # kept.  With -ffp-contract=on or =fast the FP64 adjoint kernel gave
-         # non-finite gradients on the GPU (cause not found; the same sources
-         # run correctly on the host); rerun the adjoint GPU tests before
-         # changing this.
+         # the compiler's default floating-point contraction, unless
+         # KF_FP_CONTRACT names another mode (on, fast, off)
          "-Wno-unused-command-line-argument"]
+if os.environ.get("KF_FP_CONTRACT"):
+    FLAGS.append("-ffp-contract=" + os.environ["KF_FP_CONTRACT"])
 
 
 def hipcc() -> str:
@@ -40,7 +42,7 @@ def compile_commands(build_dir: str, out: str) -> tuple[list[list[str]], list[st
         obj = os.path.join(build_dir, src.replace(".hip", ".o"))
         objs.append(obj)
         cmds.append([hipcc()] + FLAGS + ["-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj])
-    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out] + objs
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out] + objs + LIBS
     return cmds, link
 
 

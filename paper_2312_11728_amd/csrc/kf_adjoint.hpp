@@ -565,6 +565,36 @@ KF_HD inline void state_before(const AdjArgs<T>& a, const TrackGeom<T>& g, const
   }
 }
 
+// With a segment buffer: the states before entries js .. jhi (relative to
+// the first valid entry k0, 1 <= js <= jhi) of track t, recomputed from the
+// checkpoint of their segment in one pass and stored in slots 0 .. jhi - js.
+template <typename T, typename Acc>
+KF_HD inline void fill_segment(const AdjArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t t,
+                               const Acc& acc, int k0, int js, int jhi) {
+  const int64_t n = a.f.n;
+  T p[6], c[21];
+  int q, prev;
+  state_before(a, g, sal, t, acc, k0, js, p, c, q, prev);
+  for (int j = js;; ++j) {
+    T* slot = a.seg_buf + int64_t(j - js) * kSegVals * n + t;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) slot[i * n] = p[i];
+#pragma unroll
+    for (int i = 0; i < 21; ++i) slot[(6 + i) * n] = c[i];
+    slot[27 * n] = T(q);
+    slot[28 * n] = T(prev);
+    if (j == jhi) break;
+    int lay;
+    bool valid;
+    T m[3], V[6];
+    acc.load(k0 + j, lay, valid, m, V);
+    T c2;
+    uint32_t sst = 0;
+    step_forward(p, c, q, j, lay, prev, valid, m, V, g, sal, c2, sst);
+    prev = lay;
+  }
+}
+
 // Reverse sweep of track t (len entries, the first at e0 of the hit arrays),
 // read through `acc`.
 template <typename T, typename Acc>
@@ -619,10 +649,28 @@ KF_HD inline void adjoint_track(const AdjArgs<T>& a, const TrackGeom<T>& g, cons
 #pragma unroll
   for (int i = 0; i < 21; ++i) cb[i] = 0.0;
   int q_after = q_end;
+  int cached = -1;   // first entry of the segment held in the segment buffer
   for (int j = n_done - 1; j >= 0; --j) {
     T p[6], c[21];
     int q, prev;
-    state_before(a, g, sal, t, acc, k0, j, p, c, q, prev);
+    if (a.seg_buf && j >= 1) {
+      // going down, the first entry met in a segment is its highest needed
+      // one: the segment is recomputed once, up to it
+      const int js = 1 + ((j - 1) / f.seg) * f.seg;
+      if (js != cached) {
+        fill_segment(a, g, sal, t, acc, k0, js, j);
+        cached = js;
+      }
+      const T* slot = a.seg_buf + int64_t(j - js) * kSegVals * f.n + t;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) p[i] = slot[i * f.n];
+#pragma unroll
+      for (int i = 0; i < 21; ++i) c[i] = slot[(6 + i) * f.n];
+      q = int(slot[27 * f.n]);
+      prev = int(slot[28 * f.n]);
+    } else {
+      state_before(a, g, sal, t, acc, k0, j, p, c, q, prev);
+    }
     int lay;
     bool valid;
     T m[3], V[6];

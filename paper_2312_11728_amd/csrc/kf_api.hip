@@ -12,12 +12,26 @@
 #include <algorithm>
 #include <mutex>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "kf.h"
 #include "kf_backward.hpp"
 #include "kf_dedup.hpp"
 #include "kf_kernels.hpp"
 #include "kf_plane_launch.hpp"
 #include "kf_search_launch.hpp"
+
+// A named roctx range around one call of the interface, so that a profiler's
+// timeline groups each call's kernels and copies under the entry point's name
+// (rocprofv3 --marker-trace).  Without a profiler attached the push and pop
+// cost a few tens of nanoseconds.
+struct KfRange {
+  explicit KfRange(const char* name) { roctxRangePushA(name); }
+  ~KfRange() { roctxRangePop(); }
+  KfRange(const KfRange&) = delete;
+  KfRange& operator=(const KfRange&) = delete;
+};
+#define KF_RANGE() KfRange kf_range_(__func__)
 
 struct kf_ctx {
   int device = 0;
@@ -226,6 +240,7 @@ int kf_destroy(kf_ctx* c) {
 int kf_make_seeds(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const int32_t* hit_offsets,
                   const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos, double bz_tesla, int32_t mode,
                   void* seed_state, void* seed_cov, int8_t* seed_charge, uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
@@ -259,6 +274,7 @@ int kf_propagate(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const vo
                  const int8_t* charge, const int16_t* target_layer, const int16_t* from_layer, const kf_geometry* geom,
                  int32_t apply_material, void* state_out, void* cov_out, void* path_len, uint32_t* trk_status,
                  void* stream) {
+  KF_RANGE();
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
@@ -289,6 +305,7 @@ int kf_propagate(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const vo
 
 int kf_update(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, void* state, void* cov, int8_t* charge,
               const void* hit_pos, const void* hit_cov, void* chi2, uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   if (n == 0) return ok();
@@ -567,6 +584,7 @@ int kf_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const v
                   const kf_geometry* geom, const void* align, void* state_out, void* cov_out, int8_t* charge_out,
                   void* chi2, int32_t* ndf, void* checkpoints, int32_t seg, int32_t max_len, uint32_t* trk_status,
                   void* stream) {
+  KF_RANGE();
   return fit_tracks_impl(ctx, prec, n, ld, seed_state, seed_cov, seed_charge, -1, nullptr, nullptr, nullptr,
                          hit_offsets, hit_layer, hit_valid, n_hits, hit_pos, hit_cov, geom, align, state_out, cov_out,
                          charge_out, chi2, ndf, checkpoints, seg, max_len, trk_status, stream);
@@ -578,6 +596,7 @@ int kf_seed_fit_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, in
                        void* seed_state_out, void* seed_cov_out, int8_t* seed_charge_out, void* state_out,
                        void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf, void* checkpoints, int32_t seg,
                        int32_t max_len, uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   if (seed_mode != 0 && seed_mode != 1) return fail(KF_ERR_ARG, "seed mode %d unknown (0 first three, 1 spaced)", seed_mode);
   return fit_tracks_impl(ctx, prec, n, ld, nullptr, nullptr, nullptr, seed_mode, seed_state_out, seed_cov_out,
                          seed_charge_out, hit_offsets, hit_layer, hit_valid, n_hits, hit_pos, hit_cov, geom, align,
@@ -673,6 +692,7 @@ int kf_backward_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const
                     const void* hit_pos, const void* hit_cov, const kf_geometry* geom, double cov_scale,
                     int32_t max_len, void* state_out, void* cov_out, int8_t* charge_out, void* chi2, int32_t* ndf,
                     uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   return backward_impl(ctx, prec, n, ld, state_in, cov_in, charge_in, fwd_status, nullptr, hit_offsets, hit_layer,
                        hit_valid, n_hits, hit_pos, hit_cov, geom, cov_scale, max_len, state_out, cov_out, charge_out,
                        chi2, ndf, trk_status, nullptr, nullptr, "kf_backward_fit", stream);
@@ -685,6 +705,7 @@ int kf_smooth_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, cons
                      const kf_geometry* geom, double cov_scale, int32_t max_len, void* state_out, void* cov_out,
                      int8_t* charge_out, void* chi2, int32_t* ndf, uint32_t* trk_status, void* smooth_state,
                      void* smooth_cov, void* stream) {
+  KF_RANGE();
   if (!fwd_checkpoints || !smooth_state || !smooth_cov)
     return fail(KF_ERR_ARG, "kf_smooth_tracks needs fwd_checkpoints, smooth_state and smooth_cov");
   return backward_impl(ctx, prec, n, ld, state_in, cov_in, charge_in, fwd_status, fwd_checkpoints, hit_offsets,
@@ -695,6 +716,7 @@ int kf_smooth_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, cons
 int kf_remove_duplicates(kf_ctx* ctx, int64_t n, const int32_t* track_hits, int64_t hit_stride, int32_t n_layers,
                          const float* score, int64_t score_stride, float frac, uint8_t* keep, int32_t* dup_of,
                          void* stream) {
+  KF_RANGE();
   if (n < 0) return fail(KF_ERR_ARG, "n = %lld < 0", (long long)n);
   if (n_layers < 1 || n_layers > 64) return fail(KF_ERR_ARG, "n_layers = %d outside [1, 64]", n_layers);
   if (hit_stride < n_layers) return fail(KF_ERR_ARG, "hit_stride = %lld < n_layers", (long long)hit_stride);
@@ -729,6 +751,7 @@ int kf_remove_duplicates(kf_ctx* ctx, int64_t n, const int32_t* track_hits, int6
 }
 
 int kf_reserve(kf_ctx* ctx, int64_t max_tracks, int32_t max_len) {
+  KF_RANGE();
   if (max_tracks < 0) return fail(KF_ERR_ARG, "max_tracks = %lld < 0", (long long)max_tracks);
   if (max_len < 1 || max_len > kf::kMaxLen) return fail(KF_ERR_ARG, "max_len = %d outside [1, %d]", max_len, kf::kMaxLen);
   KF_REQUIRE(ctx);
@@ -827,6 +850,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
                   int64_t n_pool, const float* pool_pos, const float* pool_cov, const int32_t* pool_hit_id,
                   const int32_t* pool_module, int32_t* cand_hits, int32_t* cand_overlap, float* cand_score,
                   float* cand_state, uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
   KF_TRY(check_geometry(geom, &g));
@@ -1169,6 +1193,7 @@ int kf_final_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, int32_t 
                  const void* hit_cov, const kf_geometry* geom, double cov_scale, double chi2_cut, int32_t max_reject,
                  int32_t min_keep, int32_t max_len, void* state_out, void* cov_out, int8_t* charge_out, void* chi2,
                  int32_t* ndf, uint32_t* trk_status, uint8_t* outlier, void* hit_chi2, void* stream) {
+  KF_RANGE();
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   kf::GeomArgs g;
@@ -1286,8 +1311,15 @@ int fit_adjoint_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, cons
                   prec == KF_F32 ? "FP32" : "FP64");
     if (!ctx->scratch) return fail(KF_ERR_DEVICE, "kf_fit_adjoint_noalloc: no scratch address for this context");
     partial = ctx->scratch;
-  } else if (grad_align) {
-    const size_t need = size_t(kf::adjoint_partial_blocks(n_hits)) * 2 * kf::kMaxLayers * esz;
+  }
+  void* seg_buf = nullptr;
+  if (!no_alloc) {
+    // the alignment partials, then (seg > 1) the buffer of one checkpoint
+    // segment's states per track
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t need_part = grad_align ? up(size_t(kf::adjoint_partial_blocks(n_hits)) * 2 * kf::kMaxLayers * esz) : 0;
+    const size_t need_seg = seg > 1 ? up(size_t(n) * size_t(seg) * kf::kSegVals * esz) : 0;
+    const size_t need = need_part + need_seg;
     if (need > ctx->red_bytes) {
       int prev = 0;
       hipGetDevice(&prev);
@@ -1303,7 +1335,8 @@ int fit_adjoint_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, cons
       }
       ctx->red_bytes = need;
     }
-    partial = ctx->red_mem;
+    if (grad_align) partial = ctx->red_mem;
+    if (need_seg) seg_buf = (char*)ctx->red_mem + need_part;
   }
   hipError_t e;
   if (prec == KF_F32) {
@@ -1318,6 +1351,7 @@ int fit_adjoint_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, cons
     a.grad_hit = (float*)grad_hit_pos;
     a.grad_align = (float*)grad_align;
     a.partial = (float*)partial;
+    a.seg_buf = (float*)seg_buf;
     e = kf::launch_adjoint(a, g, s);
   } else {
     kf::AdjArgs<double> a;
@@ -1331,6 +1365,7 @@ int fit_adjoint_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, cons
     a.grad_hit = (double*)grad_hit_pos;
     a.grad_align = (double*)grad_align;
     a.partial = (double*)partial;
+    a.seg_buf = (double*)seg_buf;
     e = kf::launch_adjoint(a, g, s);
   }
   if (e != hipSuccess) return hip_fail(e, no_alloc ? "kf_fit_adjoint_noalloc" : "kf_fit_adjoint");
@@ -1347,6 +1382,7 @@ int kf_fit_adjoint(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, const 
                    const void* hit_cov, const kf_geometry* geom, const void* align, const void* checkpoints,
                    int32_t seg, int32_t max_len, const void* dL_dchi2, void* grad_seed, void* grad_hit_pos,
                    void* grad_align, const uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   return fit_adjoint_impl(ctx, prec, n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
                           n_hits, hit_pos, hit_cov, geom, align, checkpoints, seg, max_len, dL_dchi2, grad_seed,
                           grad_hit_pos, grad_align, trk_status, stream, false);
@@ -1358,6 +1394,7 @@ int kf_fit_adjoint_noalloc(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld
                            const void* hit_cov, const kf_geometry* geom, const void* align, const void* checkpoints,
                            int32_t seg, int32_t max_len, const void* dL_dchi2, void* grad_seed, void* grad_hit_pos,
                            void* grad_align, const uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   return fit_adjoint_impl(ctx, prec, n, ld, seed_state, seed_cov, seed_charge, hit_offsets, hit_layer, hit_valid,
                           n_hits, hit_pos, hit_cov, geom, align, checkpoints, seg, max_len, dL_dchi2, grad_seed,
                           grad_hit_pos, grad_align, trk_status, stream, true);
@@ -1439,6 +1476,7 @@ int kf_propagate_plane(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, co
                        const void* cov_in, const int8_t* charge, const int32_t* target_module,
                        const kf_plane_geometry* geom, int32_t apply_material, void* state_out, void* cov_out,
                        void* path_len, uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   KF_TRY(check_lanes(n, "n"));
@@ -1461,6 +1499,7 @@ int kf_propagate_plane(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, co
 int kf_update_plane(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, void* state, void* cov, int8_t* charge,
                     const int32_t* module, const void* hit_uv, const void* hit_cov_uv, const kf_plane_geometry* geom,
                     void* chi2, uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   KF_TRY(check_lanes(n, "n"));
@@ -1486,6 +1525,7 @@ int kf_fit_plane_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, c
                         const int32_t* hit_module, const uint8_t* hit_valid, int64_t n_hits, const void* hit_uv,
                         const void* hit_cov_uv, const kf_plane_geometry* geom, void* state_out, void* cov_out,
                         int8_t* charge_out, void* chi2, int32_t* ndf, uint32_t* trk_status, void* stream) {
+  KF_RANGE();
   KF_TRY(check_prec(prec));
   KF_TRY(check_sizes(n, ld));
   KF_TRY(check_lanes(n, "n"));
@@ -1519,6 +1559,7 @@ int kf_fit_plane_tracks(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, c
 
 int kf_plane_to_global(kf_ctx* ctx, kf_precision prec, int64_t n_hits, const int32_t* module, const void* hit_uv,
                        const kf_plane_geometry* geom, void* hit_pos, void* stream) {
+  KF_RANGE();
   KF_TRY(check_prec(prec));
   if (n_hits < 0) return fail(KF_ERR_ARG, "n_hits < 0");
   KF_TRY(check_lanes(n_hits, "n_hits"));

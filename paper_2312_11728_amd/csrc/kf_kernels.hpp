@@ -159,7 +159,13 @@ struct AdjArgs {
   T* grad_hit;                 // [3][n_hits]
   T* grad_align;               // [2][n_layers] or null
   T* partial;                  // [adjoint_partial_blocks(n_hits)][2][kMaxLayers] when grad_align is set
+  // the states before the entries of one checkpoint segment, recomputed once
+  // per segment ([f.seg][kSegVals][n], (slot, value, track) at
+  // (slot * kSegVals + value) * n + track), or null: each state is then
+  // recomputed from its segment's checkpoint when it is needed
+  T* seg_buf;
 };
+constexpr int kSegVals = 29;   // state (6), covariance (21), charge, layer of the previous entry
 // blocks of the alignment reduction (kAlignPerBlock entries each)
 constexpr int kAlignPerBlock = 64 * 32;
 inline int64_t adjoint_partial_blocks(int64_t n_hits) { return (n_hits + kAlignPerBlock - 1) / kAlignPerBlock; }
