@@ -430,7 +430,10 @@ typedef struct {
  * be NULL when params->overlap is 0).  The call bins the pool by (layer, phi, z) into a context-owned
  * workspace (about 64 bytes per pool hit and per candidate slot; grown on
  * demand, KF_ERR_NOMEM if that fails), unless params->reuse_bins allows the
- * bins of the previous call to be used.
+ * bins of the previous call to be used.  The per-layer parameters of the
+ * plan are copied from host memory into that workspace on `stream` (a
+ * host-to-device copy, synchronous with respect to the host) before the
+ * search, which then runs as one kernel launch.
  * Outputs: cand_hits[n][beam][plan_len] (hit id, -1 = miss; -2 for every
  * entry of a rank the seed has no candidate for), cand_overlap
  * [n][beam][plan_len] (may be NULL: the overlap hit id of each layer, -1 for

@@ -932,7 +932,8 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   const int64_t b_bins = up(n_bins * 4), b_pool4 = up(n_pool * 4), b_sum = up(nsum * 4) + 256;
   const int64_t b_pool = up(n_pool * int64_t(sizeof(kf::PoolHit))) + up((n_bins + 1) * 4);
   const int64_t b_slot = 2 * (up(S * 6 * 4) + up(S * 21 * 4) + up(S)) + 3 * up(S * kf::kMaxBeam * 4) + up(S * 4) +
-                         up(S) + up(S) + up(S * 4) + up(S * 4) + up(S) + up(P * S) + 2 * up(P * S * 4);
+                         up(S) + up(S) + up(S * 4) + up(S * 4) + up(S) + up(P * S) + 2 * up(P * S * 4) +
+                         up(P * int64_t(sizeof(kf::SearchLayer)));
   const int64_t total = b_bins + 2 * b_pool4 + b_sum + b_pool + b_slot;
   if (size_t(total) > ctx->search_bytes) {
     int prev = 0;
@@ -1012,6 +1013,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   a.hist_parent = (int8_t*)take(up(P * S));
   a.hist_id = (int32_t*)take(up(P * S * 4));
   a.hist_ovl = (int32_t*)take(up(P * S * 4));
+  kf::SearchLayer* d_layers = (kf::SearchLayer*)take(up(P * int64_t(sizeof(kf::SearchLayer))));
   a.overlap = prm->overlap;
   a.overlap_bonus = prm->overlap_bonus;
   a.cand_ovl = cand_overlap;
@@ -1046,7 +1048,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
     e = kf::launch_bin_pool(t, pool_pos, pool_cov, pool_hit_id, module, n_pool, n_bins, w, s);
     if (e == hipSuccess) ctx->bins_key = key;
   }
-  if (e == hipSuccess) e = kf::launch_search(a, layers.data(), plan_len, s);
+  if (e == hipSuccess) e = kf::launch_search(a, layers.data(), d_layers, s);
   if (e != hipSuccess) return hip_fail(e, "kf_score_hits");
   return ok();
 }

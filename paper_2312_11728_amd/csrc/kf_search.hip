@@ -124,24 +124,35 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(BinTable t, const floa
 
 // ---- search ------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) extend_kernel(SearchArgs a, SearchLayer L, SearchLayer Lp) {
-  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= a.n * a.beam) return;
-  const uint32_t st = extend_slot(a, L, Lp, s);
-  if (st) atomicOr(&a.status[s / a.beam], st);
-}
-
-__global__ void __launch_bounds__(256) select_kernel(SearchArgs a) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.n) return;
-  select_seed(a, t);
-}
-
-__global__ void __launch_bounds__(256) finish_kernel(SearchArgs a, SearchLayer Llast) {
-  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= a.n * a.beam) return;
-  const uint32_t st = finish_slot(a, Llast, s);
-  if (st) atomicOr(&a.status[s / a.beam], st);
+// The whole search in one launch.  Block b owns the seeds [b * spb,
+// (b + 1) * spb), spb = blockDim.x / beam, and their slots: thread i <
+// spb * beam extends slot b * spb * beam + i at every layer, threads i < spb
+// then select the children of seed b * spb + i, and the slot threads end
+// with the final pass.  A seed's slots exchange data (child lists, the
+// selection, the predicted states, the histories) only with each other,
+// through global memory, and block barriers order every exchange, so blocks
+// never wait for one another: each runs its seeds through the layers at its
+// own pace.
+__global__ void __launch_bounds__(kSearchBlock, 2) search_kernel(SearchArgs a, const SearchLayer* __restrict__ layers) {
+  const int spb = int(blockDim.x) / a.beam;
+  const int64_t seed0 = int64_t(blockIdx.x) * spb;
+  const int64_t s = seed0 * a.beam + threadIdx.x;
+  const int64_t t = seed0 + threadIdx.x;
+  const bool slot = int(threadIdx.x) < spb * a.beam && s < a.n * a.beam;
+  const bool seed = int(threadIdx.x) < spb && t < a.n;
+  for (int k = 0; k < a.plan_len; ++k) {
+    if (slot) {
+      const uint32_t st = extend_slot(a, layers[k], layers[k > 0 ? k - 1 : 0], k, s);
+      if (st) atomicOr(&a.status[s / a.beam], st);
+    }
+    __syncthreads();
+    if (seed) select_seed(a, k, t);
+    __syncthreads();
+  }
+  if (slot) {
+    const uint32_t st = finish_slot(a, layers[a.plan_len - 1], s);
+    if (st) atomicOr(&a.status[s / a.beam], st);
+  }
 }
 
 static unsigned blocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -164,15 +175,12 @@ hipError_t launch_bin_pool(const BinTable& t, const float* pos, const float* cov
   return hipGetLastError();
 }
 
-hipError_t launch_search(SearchArgs a, const SearchLayer* layers, int plan_len, hipStream_t s) {
-  const int64_t S = a.n * a.beam;
+hipError_t launch_search(SearchArgs a, const SearchLayer* layers, SearchLayer* d_layers, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(d_layers, layers, size_t(a.plan_len) * sizeof(SearchLayer), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks(a.n, 256)), dim3(256), 0, s, (int32_t*)a.status, a.n, 0);
-  for (int k = 0; k < plan_len; ++k) {
-    a.step = k;
-    hipLaunchKernelGGL(extend_kernel, dim3(blocks(S, 256)), dim3(256), 0, s, a, layers[k], layers[k > 0 ? k - 1 : 0]);
-    hipLaunchKernelGGL(select_kernel, dim3(blocks(a.n, 256)), dim3(256), 0, s, a);
-  }
-  hipLaunchKernelGGL(finish_kernel, dim3(blocks(S, 256)), dim3(256), 0, s, a, layers[plan_len - 1]);
+  const int spb = kSearchBlock / a.beam;
+  hipLaunchKernelGGL(search_kernel, dim3(blocks(a.n, spb)), dim3(kSearchBlock), 0, s, a, (const SearchLayer*)d_layers);
   return hipGetLastError();
 }
 

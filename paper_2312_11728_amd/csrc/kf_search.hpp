@@ -87,7 +87,7 @@ struct SearchLayer {
 
 struct SearchArgs {
   int64_t n, ld;                 // seeds, leading dimension of the seed arrays
-  int32_t beam, plan_len, step;  // step: index of the layer in the plan
+  int32_t beam, plan_len;
   const float* seed_state;       // [6][ld]
   const float* seed_cov;         // [21][ld]
   const int8_t* seed_charge;     // [n]
@@ -234,11 +234,12 @@ KF_HD inline int32_t pick_overlap(const SearchArgs& a, const SearchLayer& L, int
 
 // Extend the candidate of slot s (see the file comment).  Returns the status
 // bits of its steps.
-KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, const SearchLayer& Lp, int64_t s) {
+KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, const SearchLayer& Lp, int step,
+                                  int64_t s) {
   const int64_t S = a.n * a.beam;
   const int64_t seed = s / a.beam;
   const int r = int(s % a.beam);
-  const int cur = a.step & 1, prv = cur ^ 1;
+  const int cur = step & 1, prv = cur ^ 1;
   float p[6], c[21];
   int q = 1, prev;
   float score;
@@ -246,7 +247,7 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
   uint32_t st = 0;
   bool stopped = false;
   a.kid_n[s] = 0;
-  if (a.step == 0) {
+  if (step == 0) {
     if (r != 0) return 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * a.ld + seed];
@@ -269,7 +270,7 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
       if (a.overlap) {
         float oc2 = 0.f;
         const int32_t oid = pick_overlap(a, Lp, h, p, c, q, oc2, st);
-        a.hist_ovl[int64_t(a.step - 1) * S + s] = oid;
+        a.hist_ovl[int64_t(step - 1) * S + s] = oid;
         if (oid >= 0) ovl = a.overlap_bonus - oc2;
       }
     }
@@ -407,7 +408,7 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
 }
 
 // Merge the child lists of seed t's slots into its next candidates.
-KF_HD inline void select_seed(const SearchArgs& a, int64_t t) {
+KF_HD inline void select_seed(const SearchArgs& a, int step, int64_t t) {
   const int64_t S = a.n * a.beam;
   const int64_t s0 = t * a.beam;
   // The child lists of the seed's slots, read at once: each is sorted best
@@ -489,9 +490,9 @@ KF_HD inline void select_seed(const SearchArgs& a, int64_t t) {
     a.sel_idx[so] = idx;
     a.sel_score[so] = o_score[out];
     a.sel_miss[so] = int8_t(a.cur_miss[s0 + best] + (idx == kMissIdx ? 1 : 0));
-    a.hist_parent[int64_t(a.step) * S + so] = int8_t(best);
-    a.hist_id[int64_t(a.step) * S + so] = idx >= 0 ? o_key[out] : idx;
-    if (a.overlap) a.hist_ovl[int64_t(a.step) * S + so] = kMissIdx;
+    a.hist_parent[int64_t(step) * S + so] = int8_t(best);
+    a.hist_id[int64_t(step) * S + so] = idx >= 0 ? o_key[out] : idx;
+    if (a.overlap) a.hist_ovl[int64_t(step) * S + so] = kMissIdx;
   }
 }
 
