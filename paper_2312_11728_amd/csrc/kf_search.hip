@@ -126,29 +126,32 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(BinTable t, const floa
 
 // The whole search in one launch.  Block b owns the seeds [b * spb,
 // (b + 1) * spb), spb = blockDim.x / beam, and their slots: thread i <
-// spb * beam extends slot b * spb * beam + i at every layer, threads i < spb
-// then select the children of seed b * spb + i, and the slot threads end
-// with the final pass.  A seed's slots exchange data (child lists, the
-// selection, the predicted states, the histories) only with each other,
-// through global memory, and block barriers order every exchange, so blocks
-// never wait for one another: each runs its seeds through the layers at its
-// own pace.
+// spb * beam is slot b * spb * beam + i.  At every layer the slot runs the
+// previous layer's selection for itself, then its extend; after the last
+// layer, the last selection and the final pass.  A seed's slots exchange
+// data (child lists, predicted states, histories) only with each other,
+// through global memory, and one block barrier per layer orders every
+// exchange, so blocks never wait for one another: each runs its seeds
+// through the layers at its own pace.
 __global__ void __launch_bounds__(kSearchBlock, 2) search_kernel(SearchArgs a, const SearchLayer* __restrict__ layers) {
   const int spb = int(blockDim.x) / a.beam;
   const int64_t seed0 = int64_t(blockIdx.x) * spb;
   const int64_t s = seed0 * a.beam + threadIdx.x;
   const int64_t t = seed0 + threadIdx.x;
   const bool slot = int(threadIdx.x) < spb * a.beam && s < a.n * a.beam;
-  const bool seed = int(threadIdx.x) < spb && t < a.n;
+  // the seeds' status words collect the bits of their slots' steps
+  if (int(threadIdx.x) < spb && t < a.n) a.status[t] = 0u;
+  __syncthreads();
   for (int k = 0; k < a.plan_len; ++k) {
     if (slot) {
+      if (k > 0) select_slot(a, k - 1, s);
       const uint32_t st = extend_slot(a, layers[k], layers[k > 0 ? k - 1 : 0], k, s);
       if (st) atomicOr(&a.status[s / a.beam], st);
     }
     __syncthreads();
-    if (seed) select_seed(a, k, t);
-    __syncthreads();
   }
+  if (slot) select_slot(a, a.plan_len - 1, s);
+  __syncthreads();
   if (slot) {
     const uint32_t st = finish_slot(a, layers[a.plan_len - 1], s);
     if (st) atomicOr(&a.status[s / a.beam], st);
@@ -178,7 +181,6 @@ hipError_t launch_bin_pool(const BinTable& t, const float* pos, const float* cov
 hipError_t launch_search(SearchArgs a, const SearchLayer* layers, SearchLayer* d_layers, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(d_layers, layers, size_t(a.plan_len) * sizeof(SearchLayer), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks(a.n, 256)), dim3(256), 0, s, (int32_t*)a.status, a.n, 0);
   const int spb = kSearchBlock / a.beam;
   hipLaunchKernelGGL(search_kernel, dim3(blocks(a.n, spb)), dim3(kSearchBlock), 0, s, a, (const SearchLayer*)d_layers);
   return hipGetLastError();

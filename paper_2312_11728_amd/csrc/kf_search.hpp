@@ -11,8 +11,10 @@
 //     else one stop child: a candidate that stops -- no crossing, or no hit
 //     within its miss budget -- keeps its score and the state it entered the
 //     layer with, and from then on is carried from layer to layer unchanged);
-//   select (one thread per seed): merge the slots' sorted child lists into
-//     the seed's best `beam` children, which become the next layer's slots;
+//   select (every slot of the seed, at the start of the next layer's
+//     extend or before the final pass): merge the slots' sorted child lists
+//     into the seed's best `beam` children, which become the next layer's
+//     slots;
 //   overlap (with the overlap step on; at the next layer's extend, or in the
 //     final pass): right after a kept child's update with its hit, the best
 //     hit of a higher-numbered module of the same layer inside the window
@@ -103,11 +105,14 @@ struct SearchArgs {
   float* pred_p[2];              // [6][S] predicted state at the current / previous layer
   float* pred_c[2];              // [21][S]
   int8_t* pred_q[2];             // [S]
-  float* kid_score;              // [S][kMaxBeam] sorted child list of each slot
-  int32_t* kid_id;
-  int32_t* kid_idx;              // binned pool index, kMissIdx, kStopIdx
-  int32_t* kid_n;                // [S]
-  int8_t* cur_miss;              // [S] misses of the slot's candidate
+  // child lists and misses, by parity of the plan step (the selection of
+  // step k reads those of step k while the extend of step k + 1 writes the
+  // others)
+  float* kid_score[2];           // [S][kMaxBeam] sorted child list of each slot
+  int32_t* kid_id[2];
+  int32_t* kid_idx[2];           // binned pool index, kMissIdx, kStopIdx
+  int32_t* kid_n[2];             // [S]
+  int8_t* cur_miss[2];           // [S] misses of the slot's candidate
   int8_t* sel_parent;            // [S] parent rank of the slot's candidate, -1 = none
   int32_t* sel_idx;              // [S] binned pool index of its hit, kMissIdx, kStopIdx
   float* sel_score;              // [S]
@@ -246,7 +251,11 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
   int miss;
   uint32_t st = 0;
   bool stopped = false;
-  a.kid_n[s] = 0;
+  int32_t* const kid_n = a.kid_n[cur];
+  float* const kid_score = a.kid_score[cur];
+  int32_t* const kid_id = a.kid_id[cur];
+  int32_t* const kid_idx = a.kid_idx[cur];
+  kid_n[s] = 0;
   if (step == 0) {
     if (r != 0) return 0;
 #pragma unroll
@@ -285,12 +294,12 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
 #pragma unroll
   for (int i = 0; i < 21; ++i) a.pred_c[cur][i * S + s] = c[i];
   a.pred_q[cur][s] = int8_t(q);
-  a.cur_miss[s] = int8_t(miss);
+  a.cur_miss[cur][s] = int8_t(miss);
   if (stopped || !propagate(p, c, q, 0, L.R, L.x0, prev == L.layer, true, a.bz, a.mass, st)) {
-    a.kid_score[s * kMaxBeam] = score;
-    a.kid_id[s * kMaxBeam] = kStopKey;
-    a.kid_idx[s * kMaxBeam] = kStopIdx;
-    a.kid_n[s] = 1;
+    kid_score[s * kMaxBeam] = score;
+    kid_id[s * kMaxBeam] = kStopKey;
+    kid_idx[s * kMaxBeam] = kStopIdx;
+    kid_n[s] = 1;
     return st;
   }
   // window
@@ -398,19 +407,24 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
 #pragma unroll
   for (int j = 0; j < kMaxBeam; ++j) {
     if (j < n_out) {
-      a.kid_score[s * kMaxBeam + j] = ks[j];
-      a.kid_id[s * kMaxBeam + j] = kk[j];
-      a.kid_idx[s * kMaxBeam + j] = ki[j];
+      kid_score[s * kMaxBeam + j] = ks[j];
+      kid_id[s * kMaxBeam + j] = kk[j];
+      kid_idx[s * kMaxBeam + j] = ki[j];
     }
   }
-  a.kid_n[s] = n_out;
+  kid_n[s] = n_out;
   return st;
 }
 
-// Merge the child lists of seed t's slots into its next candidates.
-KF_HD inline void select_seed(const SearchArgs& a, int step, int64_t t) {
+// The selection of plan step `step` for slot s: the child lists of the
+// slots of s's seed are merged into the seed's next candidates, and s takes
+// the one of its rank.  Every slot of a seed runs the same merge, each keeps
+// its own result.
+KF_HD inline void select_slot(const SearchArgs& a, int step, int64_t s) {
   const int64_t S = a.n * a.beam;
-  const int64_t s0 = t * a.beam;
+  const int64_t s0 = (s / a.beam) * a.beam;
+  const int me = int(s - s0);
+  const int b = step & 1;
   // The child lists of the seed's slots, read at once: each is sorted best
   // first, so only its first `beam` entries can be chosen; absent entries
   // rank last.  The heads of the lists compete (ties by child id, then by
@@ -421,7 +435,7 @@ KF_HD inline void select_seed(const SearchArgs& a, int step, int64_t t) {
   int cnt[kMaxBeam], taken[kMaxBeam];
 #pragma unroll
   for (int r = 0; r < kMaxBeam; ++r) {
-    cnt[r] = r < a.beam ? a.kid_n[s0 + r] : 0;
+    cnt[r] = r < a.beam ? a.kid_n[b][s0 + r] : 0;
     taken[r] = 0;
   }
 #pragma unroll
@@ -430,20 +444,17 @@ KF_HD inline void select_seed(const SearchArgs& a, int step, int64_t t) {
     for (int j = 0; j < kMaxBeam; ++j) {
       const bool in = j < cnt[r] && j < a.beam;
       const int64_t k = (s0 + (in ? r : 0)) * kMaxBeam + (in ? j : 0);
-      ks[r][j] = in ? a.kid_score[k] : -k_inf<float>();
-      kk[r][j] = in ? a.kid_id[k] : kStopKey;
+      ks[r][j] = in ? a.kid_score[b][k] : -k_inf<float>();
+      kk[r][j] = in ? a.kid_id[b][k] : kStopKey;
     }
-  int o_par[kMaxBeam], o_pos[kMaxBeam];
-  float o_score[kMaxBeam];
-  int32_t o_key[kMaxBeam];
-  int n_out = 0;
+  // outputs 0 .. me in turn; the last one chosen is this slot's
+  int par = -1, pos = 0;
+  float score = 0.f;
+  int32_t key = 0;
+  bool open = true;   // every output so far had a child
 #pragma unroll
   for (int out = 0; out < kMaxBeam; ++out) {
-    o_par[out] = -1;
-    o_pos[out] = 0;
-    o_score[out] = 0.f;
-    o_key[out] = 0;
-    if (out >= a.beam || n_out < out) continue;
+    if (out > me || !open) continue;
     int best = -1, bpos = 0;
     float bs = 0.f;
     int32_t bk = 0;
@@ -456,12 +467,16 @@ KF_HD inline void select_seed(const SearchArgs& a, int step, int64_t t) {
         bk = kk[r][0];
       }
     }
-    if (best < 0) continue;
-    o_par[out] = best;
-    o_pos[out] = bpos;
-    o_score[out] = bs;
-    o_key[out] = bk;
-    n_out = out + 1;
+    if (best < 0) {
+      open = false;
+      continue;
+    }
+    if (out == me) {
+      par = best;
+      pos = bpos;
+      score = bs;
+      key = bk;
+    }
 #pragma unroll
     for (int r = 0; r < kMaxBeam; ++r) {
       if (r == best) {
@@ -474,26 +489,18 @@ KF_HD inline void select_seed(const SearchArgs& a, int step, int64_t t) {
       }
     }
   }
-  // the chosen children's pool indices and their parents' misses, read at
-  // once, then the selection
-#pragma unroll
-  for (int out = 0; out < kMaxBeam; ++out) {
-    if (out >= a.beam) continue;
-    const int64_t so = s0 + out;
-    if (out >= n_out) {
-      a.sel_parent[so] = -1;
-      continue;
-    }
-    const int best = o_par[out];
-    const int32_t idx = a.kid_idx[(s0 + best) * kMaxBeam + o_pos[out]];
-    a.sel_parent[so] = int8_t(best);
-    a.sel_idx[so] = idx;
-    a.sel_score[so] = o_score[out];
-    a.sel_miss[so] = int8_t(a.cur_miss[s0 + best] + (idx == kMissIdx ? 1 : 0));
-    a.hist_parent[int64_t(step) * S + so] = int8_t(best);
-    a.hist_id[int64_t(step) * S + so] = idx >= 0 ? o_key[out] : idx;
-    if (a.overlap) a.hist_ovl[int64_t(step) * S + so] = kMissIdx;
+  if (par < 0) {
+    a.sel_parent[s] = -1;
+    return;
   }
+  const int32_t idx = a.kid_idx[b][(s0 + par) * kMaxBeam + pos];
+  a.sel_parent[s] = int8_t(par);
+  a.sel_idx[s] = idx;
+  a.sel_score[s] = score;
+  a.sel_miss[s] = int8_t(a.cur_miss[b][s0 + par] + (idx == kMissIdx ? 1 : 0));
+  a.hist_parent[int64_t(step) * S + s] = int8_t(par);
+  a.hist_id[int64_t(step) * S + s] = idx >= 0 ? key : idx;
+  if (a.overlap) a.hist_ovl[int64_t(step) * S + s] = kMissIdx;
 }
 
 // After the last layer: the kept candidates' final states (update with their
