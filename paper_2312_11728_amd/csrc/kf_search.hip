@@ -133,6 +133,9 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(BinTable t, const floa
 // through global memory, and one block barrier per layer orders every
 // exchange, so blocks never wait for one another: each runs its seeds
 // through the layers at its own pace.
+// B: a compile-time bound on beam (2, 4, 6 or 8), the size of the child
+// lists held in registers.
+template <int B>
 __global__ void __launch_bounds__(kSearchBlock, 2) search_kernel(SearchArgs a, const SearchLayer* __restrict__ layers) {
   const int spb = int(blockDim.x) / a.beam;
   const int64_t seed0 = int64_t(blockIdx.x) * spb;
@@ -144,13 +147,13 @@ __global__ void __launch_bounds__(kSearchBlock, 2) search_kernel(SearchArgs a, c
   __syncthreads();
   for (int k = 0; k < a.plan_len; ++k) {
     if (slot) {
-      if (k > 0) select_slot(a, k - 1, s);
-      const uint32_t st = extend_slot(a, layers[k], layers[k > 0 ? k - 1 : 0], k, s);
+      if (k > 0) select_slot<B>(a, k - 1, s);
+      const uint32_t st = extend_slot<B>(a, layers[k], layers[k > 0 ? k - 1 : 0], k, s);
       if (st) atomicOr(&a.status[s / a.beam], st);
     }
     __syncthreads();
   }
-  if (slot) select_slot(a, a.plan_len - 1, s);
+  if (slot) select_slot<B>(a, a.plan_len - 1, s);
   __syncthreads();
   if (slot) {
     const uint32_t st = finish_slot(a, layers[a.plan_len - 1], s);
@@ -182,7 +185,16 @@ hipError_t launch_search(SearchArgs a, const SearchLayer* layers, SearchLayer* d
   hipError_t e = hipMemcpyAsync(d_layers, layers, size_t(a.plan_len) * sizeof(SearchLayer), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
   const int spb = kSearchBlock / a.beam;
-  hipLaunchKernelGGL(search_kernel, dim3(blocks(a.n, spb)), dim3(kSearchBlock), 0, s, a, (const SearchLayer*)d_layers);
+  const dim3 grid(blocks(a.n, spb)), block(kSearchBlock);
+  const SearchLayer* L = d_layers;
+  if (a.beam <= 2)
+    hipLaunchKernelGGL(search_kernel<2>, grid, block, 0, s, a, L);
+  else if (a.beam <= 4)
+    hipLaunchKernelGGL(search_kernel<4>, grid, block, 0, s, a, L);
+  else if (a.beam <= 6)
+    hipLaunchKernelGGL(search_kernel<6>, grid, block, 0, s, a, L);
+  else
+    hipLaunchKernelGGL(search_kernel<kMaxBeam>, grid, block, 0, s, a, L);
   return hipGetLastError();
 }
 

@@ -239,6 +239,8 @@ KF_HD inline int32_t pick_overlap(const SearchArgs& a, const SearchLayer& L, int
 
 // Extend the candidate of slot s (see the file comment).  Returns the status
 // bits of its steps.
+// B: a bound on beam known at compile time (the lists' register size).
+template <int B>
 KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, const SearchLayer& Lp, int step,
                                   int64_t s) {
   const int64_t S = a.n * a.beam;
@@ -313,10 +315,10 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
   w_z = w_z < L.wmin_z ? L.wmin_z : (w_z > L.wmax_z ? L.wmax_z : w_z);
   const float dphi = w_r / L.R;
   // child list of this slot, best first (empty entries rank last)
-  float ks[kMaxBeam];
-  int32_t kk[kMaxBeam], ki[kMaxBeam];
+  float ks[B];
+  int32_t kk[B], ki[B];
 #pragma unroll
-  for (int j = 0; j < kMaxBeam; ++j) {
+  for (int j = 0; j < B; ++j) {
     ks[j] = -k_inf<float>();
     kk[j] = kMissKey;
     ki[j] = -2;
@@ -370,7 +372,7 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
         float ns = score + a.hit_bonus - c2;
         int32_t nkey = ph.id, nidx = h;
 #pragma unroll
-        for (int j = 0; j < kMaxBeam; ++j) {
+        for (int j = 0; j < B; ++j) {
           if (j < a.beam && child_before(ns, nkey, 0, ks[j], kk[j], 0)) {
             const float ts = ks[j];
             const int32_t tk = kk[j], ti = ki[j];
@@ -405,7 +407,7 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
   }
   const int n_out = nk < a.beam ? nk : a.beam;
 #pragma unroll
-  for (int j = 0; j < kMaxBeam; ++j) {
+  for (int j = 0; j < B; ++j) {
     if (j < n_out) {
       kid_score[s * kMaxBeam + j] = ks[j];
       kid_id[s * kMaxBeam + j] = kk[j];
@@ -420,6 +422,7 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
 // slots of s's seed are merged into the seed's next candidates, and s takes
 // the one of its rank.  Every slot of a seed runs the same merge, each keeps
 // its own result.
+template <int B>
 KF_HD inline void select_slot(const SearchArgs& a, int step, int64_t s) {
   const int64_t S = a.n * a.beam;
   const int64_t s0 = (s / a.beam) * a.beam;
@@ -430,18 +433,18 @@ KF_HD inline void select_slot(const SearchArgs& a, int step, int64_t s) {
   // rank last.  The heads of the lists compete (ties by child id, then by
   // the parent's rank), and the chosen list moves up by one place; every
   // index is static, so the lists stay in registers.
-  float ks[kMaxBeam][kMaxBeam];
-  int32_t kk[kMaxBeam][kMaxBeam];
-  int cnt[kMaxBeam], taken[kMaxBeam];
+  float ks[B][B];
+  int32_t kk[B][B];
+  int cnt[B], taken[B];
 #pragma unroll
-  for (int r = 0; r < kMaxBeam; ++r) {
+  for (int r = 0; r < B; ++r) {
     cnt[r] = r < a.beam ? a.kid_n[b][s0 + r] : 0;
     taken[r] = 0;
   }
 #pragma unroll
-  for (int r = 0; r < kMaxBeam; ++r)
+  for (int r = 0; r < B; ++r)
 #pragma unroll
-    for (int j = 0; j < kMaxBeam; ++j) {
+    for (int j = 0; j < B; ++j) {
       const bool in = j < cnt[r] && j < a.beam;
       const int64_t k = (s0 + (in ? r : 0)) * kMaxBeam + (in ? j : 0);
       ks[r][j] = in ? a.kid_score[b][k] : -k_inf<float>();
@@ -453,13 +456,13 @@ KF_HD inline void select_slot(const SearchArgs& a, int step, int64_t s) {
   int32_t key = 0;
   bool open = true;   // every output so far had a child
 #pragma unroll
-  for (int out = 0; out < kMaxBeam; ++out) {
+  for (int out = 0; out < B; ++out) {
     if (out > me || !open) continue;
     int best = -1, bpos = 0;
     float bs = 0.f;
     int32_t bk = 0;
 #pragma unroll
-    for (int r = 0; r < kMaxBeam; ++r) {
+    for (int r = 0; r < B; ++r) {
       if (taken[r] < cnt[r] && (best < 0 || child_before(ks[r][0], kk[r][0], r, bs, bk, best))) {
         best = r;
         bpos = taken[r];
@@ -478,10 +481,10 @@ KF_HD inline void select_slot(const SearchArgs& a, int step, int64_t s) {
       key = bk;
     }
 #pragma unroll
-    for (int r = 0; r < kMaxBeam; ++r) {
+    for (int r = 0; r < B; ++r) {
       if (r == best) {
 #pragma unroll
-        for (int j = 0; j + 1 < kMaxBeam; ++j) {
+        for (int j = 0; j + 1 < B; ++j) {
           ks[r][j] = ks[r][j + 1];
           kk[r][j] = kk[r][j + 1];
         }
