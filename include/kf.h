@@ -428,7 +428,7 @@ typedef struct {
  * ids, which must be distinct, are what the output reports and what breaks
  * ties), pool_module[n_pool] (device, the detector module of each hit; may
  * be NULL when params->overlap is 0).  The call bins the pool by (layer, phi, z) into a context-owned
- * workspace (about 64 bytes per pool hit and per candidate slot; grown on
+ * workspace (about 64 bytes per pool hit and 9 bytes per candidate slot and plan layer; grown on
  * demand, KF_ERR_NOMEM if that fails), unless params->reuse_bins allows the
  * bins of the previous call to be used.  The per-layer parameters of the
  * plan are copied from host memory into that workspace on `stream` (a

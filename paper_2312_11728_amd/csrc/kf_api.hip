@@ -931,9 +931,7 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   const int64_t nsum = n_bins / 2048 + 2;
   const int64_t b_bins = up(n_bins * 4), b_pool4 = up(n_pool * 4), b_sum = up(nsum * 4) + 256;
   const int64_t b_pool = up(n_pool * int64_t(sizeof(kf::PoolHit))) + up((n_bins + 1) * 4);
-  const int64_t b_slot = 2 * (up(S * 6 * 4) + up(S * 21 * 4) + up(S)) +
-                         2 * (3 * up(S * kf::kMaxBeam * 4) + up(S * 4) + up(S)) +
-                         up(S) + up(S * 4) + up(S * 4) + up(S) + up(P * S) + 2 * up(P * S * 4) +
+  const int64_t b_slot = up(P * S) + 2 * up(P * S * 4) +
                          up(P * int64_t(sizeof(kf::SearchLayer)));
   const int64_t total = b_bins + 2 * b_pool4 + b_sum + b_pool + b_slot;
   if (size_t(total) > ctx->search_bytes) {
@@ -997,22 +995,6 @@ int kf_score_hits(kf_ctx* ctx, int64_t n, int64_t ld, const float* seed_state, c
   a.pool = w.pool.hits;
   a.bin_off = w.pool.bin_off;
   a.n_pool = n_pool;
-  for (int k = 0; k < 2; ++k) {
-    a.pred_p[k] = (float*)take(up(S * 6 * 4));
-    a.pred_c[k] = (float*)take(up(S * 21 * 4));
-    a.pred_q[k] = (int8_t*)take(up(S));
-  }
-  for (int k = 0; k < 2; ++k) {
-    a.kid_score[k] = (float*)take(up(S * kf::kMaxBeam * 4));
-    a.kid_id[k] = (int32_t*)take(up(S * kf::kMaxBeam * 4));
-    a.kid_idx[k] = (int32_t*)take(up(S * kf::kMaxBeam * 4));
-    a.kid_n[k] = (int32_t*)take(up(S * 4));
-    a.cur_miss[k] = (int8_t*)take(up(S));
-  }
-  a.sel_parent = (int8_t*)take(up(S));
-  a.sel_idx = (int32_t*)take(up(S * 4));
-  a.sel_score = (float*)take(up(S * 4));
-  a.sel_miss = (int8_t*)take(up(S));
   a.hist_parent = (int8_t*)take(up(P * S));
   a.hist_id = (int32_t*)take(up(P * S * 4));
   a.hist_ovl = (int32_t*)take(up(P * S * 4));

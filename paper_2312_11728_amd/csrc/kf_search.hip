@@ -126,37 +126,49 @@ __global__ void __launch_bounds__(256) bin_scatter_kernel(BinTable t, const floa
 
 // The whole search in one launch.  Block b owns the seeds [b * spb,
 // (b + 1) * spb), spb = blockDim.x / beam, and their slots: thread i <
-// spb * beam is slot b * spb * beam + i.  At every layer the slot runs the
-// previous layer's selection for itself, then its extend; after the last
-// layer, the last selection and the final pass.  A seed's slots exchange
-// data (child lists, predicted states, histories) only with each other,
-// through global memory, and one block barrier per layer orders every
-// exchange, so blocks never wait for one another: each runs its seeds
-// through the layers at its own pace.
+// spb * beam is slot b * spb * beam + i.  At every layer the slot first
+// runs the previous layer's selection for itself (its candidate and that
+// candidate's state, read from its seed's slots in LDS), then, after a
+// block barrier, its extend, which leaves its child list and the state it
+// goes on with in LDS for the next selection; a second barrier closes the
+// layer.  After the last layer come the last selection and the final pass.
+// A seed's slots exchange data only with each other, so blocks never wait
+// for one another: each runs its seeds through the layers at its own pace.
 // B: a compile-time bound on beam (2, 4, 6 or 8), the size of the child
-// lists held in registers.
+// lists held in registers and LDS.
 template <int B>
-__global__ void __launch_bounds__(kSearchBlock, 2) search_kernel(SearchArgs a, const SearchLayer* __restrict__ layers) {
-  const int spb = int(blockDim.x) / a.beam;
+__global__ void __launch_bounds__(kSearchBlock, kSearchWaves) search_kernel(SearchArgs a,
+                                                                          const SearchLayer* __restrict__ layers) {
+  __shared__ SlotExchange<B> X;
+  const int spb = kSearchBlock / a.beam;
+  const int i = int(threadIdx.x);
   const int64_t seed0 = int64_t(blockIdx.x) * spb;
-  const int64_t s = seed0 * a.beam + threadIdx.x;
-  const int64_t t = seed0 + threadIdx.x;
-  const bool slot = int(threadIdx.x) < spb * a.beam && s < a.n * a.beam;
+  const int64_t s = seed0 * a.beam + i;
+  const int64_t t = seed0 + i;
+  const bool slot = i < spb * a.beam && s < a.n * a.beam;
   // the seeds' status words collect the bits of their slots' steps
-  if (int(threadIdx.x) < spb && t < a.n) a.status[t] = 0u;
+  if (i < spb && t < a.n) a.status[t] = 0u;
   __syncthreads();
-  for (int k = 0; k < a.plan_len; ++k) {
+  Cand k;
+  k.live = false;
+  for (int step = 0; step < a.plan_len; ++step) {
     if (slot) {
-      if (k > 0) select_slot<B>(a, k - 1, s);
-      const uint32_t st = extend_slot<B>(a, layers[k], layers[k > 0 ? k - 1 : 0], k, s);
+      if (step == 0)
+        seed_candidate(a, s, k);
+      else
+        select_slot<B>(a, X, step - 1, s, i, k);
+    }
+    __syncthreads();
+    if (slot) {
+      const uint32_t st = extend_candidate<B>(a, X, layers[step], layers[step > 0 ? step - 1 : 0], step, s, i, k);
       if (st) atomicOr(&a.status[s / a.beam], st);
     }
     __syncthreads();
   }
-  if (slot) select_slot<B>(a, a.plan_len - 1, s);
+  if (slot) select_slot<B>(a, X, a.plan_len - 1, s, i, k);
   __syncthreads();
   if (slot) {
-    const uint32_t st = finish_slot(a, layers[a.plan_len - 1], s);
+    const uint32_t st = finish_candidate(a, layers[a.plan_len - 1], s, k);
     if (st) atomicOr(&a.status[s / a.beam], st);
   }
 }

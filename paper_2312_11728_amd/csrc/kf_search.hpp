@@ -32,6 +32,17 @@
 namespace kf {
 
 constexpr int kMaxBeam = 8;
+// threads (slots) of a search block: one wave
+#ifndef KF_SEARCH_BLOCK
+#define KF_SEARCH_BLOCK 64
+#endif
+constexpr int kSearchBlock = KF_SEARCH_BLOCK;
+// waves per SIMD the search kernel's register allocation must allow
+#ifndef KF_SEARCH_WAVES
+#define KF_SEARCH_WAVES 2
+#endif
+constexpr int kSearchWaves = KF_SEARCH_WAVES;
+static_assert(kSearchBlock >= kMaxBeam && kSearchBlock <= 1024, "search block size");
 constexpr float kBinArc = 0.5f;   // pool bin size along r-phi (cm)
 constexpr float kBinZ = 1.0f;     // pool bin size along z (cm)
 constexpr int32_t kMissKey = 0x7ffffffe;   // ranking keys of a miss and a stop
@@ -101,22 +112,9 @@ struct SearchArgs {
   const PoolHit* pool;           // [n_pool] in bin order
   const int32_t* bin_off;        // [n_bins + 1]
   int64_t n_pool;
-  // slots (S = n * beam; slot = seed * beam + rank)
-  float* pred_p[2];              // [6][S] predicted state at the current / previous layer
-  float* pred_c[2];              // [21][S]
-  int8_t* pred_q[2];             // [S]
-  // child lists and misses, by parity of the plan step (the selection of
-  // step k reads those of step k while the extend of step k + 1 writes the
-  // others)
-  float* kid_score[2];           // [S][kMaxBeam] sorted child list of each slot
-  int32_t* kid_id[2];
-  int32_t* kid_idx[2];           // binned pool index, kMissIdx, kStopIdx
-  int32_t* kid_n[2];             // [S]
-  int8_t* cur_miss[2];           // [S] misses of the slot's candidate
-  int8_t* sel_parent;            // [S] parent rank of the slot's candidate, -1 = none
-  int32_t* sel_idx;              // [S] binned pool index of its hit, kMissIdx, kStopIdx
-  float* sel_score;              // [S]
-  int8_t* sel_miss;              // [S]
+  // slots (S = n * beam; slot = seed * beam + rank); what a seed's slots
+  // hand on from layer to layer lives in LDS (SlotExchange), the histories
+  // in global memory
   int8_t* hist_parent;           // [plan_len][S]
   int32_t* hist_id;              // [plan_len][S] caller's hit id, -1 = miss, -3 = stopped
   uint32_t* status;              // [n]
@@ -144,15 +142,6 @@ KF_HD inline void load_pool_hit(const SearchArgs& a, int32_t h, float m[3], floa
   m[2] = ph.z;
 #pragma unroll
   for (int i = 0; i < 6; ++i) V[i] = ph.cov[i];
-}
-
-KF_HD inline void load_slot(const float* P, const float* C, const int8_t* Q, int64_t S, int64_t s, float p[6],
-                            float c[21], int& q) {
-#pragma unroll
-  for (int i = 0; i < 6; ++i) p[i] = P[i * S + s];
-#pragma unroll
-  for (int i = 0; i < 21; ++i) c[i] = C[i * S + s];
-  q = Q[s];
 }
 
 // chi2 = r^T (C_pos + V)^-1 r of the predicted state (p, c) and hit (m, V).
@@ -237,71 +226,179 @@ KF_HD inline int32_t pick_overlap(const SearchArgs& a, const SearchLayer& L, int
   return best_id;
 }
 
-// Extend the candidate of slot s (see the file comment).  Returns the status
-// bits of its steps.
-// B: a bound on beam known at compile time (the lists' register size).
+// What the slots of a block's seeds hand on from one layer to the next,
+// in LDS, indexed by the slot's place in the block: the state its candidate
+// goes on with (the predicted state, or the state it entered the layer with
+// if it stops there; p, c, then the charge), its child list at the layer
+// (best first) and its candidate's misses.
 template <int B>
-KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, const SearchLayer& Lp, int step,
-                                  int64_t s) {
-  const int64_t S = a.n * a.beam;
-  const int64_t seed = s / a.beam;
-  const int r = int(s % a.beam);
-  const int cur = step & 1, prv = cur ^ 1;
-  float p[6], c[21];
-  int q = 1, prev;
+struct SlotExchange {
+  float state[28][kSearchBlock];
+  float kid_score[B][kSearchBlock];
+  int32_t kid_id[B][kSearchBlock];
+  int32_t kid_idx[B][kSearchBlock];
+  int32_t kid_n[kSearchBlock];
+  int32_t miss[kSearchBlock];
+};
+
+// A slot's candidate for the next layer, as the selection leaves it.
+struct Cand {
+  bool live;        // the slot has a candidate
+  int32_t idx;      // binned pool index of its hit on the layer it left, kMissIdx, kStopIdx
   float score;
   int miss;
-  uint32_t st = 0;
-  bool stopped = false;
-  int32_t* const kid_n = a.kid_n[cur];
-  float* const kid_score = a.kid_score[cur];
-  int32_t* const kid_id = a.kid_id[cur];
-  int32_t* const kid_idx = a.kid_idx[cur];
-  kid_n[s] = 0;
-  if (step == 0) {
-    if (r != 0) return 0;
+  int q;
+  float p[6], c[21];
+};
+
+// The seed's own candidate at the first layer (rank 0 only): its state, no
+// hit to apply.
+KF_HD inline void seed_candidate(const SearchArgs& a, int64_t s, Cand& k) {
+  const int64_t seed = s / a.beam;
+  k.live = s % a.beam == 0;
+  if (!k.live) return;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) p[i] = a.seed_state[i * a.ld + seed];
+  for (int i = 0; i < 6; ++i) k.p[i] = a.seed_state[i * a.ld + seed];
 #pragma unroll
-    for (int i = 0; i < 21; ++i) c[i] = a.seed_cov[i * a.ld + seed];
-    q = a.seed_charge[seed];
-    prev = a.seed_layer[seed];
-    score = 0.f;
-    miss = 0;
-  } else {
-    const int par = a.sel_parent[s];
-    if (par < 0) return 0;
-    load_slot(a.pred_p[prv], a.pred_c[prv], a.pred_q[prv], S, seed * a.beam + par, p, c, q);
-    const int32_t h = a.sel_idx[s];
-    float ovl = 0.f;
-    if (h >= 0) {
-      float m[3], V[6], c2;
-      load_pool_hit(a, h, m, V);
-      update(p, c, q, m, V, c2, st);
-      if (a.overlap) {
-        float oc2 = 0.f;
-        const int32_t oid = pick_overlap(a, Lp, h, p, c, q, oc2, st);
-        a.hist_ovl[int64_t(step - 1) * S + s] = oid;
-        if (oid >= 0) ovl = a.overlap_bonus - oc2;
+  for (int i = 0; i < 21; ++i) k.c[i] = a.seed_cov[i * a.ld + seed];
+  k.q = a.seed_charge[seed];
+  k.idx = kMissIdx;
+  k.score = 0.f;
+  k.miss = 0;
+}
+
+// The selection of plan step `step` for the slot at place i of its block
+// (slot s): the child lists of the seed's slots are merged into the seed's
+// next candidates, and the slot takes the one of its rank, with its
+// parent's state; its history entry of the step goes to global memory.
+// Every slot of a seed runs the same merge, each keeps its own result.
+template <int B>
+KF_HD inline void select_slot(const SearchArgs& a, const SlotExchange<B>& X, int step, int64_t s, int i, Cand& k) {
+  const int64_t S = a.n * a.beam;
+  const int i0 = (i / a.beam) * a.beam;
+  const int me = i - i0;
+  // The child lists of the seed's slots, read at once: each is sorted best
+  // first, so only its first `beam` entries can be chosen; absent entries
+  // rank last.  The heads of the lists compete (ties by child id, then by
+  // the parent's rank), and the chosen list moves up by one place; every
+  // index is static, so the lists stay in registers.
+  float ks[B][B];
+  int32_t kk[B][B];
+  int cnt[B], taken[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    cnt[r] = r < a.beam ? X.kid_n[r < a.beam ? i0 + r : i0] : 0;
+    taken[r] = 0;
+  }
+  // (absent entries read a valid place and discard it)
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const bool in = j < cnt[r] && j < a.beam;
+      const int ir = in ? i0 + r : i0, jr = in ? j : 0;
+      ks[r][j] = in ? X.kid_score[jr][ir] : -k_inf<float>();
+      kk[r][j] = in ? X.kid_id[jr][ir] : kStopKey;
+    }
+  // outputs 0 .. me in turn; the last one chosen is this slot's
+  int par = -1, pos = 0;
+  float score = 0.f;
+  int32_t key = 0;
+  bool open = true;   // every output so far had a child
+#pragma unroll
+  for (int out = 0; out < B; ++out) {
+    if (out > me || !open) continue;
+    int best = -1, bpos = 0;
+    float bs = 0.f;
+    int32_t bk = 0;
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      if (taken[r] < cnt[r] && (best < 0 || child_before(ks[r][0], kk[r][0], r, bs, bk, best))) {
+        best = r;
+        bpos = taken[r];
+        bs = ks[r][0];
+        bk = kk[r][0];
       }
     }
-    prev = L.prev_layer;
-    score = a.sel_score[s] + ovl;
-    miss = a.sel_miss[s];
-    stopped = h == kStopIdx;   // carried unchanged
+    if (best < 0) {
+      open = false;
+      continue;
+    }
+    if (out == me) {
+      par = best;
+      pos = bpos;
+      score = bs;
+      key = bk;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      if (r == best) {
+#pragma unroll
+        for (int j = 0; j + 1 < B; ++j) {
+          ks[r][j] = ks[r][j + 1];
+          kk[r][j] = kk[r][j + 1];
+        }
+        ++taken[r];
+      }
+    }
   }
+  k.live = par >= 0;
+  if (!k.live) return;
+  const int32_t idx = X.kid_idx[pos][i0 + par];
+  k.idx = idx;
+  k.score = score;
+  k.miss = X.miss[i0 + par] + (idx == kMissIdx ? 1 : 0);
+#pragma unroll
+  for (int v = 0; v < 6; ++v) k.p[v] = X.state[v][i0 + par];
+#pragma unroll
+  for (int v = 0; v < 21; ++v) k.c[v] = X.state[6 + v][i0 + par];
+  k.q = int(X.state[27][i0 + par]);
+  a.hist_parent[int64_t(step) * S + s] = int8_t(par);
+  a.hist_id[int64_t(step) * S + s] = idx >= 0 ? key : idx;
+  if (a.overlap) a.hist_ovl[int64_t(step) * S + s] = kMissIdx;
+}
+
+// Extend candidate k of the slot at place i of its block (slot s) to layer
+// L (see the file comment): its child list and the state it goes on with
+// are left in X.  Returns the status bits of its steps.
+template <int B>
+KF_HD inline uint32_t extend_candidate(const SearchArgs& a, SlotExchange<B>& X, const SearchLayer& L,
+                                       const SearchLayer& Lp, int step, int64_t s, int i, Cand& k) {
+  const int64_t S = a.n * a.beam;
+  X.kid_n[i] = 0;
+  if (!k.live) return 0;
+  float* const p = k.p;
+  float* const c = k.c;
+  int q = k.q;
+  uint32_t st = 0;
+  float ovl = 0.f;
+  if (k.idx >= 0) {
+    float m[3], V[6], c2;
+    load_pool_hit(a, k.idx, m, V);
+    update(p, c, q, m, V, c2, st);
+    if (a.overlap) {
+      float oc2 = 0.f;
+      const int32_t oid = pick_overlap(a, Lp, k.idx, p, c, q, oc2, st);
+      a.hist_ovl[int64_t(step - 1) * S + s] = oid;
+      if (oid >= 0) ovl = a.overlap_bonus - oc2;
+    }
+  }
+  const int prev = step == 0 ? a.seed_layer[s / a.beam] : L.prev_layer;
+  const float score = k.score + ovl;
+  const int miss = k.miss;
+  const bool stopped = k.idx == kStopIdx;   // carried unchanged
   // the state entering the layer, kept if the candidate stops here
 #pragma unroll
-  for (int i = 0; i < 6; ++i) a.pred_p[cur][i * S + s] = p[i];
+  for (int v = 0; v < 6; ++v) X.state[v][i] = p[v];
 #pragma unroll
-  for (int i = 0; i < 21; ++i) a.pred_c[cur][i * S + s] = c[i];
-  a.pred_q[cur][s] = int8_t(q);
-  a.cur_miss[cur][s] = int8_t(miss);
+  for (int v = 0; v < 21; ++v) X.state[6 + v][i] = c[v];
+  X.state[27][i] = float(q);
+  X.miss[i] = miss;
   if (stopped || !propagate(p, c, q, 0, L.R, L.x0, prev == L.layer, true, a.bz, a.mass, st)) {
-    kid_score[s * kMaxBeam] = score;
-    kid_id[s * kMaxBeam] = kStopKey;
-    kid_idx[s * kMaxBeam] = kStopIdx;
-    kid_n[s] = 1;
+    X.kid_score[0][i] = score;
+    X.kid_id[0][i] = kStopKey;
+    X.kid_idx[0][i] = kStopIdx;
+    X.kid_n[i] = 1;
     return st;
   }
   // window
@@ -365,7 +462,7 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
         const float m[3] = {ph.x, ph.y, ph.z};
         float V[6];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) V[i] = ph.cov[i];
+        for (int v = 0; v < 6; ++v) V[v] = ph.cov[v];
         const float c2 = hit_chi2(p, c, m, V, st);
         if (!(c2 <= a.chi2_max)) continue;
         // insert (score, id) into the sorted list; the last entry drops out
@@ -400,139 +497,50 @@ KF_HD inline uint32_t extend_slot(const SearchArgs& a, const SearchLayer& L, con
   if (ki[0] != kStopIdx) {
     // the candidate goes on from the predicted state
 #pragma unroll
-    for (int i = 0; i < 6; ++i) a.pred_p[cur][i * S + s] = p[i];
+    for (int v = 0; v < 6; ++v) X.state[v][i] = p[v];
 #pragma unroll
-    for (int i = 0; i < 21; ++i) a.pred_c[cur][i * S + s] = c[i];
-    a.pred_q[cur][s] = int8_t(q);
+    for (int v = 0; v < 21; ++v) X.state[6 + v][i] = c[v];
+    X.state[27][i] = float(q);
   }
   const int n_out = nk < a.beam ? nk : a.beam;
 #pragma unroll
   for (int j = 0; j < B; ++j) {
     if (j < n_out) {
-      kid_score[s * kMaxBeam + j] = ks[j];
-      kid_id[s * kMaxBeam + j] = kk[j];
-      kid_idx[s * kMaxBeam + j] = ki[j];
+      X.kid_score[j][i] = ks[j];
+      X.kid_id[j][i] = kk[j];
+      X.kid_idx[j][i] = ki[j];
     }
   }
-  kid_n[s] = n_out;
+  X.kid_n[i] = n_out;
   return st;
 }
 
-// The selection of plan step `step` for slot s: the child lists of the
-// slots of s's seed are merged into the seed's next candidates, and s takes
-// the one of its rank.  Every slot of a seed runs the same merge, each keeps
-// its own result.
-template <int B>
-KF_HD inline void select_slot(const SearchArgs& a, int step, int64_t s) {
-  const int64_t S = a.n * a.beam;
-  const int64_t s0 = (s / a.beam) * a.beam;
-  const int me = int(s - s0);
-  const int b = step & 1;
-  // The child lists of the seed's slots, read at once: each is sorted best
-  // first, so only its first `beam` entries can be chosen; absent entries
-  // rank last.  The heads of the lists compete (ties by child id, then by
-  // the parent's rank), and the chosen list moves up by one place; every
-  // index is static, so the lists stay in registers.
-  float ks[B][B];
-  int32_t kk[B][B];
-  int cnt[B], taken[B];
-#pragma unroll
-  for (int r = 0; r < B; ++r) {
-    cnt[r] = r < a.beam ? a.kid_n[b][s0 + r] : 0;
-    taken[r] = 0;
-  }
-#pragma unroll
-  for (int r = 0; r < B; ++r)
-#pragma unroll
-    for (int j = 0; j < B; ++j) {
-      const bool in = j < cnt[r] && j < a.beam;
-      const int64_t k = (s0 + (in ? r : 0)) * kMaxBeam + (in ? j : 0);
-      ks[r][j] = in ? a.kid_score[b][k] : -k_inf<float>();
-      kk[r][j] = in ? a.kid_id[b][k] : kStopKey;
-    }
-  // outputs 0 .. me in turn; the last one chosen is this slot's
-  int par = -1, pos = 0;
-  float score = 0.f;
-  int32_t key = 0;
-  bool open = true;   // every output so far had a child
-#pragma unroll
-  for (int out = 0; out < B; ++out) {
-    if (out > me || !open) continue;
-    int best = -1, bpos = 0;
-    float bs = 0.f;
-    int32_t bk = 0;
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      if (taken[r] < cnt[r] && (best < 0 || child_before(ks[r][0], kk[r][0], r, bs, bk, best))) {
-        best = r;
-        bpos = taken[r];
-        bs = ks[r][0];
-        bk = kk[r][0];
-      }
-    }
-    if (best < 0) {
-      open = false;
-      continue;
-    }
-    if (out == me) {
-      par = best;
-      pos = bpos;
-      score = bs;
-      key = bk;
-    }
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      if (r == best) {
-#pragma unroll
-        for (int j = 0; j + 1 < B; ++j) {
-          ks[r][j] = ks[r][j + 1];
-          kk[r][j] = kk[r][j + 1];
-        }
-        ++taken[r];
-      }
-    }
-  }
-  if (par < 0) {
-    a.sel_parent[s] = -1;
-    return;
-  }
-  const int32_t idx = a.kid_idx[b][(s0 + par) * kMaxBeam + pos];
-  a.sel_parent[s] = int8_t(par);
-  a.sel_idx[s] = idx;
-  a.sel_score[s] = score;
-  a.sel_miss[s] = int8_t(a.cur_miss[b][s0 + par] + (idx == kMissIdx ? 1 : 0));
-  a.hist_parent[int64_t(step) * S + s] = int8_t(par);
-  a.hist_id[int64_t(step) * S + s] = idx >= 0 ? key : idx;
-  if (a.overlap) a.hist_ovl[int64_t(step) * S + s] = kMissIdx;
-}
-
-// After the last layer: the kept candidates' final states (update with their
-// last hit), scores and hit lists (backtracked through the parents).
-KF_HD inline uint32_t finish_slot(const SearchArgs& a, const SearchLayer& Llast, int64_t s) {
+// After the last layer and its selection: candidate k's final state
+// (update with its last hit), score and hit list (backtracked through the
+// parents; every slot of the seed must have written its histories).
+KF_HD inline uint32_t finish_candidate(const SearchArgs& a, const SearchLayer& Llast, int64_t s, Cand& k) {
   const int64_t S = a.n * a.beam;
   const int64_t seed = s / a.beam;
   const int r = int(s % a.beam);
   const int P = a.plan_len;
   int32_t* out = a.cand_hits + s * P;
-  const int par = a.sel_parent[s];
   uint32_t st = 0;
   int32_t* ovl_out = a.cand_ovl ? a.cand_ovl + s * P : nullptr;
-  if (par < 0) {
-    for (int k = 0; k < P; ++k) out[k] = -2;
+  if (!k.live) {
+    for (int j = 0; j < P; ++j) out[j] = -2;
     if (ovl_out)
-      for (int k = 0; k < P; ++k) ovl_out[k] = -2;
+      for (int j = 0; j < P; ++j) ovl_out[j] = -2;
     a.cand_score[s] = -k_inf<float>();
     if (a.cand_state)
 #pragma unroll
-      for (int i = 0; i < 6; ++i) a.cand_state[i * S + s] = k_nan<float>();
+      for (int v = 0; v < 6; ++v) a.cand_state[v * S + s] = k_nan<float>();
     return 0;
   }
   {
-    const int last = (P - 1) & 1;
-    float p[6], c[21];
-    int q;
-    load_slot(a.pred_p[last], a.pred_c[last], a.pred_q[last], S, seed * a.beam + par, p, c, q);
-    const int32_t h = a.sel_idx[s];
+    float* const p = k.p;
+    float* const c = k.c;
+    int q = k.q;
+    const int32_t h = k.idx;
     float ovl = 0.f;
     if (h >= 0) {
       float m[3], V[6], c2;
@@ -547,14 +555,14 @@ KF_HD inline uint32_t finish_slot(const SearchArgs& a, const SearchLayer& Llast,
     }
     if (a.cand_state)
 #pragma unroll
-      for (int i = 0; i < 6; ++i) a.cand_state[i * S + s] = p[i];
-    a.cand_score[s] = a.sel_score[s] + ovl;
+      for (int v = 0; v < 6; ++v) a.cand_state[v * S + s] = p[v];
+    a.cand_score[s] = k.score + ovl;
   }
   int rr = r;
-  for (int k = P - 1; k >= 0; --k) {
-    const int64_t hs = int64_t(k) * S + seed * a.beam + rr;
-    out[k] = a.hist_id[hs];
-    if (ovl_out) ovl_out[k] = a.overlap ? a.hist_ovl[hs] : kMissIdx;
+  for (int j = P - 1; j >= 0; --j) {
+    const int64_t hs = int64_t(j) * S + seed * a.beam + rr;
+    out[j] = a.hist_id[hs];
+    if (ovl_out) ovl_out[j] = a.overlap ? a.hist_ovl[hs] : kMissIdx;
     rr = a.hist_parent[hs];
   }
   return st;

@@ -25,11 +25,6 @@ struct SearchWork {
 
 hipError_t launch_bin_pool(const BinTable& t, const float* pos, const float* cov, const int32_t* id,
                            const int32_t* module, int64_t n, int64_t n_bins, const SearchWork& w, hipStream_t s);
-// threads of a search block
-#ifndef KF_SEARCH_BLOCK
-#define KF_SEARCH_BLOCK 64
-#endif
-constexpr int kSearchBlock = KF_SEARCH_BLOCK;
 // layers: the plan's host array (a.plan_len entries), copied to d_layers on
 // the stream before the search kernel reads it there
 hipError_t launch_search(SearchArgs a, const SearchLayer* layers, SearchLayer* d_layers, hipStream_t s);
