@@ -463,11 +463,12 @@ KF_HD inline uint32_t extend_candidate(const SearchArgs& a, SlotExchange<B>& X, 
         float V[6];
 #pragma unroll
         for (int v = 0; v < 6; ++v) V[v] = ph.cov[v];
+        const int32_t ph_id = ph.id;
         const float c2 = hit_chi2(p, c, m, V, st);
         if (!(c2 <= a.chi2_max)) continue;
         // insert (score, id) into the sorted list; the last entry drops out
         float ns = score + a.hit_bonus - c2;
-        int32_t nkey = ph.id, nidx = h;
+        int32_t nkey = ph_id, nidx = h;
 #pragma unroll
         for (int j = 0; j < B; ++j) {
           if (j < a.beam && child_before(ns, nkey, 0, ks[j], kk[j], 0)) {

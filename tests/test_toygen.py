@@ -33,6 +33,17 @@ def test_hits_on_surfaces_and_lengths():
     assert 0.05 < (L == 9).mean() < 0.10 and set(np.unique(L)) <= {9, 10}
 
 
+def test_early_stops_cover_short_lengths():
+    """A quarter of the mixed-detector batch's central tracks end after
+    3 .. n of their n crossings, so that the batch holds every length from 3
+    to 26, and every track can still be seeded."""
+    wl = workloads()["mixed26"]
+    L = generate(wl, 20_000).lengths()
+    assert L.min() == 3 and L.max() <= 26
+    assert set(range(3, 9)) <= set(np.unique(L).tolist())
+    assert 0.03 < (L < 9).mean() < 0.09
+
+
 def test_hole_fraction():
     wl = workloads()["mixed26"]
     ev = generate(wl, 5000)

@@ -90,6 +90,7 @@ class Workload:
     misalign_rphi: float = 0.0  # sigma of per-layer true offsets (cm)
     misalign_z: float = 0.0
     noise_density: float = 0.0  # noise hits per cm^2 of barrel surface
+    stop_fraction: float = 0.0  # central tracks that end early (an interaction), after 3 .. n of their n crossings
     extra: dict = field(default_factory=dict)
 
 
@@ -103,7 +104,7 @@ def workloads() -> dict[str, Workload]:
         "barrel20": Workload("barrel20", g20, 100_000, 1002),
         # uneven lengths: barrel + endcaps, loopers, 5% holes
         "mixed26": Workload("mixed26", mixed_geometry(), 500_000, 1003, eta_max=2.5,
-                            mode="nearest", hole_fraction=0.05),
+                            mode="nearest", hole_fraction=0.05, stop_fraction=0.25),
         # combinatorial hit scoring with noise
         "search20": Workload("search20", g20, 20_000, 1004, noise_density=2.0),
         # adjoint with injected misalignment

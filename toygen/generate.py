@@ -295,7 +295,7 @@ def generate(wl: Workload, n_tracks: int | None = None, *, smear: bool = True,
     """Generate ``n_tracks`` tracks (default: the workload size)."""
     n = wl.n_tracks if n_tracks is None else int(n_tracks)
     ss = np.random.SeedSequence(wl.seed)
-    r_trk, r_smear, r_kick, r_hole, r_noise = [np.random.Generator(np.random.PCG64(c)) for c in ss.spawn(5)]
+    r_trk, r_smear, r_kick, r_hole, r_noise, r_stop = [np.random.Generator(np.random.PCG64(c)) for c in ss.spawn(6)]
     g = wl.geometry
 
     chunks = []
@@ -304,6 +304,13 @@ def generate(wl: Workload, n_tracks: int | None = None, *, smear: bool = True,
     while have < n:
         m = max(64, int((n - have) * over) + 16)
         q, vtx, lay, hit, cov, tru, aft, cnt = _simulate(wl, m, r_trk, r_smear, r_kick, smear, scatter)
+        if wl.stop_fraction > 0:
+            # a central track (|eta| < 1, barrel crossings only) that ends
+            # early keeps its first k crossings, k uniform in 3 .. n
+            central = np.abs(1.0 / np.tan(tru[:, 0, 5])) < np.sinh(1.0)
+            stop = (r_stop.uniform(0.0, 1.0, m) < wl.stop_fraction) & central
+            k = r_stop.integers(3, np.maximum(cnt, 3) + 1)
+            cnt = np.where(stop & (cnt > 3), np.minimum(k, cnt), cnt)
         valid = np.zeros(lay.shape, np.uint8)
         for i in range(lay.shape[1]):
             valid[:, i] = (i < cnt).astype(np.uint8)
