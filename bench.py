@@ -654,7 +654,7 @@ def profile_only(args, K, tune_fit, generate, workloads):
         a = argparse.Namespace(**vars(args))
         a.warmup = 1
         a.no_accuracy = True
-        r = bench_adjoint(ctx, K, generate, workloads, a) if args.profile_only == "adjoint" else \
+        r = bench_adjoint(ctx, K, generate, workloads, a, seg=args.seg) if args.profile_only == "adjoint" else \
             bench_search(ctx, K, a)
         log("profile-only", args.profile_only, json.dumps(r))
         return
@@ -710,6 +710,8 @@ def main():
     ap.add_argument("--tune-cache", default=os.path.join(tempfile.gettempdir(), "kf_autotune.json"))
     ap.add_argument("--launch", default=None,
                     help="profile-only: fit launch shape block,persistent,blocks_per_cu,waves,layout")
+    ap.add_argument("--seg", type=int, default=1,
+                    help="checkpoint spacing of the adjoint in --profile-only adjoint")
     ap.add_argument("--profile-only", choices=["fit32", "fit64", "mixed32", "adjoint", "search", "backward",
                                                "planes"],
                     help="only launch the named fit --steps times (for hardware-counter runs)")
