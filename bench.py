@@ -306,9 +306,10 @@ def bench_adjoint(ctx, K, generate, workloads, args, seg=1):
     gradient is taken at zero alignment offsets (the nominal geometry).
     seg = 1 stores the state before every entry (213 MB here, nothing
     against 288 GB of HBM) so that the reverse pass recomputes no segment;
-    the larger spacings trade memory for recomputation (seg 5: 45 MB of
-    checkpoints and a 58 MB buffer into which the reverse pass recomputes
-    each segment once; adjoint kernel ~1.5x the seg 1 time)."""
+    the larger spacings keep less between the forward fit and the adjoint
+    call (seg 5: 45 MB of checkpoints), which then recomputes every segment
+    once from its checkpoint in a kernel of its own before the reverse
+    sweep (~1.3x the seg 1 time)."""
     import torch
     dev = torch.device("cuda", 0)
     wl = workloads()["align20"]

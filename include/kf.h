@@ -475,10 +475,12 @@ int kf_score_hits(kf_ctx *ctx, int64_t n, int64_t ld,
  * trk_status[n]: the status kf_fit_tracks returned; tracks it stopped
  * (NO_CROSSING, NONFINITE, bad layer id) contribute only up to the entry
  * where they stopped.  Uses a context-owned buffer of 2 * 64 * ceil(n / 64)
- * values for the alignment reduction and, for seg > 1, n * seg * 29 values
- * holding the states of one checkpoint segment per track, so that each
- * segment is recomputed from its checkpoint once, in one pass (allocated on
- * first need, grown on demand, KF_ERR_NOMEM if that fails). */
+ * values for the alignment reduction and, for seg > 1, n * (max_len - 1) * 29
+ * values into which a pass before the reverse sweep recomputes the state
+ * before every entry, each checkpoint segment once from its checkpoint
+ * (allocated on first need, grown on demand, KF_ERR_NOMEM if that fails);
+ * the checkpoints alone are what the caller keeps between the forward fit
+ * and this call. */
 int kf_fit_adjoint(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                    const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
                    const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
@@ -496,7 +498,7 @@ int kf_fit_adjoint(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
  * (4 MiB per device, held until the process ends) instead of the context's
  * growing workspace, and each state of a checkpoint segment is recomputed
  * from the segment's checkpoint when it is needed (the same steps from the
- * same values: the same bits) instead of being kept in a segment buffer.  No hipMalloc, hipFree or other allocating call is made.
+ * same values) instead of being kept in a state buffer.  No hipMalloc, hipFree or other allocating call is made.
  * Limit: with grad_align != NULL, n_hits <= 16,777,216 (FP32) or 8,388,608
  * (FP64); larger batches get KF_ERR_ARG (grad_align == NULL needs no
  * scratch and has no limit).  Every call on one device shares that device's

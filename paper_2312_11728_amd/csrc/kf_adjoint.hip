@@ -22,6 +22,24 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs<T> a, GeomArgs g) 
                 t, acc, len, e0);
 }
 
+// The states the reverse sweep reads, one thread per track (seg > 1 with a
+// state buffer): every checkpoint segment recomputed once, at the forward
+// fit's occupancy rather than under the reverse pass's registers.
+template <typename T>
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) refill_kernel(AdjArgs<T> a, GeomArgs g) {
+  __shared__ GeomLds<T> sg;
+  __shared__ T sal[2 * kMaxLayers];
+  stage_align(sal, a.f, g);
+  stage_geometry(sg, g);
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= a.f.n) return;
+  const int64_t e0 = a.f.hit_offsets[t];
+  const int len = int(a.f.hit_offsets[t + 1] - e0);
+  CsrTrack<T> acc{a.f, e0};
+  refill_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.f.align ? sal : nullptr,
+               t, acc, len);
+}
+
 // Stage 1: one wave per kAlignPerBlock consecutive entries of the batch
 // (entries hit_offsets[0] .. hit_offsets[n]), lane l taking entries l,
 // l + 64, ... of the block's range, so that every load of the wave is
@@ -88,6 +106,7 @@ template <typename T>
 hipError_t launch_adjoint(const AdjArgs<T>& a, const GeomArgs& g, hipStream_t s) {
   if (a.f.n > 0) {
     const int64_t grid = (a.f.n + 255) / 256;
+    if (a.seg_buf) hipLaunchKernelGGL(refill_kernel<T>, dim3(unsigned(grid)), dim3(256), 0, s, a, g);
     hipLaunchKernelGGL(adjoint_kernel<T>, dim3(unsigned(grid)), dim3(256), 0, s, a, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

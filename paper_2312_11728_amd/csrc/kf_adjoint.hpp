@@ -565,9 +565,10 @@ KF_HD inline void state_before(const AdjArgs<T>& a, const TrackGeom<T>& g, const
   }
 }
 
-// With a segment buffer: the states before entries js .. jhi (relative to
-// the first valid entry k0, 1 <= js <= jhi) of track t, recomputed from the
-// checkpoint of their segment in one pass and stored in slots 0 .. jhi - js.
+// With a state buffer: the states before entries js .. jhi (relative to the
+// first valid entry k0, 1 <= js <= jhi) of track t, recomputed from the
+// checkpoint of their segment in one pass and stored in slots js - 1 ..
+// jhi - 1 ([slot][kSegVals][n]).
 template <typename T, typename Acc>
 KF_HD inline void fill_segment(const AdjArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t t,
                                const Acc& acc, int k0, int js, int jhi) {
@@ -576,7 +577,7 @@ KF_HD inline void fill_segment(const AdjArgs<T>& a, const TrackGeom<T>& g, const
   int q, prev;
   state_before(a, g, sal, t, acc, k0, js, p, c, q, prev);
   for (int j = js;; ++j) {
-    T* slot = a.seg_buf + int64_t(j - js) * kSegVals * n + t;
+    T* slot = a.seg_buf + int64_t(j - 1) * kSegVals * n + t;
 #pragma unroll
     for (int i = 0; i < 6; ++i) slot[i * n] = p[i];
 #pragma unroll
@@ -592,6 +593,23 @@ KF_HD inline void fill_segment(const AdjArgs<T>& a, const TrackGeom<T>& g, const
     uint32_t sst = 0;
     step_forward(p, c, q, j, lay, prev, valid, m, V, g, sal, c2, sst);
     prev = lay;
+  }
+}
+
+// The states before entries 1 .. n_steps - 1 of track t (len entries) for
+// the reverse pass, segment by segment, each from its own checkpoint: the
+// same forward steps the reverse pass would take to reach each of them.
+template <typename T, typename Acc>
+KF_HD inline void refill_track(const AdjArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t t,
+                               const Acc& acc, int len) {
+  const FitArgs<T>& f = a.f;
+  if (len > f.max_len) len = f.max_len;
+  int k0 = 0;
+  while (k0 < len && !acc.valid(k0)) ++k0;
+  const int n_steps = len - k0;
+  for (int js = 1; js < n_steps; js += f.seg) {
+    const int jhi = js + f.seg - 1 < n_steps - 1 ? js + f.seg - 1 : n_steps - 1;
+    fill_segment(a, g, sal, t, acc, k0, js, jhi);
   }
 }
 
@@ -649,19 +667,12 @@ KF_HD inline void adjoint_track(const AdjArgs<T>& a, const TrackGeom<T>& g, cons
 #pragma unroll
   for (int i = 0; i < 21; ++i) cb[i] = 0.0;
   int q_after = q_end;
-  int cached = -1;   // first entry of the segment held in the segment buffer
   for (int j = n_done - 1; j >= 0; --j) {
     T p[6], c[21];
     int q, prev;
     if (a.seg_buf && j >= 1) {
-      // going down, the first entry met in a segment is its highest needed
-      // one: the segment is recomputed once, up to it
-      const int js = 1 + ((j - 1) / f.seg) * f.seg;
-      if (js != cached) {
-        fill_segment(a, g, sal, t, acc, k0, js, j);
-        cached = js;
-      }
-      const T* slot = a.seg_buf + int64_t(j - js) * kSegVals * f.n + t;
+      // recomputed by the refill pass
+      const T* slot = a.seg_buf + int64_t(j - 1) * kSegVals * f.n + t;
 #pragma unroll
       for (int i = 0; i < 6; ++i) p[i] = slot[i * f.n];
 #pragma unroll

@@ -1305,7 +1305,7 @@ int fit_adjoint_impl(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, cons
     // segment's states per track
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t need_part = grad_align ? up(size_t(kf::adjoint_partial_blocks(n_hits)) * 2 * kf::kMaxLayers * esz) : 0;
-    const size_t need_seg = seg > 1 ? up(size_t(n) * size_t(seg) * kf::kSegVals * esz) : 0;
+    const size_t need_seg = seg > 1 && max_len > 1 ? up(size_t(n) * size_t(max_len - 1) * kf::kSegVals * esz) : 0;
     const size_t need = need_part + need_seg;
     if (need > ctx->red_bytes) {
       int prev = 0;

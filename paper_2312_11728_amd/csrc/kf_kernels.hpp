@@ -159,10 +159,11 @@ struct AdjArgs {
   T* grad_hit;                 // [3][n_hits]
   T* grad_align;               // [2][n_layers] or null
   T* partial;                  // [adjoint_partial_blocks(n_hits)][2][kMaxLayers] when grad_align is set
-  // the states before the entries of one checkpoint segment, recomputed once
-  // per segment ([f.seg][kSegVals][n], (slot, value, track) at
-  // (slot * kSegVals + value) * n + track), or null: each state is then
-  // recomputed from its segment's checkpoint when it is needed
+  // the states before entries 1 .. max_len - 1 of every track, recomputed
+  // segment by segment from the checkpoints by a pass before the reverse
+  // sweep ([max_len - 1][kSegVals][n], entry j's state at
+  // ((j - 1) * kSegVals + value) * n + track), or null: each state is then
+  // recomputed from its segment's checkpoint when the reverse sweep needs it
   T* seg_buf;
 };
 constexpr int kSegVals = 29;   // state (6), covariance (21), charge, layer of the previous entry

@@ -2,7 +2,7 @@
 // address and undefined-behaviour sanitizers on the CPU.  The functions the
 // kernels call with one track per lane (seeding inside the forward fit, the
 // forward fit with checkpoints, the adjoint's reverse sweep with and without
-// its segment buffer, the forward fit over tilted modules) are host-device
+// its state buffer, the forward fit over tilted modules) are host-device
 // functions; this program calls them track by track on host memory.  It is a
 // test of the device code's memory accesses and arithmetic, not a product
 // path: nothing in the library calls it.
@@ -79,7 +79,7 @@ std::vector<T> as(const std::vector<double>& v) {
 }
 
 // Seeding, forward fit with checkpoints every `seg` entries, then the reverse
-// sweep twice: with the segment buffer and recomputing each state from its
+// sweep twice: with the state buffer and recomputing each state from its
 // checkpoint.  Both sweeps must give the same bits.
 template <typename T>
 int run_fit(const std::string& tag) {
@@ -148,11 +148,17 @@ int run_fit(const std::string& tag) {
   r.f.seed_charge = seed_q.data();
   r.w = w.data();
   r.fwd_status = status.data();
-  std::vector<T> gs(6 * n), gh(3 * nh), gs2(6 * n), gh2(3 * nh), segbuf(size_t(seg) * kf::kSegVals * n);
+  std::vector<T> gs(6 * n), gh(3 * nh), gs2(6 * n), gh2(3 * nh),
+      segbuf(size_t(max_len > 1 ? max_len - 1 : 1) * kf::kSegVals * n);
   for (int pass = 0; pass < 2; ++pass) {
     r.grad_seed = pass ? gs2.data() : gs.data();
     r.grad_hit = pass ? gh2.data() : gh.data();
     r.seg_buf = (pass == 0 && seg > 1) ? segbuf.data() : nullptr;
+    if (r.seg_buf)
+      for (int64_t t = 0; t < n; ++t) {
+        kf::CsrTrack<T> acc{r.f, off[t]};
+        kf::refill_track(r, g, use_align ? sal.data() : nullptr, t, acc, int(off[t + 1] - off[t]));
+      }
     for (int64_t t = 0; t < n; ++t) {
       const int64_t e0 = off[t];
       kf::CsrTrack<T> acc{r.f, e0};
@@ -173,7 +179,7 @@ int run_fit(const std::string& tag) {
   save(tag, "status", status.data(), status.size());
   save_f64(tag, "grad_seed", gs);
   save_f64(tag, "grad_hit", gh);
-  std::printf("fit%s: %lld tracks, adjoint with and without the segment buffer %s\n", tag.c_str(), (long long)n,
+  std::printf("fit%s: %lld tracks, adjoint with and without the state buffer %s\n", tag.c_str(), (long long)n,
               same ? "identical" : "DIFFERENT");
   return same ? 0 : 1;
 }

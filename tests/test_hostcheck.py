@@ -1,7 +1,7 @@
 """The per-track code of the HIP path built for the host under the address
 and undefined-behaviour sanitizers (tests/hostcheck): seeding and the forward
 fit with checkpoints on the mixed barrel + disk detector (with alignment
-offsets), the adjoint's reverse sweep with and without its segment buffer,
+offsets), the adjoint's reverse sweep with and without its state buffer,
 and the forward fit over tilted modules, in FP32 and FP64.  A sanitizer
 report ends the program with an error.  The FP64 results are held to the
 oracle at the GPU parity tolerances; the FP32 ones, whose host math library
