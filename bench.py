@@ -309,7 +309,7 @@ def bench_adjoint(ctx, K, generate, workloads, args, seg=1):
     the larger spacings keep less between the forward fit and the adjoint
     call (seg 5: 45 MB of checkpoints), which then recomputes every segment
     once from its checkpoint in a kernel of its own before the reverse
-    sweep (~1.3x the seg 1 time)."""
+    sweep (~1.2x the seg 1 time)."""
     import torch
     dev = torch.device("cuda", 0)
     wl = workloads()["align20"]

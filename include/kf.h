@@ -493,12 +493,15 @@ int kf_fit_adjoint(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
 
 /* kf_fit_adjoint for callers that cannot allocate device memory (code under
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
- * same arguments, kernels and results (bit-identical), but the block partials
- * of the alignment reduction live in a fixed device array of this library
- * (4 MiB per device, held until the process ends) instead of the context's
- * growing workspace, and each state of a checkpoint segment is recomputed
- * from the segment's checkpoint when it is needed (the same steps from the
- * same values) instead of being kept in a state buffer.  No hipMalloc, hipFree or other allocating call is made.
+ * same arguments, reverse kernel and results (to rounding: see below), but
+ * the block partials of the alignment reduction live in a fixed device array
+ * of this library (4 MiB per device, held until the process ends) instead of
+ * the context's growing workspace, and each state of a checkpoint segment is
+ * recomputed from the segment's checkpoint inside the reverse kernel when it
+ * is needed, instead of being read from a buffer a refill kernel fills.  The
+ * two run the same forward steps on the same values, compiled in two
+ * kernels, so at seg > 1 the gradients can differ in the last bits of the
+ * recomputed states (at seg 1 nothing is recomputed).  No hipMalloc, hipFree or other allocating call is made.
  * Limit: with grad_align != NULL, n_hits <= 16,777,216 (FP32) or 8,388,608
  * (FP64); larger batches get KF_ERR_ARG (grad_align == NULL needs no
  * scratch and has no limit).  Every call on one device shares that device's

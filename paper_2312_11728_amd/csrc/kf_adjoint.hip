@@ -22,22 +22,121 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs<T> a, GeomArgs g) 
                 t, acc, len, e0);
 }
 
-// The states the reverse sweep reads, one thread per track (seg > 1 with a
-// state buffer): every checkpoint segment recomputed once, at the forward
-// fit's occupancy rather than under the reverse pass's registers.
+// The states the reverse sweep reads (seg > 1 with a state buffer), one
+// thread per track, at the forward fit's occupancy rather than under the
+// reverse pass's registers: for every entry j >= 1 (relative to the track's
+// first valid entry), the state before it -- the checkpoint at the start of
+// each segment, then the segment's forward steps -- stored in slot j - 1.
+// These are the steps fill_segment takes, in the same order on the same
+// values.  The wave's hits come through LDS a few entries per track at a
+// time, as in the forward fit: all rows of a chunk are loaded before any is
+// written, consecutive lanes reading consecutive entries of one track (a
+// slot past a track's end loads its last entry and is never read).
+constexpr int kRefillBlock = 256;
+
+template <typename T, int J>
+__device__ void refill_wave_staged(const AdjArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t w0,
+                                   StageBuf<T, J>& sb) {
+  const FitArgs<T>& f = a.f;
+  const int lane = int(threadIdx.x) & 63;
+  const int64_t t = w0 + lane;
+  const bool in_range = t < f.n;
+  int64_t e0 = 0;
+  int len = 0;
+  if (in_range) {
+    e0 = f.hit_offsets[t];
+    len = int(f.hit_offsets[t + 1] - e0);
+    if (len > f.max_len) len = f.max_len;
+  }
+  sb.e0[lane] = e0;
+  sb.len[lane] = len;
+  const int kmax = wave_max(len);
+  const int64_t nh = f.n_hits, n = f.n, cst = f.ld * int64_t(f.n_seg);
+  T p[6], c[21];
+  int q = 0, prev = 0, prev_lay = 0, k0 = -1;
+  wave_sync();
+  for (int j0 = 0; j0 < kmax; j0 += J) {
+    int32_t lvr[J];
+    T vr[J][9];
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+      const int idx = r * 64 + lane;
+      const int l = idx / J, jj = idx % J;
+      const int ln = sb.len[l];
+      const int64_t e = ln > 0 ? sb.e0[l] + min(j0 + jj, ln - 1) : 0;
+      lvr[r] = int32_t(uint16_t(f.hit_layer[e])) | (f.hit_valid[e] ? (1 << 16) : 0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) vr[r][k] = f.hit_pos[k * nh + e];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) vr[r][3 + k] = f.hit_cov[k * nh + e];
+    }
+#pragma unroll
+    for (int r = 0; r < J; ++r) {
+      const int idx = r * 64 + lane;
+      const int l = idx / J, jj = idx % J;
+      sb.lv[jj][l] = lvr[r];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sb.v[k][jj][l] = vr[r][k];
+    }
+    wave_sync();
+    const int jn = min(J, kmax - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      const int k = j0 + jj;
+      if (!in_range || k >= len) continue;
+      const int32_t lv = sb.lv[jj][lane];
+      const bool valid = (lv >> 16) != 0;
+      const int lay = int16_t(lv & 0xffff);
+      if (k0 < 0) {
+        if (valid) k0 = k;   // entry j = 0: its state is the seed
+        prev_lay = lay;
+        continue;
+      }
+      const int j = k - k0;
+      if ((j - 1) % f.seg == 0) {
+        // a segment starts: its checkpoint, after entry j - 1 of layer prev_lay
+        const T* base = f.ckpt + int64_t((j - 1) / f.seg) * f.ld + t;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) p[i] = base[i * cst];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) c[i] = base[(6 + i) * cst];
+        q = int(base[27 * cst]);
+        prev = prev_lay;
+      }
+      T* slot = a.seg_buf + int64_t(j - 1) * kSegVals * n + t;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) slot[i * n] = p[i];
+#pragma unroll
+      for (int i = 0; i < 21; ++i) slot[(6 + i) * n] = c[i];
+      slot[27 * n] = T(q);
+      slot[28 * n] = T(prev);
+      if (j % f.seg != 0 && j + 1 < len - k0) {
+        T m[3], V[6];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) m[x] = sb.v[x][jj][lane];
+#pragma unroll
+        for (int x = 0; x < 6; ++x) V[x] = sb.v[3 + x][jj][lane];
+        T c2;
+        uint32_t sst = 0;
+        step_forward(p, c, q, j, lay, prev, valid, m, V, g, sal, c2, sst);
+        prev = lay;
+      }
+      prev_lay = lay;
+    }
+    wave_sync();   // every lane has read the chunk before the next one is staged
+  }
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) refill_kernel(AdjArgs<T> a, GeomArgs g) {
+__global__ void __launch_bounds__(kRefillBlock, sizeof(T) == 4 ? 2 : 1) refill_kernel(AdjArgs<T> a, GeomArgs g) {
+  constexpr int J = stage_entries<T, sizeof(T) == 4 ? 2 : 1>();
   __shared__ GeomLds<T> sg;
   __shared__ T sal[2 * kMaxLayers];
+  __shared__ StageBuf<T, J> sb[kRefillBlock / 64];
   stage_align(sal, a.f, g);
   stage_geometry(sg, g);
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.f.n) return;
-  const int64_t e0 = a.f.hit_offsets[t];
-  const int len = int(a.f.hit_offsets[t + 1] - e0);
-  CsrTrack<T> acc{a.f, e0};
-  refill_track(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)}, a.f.align ? sal : nullptr,
-               t, acc, len);
+  const int64_t w0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u);
+  refill_wave_staged<T, J>(a, TrackGeom<T>{sg.kind, sg.pos, sg.x0, g.n_layers, T(g.bz), T(g.mass)},
+                           a.f.align ? sal : nullptr, w0, sb[threadIdx.x >> 6]);
 }
 
 // Stage 1: one wave per kAlignPerBlock consecutive entries of the batch
@@ -106,7 +205,9 @@ template <typename T>
 hipError_t launch_adjoint(const AdjArgs<T>& a, const GeomArgs& g, hipStream_t s) {
   if (a.f.n > 0) {
     const int64_t grid = (a.f.n + 255) / 256;
-    if (a.seg_buf) hipLaunchKernelGGL(refill_kernel<T>, dim3(unsigned(grid)), dim3(256), 0, s, a, g);
+    if (a.seg_buf)
+      hipLaunchKernelGGL(refill_kernel<T>, dim3(unsigned((a.f.n + kRefillBlock - 1) / kRefillBlock)), dim3(kRefillBlock), 0,
+                         s, a, g);
     hipLaunchKernelGGL(adjoint_kernel<T>, dim3(unsigned(grid)), dim3(256), 0, s, a, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -599,6 +599,8 @@ KF_HD inline void fill_segment(const AdjArgs<T>& a, const TrackGeom<T>& g, const
 // The states before entries 1 .. n_steps - 1 of track t (len entries) for
 // the reverse pass, segment by segment, each from its own checkpoint: the
 // same forward steps the reverse pass would take to reach each of them.
+// This is the per-track form (host builds); the device kernel takes the same
+// steps with the wave's hits staged through LDS.
 template <typename T, typename Acc>
 KF_HD inline void refill_track(const AdjArgs<T>& a, const TrackGeom<T>& g, const T* __restrict__ sal, int64_t t,
                                const Acc& acc, int len) {

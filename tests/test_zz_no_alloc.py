@@ -1,10 +1,16 @@
 """The allocation-free adjoint entry point (kf_fit_adjoint_noalloc, through
-the C interface) against kf_fit_adjoint on the same inputs: the same kernels
-with the alignment reduction's block partials in the library's fixed device
-scratch instead of the context's workspace, so every output must be
-bit-identical.  Two calls in a row on one context, the second with a smaller
-batch (the scratch keeps the first call's partials, which the second must
-not read), in FP32 and FP64; and a batch beyond the scratch's size is refused
+the C interface) against kf_fit_adjoint on the same inputs.  It runs the
+same reverse kernel with the alignment reduction's block partials in the
+library's fixed device scratch instead of the context's workspace, and
+recomputes each state inside the reverse kernel instead of reading it from
+the refill kernel's buffer: the same forward steps compiled in two kernels,
+which may round differently in the last bit.  So the outputs are held to
+the adjoint's own tolerances (those it meets against the FP64 oracle, per
+track, relative L2): FP64 1e-6 (hits), 1e-5 (seed), 1e-8 (alignment); FP32
+5e-2 / 1e-1 / 2e-3 with medians below 1e-3.  Every output element must be
+written.  Two calls in a row on one context, the second with a smaller batch
+(the scratch keeps the first call's partials, which the second must not
+read), in FP32 and FP64; and a batch beyond the scratch's size is refused
 before any device work."""
 import sys
 
@@ -48,6 +54,25 @@ def _inputs(ctx, kf, ev, dt, seg):
     return args, dict(align=al, dL_dchi2=w)
 
 
+def _close(ev, ref, got, dt):
+    """Per-track relative L2 differences of the seed and hit gradients, and
+    of the alignment gradient, within the adjoint's tolerances."""
+    r = [x.double().cpu().numpy() for x in ref]
+    g = [x.double().cpu().numpy() for x in got]
+    es = np.linalg.norm(g[0] - r[0], axis=0) / np.maximum(np.linalg.norm(r[0], axis=0), 1e-300)
+    off = ev.hit_offsets
+    eh = np.array([np.linalg.norm(g[1][:, off[t]:off[t + 1]] - r[1][:, off[t]:off[t + 1]])
+                   / max(np.linalg.norm(r[1][:, off[t]:off[t + 1]]), 1e-300) for t in range(ev.n_tracks)])
+    ea = np.linalg.norm(g[2] - r[2]) / max(np.linalg.norm(r[2]), 1e-300)
+    say("  seed max %.2e median %.2e; hits max %.2e median %.2e; align %.2e"
+        % (es.max(), np.median(es), eh.max(), np.median(eh), ea))
+    if dt == torch.float64:
+        assert es.max() <= 1e-5 and eh.max() <= 1e-6 and ea <= 1e-8, (es.max(), eh.max(), ea)
+    else:
+        assert es.max() <= 1e-1 and eh.max() <= 5e-2 and ea <= 2e-3, (es.max(), eh.max(), ea)
+        assert np.median(es) <= 1e-3 and np.median(eh) <= 1e-3, (np.median(es), np.median(eh))
+
+
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
 def test_noalloc_adjoint_equals_adjoint_on_two_calls(kf, dt):
     ctx = kf.Context(0)
@@ -62,8 +87,9 @@ def test_noalloc_adjoint_equals_adjoint_on_two_calls(kf, dt):
             pre = tuple(torch.full_like(r, float("nan")) for r in ref)
             got = ctx.fit_adjoint(*args, **kw, no_alloc=True, out=pre)
             torch.cuda.synchronize()
-            for name, a, b in zip(("seed", "hit", "align"), ref, got):
-                assert torch.equal(a, b), (name, n, float((a - b).abs().max()))
+            for x in got:
+                assert torch.isfinite(x).all()
+            _close(ev, ref, got, dt)
             assert torch.isfinite(got[2]).all()
             assert float(got[2].abs().sum()) > 0.0
     finally:
