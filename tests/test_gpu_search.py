@@ -166,7 +166,11 @@ def test_misses_and_stops_on_the_gpu(ctx, kf):
             assert (gs["hits"] == KS.STOP).any()
 
 
-@pytest.mark.parametrize("beam,plan", [(1, PLAN), (8, PLAN), (6, PLAN[:1]), (3, PLAN[::2])])
+# every beam from 1 to 8 (the search kernel sizes its lists by a bound of 2,
+# 4, 6 or 8, so beams 2, 4, 6, 8 fill them and 1, 3, 5, 7 leave a place
+# unused); 500 seeds are not a multiple of the seeds per block (64 // beam)
+@pytest.mark.parametrize("beam,plan", [(1, PLAN), (2, PLAN), (3, PLAN[::2]), (4, PLAN), (5, PLAN), (6, PLAN[:1]),
+                                       (7, PLAN), (8, PLAN)])
 def test_search_beams_and_plans(ctx, kf, beam, plan):
     say("search beam", beam, "plan", len(plan))
     wl, ev, g, pools, p, C, q = search_inputs(500)
