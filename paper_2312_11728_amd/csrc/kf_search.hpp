@@ -277,29 +277,22 @@ KF_HD inline void select_slot(const SearchArgs& a, const SlotExchange<B>& X, int
   const int64_t S = a.n * a.beam;
   const int i0 = (i / a.beam) * a.beam;
   const int me = i - i0;
-  // The child lists of the seed's slots, read at once: each is sorted best
-  // first, so only its first `beam` entries can be chosen; absent entries
-  // rank last.  The heads of the lists compete (ties by child id, then by
-  // the parent's rank), and the chosen list moves up by one place; every
-  // index is static, so the lists stay in registers.
-  float ks[B][B];
-  int32_t kk[B][B];
+  // The heads of the seed's child lists (each sorted best first, only its
+  // first `beam` entries choosable) compete, ties by child id, then by the
+  // parent's rank; the chosen list's next entry, read from LDS, becomes its
+  // head.
   int cnt[B], taken[B];
+  float hs[B];
+  int32_t hk[B];
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     cnt[r] = r < a.beam ? X.kid_n[r < a.beam ? i0 + r : i0] : 0;
+    if (cnt[r] > a.beam) cnt[r] = a.beam;
     taken[r] = 0;
+    // (an empty list reads a valid place and discards it)
+    hs[r] = cnt[r] > 0 ? X.kid_score[0][cnt[r] > 0 ? i0 + r : i0] : -k_inf<float>();
+    hk[r] = cnt[r] > 0 ? X.kid_id[0][cnt[r] > 0 ? i0 + r : i0] : kStopKey;
   }
-  // (absent entries read a valid place and discard it)
-#pragma unroll
-  for (int r = 0; r < B; ++r)
-#pragma unroll
-    for (int j = 0; j < B; ++j) {
-      const bool in = j < cnt[r] && j < a.beam;
-      const int ir = in ? i0 + r : i0, jr = in ? j : 0;
-      ks[r][j] = in ? X.kid_score[jr][ir] : -k_inf<float>();
-      kk[r][j] = in ? X.kid_id[jr][ir] : kStopKey;
-    }
   // outputs 0 .. me in turn; the last one chosen is this slot's
   int par = -1, pos = 0;
   float score = 0.f;
@@ -313,11 +306,11 @@ KF_HD inline void select_slot(const SearchArgs& a, const SlotExchange<B>& X, int
     int32_t bk = 0;
 #pragma unroll
     for (int r = 0; r < B; ++r) {
-      if (taken[r] < cnt[r] && (best < 0 || child_before(ks[r][0], kk[r][0], r, bs, bk, best))) {
+      if (taken[r] < cnt[r] && (best < 0 || child_before(hs[r], hk[r], r, bs, bk, best))) {
         best = r;
         bpos = taken[r];
-        bs = ks[r][0];
-        bk = kk[r][0];
+        bs = hs[r];
+        bk = hk[r];
       }
     }
     if (best < 0) {
@@ -330,14 +323,19 @@ KF_HD inline void select_slot(const SearchArgs& a, const SlotExchange<B>& X, int
       score = bs;
       key = bk;
     }
+    int nc = 0;
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+      if (r == best) nc = cnt[r];
+    const bool more = bpos + 1 < nc;
+    const int jr = more ? bpos + 1 : 0;
+    const float ns = more ? X.kid_score[jr][i0 + best] : -k_inf<float>();
+    const int32_t nk = more ? X.kid_id[jr][i0 + best] : kStopKey;
 #pragma unroll
     for (int r = 0; r < B; ++r) {
       if (r == best) {
-#pragma unroll
-        for (int j = 0; j + 1 < B; ++j) {
-          ks[r][j] = ks[r][j + 1];
-          kk[r][j] = kk[r][j + 1];
-        }
+        hs[r] = ns;
+        hk[r] = nk;
         ++taken[r];
       }
     }
