@@ -327,10 +327,14 @@ int kf_smooth_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
  * forward fit stopped or could not be seeded in that round (the backward
  * pass did not refit it: there is no estimate from its other hits).  Entries outside the n tracks'
  * ranges are not written.
- * The rounds run on a context-owned workspace (about (2 * 28 + 55 * max_len)
- * values of the precision per track plus one byte per hit; grown on demand,
- * KF_ERR_NOMEM if that fails) and are enqueued without waiting for the device:
- * max_reject + 1 rounds, closed tracks costing a round almost nothing.  The
+ * The rounds run on a context-owned workspace (about (34 + 55 * max_len)
+ * values of the precision and 40 bytes per track, 10 values and 4 bytes per
+ * hit; grown on demand, KF_ERR_NOMEM if that fails).  At most max_reject + 1
+ * rounds: the first runs on all n tracks; after each round the tracks still
+ * open are gathered (their hits with them) into a compact sub-batch that the
+ * next round runs on, and the call waits for the stream once per round to
+ * read that count (it returns once the last round is enqueued, or at once
+ * when no track is left open).  The
  * forward fit runs in the context's launch shape for the precision (never in
  * a graph, never timed).
  * KF_ERR_ARG for chi2_cut not > 0 (NaN included), max_reject outside

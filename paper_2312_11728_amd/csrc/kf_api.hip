@@ -1049,6 +1049,12 @@ struct FinalWork {
   uint32_t *f_status, *b_status;
   int8_t *f_charge, *b_charge, *seed_charge;
   uint8_t *used, *open;
+  // the sub-batch of the open tracks after the first round
+  int32_t *flag, *len, *pos, *epos, *map, *sub_offsets, *counts;
+  int16_t* sub_layer;
+  uint8_t* sub_used;
+  void *sub_pos, *sub_cov, *scan_temp;
+  size_t scan_bytes;
 };
 
 size_t final_layout(int64_t n, int64_t n_hits, int32_t max_len, size_t esz, unsigned char* base, FinalWork* w) {
@@ -1080,6 +1086,23 @@ size_t final_layout(int64_t n, int64_t n_hits, int32_t max_len, size_t esz, unsi
   x.seed_charge = (int8_t*)take(N);
   x.used = (uint8_t*)take(size_t(n_hits));
   x.open = (uint8_t*)take(N);
+  x.flag = (int32_t*)take(N * 4);
+  x.len = (int32_t*)take(N * 4);
+  x.pos = (int32_t*)take(N * 4);
+  x.epos = (int32_t*)take(N * 4);
+  x.map = (int32_t*)take(N * 4);
+  x.sub_offsets = (int32_t*)take((N + 1) * 4);
+  x.counts = (int32_t*)take(2 * 4);
+  x.sub_layer = (int16_t*)take(size_t(n_hits) * 2);
+  x.sub_used = (uint8_t*)take(size_t(n_hits));
+  x.sub_pos = take(3 * size_t(n_hits) * esz);
+  x.sub_cov = take(6 * size_t(n_hits) * esz);
+  // hipCUB's exclusive scan over n int32 (its storage does not depend on T)
+  kf::GatherArgs<float> q{};
+  q.n = n;
+  kf::launch_final_gather(q, nullptr);
+  x.scan_bytes = q.scan_bytes;
+  x.scan_temp = take(x.scan_bytes > 0 ? x.scan_bytes : 1);
   if (w) *w = x;
   return off;
 }
@@ -1089,9 +1112,12 @@ size_t final_layout(int64_t n, int64_t n_hits, int32_t max_len, size_t esz, unsi
 // state after every entry), the backward fit storing its prediction at every
 // entry, the unbiased chi2 of every used hit (entry-parallel) and the
 // round's decisions.
-// The rounds are enqueued without waiting for the device: a round finds
-// nothing to do for closed tracks (their used flags are cleared, so the fit
-// sees no valid hit and the backward pass does not refit them).
+// The first round runs on the caller's batch.  After each round the tracks
+// still open are gathered, with their used hits, into a compact sub-batch
+// (the map keeps each one's index in the caller's batch, where the round's
+// decisions and outputs are written), and the host waits for the stream to
+// read their count: the next round is launched on that many tracks only, and
+// none when the count is 0.
 template <typename T>
 hipError_t final_rounds(kf_ctx* ctx, int pi, int64_t n, int64_t ld, int32_t seed_mode, const int32_t* hit_offsets,
                         const int16_t* hit_layer, const uint8_t* hit_valid, int64_t n_hits, const void* hit_pos,
@@ -1135,14 +1161,26 @@ hipError_t final_rounds(kf_ctx* ctx, int pi, int64_t n, int64_t ld, int32_t seed
   r.chi2_out = (T*)chi2;
   r.ndf_out = ndf;
   r.status_out = trk_status;
+  r.map = nullptr;
+  r.orig_offsets = hit_offsets;
+  r.used_orig = w.used;
+  r.open_orig = w.open;
   hipError_t e = kf::launch_final_init(r, s);
   const kf::FitLaunch l = ctx->fit[pi];
-  const bool room = ctx->work.cap > 0 && n <= ctx->work.max_tracks && max_len <= ctx->work.max_len;
-  const int layout = room || l.layout == 3 ? l.layout : (l.layout == 4 ? 3 : 0);
   const int32_t n_seg = max_len > 1 ? max_len - 1 : 1;
+  // the batch a round runs on: the caller's tracks in the first round, then
+  // the sub-batch of those still open (the same hits, compacted)
+  int64_t nb = n;
+  const int32_t* b_off = hit_offsets;
+  const int16_t* b_lay = hit_layer;
+  uint8_t* b_used = w.used;
+  const void* b_pos = hit_pos;
+  const void* b_cov = hit_cov;
   for (int32_t round = 0; round <= max_reject && e == hipSuccess; ++round) {
-    auto f = make_fit_args<T>(n, n, nullptr, nullptr, nullptr, hit_offsets, hit_layer, w.used, n_hits, hit_pos,
-                              hit_cov, nullptr, w.f_state, w.f_cov, w.f_charge, w.f_chi2, w.f_ndf, w.ckpt, 1, n_seg,
+    const bool room = ctx->work.cap > 0 && nb <= ctx->work.max_tracks && max_len <= ctx->work.max_len;
+    const int layout = room || l.layout == 3 ? l.layout : (l.layout == 4 ? 3 : 0);
+    auto f = make_fit_args<T>(nb, nb, nullptr, nullptr, nullptr, b_off, b_lay, b_used, n_hits, b_pos, b_cov,
+                              nullptr, w.f_state, w.f_cov, w.f_charge, w.f_chi2, w.f_ndf, w.ckpt, 1, n_seg,
                               w.f_status, ctx->d_counter);
     f.max_len = max_len;
     f.make_seeds = seed_mode + 1;
@@ -1151,9 +1189,9 @@ hipError_t final_rounds(kf_ctx* ctx, int pi, int64_t n, int64_t ld, int32_t seed
     e = run_fit(ctx, f, g, l, layout, s, false);
     if (e != hipSuccess) break;
     kf::BwdArgs<T> b;
-    b.f = make_fit_args<T>(n, n, w.f_state, w.f_cov, w.f_charge, hit_offsets, hit_layer, w.used, n_hits, hit_pos,
-                           hit_cov, nullptr, w.b_state, w.b_cov, w.b_charge, w.b_chi2, w.b_ndf, nullptr, 1, 0,
-                           w.b_status, ctx->d_counter);
+    b.f = make_fit_args<T>(nb, nb, w.f_state, w.f_cov, w.f_charge, b_off, b_lay, b_used, n_hits, b_pos, b_cov,
+                           nullptr, w.b_state, w.b_cov, w.b_charge, w.b_chi2, w.b_ndf, nullptr, 1, 0, w.b_status,
+                           ctx->d_counter);
     b.f.max_len = max_len;
     b.fwd_status = w.f_status;
     b.cov_scale = T(cov_scale);
@@ -1163,10 +1201,55 @@ hipError_t final_rounds(kf_ctx* ctx, int pi, int64_t n, int64_t ld, int32_t seed
     b.smooth_cov = (T*)w.sm_cov;
     e = kf::launch_backward_predictions(b, g, s);
     if (e != hipSuccess) break;
+    r.n = nb;
+    r.hit_offsets = b_off;
+    r.hit_layer = b_lay;
+    r.hit_pos = (const T*)b_pos;
+    r.hit_cov = (const T*)b_cov;
+    r.used = b_used;
     r.round = round;
     e = kf::launch_final_chi2(r, g, s);
     if (e != hipSuccess) break;
     e = kf::launch_final_round(r, s);
+    if (e != hipSuccess || round == max_reject) break;
+    // the tracks still open, gathered for the next round (the host needs
+    // their count to size the next round's launches)
+    kf::GatherArgs<T> ga{};
+    ga.n = n;
+    ga.hit_offsets = hit_offsets;
+    ga.hit_layer = hit_layer;
+    ga.used = w.used;
+    ga.hit_pos = (const T*)hit_pos;
+    ga.hit_cov = (const T*)hit_cov;
+    ga.n_hits = n_hits;
+    ga.open = w.open;
+    ga.flag = w.flag;
+    ga.len = w.len;
+    ga.pos = w.pos;
+    ga.epos = w.epos;
+    ga.map = w.map;
+    ga.sub_offsets = w.sub_offsets;
+    ga.sub_layer = w.sub_layer;
+    ga.sub_used = w.sub_used;
+    ga.sub_pos = (T*)w.sub_pos;
+    ga.sub_cov = (T*)w.sub_cov;
+    ga.counts = w.counts;
+    ga.scan_temp = w.scan_temp;
+    ga.scan_bytes = w.scan_bytes;
+    e = kf::launch_final_gather(ga, s);
+    if (e != hipSuccess) break;
+    int32_t counts[2] = {0, 0};
+    e = hipMemcpyAsync(counts, w.counts, sizeof(counts), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess || counts[0] == 0) break;
+    nb = counts[0];
+    b_off = w.sub_offsets;
+    b_lay = w.sub_layer;
+    b_used = w.sub_used;
+    b_pos = w.sub_pos;
+    b_cov = w.sub_cov;
+    r.open = nullptr;   // every track of the sub-batch is open
+    r.map = w.map;
   }
   return e;
 }

@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(256) final_chi2_kernel(FinalRoundArgs<T> a, Ge
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = int(blockIdx.y);
   if (t >= a.n) return;
-  if (!(a.open[t] & kFinalOpen)) return;
+  if (a.open && !(a.open[t] & kFinalOpen)) return;
   const int64_t e0 = a.hit_offsets[t];
   int n_e = int(a.hit_offsets[t + 1] - e0);
   if (n_e > a.max_len) n_e = a.max_len;

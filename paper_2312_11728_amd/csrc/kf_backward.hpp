@@ -26,7 +26,17 @@ struct FinalRoundArgs {
   int32_t round, max_reject, min_keep;
   double chi2_cut;
   uint8_t* used;                 // [n_hits] valid, not rejected, track still open
-  uint8_t* open;                 // [n] kFinalOpen | kFinalRejected
+  uint8_t* open;                 // [n] kFinalOpen | kFinalRejected, or null: every track of the batch is open
+  // After the first round a round runs on a sub-batch of the open tracks
+  // (hit_offsets ... used then describe the sub-batch): map[i] is the
+  // caller's track of sub-batch track i, orig_offsets the caller's hit
+  // offsets, and the round's decisions go to the caller-indexed used_orig
+  // and open_orig (and outlier, hit_chi2).  Without a sub-batch map is null
+  // and used_orig / open_orig are used / open.
+  const int32_t* map;            // [n] or null
+  const int32_t* orig_offsets;   // the caller's [n_tracks + 1]
+  uint8_t* used_orig;
+  uint8_t* open_orig;
   uint8_t* outlier;              // [n_hits] 1 rejected
   T* hit_chi2;                   // [n_hits] the caller's copy of the unbiased chi2, or null
   T* chi2_work;                  // [n_hits] this round's unbiased chi2 of the used hits
@@ -65,6 +75,40 @@ hipError_t launch_final_chi2(const FinalRoundArgs<T>& a, const GeomArgs& g, hipS
 // One round's decisions (after launch_final_chi2).
 template <typename T>
 hipError_t launch_final_round(const FinalRoundArgs<T>& a, hipStream_t s);
+
+// The open tracks of the caller's batch gathered into a sub-batch for the
+// next round: the caller's n tracks (hit_offsets, hit_layer, used, hit_pos,
+// hit_cov, open) in, the sub-batch's map, offsets, layers, used flags,
+// positions and covariances out, in the caller's track order, and counts[0]
+// = its tracks, counts[1] = its entries (device).  flag, len, pos, epos: [n]
+// int32 scratch; scan_temp / scan_bytes: hipCUB scan storage (null: only
+// report the storage needed in scan_bytes).
+template <typename T>
+struct GatherArgs {
+  int64_t n;
+  const int32_t* hit_offsets;
+  const int16_t* hit_layer;
+  const uint8_t* used;
+  const T* hit_pos;
+  const T* hit_cov;
+  int64_t n_hits;
+  const uint8_t* open;
+  int32_t* flag;
+  int32_t* len;
+  int32_t* pos;
+  int32_t* epos;
+  int32_t* map;
+  int32_t* sub_offsets;   // [n + 1]
+  int16_t* sub_layer;     // [n_hits]
+  uint8_t* sub_used;      // [n_hits]
+  T* sub_pos;             // [3][n_hits] (leading dimension n_hits)
+  T* sub_cov;             // [6][n_hits]
+  int32_t* counts;        // [2]
+  void* scan_temp;
+  size_t scan_bytes;
+};
+template <typename T>
+hipError_t launch_final_gather(GatherArgs<T>& a, hipStream_t s);
 // The backward pass of the smoother alone: its prediction at every entry
 // stored in b.smooth_state / b.smooth_cov, without the combination.
 template <typename T>
