@@ -1,7 +1,8 @@
 // HIP kernels of the combinatorial candidate search: binning of the hit pool
-// by (layer, phi, z), then per layer of the plan the extend kernel (one
-// thread per candidate slot) and the select kernel (one thread per seed), and
-// a final pass that writes the kept candidates.
+// by (layer, phi, z), then the search itself in one launch (one thread per
+// candidate slot, one wave per block; per layer of the plan the selection,
+// the extend with its window scan, and at the end the final pass that writes
+// the kept candidates).
 #include "kf_kernels.hpp"
 #include "kf_search.hpp"
 #include "kf_search_launch.hpp"
@@ -159,10 +160,17 @@ __global__ void __launch_bounds__(kSearchBlock, kSearchWaves) search_kernel(Sear
         select_slot<B>(a, X, step - 1, s, i, k);
     }
     __syncthreads();
-    if (slot) {
-      const uint32_t st = extend_candidate<B>(a, X, layers[step], layers[step > 0 ? step - 1 : 0], step, s, i, k);
-      if (st) atomicOr(&a.status[s / a.beam], st);
-    }
+    const SearchLayer& L = layers[step];
+    uint32_t st = 0;
+    float score = 0.f;
+    ScanWindow w;
+    w.scan = false;
+    const bool open = slot && extend_open<B>(a, X, L, layers[step > 0 ? step - 1 : 0], step, s, i, k, score, w, st);
+    Kids<B> K;
+    kids_init(K);
+    scan_window<B>(a, L, w, k.p, k.c, score, K, st);
+    if (open) extend_close<B>(a, X, i, k, score, K);
+    if (st) atomicOr(&a.status[s / a.beam], st);
     __syncthreads();
   }
   if (slot) select_slot<B>(a, X, a.plan_len - 1, s, i, k);

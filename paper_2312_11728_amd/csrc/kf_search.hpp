@@ -144,8 +144,9 @@ KF_HD inline void load_pool_hit(const SearchArgs& a, int32_t h, float m[3], floa
   for (int i = 0; i < 6; ++i) V[i] = ph.cov[i];
 }
 
-// chi2 = r^T (C_pos + V)^-1 r of the predicted state (p, c) and hit (m, V).
-KF_HD inline float hit_chi2(const float p[6], const float c[21], const float m[3], const float V[6], uint32_t& st) {
+// chi2 = r^T (C_pos + V)^-1 r of the predicted state (p, c) and hit (m, V);
+// reads the position p[0..2] and its covariance block c[0..5] only.
+KF_HD inline float hit_chi2(const float* p, const float* c, const float m[3], const float V[6], uint32_t& st) {
   float S[6];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -160,6 +161,63 @@ KF_HD inline float hit_chi2(const float p[6], const float c[21], const float m[3
   return acc;
 }
 
+// A slot's window at a layer (step 2 of the search): phi_p +- dphi and
+// zp +- w_z around the predicted position, covering the phi bins [b0, b1]
+// (taken modulo nphi) and the z bins [z0, z1] of the layer's binned pool,
+// slightly widened so that the exact test (in_window) decides.  scan is
+// false when the window covers nothing (a non-finite prediction).
+struct ScanWindow {
+  bool scan;
+  float phi_p, dphi, zp, w_z;
+  int32_t b0, b1, z0, z1;
+};
+
+KF_HD inline ScanWindow open_window(const SearchArgs& a, const SearchLayer& L, const float p[6], const float c[21]) {
+  ScanWindow w;
+  w.phi_p = k_atan2(p[1], p[0]);
+  const float ir = 1.f / k_sqrt(p[0] * p[0] + p[1] * p[1]);
+  const float sp = p[1] * ir, cp = p[0] * ir;
+  const float var_r = sp * sp * c[sym(0, 0)] - 2.f * sp * cp * c[sym(1, 0)] + cp * cp * c[sym(1, 1)];
+  float w_r = a.n_sigma * k_sqrt(var_r + L.sig_r * L.sig_r);
+  w_r = w_r < L.wmin_r ? L.wmin_r : (w_r > L.wmax_r ? L.wmax_r : w_r);
+  float w_z = a.n_sigma * k_sqrt(c[sym(2, 2)] + L.sig_z * L.sig_z);
+  w.w_z = w_z < L.wmin_z ? L.wmin_z : (w_z > L.wmax_z ? L.wmax_z : w_z);
+  w.dphi = w_r / L.R;
+  w.zp = p[2];
+  const float bw = float(L.nphi) * float(0.5 / kPi);
+  const float fb0 = k_floor((w.phi_p - w.dphi - 1e-5f + float(kPi)) * bw);
+  const float fb1 = k_floor((w.phi_p + w.dphi + 1e-5f + float(kPi)) * bw);
+  w.scan = fb0 >= -float(L.nphi) && fb1 <= 2.f * float(L.nphi) && fb1 >= fb0 && k_finite(w.zp) && k_finite(w.w_z);
+  w.b0 = w.b1 = w.z0 = w.z1 = 0;
+  if (w.scan) {
+    w.b0 = int32_t(fb0);
+    w.b1 = int32_t(fb1);
+    if (w.b1 - w.b0 + 1 > L.nphi) {
+      w.b0 = 0;
+      w.b1 = L.nphi - 1;
+    }
+    w.z0 = z_bin(w.zp - w.w_z - 1e-4f, L.lo, L.hi, L.nz);
+    w.z1 = z_bin(w.zp + w.w_z + 1e-4f, L.lo, L.hi, L.nz);
+  }
+  return w;
+}
+
+// The run of the binned pool that phi bin b of the window covers: every phi
+// bin's z range [z0, z1] is one contiguous run [lo, hi).
+KF_HD inline void bin_run(const SearchArgs& a, const SearchLayer& L, int32_t z0, int32_t z1, int32_t b, int32_t& lo,
+                          int32_t& hi) {
+  const int32_t pb = b < 0 ? b + L.nphi : (b >= L.nphi ? b - L.nphi : b);
+  lo = a.bin_off[L.base + pb * L.nz + z0];
+  hi = a.bin_off[L.base + pb * L.nz + z1 + 1];
+}
+
+// the exact window test of a pool hit
+KF_HD inline bool in_window(float phi_p, float dphi, float zp, float w_z, const PoolHit& ph) {
+  float d = ph.phi - phi_p;
+  d = d > float(kPi) ? d - float(2 * kPi) : (d < -float(kPi) ? d + float(2 * kPi) : d);
+  return k_abs(d) <= dphi && k_abs(ph.z - zp) <= w_z;
+}
+
 // The overlap step for a candidate that took binned pool hit h on layer L
 // and has just been updated with it (p, c, q): among the hits of L on a
 // module with a higher id than h's inside the window around the updated
@@ -171,44 +229,19 @@ KF_HD inline float hit_chi2(const float p[6], const float c[21], const float m[3
 KF_HD inline int32_t pick_overlap(const SearchArgs& a, const SearchLayer& L, int32_t h, float p[6], float c[21],
                                   int& q, float& c2_out, uint32_t& st) {
   const int32_t mod = a.pool[h].module;
-  const float phi_p = k_atan2(p[1], p[0]);
-  const float ir = 1.f / k_sqrt(p[0] * p[0] + p[1] * p[1]);
-  const float sp = p[1] * ir, cp = p[0] * ir;
-  const float var_r = sp * sp * c[sym(0, 0)] - 2.f * sp * cp * c[sym(1, 0)] + cp * cp * c[sym(1, 1)];
-  float w_r = a.n_sigma * k_sqrt(var_r + L.sig_r * L.sig_r);
-  w_r = w_r < L.wmin_r ? L.wmin_r : (w_r > L.wmax_r ? L.wmax_r : w_r);
-  float w_z = a.n_sigma * k_sqrt(c[sym(2, 2)] + L.sig_z * L.sig_z);
-  w_z = w_z < L.wmin_z ? L.wmin_z : (w_z > L.wmax_z ? L.wmax_z : w_z);
-  const float dphi = w_r / L.R;
-  const float zp = p[2];
-  const float bw = float(L.nphi) * float(0.5 / kPi);
-  const float fb0 = k_floor((phi_p - dphi - 1e-5f + float(kPi)) * bw);
-  const float fb1 = k_floor((phi_p + dphi + 1e-5f + float(kPi)) * bw);
+  const ScanWindow w = open_window(a, L, p, c);
   int32_t best = -1, best_id = 0;
   float best_c2 = 0.f;
-  if (fb0 >= -float(L.nphi) && fb1 <= 2.f * float(L.nphi) && fb1 >= fb0 && k_finite(zp) && k_finite(w_z)) {
-    int32_t b0 = int32_t(fb0), b1 = int32_t(fb1);
-    if (b1 - b0 + 1 > L.nphi) {
-      b0 = 0;
-      b1 = L.nphi - 1;
-    }
-    const int32_t z0 = z_bin(zp - w_z - 1e-4f, L.lo, L.hi, L.nz);
-    const int32_t z1 = z_bin(zp + w_z + 1e-4f, L.lo, L.hi, L.nz);
-    for (int32_t b = b0; b <= b1; ++b) {
-      const int32_t pb = b < 0 ? b + L.nphi : (b >= L.nphi ? b - L.nphi : b);
-      const int32_t h0 = a.bin_off[L.base + pb * L.nz + z0];
-      const int32_t h1 = a.bin_off[L.base + pb * L.nz + z1 + 1];
+  if (w.scan) {
+    for (int32_t b = w.b0; b <= w.b1; ++b) {
+      int32_t h0, h1;
+      bin_run(a, L, w.z0, w.z1, b, h0, h1);
       for (int32_t k = h0; k < h1; ++k) {
         const PoolHit ph = a.pool[k];
         if (ph.module <= mod) continue;
-        float d = ph.phi - phi_p;
-        d = d > float(kPi) ? d - float(2 * kPi) : (d < -float(kPi) ? d + float(2 * kPi) : d);
-        if (!(k_abs(d) <= dphi) || !(k_abs(ph.z - zp) <= w_z)) continue;
+        if (!in_window(w.phi_p, w.dphi, w.zp, w.w_z, ph)) continue;
         const float m[3] = {ph.x, ph.y, ph.z};
-        float V[6];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) V[i] = ph.cov[i];
-        const float c2 = hit_chi2(p, c, m, V, st);
+        const float c2 = hit_chi2(p, c, m, ph.cov, st);
         if (!(c2 <= a.chi2_max)) continue;
         if (best < 0 || c2 < best_c2 || (c2 == best_c2 && ph.id < best_id)) {
           best = k;
@@ -356,162 +389,161 @@ KF_HD inline void select_slot(const SearchArgs& a, const SlotExchange<B>& X, int
   if (a.overlap) a.hist_ovl[int64_t(step) * S + s] = kMissIdx;
 }
 
-// Extend candidate k of the slot at place i of its block (slot s) to layer
-// L (see the file comment): its child list and the state it goes on with
-// are left in X.  Returns the status bits of its steps.
+// A slot's child list at a layer, best first (empty entries rank last), and
+// the number of hits it accepted.
 template <int B>
-KF_HD inline uint32_t extend_candidate(const SearchArgs& a, SlotExchange<B>& X, const SearchLayer& L,
-                                       const SearchLayer& Lp, int step, int64_t s, int i, Cand& k) {
+struct Kids {
+  float s[B];
+  int32_t key[B], idx[B];
+  int n;
+};
+
+template <int B>
+KF_HD inline void kids_init(Kids<B>& K) {
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    K.s[j] = -k_inf<float>();
+    K.key[j] = kMissKey;
+    K.idx[j] = -2;
+  }
+  K.n = 0;
+}
+
+// an accepted hit (child score ns, hit id key, binned pool index idx) into
+// the sorted list; the last entry drops out
+template <int B>
+KF_HD inline void kids_add(const SearchArgs& a, Kids<B>& K, float ns, int32_t key, int32_t idx) {
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    if (j < a.beam && child_before(ns, key, 0, K.s[j], K.key[j], 0)) {
+      const float ts = K.s[j];
+      const int32_t tk = K.key[j], ti = K.idx[j];
+      K.s[j] = ns;
+      K.key[j] = key;
+      K.idx[j] = idx;
+      ns = ts;
+      key = tk;
+      idx = ti;
+    }
+  }
+  ++K.n;
+}
+
+// Extend of candidate k of the slot at place i of its block (slot s) to
+// layer L (see the file comment), in three parts: extend_open, the scan of
+// its window (scan_window), extend_close.
+//
+// extend_open: the update with the hit the candidate took at the previous
+// layer (and the overlap step), the state it enters L with (left in X, kept
+// if it stops here), the propagation to L and its window.  Returns false
+// when the slot has nothing to scan: no candidate, or one that stops (its
+// stop child is then written).  score: the candidate's score with the
+// overlap term; st collects the status bits.
+template <int B>
+KF_HD inline bool extend_open(const SearchArgs& a, SlotExchange<B>& X, const SearchLayer& L, const SearchLayer& Lp,
+                              int step, int64_t s, int i, Cand& k, float& score, ScanWindow& w, uint32_t& st) {
   const int64_t S = a.n * a.beam;
   X.kid_n[i] = 0;
-  if (!k.live) return 0;
+  w.scan = false;
+  score = 0.f;
+  if (!k.live) return false;
   float* const p = k.p;
   float* const c = k.c;
-  int q = k.q;
-  uint32_t st = 0;
   float ovl = 0.f;
   if (k.idx >= 0) {
     float m[3], V[6], c2;
     load_pool_hit(a, k.idx, m, V);
-    update(p, c, q, m, V, c2, st);
+    update(p, c, k.q, m, V, c2, st);
     if (a.overlap) {
       float oc2 = 0.f;
-      const int32_t oid = pick_overlap(a, Lp, k.idx, p, c, q, oc2, st);
+      const int32_t oid = pick_overlap(a, Lp, k.idx, p, c, k.q, oc2, st);
       a.hist_ovl[int64_t(step - 1) * S + s] = oid;
       if (oid >= 0) ovl = a.overlap_bonus - oc2;
     }
   }
   const int prev = step == 0 ? a.seed_layer[s / a.beam] : L.prev_layer;
-  const float score = k.score + ovl;
-  const int miss = k.miss;
+  score = k.score + ovl;
   const bool stopped = k.idx == kStopIdx;   // carried unchanged
   // the state entering the layer, kept if the candidate stops here
 #pragma unroll
   for (int v = 0; v < 6; ++v) X.state[v][i] = p[v];
 #pragma unroll
   for (int v = 0; v < 21; ++v) X.state[6 + v][i] = c[v];
-  X.state[27][i] = float(q);
-  X.miss[i] = miss;
-  if (stopped || !propagate(p, c, q, 0, L.R, L.x0, prev == L.layer, true, a.bz, a.mass, st)) {
+  X.state[27][i] = float(k.q);
+  X.miss[i] = k.miss;
+  if (stopped || !propagate(p, c, k.q, 0, L.R, L.x0, prev == L.layer, true, a.bz, a.mass, st)) {
     X.kid_score[0][i] = score;
     X.kid_id[0][i] = kStopKey;
     X.kid_idx[0][i] = kStopIdx;
     X.kid_n[i] = 1;
-    return st;
+    return false;
   }
-  // window
-  const float phi_p = k_atan2(p[1], p[0]);
-  const float ir = 1.f / k_sqrt(p[0] * p[0] + p[1] * p[1]);
-  const float sp = p[1] * ir, cp = p[0] * ir;
-  const float var_r = sp * sp * c[sym(0, 0)] - 2.f * sp * cp * c[sym(1, 0)] + cp * cp * c[sym(1, 1)];
-  float w_r = a.n_sigma * k_sqrt(var_r + L.sig_r * L.sig_r);
-  w_r = w_r < L.wmin_r ? L.wmin_r : (w_r > L.wmax_r ? L.wmax_r : w_r);
-  float w_z = a.n_sigma * k_sqrt(c[sym(2, 2)] + L.sig_z * L.sig_z);
-  w_z = w_z < L.wmin_z ? L.wmin_z : (w_z > L.wmax_z ? L.wmax_z : w_z);
-  const float dphi = w_r / L.R;
-  // child list of this slot, best first (empty entries rank last)
-  float ks[B];
-  int32_t kk[B], ki[B];
-#pragma unroll
-  for (int j = 0; j < B; ++j) {
-    ks[j] = -k_inf<float>();
-    kk[j] = kMissKey;
-    ki[j] = -2;
-  }
-  int nk = 0;
-  // bin ranges, widened slightly so that the exact test below decides; a
-  // non-finite prediction scans nothing (the range test below is false)
-  const float zp = p[2];
-  const float bw = float(L.nphi) * float(0.5 / kPi);
-  const float fb0 = k_floor((phi_p - dphi - 1e-5f + float(kPi)) * bw);
-  const float fb1 = k_floor((phi_p + dphi + 1e-5f + float(kPi)) * bw);
-  if (fb0 >= -float(L.nphi) && fb1 <= 2.f * float(L.nphi) && fb1 >= fb0 && k_finite(zp) && k_finite(w_z)) {
-    int32_t b0 = int32_t(fb0), b1 = int32_t(fb1);
-    if (b1 - b0 + 1 > L.nphi) {
-      b0 = 0;
-      b1 = L.nphi - 1;
+  w = open_window(a, L, p, c);
+  return true;
+}
+
+// The scan of one slot's window by its own thread: chi2 of every pool hit
+// inside it, each accepted one (chi2 <= chi2_max) added to K with the child
+// score score + hit_bonus - chi2.  Reads run one step ahead, so that a load
+// is in flight while the previous hit is scored: the next bin's run bounds
+// while a bin is scanned, the next hit while a hit is scored (the index is
+// clamped to the run, the last read repeats the current hit and is not used;
+// an empty run reads nothing).
+template <int B>
+KF_HD inline void scan_window(const SearchArgs& a, const SearchLayer& L, const ScanWindow& w, const float p[6],
+                              const float c[21], float score, Kids<B>& K, uint32_t& st) {
+  if (!w.scan) return;
+  int32_t h0, h1;
+  bin_run(a, L, w.z0, w.z1, w.b0, h0, h1);
+  for (int32_t b = w.b0; b <= w.b1; ++b) {
+    int32_t n0 = 0, n1 = 0;
+    if (b < w.b1) bin_run(a, L, w.z0, w.z1, b + 1, n0, n1);
+    PoolHit cur;
+    if (h0 < h1) cur = a.pool[h0];
+    for (int32_t h = h0; h < h1; ++h) {
+      const PoolHit ph = cur;
+      cur = a.pool[h + 1 < h1 ? h + 1 : h];
+      if (!in_window(w.phi_p, w.dphi, w.zp, w.w_z, ph)) continue;
+      const float m[3] = {ph.x, ph.y, ph.z};
+      const float c2 = hit_chi2(p, c, m, ph.cov, st);
+      if (c2 <= a.chi2_max) kids_add(a, K, score + a.hit_bonus - c2, ph.id, h);
     }
-    const int32_t z0 = z_bin(zp - w_z - 1e-4f, L.lo, L.hi, L.nz);
-    const int32_t z1 = z_bin(zp + w_z + 1e-4f, L.lo, L.hi, L.nz);
-    // Every phi bin's z range [z0, z1] is one contiguous run of the binned
-    // pool.  Reads run one step ahead, so that a load is in flight while the
-    // previous hit is scored: the next bin's run bounds while a bin is
-    // scanned, the next hit while a hit is scored (the index is clamped to
-    // the run, the last read repeats the current hit and is not used; an
-    // empty run reads nothing).
-    auto run_of = [&](int32_t b, int32_t& lo, int32_t& hi) {
-      const int32_t pb = b < 0 ? b + L.nphi : (b >= L.nphi ? b - L.nphi : b);
-      lo = a.bin_off[L.base + pb * L.nz + z0];
-      hi = a.bin_off[L.base + pb * L.nz + z1 + 1];
-    };
-    int32_t h0, h1;
-    run_of(b0, h0, h1);
-    for (int32_t b = b0; b <= b1; ++b) {
-      int32_t n0 = 0, n1 = 0;
-      if (b < b1) run_of(b + 1, n0, n1);
-      PoolHit cur;
-      if (h0 < h1) cur = a.pool[h0];
-      for (int32_t h = h0; h < h1; ++h) {
-        const PoolHit ph = cur;
-        cur = a.pool[h + 1 < h1 ? h + 1 : h];
-        float d = ph.phi - phi_p;
-        d = d > float(kPi) ? d - float(2 * kPi) : (d < -float(kPi) ? d + float(2 * kPi) : d);
-        if (!(k_abs(d) <= dphi) || !(k_abs(ph.z - zp) <= w_z)) continue;
-        const float m[3] = {ph.x, ph.y, ph.z};
-        float V[6];
-#pragma unroll
-        for (int v = 0; v < 6; ++v) V[v] = ph.cov[v];
-        const int32_t ph_id = ph.id;
-        const float c2 = hit_chi2(p, c, m, V, st);
-        if (!(c2 <= a.chi2_max)) continue;
-        // insert (score, id) into the sorted list; the last entry drops out
-        float ns = score + a.hit_bonus - c2;
-        int32_t nkey = ph_id, nidx = h;
-#pragma unroll
-        for (int j = 0; j < B; ++j) {
-          if (j < a.beam && child_before(ns, nkey, 0, ks[j], kk[j], 0)) {
-            const float ts = ks[j];
-            const int32_t tk = kk[j], ti = ki[j];
-            ks[j] = ns;
-            kk[j] = nkey;
-            ki[j] = nidx;
-            ns = ts;
-            nkey = tk;
-            nidx = ti;
-          }
-        }
-        ++nk;
-      }
-      h0 = n0;
-      h1 = n1;
-    }
+    h0 = n0;
+    h1 = n1;
   }
-  if (nk == 0) {
-    const bool can_miss = miss < a.max_miss;
-    ks[0] = can_miss ? score - a.miss_penalty : score;
-    kk[0] = can_miss ? kMissKey : kStopKey;
-    ki[0] = can_miss ? kMissIdx : kStopIdx;
-    nk = 1;
+}
+
+// extend_close: the slot's child list after its scan (a miss child when no
+// hit was accepted and the miss budget allows, else a stop child) and the
+// predicted state the candidate goes on with, into X.
+template <int B>
+KF_HD inline void extend_close(const SearchArgs& a, SlotExchange<B>& X, int i, const Cand& k, float score,
+                               Kids<B>& K) {
+  if (K.n == 0) {
+    const bool can_miss = k.miss < a.max_miss;
+    K.s[0] = can_miss ? score - a.miss_penalty : score;
+    K.key[0] = can_miss ? kMissKey : kStopKey;
+    K.idx[0] = can_miss ? kMissIdx : kStopIdx;
+    K.n = 1;
   }
-  if (ki[0] != kStopIdx) {
+  if (K.idx[0] != kStopIdx) {
     // the candidate goes on from the predicted state
 #pragma unroll
-    for (int v = 0; v < 6; ++v) X.state[v][i] = p[v];
+    for (int v = 0; v < 6; ++v) X.state[v][i] = k.p[v];
 #pragma unroll
-    for (int v = 0; v < 21; ++v) X.state[6 + v][i] = c[v];
-    X.state[27][i] = float(q);
+    for (int v = 0; v < 21; ++v) X.state[6 + v][i] = k.c[v];
+    X.state[27][i] = float(k.q);
   }
-  const int n_out = nk < a.beam ? nk : a.beam;
+  const int n_out = K.n < a.beam ? K.n : a.beam;
 #pragma unroll
   for (int j = 0; j < B; ++j) {
     if (j < n_out) {
-      X.kid_score[j][i] = ks[j];
-      X.kid_id[j][i] = kk[j];
-      X.kid_idx[j][i] = ki[j];
+      X.kid_score[j][i] = K.s[j];
+      X.kid_id[j][i] = K.key[j];
+      X.kid_idx[j][i] = K.idx[j];
     }
   }
   X.kid_n[i] = n_out;
-  return st;
 }
 
 // After the last layer and its selection: candidate k's final state
