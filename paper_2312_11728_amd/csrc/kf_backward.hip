@@ -10,6 +10,15 @@
 #include "kf_stage.hpp"
 #include "kf_track.hpp"
 
+// waves per SIMD that the register allocation of the smoother's combination
+// and of the final fit's chi2 kernel must allow
+#ifndef KF_SMOOTH_WAVES
+#define KF_SMOOTH_WAVES 2
+#endif
+#ifndef KF_FINAL_CHI2_WAVES
+#define KF_FINAL_CHI2_WAVES 2
+#endif
+
 namespace kf {
 
 namespace {
@@ -239,7 +248,7 @@ __device__ inline bool smooth_step(const BwdArgs<T>& b, const TrackGeom<T>& g, i
 // Entries from the first valid one to the last but one of refitted tracks
 // whose prediction is finite; the last entry already holds its filtered state.
 template <typename T>
-__global__ void __launch_bounds__(256, 2) smooth_combine_kernel(BwdArgs<T> b, GeomArgs g) {
+__global__ void __launch_bounds__(256, KF_SMOOTH_WAVES) smooth_combine_kernel(BwdArgs<T> b, GeomArgs g) {
   const FitArgs<T>& a = b.f;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int r = int(blockIdx.y);
@@ -435,7 +444,7 @@ __global__ void __launch_bounds__(kBwdBlock, WAVES) backward_kernel(BwdArgs<T> b
 // r = m - H x (FP64 from here on; NaN when the forward prediction fails or
 // the combination is not positive definite).
 template <typename T>
-__global__ void __launch_bounds__(256) final_chi2_kernel(FinalRoundArgs<T> a, GeomArgs g) {
+__global__ void __launch_bounds__(256, KF_FINAL_CHI2_WAVES) final_chi2_kernel(FinalRoundArgs<T> a, GeomArgs g) {
   __shared__ GeomLds<T> sg;
   stage_geometry(sg, g);
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -456,6 +465,23 @@ __global__ void __launch_bounds__(256) final_chi2_kernel(FinalRoundArgs<T> a, Ge
     if (lay >= 0 && lay < g.n_layers) {
       const int kind = sg.kind[lay];
       const T pos = sg.pos[lay], x0 = sg.x0[lay];
+      // what the entry reads besides the forward prediction (the backward
+      // prediction, the hit), loaded before the prediction is computed
+      const int64_t os = a.n * int64_t(a.max_len), at = int64_t(r) * a.n + t;
+      const bool two = r < n_e - 1;
+      T pb[6], cb[21];
+      if (two) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) pb[i] = a.pred_state[i * os + at];
+#pragma unroll
+        for (int i = 0; i < 21; ++i) cb[i] = a.pred_cov[i * os + at];
+      }
+      const int64_t nh = a.n_hits;
+      T hm[3], hv[6];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) hm[i] = a.hit_pos[i * nh + e];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) hv[i] = a.hit_cov[i * nh + e];
       T p[6], c[21];
       int q;
       uint32_t st = 0;
@@ -478,19 +504,11 @@ __global__ void __launch_bounds__(256) final_chi2_kernel(FinalRoundArgs<T> a, Ge
         ok = propagate(p, c, q, kind, pos, x0, lay == prev, true, T(g.bz), T(g.mass), st);
       }
       if (ok) {
-        const int64_t os = a.n * int64_t(a.max_len), at = int64_t(r) * a.n + t;
         T px[6], cx[21];
         bool have = false;
-        if (r < n_e - 1) {
-          T pb[6], cb[21];
-#pragma unroll
-          for (int i = 0; i < 6; ++i) pb[i] = a.pred_state[i * os + at];
-          if (pb[0] == pb[0]) {
-#pragma unroll
-            for (int i = 0; i < 21; ++i) cb[i] = a.pred_cov[i * os + at];
-            ok = combine_on_surface(p, c, pb, cb, kind, pos, px, cx);
-            have = true;
-          }
+        if (two && pb[0] == pb[0]) {
+          ok = combine_on_surface(p, c, pb, cb, kind, pos, px, cx);
+          have = true;
         }
         if (!have) {
 #pragma unroll
@@ -499,16 +517,15 @@ __global__ void __launch_bounds__(256) final_chi2_kernel(FinalRoundArgs<T> a, Ge
           for (int i = 0; i < 21; ++i) cx[i] = c[i];
         }
         if (ok) {
-          const int64_t nh = a.n_hits;
-          const double r0 = double(a.hit_pos[e]) - double(px[0]);
-          const double r1 = double(a.hit_pos[nh + e]) - double(px[1]);
-          const double r2 = double(a.hit_pos[2 * nh + e]) - double(px[2]);
-          const double sa = double(a.hit_cov[e]) + double(cx[0]);
-          const double sb = double(a.hit_cov[nh + e]) + double(cx[1]);
-          const double sc = double(a.hit_cov[2 * nh + e]) + double(cx[2]);
-          const double sd = double(a.hit_cov[3 * nh + e]) + double(cx[3]);
-          const double se = double(a.hit_cov[4 * nh + e]) + double(cx[4]);
-          const double sf = double(a.hit_cov[5 * nh + e]) + double(cx[5]);
+          const double r0 = double(hm[0]) - double(px[0]);
+          const double r1 = double(hm[1]) - double(px[1]);
+          const double r2 = double(hm[2]) - double(px[2]);
+          const double sa = double(hv[0]) + double(cx[0]);
+          const double sb = double(hv[1]) + double(cx[1]);
+          const double sc = double(hv[2]) + double(cx[2]);
+          const double sd = double(hv[3]) + double(cx[3]);
+          const double se = double(hv[4]) + double(cx[4]);
+          const double sf = double(hv[5]) + double(cx[5]);
           const double i00 = sc * sf - se * se, i10 = sd * se - sb * sf, i20 = sb * se - sc * sd;
           const double i11 = sa * sf - sd * sd, i21 = sb * sd - sa * se, i22 = sa * sc - sb * sb;
           const double det = sa * i00 + sb * i10 + sd * i20;

@@ -15,18 +15,23 @@ namespace {
 
 constexpr int kFinalBlock = 256;
 
+// The per-entry kernels below run a grid of (tracks / kFinalBlock) x
+// kFinalRows blocks: thread (t, y) takes entries y, y + kFinalRows, ... of
+// track t, so that a track's entries are written in parallel.
+constexpr int kFinalRows = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(kFinalBlock) final_init_kernel(FinalRoundArgs<T> a) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= a.n) return;
   const int64_t e0 = a.hit_offsets[t], e1 = a.hit_offsets[t + 1];
-  for (int64_t e = e0; e < e1; ++e) {
+  for (int64_t e = e0 + blockIdx.y; e < e1; e += gridDim.y) {
     a.outlier[e] = 0;
     a.used[e] = a.hit_valid[e] ? 1 : 0;
     a.chi2_work[e] = T(NAN);
     if (a.hit_chi2) a.hit_chi2[e] = T(NAN);
   }
-  a.open[t] = kFinalOpen;
+  if (blockIdx.y == 0) a.open[t] = kFinalOpen;
 }
 
 template <typename T>
@@ -44,6 +49,7 @@ __global__ void __launch_bounds__(kFinalBlock) final_round_kernel(FinalRoundArgs
   if (n_e > a.max_len) n_e = a.max_len;
   double worst = -INFINITY;
   int worst_r = -1, n_used = 0;
+#pragma unroll 4
   for (int r = 0; r < n_e; ++r) {
     if (!a.used[e0 + r]) continue;
     ++n_used;
@@ -91,7 +97,8 @@ template <typename T>
 __global__ void __launch_bounds__(kFinalBlock) final_gather_kernel(GatherArgs<T> a) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= a.n) return;
-  if (t == a.n - 1) {
+  const bool head = blockIdx.y == 0;
+  if (head && t == a.n - 1) {
     const int32_t ns = a.pos[t] + a.flag[t], nh = a.epos[t] + a.len[t];
     a.counts[0] = ns;
     a.counts[1] = nh;
@@ -100,9 +107,11 @@ __global__ void __launch_bounds__(kFinalBlock) final_gather_kernel(GatherArgs<T>
   if (!a.flag[t]) return;
   const int32_t i = a.pos[t], d0 = a.epos[t], m = a.len[t];
   const int64_t s0 = a.hit_offsets[t];
-  a.map[i] = int32_t(t);
-  a.sub_offsets[i] = d0;
-  for (int32_t r = 0; r < m; ++r) {
+  if (head) {
+    a.map[i] = int32_t(t);
+    a.sub_offsets[i] = d0;
+  }
+  for (int32_t r = int32_t(blockIdx.y); r < m; r += int32_t(gridDim.y)) {
     const int64_t e = s0 + r, d = int64_t(d0) + r;
     a.sub_layer[d] = a.hit_layer[e];
     a.sub_used[d] = a.used[e];
@@ -118,8 +127,8 @@ __global__ void __launch_bounds__(kFinalBlock) final_gather_kernel(GatherArgs<T>
 template <typename T>
 hipError_t launch_final_init(const FinalRoundArgs<T>& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(final_init_kernel<T>, dim3(unsigned((a.n + kFinalBlock - 1) / kFinalBlock)), dim3(kFinalBlock),
-                     0, s, a);
+  hipLaunchKernelGGL(final_init_kernel<T>, dim3(unsigned((a.n + kFinalBlock - 1) / kFinalBlock), kFinalRows),
+                     dim3(kFinalBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -151,7 +160,7 @@ hipError_t launch_final_gather(GatherArgs<T>& a, hipStream_t s) {
   bytes = a.scan_bytes;
   e = hipcub::DeviceScan::ExclusiveSum(a.scan_temp, bytes, a.len, a.epos, int(a.n), s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(final_gather_kernel<T>, dim3(grid), dim3(kFinalBlock), 0, s, a);
+  hipLaunchKernelGGL(final_gather_kernel<T>, dim3(grid, kFinalRows), dim3(kFinalBlock), 0, s, a);
   return hipGetLastError();
 }
 
