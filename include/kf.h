@@ -333,8 +333,9 @@ int kf_smooth_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
  * rounds: the first runs on all n tracks; after each round the tracks still
  * open are gathered (their hits with them) into a compact sub-batch that the
  * next round runs on, and the call waits for the stream once per round to
- * read that count (it returns once the last round is enqueued, or at once
- * when no track is left open).  The
+ * read that count into 8 bytes of pinned host memory the context allocates
+ * at its first final fit (it returns once the last round is enqueued, or at
+ * once when no track is left open).  The
  * forward fit runs in the context's launch shape for the precision (never in
  * a graph, never timed).
  * KF_ERR_ARG for chi2_cut not > 0 (NaN included), max_reject outside

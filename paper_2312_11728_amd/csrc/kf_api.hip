@@ -62,6 +62,7 @@ struct kf_ctx {
   // workspace of the final fit's rounds (grown on demand)
   void* final_mem = nullptr;
   size_t final_bytes = 0;
+  int32_t* final_counts = nullptr;   // pinned host copy of a round's open-track count
   // event pairs around the fit kernel of direct launches (kf_set_kernel_timing)
   bool timing = false;
   std::vector<hipEvent_t> t_start, t_stop;
@@ -232,6 +233,7 @@ int kf_destroy(kf_ctx* c) {
   if (c->search_mem) hipFree(c->search_mem);
   if (c->dedup_mem) hipFree(c->dedup_mem);
   if (c->final_mem) hipFree(c->final_mem);
+  if (c->final_counts) hipHostFree(c->final_counts);
   hipSetDevice(prev);
   delete c;
   return ok();
@@ -1238,8 +1240,8 @@ hipError_t final_rounds(kf_ctx* ctx, int pi, int64_t n, int64_t ld, int32_t seed
     ga.scan_bytes = w.scan_bytes;
     e = kf::launch_final_gather(ga, s);
     if (e != hipSuccess) break;
-    int32_t counts[2] = {0, 0};
-    e = hipMemcpyAsync(counts, w.counts, sizeof(counts), hipMemcpyDeviceToHost, s);
+    int32_t* counts = ctx->final_counts;
+    e = hipMemcpyAsync(counts, w.counts, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess || counts[0] == 0) break;
     nb = counts[0];
@@ -1305,6 +1307,17 @@ int kf_final_fit(kf_ctx* ctx, kf_precision prec, int64_t n, int64_t ld, int32_t 
       return fail(KF_ERR_NOMEM, "kf_final_fit: %zu bytes: %s", need, hipGetErrorString(e));
     }
     ctx->final_bytes = need;
+  }
+  if (!ctx->final_counts) {
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    hipError_t e = hipHostMalloc((void**)&ctx->final_counts, 2 * sizeof(int32_t), hipHostMallocDefault);
+    hipSetDevice(prev);
+    if (e != hipSuccess) {
+      ctx->final_counts = nullptr;
+      return fail(KF_ERR_NOMEM, "kf_final_fit: pinned count: %s", hipGetErrorString(e));
+    }
   }
   FinalWork w;
   final_layout(n, n_hits, max_len, esz, (unsigned char*)ctx->final_mem, &w);

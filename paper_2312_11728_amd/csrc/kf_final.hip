@@ -15,24 +15,25 @@ namespace {
 
 constexpr int kFinalBlock = 256;
 
-// The per-entry kernels below run a grid of (tracks / kFinalBlock) x
-// kFinalRows blocks: thread (t, y) takes entries y, y + kFinalRows, ... of
-// track t, so that a track's entries are written in parallel.
-constexpr int kFinalRows = 8;
-
+// Set-up, one thread per track (its open flag) and per entry: the tracks'
+// entries are the one range [hit_offsets[0], hit_offsets[n]), written
+// thread by thread.
 template <typename T>
 __global__ void __launch_bounds__(kFinalBlock) final_init_kernel(FinalRoundArgs<T> a) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.n) return;
-  const int64_t e0 = a.hit_offsets[t], e1 = a.hit_offsets[t + 1];
-  for (int64_t e = e0 + blockIdx.y; e < e1; e += gridDim.y) {
-    a.outlier[e] = 0;
-    a.used[e] = a.hit_valid[e] ? 1 : 0;
-    a.chi2_work[e] = T(NAN);
-    if (a.hit_chi2) a.hit_chi2[e] = T(NAN);
-  }
-  if (blockIdx.y == 0) a.open[t] = kFinalOpen;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < a.n) a.open[i] = kFinalOpen;
+  const int64_t e = int64_t(a.hit_offsets[0]) + i;
+  if (e >= a.hit_offsets[a.n] || e >= a.n_hits) return;
+  a.outlier[e] = 0;
+  a.used[e] = a.hit_valid[e] ? 1 : 0;
+  a.chi2_work[e] = T(NAN);
+  if (a.hit_chi2) a.hit_chi2[e] = T(NAN);
 }
+
+// The gather runs a grid of (tracks / kFinalBlock) x kFinalRows blocks:
+// thread (t, y) copies entries y, y + kFinalRows, ... of track t, so that a
+// track's entries are copied in parallel.
+constexpr int kFinalRows = 8;
 
 template <typename T>
 __global__ void __launch_bounds__(kFinalBlock) final_round_kernel(FinalRoundArgs<T> a) {
@@ -127,8 +128,9 @@ __global__ void __launch_bounds__(kFinalBlock) final_gather_kernel(GatherArgs<T>
 template <typename T>
 hipError_t launch_final_init(const FinalRoundArgs<T>& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(final_init_kernel<T>, dim3(unsigned((a.n + kFinalBlock - 1) / kFinalBlock), kFinalRows),
-                     dim3(kFinalBlock), 0, s, a);
+  const int64_t m = a.n > a.n_hits ? a.n : a.n_hits;
+  hipLaunchKernelGGL(final_init_kernel<T>, dim3(unsigned((m + kFinalBlock - 1) / kFinalBlock)), dim3(kFinalBlock), 0,
+                     s, a);
   return hipGetLastError();
 }
 
