@@ -237,6 +237,43 @@ def test_final_fit_ragged_sizes_and_repeat(ctx, kf):
     say("ragged ok")
 
 
+def test_final_fit_offsets_past_zero(ctx, kf):
+    """The tracks' entries need not start at entry 0 of the hit arrays: the
+    same tracks behind 7 entries that belong to no track (valid hits, so that
+    a kernel reading them would use them) and before 5 more give the same
+    results bit for bit, and the entries outside the tracks keep what the
+    caller's outlier and hit_chi2 arrays held."""
+    say("final fit, offsets past zero")
+    ev = planted(generate(workloads()["barrel10"], 300))
+    dev = ctx.device
+    for dt in (torch.float32, torch.float64):
+        t = kf.event_tensors(ev, dt, dev)
+        geom = kf.Geometry.from_toy(ev.geometry)
+        nh = ev.n_hits
+        ref = ctx.final_fit(t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"], geom, 0,
+                            chi2_cut=CUT, cov_scale=BACKWARD_SCALE)
+        front, back = 7, 5
+        src = (torch.arange(front + nh + back, device=dev) - front) % nh   # entry front + e holds hit e; the padding copies real hits
+        pad = lambda x: x[..., src].contiguous()
+        off = (t["hit_offsets"] + front).contiguous()
+        mask = torch.full((front + nh + back,), 9, dtype=torch.uint8, device=dev)
+        hc = torch.full((front + nh + back,), -5.0, dtype=dt, device=dev)
+        valid = pad(t["hit_valid"])
+        valid[:front] = 1
+        valid[front + nh:] = 1
+        got = ctx.final_fit(off, pad(t["hit_layer"]), valid, pad(t["hit_pos"]), pad(t["hit_cov"]), geom, 0,
+                            chi2_cut=CUT, cov_scale=BACKWARD_SCALE, outlier=mask, hit_chi2=hc)
+        torch.cuda.synchronize()
+        for k in ref[0]:
+            assert torch.equal(ref[0][k], got[0][k]), (dt, k)
+        assert torch.equal(got[1][front:front + nh], ref[1]), dt
+        assert torch.equal(got[2][front:front + nh].nan_to_num(7.0), ref[2].nan_to_num(7.0)), dt
+        assert (mask[:front] == 9).all() and (mask[front + nh:] == 9).all(), dt
+        assert (hc[:front] == -5.0).all() and (hc[front + nh:] == -5.0).all(), dt
+        assert int(ref[1].sum()) > 0
+    say("offsets past zero ok")
+
+
 def test_final_fit_limits_and_degenerate_cut(ctx, kf):
     """max_reject = 0 is the smoothed fit; a tiny cut rejects a hit in every
     round it may (max_reject of them) unless the track would keep fewer than

@@ -701,3 +701,37 @@ def test_fit_graph_replay_matches_direct_launches(kf, layout, persistent):
         assert torch.equal(again["state"], ref["state"])
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_seed_fit_offsets_past_zero(kf, dtype):
+    """The tracks' entries need not start at entry 0 of the hit arrays: in
+    every layout, the same tracks behind 7 entries that belong to no track
+    (valid hits, so that a kernel reading them would use them) and before 5
+    more give the same results, bit for bit."""
+    say("seed + fit, offsets past zero", dtype)
+    ev = generate(workloads()["barrel10"], 300)
+    dev = torch.device("cuda", 0)
+    geom = kf.Geometry.from_toy(ev.geometry)
+    t = kf.event_tensors(ev, dtype, dev)
+    nh, front, back = ev.n_hits, 7, 5
+    src = (torch.arange(front + nh + back, device=dev) - front) % nh   # entry front + e holds hit e
+    pad = lambda x: x[..., src].contiguous()
+    valid = pad(t["hit_valid"])
+    valid[:front] = 1
+    valid[front + nh:] = 1
+    padded = ((t["hit_offsets"] + front).contiguous(), pad(t["hit_layer"]), valid, pad(t["hit_pos"]),
+              pad(t["hit_cov"]))
+    plain = (t["hit_offsets"], t["hit_layer"], t["hit_valid"], t["hit_pos"], t["hit_cov"])
+    for layout in range(5):
+        c = kf.Context(0)
+        try:
+            c.reserve(ev.n_tracks, 26)
+            c.set_fit_launch(dtype, 256, 0, 1, 2 if dtype == torch.float32 else 1, layout)
+            a = c.seed_fit_tracks(*plain, geom, 0)
+            b = c.seed_fit_tracks(*padded, geom, 0)
+            torch.cuda.synchronize()
+            for k in a:
+                assert torch.equal(a[k].nan_to_num(7.0), b[k].nan_to_num(7.0)), (layout, k)
+        finally:
+            c.close()
