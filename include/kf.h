@@ -187,7 +187,10 @@ int kf_update(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
  * fit; with the sort, if a workspace is there).  Without a workspace the fit
  * reads the CSR arrays in track order.  Results are bit-identical within each
  * family of layouts (direct reads: 0-2; LDS staging: 3, 4) and agree to
- * rounding across the two (see kf_set_fit_launch). */
+ * rounding across the two (see kf_set_fit_launch).  The order of the tracks
+ * changes no result, but in a geometry of barrel cylinders and disks, tracks
+ * given in order of direction (and length) run faster: the lanes of a wave
+ * then cross the same kind of layer at the same step. */
 int kf_fit_tracks(kf_ctx *ctx, kf_precision prec, int64_t n, int64_t ld,
                   const void *seed_state, const void *seed_cov, const int8_t *seed_charge,
                   const int32_t *hit_offsets, const int16_t *hit_layer, const uint8_t *hit_valid,
