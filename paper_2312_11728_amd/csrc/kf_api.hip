@@ -1188,7 +1188,11 @@ hipError_t final_rounds(kf_ctx* ctx, int pi, int64_t n, int64_t ld, int32_t seed
     f.make_seeds = seed_mode + 1;
     f.seed_state_out = (T*)w.seed_state;
     f.seed_charge_out = w.seed_charge;
-    e = run_fit(ctx, f, g, l, layout, s, false);
+    // the later rounds' few open tracks: one wave per block, so that each
+    // wave has a compute unit to itself
+    kf::FitLaunch lr = l;
+    if (round > 0 && !l.persistent) lr.block = 64;
+    e = run_fit(ctx, f, g, lr, layout, s, false);
     if (e != hipSuccess) break;
     kf::BwdArgs<T> b;
     b.f = make_fit_args<T>(nb, nb, w.f_state, w.f_cov, w.f_charge, b_off, b_lay, b_used, n_hits, b_pos, b_cov,
