@@ -1188,8 +1188,8 @@ hipError_t final_rounds(kf_ctx* ctx, int pi, int64_t n, int64_t ld, int32_t seed
     f.make_seeds = seed_mode + 1;
     f.seed_state_out = (T*)w.seed_state;
     f.seed_charge_out = w.seed_charge;
-    // the later rounds' few open tracks: one wave per block, so that each
-    // wave has a compute unit to itself
+    // the later rounds' few open tracks: one wave per block (here and in the
+    // backward pass), so that each wave has a compute unit to itself
     kf::FitLaunch lr = l;
     if (round > 0 && !l.persistent) lr.block = 64;
     e = run_fit(ctx, f, g, lr, layout, s, false);
@@ -1205,7 +1205,7 @@ hipError_t final_rounds(kf_ctx* ctx, int pi, int64_t n, int64_t ld, int32_t seed
     b.n_seg_f = n_seg;
     b.smooth_state = (T*)w.sm_state;
     b.smooth_cov = (T*)w.sm_cov;
-    e = kf::launch_backward_predictions(b, g, s);
+    e = kf::launch_backward_predictions(b, g, s, round > 0 ? 64 : 256);
     if (e != hipSuccess) break;
     r.n = nb;
     r.hit_offsets = b_off;

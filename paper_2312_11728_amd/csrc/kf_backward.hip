@@ -559,11 +559,13 @@ hipError_t launch_backward(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s
 }
 
 template <typename T>
-hipError_t launch_backward_predictions(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s) {
+hipError_t launch_backward_predictions(const BwdArgs<T>& a, const GeomArgs& g, hipStream_t s, int block) {
   if (a.f.n == 0) return hipSuccess;
-  const int64_t grid = (a.f.n + kBwdBlock - 1) / kBwdBlock;
-  hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, kSmooth>), dim3(unsigned(grid)), dim3(kBwdBlock), 0,
-                     s, a, g);
+  // the kernel's LDS is sized for kBwdBlock threads; smaller blocks of whole waves use part of it
+  const int bs = block >= 64 && block <= kBwdBlock && block % 64 == 0 ? block : kBwdBlock;
+  const int64_t grid = (a.f.n + bs - 1) / bs;
+  hipLaunchKernelGGL((backward_kernel<T, sizeof(T) == 4 ? 2 : 1, kSmooth>), dim3(unsigned(grid)), dim3(bs), 0, s, a,
+                     g);
   return hipGetLastError();
 }
 
@@ -577,8 +579,8 @@ hipError_t launch_final_chi2(const FinalRoundArgs<T>& a, const GeomArgs& g, hipS
 
 template hipError_t launch_backward<float>(const BwdArgs<float>&, const GeomArgs&, hipStream_t);
 template hipError_t launch_backward<double>(const BwdArgs<double>&, const GeomArgs&, hipStream_t);
-template hipError_t launch_backward_predictions<float>(const BwdArgs<float>&, const GeomArgs&, hipStream_t);
-template hipError_t launch_backward_predictions<double>(const BwdArgs<double>&, const GeomArgs&, hipStream_t);
+template hipError_t launch_backward_predictions<float>(const BwdArgs<float>&, const GeomArgs&, hipStream_t, int);
+template hipError_t launch_backward_predictions<double>(const BwdArgs<double>&, const GeomArgs&, hipStream_t, int);
 template hipError_t launch_final_chi2<float>(const FinalRoundArgs<float>&, const GeomArgs&, hipStream_t);
 template hipError_t launch_final_chi2<double>(const FinalRoundArgs<double>&, const GeomArgs&, hipStream_t);
 

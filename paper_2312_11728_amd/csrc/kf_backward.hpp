@@ -110,8 +110,9 @@ struct GatherArgs {
 template <typename T>
 hipError_t launch_final_gather(GatherArgs<T>& a, hipStream_t s);
 // The backward pass of the smoother alone: its prediction at every entry
-// stored in b.smooth_state / b.smooth_cov, without the combination.
+// stored in b.smooth_state / b.smooth_cov, without the combination.  block:
+// threads per block (64, 128, 192 or 256; anything else: 256).
 template <typename T>
-hipError_t launch_backward_predictions(const BwdArgs<T>& b, const GeomArgs& g, hipStream_t s);
+hipError_t launch_backward_predictions(const BwdArgs<T>& b, const GeomArgs& g, hipStream_t s, int block = 256);
 
 }  // namespace kf
